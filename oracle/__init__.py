@@ -1,0 +1,46 @@
+"""FP64 CPU oracle for the projected tensor-tensor product and the truncated tSVDQ.
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, plain, obviously-correct
+reference that the GPU library is checked against.  Only the test suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+product path (the HIP library and its Python binding) never does, and the
+oracle never imports the product path.  The two share no code; they meet only
+through the seeded input generators, which hold none of the method's
+arithmetic.
+
+Everything is numpy float64 (LAPACK for the per-face SVD).  Tensors are numpy
+arrays with the paper's logical index order A[i, j, t] (i < n1, j < n2,
+t < n3), real-valued throughout (the paper restricts its experiments to real
+transformations, Sec. 5.1.1), so Q^H = Q^T.
+
+Every function cites the definition, equation, algorithm or theorem of
+Keegan & Newman, "Projected Tensor-Tensor Products for Efficient Computation
+of Optimal Multiway Data Representations" (arXiv:2409.19402) that it follows.
+Parity status of each function is listed in ``PARITY`` below.
+"""
+
+from .core import (  # noqa: F401
+    unfold3, fold3, mode3, facewise, mprod, hat, unhat, qprod, proj,
+    identity_tensor, ftranspose, check_q, fro2,
+)
+from .tsvdq import (  # noqa: F401
+    tsvdq, tsvdq_error_terms, relative_error, tsvdq_ii, TSVDQResult,
+)
+from .grad import qprod_backward, proj_backward  # noqa: F401
+
+# Which pin holds each oracle function (see tests/test_oracle_pins.py).
+PARITY = {
+    "unfold3/fold3/mode3": "pinned: Appendix A printed tubes; brute-force loops",
+    "facewise": "pinned: brute-force loops",
+    "mprod": "pinned: Appendix A printed a*_M b",
+    "hat/unhat/qprod/proj": "pinned: Appendix A printed values, brute force, "
+                            "Q=I reduction, square-orthogonal reduction to *_M, "
+                            "Sec. 3.2 splitting identities",
+    "tsvdq": "pinned: Example 4.1 printed errors, Thm 4.2 identity, Cor 4.1, "
+             "Eckart-Young optimality, full-rank reduction to proj",
+    "tsvdq_ii": "pinned: Thm 4.5 (SVDII error <= tSVDQ error at equal storage), "
+                "gamma=1 reduction",
+    "qprod_backward/proj_backward": "pinned: central finite differences and "
+                                    "torch CPU float64 autograd",
+    "check_q": "pinned: closed form on constructed matrices",
+}

@@ -1,0 +1,410 @@
+"""Pins of the FP64 oracle to what the paper and the mathematics fix.
+
+None of these tests re-types an oracle formula: each checks the oracle against
+a value printed in the paper, a brute-force loop, a library routine reached by
+another route, or an identity the paper proves.  CPU only.
+"""
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from golden.load import load
+from paper_2409_19402_amd import synth
+
+
+def tube(v):
+    return np.asarray(v, dtype=np.float64).reshape(1, 1, -1)
+
+
+def haar4():
+    g = load("appendix_a.txt")
+    return 0.5 * np.array([g["H4_row0"], g["H4_row1"], g["H4_row2"], g["H4_row3"]])
+
+
+# ---------------------------------------------------------------------------
+# Appendix A: printed values of the worked example
+# ---------------------------------------------------------------------------
+
+def test_appendix_a_printed_values():
+    g = load("appendix_a.txt")
+    H4 = haar4()
+    M = H4.T
+    p = int(g["p"][0])
+    Q, Qp = H4[:, :p], H4[:, p:]   # M = [Q Q_perp]^H
+    a, b = tube(g["a"]), tube(g["b"])
+    np.testing.assert_allclose(oracle.mprod(a, b, M).ravel(), g["a_starM_b"], atol=1e-13)
+    np.testing.assert_allclose(oracle.qprod(a, b, Q).ravel(), g["a_starQ_b"], atol=1e-13)
+    np.testing.assert_allclose(oracle.qprod(a, b, Qp).ravel(), g["a_starQperp_b"], atol=1e-13)
+    np.testing.assert_allclose(oracle.proj(a, Q).ravel(), g["a_projQ"], atol=1e-13)
+    np.testing.assert_allclose(oracle.proj(b, Q).ravel(), g["b_projQ"], atol=1e-13)
+    np.testing.assert_allclose(oracle.proj(a, Qp).ravel(), g["a_projQperp"], atol=1e-13)
+    np.testing.assert_allclose(oracle.proj(b, Qp).ravel(), g["b_projQperp"], atol=1e-13)
+    # eq. colSpaceDef: *_Q equals *_M of the projected tubes
+    lhs = oracle.mprod(oracle.proj(a, Q), oracle.proj(b, Q), M)
+    np.testing.assert_allclose(lhs.ravel(), g["a_starQ_b"], atol=1e-13)
+
+
+def test_appendix_a_discriminates_orientation():
+    """The printed values fix Q = first columns of H4 (not of H4^T); the other
+    reading must fail, or the pin would not guard the orientation."""
+    g = load("appendix_a.txt")
+    H4 = haar4()
+    a, b = tube(g["a"]), tube(g["b"])
+    wrong = oracle.qprod(a, b, H4.T[:, :2]).ravel()
+    assert np.max(np.abs(wrong - np.array(g["a_starQ_b"]))) > 0.1
+
+
+# ---------------------------------------------------------------------------
+# Example 4.1: printed squared errors
+# ---------------------------------------------------------------------------
+
+def example41_tensor():
+    g = load("example_4_1.txt")
+    A = np.zeros((2, 2, 2))
+    A[:, :, 0] = [g["face1_row0"], g["face1_row1"]]
+    A[:, :, 1] = [g["face2_row0"], g["face2_row1"]]
+    return A, g
+
+
+def test_example_4_1_errors():
+    A, g = example41_tensor()
+    k = int(g["k"][0])
+    for qkey, ekey, tkey, scale in (("Q_u3", "err2_u3", "err2_u3_terms", 1.0),
+                                    ("Q_haar_scaled_by_sqrt2", "err2_haar",
+                                     "err2_haar_terms", 1 / math.sqrt(2))):
+        Q = scale * np.array(g[qkey]).reshape(2, 1)
+        res = oracle.tsvdq(A, Q, k)
+        err2 = oracle.fro2(A - res.Ak)
+        assert err2 == pytest.approx(g[ekey][0], abs=1e-12)
+        ey, pe = oracle.tsvdq_error_terms(A, Q, k)
+        assert (ey, pe) == pytest.approx(tuple(g[tkey]), abs=1e-12)
+    Qh = np.array(g["Q_haar_scaled_by_sqrt2"]).reshape(2, 1) / math.sqrt(2)
+    face = oracle.hat(A, Qh)[:, :, 0] / math.sqrt(2)
+    np.testing.assert_allclose(face, [g["haar_face_scaled_by_inv_sqrt2_row0"],
+                                      g["haar_face_scaled_by_inv_sqrt2_row1"]], atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Brute force on tiny tensors (pure Python loops, no reshapes)
+# ---------------------------------------------------------------------------
+
+def brute_qprod(A, B, Q):
+    n1, m, n3 = len(A), len(A[0]), len(A[0][0])
+    n2 = len(B[0])
+    p = len(Q[0])
+    Ah = [[[sum(Q[t][l] * A[i][r][t] for t in range(n3)) for l in range(p)]
+           for r in range(m)] for i in range(n1)]
+    Bh = [[[sum(Q[t][l] * B[r][j][t] for t in range(n3)) for l in range(p)]
+           for j in range(n2)] for r in range(m)]
+    Ch = [[[sum(Ah[i][r][l] * Bh[r][j][l] for r in range(m)) for l in range(p)]
+           for j in range(n2)] for i in range(n1)]
+    C = [[[sum(Q[t][l] * Ch[i][j][l] for l in range(p)) for t in range(n3)]
+          for j in range(n2)] for i in range(n1)]
+    return np.array(Ah), np.array(C)
+
+
+@pytest.mark.parametrize("shape", [(3, 2, 4, 5, 3), (1, 3, 1, 4, 4), (2, 1, 3, 6, 1)])
+def test_brute_force_tiny(shape):
+    n1, m, n2, n3, p = shape
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((n1, m, n3))
+    B = rng.standard_normal((m, n2, n3))
+    Q = synth.random_orthonormal(rng, n3, p)
+    Ah_ref, C_ref = brute_qprod(A.tolist(), B.tolist(), Q.tolist())
+    np.testing.assert_allclose(oracle.hat(A, Q), Ah_ref, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(oracle.qprod(A, B, Q), C_ref, rtol=1e-12, atol=1e-12)
+
+
+def test_unfold_column_order():
+    """Def. 2.1: column J(i,j) = i + j*n1 (0-based) of A_(3) is tube (i, j)."""
+    n1, n2, n3 = 3, 4, 5
+    A = np.arange(n1 * n2 * n3, dtype=np.float64).reshape(n1, n2, n3)
+    U = oracle.unfold3(A)
+    for i, j in itertools.product(range(n1), range(n2)):
+        np.testing.assert_array_equal(U[:, i + j * n1], A[i, j, :])
+    np.testing.assert_array_equal(oracle.fold3(U, n1, n2), A)
+    # face-major storage element [t, j, i] is A(i, j, t), so reshape(n3, -1) is A_(3)
+    S = synth.storage(A)
+    np.testing.assert_array_equal(S.reshape(n3, -1), U)
+    np.testing.assert_array_equal(synth.logical(S), A)
+
+
+# ---------------------------------------------------------------------------
+# Special cases that reduce to library routines
+# ---------------------------------------------------------------------------
+
+def test_identity_q_full_is_facewise():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((5, 4, 6))
+    B = rng.standard_normal((4, 3, 6))
+    C = oracle.qprod(A, B, np.eye(6))
+    ref = np.einsum("irt,rjt->ijt", A, B)
+    np.testing.assert_allclose(C, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_square_orthogonal_q_is_starM_and_roundtrip():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((4, 3, 7))
+    B = rng.standard_normal((3, 5, 7))
+    Q = synth.random_orthonormal(rng, 7, 7)
+    # Sec. 3.2: with M = Q^H the *_M and *_Q products coincide
+    np.testing.assert_allclose(oracle.qprod(A, B, Q), oracle.mprod(A, B, Q.T),
+                               rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(oracle.proj(A, Q), A, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(oracle.unhat(oracle.hat(A, Q), Q), A, atol=1e-13)
+
+
+def test_starM_split_into_Q_and_Qperp():
+    """eq. sum_proj_prod and backFrontalSlicesZero."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((3, 4, 8))
+    B = rng.standard_normal((4, 2, 8))
+    W = synth.random_orthonormal(rng, 8, 8)
+    M = W.T
+    Q, Qp = W[:, :3], W[:, 3:]
+    lhs = oracle.mprod(A, B, M)
+    rhs = oracle.qprod(A, B, Q) + oracle.qprod(A, B, Qp)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(oracle.mode3(oracle.qprod(A, B, Q), M[3:, :]), 0, atol=1e-12)
+    np.testing.assert_allclose(oracle.mode3(oracle.qprod(A, B, Qp), M[:3, :]), 0, atol=1e-12)
+    # eq. tensorSplitProjection
+    np.testing.assert_allclose(oracle.proj(A, Q) + oracle.proj(A, Qp), A, atol=1e-12)
+
+
+def test_projector_identity_and_idempotence():
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((4, 5, 9))
+    Q = synth.random_orthonormal(rng, 9, 4)
+    P = oracle.proj(A, Q)
+    np.testing.assert_allclose(oracle.proj(P, Q), P, atol=1e-12)
+    Il = oracle.identity_tensor(4, Q)
+    Ir = oracle.identity_tensor(5, Q)
+    np.testing.assert_allclose(oracle.qprod(Il, A, Q), P, atol=1e-12)
+    np.testing.assert_allclose(oracle.qprod(A, Ir, Q), P, atol=1e-12)
+    # the projection is orthogonal: residual is orthogonal to the projection
+    assert abs(np.sum((A - P) * P)) < 1e-10
+
+
+def test_algebraic_properties():
+    rng = np.random.default_rng(7)
+    n3, p = 6, 3
+    Q = synth.random_orthonormal(rng, n3, p)
+    a, b, c = (rng.standard_normal((1, 1, n3)) for _ in range(3))
+    # Thm 3.1 commutativity for tubes
+    np.testing.assert_allclose(oracle.qprod(a, b, Q), oracle.qprod(b, a, Q), atol=1e-13)
+    # Thm 3.2 associativity and distributivity (tensors, as the proof extends)
+    A = rng.standard_normal((3, 4, n3))
+    B = rng.standard_normal((4, 2, n3))
+    C = rng.standard_normal((2, 5, n3))
+    lhs = oracle.qprod(oracle.qprod(A, B, Q), C, Q)
+    rhs = oracle.qprod(A, oracle.qprod(B, C, Q), Q)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-12)
+    B2 = rng.standard_normal((4, 2, n3))
+    np.testing.assert_allclose(oracle.qprod(A, B + B2, Q),
+                               oracle.qprod(A, B, Q) + oracle.qprod(A, B2, Q), atol=1e-12)
+    # Thm 3.3 transposition
+    lhs = oracle.ftranspose(oracle.qprod(A, B, Q), Q)
+    rhs = oracle.qprod(oracle.ftranspose(B, Q), oracle.ftranspose(A, Q), Q)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-12)
+
+
+def test_hat_unhat_adjoint():
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((5, 6, 11))
+    Y = rng.standard_normal((5, 6, 4))
+    Q = synth.random_orthonormal(rng, 11, 4)
+    lhs = np.sum(oracle.hat(X, Q) * Y)
+    rhs = np.sum(X * oracle.unhat(Y, Q))
+    assert lhs == pytest.approx(rhs, rel=1e-12, abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# tSVDQ pins
+# ---------------------------------------------------------------------------
+
+def test_tsvdq_error_identity_and_factors():
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((7, 5, 10))
+    Q = synth.random_orthonormal(rng, 10, 4)
+    for k in (1, 2, 4, 5):
+        r = oracle.tsvdq(A, Q, k)
+        ey, pe = oracle.tsvdq_error_terms(A, Q, k)
+        assert oracle.fro2(A - r.Ak) == pytest.approx(ey + pe, rel=1e-11)
+        for i in range(4):
+            np.testing.assert_allclose(r.Uhat[:, :, i].T @ r.Uhat[:, :, i], np.eye(k), atol=1e-12)
+            np.testing.assert_allclose(r.Vhat[:, :, i].T @ r.Vhat[:, :, i], np.eye(k), atol=1e-12)
+            face = oracle.hat(A, Q)[:, :, i]
+            # singular values by another route: eigenvalues of the face Gram
+            ev = np.sort(np.linalg.eigvalsh(face.T @ face))[::-1][:k]
+            np.testing.assert_allclose(r.s[:, i] ** 2, ev, rtol=1e-10, atol=1e-12)
+            assert np.all(np.diff(r.s[:, i]) <= 0)
+    # k = min(n1, n2) reproduces the projection
+    r = oracle.tsvdq(A, Q, 5)
+    np.testing.assert_allclose(r.Ak, oracle.proj(A, Q), atol=1e-11)
+    # f-diagonal spatial S_k whose diagonal tubes carry the singular values
+    assert np.allclose(r.Sk[0, 1, :], 0)
+    np.testing.assert_allclose(np.linalg.norm(r.Sk[0, 0, :]), np.linalg.norm(r.s[0, :]))
+
+
+def test_tsvdq_eckart_young_optimality():
+    """Thm 4.2: no X *_Q Y^H of *_Q-rank k does better than A_k."""
+    rng = np.random.default_rng(10)
+    A = rng.standard_normal((6, 5, 8))
+    Q = synth.random_orthonormal(rng, 8, 3)
+    k = 2
+    best = oracle.fro2(A - oracle.tsvdq(A, Q, k).Ak)
+    for _ in range(50):
+        X = rng.standard_normal((6, k, 8))
+        Y = rng.standard_normal((5, k, 8))
+        cand = oracle.qprod(X, oracle.ftranspose(Y, Q), Q)
+        assert oracle.fro2(A - cand) >= best - 1e-12
+    # a perturbed optimum is worse too
+    r = oracle.tsvdq(A, Q, k)
+    Up = r.Uhat + 1e-3 * rng.standard_normal(r.Uhat.shape)
+    Sh = np.stack([np.diag(r.s[:, i]) for i in range(3)], axis=2)
+    cand = oracle.unhat(oracle.facewise(oracle.facewise(Up, Sh),
+                                        np.transpose(r.Vhat, (1, 0, 2))), Q)
+    assert oracle.fro2(A - cand) > best
+
+
+def test_cor_4_1_u3_choice():
+    """Cor 4.1 and Fig. 4.2: with Q = U3(:, :p) the transform faces have
+    Frobenius norms sigma_i(A_(3)) and the projection error is the tail sum."""
+    rng = np.random.default_rng(12)
+    A_st = synth.gaussian(rng, 6, 5, 9, np.float64)
+    A = synth.logical(A_st)
+    p = 4
+    Q = synth.u3_leading(A_st, p)
+    sig = np.linalg.svd(oracle.unfold3(A), compute_uv=False)
+    Ah = oracle.hat(A, Q)
+    norms = np.sqrt(np.sum(Ah ** 2, axis=(0, 1)))
+    np.testing.assert_allclose(norms, sig[:p], rtol=1e-10)
+    _, pe = oracle.tsvdq_error_terms(A, Q, 2)
+    assert pe == pytest.approx(np.sum(sig[p:] ** 2), rel=1e-10)
+    # Thm 4.3: U3 minimises the projection error over random competitors
+    for _ in range(20):
+        W = synth.random_orthonormal(rng, 9, p)
+        assert oracle.fro2(A - oracle.proj(A, W)) >= pe - 1e-10
+
+
+def test_thm_4_1_rank_bound():
+    rng = np.random.default_rng(13)
+    # a tensor whose *_M transform faces have ranks 1, 2, 3, 3
+    W = synth.random_orthonormal(rng, 4, 4)
+    M = W.T
+    Ah = np.zeros((5, 5, 4))
+    for i, r in enumerate((1, 2, 3, 3)):
+        Ah[:, :, i] = rng.standard_normal((5, r)) @ rng.standard_normal((r, 5))
+    A = oracle.mode3(Ah, np.linalg.inv(M))
+    Q = W[:, :2]
+    rk_q = max(np.linalg.matrix_rank(oracle.hat(A, Q)[:, :, i]) for i in range(2))
+    rk_m = max(np.linalg.matrix_rank(oracle.mode3(A, M)[:, :, i]) for i in range(4))
+    assert rk_q == 2 and rk_m == 3 and rk_q <= rk_m
+
+
+def test_tsvdq_ii_beats_tsvdq_at_equal_storage():
+    """Thm 4.5: with gamma set to the energy kept by the rank-k tSVDQ, the
+    SVDII keeps at most kp singular values and errs no more."""
+    rng = np.random.default_rng(14)
+    A = rng.standard_normal((8, 6, 10)) * np.linspace(3, 0.1, 10)
+    Q = synth.random_orthonormal(rng, 10, 5)
+    k = 2
+    r = oracle.tsvdq(A, Q, k)
+    gamma = np.sum(r.s ** 2) / np.sum(r.s_all ** 2)
+    rho, Ak2 = oracle.tsvdq_ii(A, Q, gamma)
+    assert rho.sum() <= k * 5
+    assert oracle.fro2(A - Ak2) <= oracle.fro2(A - r.Ak) + 1e-10
+    rho1, Ak1 = oracle.tsvdq_ii(A, Q, 1.0)
+    np.testing.assert_allclose(Ak1, oracle.proj(A, Q), atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Gradients: central finite differences and torch CPU float64 autograd
+# ---------------------------------------------------------------------------
+
+def _loss(A, B, Q, T):
+    return oracle.fro2(oracle.qprod(A, B, Q) - T)
+
+
+def test_qprod_backward_finite_differences():
+    rng = np.random.default_rng(15)
+    A = rng.standard_normal((4, 3, 7))
+    B = rng.standard_normal((3, 5, 7))
+    Q = synth.random_orthonormal(rng, 7, 3)
+    T = rng.standard_normal((4, 5, 7))
+    G = 2 * (oracle.qprod(A, B, Q) - T)
+    dA, dB, dQ = oracle.qprod_backward(G, A, B, Q)
+    for X, dX, h, tol in ((A, dA, 1e-3, 1e-9), (B, dB, 1e-3, 1e-9), (Q, dQ, 1e-5, 1e-6)):
+        for _ in range(6):
+            D = rng.standard_normal(X.shape)
+            D /= np.linalg.norm(D)
+            Xp, Xm = X + h * D, X - h * D
+            args_p = [Xp if Y is X else Y for Y in (A, B, Q)]
+            args_m = [Xm if Y is X else Y for Y in (A, B, Q)]
+            fd = (_loss(*args_p, T) - _loss(*args_m, T)) / (2 * h)
+            assert fd == pytest.approx(np.sum(dX * D), rel=tol, abs=tol)
+
+
+def test_proj_backward_finite_differences():
+    rng = np.random.default_rng(16)
+    A = rng.standard_normal((4, 3, 9))
+    Q = synth.random_orthonormal(rng, 9, 4)
+    T = rng.standard_normal((4, 3, 9))
+    L = lambda A_, Q_: oracle.fro2(oracle.proj(A_, Q_) - T)
+    G = 2 * (oracle.proj(A, Q) - T)
+    dA, dQ = oracle.proj_backward(G, A, Q)
+    for X, dX, h in ((A, dA, 1e-3), (Q, dQ, 1e-5)):
+        for _ in range(6):
+            D = rng.standard_normal(X.shape)
+            D /= np.linalg.norm(D)
+            if X is A:
+                fd = (L(A + h * D, Q) - L(A - h * D, Q)) / (2 * h)
+            else:
+                fd = (L(A, Q + h * D) - L(A, Q - h * D)) / (2 * h)
+            assert fd == pytest.approx(np.sum(dX * D), rel=1e-6, abs=1e-6)
+
+
+def test_qprod_backward_torch_autograd():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal((5, 4, 8))
+    B = rng.standard_normal((4, 6, 8))
+    Q = synth.random_orthonormal(rng, 8, 3)
+    T = rng.standard_normal((5, 6, 8))
+    tA, tB, tQ = (torch.tensor(x, dtype=torch.float64, requires_grad=True) for x in (A, B, Q))
+    Ah = torch.einsum("irt,tl->irl", tA, tQ)
+    Bh = torch.einsum("rjt,tl->rjl", tB, tQ)
+    Ch = torch.einsum("irl,rjl->ijl", Ah, Bh)
+    C = torch.einsum("ijl,tl->ijt", Ch, tQ)
+    loss = ((C - torch.tensor(T)) ** 2).sum()
+    loss.backward()
+    G = 2 * (oracle.qprod(A, B, Q) - T)
+    dA, dB, dQ = oracle.qprod_backward(G, A, B, Q)
+    np.testing.assert_allclose(dA, tA.grad.numpy(), rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(dB, tB.grad.numpy(), rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(dQ, tQ.grad.numpy(), rtol=1e-11, atol=1e-11)
+
+
+def test_check_q_closed_form():
+    d = 0.25
+    Q = np.array([[1.0, d], [0.0, 1.0], [0.0, 0.0]])
+    # Q^T Q - I = [[0, d], [d, d^2]]
+    assert oracle.check_q(Q) == pytest.approx(d)
+    assert oracle.check_q(np.eye(5)[:, :3]) == 0.0
+
+
+def test_synth_generators_shapes_and_structure():
+    rng = np.random.default_rng(0)
+    Q = synth.random_orthonormal(rng, 16, 4)
+    assert np.allclose(Q.T @ Q, np.eye(4))
+    bits = synth.bf16_bits(np.array([1.0, 1.00390625, 1.01171875, -2.5], np.float32))
+    # 1+2^-8 is a tie -> even (1.0); 1+3*2^-8 is a tie -> even (1+2^-6... 0x3f82)
+    assert list(bits) == [0x3F80, 0x3F80, 0x3F82, 0xC020]
+    v = synth.video(np.random.default_rng(1), 24, 32, 20, components=3)
+    assert v.shape == (20, 32, 24) and v.dtype == np.float32
+    shapes = synth.batched_shapes(count=8)
+    assert all(4 <= s["p"] <= min(32, s["n3"]) for s in shapes)
