@@ -1,0 +1,219 @@
+/*
+ * projprod.h — C ABI of the MI355X (gfx950) library for the projected
+ * tensor-tensor product *_Q and the truncated tSVDQ built on it
+ * (Keegan & Newman, "Projected Tensor-Tensor Products for Efficient
+ * Computation of Optimal Multiway Data Representations", arXiv:2409.19402).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Tensors are real, third order, stored FACE-MAJOR: element (i, j, t) of an
+ * n1 x n2 x n3 tensor sits at offset i + j*n1 + t*n1*n2 (0-based; the
+ * column order of the mode-3 unfolding, Def. 2.1).  Each frontal slice is a
+ * contiguous column-major n1 x n2 matrix, and row t of the n3 x (n1 n2)
+ * row-major matrix seen by the kernels is frontal slice t.
+ *
+ * Q is an n3 x p matrix with orthonormal columns (Q in St_{n3,p}, Def. 3.1),
+ * stored ROW-MAJOR: Q(t, l) at t*p + l.  1 <= p <= n3.
+ *
+ * Every pointer argument is a DEVICE pointer owned by the caller, except where
+ * a comment says "host".  Entry points never allocate and never synchronise;
+ * all work is enqueued on `stream` in order.  Inputs are read only; outputs
+ * must not overlap inputs (PQ_ERR_ALIAS is returned for exact pointer
+ * equality; partial overlap is the caller's responsibility).  Scratch memory
+ * is passed in `ws` (device, 256-byte aligned) of `ws_bytes` bytes; the
+ * matching *_workspace query returns the size needed.  The return value
+ * reports errors the host can detect (shapes, dtypes, null pointers, too
+ * small a workspace, a failed launch); nothing is launched when it is not
+ * PQ_OK.  Conditions only the device can see (Jacobi non-convergence) are
+ * written to device memory the caller passes.
+ *
+ * Data types (dtype arguments): PQ_F32, PQ_F64, PQ_BF16 (bfloat16 bit
+ * patterns, inputs only).  A float64 call keeps every operand and result in
+ * float64.  A float32 call takes float32 or bfloat16 tensor inputs, float32 Q
+ * and writes float32 results.
+ *
+ * Precision modes (prec arguments, float32 calls only) select how the dense
+ * contractions run on the matrix cores:
+ *   PQ_PREC_DEFAULT  float32 MFMA (float64 calls: float64 arithmetic)
+ *   PQ_PREC_BF16     one bfloat16 MFMA pass, float32 accumulation
+ *   PQ_PREC_BF16X3   split-bfloat16 compensated products, x = x_hi + x_lo,
+ *                    x*y ~ x_hi y_hi + x_hi y_lo + x_lo y_hi (3 passes); when
+ *                    the tensor operand is already bfloat16 the other operand
+ *                    is split three ways instead, which is exact in float32
+ *   PQ_PREC_BF16X6   three-way split of both operands, 6 passes
+ */
+#ifndef PROJPROD_H
+#define PROJPROD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define PQ_OK               0
+#define PQ_ERR_NULL        -1  /* a required pointer is NULL                     */
+#define PQ_ERR_SHAPE       -2  /* a size is < 1, or sizes do not agree           */
+#define PQ_ERR_P           -3  /* p < 1 or p > n3                                */
+#define PQ_ERR_K           -4  /* k < 1 or k > min(n1, n2)                       */
+#define PQ_ERR_DTYPE       -5  /* unsupported dtype combination                  */
+#define PQ_ERR_PREC        -6  /* unsupported precision mode for this call       */
+#define PQ_ERR_ALIAS       -7  /* an output pointer equals an input pointer      */
+#define PQ_ERR_WORKSPACE   -8  /* ws is NULL or ws_bytes too small               */
+#define PQ_ERR_HIP         -9  /* a kernel launch failed (see pq_last_hip_error) */
+#define PQ_ERR_UNSUPPORTED -10 /* size beyond what this build supports          */
+#define PQ_ERR_ARG         -11 /* another argument out of range                  */
+
+/* ---- dtypes and precision modes ------------------------------------------ */
+#define PQ_F32  0
+#define PQ_F64  1
+#define PQ_BF16 2
+
+#define PQ_PREC_DEFAULT 0
+#define PQ_PREC_BF16    1
+#define PQ_PREC_BF16X3  2
+#define PQ_PREC_BF16X6  3
+
+/* Library version (major*10000 + minor*100 + patch). */
+int pq_version(void);
+
+/* Static text for a status code; never NULL. */
+const char* pq_status_string(int code);
+
+/* The hipError_t of the last failed launch on the calling thread (0 if none). */
+int pq_last_hip_error(void);
+
+/* ---- Q intake ------------------------------------------------------------ */
+/*
+ * Distance of Q from the Stiefel manifold, max_ij |(Q^T Q - I_p)_ij|, in
+ * float64 (precondition Q in St_{n3,p} of Def. 3.1).  q_dtype is PQ_F32 or
+ * PQ_F64.  Writes one double to out_dev.  Workspace: none.
+ */
+int pq_check_q(const void* Q, int q_dtype, int64_t n3, int64_t p,
+               double* out_dev, hipStream_t stream);
+
+/* ---- mode-3 transforms (Def. 2.2 with M = Q^T and M = Q) ----------------- */
+/*
+ * Ahat = A x_3 Q^T (the "hat" transform after Def. 3.1; Alg. 4.1 step 2).
+ * A: n1 x n2 x n3 face-major, dtype a_dtype (F32, BF16 or F64).
+ * Ahat: n1 x n2 x p face-major, float32 (float64 when a_dtype is F64).
+ */
+int pq_hat(const void* A, int a_dtype, const void* Q, void* Ahat,
+           int64_t n1, int64_t n2, int64_t n3, int64_t p, int prec,
+           hipStream_t stream);
+
+/*
+ * A = Ahat x_3 Q (the return to the spatial domain in Def. 3.1 and
+ * Alg. 4.1 step 4).  Ahat: n1 x n2 x p; A: n1 x n2 x n3; both of dtype
+ * (F32 or F64).
+ */
+int pq_unhat(const void* Ahat, const void* Q, void* A, int dtype,
+             int64_t n1, int64_t n2, int64_t n3, int64_t p, int prec,
+             hipStream_t stream);
+
+/*
+ * out = A x_3 Q Q^T, the orthogonal projection of every tube onto range(Q)
+ * (the remark after Fig. 3.1).  A: a_dtype (F32, BF16 or F64); out float32
+ * (float64 for F64).  Fused into one pass over A when p <= 32; otherwise it
+ * needs pq_proj_workspace bytes of ws.
+ */
+size_t pq_proj_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int a_dtype);
+int pq_proj(const void* A, int a_dtype, const void* Q, void* out,
+            int64_t n1, int64_t n2, int64_t n3, int64_t p, int prec,
+            void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- facewise product (Def. 2.3) ----------------------------------------- */
+/*
+ * Ch(:,:,l) = Ah(:,:,l) Bh(:,:,l) for l < p.  Ah: n1 x m x p, Bh: m x n2 x p,
+ * Ch: n1 x n2 x p, all face-major, dtype F32 or F64.
+ */
+int pq_facewise(const void* Ah, const void* Bh, void* Ch, int dtype,
+                int64_t n1, int64_t m, int64_t n2, int64_t p, int prec,
+                hipStream_t stream);
+
+/* ---- the projected product (Def. 3.1) ------------------------------------ */
+/*
+ * C = A *_Q B = [(A x_3 Q^T) tri (B x_3 Q^T)] x_3 Q.
+ * A: n1 x m x n3, B: m x n2 x n3 (ab_dtype F32, BF16 or F64; both the same),
+ * C: n1 x n2 x n3 (float32, or float64 for F64).
+ * Ahat_out (n1 x m x p) and Bhat_out (m x n2 x p) are optional (NULL = not
+ * wanted); when given, the transform-domain inputs are left there for a later
+ * pq_qprod_backward.  Workspace: pq_qprod_workspace bytes.
+ */
+size_t pq_qprod_workspace(int64_t n1, int64_t m, int64_t n2, int64_t n3, int64_t p,
+                          int ab_dtype);
+int pq_qprod(const void* A, const void* B, int ab_dtype, const void* Q, void* C,
+             int64_t n1, int64_t m, int64_t n2, int64_t n3, int64_t p, int prec,
+             void* Ahat_out, void* Bhat_out,
+             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adjoint of pq_qprod (chain rule through Def. 3.1).  G = dL/dC is
+ * n1 x n2 x n3.  With dCh = G x_3 Q^T:
+ *   dAh_l = dCh_l Bh_l^T,  dBh_l = Ah_l^T dCh_l,  dA = dAh x_3 Q,
+ *   dB = dBh x_3 Q,  dQ = G_(3) Ch_(3)^T + A_(3) dAh_(3)^T + B_(3) dBh_(3)^T.
+ * dA (n1 x m x n3), dB (m x n2 x n3), dQ (n3 x p row-major) may each be NULL
+ * (= not needed).  Ahat/Bhat may be NULL, in which case they are recomputed.
+ * dtype F32 or F64 for every operand.  dQ is reduced in a fixed order, so
+ * repeated calls give bit-identical results.  Workspace:
+ * pq_qprod_backward_workspace bytes.
+ */
+size_t pq_qprod_backward_workspace(int64_t n1, int64_t m, int64_t n2, int64_t n3,
+                                   int64_t p, int dtype);
+int pq_qprod_backward(const void* G, const void* A, const void* B, const void* Q,
+                      const void* Ahat, const void* Bhat, int dtype,
+                      int64_t n1, int64_t m, int64_t n2, int64_t n3, int64_t p,
+                      void* dA, void* dB, void* dQ,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adjoint of pq_proj: dA = G x_3 Q Q^T, dQ = G_(3) A_(3)^T Q + A_(3) G_(3)^T Q.
+ * dA or dQ may be NULL.  dtype F32 or F64.  Workspace:
+ * pq_proj_backward_workspace bytes.
+ */
+size_t pq_proj_backward_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int dtype);
+int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
+                     int64_t n1, int64_t n2, int64_t n3, int64_t p,
+                     void* dA, void* dQ, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+
+/* ---- truncated tSVDQ (Alg. 4.1) ------------------------------------------ */
+/*
+ * Truncated *_Q-SVD of A (n1 x n2 x n3, a_dtype F32, BF16 or F64) with rank
+ * k per face, 1 <= k <= min(n1, n2).
+ *   step 2: Ahat = A x_3 Q^T;
+ *   step 3: every face Ahat_l ~ Uhat_l diag(s_l) Vhat_l^T, the exact rank-k
+ *           truncation (one-sided Jacobi, rotation angles in float64);
+ *   step 4 (optional outputs): Uk = Uhat x_3 Q, the diagonal tubes of
+ *           S_k = Shat x_3 Q, Vk = Vhat x_3 Q, and the approximation
+ *           A_k = (Uhat tri Shat tri Vhat^T) x_3 Q of Thm. 4.2.
+ * Outputs (float32, or float64 for F64):
+ *   Uhat n1 x k x p, s k x p (element (j, l) at j + l*k, descending in j),
+ *   Vhat n2 x k x p — required;
+ *   Uk n1 x k x n3, Sk k x n3 (element (j, t) at j + t*k), Vk n2 x k x n3,
+ *   Ak n1 x n2 x n3 — each optional (NULL).
+ * Singular vectors of a face whose singular value is zero (rank-deficient
+ * faces) are written as zero vectors.  tol is the Jacobi stopping threshold
+ * on |a_i . a_j| / (|a_i| |a_j|) (<= 0 selects the default for the dtype),
+ * max_sweeps caps the sweeps (<= 0: default 30).  info_dev (device int[2],
+ * may be NULL) receives [0] = the largest number of sweeps any face used and
+ * [1] = the number of faces that hit max_sweeps before converging (their
+ * outputs are still written).  Workspace: pq_tsvdq_workspace bytes.
+ */
+size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k,
+                          int a_dtype);
+int pq_tsvdq(const void* A, int a_dtype, const void* Q,
+             int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k, int prec,
+             void* Uhat, void* s, void* Vhat,
+             void* Uk, void* Sk, void* Vk, void* Ak,
+             double tol, int max_sweeps, int* info_dev,
+             void* ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROJPROD_H */

@@ -1,0 +1,297 @@
+"""Python binding of the projprod C ABI: argument checks and marshalling only.
+
+Tensors are torch tensors on a ROCm device, indexed like the paper,
+X[i, j, t] for an n1 x n2 x n3 tensor, and stored face-major (strides
+(1, n1, n1*n2)): ``empty(n1, n2, n3)`` makes one, ``from_storage(S)`` views a
+contiguous (n3, n2, n1) tensor as one.  Q is a contiguous (n3, p) tensor.
+float32, bfloat16 (inputs) and float64 are accepted; results are float32
+(float64 for float64 inputs).  Every call is enqueued on the current stream;
+PyTorch only provides memory and the stream, the arithmetic runs in the HIP
+kernels of libprojprod.so.
+"""
+
+from collections import namedtuple
+
+import torch
+
+from . import _lib
+from ._lib import PQ_F32, PQ_F64, PQ_BF16, PREC, call
+
+__all__ = [
+    "empty", "from_storage", "is_face_major", "check_q", "hat", "unhat", "proj", "facewise",
+    "qprod", "qprod_backward", "proj_backward", "tsvdq", "TSVDQ", "QProd", "Proj",
+]
+
+_DT = {torch.float32: PQ_F32, torch.float64: PQ_F64, torch.bfloat16: PQ_BF16}
+
+
+def _stream(device):
+    return ctypes_stream(torch.cuda.current_stream(device))
+
+
+def ctypes_stream(s):
+    return s.cuda_stream
+
+
+def empty(n1, n2, n3, dtype=torch.float32, device="cuda"):
+    """An uninitialised face-major n1 x n2 x n3 tensor."""
+    return torch.empty((n3, n2, n1), dtype=dtype, device=device).permute(2, 1, 0)
+
+
+def from_storage(S):
+    """View a contiguous (n3, n2, n1) tensor as the face-major n1 x n2 x n3 tensor."""
+    if S.dim() != 3 or not S.is_contiguous():
+        raise ValueError("from_storage expects a contiguous 3-d tensor")
+    return S.permute(2, 1, 0)
+
+
+def is_face_major(X):
+    if X.dim() != 3:
+        return False
+    n1, n2, n3 = X.shape
+    want = (1, n1, n1 * n2)
+    return all(s == w or d == 1 for s, w, d in zip(X.stride(), want, X.shape))
+
+
+def _tensor(X, name, dtypes=(torch.float32, torch.float64, torch.bfloat16)):
+    if not isinstance(X, torch.Tensor) or X.device.type != "cuda":
+        raise TypeError(f"{name} must be a torch tensor on a ROCm device")
+    if X.dtype not in dtypes:
+        raise TypeError(f"{name}: dtype {X.dtype} not supported")
+    if not is_face_major(X):
+        raise ValueError(f"{name} must be face-major (strides (1, n1, n1*n2)); "
+                         "see binding.empty / binding.from_storage")
+    return X
+
+
+def _q(Q, dtype):
+    if not isinstance(Q, torch.Tensor) or Q.device.type != "cuda" or Q.dim() != 2:
+        raise TypeError("Q must be a 2-d torch tensor (n3, p) on a ROCm device")
+    want = torch.float64 if dtype == torch.float64 else torch.float32
+    if Q.dtype != want:
+        raise TypeError(f"Q must be {want} for {dtype} data")
+    if not Q.is_contiguous():
+        raise ValueError("Q must be a contiguous (n3, p) tensor (row-major)")
+    return Q
+
+
+def _out_dtype(dtype):
+    return torch.float64 if dtype == torch.float64 else torch.float32
+
+
+def _ws(nbytes, device):
+    if nbytes == 0:
+        return None, 0
+    buf = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+    return buf, int(nbytes)
+
+
+def _ptr(X):
+    return None if X is None else X.data_ptr()
+
+
+def check_q(Q):
+    """float64 max |Q^T Q - I| as a 0-d device tensor (Def. 3.1 precondition)."""
+    if Q.dtype not in (torch.float32, torch.float64):
+        raise TypeError("Q must be float32 or float64")
+    Q = _q(Q, Q.dtype)
+    out = torch.empty((), dtype=torch.float64, device=Q.device)
+    call("pq_check_q", _ptr(Q), _DT[Q.dtype], Q.shape[0], Q.shape[1], _ptr(out), _stream(Q.device))
+    return out
+
+
+def hat(A, Q, prec="default"):
+    """A x_3 Q^T: n1 x n2 x p transform-domain tensor."""
+    _tensor(A, "A")
+    _q(Q, A.dtype)
+    n1, n2, n3 = A.shape
+    if Q.shape[0] != n3:
+        raise ValueError("Q must have n3 rows")
+    p = Q.shape[1]
+    Ah = empty(n1, n2, p, _out_dtype(A.dtype), A.device)
+    call("pq_hat", _ptr(A), _DT[A.dtype], _ptr(Q), _ptr(Ah), n1, n2, n3, p, PREC[prec],
+         _stream(A.device))
+    return Ah
+
+
+def unhat(Ah, Q, prec="default"):
+    """Ah x_3 Q: back to the spatial domain, n1 x n2 x n3."""
+    _tensor(Ah, "Ahat", (torch.float32, torch.float64))
+    _q(Q, Ah.dtype)
+    n1, n2, p = Ah.shape
+    n3 = Q.shape[0]
+    if Q.shape[1] != p:
+        raise ValueError("Q must have p columns")
+    A = empty(n1, n2, n3, Ah.dtype, Ah.device)
+    call("pq_unhat", _ptr(Ah), _ptr(Q), _ptr(A), _DT[Ah.dtype], n1, n2, n3, p, PREC[prec],
+         _stream(Ah.device))
+    return A
+
+
+def _proj_fwd(A, Q, prec):
+    _tensor(A, "A")
+    _q(Q, A.dtype)
+    n1, n2, n3 = A.shape
+    p = Q.shape[1]
+    if Q.shape[0] != n3:
+        raise ValueError("Q must have n3 rows")
+    out = empty(n1, n2, n3, _out_dtype(A.dtype), A.device)
+    lib = _lib.load()
+    wsb, nb = _ws(lib.pq_proj_workspace(n1, n2, n3, p, _DT[A.dtype]), A.device)
+    call("pq_proj", _ptr(A), _DT[A.dtype], _ptr(Q), _ptr(out), n1, n2, n3, p, PREC[prec],
+         _ptr(wsb), nb, _stream(A.device))
+    return out
+
+
+def facewise(Ah, Bh, prec="default"):
+    """Facewise product (Def. 2.3) of two n1 x m x p and m x n2 x p tensors."""
+    _tensor(Ah, "Ahat", (torch.float32, torch.float64))
+    _tensor(Bh, "Bhat", (Ah.dtype,))
+    n1, m, p = Ah.shape
+    if Bh.shape[0] != m or Bh.shape[2] != p:
+        raise ValueError("facewise: shapes do not agree")
+    n2 = Bh.shape[1]
+    Ch = empty(n1, n2, p, Ah.dtype, Ah.device)
+    call("pq_facewise", _ptr(Ah), _ptr(Bh), _ptr(Ch), _DT[Ah.dtype], n1, m, n2, p, PREC[prec],
+         _stream(Ah.device))
+    return Ch
+
+
+def _qprod_fwd(A, B, Q, prec, save=False):
+    _tensor(A, "A")
+    _tensor(B, "B", (A.dtype,))
+    _q(Q, A.dtype)
+    n1, m, n3 = A.shape
+    if B.shape[0] != m or B.shape[2] != n3:
+        raise ValueError("qprod: A is n1 x m x n3 and B must be m x n2 x n3")
+    n2 = B.shape[1]
+    if Q.shape[0] != n3:
+        raise ValueError("Q must have n3 rows")
+    p = Q.shape[1]
+    od = _out_dtype(A.dtype)
+    C = empty(n1, n2, n3, od, A.device)
+    Ah = empty(n1, m, p, od, A.device) if save else None
+    Bh = empty(m, n2, p, od, A.device) if save else None
+    lib = _lib.load()
+    wsb, nb = _ws(lib.pq_qprod_workspace(n1, m, n2, n3, p, _DT[A.dtype]), A.device)
+    call("pq_qprod", _ptr(A), _ptr(B), _DT[A.dtype], _ptr(Q), _ptr(C), n1, m, n2, n3, p,
+         PREC[prec], _ptr(Ah), _ptr(Bh), _ptr(wsb), nb, _stream(A.device))
+    return C, Ah, Bh
+
+
+def _face_major(G):
+    # the adjoint kernels read face-major storage; autograd may hand over any layout
+    return G if is_face_major(G) else G.permute(2, 1, 0).contiguous().permute(2, 1, 0)
+
+
+def qprod_backward(G, A, B, Q, Ahat=None, Bhat=None, need=(True, True, True)):
+    """(dA, dB, dQ) of L given G = dL/dC for C = A *_Q B; entries of `need`
+    that are False come back as None."""
+    for X, nm in ((G, "G"), (A, "A"), (B, "B")):
+        _tensor(X, nm, (torch.float32, torch.float64))
+    _q(Q, A.dtype)
+    n1, m, n3 = A.shape
+    n2 = B.shape[1]
+    p = Q.shape[1]
+    dt = A.dtype
+    dA = empty(n1, m, n3, dt, A.device) if need[0] else None
+    dB = empty(m, n2, n3, dt, A.device) if need[1] else None
+    dQ = torch.empty((n3, p), dtype=dt, device=A.device) if need[2] else None
+    lib = _lib.load()
+    wsb, nb = _ws(lib.pq_qprod_backward_workspace(n1, m, n2, n3, p, _DT[dt]), A.device)
+    call("pq_qprod_backward", _ptr(G), _ptr(A), _ptr(B), _ptr(Q), _ptr(Ahat), _ptr(Bhat), _DT[dt],
+         n1, m, n2, n3, p, _ptr(dA), _ptr(dB), _ptr(dQ), _ptr(wsb), nb, _stream(A.device))
+    return dA, dB, dQ
+
+
+def proj_backward(G, A, Q, need=(True, True)):
+    _tensor(G, "G", (torch.float32, torch.float64))
+    _tensor(A, "A", (G.dtype,))
+    _q(Q, G.dtype)
+    n1, n2, n3 = A.shape
+    p = Q.shape[1]
+    dA = empty(n1, n2, n3, G.dtype, G.device) if need[0] else None
+    dQ = torch.empty((n3, p), dtype=G.dtype, device=G.device) if need[1] else None
+    lib = _lib.load()
+    wsb, nb = _ws(lib.pq_proj_backward_workspace(n1, n2, n3, p, _DT[G.dtype]), G.device)
+    call("pq_proj_backward", _ptr(G), _ptr(A), _ptr(Q), _DT[G.dtype], n1, n2, n3, p, _ptr(dA),
+         _ptr(dQ), _ptr(wsb), nb, _stream(G.device))
+    return dA, dQ
+
+
+class QProd(torch.autograd.Function):
+    """C = A *_Q B (Def. 3.1) with the hand-written adjoint for dA, dB, dQ."""
+
+    @staticmethod
+    def forward(ctx, A, B, Q, prec="default"):
+        C, Ah, Bh = _qprod_fwd(A, B, Q, prec, save=True)
+        ctx.save_for_backward(A, B, Q, Ah, Bh)
+        return C
+
+    @staticmethod
+    def backward(ctx, G):
+        A, B, Q, Ah, Bh = ctx.saved_tensors
+        need = ctx.needs_input_grad[:3]
+        dA, dB, dQ = qprod_backward(_face_major(G.to(Ah.dtype)), A, B, Q, Ah, Bh, need)
+        return dA, dB, dQ, None
+
+
+class Proj(torch.autograd.Function):
+    """A x_3 Q Q^T with the hand-written adjoint for dA and dQ."""
+
+    @staticmethod
+    def forward(ctx, A, Q, prec="default"):
+        ctx.save_for_backward(A, Q)
+        return _proj_fwd(A, Q, prec)
+
+    @staticmethod
+    def backward(ctx, G):
+        A, Q = ctx.saved_tensors
+        need = ctx.needs_input_grad[:2]
+        dA, dQ = proj_backward(_face_major(G.to(Q.dtype)), A, Q, need)
+        return dA, dQ, None
+
+
+def qprod(A, B, Q, prec="default"):
+    """A *_Q B (Def. 3.1); differentiable in A, B and Q (float32/float64)."""
+    if torch.is_grad_enabled() and any(x.requires_grad for x in (A, B, Q)):
+        return QProd.apply(A, B, Q, prec)
+    return _qprod_fwd(A, B, Q, prec)[0]
+
+
+def proj(A, Q, prec="default"):
+    """A x_3 Q Q^T; differentiable in A and Q (float32/float64)."""
+    if torch.is_grad_enabled() and any(x.requires_grad for x in (A, Q)):
+        return Proj.apply(A, Q, prec)
+    return _proj_fwd(A, Q, prec)
+
+
+TSVDQ = namedtuple("TSVDQ", "Uhat s Vhat Uk Sk Vk Ak info")
+
+
+def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_sweeps=0):
+    """Truncated *_Q-SVD (Alg. 4.1).  Returns TSVDQ(Uhat n1 x k x p,
+    s (k, p), Vhat n2 x k x p, Uk, Sk (k, n3), Vk [spatial=True], Ak
+    [approx=True], info = int32 device tensor [max sweeps, unconverged faces])."""
+    _tensor(A, "A")
+    _q(Q, A.dtype)
+    n1, n2, n3 = A.shape
+    if Q.shape[0] != n3:
+        raise ValueError("Q must have n3 rows")
+    p = Q.shape[1]
+    od = _out_dtype(A.dtype)
+    dev = A.device
+    Uh = empty(n1, k, p, od, dev)
+    Vh = empty(n2, k, p, od, dev)
+    s = torch.empty((p, k), dtype=od, device=dev)
+    Uk = empty(n1, k, n3, od, dev) if spatial else None
+    Vk = empty(n2, k, n3, od, dev) if spatial else None
+    Sk = torch.empty((n3, k), dtype=od, device=dev) if spatial else None
+    Ak = empty(n1, n2, n3, od, dev) if approx else None
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    lib = _lib.load()
+    wsb, nb = _ws(lib.pq_tsvdq_workspace(n1, n2, n3, p, k, _DT[A.dtype]), dev)
+    call("pq_tsvdq", _ptr(A), _DT[A.dtype], _ptr(Q), n1, n2, n3, p, k, PREC[prec], _ptr(Uh),
+         _ptr(s), _ptr(Vh), _ptr(Uk), _ptr(Sk), _ptr(Vk), _ptr(Ak), float(tol), int(max_sweeps),
+         _ptr(info), _ptr(wsb), nb, _stream(dev))
+    return TSVDQ(Uh, s.t(), Vh, Uk, None if Sk is None else Sk.t(), Vk, Ak, info)

@@ -1,0 +1,495 @@
+// C ABI of the projprod library: argument validation, workspace layout and
+// the order of kernel launches for each call.  Every step of every call runs
+// in the kernels of this library; nothing here touches tensor data.
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/projprod.h"
+#include "internal.hpp"
+
+using pq::Gemm;
+using pq::Prec;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return PQ_OK;
+  g_last_hip = static_cast<int>(e);
+  return PQ_ERR_HIP;
+}
+
+#define PQ_TRY(expr)                        \
+  do {                                      \
+    int _rc = hip_status(expr);             \
+    if (_rc != PQ_OK) return _rc;           \
+  } while (0)
+
+#define PQ_CHECK(expr)                      \
+  do {                                      \
+    int _rc = (expr);                       \
+    if (_rc != PQ_OK) return _rc;           \
+  } while (0)
+
+constexpr int64_t kMaxDim = (int64_t)1 << 30;
+
+int check_dims(std::initializer_list<int64_t> dims) {
+  for (int64_t d : dims)
+    if (d < 1) return PQ_ERR_SHAPE;
+  for (int64_t d : dims)
+    if (d > kMaxDim) return PQ_ERR_UNSUPPORTED;
+  return PQ_OK;
+}
+
+int check_p(int64_t n3, int64_t p) { return (p < 1 || p > n3) ? PQ_ERR_P : PQ_OK; }
+
+// elements of an area must stay addressable with 32-bit GEMM sizes
+int check_area(int64_t a, int64_t b) { return (a * b >= ((int64_t)1 << 31)) ? PQ_ERR_UNSUPPORTED : PQ_OK; }
+
+bool is_f64(int dtype) { return dtype == PQ_F64; }
+size_t elem(int dtype) { return dtype == PQ_F64 ? 8 : 4; }
+
+// tensor input dtype (F32, BF16 or F64)
+int check_in_dtype(int dt) { return (dt == PQ_F32 || dt == PQ_F64 || dt == PQ_BF16) ? PQ_OK : PQ_ERR_DTYPE; }
+// dtype of arithmetic-only arguments (F32 or F64)
+int check_ar_dtype(int dt) { return (dt == PQ_F32 || dt == PQ_F64) ? PQ_OK : PQ_ERR_DTYPE; }
+
+int check_prec(int prec, int dtype) {
+  if (prec < PQ_PREC_DEFAULT || prec > PQ_PREC_BF16X6) return PQ_ERR_PREC;
+  if (dtype == PQ_F64 && prec != PQ_PREC_DEFAULT) return PQ_ERR_PREC;
+  if (prec != PQ_PREC_DEFAULT) return PQ_ERR_PREC;  // matrix-core bfloat16 modes: see pq_version notes
+  return PQ_OK;
+}
+
+int no_alias(const void* out, std::initializer_list<const void*> ins) {
+  if (!out) return PQ_OK;
+  for (const void* in : ins)
+    if (in && in == out) return PQ_ERR_ALIAS;
+  return PQ_OK;
+}
+
+// Bump allocator over the caller's workspace.
+struct Arena {
+  char* base;
+  size_t cap, used = 0;
+  Arena(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  void* take(size_t bytes) {
+    void* p = base ? base + used : nullptr;
+    used += align_up(bytes);
+    return p;
+  }
+  bool fits() const { return used <= cap; }
+};
+
+int ksplit_for(int64_t K) { return (int)std::clamp<int64_t>(K / 512, 1, 1024); }
+
+// ---- dispatch by dtype -------------------------------------------------------
+hipError_t do_hat(const void* A, int a_dtype, const void* Q, void* Ah, int64_t N, int n3, int p,
+                  Prec prec, hipStream_t s) {
+  if (a_dtype == PQ_F64)
+    return pq::hat_f64(static_cast<const double*>(A), static_cast<const double*>(Q),
+                       static_cast<double*>(Ah), N, n3, p, s);
+  return pq::hat_f32(A, a_dtype == PQ_BF16, static_cast<const float*>(Q), static_cast<float*>(Ah), N,
+                     n3, p, prec, s);
+}
+
+hipError_t do_unhat(const void* Ah, const void* Q, void* A, int dtype, int64_t N, int n3, int p,
+                    Prec prec, hipStream_t s) {
+  if (dtype == PQ_F64)
+    return pq::unhat_f64(static_cast<const double*>(Ah), static_cast<const double*>(Q),
+                         static_cast<double*>(A), N, n3, p, s);
+  return pq::unhat_f32(static_cast<const float*>(Ah), static_cast<const float*>(Q),
+                       static_cast<float*>(A), N, n3, p, prec, s);
+}
+
+hipError_t do_gemm(const Gemm& g, int dtype, Prec prec, hipStream_t s) {
+  return dtype == PQ_F64 ? pq::gemm_f64(g, s) : pq::gemm_f32(g, prec, s);
+}
+
+hipError_t do_sum(const void* parts, int nparts, int64_t stride, int64_t count, void* out, int dtype,
+                  hipStream_t s) {
+  if (dtype == PQ_F64)
+    return pq::sum_partials_f64(static_cast<const double*>(parts), nparts, stride, count,
+                                static_cast<double*>(out), s);
+  return pq::sum_partials_f32(static_cast<const float*>(parts), nparts, stride, count,
+                              static_cast<float*>(out), s);
+}
+
+// Facewise C_l = op(A_l) op(B_l) over p faces with face-major operands.
+Gemm face_gemm(bool ta, bool tb, int M, int N, int K, const void* A, int64_t lda, int64_t sA,
+               const void* B, int64_t ldb, int64_t sB, void* C, int64_t ldc, int64_t sC, int p) {
+  Gemm g{};
+  g.ta = ta; g.tb = tb; g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.sA = sA;
+  g.B = B; g.ldb = ldb; g.sB = sB;
+  g.C = C; g.ldc = ldc; g.sC = sC;
+  g.batch = p; g.ksplit = 1; g.sSplit = 0;
+  return g;
+}
+
+// dQ^T (p x n3, column-major = dQ row-major) partial: Xh_(3) (p x K) times
+// Y_(3)^T (K x n3); both operands are row-major (rows x K) in storage.
+Gemm dq_gemm(const void* Xh, const void* Y, int p, int n3, int64_t K, void* parts, int ks) {
+  Gemm g{};
+  g.ta = true; g.tb = false; g.M = p; g.N = n3; g.K = (int)K;
+  g.A = Xh; g.lda = K; g.sA = 0;
+  g.B = Y; g.ldb = K; g.sB = 0;
+  g.C = parts; g.ldc = p; g.sC = 0;
+  g.batch = 1; g.ksplit = ks; g.sSplit = (int64_t)p * n3;
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pq_version(void) { return 100; }
+
+const char* pq_status_string(int code) {
+  switch (code) {
+    case PQ_OK: return "ok";
+    case PQ_ERR_NULL: return "a required pointer is NULL";
+    case PQ_ERR_SHAPE: return "a size is < 1 or the sizes do not agree";
+    case PQ_ERR_P: return "p must satisfy 1 <= p <= n3";
+    case PQ_ERR_K: return "k must satisfy 1 <= k <= min(n1, n2)";
+    case PQ_ERR_DTYPE: return "unsupported dtype combination";
+    case PQ_ERR_PREC: return "unsupported precision mode for this call";
+    case PQ_ERR_ALIAS: return "an output pointer equals an input pointer";
+    case PQ_ERR_WORKSPACE: return "workspace missing or too small";
+    case PQ_ERR_HIP: return "a HIP launch failed";
+    case PQ_ERR_UNSUPPORTED: return "size beyond what this build supports";
+    case PQ_ERR_ARG: return "argument out of range";
+    default: return "unknown status code";
+  }
+}
+
+int pq_last_hip_error(void) { return g_last_hip; }
+
+int pq_check_q(const void* Q, int q_dtype, int64_t n3, int64_t p, double* out_dev, hipStream_t stream) {
+  if (!Q || !out_dev) return PQ_ERR_NULL;
+  PQ_CHECK(check_ar_dtype(q_dtype));
+  PQ_CHECK(check_dims({n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_TRY(pq::check_q_launch(Q, is_f64(q_dtype), (int)n3, (int)p, out_dev, stream));
+  return PQ_OK;
+}
+
+int pq_hat(const void* A, int a_dtype, const void* Q, void* Ahat, int64_t n1, int64_t n2, int64_t n3,
+           int64_t p, int prec, hipStream_t stream) {
+  if (!A || !Q || !Ahat) return PQ_ERR_NULL;
+  PQ_CHECK(check_in_dtype(a_dtype));
+  PQ_CHECK(check_dims({n1, n2, n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_CHECK(check_prec(prec, a_dtype));
+  PQ_CHECK(no_alias(Ahat, {A, Q}));
+  PQ_TRY(do_hat(A, a_dtype, Q, Ahat, n1 * n2, (int)n3, (int)p, (Prec)prec, stream));
+  return PQ_OK;
+}
+
+int pq_unhat(const void* Ahat, const void* Q, void* A, int dtype, int64_t n1, int64_t n2, int64_t n3,
+             int64_t p, int prec, hipStream_t stream) {
+  if (!A || !Q || !Ahat) return PQ_ERR_NULL;
+  PQ_CHECK(check_ar_dtype(dtype));
+  PQ_CHECK(check_dims({n1, n2, n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_CHECK(check_prec(prec, dtype));
+  PQ_CHECK(no_alias(A, {Ahat, Q}));
+  if (p > 512 && dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
+  PQ_TRY(do_unhat(Ahat, Q, A, dtype, n1 * n2, (int)n3, (int)p, (Prec)prec, stream));
+  return PQ_OK;
+}
+
+size_t pq_proj_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int a_dtype) {
+  if (a_dtype != PQ_F64 && pq::proj_fused_ok((int)n3, (int)p)) return 0;
+  return align_up((size_t)n1 * n2 * p * elem(a_dtype == PQ_F64 ? PQ_F64 : PQ_F32));
+}
+
+int pq_proj(const void* A, int a_dtype, const void* Q, void* out, int64_t n1, int64_t n2, int64_t n3,
+            int64_t p, int prec, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!A || !Q || !out) return PQ_ERR_NULL;
+  PQ_CHECK(check_in_dtype(a_dtype));
+  PQ_CHECK(check_dims({n1, n2, n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_CHECK(check_prec(prec, a_dtype));
+  PQ_CHECK(no_alias(out, {A, Q}));
+  const int64_t N = n1 * n2;
+  if (a_dtype != PQ_F64 && pq::proj_fused_ok((int)n3, (int)p)) {
+    PQ_TRY(pq::proj_fused_f32(A, a_dtype == PQ_BF16, static_cast<const float*>(Q),
+                              static_cast<float*>(out), N, (int)n3, (int)p, (Prec)prec, stream));
+    return PQ_OK;
+  }
+  if (p > 512 && a_dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
+  const size_t need = pq_proj_workspace(n1, n2, n3, p, a_dtype);
+  if (!ws || ws_bytes < need) return PQ_ERR_WORKSPACE;
+  const int dt = a_dtype == PQ_F64 ? PQ_F64 : PQ_F32;
+  PQ_TRY(do_hat(A, a_dtype, Q, ws, N, (int)n3, (int)p, (Prec)prec, stream));
+  PQ_TRY(do_unhat(ws, Q, out, dt, N, (int)n3, (int)p, (Prec)prec, stream));
+  return PQ_OK;
+}
+
+int pq_facewise(const void* Ah, const void* Bh, void* Ch, int dtype, int64_t n1, int64_t m, int64_t n2,
+                int64_t p, int prec, hipStream_t stream) {
+  if (!Ah || !Bh || !Ch) return PQ_ERR_NULL;
+  PQ_CHECK(check_ar_dtype(dtype));
+  PQ_CHECK(check_dims({n1, m, n2, p}));
+  PQ_CHECK(check_prec(prec, dtype));
+  PQ_CHECK(no_alias(Ch, {Ah, Bh}));
+  Gemm g = face_gemm(false, false, (int)n1, (int)n2, (int)m, Ah, n1, n1 * m, Bh, m, m * n2, Ch, n1,
+                     n1 * n2, (int)p);
+  PQ_TRY(do_gemm(g, dtype, (Prec)prec, stream));
+  return PQ_OK;
+}
+
+size_t pq_qprod_workspace(int64_t n1, int64_t m, int64_t n2, int64_t n3, int64_t p, int ab_dtype) {
+  (void)n3;
+  const size_t e = elem(ab_dtype);
+  return align_up(e * n1 * m * p) + align_up(e * m * n2 * p) + align_up(e * n1 * n2 * p);
+}
+
+int pq_qprod(const void* A, const void* B, int ab_dtype, const void* Q, void* C, int64_t n1, int64_t m,
+             int64_t n2, int64_t n3, int64_t p, int prec, void* Ahat_out, void* Bhat_out, void* ws,
+             size_t ws_bytes, hipStream_t stream) {
+  if (!A || !B || !Q || !C) return PQ_ERR_NULL;
+  PQ_CHECK(check_in_dtype(ab_dtype));
+  PQ_CHECK(check_dims({n1, m, n2, n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_CHECK(check_prec(prec, ab_dtype));
+  PQ_CHECK(no_alias(C, {A, B, Q, Ahat_out, Bhat_out}));
+  PQ_CHECK(no_alias(Ahat_out, {A, B, Q}));
+  PQ_CHECK(no_alias(Bhat_out, {A, B, Q, Ahat_out}));
+  if (p > 512 && ab_dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
+  if (!ws || ws_bytes < pq_qprod_workspace(n1, m, n2, n3, p, ab_dtype)) return PQ_ERR_WORKSPACE;
+  const int dt = ab_dtype == PQ_F64 ? PQ_F64 : PQ_F32;
+  const size_t e = elem(dt);
+  Arena ar(ws, ws_bytes);
+  void* Ah = ar.take(e * n1 * m * p);
+  void* Bh = ar.take(e * m * n2 * p);
+  void* Ch = ar.take(e * n1 * n2 * p);
+  if (Ahat_out) Ah = Ahat_out;
+  if (Bhat_out) Bh = Bhat_out;
+  const Prec pr = (Prec)prec;
+  PQ_TRY(do_hat(A, ab_dtype, Q, Ah, n1 * m, (int)n3, (int)p, pr, stream));
+  PQ_TRY(do_hat(B, ab_dtype, Q, Bh, m * n2, (int)n3, (int)p, pr, stream));
+  Gemm g = face_gemm(false, false, (int)n1, (int)n2, (int)m, Ah, n1, n1 * m, Bh, m, m * n2, Ch, n1,
+                     n1 * n2, (int)p);
+  PQ_TRY(do_gemm(g, dt, pr, stream));
+  PQ_TRY(do_unhat(Ch, Q, C, dt, n1 * n2, (int)n3, (int)p, pr, stream));
+  return PQ_OK;
+}
+
+size_t pq_qprod_backward_workspace(int64_t n1, int64_t m, int64_t n2, int64_t n3, int64_t p, int dtype) {
+  const size_t e = elem(dtype);
+  size_t bytes = align_up(e * n1 * m * p) + align_up(e * m * n2 * p)   // Ah, Bh
+                 + align_up(e * n1 * n2 * p) + align_up(e * n1 * n2 * p)  // Ch, dCh
+                 + align_up(e * n1 * m * p) + align_up(e * m * n2 * p);   // dAh, dBh
+  const int parts = ksplit_for(n1 * n2) + ksplit_for(n1 * m) + ksplit_for(m * n2);
+  bytes += align_up(e * (size_t)parts * p * n3);
+  return bytes;
+}
+
+int pq_qprod_backward(const void* G, const void* A, const void* B, const void* Q, const void* Ahat,
+                      const void* Bhat, int dtype, int64_t n1, int64_t m, int64_t n2, int64_t n3,
+                      int64_t p, void* dA, void* dB, void* dQ, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+  if (!G || !Q) return PQ_ERR_NULL;
+  if ((!Ahat || dQ) && !A) return PQ_ERR_NULL;
+  if ((!Bhat || dQ) && !B) return PQ_ERR_NULL;
+  PQ_CHECK(check_ar_dtype(dtype));
+  PQ_CHECK(check_dims({n1, m, n2, n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_CHECK(check_area(n1, n2));
+  PQ_CHECK(check_area(n1, m));
+  PQ_CHECK(check_area(m, n2));
+  for (const void* o : {dA, dB, dQ}) PQ_CHECK(no_alias(o, {G, A, B, Q, Ahat, Bhat}));
+  if ((dA && (dA == dB || dA == dQ)) || (dB && dB == dQ)) return PQ_ERR_ALIAS;
+  if (p > 512 && dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
+  if (!ws || ws_bytes < pq_qprod_backward_workspace(n1, m, n2, n3, p, dtype)) return PQ_ERR_WORKSPACE;
+  if (!dA && !dB && !dQ) return PQ_OK;
+  const size_t e = elem(dtype);
+  Arena ar(ws, ws_bytes);
+  void* Ah_ws = ar.take(e * n1 * m * p);
+  void* Bh_ws = ar.take(e * m * n2 * p);
+  void* Ch = ar.take(e * n1 * n2 * p);
+  void* dCh = ar.take(e * n1 * n2 * p);
+  void* dAh = ar.take(e * n1 * m * p);
+  void* dBh = ar.take(e * m * n2 * p);
+  const int ks1 = ksplit_for(n1 * n2), ks2 = ksplit_for(n1 * m), ks3 = ksplit_for(m * n2);
+  void* parts = ar.take(e * (size_t)(ks1 + ks2 + ks3) * p * n3);
+  const Prec pr = Prec::Default;
+  const void* Ah = Ahat;
+  const void* Bh = Bhat;
+  if (!Ah) {
+    PQ_TRY(do_hat(A, dtype, Q, Ah_ws, n1 * m, (int)n3, (int)p, pr, stream));
+    Ah = Ah_ws;
+  }
+  if (!Bh) {
+    PQ_TRY(do_hat(B, dtype, Q, Bh_ws, m * n2, (int)n3, (int)p, pr, stream));
+    Bh = Bh_ws;
+  }
+  // dCh = G x_3 Q^T
+  PQ_TRY(do_hat(G, dtype, Q, dCh, n1 * n2, (int)n3, (int)p, pr, stream));
+  const bool need_dAh = dA || dQ, need_dBh = dB || dQ;
+  if (need_dAh) {  // dAh_l = dCh_l Bh_l^T   (n1 x m)
+    Gemm g = face_gemm(false, true, (int)n1, (int)m, (int)n2, dCh, n1, n1 * n2, Bh, m, m * n2, dAh, n1,
+                       n1 * m, (int)p);
+    PQ_TRY(do_gemm(g, dtype, pr, stream));
+  }
+  if (need_dBh) {  // dBh_l = Ah_l^T dCh_l   (m x n2)
+    Gemm g = face_gemm(true, false, (int)m, (int)n2, (int)n1, Ah, n1, n1 * m, dCh, n1, n1 * n2, dBh, m,
+                       m * n2, (int)p);
+    PQ_TRY(do_gemm(g, dtype, pr, stream));
+  }
+  if (dA) PQ_TRY(do_unhat(dAh, Q, dA, dtype, n1 * m, (int)n3, (int)p, pr, stream));
+  if (dB) PQ_TRY(do_unhat(dBh, Q, dB, dtype, m * n2, (int)n3, (int)p, pr, stream));
+  if (dQ) {
+    Gemm fw = face_gemm(false, false, (int)n1, (int)n2, (int)m, Ah, n1, n1 * m, Bh, m, m * n2, Ch, n1,
+                        n1 * n2, (int)p);
+    PQ_TRY(do_gemm(fw, dtype, pr, stream));
+    char* pb = static_cast<char*>(parts);
+    const size_t slab = e * (size_t)p * n3;
+    PQ_TRY(do_gemm(dq_gemm(Ch, G, (int)p, (int)n3, n1 * n2, pb, ks1), dtype, pr, stream));
+    PQ_TRY(do_gemm(dq_gemm(dAh, A, (int)p, (int)n3, n1 * m, pb + slab * ks1, ks2), dtype, pr, stream));
+    PQ_TRY(do_gemm(dq_gemm(dBh, B, (int)p, (int)n3, m * n2, pb + slab * (ks1 + ks2), ks3), dtype, pr,
+                   stream));
+    PQ_TRY(do_sum(parts, ks1 + ks2 + ks3, p * n3, p * n3, dQ, dtype, stream));
+  }
+  return PQ_OK;
+}
+
+size_t pq_proj_backward_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int dtype) {
+  const size_t e = elem(dtype);
+  const int ks = ksplit_for(n1 * n2);
+  return align_up(e * n1 * n2 * p) * 2 + align_up(e * (size_t)2 * ks * p * n3);
+}
+
+int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype, int64_t n1, int64_t n2,
+                     int64_t n3, int64_t p, void* dA, void* dQ, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
+  if (!G || !Q || (dQ && !A)) return PQ_ERR_NULL;
+  PQ_CHECK(check_ar_dtype(dtype));
+  PQ_CHECK(check_dims({n1, n2, n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_CHECK(check_area(n1, n2));
+  for (const void* o : {dA, dQ}) PQ_CHECK(no_alias(o, {G, A, Q}));
+  if (dA && dA == dQ) return PQ_ERR_ALIAS;
+  if (p > 512 && dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
+  if (!ws || ws_bytes < pq_proj_backward_workspace(n1, n2, n3, p, dtype)) return PQ_ERR_WORKSPACE;
+  const size_t e = elem(dtype);
+  const int64_t N = n1 * n2;
+  Arena ar(ws, ws_bytes);
+  void* Ah = ar.take(e * N * p);
+  void* Gh = ar.take(e * N * p);
+  const int ks = ksplit_for(N);
+  void* parts = ar.take(e * (size_t)2 * ks * p * n3);
+  const Prec pr = Prec::Default;
+  PQ_TRY(do_hat(G, dtype, Q, Gh, N, (int)n3, (int)p, pr, stream));
+  if (dA) PQ_TRY(do_unhat(Gh, Q, dA, dtype, N, (int)n3, (int)p, pr, stream));
+  if (dQ) {
+    PQ_TRY(do_hat(A, dtype, Q, Ah, N, (int)n3, (int)p, pr, stream));
+    char* pb = static_cast<char*>(parts);
+    const size_t slab = e * (size_t)p * n3;
+    // dQ^T = Ah_(3) G_(3)^T + Gh_(3) A_(3)^T
+    PQ_TRY(do_gemm(dq_gemm(Ah, G, (int)p, (int)n3, N, pb, ks), dtype, pr, stream));
+    PQ_TRY(do_gemm(dq_gemm(Gh, A, (int)p, (int)n3, N, pb + slab * ks, ks), dtype, pr, stream));
+    PQ_TRY(do_sum(parts, 2 * ks, p * n3, p * n3, dQ, dtype, stream));
+  }
+  return PQ_OK;
+}
+
+size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k, int a_dtype) {
+  (void)n3;
+  const size_t e = elem(a_dtype == PQ_F64 ? PQ_F64 : PQ_F32);
+  const int64_t mx = std::max(n1, n2);
+  return align_up(e * n1 * n2 * p)        // Ah
+         + align_up(e * n1 * n2 * p)      // Jacobi working vectors
+         + align_up(sizeof(int) * p)      // sweeps per face
+         + align_up(e * k * p)            // 1 / singular values
+         + align_up(e * mx * k * p)       // unscaled other factor
+         + align_up(e * n1 * n2 * p);     // transform-domain A_k
+}
+
+int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p,
+             int64_t k, int prec, void* Uhat, void* s, void* Vhat, void* Uk, void* Sk, void* Vk, void* Ak,
+             double tol, int max_sweeps, int* info_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!A || !Q || !Uhat || !s || !Vhat) return PQ_ERR_NULL;
+  PQ_CHECK(check_in_dtype(a_dtype));
+  PQ_CHECK(check_dims({n1, n2, n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_CHECK(check_area(n1, n2));
+  if (k < 1 || k > std::min(n1, n2)) return PQ_ERR_K;
+  PQ_CHECK(check_prec(prec, a_dtype));
+  const void* ins[] = {A, Q};
+  for (const void* o : {Uhat, s, Vhat, Uk, Sk, Vk, Ak})
+    for (const void* in : ins)
+      if (o && o == in) return PQ_ERR_ALIAS;
+  if (std::min(n1, n2) > 4096) return PQ_ERR_UNSUPPORTED;
+  if (p > 512 && a_dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
+  if (!ws || ws_bytes < pq_tsvdq_workspace(n1, n2, n3, p, k, a_dtype)) return PQ_ERR_WORKSPACE;
+  if (max_sweeps <= 0) max_sweeps = 30;
+  const bool f64 = a_dtype == PQ_F64;
+  const int dt = f64 ? PQ_F64 : PQ_F32;
+  if (tol <= 0.0) tol = f64 ? 1e-14 : 2e-7;
+  const size_t e = elem(dt);
+  const int64_t N = n1 * n2;
+  const int64_t mx = std::max(n1, n2);
+  Arena ar(ws, ws_bytes);
+  void* Ah = ar.take(e * N * p);
+  void* W = ar.take(e * N * p);
+  int* used = static_cast<int*>(ar.take(sizeof(int) * p));
+  void* inv_s = ar.take(e * k * p);
+  void* Y = ar.take(e * mx * k * p);
+  void* Akh = ar.take(e * N * p);
+  const Prec pr = (Prec)prec;
+  const int in1 = (int)n1, in2 = (int)n2, ip = (int)p, ik = (int)k;
+  // step 2: transform domain
+  PQ_TRY(do_hat(A, a_dtype, Q, Ah, N, (int)n3, ip, pr, stream));
+  // step 3: facewise truncated SVD
+  const bool cols = n1 >= n2;  // orthogonalise the shorter side's vectors
+  const int nv = cols ? in2 : in1, L = cols ? in1 : in2;
+  void* F = cols ? Uhat : Vhat;        // side given by the Jacobi vectors
+  void* Other = cols ? Vhat : Uhat;    // side given by one more product
+  if (f64) {
+    PQ_TRY(pq::jacobi_prep_f64(static_cast<const double*>(Ah), static_cast<double*>(W), in1, in2, ip, stream));
+    PQ_TRY(pq::jacobi_sweeps_f64(static_cast<double*>(W), ip, nv, L, max_sweeps, tol, used, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(static_cast<const double*>(W), ip, nv, L, ik, static_cast<double*>(F),
+                                   static_cast<double*>(s), static_cast<double*>(inv_s), stream));
+  } else {
+    PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(Ah), static_cast<float*>(W), in1, in2, ip, stream));
+    PQ_TRY(pq::jacobi_sweeps_f32(static_cast<float*>(W), ip, nv, L, max_sweeps, tol, used, stream));
+    PQ_TRY(pq::jacobi_finalize_f32(static_cast<const float*>(W), ip, nv, L, ik, static_cast<float*>(F),
+                                   static_cast<float*>(s), static_cast<float*>(inv_s), stream));
+  }
+  // Other side, unscaled: Y = Ah_l^T Uhat_l (n2 x k) or Y = Ah_l Vhat_l (n1 x k)
+  const int orows = cols ? in2 : in1;
+  {
+    Gemm g = cols ? face_gemm(true, false, in2, ik, in1, Ah, n1, N, F, n1, n1 * k, Y, n2, n2 * k, ip)
+                  : face_gemm(false, false, in1, ik, in2, Ah, n1, N, F, n2, n2 * k, Y, n1, n1 * k, ip);
+    PQ_TRY(do_gemm(g, dt, pr, stream));
+  }
+  if (f64)
+    PQ_TRY(pq::scale_cols_f64(static_cast<const double*>(Y), static_cast<double*>(Other), orows, ik, ip,
+                              static_cast<const double*>(inv_s), stream));
+  else
+    PQ_TRY(pq::scale_cols_f32(static_cast<const float*>(Y), static_cast<float*>(Other), orows, ik, ip,
+                              static_cast<const float*>(inv_s), stream));
+  if (info_dev) PQ_TRY(pq::jacobi_info(used, ip, max_sweeps, info_dev, stream));
+  // step 4 and the approximation of Thm. 4.2
+  if (Ak) {
+    // Akh_l = Uhat_l Y_l^T (cols) or Y_l Vhat_l^T (rows): both equal Uhat S Vhat^T
+    Gemm g = cols ? face_gemm(false, true, in1, in2, ik, F, n1, n1 * k, Y, n2, n2 * k, Akh, n1, N, ip)
+                  : face_gemm(false, true, in1, in2, ik, Y, n1, n1 * k, F, n2, n2 * k, Akh, n1, N, ip);
+    PQ_TRY(do_gemm(g, dt, pr, stream));
+    PQ_TRY(do_unhat(Akh, Q, Ak, dt, N, (int)n3, ip, pr, stream));
+  }
+  if (Uk) PQ_TRY(do_unhat(Uhat, Q, Uk, dt, n1 * k, (int)n3, ip, pr, stream));
+  if (Vk) PQ_TRY(do_unhat(Vhat, Q, Vk, dt, n2 * k, (int)n3, ip, pr, stream));
+  if (Sk) PQ_TRY(do_unhat(s, Q, Sk, dt, k, (int)n3, ip, pr, stream));
+  return PQ_OK;
+}
+
+}  // extern "C"

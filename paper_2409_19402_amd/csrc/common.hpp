@@ -1,0 +1,95 @@
+// Device-side helpers shared by the projprod kernels (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace pq {
+
+constexpr int kWave = 64;
+
+// bfloat16 bit pattern -> float32 (exact).
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// float32 -> bfloat16 bit pattern, round to nearest, ties to even.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+template <typename T> struct Loader;
+template <> struct Loader<float> {
+  static __device__ __forceinline__ float ld(const float* p) { return *p; }
+};
+template <> struct Loader<double> {
+  static __device__ __forceinline__ double ld(const double* p) { return *p; }
+};
+template <> struct Loader<uint16_t> {
+  static __device__ __forceinline__ float ld(const uint16_t* p) { return bf16_to_f32(*p); }
+};
+
+// Load VEC consecutive elements (as float) starting at p; p is VEC-aligned.
+template <int VEC, typename TIn>
+__device__ __forceinline__ void load_vec(const TIn* __restrict__ p, float (&v)[VEC]);
+
+template <>
+__device__ __forceinline__ void load_vec<1, float>(const float* __restrict__ p, float (&v)[1]) { v[0] = *p; }
+template <>
+__device__ __forceinline__ void load_vec<2, float>(const float* __restrict__ p, float (&v)[2]) {
+  float2 t = *reinterpret_cast<const float2*>(p);
+  v[0] = t.x; v[1] = t.y;
+}
+template <>
+__device__ __forceinline__ void load_vec<4, float>(const float* __restrict__ p, float (&v)[4]) {
+  float4 t = *reinterpret_cast<const float4*>(p);
+  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+template <>
+__device__ __forceinline__ void load_vec<1, uint16_t>(const uint16_t* __restrict__ p, float (&v)[1]) {
+  v[0] = bf16_to_f32(*p);
+}
+template <>
+__device__ __forceinline__ void load_vec<2, uint16_t>(const uint16_t* __restrict__ p, float (&v)[2]) {
+  uint32_t u = *reinterpret_cast<const uint32_t*>(p);
+  v[0] = __uint_as_float(u << 16); v[1] = __uint_as_float(u & 0xffff0000u);
+}
+template <>
+__device__ __forceinline__ void load_vec<4, uint16_t>(const uint16_t* __restrict__ p, float (&v)[4]) {
+  uint2 u = *reinterpret_cast<const uint2*>(p);
+  v[0] = __uint_as_float(u.x << 16); v[1] = __uint_as_float(u.x & 0xffff0000u);
+  v[2] = __uint_as_float(u.y << 16); v[3] = __uint_as_float(u.y & 0xffff0000u);
+}
+
+template <int VEC>
+__device__ __forceinline__ void store_vec(float* __restrict__ p, const float (&v)[VEC]) {
+  if constexpr (VEC == 1) { *p = v[0]; }
+  else if constexpr (VEC == 2) { *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]); }
+  else { *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]); }
+}
+
+// Sum over the 64 lanes of a wave (every lane gets the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+}  // namespace pq

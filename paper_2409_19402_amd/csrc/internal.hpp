@@ -1,0 +1,83 @@
+// Host-side launchers of the projprod kernels.  Tensors are seen as row-major
+// matrices: an n1 x n2 x n3 face-major tensor is the n3 x N matrix (N = n1*n2)
+// whose row t is frontal slice t; Q is n3 x p row-major.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pq {
+
+enum class Prec : int { Default = 0, BF16 = 1, BF16x3 = 2, BF16x6 = 3 };
+
+// ---- mode-3 transforms (transform.hip) -----------------------------------
+// Ah (p x N) = Q^T (p x n3) * A (n3 x N); A is float32 or bfloat16 bits.
+hipError_t hat_f32(const void* A, bool a_bf16, const float* Q, float* Ah,
+                   int64_t N, int n3, int p, Prec prec, hipStream_t s);
+hipError_t hat_f64(const double* A, const double* Q, double* Ah,
+                   int64_t N, int n3, int p, hipStream_t s);
+// A (n3 x N) = Q (n3 x p) * Ah (p x N)
+hipError_t unhat_f32(const float* Ah, const float* Q, float* A,
+                     int64_t N, int n3, int p, Prec prec, hipStream_t s);
+hipError_t unhat_f64(const double* Ah, const double* Q, double* A,
+                     int64_t N, int n3, int p, hipStream_t s);
+// out (n3 x N) = Q Q^T A in one pass; valid when proj_fused_ok(n3, p).
+bool proj_fused_ok(int n3, int p);
+hipError_t proj_fused_f32(const void* A, bool a_bf16, const float* Q, float* out,
+                          int64_t N, int n3, int p, Prec prec, hipStream_t s);
+
+// ---- batched GEMM (gemm.hip) ----------------------------------------------
+// For every batch b: C_b = op(A_b) op(B_b), column-major operands;
+// op(X) = X^T when the flag is set.  op(A) is M x K, op(B) is K x N.
+// With ksplit > 1 the K range is cut into ksplit slices and slice z writes
+// its partial product to C + z * sSplit (to be summed by sum_partials).
+struct Gemm {
+  bool ta, tb;
+  int M, N, K;
+  const void* A; int64_t lda, sA;
+  const void* B; int64_t ldb, sB;
+  void* C; int64_t ldc, sC;
+  int batch;
+  int ksplit; int64_t sSplit;
+};
+hipError_t gemm_f32(const Gemm& g, Prec prec, hipStream_t s);
+hipError_t gemm_f64(const Gemm& g, hipStream_t s);
+// out[e] = sum_{z < nparts} parts[z * stride + e] for e < count, fixed order.
+hipError_t sum_partials_f32(const float* parts, int nparts, int64_t stride,
+                            int64_t count, float* out, hipStream_t s);
+hipError_t sum_partials_f64(const double* parts, int nparts, int64_t stride,
+                            int64_t count, double* out, hipStream_t s);
+
+// ---- small helpers (misc.hip) ---------------------------------------------
+hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, hipStream_t s);
+// out(i, j, l) = in(i, j, l) * scale[j + l*k]; face l is rows x k column-major.
+hipError_t scale_cols_f32(const float* in, float* out, int64_t rows, int k, int p,
+                          const float* scale, hipStream_t s);
+hipError_t scale_cols_f64(const double* in, double* out, int64_t rows, int k, int p,
+                          const double* scale, hipStream_t s);
+
+// ---- facewise one-sided Jacobi SVD (jacobi.hip) -----------------------------
+// W holds, for each of p faces, nv vectors of length L (vector j of face l at
+// W + (l*nv + j)*L).  prep copies the faces of Ah (n1 x n2 x p, face-major)
+// into W: the columns when n1 >= n2 (nv = n2, L = n1), else the rows
+// (nv = n1, L = n2).
+hipError_t jacobi_prep_f32(const float* Ah, float* W, int n1, int n2, int p, hipStream_t s);
+hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, hipStream_t s);
+// Orthogonalises the nv vectors of every face; sweeps_used[l] gets the sweep
+// count of face l, or max_sweeps + 1 when it stopped without converging.
+hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol,
+                             int* sweeps_used, hipStream_t s);
+hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol,
+                             int* sweeps_used, hipStream_t s);
+// Column norms, descending order, top k: s (k x p), inv_s (k x p, 0 for a
+// zero singular value) and the normalised vectors F (L x k x p).
+hipError_t jacobi_finalize_f32(const float* W, int p, int nv, int L, int k,
+                               float* F, float* s_out, float* inv_s, hipStream_t s);
+hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k,
+                               double* F, double* s_out, double* inv_s, hipStream_t s);
+// info[0] = max_l min(sweeps_used[l], max_sweeps); info[1] = #faces that did
+// not converge.
+hipError_t jacobi_info(const int* sweeps_used, int p, int max_sweeps, int* info, hipStream_t s);
+
+}  // namespace pq

@@ -1,0 +1,87 @@
+"""The C ABI without a GPU: the library loads, exports every symbol the header
+declares, and rejects bad arguments on the host before launching anything."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2409_19402_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "projprod.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH),
+                                reason="libprojprod.so not built")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pq_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = _lib.load()
+    names = declared_symbols()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding signatures must cover the header"
+
+
+def test_status_strings():
+    lib = _lib.load()
+    assert lib.pq_version() >= 100
+    for code in range(0, -12, -1):
+        assert lib.pq_status_string(code)
+    assert b"unknown" in lib.pq_status_string(-99)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def rc(name, *args):
+    return getattr(_lib.load(), name)(*args)
+
+
+def test_validation_errors():
+    # null pointers
+    assert rc("pq_hat", None, 0, FAKE, FAKE, 4, 4, 8, 2, 0, None) == -1
+    # p > n3 and p < 1
+    assert rc("pq_hat", FAKE, 0, FAKE, ctypes.c_void_p(0x2000), 4, 4, 8, 9, 0, None) == -3
+    assert rc("pq_hat", FAKE, 0, FAKE, ctypes.c_void_p(0x2000), 4, 4, 8, 0, 0, None) == -3
+    # non-positive size
+    assert rc("pq_hat", FAKE, 0, FAKE, ctypes.c_void_p(0x2000), 0, 4, 8, 2, 0, None) == -2
+    # dtype
+    assert rc("pq_hat", FAKE, 7, FAKE, ctypes.c_void_p(0x2000), 4, 4, 8, 2, 0, None) == -5
+    assert rc("pq_unhat", FAKE, FAKE, ctypes.c_void_p(0x2000), 2, 4, 4, 8, 2, 0, None) == -5
+    # precision mode on float64 data
+    assert rc("pq_hat", FAKE, 1, FAKE, ctypes.c_void_p(0x2000), 4, 4, 8, 2, 2, None) == -6
+    # alias: output == input
+    assert rc("pq_hat", FAKE, 0, ctypes.c_void_p(0x3000), FAKE, 4, 4, 8, 2, 0, None) == -7
+    # k out of range
+    for k in (0, 5):
+        assert rc("pq_tsvdq", FAKE, 0, ctypes.c_void_p(0x2000), 4, 6, 8, 2, k, 0,
+                  ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), ctypes.c_void_p(0x5000),
+                  None, None, None, None, 0.0, 0, None, ctypes.c_void_p(0x6000), 1 << 30,
+                  None) in (-4, -2)
+    # workspace too small
+    assert rc("pq_qprod", FAKE, ctypes.c_void_p(0x2000), 0, ctypes.c_void_p(0x3000),
+              ctypes.c_void_p(0x4000), 4, 3, 5, 8, 2, 0, None, None, ctypes.c_void_p(0x5000), 16,
+              None) == -8
+    # shape: m of B must match (facewise shapes come from the caller, so check p)
+    assert rc("pq_qprod_backward", FAKE, FAKE, FAKE, FAKE, None, None, 0, 4, 3, 5, 8, 9,
+              ctypes.c_void_p(0x2000), None, None, ctypes.c_void_p(0x5000), 1 << 30, None) == -3
+
+
+def test_workspace_queries_monotone():
+    lib = _lib.load()
+    a = lib.pq_qprod_workspace(32, 24, 20, 16, 4, 0)
+    b = lib.pq_qprod_workspace(64, 24, 20, 16, 4, 0)
+    assert 0 < a < b
+    assert lib.pq_qprod_workspace(32, 24, 20, 16, 4, 1) > a  # float64 needs more
+    assert lib.pq_proj_workspace(100, 100, 64, 16, 0) == 0   # fused, one pass
+    assert lib.pq_proj_workspace(100, 100, 64, 40, 0) > 0
+    assert lib.pq_tsvdq_workspace(240, 320, 200, 20, 10, 0) > 2 * 240 * 320 * 20 * 4

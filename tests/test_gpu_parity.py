@@ -1,0 +1,297 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: relative Frobenius error <= 1e-5 for float32 results, <= 1e-12
+for float64 results, <= 1e-4 for float32 gradients against the float64
+reference gradient.  Inputs are seeded and synthetic; the oracle sees exactly
+the values the GPU sees (float32 Q and data upcast to float64).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import dev, dev_bf16, devq, host, rel, say
+from paper_2409_19402_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def pq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    from paper_2409_19402_amd import binding
+    return binding
+
+
+def _case(seed, n1, n2, n3, p, dtype=np.float32):
+    rng = np.random.default_rng(seed)
+    A = synth.gaussian(rng, n1, n2, n3, dtype)
+    Q = synth.random_orthonormal(rng, n3, p).astype(dtype)
+    return A, Q
+
+
+TRANSFORM_SHAPES = [
+    (32, 24, 16, 4),     # tiny
+    (7, 9, 33, 5),       # N = 63: odd tube count, scalar loads, ragged strip
+    (50, 30, 200, 20),   # several strips, n3 beyond one 128-row chunk
+    (17, 6, 130, 37),    # p > 32: two transform chunks, unhat from global
+    (64, 64, 256, 32),   # p = 32 exactly
+    (3, 2, 5, 5),        # p = n3
+    (1, 1, 9, 3),        # a single tube
+]
+
+
+@pytest.mark.parametrize("shape", TRANSFORM_SHAPES)
+def test_transforms_f32(pq, shape):
+    n1, n2, n3, p = shape
+    say(f"transforms f32 {shape}")
+    A, Q = _case(100 + n3, n1, n2, n3, p)
+    Ad, Qd = dev(A), devq(Q)
+    Al = synth.logical(A)
+    Ah = pq.hat(Ad, Qd)
+    assert rel(host(Ah), oracle.hat(Al, Q)) <= TOL32
+    back = pq.unhat(Ah, Qd)
+    assert rel(host(back), oracle.unhat(host(Ah), Q)) <= TOL32
+    P = pq.proj(Ad, Qd)
+    assert rel(host(P), oracle.proj(Al, Q)) <= TOL32
+
+
+@pytest.mark.parametrize("shape", [(32, 24, 20, 16, 4), (33, 17, 9, 40, 7), (5, 70, 3, 64, 33),
+                                   (65, 31, 66, 12, 12)])
+def test_qprod_f32(pq, shape):
+    n1, m, n2, n3, p = shape
+    say(f"qprod f32 {shape}")
+    rng = np.random.default_rng(7 + n1)
+    A = synth.gaussian(rng, n1, m, n3)
+    B = synth.gaussian(rng, m, n2, n3)
+    Q = synth.random_orthonormal(rng, n3, p).astype(np.float32)
+    C = pq.qprod(dev(A), dev(B), devq(Q))
+    ref = oracle.qprod(synth.logical(A), synth.logical(B), Q)
+    assert rel(host(C), ref) <= TOL32
+
+
+def test_facewise_matches_batched_matmul(pq):
+    """p = n3 with Q = I: the projected product is the facewise product."""
+    say("identity Q")
+    rng = np.random.default_rng(21)
+    A = synth.gaussian(rng, 40, 30, 8)
+    B = synth.gaussian(rng, 30, 50, 8)
+    Q = np.eye(8, dtype=np.float32)
+    C = host(pq.qprod(dev(A), dev(B), devq(Q)))
+    ref = np.einsum("irt,rjt->ijt", synth.logical(A).astype(np.float64),
+                    synth.logical(B).astype(np.float64))
+    assert rel(C, ref) <= TOL32
+    Ch = host(pq.facewise(dev(A), dev(B)))
+    assert rel(Ch, ref) <= TOL32
+
+
+def test_square_orthogonal_roundtrip(pq):
+    say("square Q round trip")
+    A, Q = _case(5, 20, 12, 24, 24)
+    Ad, Qd = dev(A), devq(Q)
+    assert rel(host(pq.unhat(pq.hat(Ad, Qd), Qd)), synth.logical(A)) <= TOL32
+    assert rel(host(pq.proj(Ad, Qd)), synth.logical(A)) <= TOL32
+
+
+def test_proj_idempotent(pq):
+    say("proj idempotent")
+    A, Q = _case(6, 40, 33, 64, 10)
+    Qd = devq(Q)
+    P1 = pq.proj(dev(A), Qd)
+    P2 = pq.proj(P1, Qd)
+    assert rel(host(P2), host(P1)) <= TOL32
+
+
+def test_f64_tiny_case(pq):
+    """Tiny plain-method case in float64: qprod and tSVDQ (k=5)."""
+    say("tiny f64")
+    import torch
+    c = synth.tiny()
+    A, B, Q, k = c["A"], c["B"], c["Q"], c["k"]
+    Ad, Bd, Qd = dev(A), dev(B), devq(Q)
+    C = pq.qprod(Ad, Bd, Qd)
+    assert C.dtype == torch.float64
+    assert rel(host(C), oracle.qprod(synth.logical(A), synth.logical(B), Q)) <= TOL64
+    r = pq.tsvdq(Ad, Qd, k, spatial=True, approx=True)
+    ref = oracle.tsvdq(synth.logical(A), Q, k)
+    assert rel(host(r.s), ref.s) <= TOL64
+    assert rel(host(r.Ak), ref.Ak) <= 1e-11
+    # spatial factors (Alg. 4.1 step 4): S_k is sign-free; U_k and V_k are
+    # checked as the transform of the GPU's own transform-domain factors
+    ref_sk = np.stack([np.diagonal(ref.Sk[:, :, t]) for t in range(16)], axis=1)
+    assert rel(host(r.Sk), ref_sk) <= 1e-11
+    assert rel(host(r.Uk), oracle.unhat(host(r.Uhat), Q)) <= TOL64
+    assert rel(host(r.Vk), oracle.unhat(host(r.Vhat), Q)) <= TOL64
+    info = r.info.cpu().numpy()
+    assert info[1] == 0 and 1 <= info[0] <= 30
+
+
+def _check_tsvdq(pq, A_st, Q, k, tol_s=TOL32, tol_a=TOL32, a_dev=None):
+    Al = synth.logical(A_st)
+    Ad = dev(A_st) if a_dev is None else a_dev
+    r = pq.tsvdq(Ad, devq(Q), k, spatial=True, approx=True)
+    ref = oracle.tsvdq(Al, Q, k)
+    s = host(r.s)
+    p = Q.shape[1]
+    for l in range(p):
+        assert rel(s[:, l], ref.s[:, l]) <= tol_s, f"face {l}"
+    assert rel(host(r.Ak), ref.Ak) <= tol_a
+    Uh, Vh = host(r.Uhat), host(r.Vhat)
+    Ah = oracle.hat(Al, Q)
+    for l in range(p):
+        nz = s[:, l] > 0
+        U = Uh[:, nz, l]
+        np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=2e-5)
+        # U^T Ah = diag(s) V^T on every face
+        lhs = U.T @ Ah[:, :, l]
+        rhs = s[nz, l][:, None] * Vh[:, nz, l].T
+        assert rel(lhs, rhs) <= 10 * tol_a
+    # Thm 4.2 from the GPU's own outputs
+    ey, pe = oracle.tsvdq_error_terms(Al, Q, k, s_all=ref.s_all)
+    err2 = oracle.fro2(Al - host(r.Ak))
+    assert abs(err2 - (ey + pe)) <= 1e-4 * (ey + pe) + 1e-6 * oracle.fro2(Al)
+    info = r.info.cpu().numpy()
+    assert info[1] == 0, f"unconverged faces: {info}"
+    return r, ref
+
+
+@pytest.mark.parametrize("shape", [(32, 24, 16, 4, 5), (24, 40, 20, 6, 3), (50, 50, 12, 3, 50),
+                                   (70, 9, 30, 5, 1), (9, 70, 30, 5, 9), (129, 65, 40, 7, 8)])
+def test_tsvdq_f32(pq, shape):
+    n1, n2, n3, p, k = shape
+    say(f"tsvdq f32 {shape}")
+    A, Q = _case(300 + n1, n1, n2, n3, p)
+    _check_tsvdq(pq, A, Q, k)
+
+
+def test_tsvdq_rank_deficient(pq):
+    """Example 4.1 with the Haar column: the transform face is rank one, so the
+    second singular vector of each side must come back as zeros, and the error
+    is the printed 0 + 2."""
+    say("tsvdq rank deficient")
+    import torch
+    A = np.zeros((2, 2, 2))
+    A[:, :, 0] = [[1, 0], [0, 1]]
+    A[:, :, 1] = [[1, 0], [0, -1]]
+    Q = (np.array([[1.0], [1.0]]) / np.sqrt(2.0))
+    r = pq.tsvdq(dev(synth.storage(A)), devq(Q), 2, approx=True)
+    s = host(r.s)
+    assert s[0, 0] == pytest.approx(np.sqrt(2.0), rel=1e-14) and s[1, 0] == 0.0
+    assert np.all(host(r.Uhat)[:, 1, 0] == 0) and np.all(host(r.Vhat)[:, 1, 0] == 0)
+    assert oracle.fro2(A - host(r.Ak)) == pytest.approx(2.0, abs=1e-12)
+    assert r.Ak.dtype == torch.float64
+
+
+def test_tsvdq_max_sweeps_reported(pq):
+    say("tsvdq max_sweeps=1")
+    A, Q = _case(9, 40, 30, 12, 3)
+    r = pq.tsvdq(dev(A), devq(Q), 4, max_sweeps=1)
+    info = r.info.cpu().numpy()
+    assert info[0] == 1 and info[1] == 3
+
+
+def test_video_case_full_size(pq):
+    """Video-shaped tSVDQ at 240 x 320 x 200, p = 20, k = 10 (float32)."""
+    say("video case 240x320x200")
+    c = synth.video_case()
+    r, ref = _check_tsvdq(pq, c["A"], c["Q"], c["k"])
+    re_gpu = oracle.relative_error(synth.logical(c["A"]), host(r.Ak))
+    re_ref = oracle.relative_error(synth.logical(c["A"]), ref.Ak)
+    say(f"  RE gpu {re_gpu:.6e}  oracle {re_ref:.6e}")
+    assert abs(re_gpu - re_ref) <= 1e-5 * re_ref
+
+
+def test_hyperspectral_hat_bf16_input(pq):
+    """bfloat16-stored hyperspectral cube (512 x 512 x 224, p = 32): float32
+    transform of the exact bfloat16 values."""
+    say("hyperspectral hat bf16 input")
+    c = synth.hyperspectral_case()
+    Ad = dev_bf16(c["A_bits"])
+    Ah = pq.hat(Ad, devq(c["Q"]))
+    ref = oracle.hat(synth.logical(c["A"]), c["Q"])
+    assert rel(host(Ah), ref) <= TOL32
+
+
+def test_differentiation_case(pq):
+    """Gradients of ||A *_Q B - T||^2 at 256x128x128 * 128x256x128, p = 16,
+    against the float64 reference gradient; dQ is deterministic."""
+    say("differentiation case")
+    import torch
+    c = synth.differentiation_case()
+    A, B, Q, T = c["A"], c["B"], c["Q"], c["T"]
+    Ad = dev(A).requires_grad_(True)
+    Bd = dev(B).requires_grad_(True)
+    Qd = devq(Q).requires_grad_(True)
+    Td = dev(T)
+    C = pq.qprod(Ad, Bd, Qd)
+    loss = ((C - Td) ** 2).sum()
+    loss.backward()
+    Al, Bl, Tl = synth.logical(A), synth.logical(B), synth.logical(T)
+    Cref = oracle.qprod(Al, Bl, Q)
+    assert rel(host(C), Cref) <= TOL32
+    dA, dB, dQ = oracle.qprod_backward(2 * (Cref - Tl), Al, Bl, Q)
+    assert rel(host(Ad.grad), dA) <= 1e-4
+    assert rel(host(Bd.grad), dB) <= 1e-4
+    assert rel(host(Qd.grad), dQ) <= 1e-4
+    # fixed-order split-K reduction: bit-identical on repetition
+    G = pq.from_storage(torch.from_numpy(np.ascontiguousarray(
+        synth.storage(2 * (host(C) - Tl)).astype(np.float32))).cuda())
+    r1 = pq.qprod_backward(G, Ad.detach(), Bd.detach(), Qd.detach())
+    r2 = pq.qprod_backward(G, Ad.detach(), Bd.detach(), Qd.detach())
+    for x, y in zip(r1, r2):
+        assert torch.equal(x, y)
+
+
+def test_proj_backward(pq):
+    say("proj backward")
+    A, Q = _case(44, 30, 20, 48, 6)
+    rng = np.random.default_rng(45)
+    T = synth.gaussian(rng, 30, 20, 48)
+    Ad = dev(A).requires_grad_(True)
+    Qd = devq(Q).requires_grad_(True)
+    P = pq.proj(Ad, Qd)
+    ((P - dev(T)) ** 2).sum().backward()
+    Al, Tl = synth.logical(A), synth.logical(T)
+    G = 2 * (oracle.proj(Al, Q) - Tl)
+    dA, dQ = oracle.proj_backward(G, Al, Q)
+    assert rel(host(Ad.grad), dA) <= 1e-4
+    assert rel(host(Qd.grad), dQ) <= 1e-4
+
+
+def test_f64_gradients(pq):
+    say("f64 gradients")
+    c = synth.tiny()
+    A, B, Q = c["A"], c["B"], c["Q"]
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((16, 20, 32))
+    dA, dB, dQ = pq.qprod_backward(dev(G), dev(A), dev(B), devq(Q))
+    ref = oracle.qprod_backward(synth.logical(G), synth.logical(A), synth.logical(B), Q)
+    assert rel(host(dA), ref[0]) <= TOL64
+    assert rel(host(dB), ref[1]) <= TOL64
+    assert rel(host(dQ), ref[2]) <= TOL64
+
+
+def test_check_q(pq):
+    say("check_q")
+    import torch
+    Q = synth.random_orthonormal(np.random.default_rng(1), 200, 20)
+    assert pq.check_q(devq(Q)).item() == pytest.approx(oracle.check_q(Q), abs=1e-15)
+    Qp = Q.copy()
+    Qp[3, 2] += 1e-3
+    assert pq.check_q(devq(Qp)).item() == pytest.approx(oracle.check_q(Qp), rel=1e-12)
+    Q32 = Q.astype(np.float32)
+    assert pq.check_q(devq(Q32)).item() == pytest.approx(oracle.check_q(Q32), rel=1e-9, abs=1e-15)
+    assert pq.check_q(devq(Q32)).dtype == torch.float64
+
+
+def test_rejects_non_face_major(pq):
+    import torch
+    X = torch.zeros((4, 5, 6), device="cuda")  # C-contiguous, not face-major
+    Q = torch.zeros((6, 2), device="cuda")
+    with pytest.raises(ValueError):
+        pq.hat(X, Q)
