@@ -1,0 +1,308 @@
+#!/usr/bin/env python3
+"""Throughput of the projected-product hot path on one MI355X.
+
+Default workload: the video-shaped truncated tSVDQ, A 240 x 320 x 200 float32
+(a sum of 10 separable blob x drifting-cosine components plus noise),
+Q = U3(:, :20), rank k = 10 per face.  One step is the whole path on that
+input: the float64 Stiefel check of Q, the transform A x_3 Q^T, the facewise
+one-sided-Jacobi SVD truncated to rank 10, the factor products, and the
+return to the spatial domain of the factors and of the approximation A_k.
+
+Prints ONE JSON line (metric, value in GFLOP/s of the nominal flop count,
+roofline of the dominant kernel measured with HIP events on the launch stream,
+and the float64 CPU oracle timed on this host as a baseline).  Per-kernel
+details go to stderr and to gpurun_out/bench_kernels.json when that folder
+exists.
+
+    python bench.py [--steps K] [--warmup W] [--workload video|hyper|diff|tiny]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_MFMA_PEAK = 157.3         # TFLOP/s dense
+FP64_VALU_PEAK = 78.6          # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+BF16_MFMA_PEAK = 2500.0        # TFLOP/s dense
+
+# HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE + WRITE_SIZE,
+# scaled by the copy-kernel calibration); None until measured for the kernel
+# as it is now.
+TRAFFIC_BYTES = {}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="video",
+                    choices=["video", "hyper", "diff", "tiny", "copy"])
+    ap.add_argument("--prec", default="default")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall-clock budget of the CPU-oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# workloads: each returns (step_fn, flops_per_step, info dict, kernel models)
+# kernel model: name -> (bound, units_per_launch_fn) giving algorithmic
+# bytes ("hbm") or flops ("alu"/"mfma") per launch
+# ---------------------------------------------------------------------------
+
+def svd_nominal_flops(n1, n2, p):
+    """Golub-Van Loan R-SVD count for Sigma, U1, V of an m x n matrix
+    (m >= n): 6 m n^2 + 20 n^3, per face."""
+    mx, mn = max(n1, n2), min(n1, n2)
+    return p * (6.0 * mx * mn * mn + 20.0 * mn ** 3)
+
+
+def workload_tsvdq(pq, torch, A_dev, Q_dev, k, a_bytes, name, prec):
+    n1, n2, n3 = A_dev.shape
+    p = Q_dev.shape[1]
+    N = n1 * n2
+
+    def step():
+        pq.check_q(Q_dev)
+        return pq.tsvdq(A_dev, Q_dev, k, prec=prec, spatial=True, approx=True)
+
+    flops = (2.0 * N * n3 * p                         # transform
+             + svd_nominal_flops(n1, n2, p)           # facewise SVD (nominal)
+             + 2.0 * N * k * p * 2                    # factor + approximation products
+             + 2.0 * N * n3 * p                       # A_k back to the spatial domain
+             + 2.0 * (n1 + n2 + 1) * k * n3 * p)      # spatial factors
+    models = {
+        "hat": ("hbm", a_bytes * N * n3 + 4.0 * N * p + 4.0 * n3 * p),
+        "unhat": ("hbm", None),   # several launches of different sizes; see per-launch note
+        "jacobi_sweeps": ("alu", svd_nominal_flops(n1, n2, p)),
+    }
+    info = {"workload": name, "n1": n1, "n2": n2, "n3": n3, "p": p, "k": k}
+    return step, flops, info, models
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(every GPU box here has one GPU)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2409_19402_amd import binding as pq
+    from paper_2409_19402_amd import _lib, synth
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm device", file=sys.stderr)
+        sys.exit(1)
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+
+    def up(storage):
+        return pq.from_storage(torch.from_numpy(np.ascontiguousarray(storage)).to(dev))
+
+    if args.workload == "copy":
+        # calibration of the HBM byte counters: a plain device copy of known size
+        nbytes = 512 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        print(json.dumps({"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                          "ms": ms, "GB/s": 2 * nbytes / ms / 1e6}), flush=True)
+        return
+
+    t0 = time.time()
+    cpu_case = None
+    if args.workload == "video":
+        c = synth.video_case()
+        A, Q = up(c["A"]), torch.from_numpy(c["Q"]).to(dev)
+        step, flops, info, models = workload_tsvdq(
+            pq, torch, A, Q, c["k"], 4, "video-shaped tSVDQ 240x320x200 fp32, p=20, k=10", args.prec)
+        dtype = "f32"
+        cpu_case = ("tsvdq", synth.logical(c["A"]), c["Q"], c["k"])
+    elif args.workload == "hyper":
+        c = synth.hyperspectral_case()
+        A = pq.from_storage(torch.from_numpy(c["A_bits"].view(np.int16)).to(dev).view(torch.bfloat16))
+        Q = torch.from_numpy(c["Q"]).to(dev)
+        step, flops, info, models = workload_tsvdq(
+            pq, torch, A, Q, c["k"], 2, "hyperspectral-shaped tSVDQ 512x512x224 bf16, p=32, k=16",
+            args.prec)
+        dtype = "bf16-in/f32"
+        cpu_case = ("tsvdq", synth.logical(c["A"]), c["Q"], c["k"])
+    elif args.workload == "tiny":
+        c = synth.tiny()
+        A, Q = up(c["A"]), torch.from_numpy(c["Q"]).to(dev)
+        step, flops, info, models = workload_tsvdq(
+            pq, torch, A, Q, c["k"], 8, "tiny tSVDQ 32x24x16 fp64, p=4, k=5", "default")
+        dtype = "f64"
+        cpu_case = ("tsvdq", synth.logical(c["A"]), c["Q"], c["k"])
+    else:  # diff
+        c = synth.differentiation_case()
+        A = up(c["A"]).requires_grad_(True)
+        B = up(c["B"]).requires_grad_(True)
+        Q = torch.from_numpy(c["Q"]).to(dev).requires_grad_(True)
+        T = up(c["T"])
+        n1, m, n3 = A.shape
+        n2 = B.shape[1]
+        p = Q.shape[1]
+        G = pq.empty(n1, n2, n3, device=dev)
+
+        def step():
+            C = pq.QProd.apply(A, B, Q, args.prec)
+            with torch.no_grad():  # the loss gradient G = 2 (C - T)
+                G.copy_(C)
+                G.sub_(T).mul_(2.0)
+            return pq.qprod_backward(G, A.detach(), B.detach(), Q.detach())
+
+        fw = 2.0 * p * (n1 * m * n3 + m * n2 * n3 + n1 * m * n2 + n1 * n2 * n3)
+        bw = (2.0 * n1 * n2 * n3 * p + 4.0 * n1 * m * n2 * p + 2.0 * n3 * p * (n1 * m + m * n2)
+              + 2.0 * n3 * p * (n1 * n2 + n1 * m + m * n2) + 2.0 * p * (n1 * m * n3 + m * n2 * n3)
+              + 2.0 * p * n1 * m * n2)
+        flops = fw + bw
+        models = {"hat": ("hbm", None), "facewise_gemm": ("mfma", 2.0 * n1 * m * n2 * p),
+                  "dq_gemm": ("hbm", None)}
+        info = {"workload": "qprod forward+backward 256x128x128 * 128x256x128 fp32, p=16",
+                "n1": n1, "m": m, "n2": n2, "n3": n3, "p": p}
+        dtype = "f32"
+    log(f"inputs ready in {time.time() - t0:.1f}s: {info['workload']}")
+
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        out = step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    lib.pq_profile_reset()
+    lib.pq_profile_enable(1)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        out = step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    lib.pq_profile_enable(0)
+    total_ms = ev0.elapsed_time(ev1)
+    ms_per_step = total_ms / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step")
+
+    # per-kernel durations from the library's own events on the launch stream
+    import ctypes
+    buf = ctypes.create_string_buffer(4096)
+    lib.pq_profile_names(buf, 4096)
+    kernels = {}
+    for nm in [x for x in buf.value.decode().split(",") if x]:
+        t = ctypes.c_double()
+        n = ctypes.c_int()
+        lib.pq_profile_query(nm.encode(), ctypes.byref(t), ctypes.byref(n))
+        kernels[nm] = {"total_ms": t.value, "launches": n.value,
+                       "avg_us": 1000.0 * t.value / max(1, n.value)}
+    lib.pq_profile_reset()
+    for nm, d in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"]):
+        log(f"  {nm:18s} {d['total_ms'] / args.steps * 1000:10.1f} us/step  "
+            f"{d['launches'] // max(1, args.steps)} launches/step  avg {d['avg_us']:.1f} us")
+
+    # dominant kernel and its roofline
+    dom = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])[0] if kernels else None
+    roof = None
+    if dom is not None:
+        bound, units = models.get(dom, ("hbm", None))
+        avg_s = kernels[dom]["avg_us"] * 1e-6
+        if units is not None and avg_s > 0:
+            if bound == "hbm":
+                achieved, peak, unit = units / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+            elif bound == "alu":
+                achieved, peak, unit = units / avg_s / 1e12, FP64_VALU_PEAK, "TFLOP/s"
+            else:
+                achieved, peak, unit = units / avg_s / 1e12, FP32_MFMA_PEAK, "TFLOP/s"
+            roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 4), "peak": peak,
+                    "unit": unit, "frac": round(achieved / peak, 6),
+                    "traffic": TRAFFIC_BYTES.get(dom), "avg_us": round(kernels[dom]["avg_us"], 3)}
+
+    extra = {}
+    if args.workload in ("video", "hyper", "tiny"):
+        Ak = out.Ak
+        Af = A.float() if A.dtype != torch.float64 else A
+        re = (torch.linalg.vector_norm((Af - Ak).reshape(-1)) /
+              torch.linalg.vector_norm(Af.reshape(-1))).item()
+        inf = out.info.cpu().tolist()
+        extra = {"relative_error_A_k": re, "jacobi_sweeps_max": inf[0],
+                 "unconverged_faces": inf[1], "jacobi_sweeps_total": inf[2]}
+        log(f"RE(A_k) = {re:.6e}, sweeps max {inf[0]}, total {inf[2]}, unconverged {inf[1]}")
+
+    value = flops / (ms_per_step * 1e-3) / 1e9
+
+    # CPU oracle baseline (float64, this host's cores), a bounded sample
+    cpu = None
+    if not args.no_cpu_baseline and cpu_case is not None:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()
+                         if d.get("user_api") == "blas"] or [1])
+        except Exception:  # threadpoolctl missing
+            cores = os.cpu_count()
+        _, Al, Qn, k = cpu_case
+        oracle.check_q(Qn)
+        oracle.tsvdq(Al, Qn, k)  # warm-up
+        reps, t_cpu = 0, 0.0
+        t_start = time.time()
+        while time.time() - t_start < args.cpu_seconds or reps == 0:
+            t1 = time.time()
+            oracle.check_q(Qn)
+            oracle.tsvdq(Al, Qn, k)
+            t_cpu += time.time() - t1
+            reps += 1
+        cpu = {"value": round(flops * reps / t_cpu / 1e9, 4), "unit": "GFLOP/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{reps} full passes of the same workload (check_q + tsvdq with A_k, "
+                         f"spatial factors), {t_cpu:.1f}s, float64 numpy/LAPACK"}
+        log(f"cpu oracle: {cpu['value']} GFLOP/s over {reps} passes on {cores} threads")
+
+    line = {
+        "metric": "tSVDQ / *_Q GFLOP/s (nominal flop count) and % roofline, fp32 path, rel err <= 1e-5",
+        "value": round(value, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": dict(info, prec=args.prec, **extra),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    detail = {"kernels_per_step_us": {k2: v["total_ms"] / args.steps * 1000 for k2, v in kernels.items()},
+              "kernels": kernels, "flops_per_step": flops, "line": line}
+    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
+        with open(os.path.join(ROOT, "gpurun_out", f"bench_kernels_{args.workload}.json"), "w") as fh:
+            json.dump(detail, fh, indent=1)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

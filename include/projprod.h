@@ -86,6 +86,22 @@ const char* pq_status_string(int code);
 /* The hipError_t of the last failed launch on the calling thread (0 if none). */
 int pq_last_hip_error(void);
 
+/* ---- per-launch timing ---------------------------------------------------- */
+/*
+ * While enabled, every kernel launch the library makes is bracketed by two
+ * hipEvents recorded on the caller's stream (events come from a pool owned by
+ * the library; no device memory is allocated).  pq_profile_query waits for
+ * the recorded events of the launches named `name` (e.g. "hat", "unhat",
+ * "proj_fused", "facewise_gemm", "jacobi_sweeps"), and returns their summed
+ * duration in milliseconds and their count.  pq_profile_names writes the
+ * comma-separated names seen since the last reset into buf (host, len bytes).
+ * pq_profile_reset forgets the records.  Process-wide; calls are serialised.
+ */
+int pq_profile_enable(int on);
+int pq_profile_reset(void);
+int pq_profile_query(const char* name, double* total_ms, int* launches);
+int pq_profile_names(char* buf, size_t len);
+
 /* ---- Q intake ------------------------------------------------------------ */
 /*
  * Distance of Q from the Stiefel manifold, max_ij |(Q^T Q - I_p)_ij|, in
@@ -198,10 +214,10 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
  * Singular vectors of a face whose singular value is zero (rank-deficient
  * faces) are written as zero vectors.  tol is the Jacobi stopping threshold
  * on |a_i . a_j| / (|a_i| |a_j|) (<= 0 selects the default for the dtype),
- * max_sweeps caps the sweeps (<= 0: default 30).  info_dev (device int[2],
- * may be NULL) receives [0] = the largest number of sweeps any face used and
+ * max_sweeps caps the sweeps (<= 0: default 30).  info_dev (device int[3],
+ * may be NULL) receives [0] = the largest number of sweeps any face used,
  * [1] = the number of faces that hit max_sweeps before converging (their
- * outputs are still written).  Workspace: pq_tsvdq_workspace bytes.
+ * outputs are still written) and [2] = the sweeps summed over the faces.  Workspace: pq_tsvdq_workspace bytes.
  */
 size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k,
                           int a_dtype);

@@ -18,6 +18,11 @@ SIGNATURES = {
     "pq_version": (_i32, []),
     "pq_status_string": (ctypes.c_char_p, [_i32]),
     "pq_last_hip_error": (_i32, []),
+    "pq_profile_enable": (_i32, [_i32]),
+    "pq_profile_reset": (_i32, []),
+    "pq_profile_query": (_i32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_int)]),
+    "pq_profile_names": (_i32, [ctypes.c_char_p, _sz]),
     "pq_check_q": (_i32, [_vp, _i32, _i64, _i64, _vp, _vp]),
     "pq_hat": (_i32, [_vp, _i32, _vp, _vp, _i64, _i64, _i64, _i64, _i32, _vp]),
     "pq_unhat": (_i32, [_vp, _vp, _vp, _i32, _i64, _i64, _i64, _i64, _i32, _vp]),

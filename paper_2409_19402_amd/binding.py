@@ -272,7 +272,8 @@ TSVDQ = namedtuple("TSVDQ", "Uhat s Vhat Uk Sk Vk Ak info")
 def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_sweeps=0):
     """Truncated *_Q-SVD (Alg. 4.1).  Returns TSVDQ(Uhat n1 x k x p,
     s (k, p), Vhat n2 x k x p, Uk, Sk (k, n3), Vk [spatial=True], Ak
-    [approx=True], info = int32 device tensor [max sweeps, unconverged faces])."""
+    [approx=True], info = int32 device tensor [max sweeps, unconverged faces,
+    total sweeps])."""
     _tensor(A, "A")
     _q(Q, A.dtype)
     n1, n2, n3 = A.shape
@@ -288,7 +289,7 @@ def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_swe
     Vk = empty(n2, k, n3, od, dev) if spatial else None
     Sk = torch.empty((n3, k), dtype=od, device=dev) if spatial else None
     Ak = empty(n1, n2, n3, od, dev) if approx else None
-    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    info = torch.zeros(3, dtype=torch.int32, device=dev)
     lib = _lib.load()
     wsb, nb = _ws(lib.pq_tsvdq_workspace(n1, n2, n3, p, k, _DT[A.dtype]), dev)
     call("pq_tsvdq", _ptr(A), _DT[A.dtype], _ptr(Q), n1, n2, n3, p, k, PREC[prec], _ptr(Uh),

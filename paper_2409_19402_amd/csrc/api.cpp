@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "../../include/projprod.h"
 #include "internal.hpp"
@@ -35,6 +38,51 @@ int hip_status(hipError_t e) {
     int _rc = (expr);                       \
     if (_rc != PQ_OK) return _rc;           \
   } while (0)
+
+// ---- per-launch timing (pq_profile_*) ------------------------------------
+// When enabled, every launch below is bracketed by two hipEvents recorded on
+// the caller's stream; the events come from a pool that grows on demand.
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(const char* n, hipStream_t st) : name(n), s(st) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on) return;
+    a = prof_event();
+    if (a) hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    hipEvent_t b = prof_event();
+    if (!b) return;
+    hipEventRecord(b, s);
+    g_prof_recs.push_back({name, a, b});
+  }
+};
+
+#define PQ_PROF(name, stream) ProfScope _pq_prof_scope(name, stream)
 
 constexpr int64_t kMaxDim = (int64_t)1 << 30;
 
@@ -91,6 +139,7 @@ int ksplit_for(int64_t K) { return (int)std::clamp<int64_t>(K / 512, 1, 1024); }
 // ---- dispatch by dtype -------------------------------------------------------
 hipError_t do_hat(const void* A, int a_dtype, const void* Q, void* Ah, int64_t N, int n3, int p,
                   Prec prec, hipStream_t s) {
+  PQ_PROF("hat", s);
   if (a_dtype == PQ_F64)
     return pq::hat_f64(static_cast<const double*>(A), static_cast<const double*>(Q),
                        static_cast<double*>(Ah), N, n3, p, s);
@@ -100,6 +149,7 @@ hipError_t do_hat(const void* A, int a_dtype, const void* Q, void* Ah, int64_t N
 
 hipError_t do_unhat(const void* Ah, const void* Q, void* A, int dtype, int64_t N, int n3, int p,
                     Prec prec, hipStream_t s) {
+  PQ_PROF("unhat", s);
   if (dtype == PQ_F64)
     return pq::unhat_f64(static_cast<const double*>(Ah), static_cast<const double*>(Q),
                          static_cast<double*>(A), N, n3, p, s);
@@ -107,12 +157,14 @@ hipError_t do_unhat(const void* Ah, const void* Q, void* A, int dtype, int64_t N
                        static_cast<float*>(A), N, n3, p, prec, s);
 }
 
-hipError_t do_gemm(const Gemm& g, int dtype, Prec prec, hipStream_t s) {
+hipError_t do_gemm(const char* name, const Gemm& g, int dtype, Prec prec, hipStream_t s) {
+  PQ_PROF(name, s);
   return dtype == PQ_F64 ? pq::gemm_f64(g, s) : pq::gemm_f32(g, prec, s);
 }
 
 hipError_t do_sum(const void* parts, int nparts, int64_t stride, int64_t count, void* out, int dtype,
                   hipStream_t s) {
+  PQ_PROF("sum_partials", s);
   if (dtype == PQ_F64)
     return pq::sum_partials_f64(static_cast<const double*>(parts), nparts, stride, count,
                                 static_cast<double*>(out), s);
@@ -170,11 +222,68 @@ const char* pq_status_string(int code) {
 
 int pq_last_hip_error(void) { return g_last_hip; }
 
+int pq_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+  return PQ_OK;
+}
+
+int pq_profile_reset(void) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (ProfRec& r : g_prof_recs) {
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_recs.clear();
+  return PQ_OK;
+}
+
+int pq_profile_query(const char* name, double* total_ms, int* launches) {
+  if (!name || !total_ms || !launches) return PQ_ERR_NULL;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  double tot = 0.0;
+  int n = 0;
+  for (const ProfRec& r : g_prof_recs) {
+    if (std::strcmp(r.name, name) != 0) continue;
+    PQ_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    PQ_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *launches = n;
+  return PQ_OK;
+}
+
+int pq_profile_names(char* buf, size_t len) {
+  if (!buf || len == 0) return PQ_ERR_NULL;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  std::vector<const char*> seen;
+  for (const ProfRec& r : g_prof_recs) {
+    bool dup = false;
+    for (const char* q : seen) dup |= std::strcmp(q, r.name) == 0;
+    if (!dup) seen.push_back(r.name);
+  }
+  size_t pos = 0;
+  buf[0] = 0;
+  for (const char* q : seen) {
+    const size_t l = std::strlen(q);
+    if (pos + l + 2 > len) return PQ_ERR_ARG;
+    if (pos) buf[pos++] = ',';
+    std::memcpy(buf + pos, q, l);
+    pos += l;
+    buf[pos] = 0;
+  }
+  return PQ_OK;
+}
+
 int pq_check_q(const void* Q, int q_dtype, int64_t n3, int64_t p, double* out_dev, hipStream_t stream) {
   if (!Q || !out_dev) return PQ_ERR_NULL;
   PQ_CHECK(check_ar_dtype(q_dtype));
   PQ_CHECK(check_dims({n3}));
   PQ_CHECK(check_p(n3, p));
+  PQ_PROF("check_q", stream);
   PQ_TRY(pq::check_q_launch(Q, is_f64(q_dtype), (int)n3, (int)p, out_dev, stream));
   return PQ_OK;
 }
@@ -219,6 +328,7 @@ int pq_proj(const void* A, int a_dtype, const void* Q, void* out, int64_t n1, in
   PQ_CHECK(no_alias(out, {A, Q}));
   const int64_t N = n1 * n2;
   if (a_dtype != PQ_F64 && pq::proj_fused_ok((int)n3, (int)p)) {
+    PQ_PROF("proj_fused", stream);
     PQ_TRY(pq::proj_fused_f32(A, a_dtype == PQ_BF16, static_cast<const float*>(Q),
                               static_cast<float*>(out), N, (int)n3, (int)p, (Prec)prec, stream));
     return PQ_OK;
@@ -241,7 +351,7 @@ int pq_facewise(const void* Ah, const void* Bh, void* Ch, int dtype, int64_t n1,
   PQ_CHECK(no_alias(Ch, {Ah, Bh}));
   Gemm g = face_gemm(false, false, (int)n1, (int)n2, (int)m, Ah, n1, n1 * m, Bh, m, m * n2, Ch, n1,
                      n1 * n2, (int)p);
-  PQ_TRY(do_gemm(g, dtype, (Prec)prec, stream));
+  PQ_TRY(do_gemm("facewise_gemm", g, dtype, (Prec)prec, stream));
   return PQ_OK;
 }
 
@@ -277,7 +387,7 @@ int pq_qprod(const void* A, const void* B, int ab_dtype, const void* Q, void* C,
   PQ_TRY(do_hat(B, ab_dtype, Q, Bh, m * n2, (int)n3, (int)p, pr, stream));
   Gemm g = face_gemm(false, false, (int)n1, (int)n2, (int)m, Ah, n1, n1 * m, Bh, m, m * n2, Ch, n1,
                      n1 * n2, (int)p);
-  PQ_TRY(do_gemm(g, dt, pr, stream));
+  PQ_TRY(do_gemm("facewise_gemm", g, dt, pr, stream));
   PQ_TRY(do_unhat(Ch, Q, C, dt, n1 * n2, (int)n3, (int)p, pr, stream));
   return PQ_OK;
 }
@@ -337,24 +447,24 @@ int pq_qprod_backward(const void* G, const void* A, const void* B, const void* Q
   if (need_dAh) {  // dAh_l = dCh_l Bh_l^T   (n1 x m)
     Gemm g = face_gemm(false, true, (int)n1, (int)m, (int)n2, dCh, n1, n1 * n2, Bh, m, m * n2, dAh, n1,
                        n1 * m, (int)p);
-    PQ_TRY(do_gemm(g, dtype, pr, stream));
+    PQ_TRY(do_gemm("adjoint_gemm", g, dtype, pr, stream));
   }
   if (need_dBh) {  // dBh_l = Ah_l^T dCh_l   (m x n2)
     Gemm g = face_gemm(true, false, (int)m, (int)n2, (int)n1, Ah, n1, n1 * m, dCh, n1, n1 * n2, dBh, m,
                        m * n2, (int)p);
-    PQ_TRY(do_gemm(g, dtype, pr, stream));
+    PQ_TRY(do_gemm("adjoint_gemm", g, dtype, pr, stream));
   }
   if (dA) PQ_TRY(do_unhat(dAh, Q, dA, dtype, n1 * m, (int)n3, (int)p, pr, stream));
   if (dB) PQ_TRY(do_unhat(dBh, Q, dB, dtype, m * n2, (int)n3, (int)p, pr, stream));
   if (dQ) {
     Gemm fw = face_gemm(false, false, (int)n1, (int)n2, (int)m, Ah, n1, n1 * m, Bh, m, m * n2, Ch, n1,
                         n1 * n2, (int)p);
-    PQ_TRY(do_gemm(fw, dtype, pr, stream));
+    PQ_TRY(do_gemm("facewise_gemm", fw, dtype, pr, stream));
     char* pb = static_cast<char*>(parts);
     const size_t slab = e * (size_t)p * n3;
-    PQ_TRY(do_gemm(dq_gemm(Ch, G, (int)p, (int)n3, n1 * n2, pb, ks1), dtype, pr, stream));
-    PQ_TRY(do_gemm(dq_gemm(dAh, A, (int)p, (int)n3, n1 * m, pb + slab * ks1, ks2), dtype, pr, stream));
-    PQ_TRY(do_gemm(dq_gemm(dBh, B, (int)p, (int)n3, m * n2, pb + slab * (ks1 + ks2), ks3), dtype, pr,
+    PQ_TRY(do_gemm("dq_gemm", dq_gemm(Ch, G, (int)p, (int)n3, n1 * n2, pb, ks1), dtype, pr, stream));
+    PQ_TRY(do_gemm("dq_gemm", dq_gemm(dAh, A, (int)p, (int)n3, n1 * m, pb + slab * ks1, ks2), dtype, pr, stream));
+    PQ_TRY(do_gemm("dq_gemm", dq_gemm(dBh, B, (int)p, (int)n3, m * n2, pb + slab * (ks1 + ks2), ks3), dtype, pr,
                    stream));
     PQ_TRY(do_sum(parts, ks1 + ks2 + ks3, p * n3, p * n3, dQ, dtype, stream));
   }
@@ -394,8 +504,8 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype, int
     char* pb = static_cast<char*>(parts);
     const size_t slab = e * (size_t)p * n3;
     // dQ^T = Ah_(3) G_(3)^T + Gh_(3) A_(3)^T
-    PQ_TRY(do_gemm(dq_gemm(Ah, G, (int)p, (int)n3, N, pb, ks), dtype, pr, stream));
-    PQ_TRY(do_gemm(dq_gemm(Gh, A, (int)p, (int)n3, N, pb + slab * ks, ks), dtype, pr, stream));
+    PQ_TRY(do_gemm("dq_gemm", dq_gemm(Ah, G, (int)p, (int)n3, N, pb, ks), dtype, pr, stream));
+    PQ_TRY(do_gemm("dq_gemm", dq_gemm(Gh, A, (int)p, (int)n3, N, pb + slab * ks, ks), dtype, pr, stream));
     PQ_TRY(do_sum(parts, 2 * ks, p * n3, p * n3, dQ, dtype, stream));
   }
   return PQ_OK;
@@ -453,37 +563,48 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   const int nv = cols ? in2 : in1, L = cols ? in1 : in2;
   void* F = cols ? Uhat : Vhat;        // side given by the Jacobi vectors
   void* Other = cols ? Vhat : Uhat;    // side given by one more product
-  if (f64) {
-    PQ_TRY(pq::jacobi_prep_f64(static_cast<const double*>(Ah), static_cast<double*>(W), in1, in2, ip, stream));
-    PQ_TRY(pq::jacobi_sweeps_f64(static_cast<double*>(W), ip, nv, L, max_sweeps, tol, used, stream));
-    PQ_TRY(pq::jacobi_finalize_f64(static_cast<const double*>(W), ip, nv, L, ik, static_cast<double*>(F),
-                                   static_cast<double*>(s), static_cast<double*>(inv_s), stream));
-  } else {
-    PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(Ah), static_cast<float*>(W), in1, in2, ip, stream));
-    PQ_TRY(pq::jacobi_sweeps_f32(static_cast<float*>(W), ip, nv, L, max_sweeps, tol, used, stream));
-    PQ_TRY(pq::jacobi_finalize_f32(static_cast<const float*>(W), ip, nv, L, ik, static_cast<float*>(F),
-                                   static_cast<float*>(s), static_cast<float*>(inv_s), stream));
+  {
+    PQ_PROF("jacobi_prep", stream);
+    if (f64) PQ_TRY(pq::jacobi_prep_f64(static_cast<const double*>(Ah), static_cast<double*>(W), in1, in2, ip, stream));
+    else PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(Ah), static_cast<float*>(W), in1, in2, ip, stream));
+  }
+  {
+    PQ_PROF("jacobi_sweeps", stream);
+    if (f64) PQ_TRY(pq::jacobi_sweeps_f64(static_cast<double*>(W), ip, nv, L, max_sweeps, tol, used, stream));
+    else PQ_TRY(pq::jacobi_sweeps_f32(static_cast<float*>(W), ip, nv, L, max_sweeps, tol, used, stream));
+  }
+  {
+    PQ_PROF("jacobi_finalize", stream);
+    if (f64)
+      PQ_TRY(pq::jacobi_finalize_f64(static_cast<const double*>(W), ip, nv, L, ik, static_cast<double*>(F),
+                                     static_cast<double*>(s), static_cast<double*>(inv_s), stream));
+    else
+      PQ_TRY(pq::jacobi_finalize_f32(static_cast<const float*>(W), ip, nv, L, ik, static_cast<float*>(F),
+                                     static_cast<float*>(s), static_cast<float*>(inv_s), stream));
   }
   // Other side, unscaled: Y = Ah_l^T Uhat_l (n2 x k) or Y = Ah_l Vhat_l (n1 x k)
   const int orows = cols ? in2 : in1;
   {
     Gemm g = cols ? face_gemm(true, false, in2, ik, in1, Ah, n1, N, F, n1, n1 * k, Y, n2, n2 * k, ip)
                   : face_gemm(false, false, in1, ik, in2, Ah, n1, N, F, n2, n2 * k, Y, n1, n1 * k, ip);
-    PQ_TRY(do_gemm(g, dt, pr, stream));
+    PQ_TRY(do_gemm("factor_gemm", g, dt, pr, stream));
   }
-  if (f64)
-    PQ_TRY(pq::scale_cols_f64(static_cast<const double*>(Y), static_cast<double*>(Other), orows, ik, ip,
-                              static_cast<const double*>(inv_s), stream));
-  else
-    PQ_TRY(pq::scale_cols_f32(static_cast<const float*>(Y), static_cast<float*>(Other), orows, ik, ip,
-                              static_cast<const float*>(inv_s), stream));
+  {
+    PQ_PROF("scale_cols", stream);
+    if (f64)
+      PQ_TRY(pq::scale_cols_f64(static_cast<const double*>(Y), static_cast<double*>(Other), orows, ik, ip,
+                                static_cast<const double*>(inv_s), stream));
+    else
+      PQ_TRY(pq::scale_cols_f32(static_cast<const float*>(Y), static_cast<float*>(Other), orows, ik, ip,
+                                static_cast<const float*>(inv_s), stream));
+  }
   if (info_dev) PQ_TRY(pq::jacobi_info(used, ip, max_sweeps, info_dev, stream));
   // step 4 and the approximation of Thm. 4.2
   if (Ak) {
     // Akh_l = Uhat_l Y_l^T (cols) or Y_l Vhat_l^T (rows): both equal Uhat S Vhat^T
     Gemm g = cols ? face_gemm(false, true, in1, in2, ik, F, n1, n1 * k, Y, n2, n2 * k, Akh, n1, N, ip)
                   : face_gemm(false, true, in1, in2, ik, Y, n1, n1 * k, F, n2, n2 * k, Akh, n1, N, ip);
-    PQ_TRY(do_gemm(g, dt, pr, stream));
+    PQ_TRY(do_gemm("approx_gemm", g, dt, pr, stream));
     PQ_TRY(do_unhat(Akh, Q, Ak, dt, N, (int)n3, ip, pr, stream));
   }
   if (Uk) PQ_TRY(do_unhat(Uhat, Q, Uk, dt, n1 * k, (int)n3, ip, pr, stream));

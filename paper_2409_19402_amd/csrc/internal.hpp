@@ -77,7 +77,7 @@ hipError_t jacobi_finalize_f32(const float* W, int p, int nv, int L, int k,
 hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k,
                                double* F, double* s_out, double* inv_s, hipStream_t s);
 // info[0] = max_l min(sweeps_used[l], max_sweeps); info[1] = #faces that did
-// not converge.
+// not converge; info[2] = sum_l min(sweeps_used[l], max_sweeps).
 hipError_t jacobi_info(const int* sweeps_used, int p, int max_sweeps, int* info, hipStream_t s);
 
 }  // namespace pq

@@ -183,8 +183,11 @@ __global__ void info_kernel(const int* __restrict__ used, int p, int max_sweeps,
       mx = max(mx, u);
     }
   }
+  int total = 0;
+  for (int l = 0; l < p; ++l) total += min(used[l], max_sweeps);
   info[0] = mx;
   info[1] = bad;
+  info[2] = total;
 }
 
 }  // namespace
