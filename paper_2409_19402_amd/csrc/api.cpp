@@ -134,6 +134,9 @@ struct Arena {
   bool fits() const { return used <= cap; }
 };
 
+constexpr int kDefaultSweeps = 30;
+constexpr int kMaxSweepsCap = 100;
+
 int ksplit_for(int64_t K) { return (int)std::clamp<int64_t>(K / 512, 1, 1024); }
 
 // ---- dispatch by dtype -------------------------------------------------------
@@ -514,13 +517,14 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype, int
 size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k, int a_dtype) {
   (void)n3;
   const size_t e = elem(a_dtype == PQ_F64 ? PQ_F64 : PQ_F32);
-  const int64_t mx = std::max(n1, n2);
-  return align_up(e * n1 * n2 * p)        // Ah
-         + align_up(e * n1 * n2 * p)      // Jacobi working vectors
-         + align_up(sizeof(int) * p)      // sweeps per face
-         + align_up(e * k * p)            // 1 / singular values
-         + align_up(e * mx * k * p)       // unscaled other factor
-         + align_up(e * n1 * n2 * p);     // transform-domain A_k
+  const int64_t mx = std::max(n1, n2), mn = std::min(n1, n2);
+  return align_up(e * n1 * n2 * p)                    // Ah
+         + align_up(e * n1 * n2 * p)                  // Jacobi working vectors
+         + align_up(sizeof(int) * p)                  // sweeps per face
+         + align_up(sizeof(int) * p * kMaxSweepsCap)  // per-sweep rotation flags
+         + align_up(e * mx * k * p)                   // top-k Jacobi vectors
+         + align_up(e * mn * k * p) * 2               // other side, before and after ordering
+         + align_up(e * n1 * n2 * p);                 // transform-domain A_k
 }
 
 int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p,
@@ -540,29 +544,33 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   if (std::min(n1, n2) > 4096) return PQ_ERR_UNSUPPORTED;
   if (p > 512 && a_dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
   if (!ws || ws_bytes < pq_tsvdq_workspace(n1, n2, n3, p, k, a_dtype)) return PQ_ERR_WORKSPACE;
-  if (max_sweeps <= 0) max_sweeps = 30;
+  if (max_sweeps <= 0) max_sweeps = kDefaultSweeps;
+  if (max_sweeps > kMaxSweepsCap) return PQ_ERR_ARG;
   const bool f64 = a_dtype == PQ_F64;
   const int dt = f64 ? PQ_F64 : PQ_F32;
   if (tol <= 0.0) tol = f64 ? 1e-14 : 2e-7;
   const size_t e = elem(dt);
   const int64_t N = n1 * n2;
-  const int64_t mx = std::max(n1, n2);
+  const int64_t mx = std::max(n1, n2), mn = std::min(n1, n2);
   Arena ar(ws, ws_bytes);
   void* Ah = ar.take(e * N * p);
   void* W = ar.take(e * N * p);
   int* used = static_cast<int*>(ar.take(sizeof(int) * p));
-  void* inv_s = ar.take(e * k * p);
-  void* Y = ar.take(e * mx * k * p);
+  int* flags = static_cast<int*>(ar.take(sizeof(int) * p * kMaxSweepsCap));
+  void* Ft = ar.take(e * mx * k * p);
+  void* Y = ar.take(e * mn * k * p);
+  void* Ys = ar.take(e * mn * k * p);
   void* Akh = ar.take(e * N * p);
   const Prec pr = (Prec)prec;
   const int in1 = (int)n1, in2 = (int)n2, ip = (int)p, ik = (int)k;
   // step 2: transform domain
   PQ_TRY(do_hat(A, a_dtype, Q, Ah, N, (int)n3, ip, pr, stream));
-  // step 3: facewise truncated SVD
-  const bool cols = n1 >= n2;  // orthogonalise the shorter side's vectors
-  const int nv = cols ? in2 : in1, L = cols ? in1 : in2;
-  void* F = cols ? Uhat : Vhat;        // side given by the Jacobi vectors
-  void* Other = cols ? Vhat : Uhat;    // side given by one more product
+  // step 3: facewise truncated SVD.  The Jacobi vectors are the shorter side's
+  // (columns of each face when n1 >= n2, rows otherwise).
+  const bool cols = n1 >= n2;
+  const int nv = (int)mn, L = (int)mx;
+  void* Fo = cols ? Uhat : Vhat;     // side given by the Jacobi vectors
+  void* Other = cols ? Vhat : Uhat;  // side given by one more product
   {
     PQ_PROF("jacobi_prep", stream);
     if (f64) PQ_TRY(pq::jacobi_prep_f64(static_cast<const double*>(Ah), static_cast<double*>(W), in1, in2, ip, stream));
@@ -570,40 +578,37 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   }
   {
     PQ_PROF("jacobi_sweeps", stream);
-    if (f64) PQ_TRY(pq::jacobi_sweeps_f64(static_cast<double*>(W), ip, nv, L, max_sweeps, tol, used, stream));
-    else PQ_TRY(pq::jacobi_sweeps_f32(static_cast<float*>(W), ip, nv, L, max_sweeps, tol, used, stream));
+    if (f64) PQ_TRY(pq::jacobi_sweeps_f64(static_cast<double*>(W), ip, nv, L, max_sweeps, tol, used, flags, stream));
+    else PQ_TRY(pq::jacobi_sweeps_f32(static_cast<float*>(W), ip, nv, L, max_sweeps, tol, used, flags, stream));
   }
   {
     PQ_PROF("jacobi_finalize", stream);
-    if (f64)
-      PQ_TRY(pq::jacobi_finalize_f64(static_cast<const double*>(W), ip, nv, L, ik, static_cast<double*>(F),
-                                     static_cast<double*>(s), static_cast<double*>(inv_s), stream));
-    else
-      PQ_TRY(pq::jacobi_finalize_f32(static_cast<const float*>(W), ip, nv, L, ik, static_cast<float*>(F),
-                                     static_cast<float*>(s), static_cast<float*>(inv_s), stream));
+    if (f64) PQ_TRY(pq::jacobi_finalize_f64(static_cast<const double*>(W), ip, nv, L, ik, static_cast<double*>(Ft), stream));
+    else PQ_TRY(pq::jacobi_finalize_f32(static_cast<const float*>(W), ip, nv, L, ik, static_cast<float*>(Ft), stream));
   }
-  // Other side, unscaled: Y = Ah_l^T Uhat_l (n2 x k) or Y = Ah_l Vhat_l (n1 x k)
-  const int orows = cols ? in2 : in1;
+  // Y = Ah_l^T Ft_l (n2 x k) or Ah_l Ft_l (n1 x k), unscaled
   {
-    Gemm g = cols ? face_gemm(true, false, in2, ik, in1, Ah, n1, N, F, n1, n1 * k, Y, n2, n2 * k, ip)
-                  : face_gemm(false, false, in1, ik, in2, Ah, n1, N, F, n2, n2 * k, Y, n1, n1 * k, ip);
+    Gemm g = cols ? face_gemm(true, false, in2, ik, in1, Ah, n1, N, Ft, n1, n1 * k, Y, n2, n2 * k, ip)
+                  : face_gemm(false, false, in1, ik, in2, Ah, n1, N, Ft, n2, n2 * k, Y, n1, n1 * k, ip);
     PQ_TRY(do_gemm("factor_gemm", g, dt, pr, stream));
   }
   {
-    PQ_PROF("scale_cols", stream);
+    PQ_PROF("jacobi_refine", stream);
     if (f64)
-      PQ_TRY(pq::scale_cols_f64(static_cast<const double*>(Y), static_cast<double*>(Other), orows, ik, ip,
-                                static_cast<const double*>(inv_s), stream));
+      PQ_TRY(pq::jacobi_refine_f64(static_cast<double*>(Y), static_cast<double*>(Ft), nv, L, ik, ip, tol,
+                                   static_cast<double*>(s), static_cast<double*>(Other),
+                                   static_cast<double*>(Fo), static_cast<double*>(Ys), stream));
     else
-      PQ_TRY(pq::scale_cols_f32(static_cast<const float*>(Y), static_cast<float*>(Other), orows, ik, ip,
-                                static_cast<const float*>(inv_s), stream));
+      PQ_TRY(pq::jacobi_refine_f32(static_cast<float*>(Y), static_cast<float*>(Ft), nv, L, ik, ip, tol,
+                                   static_cast<float*>(s), static_cast<float*>(Other),
+                                   static_cast<float*>(Fo), static_cast<float*>(Ys), stream));
   }
   if (info_dev) PQ_TRY(pq::jacobi_info(used, ip, max_sweeps, info_dev, stream));
   // step 4 and the approximation of Thm. 4.2
   if (Ak) {
-    // Akh_l = Uhat_l Y_l^T (cols) or Y_l Vhat_l^T (rows): both equal Uhat S Vhat^T
-    Gemm g = cols ? face_gemm(false, true, in1, in2, ik, F, n1, n1 * k, Y, n2, n2 * k, Akh, n1, N, ip)
-                  : face_gemm(false, true, in1, in2, ik, Y, n1, n1 * k, F, n2, n2 * k, Akh, n1, N, ip);
+    // Akh_l = Uhat_l Ys_l^T (cols) or Ys_l Vhat_l^T (rows): both Uhat S Vhat^T
+    Gemm g = cols ? face_gemm(false, true, in1, in2, ik, Fo, n1, n1 * k, Ys, n2, n2 * k, Akh, n1, N, ip)
+                  : face_gemm(false, true, in1, in2, ik, Ys, n1, n1 * k, Fo, n2, n2 * k, Akh, n1, N, ip);
     PQ_TRY(do_gemm("approx_gemm", g, dt, pr, stream));
     PQ_TRY(do_unhat(Akh, Q, Ak, dt, N, (int)n3, ip, pr, stream));
   }

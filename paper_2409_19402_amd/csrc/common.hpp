@@ -86,6 +86,33 @@ __device__ __forceinline__ float wave_sum(float v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
+// Cross-lane move of a double with a DPP control (both 32-bit halves moved
+// alike); lanes of rows left out of ROW_MASK get 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes on the VALU (DPP, no LDS traffic), returned as a
+// wave-uniform value.  Lanes 0-15 form row 0 and so on:
+//   quad_perm [1,0,3,2], [2,3,0,1]  -> every lane holds its quad's sum
+//   row_half_mirror, row_mirror     -> every lane holds its row's sum
+//   row_bcast:15 into rows 1 and 3  -> rows 1, 3 hold rows 0+1, 2+3
+//   row_bcast:31 into rows 2 and 3  -> row 3 holds the total; read lane 63.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  v += dpp_f64<0x142, 0xA>(v);
+  v += dpp_f64<0x143, 0xC>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));

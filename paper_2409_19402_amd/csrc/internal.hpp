@@ -51,11 +51,6 @@ hipError_t sum_partials_f64(const double* parts, int nparts, int64_t stride,
 
 // ---- small helpers (misc.hip) ---------------------------------------------
 hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, hipStream_t s);
-// out(i, j, l) = in(i, j, l) * scale[j + l*k]; face l is rows x k column-major.
-hipError_t scale_cols_f32(const float* in, float* out, int64_t rows, int k, int p,
-                          const float* scale, hipStream_t s);
-hipError_t scale_cols_f64(const double* in, double* out, int64_t rows, int k, int p,
-                          const double* scale, hipStream_t s);
 
 // ---- facewise one-sided Jacobi SVD (jacobi.hip) -----------------------------
 // W holds, for each of p faces, nv vectors of length L (vector j of face l at
@@ -66,16 +61,21 @@ hipError_t jacobi_prep_f32(const float* Ah, float* W, int n1, int n2, int p, hip
 hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, hipStream_t s);
 // Orthogonalises the nv vectors of every face; sweeps_used[l] gets the sweep
 // count of face l, or max_sweeps + 1 when it stopped without converging.
+// flags: p * max_sweeps ints of scratch.
 hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol,
-                             int* sweeps_used, hipStream_t s);
+                             int* sweeps_used, int* flags, hipStream_t s);
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol,
-                             int* sweeps_used, hipStream_t s);
-// Column norms, descending order, top k: s (k x p), inv_s (k x p, 0 for a
-// zero singular value) and the normalised vectors F (L x k x p).
-hipError_t jacobi_finalize_f32(const float* W, int p, int nv, int L, int k,
-                               float* F, float* s_out, float* inv_s, hipStream_t s);
-hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k,
-                               double* F, double* s_out, double* inv_s, hipStream_t s);
+                             int* sweeps_used, int* flags, hipStream_t s);
+// Column norms, descending order, top k normalised vectors F (L x k x p).
+hipError_t jacobi_finalize_f32(const float* W, int p, int nv, int L, int k, float* F, hipStream_t s);
+hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k, double* F, hipStream_t s);
+// Jacobi on the k columns of Y (m1 x k x p), each rotation applied to F
+// (m2 x k x p) too; writes s (k x p, descending), Other = Y / s, Fo = F and
+// Ys = Y, all in descending order of s.
+hipError_t jacobi_refine_f32(float* Y, float* F, int m1, int m2, int k, int p, double tol,
+                             float* s_out, float* Other, float* Fo, float* Ys, hipStream_t s);
+hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, double tol,
+                             double* s_out, double* Other, double* Fo, double* Ys, hipStream_t s);
 // info[0] = max_l min(sweeps_used[l], max_sweeps); info[1] = #faces that did
 // not converge; info[2] = sum_l min(sweeps_used[l], max_sweeps).
 hipError_t jacobi_info(const int* sweeps_used, int p, int max_sweeps, int* info, hipStream_t s);

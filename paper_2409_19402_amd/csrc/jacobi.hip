@@ -2,15 +2,31 @@
 // one-sided (Hestenes) Jacobi.
 //
 // Each face contributes nv = min(n1, n2) vectors of length L = max(n1, n2)
-// (its columns when n1 >= n2, its rows otherwise).  A sweep visits every pair
-// once in round-robin order: nv - 1 rounds of nv/2 disjoint pairs, so the
-// pairs of a round rotate independently, one pair per wave.  For a pair the
-// wave forms alpha = |a|^2, beta = |b|^2, gamma = a.b with float64
-// accumulation and 64-lane shuffle reductions, computes the rotation that
-// zeroes gamma in float64, and applies it.  A face has converged after a
-// sweep in which no pair had |gamma| > tol sqrt(alpha beta).  Converged
-// vectors are mutually orthogonal; their norms are the singular values and,
-// normalised, they are the singular vectors of their side.
+// (its columns when n1 >= n2, its rows otherwise).  For a pair (a, c) a wave
+// forms alpha = |a|^2, beta = |c|^2, gamma = a.c with float64 accumulation
+// and a DPP reduction across its lanes, computes in float64 the plane
+// rotation that zeroes gamma, and applies it.  Converged vectors are mutually
+// orthogonal; their norms are the singular values and, normalised, they are
+// the singular vectors of their side.  A face has converged after a sweep in
+// which no pair had |gamma| > tol sqrt(alpha beta).
+//
+// Schedule (block form): the nv vectors are cut into nb blocks of b vectors
+// (nb even; vectors past nv are zero and never rotate; b = 4 per wave, one
+// pair per 16-lane row).  One launch is one
+// round of a round-robin tournament over the blocks: workgroup (x, face)
+// stages the 2b vectors of block pair x in LDS.  In the first round of a sweep
+// it runs a full round-robin over all 2b vectors (every block takes part in
+// that round, so every pair inside a block is visited once per sweep); in the
+// other rounds only the b*b pairs between its two blocks are left, visited in
+// b rounds with the first block's vectors kept in registers.  nb - 1 launches
+// make a sweep.  With nb == 2 one workgroup holds the whole face and loops
+// over sweeps by itself.  Vectors longer than 1024 fall back to a form with
+// one workgroup per face and the pairs read from global memory.
+//
+// The factor on the other side is Y = Ahat F (or Ahat^T F) for the top-k
+// Jacobi vectors F.  A last small Jacobi on the k columns of Y, applying each
+// rotation to F as well, makes both factors orthonormal to working precision
+// without changing Y F^T; its column norms are the singular values.
 #include <algorithm>
 
 #include "common.hpp"
@@ -21,62 +37,217 @@ namespace {
 
 constexpr int kJacobiThreads = 1024;
 
+// circle-method round robin over n (even) players: pair `pi` of round `r`
+__device__ __forceinline__ void circle_pair(int n, int r, int pi, int& a, int& c) {
+  if (pi == 0) {
+    a = n - 1;
+    c = r;
+  } else {
+    a = (r + pi) % (n - 1);
+    c = (r - pi + n - 1) % (n - 1);
+  }
+}
+
+struct Rot {
+  double c, s;
+  bool on;
+};
+
+__device__ __forceinline__ Rot rotation(double al, double be, double ga, double tol) {
+  Rot q{1.0, 0.0, false};
+  if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+    const double zeta = (be - al) / (2.0 * ga);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    q.c = 1.0 / sqrt(1.0 + t * t);
+    q.s = q.c * t;
+    q.on = true;
+  }
+  return q;
+}
+
+// Row-granular pairs: every 16-lane row of a wave owns one pair, so a wave
+// rotates four pairs with the same instructions.  Lane g of a row holds, of
+// each of its two vectors, elements 64c + 4g + j (c < R, j < 4): four
+// consecutive values per 64-element chunk, read from LDS as one 16-byte load.
+// Sums over the 16 lanes of a row use DPP within the row and leave the result
+// in every lane of the row.
+__device__ __forceinline__ double row_total(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return v;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ bool rotate_row_pair(T (&xa)[4 * R], T (&xc)[4 * R], double tol) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4 * R; ++i) {
+    const double a = (double)xa[i], c = (double)xc[i];
+    al = fma(a, a, al);
+    be = fma(c, c, be);
+    ga = fma(a, c, ga);
+  }
+  al = row_total(al);
+  be = row_total(be);
+  ga = row_total(ga);
+  // rotate when |gamma| > tol sqrt(alpha beta)
+  if (!(ga * ga > tol * tol * al * be)) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t);
+  const double sn = cs * t;
+#pragma unroll
+  for (int i = 0; i < 4 * R; ++i) {
+    const double a = (double)xa[i], c = (double)xc[i];
+    xa[i] = static_cast<T>(cs * a - sn * c);
+    xc[i] = static_cast<T>(sn * a + cs * c);
+  }
+  return true;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void row_load(const T* v, int g, T (&x)[4 * R]) {
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[4 * c + j] = v[64 * c + 4 * g + j];
+}
+template <typename T, int R>
+__device__ __forceinline__ void row_store(T* v, int g, const T (&x)[4 * R]) {
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[64 * c + 4 * g + j] = x[4 * c + j];
+}
+
+constexpr int kPairsPerWave = 4;
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void jacobi_block_kernel(T* __restrict__ W, int nv, int L, int nb,
+                                                            int round, int sweep, int max_sweeps,
+                                                            double tol, int* __restrict__ flags,
+                                                            int* __restrict__ sweeps_used) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* V = reinterpret_cast<T*>(smem_raw);
+  __shared__ int any_rot;
+  constexpr int Lp = 64 * R;
+  const int NW = blockDim.x >> 6;
+  const int b = NW * kPairsPerWave;  // vectors per block = pairs per round
+  const int nvl = 2 * b;
+  const int face = blockIdx.y;
+  const bool whole = nb == 2;
+  if (!whole && sweep > 0 && flags[face * max_sweeps + sweep - 1] == 0) return;
+  int I, J;
+  circle_pair(nb, round, blockIdx.x, I, J);
+  T* Wf = W + (int64_t)face * nv * L;
+  for (int idx = threadIdx.x; idx < nvl * Lp; idx += blockDim.x) {
+    const int u = idx / Lp, e = idx - u * Lp;
+    const int g = (u < b) ? I * b + u : J * b + (u - b);
+    T v = T(0);
+    if (g < nv && e < L) v = Wf[(int64_t)g * L + e];
+    V[idx] = v;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gl = lane & 15;                          // lane within the row
+  const int pi = wave * kPairsPerWave + (lane >> 4);  // this row's pair
+  int sw = 0;
+  bool converged = false;
+  do {
+    if (threadIdx.x == 0) any_rot = 0;
+    __syncthreads();
+    bool mine = false;
+    if (whole || round == 0) {
+      for (int r = 0; r < nvl - 1; ++r) {
+        int ia, ic;
+        circle_pair(nvl, r, pi, ia, ic);
+        T xa[4 * R], xc[4 * R];
+        row_load<T, R>(V + ia * Lp, gl, xa);
+        row_load<T, R>(V + ic * Lp, gl, xc);
+        if (rotate_row_pair<T, R>(xa, xc, tol)) {
+          row_store<T, R>(V + ia * Lp, gl, xa);
+          row_store<T, R>(V + ic * Lp, gl, xc);
+          mine = true;
+        }
+        __syncthreads();
+      }
+    } else {
+      T xi[4 * R];
+      row_load<T, R>(V + pi * Lp, gl, xi);
+      for (int r = 0; r < b; ++r) {
+        const int ic = b + (pi + r) % b;
+        T xc[4 * R];
+        row_load<T, R>(V + ic * Lp, gl, xc);
+        if (rotate_row_pair<T, R>(xi, xc, tol)) {
+          row_store<T, R>(V + ic * Lp, gl, xc);
+          mine = true;
+        }
+        __syncthreads();
+      }
+      row_store<T, R>(V + pi * Lp, gl, xi);
+    }
+    if (mine) any_rot = 1;
+    __syncthreads();
+    ++sw;
+    const int rotated = any_rot;
+    __syncthreads();
+    if (!rotated) converged = true;
+    else if (!whole && threadIdx.x == 0) flags[face * max_sweeps + sweep] = 1;
+    if (!whole) break;
+  } while (!converged && sw < max_sweeps);
+  for (int idx = threadIdx.x; idx < nvl * Lp; idx += blockDim.x) {
+    const int u = idx / Lp, e = idx - u * Lp;
+    const int g = (u < b) ? I * b + u : J * b + (u - b);
+    if (g < nv && e < L) Wf[(int64_t)g * L + e] = V[idx];
+  }
+  if (whole && threadIdx.x == 0) sweeps_used[face] = converged ? sw : max_sweeps + 1;
+}
+
+// Long vectors: one workgroup per face, pairs read from global memory.
 template <typename T>
-__global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(T* __restrict__ W, int nv, int L,
-                                                                int max_sweeps, double tol,
-                                                                int* __restrict__ sweeps_used) {
+__global__ __launch_bounds__(kJacobiThreads) void jacobi_global_kernel(T* __restrict__ W, int nv, int L,
+                                                                       int max_sweeps, double tol,
+                                                                       int* __restrict__ sweeps_used) {
   constexpr int NW = kJacobiThreads / 64;
-  __shared__ int rotated;
+  __shared__ int any_rot;
   const int face = blockIdx.x;
   T* Wf = W + (int64_t)face * nv * L;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nvp = nv + (nv & 1);  // with nv odd, index nv is a bye
-  const int npairs = nvp / 2;
+  const int nvp = nv + (nv & 1);
   int sweep = 0;
   bool converged = false;
   while (sweep < max_sweeps) {
-    if (threadIdx.x == 0) rotated = 0;
+    if (threadIdx.x == 0) any_rot = 0;
     __syncthreads();
     for (int round = 0; round < nvp - 1; ++round) {
-      for (int pi = wave; pi < npairs; pi += NW) {
-        int a, b;
-        if (pi == 0) {
-          a = nvp - 1;
-          b = round;
-        } else {
-          a = (round + pi) % (nvp - 1);
-          b = (round - pi + nvp - 1) % (nvp - 1);
-        }
-        if (a >= nv || b >= nv) continue;
+      for (int pi = wave; pi < nvp / 2; pi += NW) {
+        int a, c;
+        circle_pair(nvp, round, pi, a, c);
+        if (a >= nv || c >= nv) continue;
         T* va = Wf + (int64_t)a * L;
-        T* vb = Wf + (int64_t)b * L;
+        T* vc = Wf + (int64_t)c * L;
         double al = 0.0, be = 0.0, ga = 0.0;
         for (int e = lane; e < L; e += 64) {
-          const double x = va[e], y = vb[e];
+          const double x = va[e], y = vc[e];
           al = fma(x, x, al);
           be = fma(y, y, be);
           ga = fma(x, y, ga);
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          const double s = c * t;
+        const Rot q = rotation(wave_total(al), wave_total(be), wave_total(ga), tol);
+        if (q.on) {
           for (int e = lane; e < L; e += 64) {
-            const double x = va[e], y = vb[e];
-            va[e] = static_cast<T>(c * x - s * y);
-            vb[e] = static_cast<T>(s * x + c * y);
+            const double x = va[e], y = vc[e];
+            va[e] = static_cast<T>(q.c * x - q.s * y);
+            vc[e] = static_cast<T>(q.s * x + q.c * y);
           }
-          if (lane == 0) rotated = 1;
+          if (lane == 0) any_rot = 1;
         }
       }
       __syncthreads();
     }
     ++sweep;
-    const int any = rotated;
+    const int any = any_rot;
     __syncthreads();
     if (!any) {
       converged = true;
@@ -84,6 +255,27 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(T* __restrict__ 
     }
   }
   if (threadIdx.x == 0) sweeps_used[face] = converged ? sweep : max_sweeps + 1;
+}
+
+__global__ void zero_ints_kernel(int* __restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
+// sweeps_used[l] from the per-sweep rotation flags: the first sweep without a
+// rotation ends the iteration (it is counted); none means not converged.
+__global__ void count_sweeps_kernel(const int* __restrict__ flags, int p, int max_sweeps,
+                                    int* __restrict__ sweeps_used) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= p) return;
+  int u = max_sweeps + 1;
+  for (int s = 0; s < max_sweeps; ++s) {
+    if (flags[l * max_sweeps + s] == 0) {
+      u = s + 1;
+      break;
+    }
+  }
+  sweeps_used[l] = u;
 }
 
 // W face l (nv x L, vector-major) <- transpose of Ah face l (n1 x n2 column
@@ -108,10 +300,11 @@ __global__ __launch_bounds__(256) void transpose_faces_kernel(const T* __restric
   }
 }
 
+// Norms of the converged vectors, descending order, top k normalised into F
+// (L x k x p); a zero vector stays zero.
 template <typename T>
 __global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, int nv, int L, int k,
-                                                       T* __restrict__ F, T* __restrict__ s_out,
-                                                       T* __restrict__ inv_s) {
+                                                       T* __restrict__ F) {
   extern __shared__ double sig[];  // nv doubles, then k ints
   int* order = reinterpret_cast<int*>(sig + nv);
   const int face = blockIdx.x;
@@ -123,7 +316,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, 
       const double x = Wf[(int64_t)j * L + e];
       acc = fma(x, x, acc);
     }
-    acc = wave_sum(acc);
+    acc = wave_total(acc);
     if (lane == 0) sig[j] = sqrt(acc);
   }
   __syncthreads();
@@ -138,13 +331,185 @@ __global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, 
     const int j = order[r];
     const double v = sig[j];
     const double inv = v > 0.0 ? 1.0 / v : 0.0;
-    if (lane == 0) {
-      s_out[(int64_t)face * k + r] = static_cast<T>(v);
-      inv_s[(int64_t)face * k + r] = static_cast<T>(inv);
-    }
     T* dst = F + ((int64_t)face * k + r) * L;
     for (int e = lane; e < L; e += 64) dst[e] = static_cast<T>(inv * (double)Wf[(int64_t)j * L + e]);
   }
+}
+
+// Jacobi on the k columns of Y (m1 x k, face-major) with every rotation also
+// applied to the k columns of F (m2 x k); then norms, descending order and
+// the outputs: s (k), Other = Y / s, Fo = F, Ys = Y, all in that order.
+template <typename T>
+__global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __restrict__ F, int m1,
+                                                     int m2, int k, double tol, int max_sweeps,
+                                                     T* __restrict__ s_out, T* __restrict__ Other,
+                                                     T* __restrict__ Fo, T* __restrict__ Ys) {
+  extern __shared__ double sig[];  // k doubles, then k ints
+  int* order = reinterpret_cast<int*>(sig + k);
+  __shared__ int any_rot;
+  const int face = blockIdx.x;
+  T* Yf = Y + (int64_t)face * m1 * k;
+  T* Ff = F + (int64_t)face * m2 * k;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kp = k + (k & 1);
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) any_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < kp - 1; ++r) {
+      for (int pi = wave; pi < kp / 2; pi += 4) {
+        int a, c;
+        circle_pair(kp, r, pi, a, c);
+        if (a >= k || c >= k) continue;
+        T* ya = Yf + (int64_t)a * m1;
+        T* yc = Yf + (int64_t)c * m1;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int e = lane; e < m1; e += 64) {
+          const double x = ya[e], y = yc[e];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+        const Rot q = rotation(wave_total(al), wave_total(be), wave_total(ga), tol);
+        if (q.on) {
+          for (int e = lane; e < m1; e += 64) {
+            const double x = ya[e], y = yc[e];
+            ya[e] = static_cast<T>(q.c * x - q.s * y);
+            yc[e] = static_cast<T>(q.s * x + q.c * y);
+          }
+          T* fa = Ff + (int64_t)a * m2;
+          T* fc = Ff + (int64_t)c * m2;
+          for (int e = lane; e < m2; e += 64) {
+            const double x = fa[e], y = fc[e];
+            fa[e] = static_cast<T>(q.c * x - q.s * y);
+            fc[e] = static_cast<T>(q.s * x + q.c * y);
+          }
+          if (lane == 0) any_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = any_rot;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int j = wave; j < k; j += 4) {
+    double acc = 0.0;
+    for (int e = lane; e < m1; e += 64) {
+      const double x = Yf[(int64_t)j * m1 + e];
+      acc = fma(x, x, acc);
+    }
+    acc = wave_total(acc);
+    if (lane == 0) sig[j] = sqrt(acc);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += 256) {
+    const double v = sig[j];
+    int r = 0;
+    for (int i = 0; i < k; ++i) r += (sig[i] > v) || (sig[i] == v && i < j);
+    order[r] = j;
+  }
+  __syncthreads();
+  for (int r = wave; r < k; r += 4) {
+    const int j = order[r];
+    const double v = sig[j];
+    const double inv = v > 0.0 ? 1.0 / v : 0.0;
+    if (lane == 0) s_out[(int64_t)face * k + r] = static_cast<T>(v);
+    const T* yj = Yf + (int64_t)j * m1;
+    T* o = Other + ((int64_t)face * k + r) * m1;
+    T* ys = Ys + ((int64_t)face * k + r) * m1;
+    for (int e = lane; e < m1; e += 64) {
+      const T x = yj[e];
+      ys[e] = x;
+      o[e] = static_cast<T>(inv * (double)x);
+    }
+    const T* fj = Ff + (int64_t)j * m2;
+    T* fo = Fo + ((int64_t)face * k + r) * m2;
+    for (int e = lane; e < m2; e += 64) fo[e] = fj[e];
+  }
+}
+
+__global__ void info_kernel(const int* __restrict__ used, int p, int max_sweeps, int* __restrict__ info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int mx = 0, bad = 0, total = 0;
+  for (int l = 0; l < p; ++l) {
+    const int u = used[l];
+    if (u > max_sweeps) ++bad;
+    mx = max(mx, min(u, max_sweeps));
+    total += min(u, max_sweeps);
+  }
+  info[0] = mx;
+  info[1] = bad;
+  info[2] = total;
+}
+
+constexpr size_t kLdsCap = 131072;
+
+template <typename T, int R>
+hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, double tol, int* used,
+                        int* flags, hipStream_t s) {
+  const int b = nw * kPairsPerWave;
+  int nb = (nv + b - 1) / b;
+  nb += nb & 1;
+  const size_t lds = sizeof(T) * (size_t)2 * b * 64 * R;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_block_kernel<T, R>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsCap);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const dim3 block((unsigned)(64 * nw));
+  if (nb == 2) {
+    jacobi_block_kernel<T, R><<<dim3(1, p), block, lds, s>>>(W, nv, L, nb, 0, 0, max_sweeps, tol, flags,
+                                                              used);
+    return hipGetLastError();
+  }
+  const int nflags = p * max_sweeps;
+  zero_ints_kernel<<<(nflags + 255) / 256, 256, 0, s>>>(flags, nflags);
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    for (int round = 0; round < nb - 1; ++round) {
+      jacobi_block_kernel<T, R><<<dim3(nb / 2, p), block, lds, s>>>(W, nv, L, nb, round, sw, max_sweeps,
+                                                                     tol, flags, used);
+    }
+  }
+  count_sweeps_kernel<<<(p + 63) / 64, 64, 0, s>>>(flags, p, max_sweeps, used);
+  return hipGetLastError();
+}
+
+// waves per workgroup (4 vectors of a block each): blocks of 16 vectors, fewer
+// for faces of fewer than 32 vectors, and the 2b staged vectors within the
+// LDS budget
+template <typename T>
+int pick_waves(int nv, int Lp) {
+  int nw = std::min(4, std::max(1, (nv + 7) / 8));
+  while (nw > 1 && sizeof(T) * (size_t)2 * kPairsPerWave * nw * Lp > kLdsCap) --nw;
+  return nw;
+}
+
+template <typename T>
+hipError_t sweeps(T* W, int p, int nv, int L, int max_sweeps, double tol, int* used, int* flags,
+                  hipStream_t s) {
+  const int R = (L + 63) / 64;
+  int Rk = 0;
+  for (int c : {1, 2, 3, 4, 5, 6, 8, 10, 12, 16})
+    if (!Rk && R <= c) Rk = c;
+  if (Rk > 0 && sizeof(T) * (size_t)2 * kPairsPerWave * 64 * Rk <= kLdsCap) {
+    const int nw = pick_waves<T>(nv, 64 * Rk);
+    switch (Rk) {
+      case 1: return block_sweeps<T, 1>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      case 2: return block_sweeps<T, 2>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      case 3: return block_sweeps<T, 3>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      case 4: return block_sweeps<T, 4>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      case 5: return block_sweeps<T, 5>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      case 6: return block_sweeps<T, 6>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      case 8: return block_sweeps<T, 8>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      case 10: return block_sweeps<T, 10>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      case 12: return block_sweeps<T, 12>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      default: return block_sweeps<T, 16>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+    }
+  }
+  jacobi_global_kernel<T><<<p, kJacobiThreads, 0, s>>>(W, nv, L, max_sweeps, tol, used);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -158,36 +523,18 @@ hipError_t prep(const T* Ah, T* W, int n1, int n2, int p, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t sweeps(T* W, int p, int nv, int L, int max_sweeps, double tol, int* used, hipStream_t s) {
-  jacobi_kernel<T><<<p, kJacobiThreads, 0, s>>>(W, nv, L, max_sweeps, tol, used);
+hipError_t finalize(const T* W, int p, int nv, int L, int k, T* F, hipStream_t s) {
+  const size_t lds = sizeof(double) * (size_t)nv + sizeof(int) * (size_t)k;
+  finalize_kernel<T><<<p, 256, lds, s>>>(W, nv, L, k, F);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t finalize(const T* W, int p, int nv, int L, int k, T* F, T* s_out, T* inv_s,
-                    hipStream_t s) {
-  const size_t lds = sizeof(double) * (size_t)nv + sizeof(int) * (size_t)k;
-  finalize_kernel<T><<<p, 256, lds, s>>>(W, nv, L, k, F, s_out, inv_s);
+hipError_t refine(T* Y, T* F, int m1, int m2, int k, int p, double tol, T* s_out, T* Other, T* Fo,
+                  T* Ys, hipStream_t s) {
+  const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)k;
+  refine_kernel<T><<<p, 256, lds, s>>>(Y, F, m1, m2, k, tol, 12, s_out, Other, Fo, Ys);
   return hipGetLastError();
-}
-
-__global__ void info_kernel(const int* __restrict__ used, int p, int max_sweeps, int* __restrict__ info) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int mx = 0, bad = 0;
-  for (int l = 0; l < p; ++l) {
-    const int u = used[l];
-    if (u > max_sweeps) {
-      ++bad;
-      mx = max(mx, max_sweeps);
-    } else {
-      mx = max(mx, u);
-    }
-  }
-  int total = 0;
-  for (int l = 0; l < p; ++l) total += min(used[l], max_sweeps);
-  info[0] = mx;
-  info[1] = bad;
-  info[2] = total;
 }
 
 }  // namespace
@@ -199,20 +546,26 @@ hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, h
   return prep<double>(Ah, W, n1, n2, p, s);
 }
 hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
-                             hipStream_t s) {
-  return sweeps<float>(W, p, nv, L, max_sweeps, tol, used, s);
+                             int* flags, hipStream_t s) {
+  return sweeps<float>(W, p, nv, L, max_sweeps, tol, used, flags, s);
 }
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
-                             hipStream_t s) {
-  return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, s);
+                             int* flags, hipStream_t s) {
+  return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
 }
-hipError_t jacobi_finalize_f32(const float* W, int p, int nv, int L, int k, float* F, float* s_out,
-                               float* inv_s, hipStream_t s) {
-  return finalize<float>(W, p, nv, L, k, F, s_out, inv_s, s);
+hipError_t jacobi_finalize_f32(const float* W, int p, int nv, int L, int k, float* F, hipStream_t s) {
+  return finalize<float>(W, p, nv, L, k, F, s);
 }
-hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k, double* F,
-                               double* s_out, double* inv_s, hipStream_t s) {
-  return finalize<double>(W, p, nv, L, k, F, s_out, inv_s, s);
+hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k, double* F, hipStream_t s) {
+  return finalize<double>(W, p, nv, L, k, F, s);
+}
+hipError_t jacobi_refine_f32(float* Y, float* F, int m1, int m2, int k, int p, double tol, float* s_out,
+                             float* Other, float* Fo, float* Ys, hipStream_t s) {
+  return refine<float>(Y, F, m1, m2, k, p, tol, s_out, Other, Fo, Ys, s);
+}
+hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, double tol,
+                             double* s_out, double* Other, double* Fo, double* Ys, hipStream_t s) {
+  return refine<double>(Y, F, m1, m2, k, p, tol, s_out, Other, Fo, Ys, s);
 }
 hipError_t jacobi_info(const int* used, int p, int max_sweeps, int* info, hipStream_t s) {
   info_kernel<<<1, 64, 0, s>>>(used, p, max_sweeps, info);

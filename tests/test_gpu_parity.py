@@ -135,6 +135,9 @@ def _check_tsvdq(pq, A_st, Q, k, tol_s=TOL32, tol_a=TOL32, a_dev=None):
     Al = synth.logical(A_st)
     Ad = dev(A_st) if a_dev is None else a_dev
     r = pq.tsvdq(Ad, devq(Q), k, spatial=True, approx=True)
+    info = r.info.cpu().numpy()
+    say(f"  jacobi info (max sweeps, unconverged, total) = {info.tolist()}")
+    assert info[1] == 0, f"unconverged faces: {info}"
     ref = oracle.tsvdq(Al, Q, k)
     s = host(r.s)
     p = Q.shape[1]
@@ -146,7 +149,11 @@ def _check_tsvdq(pq, A_st, Q, k, tol_s=TOL32, tol_a=TOL32, a_dev=None):
     for l in range(p):
         nz = s[:, l] > 0
         U = Uh[:, nz, l]
-        np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=2e-5)
+        V = Vh[:, nz, l]
+        # both factors orthonormal to working precision (Def. 3.4 in the
+        # transform domain: each face of Uhat and Vhat has orthonormal columns)
+        np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=2e-6)
+        np.testing.assert_allclose(V.T @ V, np.eye(V.shape[1]), atol=2e-6)
         # U^T Ah = diag(s) V^T on every face
         lhs = U.T @ Ah[:, :, l]
         rhs = s[nz, l][:, None] * Vh[:, nz, l].T
@@ -155,18 +162,29 @@ def _check_tsvdq(pq, A_st, Q, k, tol_s=TOL32, tol_a=TOL32, a_dev=None):
     ey, pe = oracle.tsvdq_error_terms(Al, Q, k, s_all=ref.s_all)
     err2 = oracle.fro2(Al - host(r.Ak))
     assert abs(err2 - (ey + pe)) <= 1e-4 * (ey + pe) + 1e-6 * oracle.fro2(Al)
-    info = r.info.cpu().numpy()
-    assert info[1] == 0, f"unconverged faces: {info}"
     return r, ref
 
 
 @pytest.mark.parametrize("shape", [(32, 24, 16, 4, 5), (24, 40, 20, 6, 3), (50, 50, 12, 3, 50),
-                                   (70, 9, 30, 5, 1), (9, 70, 30, 5, 9), (129, 65, 40, 7, 8)])
+                                   (70, 9, 30, 5, 1), (9, 70, 30, 5, 9), (129, 65, 40, 7, 8),
+                                   (1100, 8, 10, 3, 4), (1, 17, 6, 2, 1)])
 def test_tsvdq_f32(pq, shape):
     n1, n2, n3, p, k = shape
     say(f"tsvdq f32 {shape}")
     A, Q = _case(300 + n1, n1, n2, n3, p)
     _check_tsvdq(pq, A, Q, k)
+
+
+def test_tsvdq_f64_blocked(pq):
+    """float64 faces large enough to need several block pairs per sweep."""
+    say("tsvdq f64 blocked")
+    A, Q = _case(77, 70, 40, 12, 3, np.float64)
+    Al = synth.logical(A)
+    r = pq.tsvdq(dev(A), devq(Q), 5, approx=True)
+    ref = oracle.tsvdq(Al, Q, 5)
+    assert rel(host(r.s), ref.s) <= TOL64
+    assert rel(host(r.Ak), ref.Ak) <= 1e-11
+    assert r.info.cpu().numpy()[1] == 0
 
 
 def test_tsvdq_rank_deficient(pq):
