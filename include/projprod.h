@@ -41,6 +41,9 @@
  *                    the tensor operand is already bfloat16 the other operand
  *                    is split three ways instead, which is exact in float32
  *   PQ_PREC_BF16X6   three-way split of both operands, 6 passes
+ * The modes apply to the forward transform A x_3 Q^T (pq_hat and the
+ * transform steps of pq_qprod and pq_tsvdq).  The return transform, the fused
+ * projection and the facewise products run on float32 MFMA in every mode.
  */
 #ifndef PROJPROD_H
 #define PROJPROD_H
@@ -85,6 +88,24 @@ const char* pq_status_string(int code);
 
 /* The hipError_t of the last failed launch on the calling thread (0 if none). */
 int pq_last_hip_error(void);
+
+/* ---- launch-configuration autotuner --------------------------------------- */
+/*
+ * The library keeps a process-wide table from a launch shape (kernel family,
+ * precision mode and sizes) to the fastest of that kernel's candidate launch
+ * configurations (vectors per lane, waves per workgroup).  While
+ * pq_autotune_enable(1) is in force, a call whose launch shape is not yet in
+ * the table times every candidate on its stream (this synchronises the
+ * stream; the call's outputs are still written correctly) and records the
+ * fastest; otherwise the recorded choice, or a built-in default, is used
+ * without synchronising.  pq_autotune_save / pq_autotune_load write and read
+ * the table as text ("key choice" per line; host path).  pq_autotune_entries
+ * returns the number of recorded shapes.
+ */
+int pq_autotune_enable(int on);
+int pq_autotune_entries(void);
+int pq_autotune_save(const char* path);
+int pq_autotune_load(const char* path);
 
 /* ---- per-launch timing ---------------------------------------------------- */
 /*
@@ -202,7 +223,9 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
  * k per face, 1 <= k <= min(n1, n2).
  *   step 2: Ahat = A x_3 Q^T;
  *   step 3: every face Ahat_l ~ Uhat_l diag(s_l) Vhat_l^T, the exact rank-k
- *           truncation (one-sided Jacobi, rotation angles in float64);
+ *           truncation (one-sided Jacobi with float64 rotation angles: for
+ *           float32 data, float32 sweeps to a coarse threshold and then
+ *           float64 polishing sweeps);
  *   step 4 (optional outputs): Uk = Uhat x_3 Q, the diagonal tubes of
  *           S_k = Shat x_3 Q, Vk = Vhat x_3 Q, and the approximation
  *           A_k = (Uhat tri Shat tri Vhat^T) x_3 Q of Thm. 4.2.
@@ -213,11 +236,15 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
  *   Ak n1 x n2 x n3 — each optional (NULL).
  * Singular vectors of a face whose singular value is zero (rank-deficient
  * faces) are written as zero vectors.  tol is the Jacobi stopping threshold
- * on |a_i . a_j| / (|a_i| |a_j|) (<= 0 selects the default for the dtype),
- * max_sweeps caps the sweeps (<= 0: default 30).  info_dev (device int[3],
- * may be NULL) receives [0] = the largest number of sweeps any face used,
- * [1] = the number of faces that hit max_sweeps before converging (their
- * outputs are still written) and [2] = the sweeps summed over the faces.  Workspace: pq_tsvdq_workspace bytes.
+ * on |a_i . a_j| / (|a_i| |a_j|) of the final (float64) sweeps (<= 0 selects
+ * 1e-13; two singular vectors come out coupled by about tol / (2 x the
+ * relative gap of their singular values)),
+ * max_sweeps caps the sweeps of each phase (<= 0: 20 for float32 data,
+ * 30 for float64; at most 100).  info_dev (device int[3], may be NULL)
+ * receives [0] = the largest number of sweeps any face used (both phases),
+ * [1] = the number of faces whose last phase hit max_sweeps before
+ * converging (their outputs are still written) and [2] = the sweeps summed
+ * over the faces.  Workspace: pq_tsvdq_workspace bytes.
  */
 size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k,
                           int a_dtype);

@@ -18,6 +18,10 @@ SIGNATURES = {
     "pq_version": (_i32, []),
     "pq_status_string": (ctypes.c_char_p, [_i32]),
     "pq_last_hip_error": (_i32, []),
+    "pq_autotune_enable": (_i32, [_i32]),
+    "pq_autotune_entries": (_i32, []),
+    "pq_autotune_save": (_i32, [ctypes.c_char_p]),
+    "pq_autotune_load": (_i32, [ctypes.c_char_p]),
     "pq_profile_enable": (_i32, [_i32]),
     "pq_profile_reset": (_i32, []),
     "pq_profile_query": (_i32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),

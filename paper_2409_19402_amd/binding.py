@@ -18,7 +18,8 @@ from . import _lib
 from ._lib import PQ_F32, PQ_F64, PQ_BF16, PREC, call
 
 __all__ = [
-    "empty", "from_storage", "is_face_major", "check_q", "hat", "unhat", "proj", "facewise",
+    "empty", "from_storage", "is_face_major", "autotune", "autotune_save", "autotune_load",
+    "check_q", "hat", "unhat", "proj", "facewise",
     "qprod", "qprod_backward", "proj_backward", "tsvdq", "TSVDQ", "QProd", "Proj",
 ]
 
@@ -88,6 +89,21 @@ def _ws(nbytes, device):
 
 def _ptr(X):
     return None if X is None else X.data_ptr()
+
+
+def autotune(on=True):
+    """Switch the library's launch-configuration autotuner on or off: while on,
+    a call whose launch shape has no recorded choice times the candidate
+    configurations (synchronising the stream) and records the fastest."""
+    _lib.load().pq_autotune_enable(1 if on else 0)
+
+
+def autotune_save(path):
+    call("pq_autotune_save", str(path).encode())
+
+
+def autotune_load(path):
+    call("pq_autotune_load", str(path).encode())
 
 
 def check_q(Q):

@@ -2,6 +2,7 @@
 // the order of kernel launches for each call.  Every step of every call runs
 // in the kernels of this library; nothing here touches tensor data.
 #include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
@@ -110,7 +111,6 @@ int check_ar_dtype(int dt) { return (dt == PQ_F32 || dt == PQ_F64) ? PQ_OK : PQ_
 int check_prec(int prec, int dtype) {
   if (prec < PQ_PREC_DEFAULT || prec > PQ_PREC_BF16X6) return PQ_ERR_PREC;
   if (dtype == PQ_F64 && prec != PQ_PREC_DEFAULT) return PQ_ERR_PREC;
-  if (prec != PQ_PREC_DEFAULT) return PQ_ERR_PREC;  // matrix-core bfloat16 modes: see pq_version notes
   return PQ_OK;
 }
 
@@ -134,7 +134,13 @@ struct Arena {
   bool fits() const { return used <= cap; }
 };
 
-constexpr int kDefaultSweeps = 30;
+constexpr int kDefaultSweeps32 = 20;  // per phase; float32 faces need 6-12 coarse sweeps
+constexpr int kDefaultSweeps64 = 30;
+// Jacobi thresholds on |a.c| / (|a||c|): the float32 phase stops at the coarse
+// one, the float64 phase polishes to the default final one.
+constexpr double kCoarseTol32 = 1e-5;
+constexpr int kPolishSweeps = 8;  // float64 polishing from the coarse threshold: 2-4 sweeps
+constexpr double kPolishTol = 1e-13;
 constexpr int kMaxSweepsCap = 100;
 
 int ksplit_for(int64_t K) { return (int)std::clamp<int64_t>(K / 512, 1, 1024); }
@@ -224,6 +230,23 @@ const char* pq_status_string(int code) {
 }
 
 int pq_last_hip_error(void) { return g_last_hip; }
+
+int pq_autotune_enable(int on) {
+  pq::tune_enable(on != 0);
+  return PQ_OK;
+}
+
+int pq_autotune_entries(void) { return pq::tune_entries(); }
+
+int pq_autotune_save(const char* path) {
+  if (!path) return PQ_ERR_NULL;
+  return pq::tune_save(path) ? PQ_OK : PQ_ERR_ARG;
+}
+
+int pq_autotune_load(const char* path) {
+  if (!path) return PQ_ERR_NULL;
+  return pq::tune_load(path) ? PQ_OK : PQ_ERR_ARG;
+}
 
 int pq_profile_enable(int on) {
   std::lock_guard<std::mutex> g(g_prof_mu);
@@ -516,15 +539,18 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype, int
 
 size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k, int a_dtype) {
   (void)n3;
-  const size_t e = elem(a_dtype == PQ_F64 ? PQ_F64 : PQ_F32);
+  const bool f64 = a_dtype == PQ_F64;
+  const size_t e = elem(f64 ? PQ_F64 : PQ_F32);
   const int64_t mx = std::max(n1, n2), mn = std::min(n1, n2);
-  return align_up(e * n1 * n2 * p)                    // Ah
-         + align_up(e * n1 * n2 * p)                  // Jacobi working vectors
-         + align_up(sizeof(int) * p)                  // sweeps per face
-         + align_up(sizeof(int) * p * kMaxSweepsCap)  // per-sweep rotation flags
-         + align_up(e * mx * k * p)                   // top-k Jacobi vectors
-         + align_up(e * mn * k * p) * 2               // other side, before and after ordering
-         + align_up(e * n1 * n2 * p);                 // transform-domain A_k
+  return align_up(e * n1 * n2 * p)                        // Ah
+         + (f64 ? 0 : align_up(4 * n1 * n2 * p))          // float32 Jacobi vectors
+         + align_up(8 * n1 * n2 * p)                      // float64 Jacobi vectors
+         + align_up(sizeof(int) * p) * 2                  // sweeps per face, both phases
+         + align_up(sizeof(int) * p * kMaxSweepsCap)      // per-sweep rotation flags
+         + align_up(8 * mx * k * p)                       // top-k Jacobi vectors
+         + align_up(8 * mn * k * p)                       // other side (float64)
+         + align_up(e * mn * k * p)                       // other side, ordered, unscaled
+         + align_up(e * n1 * n2 * p);                     // transform-domain A_k
 }
 
 int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p,
@@ -544,21 +570,23 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   if (std::min(n1, n2) > 4096) return PQ_ERR_UNSUPPORTED;
   if (p > 512 && a_dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
   if (!ws || ws_bytes < pq_tsvdq_workspace(n1, n2, n3, p, k, a_dtype)) return PQ_ERR_WORKSPACE;
-  if (max_sweeps <= 0) max_sweeps = kDefaultSweeps;
-  if (max_sweeps > kMaxSweepsCap) return PQ_ERR_ARG;
   const bool f64 = a_dtype == PQ_F64;
+  if (max_sweeps <= 0) max_sweeps = f64 ? kDefaultSweeps64 : kDefaultSweeps32;
+  if (max_sweeps > kMaxSweepsCap) return PQ_ERR_ARG;
+  if (tol <= 0.0) tol = kPolishTol;
   const int dt = f64 ? PQ_F64 : PQ_F32;
-  if (tol <= 0.0) tol = f64 ? 1e-14 : 2e-7;
   const size_t e = elem(dt);
   const int64_t N = n1 * n2;
   const int64_t mx = std::max(n1, n2), mn = std::min(n1, n2);
   Arena ar(ws, ws_bytes);
   void* Ah = ar.take(e * N * p);
-  void* W = ar.take(e * N * p);
-  int* used = static_cast<int*>(ar.take(sizeof(int) * p));
+  float* W32 = f64 ? nullptr : static_cast<float*>(ar.take(4 * N * p));
+  double* W64 = static_cast<double*>(ar.take(8 * N * p));
+  int* used1 = static_cast<int*>(ar.take(sizeof(int) * p));
+  int* used2 = static_cast<int*>(ar.take(sizeof(int) * p));
   int* flags = static_cast<int*>(ar.take(sizeof(int) * p * kMaxSweepsCap));
-  void* Ft = ar.take(e * mx * k * p);
-  void* Y = ar.take(e * mn * k * p);
+  double* Ft = static_cast<double*>(ar.take(8 * mx * k * p));
+  double* Y = static_cast<double*>(ar.take(8 * mn * k * p));
   void* Ys = ar.take(e * mn * k * p);
   void* Akh = ar.take(e * N * p);
   const Prec pr = (Prec)prec;
@@ -571,39 +599,49 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   const int nv = (int)mn, L = (int)mx;
   void* Fo = cols ? Uhat : Vhat;     // side given by the Jacobi vectors
   void* Other = cols ? Vhat : Uhat;  // side given by one more product
-  {
+  if (f64) {
     PQ_PROF("jacobi_prep", stream);
-    if (f64) PQ_TRY(pq::jacobi_prep_f64(static_cast<const double*>(Ah), static_cast<double*>(W), in1, in2, ip, stream));
-    else PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(Ah), static_cast<float*>(W), in1, in2, ip, stream));
+    PQ_TRY(pq::jacobi_prep_f64(static_cast<const double*>(Ah), W64, in1, in2, ip, stream));
+  } else {
+    {
+      PQ_PROF("jacobi_prep", stream);
+      PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(Ah), W32, in1, in2, ip, stream));
+    }
+    {  // float32 sweeps down to a coarse threshold
+      PQ_PROF("jacobi_sweeps", stream);
+      PQ_TRY(pq::jacobi_sweeps_f32(W32, ip, nv, L, max_sweeps, kCoarseTol32, used1, flags, stream));
+    }
+    PQ_PROF("jacobi_widen", stream);
+    PQ_TRY(pq::jacobi_widen(W32, W64, N * p, stream));
   }
-  {
-    PQ_PROF("jacobi_sweeps", stream);
-    if (f64) PQ_TRY(pq::jacobi_sweeps_f64(static_cast<double*>(W), ip, nv, L, max_sweeps, tol, used, flags, stream));
-    else PQ_TRY(pq::jacobi_sweeps_f32(static_cast<float*>(W), ip, nv, L, max_sweeps, tol, used, flags, stream));
+  {  // float64 sweeps to tol
+    PQ_PROF("jacobi_polish", stream);
+    PQ_TRY(pq::jacobi_sweeps_f64(W64, ip, nv, L, f64 ? max_sweeps : std::min(max_sweeps, kPolishSweeps),
+                                 tol, f64 ? used1 : used2, flags, stream));
   }
   {
     PQ_PROF("jacobi_finalize", stream);
-    if (f64) PQ_TRY(pq::jacobi_finalize_f64(static_cast<const double*>(W), ip, nv, L, ik, static_cast<double*>(Ft), stream));
-    else PQ_TRY(pq::jacobi_finalize_f32(static_cast<const float*>(W), ip, nv, L, ik, static_cast<float*>(Ft), stream));
+    PQ_TRY(pq::jacobi_finalize_f64(W64, ip, nv, L, ik, Ft, stream));
   }
-  // Y = Ah_l^T Ft_l (n2 x k) or Ah_l Ft_l (n1 x k), unscaled
-  {
-    Gemm g = cols ? face_gemm(true, false, in2, ik, in1, Ah, n1, N, Ft, n1, n1 * k, Y, n2, n2 * k, ip)
-                  : face_gemm(false, false, in1, ik, in2, Ah, n1, N, Ft, n2, n2 * k, Y, n1, n1 * k, ip);
-    PQ_TRY(do_gemm("factor_gemm", g, dt, pr, stream));
+  {  // Y = Ah_l^T Ft_l (n2 x k) or Ah_l Ft_l (n1 x k), float64 accumulation
+    PQ_PROF("factor_product", stream);
+    if (f64) PQ_TRY(pq::jacobi_factor_f64(static_cast<const double*>(Ah), Ft, Y, in1, in2, ik, ip, cols, stream));
+    else PQ_TRY(pq::jacobi_factor_f32(static_cast<const float*>(Ah), Ft, Y, in1, in2, ik, ip, cols, stream));
   }
   {
     PQ_PROF("jacobi_refine", stream);
     if (f64)
-      PQ_TRY(pq::jacobi_refine_f64(static_cast<double*>(Y), static_cast<double*>(Ft), nv, L, ik, ip, tol,
-                                   static_cast<double*>(s), static_cast<double*>(Other),
-                                   static_cast<double*>(Fo), static_cast<double*>(Ys), stream));
+      PQ_TRY(pq::jacobi_refine_f64(Y, Ft, nv, L, ik, ip, tol, static_cast<double*>(s),
+                                   static_cast<double*>(Other), static_cast<double*>(Fo),
+                                   static_cast<double*>(Ys), stream));
     else
-      PQ_TRY(pq::jacobi_refine_f32(static_cast<float*>(Y), static_cast<float*>(Ft), nv, L, ik, ip, tol,
-                                   static_cast<float*>(s), static_cast<float*>(Other),
-                                   static_cast<float*>(Fo), static_cast<float*>(Ys), stream));
+      PQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, tol, static_cast<float*>(s),
+                                   static_cast<float*>(Other), static_cast<float*>(Fo),
+                                   static_cast<float*>(Ys), stream));
   }
-  if (info_dev) PQ_TRY(pq::jacobi_info(used, ip, max_sweeps, info_dev, stream));
+  if (info_dev)
+    PQ_TRY(pq::jacobi_info(used1, f64 ? nullptr : used2, ip, max_sweeps,
+                           f64 ? max_sweeps : std::min(max_sweeps, kPolishSweeps), info_dev, stream));
   // step 4 and the approximation of Thm. 4.2
   if (Ak) {
     // Akh_l = Uhat_l Ys_l^T (cols) or Ys_l Vhat_l^T (rows): both Uhat S Vhat^T

@@ -7,9 +7,24 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
+#include <string>
+
 namespace pq {
 
 enum class Prec : int { Default = 0, BF16 = 1, BF16x3 = 2, BF16x6 = 3 };
+
+// ---- launch-configuration autotuner (tune.cpp) ------------------------------
+// launch(c) enqueues candidate configuration c (0 <= c < ncand) on s.  The
+// recorded choice for key is used; with none recorded and tuning switched on
+// every candidate is timed (synchronising s) and the fastest recorded;
+// otherwise candidate dflt is used.
+hipError_t tuned_launch(const std::string& key, int ncand, int dflt, hipStream_t s,
+                        const std::function<hipError_t(int)>& launch);
+void tune_enable(bool on);
+int tune_entries();
+bool tune_save(const char* path);
+bool tune_load(const char* path);
 
 // ---- mode-3 transforms (transform.hip) -----------------------------------
 // Ah (p x N) = Q^T (p x n3) * A (n3 x N); A is float32 or bfloat16 bits.
@@ -67,17 +82,26 @@ hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, dou
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol,
                              int* sweeps_used, int* flags, hipStream_t s);
 // Column norms, descending order, top k normalised vectors F (L x k x p).
-hipError_t jacobi_finalize_f32(const float* W, int p, int nv, int L, int k, float* F, hipStream_t s);
 hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k, double* F, hipStream_t s);
-// Jacobi on the k columns of Y (m1 x k x p), each rotation applied to F
-// (m2 x k x p) too; writes s (k x p, descending), Other = Y / s, Fo = F and
-// Ys = Y, all in descending order of s.
-hipError_t jacobi_refine_f32(float* Y, float* F, int m1, int m2, int k, int p, double tol,
+// float64 Jacobi on the k columns of Y (m1 x k x p), each rotation applied
+// to F (m2 x k x p) too; writes s (k x p, descending), Other = Y / s, Fo = F
+// and Ys = Y, all in descending order of s, in the output type.
+hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int p, double tol,
                              float* s_out, float* Other, float* Fo, float* Ys, hipStream_t s);
 hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, double tol,
                              double* s_out, double* Other, double* Fo, double* Ys, hipStream_t s);
-// info[0] = max_l min(sweeps_used[l], max_sweeps); info[1] = #faces that did
-// not converge; info[2] = sum_l min(sweeps_used[l], max_sweeps).
-hipError_t jacobi_info(const int* sweeps_used, int p, int max_sweeps, int* info, hipStream_t s);
+// y[i] = x[i] for i < n (float32 -> float64)
+hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s);
+// Y = Ah_l^T F_l (cols: Y n2 x k, F n1 x k) or Ah_l F_l (rows: Y n1 x k,
+// F n2 x k) per face, float64 accumulation and result
+hipError_t jacobi_factor_f32(const float* Ah, const double* F, double* Y, int n1, int n2, int k, int p,
+                             bool cols, hipStream_t s);
+hipError_t jacobi_factor_f64(const double* Ah, const double* F, double* Y, int n1, int n2, int k, int p,
+                             bool cols, hipStream_t s);
+// info[0] = the most sweeps a face used over both phases (used2 may be
+// NULL; max1 and max2 are the phases' caps), info[1] = #faces whose last
+// phase did not converge, info[2] = the sweeps summed over the faces.
+hipError_t jacobi_info(const int* used1, const int* used2, int p, int max1, int max2, int* info,
+                       hipStream_t s);
 
 }  // namespace pq

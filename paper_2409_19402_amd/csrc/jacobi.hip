@@ -23,10 +23,19 @@
 // over sweeps by itself.  Vectors longer than 1024 fall back to a form with
 // one workgroup per face and the pairs read from global memory.
 //
+// Precision: float32 faces are first swept with float32 storage down to a
+// coarse threshold, then the vectors are promoted to float64 and polished by
+// float64 sweeps (quadratic convergence: a few sweeps).  The residual coupling
+// of two singular vectors at convergence is about tol / (2 x relative gap of
+// their singular values); float32 storage cannot push tol much below 1e-7,
+// which on the nearly flat spectra of noise faces (relative gaps of 1e-3)
+// would leave the rank-k truncation visibly mixed.
+//
 // The factor on the other side is Y = Ahat F (or Ahat^T F) for the top-k
-// Jacobi vectors F.  A last small Jacobi on the k columns of Y, applying each
-// rotation to F as well, makes both factors orthonormal to working precision
-// without changing Y F^T; its column norms are the singular values.
+// Jacobi vectors F, formed with float64 accumulation.  A last small float64
+// Jacobi on the k columns of Y, applying each rotation to F as well, makes
+// both factors orthonormal to working precision without changing Y F^T; its
+// column norms are the singular values.
 #include <algorithm>
 
 #include "common.hpp"
@@ -38,13 +47,16 @@ namespace {
 constexpr int kJacobiThreads = 1024;
 
 // circle-method round robin over n (even) players: pair `pi` of round `r`
+// (0 <= r < n - 1, 0 <= pi < n / 2)
 __device__ __forceinline__ void circle_pair(int n, int r, int pi, int& a, int& c) {
   if (pi == 0) {
     a = n - 1;
     c = r;
   } else {
-    a = (r + pi) % (n - 1);
-    c = (r - pi + n - 1) % (n - 1);
+    a = r + pi;
+    if (a >= n - 1) a -= n - 1;
+    c = r - pi;
+    if (c < 0) c += n - 1;
   }
 }
 
@@ -96,6 +108,9 @@ __device__ __forceinline__ bool rotate_row_pair(T (&xa)[4 * R], T (&xc)[4 * R], 
   if (!(ga * ga > tol * tol * al * be)) return false;
   const double zeta = (be - al) / (2.0 * ga);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  // the rotation is applied in float64 and rounded once: an exactly
+  // orthogonal update, so the residual |gamma| left behind is at the rounding
+  // floor of the storage type even for pairs of very different norms
   const double cs = 1.0 / sqrt(1.0 + t * t);
   const double sn = cs * t;
 #pragma unroll
@@ -175,8 +190,7 @@ __global__ __launch_bounds__(256) void jacobi_block_kernel(T* __restrict__ W, in
     } else {
       T xi[4 * R];
       row_load<T, R>(V + pi * Lp, gl, xi);
-      for (int r = 0; r < b; ++r) {
-        const int ic = b + (pi + r) % b;
+      for (int r = 0, ic = b + pi; r < b; ++r, ic = (ic + 1 == 2 * b) ? b : ic + 1) {
         T xc[4 * R];
         row_load<T, R>(V + ic * Lp, gl, xc);
         if (rotate_row_pair<T, R>(xi, xc, tol)) {
@@ -338,12 +352,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, 
 
 // Jacobi on the k columns of Y (m1 x k, face-major) with every rotation also
 // applied to the k columns of F (m2 x k); then norms, descending order and
-// the outputs: s (k), Other = Y / s, Fo = F, Ys = Y, all in that order.
-template <typename T>
+// the outputs (type TO): s (k), Other = Y / s, Fo = F, Ys = Y, in that order.
+template <typename T, typename TO>
 __global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __restrict__ F, int m1,
                                                      int m2, int k, double tol, int max_sweeps,
-                                                     T* __restrict__ s_out, T* __restrict__ Other,
-                                                     T* __restrict__ Fo, T* __restrict__ Ys) {
+                                                     TO* __restrict__ s_out, TO* __restrict__ Other,
+                                                     TO* __restrict__ Fo, TO* __restrict__ Ys) {
   extern __shared__ double sig[];  // k doubles, then k ints
   int* order = reinterpret_cast<int*>(sig + k);
   __shared__ int any_rot;
@@ -413,29 +427,114 @@ __global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __res
     const int j = order[r];
     const double v = sig[j];
     const double inv = v > 0.0 ? 1.0 / v : 0.0;
-    if (lane == 0) s_out[(int64_t)face * k + r] = static_cast<T>(v);
+    if (lane == 0) s_out[(int64_t)face * k + r] = static_cast<TO>(v);
     const T* yj = Yf + (int64_t)j * m1;
-    T* o = Other + ((int64_t)face * k + r) * m1;
-    T* ys = Ys + ((int64_t)face * k + r) * m1;
+    TO* o = Other + ((int64_t)face * k + r) * m1;
+    TO* ys = Ys + ((int64_t)face * k + r) * m1;
     for (int e = lane; e < m1; e += 64) {
-      const T x = yj[e];
-      ys[e] = x;
-      o[e] = static_cast<T>(inv * (double)x);
+      const double x = (double)yj[e];
+      ys[e] = static_cast<TO>(x);
+      o[e] = static_cast<TO>(inv * x);
     }
     const T* fj = Ff + (int64_t)j * m2;
-    T* fo = Fo + ((int64_t)face * k + r) * m2;
-    for (int e = lane; e < m2; e += 64) fo[e] = fj[e];
+    TO* fo = Fo + ((int64_t)face * k + r) * m2;
+    for (int e = lane; e < m2; e += 64) fo[e] = static_cast<TO>(fj[e]);
   }
 }
 
-__global__ void info_kernel(const int* __restrict__ used, int p, int max_sweeps, int* __restrict__ info) {
+// float32 -> float64 copy of the Jacobi vectors (the float64 polishing sweeps)
+__global__ __launch_bounds__(256) void widen_kernel(const float* __restrict__ x, double* __restrict__ y,
+                                                    int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+
+// Y(:, c) = Ah_l^T F(:, c) (Ah face n1 x n2, F n1 x k, Y n2 x k) with float64
+// accumulation: one wave per column j2 of the face, lanes over i.
+template <typename TA>
+__global__ __launch_bounds__(256) void factor_t_kernel(const TA* __restrict__ Ah, const double* __restrict__ F,
+                                                       double* __restrict__ Y, int n1, int n2, int k) {
+  const int face = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int j2 = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j2 >= n2) return;
+  const TA* a = Ah + (int64_t)face * n1 * n2 + (int64_t)j2 * n1;
+  const double* f = F + (int64_t)face * n1 * k;
+  double* y = Y + (int64_t)face * n2 * k;
+  for (int c0 = 0; c0 < k; c0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int i = lane; i < n1; i += 64) {
+      const double x = (double)a[i];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c0 + c < k) acc[c] = fma(x, f[(int64_t)(c0 + c) * n1 + i], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double t = wave_total(acc[c]);
+      if (lane == 0 && c0 + c < k) y[(int64_t)(c0 + c) * n2 + j2] = t;
+    }
+  }
+}
+
+// Y(:, c) = Ah_l F(:, c) (Ah face n1 x n2, F n2 x k, Y n1 x k) with float64
+// accumulation: one thread per row i, columns of the face read coalesced,
+// F staged in LDS 64 rows at a time and read as broadcasts.
+template <typename TA>
+__global__ __launch_bounds__(256) void factor_n_kernel(const TA* __restrict__ Ah, const double* __restrict__ F,
+                                                       double* __restrict__ Y, int n1, int n2, int k) {
+  constexpr int JC = 64;
+  __shared__ double Fs[JC][16];
+  const int face = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int c0 = blockIdx.z * 16;
+  const int kc = min(16, k - c0);
+  const TA* a = Ah + (int64_t)face * n1 * n2;
+  const double* f = F + (int64_t)face * n2 * k;
+  double acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+  for (int j0 = 0; j0 < n2; j0 += JC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < JC * 16; e += 256) {
+      const int jj = e >> 4, c = e & 15;
+      Fs[jj][c] = (j0 + jj < n2 && c < kc) ? f[(int64_t)(c0 + c) * n2 + j0 + jj] : 0.0;
+    }
+    __syncthreads();
+    if (i < n1) {
+      const int jn = min(JC, n2 - j0);
+      for (int jj = 0; jj < jn; ++jj) {
+        const double x = (double)a[i + (int64_t)(j0 + jj) * n1];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] = fma(x, Fs[jj][c], acc[c]);
+      }
+    }
+  }
+  if (i >= n1) return;
+  double* y = Y + (int64_t)face * n1 * k;
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+    if (c < kc) y[(int64_t)(c0 + c) * n1 + i] = acc[c];
+}
+
+__global__ void info_kernel(const int* __restrict__ used1, const int* __restrict__ used2, int p,
+                            int max1, int max2, int* __restrict__ info) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int mx = 0, bad = 0, total = 0;
   for (int l = 0; l < p; ++l) {
-    const int u = used[l];
-    if (u > max_sweeps) ++bad;
-    mx = max(mx, min(u, max_sweeps));
-    total += min(u, max_sweeps);
+    const int u1 = used1[l];
+    int n = min(u1, max1);
+    bool conv = u1 <= max1;
+    if (used2) {
+      const int u2 = used2[l];
+      n += min(u2, max2);
+      conv = u2 <= max2;
+    }
+    if (!conv) ++bad;
+    mx = max(mx, n);
+    total += n;
   }
   info[0] = mx;
   info[1] = bad;
@@ -529,11 +628,23 @@ hipError_t finalize(const T* W, int p, int nv, int L, int k, T* F, hipStream_t s
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t refine(T* Y, T* F, int m1, int m2, int k, int p, double tol, T* s_out, T* Other, T* Fo,
-                  T* Ys, hipStream_t s) {
+template <typename TO>
+hipError_t refine(double* Y, double* F, int m1, int m2, int k, int p, double tol, TO* s_out, TO* Other,
+                  TO* Fo, TO* Ys, hipStream_t s) {
   const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)k;
-  refine_kernel<T><<<p, 256, lds, s>>>(Y, F, m1, m2, k, tol, 12, s_out, Other, Fo, Ys);
+  refine_kernel<double, TO><<<p, 256, lds, s>>>(Y, F, m1, m2, k, tol, 12, s_out, Other, Fo, Ys);
+  return hipGetLastError();
+}
+
+template <typename TA>
+hipError_t factor(const TA* Ah, const double* F, double* Y, int n1, int n2, int k, int p, bool cols,
+                  hipStream_t s) {
+  if (cols) {
+    factor_t_kernel<TA><<<dim3((unsigned)((n2 + 3) / 4), (unsigned)p), 256, 0, s>>>(Ah, F, Y, n1, n2, k);
+  } else {
+    factor_n_kernel<TA><<<dim3((unsigned)((n1 + 255) / 256), (unsigned)p, (unsigned)((k + 15) / 16)), 256,
+                          0, s>>>(Ah, F, Y, n1, n2, k);
+  }
   return hipGetLastError();
 }
 
@@ -553,22 +664,32 @@ hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, do
                              int* flags, hipStream_t s) {
   return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
 }
-hipError_t jacobi_finalize_f32(const float* W, int p, int nv, int L, int k, float* F, hipStream_t s) {
-  return finalize<float>(W, p, nv, L, k, F, s);
-}
 hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k, double* F, hipStream_t s) {
   return finalize<double>(W, p, nv, L, k, F, s);
 }
-hipError_t jacobi_refine_f32(float* Y, float* F, int m1, int m2, int k, int p, double tol, float* s_out,
-                             float* Other, float* Fo, float* Ys, hipStream_t s) {
+hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int p, double tol,
+                             float* s_out, float* Other, float* Fo, float* Ys, hipStream_t s) {
   return refine<float>(Y, F, m1, m2, k, p, tol, s_out, Other, Fo, Ys, s);
 }
 hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, double tol,
                              double* s_out, double* Other, double* Fo, double* Ys, hipStream_t s) {
   return refine<double>(Y, F, m1, m2, k, p, tol, s_out, Other, Fo, Ys, s);
 }
-hipError_t jacobi_info(const int* used, int p, int max_sweeps, int* info, hipStream_t s) {
-  info_kernel<<<1, 64, 0, s>>>(used, p, max_sweeps, info);
+hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s) {
+  widen_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
+  return hipGetLastError();
+}
+hipError_t jacobi_factor_f32(const float* Ah, const double* F, double* Y, int n1, int n2, int k, int p,
+                             bool cols, hipStream_t s) {
+  return factor<float>(Ah, F, Y, n1, n2, k, p, cols, s);
+}
+hipError_t jacobi_factor_f64(const double* Ah, const double* F, double* Y, int n1, int n2, int k, int p,
+                             bool cols, hipStream_t s) {
+  return factor<double>(Ah, F, Y, n1, n2, k, p, cols, s);
+}
+hipError_t jacobi_info(const int* used1, const int* used2, int p, int max1, int max2, int* info,
+                       hipStream_t s) {
+  info_kernel<<<1, 64, 0, s>>>(used1, used2, p, max1, max2, info);
   return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@
 // accumulators as VEC-wide contiguous stores too.
 #include <algorithm>
 #include <initializer_list>
+#include <string>
+#include <vector>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -18,86 +20,164 @@
 namespace pq {
 namespace {
 
-constexpr int kKC = 128;  // rows of Q staged in LDS per chunk (hat)
 
-// acc[q] += Q(rows kc.., lc + m)^T * A(rows kc.., strip) over `rows` rows;
-// Qs is the LDS copy of those rows of the 32-column chunk, leading dim ldq.
-template <int VEC, typename TIn>
-__device__ __forceinline__ void hat_accumulate(const TIn* __restrict__ Ap, int64_t N, bool active,
-                                               int rows, int rows_valid, const float* Qs, int ldq,
-                                               int n, int kh, f32x16 (&acc)[VEC]) {
-  int r = 0;
-  for (; r + 16 <= rows_valid; r += 16) {
-    float b[8][VEC];
+// ---- float32 matrix-core transform -------------------------------------------
+// Persistent strips with split-K inside the workgroup: a workgroup stages the
+// rows of Q it needs in LDS once and then walks over several strips of tubes
+// (strip = blockIdx.x + i * gridDim.x).  Its S waves share the current strip
+// and take its 16-row blocks of the frontal-slice index in turn (block b goes
+// to wave b mod S), so S x 16 rows of the strip are in flight even when the
+// tensor has few tubes; a wave issues the loads of its next block before the
+// MFMAs of its current one.  The S partial accumulators are summed through
+// LDS.  Q rows are staged in chunks of at most kKC rows, zero-filled past n3
+// and past p; with n3 > kKC the chunks are restaged for every strip.
+constexpr int kKC = 256;
+
+// Q(kc + r, lc + c) for r < kcr, c < 32 into Qs[r * ldq + c] (zero past n3 and
+// past p), `nthr` threads, 8 loads in flight per thread before the LDS writes.
+__device__ __forceinline__ void stage_q_rows(const float* __restrict__ Q, int p, int n3, int kc, int kcr,
+                                             int lc, float* Qs, int ldq, int nthr) {
+  const int total = kcr * 32;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 8 * nthr) {
+    float v[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      if (active) {
-        load_vec<VEC>(Ap + (int64_t)(r + 2 * s + kh) * N, b[s]);
-      } else {
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) b[s][q] = 0.f;
-      }
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(e0 + u * nthr, total - 1);
+      const int t = kc + (e >> 5), c = lc + (e & 31);
+      v[u] = Q[(int64_t)min(t, n3 - 1) * p + min(c, p - 1)];
+      v[u] = (t < n3 && c < p) ? v[u] : 0.f;
     }
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const float a = Qs[(r + 2 * s + kh) * ldq + n];
-#pragma unroll
-      for (int q = 0; q < VEC; ++q)
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b[s][q], acc[q], 0, 0, 0);
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < total) Qs[(e >> 5) * ldq + (e & 31)] = v[u];
     }
   }
-  for (; r < rows_valid; r += 2) {
-    const int t = r + kh;
-    float b[VEC];
-    if (active && t < rows_valid) {
-      load_vec<VEC>(Ap + (int64_t)t * N, b);
-    } else {
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) b[q] = 0.f;
-    }
-    const float a = Qs[t * ldq + n];  // row rows_valid of Qs is zero-filled
-#pragma unroll
-    for (int q = 0; q < VEC; ++q)
-      acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b[q], acc[q], 0, 0, 0);
-  }
-  (void)rows;
 }
 
-template <int VEC, int WAVES, typename TIn>
-__global__ __launch_bounds__(WAVES * 64) void hat_f32_kernel(const TIn* __restrict__ A,
-                                                             const float* __restrict__ Q,
-                                                             float* __restrict__ Ah, int64_t N,
-                                                             int n3, int p) {
-  __shared__ float Qs[(kKC + 2) * 32];
+// Loads are unconditional, from a clamped in-bounds address, and values that
+// lie outside the tensor are zeroed afterwards by a select: with no branch
+// around them the compiler can keep a whole block of loads in flight.  Ap
+// must point at a valid tube of row 0 for inactive lanes too.
+template <int VEC, typename TIn>
+__device__ __forceinline__ void load_block16(const TIn* __restrict__ Ap, int64_t N, bool active,
+                                             int t0, int tmax, int kh, float (&b)[8][VEC]) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int t = t0 + 2 * s + kh;
+    const bool ok = active && t < tmax;
+    load_vec<VEC>(Ap + (int64_t)min(t, tmax - 1) * N, b[s]);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) b[s][q] = ok ? b[s][q] : 0.f;
+  }
+}
+
+template <int VEC>
+__device__ __forceinline__ void mfma_block16(const float* Qs, int ldq, int r, int n, int kh,
+                                             const float (&b)[8][VEC], f32x16 (&acc)[VEC]) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const float a = Qs[(r + 2 * s + kh) * ldq + n];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q)
+      acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b[s][q], acc[q], 0, 0, 0);
+  }
+}
+
+// acc += Q(rows, chunk)^T A(rows, strip) over this wave's 16-row blocks of
+// `rows` rows; Ap points at the first row, Qs at the staged rows (zero-filled
+// to a multiple of 16).
+template <int VEC, int S, typename TIn>
+__device__ __forceinline__ void hat_accumulate(const TIn* __restrict__ Ap, int64_t N, bool active,
+                                               int rows, const float* Qs, int ldq, int wave, int n,
+                                               int kh, f32x16 (&acc)[VEC]) {
+  const int nblk = (rows + 15) / 16;
+  float b0[8][VEC], b1[8][VEC];
+  int blk = wave;
+  if (blk < nblk) load_block16<VEC, TIn>(Ap, N, active, 16 * blk, rows, kh, b0);
+  for (; blk < nblk; blk += 2 * S) {
+    if (blk + S < nblk) load_block16<VEC, TIn>(Ap, N, active, 16 * (blk + S), rows, kh, b1);
+    mfma_block16<VEC>(Qs, ldq, 16 * blk, n, kh, b0, acc);
+    if (blk + S >= nblk) break;
+    if (blk + 2 * S < nblk) load_block16<VEC, TIn>(Ap, N, active, 16 * (blk + 2 * S), rows, kh, b0);
+    mfma_block16<VEC>(Qs, ldq, 16 * (blk + S), n, kh, b1, acc);
+  }
+}
+
+// Sum the S waves' accumulators into wave 0 through LDS (red holds
+// (S - 1) * VEC * 16 * 64 floats).  Every wave of the workgroup must call it.
+// Returns true in the wave that holds the sum.
+template <int VEC, int S>
+__device__ __forceinline__ bool reduce_waves(f32x16 (&acc)[VEC], float* red, int wave, int lane) {
+  if constexpr (S == 1) {
+    return true;
+  } else {
+    if (wave > 0) {
+#pragma unroll
+      for (int q = 0; q < VEC; ++q)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) red[(((wave - 1) * VEC + q) * 16 + j) * 64 + lane] = acc[q][j];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int w = 1; w < S; ++w)
+#pragma unroll
+        for (int q = 0; q < VEC; ++q)
+#pragma unroll
+          for (int j = 0; j < 16; ++j) acc[q][j] += red[(((w - 1) * VEC + q) * 16 + j) * 64 + lane];
+    }
+    __syncthreads();
+    return wave == 0;
+  }
+}
+
+template <int VEC, int S, typename TIn>
+__global__ __launch_bounds__(S * 64) void hat_f32_kernel(const TIn* __restrict__ A,
+                                                         const float* __restrict__ Q,
+                                                         float* __restrict__ Ah, int64_t N, int n3,
+                                                         int p, int kcr, int64_t nstrips) {
+  extern __shared__ float smem[];
+  float* Qs = smem;              // kcr x 32
+  float* red = smem + kcr * 32;  // (S - 1) * VEC * 16 * 64
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 31, kh = lane >> 5;
   const int lc = blockIdx.y * 32;
-  const int64_t xl = ((int64_t)blockIdx.x * WAVES + wave) * (32 * VEC) + (int64_t)VEC * n;
-  const bool active = xl < N;
-  f32x16 acc[VEC];
-#pragma unroll
-  for (int q = 0; q < VEC; ++q)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) acc[q][j] = 0.f;
-  for (int kc = 0; kc < n3; kc += kKC) {
-    const int rows = min(kKC, n3 - kc);
+  const bool one_chunk = n3 <= kcr;
+  auto stage = [&](int kc) { stage_q_rows(Q, p, n3, kc, kcr, lc, Qs, 32, S * 64); };
+  if (one_chunk) {
+    stage(0);
     __syncthreads();
-    for (int e = threadIdx.x; e < (kKC + 2) * 32; e += WAVES * 64) {
-      const int r = e >> 5, c = e & 31;
-      Qs[e] = (r < rows && lc + c < p) ? Q[(int64_t)(kc + r) * p + lc + c] : 0.f;
-    }
-    __syncthreads();
-    hat_accumulate<VEC, TIn>(A + (int64_t)kc * N + xl, N, active, rows, rows, Qs, 32, n, kh, acc);
   }
-  if (!active) return;
+  for (int64_t strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
+    const int64_t xl = strip * (32 * VEC) + (int64_t)VEC * n;
+    const bool active = xl < N;
+    const int64_t xs = active ? xl : N - VEC;  // a valid tube for address arithmetic
+    f32x16 acc[VEC];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int l = lc + 8 * (j >> 2) + 4 * kh + (j & 3);
-    if (l < p) {
-      float v[VEC];
+    for (int q = 0; q < VEC; ++q)
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) v[q] = acc[q][j];
-      store_vec<VEC>(Ah + (int64_t)l * N + xl, v);
+      for (int j = 0; j < 16; ++j) acc[q][j] = 0.f;
+    for (int kc = 0; kc < n3; kc += kcr) {
+      if (!one_chunk) {
+        __syncthreads();
+        stage(kc);
+        __syncthreads();
+      }
+      hat_accumulate<VEC, S, TIn>(A + (int64_t)kc * N + xs, N, active, min(kcr, n3 - kc), Qs, 32,
+                                  wave, n, kh, acc);
+    }
+    if (reduce_waves<VEC, S>(acc, red, wave, lane) && active) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int l = lc + 8 * (j >> 2) + 4 * kh + (j & 3);
+        if (l < p) {
+          float v[VEC];
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) v[q] = acc[q][j];
+          store_vec<VEC>(Ah + (int64_t)l * N + xl, v);
+        }
+      }
     }
   }
 }
@@ -115,17 +195,15 @@ __global__ __launch_bounds__(WAVES * 64) void unhat_f32_kernel(const float* __re
   const bool active = xl < N;
   const int ntiles = (n3 + 31) / 32;
   const bool regB = p <= 32;
+  const int64_t xs = active ? xl : N - VEC;  // a valid tube for address arithmetic
   float breg[16][VEC];
   if (regB) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int l = 2 * s + kh;
-      if (active && l < p) {
-        load_vec<VEC, float>(Ah + (int64_t)l * N + xl, breg[s]);
-      } else {
+      load_vec<VEC, float>(Ah + (int64_t)min(l, p - 1) * N + xs, breg[s]);
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) breg[s][q] = 0.f;
-      }
+      for (int q = 0; q < VEC; ++q) breg[s][q] = (active && l < p) ? breg[s][q] : 0.f;
     }
   }
   for (int tile = blockIdx.y; tile < ntiles; tile += gridDim.y) {
@@ -133,7 +211,8 @@ __global__ __launch_bounds__(WAVES * 64) void unhat_f32_kernel(const float* __re
     __syncthreads();
     for (int e = threadIdx.x; e < p_pad * 32; e += WAVES * 64) {
       const int l = e >> 5, tt = e & 31;
-      QsT[e] = (t0 + tt < n3 && l < p) ? Q[(int64_t)(t0 + tt) * p + l] : 0.f;
+      const float v = Q[(int64_t)min(t0 + tt, n3 - 1) * p + min(l, p - 1)];
+      QsT[e] = (t0 + tt < n3 && l < p) ? v : 0.f;
     }
     __syncthreads();
     f32x16 acc[VEC];
@@ -155,12 +234,9 @@ __global__ __launch_bounds__(WAVES * 64) void unhat_f32_kernel(const float* __re
       for (int l0 = 0; l0 < p; l0 += 2) {
         const int l = l0 + kh;
         float b[VEC];
-        if (active && l < p) {
-          load_vec<VEC, float>(Ah + (int64_t)l * N + xl, b);
-        } else {
+        load_vec<VEC, float>(Ah + (int64_t)min(l, p - 1) * N + xs, b);
 #pragma unroll
-          for (int q = 0; q < VEC; ++q) b[q] = 0.f;
-        }
+        for (int q = 0; q < VEC; ++q) b[q] = (active && l < p) ? b[q] : 0.f;
         const float a = QsT[l * 32 + n];
 #pragma unroll
         for (int q = 0; q < VEC; ++q)
@@ -182,37 +258,53 @@ __global__ __launch_bounds__(WAVES * 64) void unhat_f32_kernel(const float* __re
   }
 }
 
-// Fused projection, p <= 32: hat of the strip into the accumulators, then the
-// accumulators feed the unhat MFMAs directly.  For unhat step j a lane
-// supplies, as its B operand, its accumulator register j, which holds
-// transform row l = 8*(j/4) + 4*kh + j%4 of its tube; the A operand it
-// supplies is Q(t, l) for that same l, so each step contracts over the two
-// rows held by the two half-waves and no data moves between lanes.
-template <int VEC, int WAVES, typename TIn>
-__global__ __launch_bounds__(WAVES * 64) void proj_f32_kernel(const TIn* __restrict__ A,
-                                                              const float* __restrict__ Q,
-                                                              float* __restrict__ out, int64_t N,
-                                                              int n3, int p) {
-  extern __shared__ float Qs[];  // [rows_pad][33]
+// Fused projection, p <= 32: hat of the strip into the accumulators (split
+// over the S waves as above), the sum broadcast back to every wave through
+// LDS, then the accumulators feed the unhat MFMAs directly, each wave taking
+// every S-th 32-row output tile.  For unhat step j a lane supplies, as its B
+// operand, its accumulator register j, which holds transform row
+// l = 8*(j/4) + 4*kh + j%4 of its tube; the A operand it supplies is Q(t, l)
+// for that same l, so each step contracts over the two rows held by the two
+// half-waves and no data moves between lanes.
+template <int VEC, int S, typename TIn>
+__global__ __launch_bounds__(S * 64) void proj_f32_kernel(const TIn* __restrict__ A,
+                                                          const float* __restrict__ Q,
+                                                          float* __restrict__ out, int64_t N,
+                                                          int n3, int p) {
+  extern __shared__ float smem[];
   constexpr int ld = 33;
   const int ntiles = (n3 + 31) / 32;
-  const int rows_pad = ntiles * 32 + 2;
-  for (int e = threadIdx.x; e < rows_pad * ld; e += WAVES * 64) {
-    const int r = e / ld, c = e - r * ld;
-    Qs[e] = (r < n3 && c < p) ? Q[(int64_t)r * p + c] : 0.f;
-  }
+  const int rows_pad = ntiles * 32 + 16;
+  float* Qs = smem;                            // [rows_pad][33]
+  float* red = smem + rows_pad * ld;           // S * VEC * 16 * 64 floats
+  for (int kc = 0; kc < rows_pad; kc += 32) stage_q_rows(Q, p, n3, kc, min(32, rows_pad - kc), 0, Qs + kc * ld, ld, S * 64);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 31, kh = lane >> 5;
-  const int64_t xl = ((int64_t)blockIdx.x * WAVES + wave) * (32 * VEC) + (int64_t)VEC * n;
+  const int64_t xl = (int64_t)blockIdx.x * (32 * VEC) + (int64_t)VEC * n;
   const bool active = xl < N;
+  const int64_t xs = active ? xl : N - VEC;  // a valid tube for address arithmetic
   f32x16 h[VEC];
 #pragma unroll
   for (int q = 0; q < VEC; ++q)
 #pragma unroll
     for (int j = 0; j < 16; ++j) h[q][j] = 0.f;
-  hat_accumulate<VEC, TIn>(A + xl, N, active, n3, n3, Qs, ld, n, kh, h);
-  for (int tile = 0; tile < ntiles; ++tile) {
+  hat_accumulate<VEC, S, TIn>(A + xs, N, active, n3, Qs, ld, wave, n, kh, h);
+  if constexpr (S > 1) {
+    const bool w0 = reduce_waves<VEC, S>(h, red, wave, lane);
+    if (w0) {
+#pragma unroll
+      for (int q = 0; q < VEC; ++q)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) red[((S - 1) * VEC + q) * 16 * 64 + j * 64 + lane] = h[q][j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < VEC; ++q)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) h[q][j] = red[((S - 1) * VEC + q) * 16 * 64 + j * 64 + lane];
+  }
+  for (int tile = wave; tile < ntiles; tile += S) {
     const int t0 = tile * 32;
     f32x16 acc[VEC];
 #pragma unroll
@@ -238,6 +330,176 @@ __global__ __launch_bounds__(WAVES * 64) void proj_f32_kernel(const TIn* __restr
 #pragma unroll
           for (int q = 0; q < VEC; ++q) v[q] = acc[q][j];
           store_vec<VEC>(out + (int64_t)t * N + xl, v);
+        }
+      }
+    }
+  }
+}
+
+// ---- bfloat16 matrix-core forms of the transform ---------------------------
+// v_mfma_f32_32x32x16_bf16: D(32 x 32) += A(32 x 16) B(16 x 32); lane L holds
+// A row L%32 and B column L%32, each over k = 8*(L/32) .. +7 (8 bfloat16 in 4
+// dwords, k pairs packed low/high).  Here A = Q^T (rows: transform index l,
+// k: the frontal-slice index t) and B = a 16-row slab of the tensor.
+//
+// A lane reads 8 consecutive rows t of TPL consecutive tubes (coalesced
+// across the 32 lanes of a half-wave), packs rows 2q and 2q+1 of each tube
+// into dword q of that tube's B operand (v_cvt_pk_bf16_f32 does the packing
+// and the rounding at once), and issues one MFMA per tube and product; MFMA
+// column n of tube slot c is tube 32*TPL*strip + TPL*n + c.
+//
+// Precision modes are sums of products of bfloat16 parts, x = x0 + x1 + x2
+// with x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1):
+//   plain: a0 q0;  split x3: a0 q0 + a0 q1 + a1 q0;
+//   split x6: a0 q0 + a0 q1 + a1 q0 + a0 q2 + a1 q1 + a2 q0;
+//   bfloat16 input, x3 or x6: a q0 + a q1 + a q2 (exact in float32: three
+//   bfloat16 parts carry the full 24-bit significand of q).
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  f32x2v v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
+}
+__device__ __forceinline__ float bf16_lo(uint32_t d) { return __uint_as_float(d << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t d) { return __uint_as_float(d & 0xffff0000u); }
+
+template <int NA, int NQ>
+struct Split;
+// product list (a-part, q-part) per mode, smallest terms first
+template <> struct Split<1, 1> { static constexpr int n = 1; static constexpr int a[1] = {0}; static constexpr int q[1] = {0}; };
+template <> struct Split<2, 2> { static constexpr int n = 3; static constexpr int a[3] = {1, 0, 0}; static constexpr int q[3] = {0, 1, 0}; };
+template <> struct Split<3, 3> { static constexpr int n = 6; static constexpr int a[6] = {2, 1, 0, 1, 0, 0}; static constexpr int q[6] = {0, 1, 2, 0, 1, 0}; };
+template <> struct Split<1, 3> { static constexpr int n = 3; static constexpr int a[3] = {0, 0, 0}; static constexpr int q[3] = {2, 1, 0}; };
+
+// split float pairs into NP bfloat16 parts, packed: out[i] holds part i
+template <int NP>
+__device__ __forceinline__ void split_pack(float x, float y, uint32_t (&out)[NP]) {
+  out[0] = pack_bf16(x, y);
+  if constexpr (NP > 1) {
+    const float rx = x - bf16_lo(out[0]), ry = y - bf16_hi(out[0]);
+    out[1] = pack_bf16(rx, ry);
+    if constexpr (NP > 2) out[2] = pack_bf16(rx - bf16_lo(out[1]), ry - bf16_hi(out[1]));
+  }
+}
+
+template <typename TIn, int NA, int NQ, int TPL, int S>
+__global__ __launch_bounds__(S * 64) void hat_bf16_kernel(const TIn* __restrict__ A,
+                                                          const float* __restrict__ Q,
+                                                          float* __restrict__ Ah, int64_t N, int n3,
+                                                          int p, int kcr, int64_t nstrips) {
+  using SP = Split<NA, NQ>;
+  // Q parts in LDS as [part][t/8][l][8 bfloat16] (kcr rows): the 32 lanes of
+  // a half-wave read 32 consecutive 16-byte rows.  Then the reduction buffer.
+  extern __shared__ __align__(16) uint32_t smem_u[];
+  auto qs = [&](int i, int t8, int l) -> uint32_t* {
+    return smem_u + (((i * (kcr >> 3) + t8) * 32 + l) << 2);
+  };
+  float* red = reinterpret_cast<float*>(smem_u + NQ * kcr * 16);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 31, kh = lane >> 5;
+  const int lc = blockIdx.y * 32;
+  const bool one_chunk = n3 <= kcr;
+  auto stage = [&](int kc) {
+    const int rows = min(kcr, n3 - kc);
+    const int total = (kcr / 2) * 32;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * S * 64) {
+      float qv[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * S * 64, total - 1);
+        const int l = e & 31, t = 2 * (e >> 5);
+        const int lcl = min(lc + l, p - 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float v = Q[(int64_t)(kc + min(t + h, rows - 1)) * p + lcl];
+          qv[u][h] = (t + h < rows && lc + l < p) ? v : 0.f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * S * 64;
+        if (e >= total) continue;
+        const int l = e & 31, t = 2 * (e >> 5);
+        uint32_t parts[NQ];
+        split_pack<NQ>(qv[u][0], qv[u][1], parts);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) qs(i, t >> 3, l)[(t & 7) >> 1] = parts[i];
+      }
+    }
+  };
+  if (one_chunk) {
+    stage(0);
+    __syncthreads();
+  }
+  for (int64_t strip = blockIdx.x; strip < nstrips; strip += gridDim.x) {
+    const int64_t xl = strip * (32 * TPL) + (int64_t)TPL * n;
+    const bool active = xl < N;
+    const int64_t xs = active ? xl : N - TPL;  // a valid tube for address arithmetic
+    f32x16 acc[TPL];
+#pragma unroll
+    for (int c = 0; c < TPL; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[c][j] = 0.f;
+    for (int kc = 0; kc < n3; kc += kcr) {
+      if (!one_chunk) {
+        __syncthreads();
+        stage(kc);
+        __syncthreads();
+      }
+      const int rows = min(kcr, n3 - kc);
+      const int nsteps = (rows + 15) / 16;
+      float x0[8][TPL], x1[8][TPL];
+      auto load_step = [&](int st, float (&x)[8][TPL]) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int t = 16 * st + 8 * kh + r;
+          const bool ok = active && t < rows;
+          load_vec<TPL, TIn>(A + (int64_t)(kc + min(t, rows - 1)) * N + xs, x[r]);
+#pragma unroll
+          for (int c = 0; c < TPL; ++c) x[r][c] = ok ? x[r][c] : 0.f;
+        }
+      };
+      auto mfma_step = [&](int st, const float (&x)[8][TPL]) {
+        bf16x8 qop[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) qop[i] = *reinterpret_cast<const bf16x8*>(qs(i, 2 * st + kh, n));
+#pragma unroll
+        for (int c = 0; c < TPL; ++c) {
+          uint32_t bw[NA][4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            uint32_t parts[NA];
+            split_pack<NA>(x[2 * q][c], x[2 * q + 1][c], parts);
+#pragma unroll
+            for (int i = 0; i < NA; ++i) bw[i][q] = parts[i];
+          }
+#pragma unroll
+          for (int pr = 0; pr < SP::n; ++pr) {
+            const bf16x8 bop = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(bw[SP::a[pr]]));
+            acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qop[SP::q[pr]], bop, acc[c], 0, 0, 0);
+          }
+        }
+      };
+      int st = wave;
+      if (st < nsteps) load_step(st, x0);
+      for (; st < nsteps; st += 2 * S) {
+        if (st + S < nsteps) load_step(st + S, x1);
+        mfma_step(st, x0);
+        if (st + S >= nsteps) break;
+        if (st + 2 * S < nsteps) load_step(st + 2 * S, x0);
+        mfma_step(st + S, x1);
+      }
+    }
+    if (reduce_waves<TPL, S>(acc, red, wave, lane) && active) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int l = lc + 8 * (j >> 2) + 4 * kh + (j & 3);
+        if (l < p) {
+          float v[TPL];
+#pragma unroll
+          for (int c = 0; c < TPL; ++c) v[c] = acc[c][j];
+          store_vec<TPL>(Ah + (int64_t)l * N + xl, v);
         }
       }
     }
@@ -301,92 +563,241 @@ int pick_vec(int64_t N, std::initializer_list<const void*> ptrs, int elem) {
   return 1;
 }
 
-constexpr int kWaves = 4;
+// Candidate launch configurations of the transforms: vector width (tubes per
+// lane) x waves per workgroup x strips per workgroup.  For the forward
+// transform and the projection the waves of a workgroup split the rows of its
+// current strip (split-K inside the workgroup) and the workgroup walks over
+// `spw` strips; for the return transform each wave has its own strip.
+struct Cfg {
+  int vec, waves, spw;
+};
 
-template <int VEC, typename TIn>
-hipError_t hat_f32_vec(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p,
-                       hipStream_t s) {
-  const int64_t strips = (N + 32 * VEC - 1) / (32 * VEC);
-  dim3 grid((unsigned)((strips + kWaves - 1) / kWaves), (unsigned)((p + 31) / 32));
-  hat_f32_kernel<VEC, kWaves, TIn><<<grid, kWaves * 64, 0, s>>>(A, Q, Ah, N, n3, p);
+std::vector<Cfg> cands(int vmax, bool splitk) {
+  std::vector<Cfg> v;
+  for (int vec : {4, 2, 1})
+    if (vec <= vmax)
+      for (int w : {1, 2, 4, 8}) {
+        if (!splitk) {
+          if (w >= 2) v.push_back({vec, w, 1});
+        } else if (vec * w <= 16) {
+          for (int spw : {1, 4}) v.push_back({vec, w, spw});
+        }
+      }
+  return v;
+}
+
+// untuned default for the split-K kernels: the widest vector whose strips,
+// times up to 16 / vec waves each, still give about 2048+ waves; the waves
+// per strip chosen to reach about 4096; one strip per workgroup
+int default_splitk(const std::vector<Cfg>& c, int64_t N) {
+  Cfg want{1, 8, 1};
+  for (int vec : {4, 2, 1}) {
+    const int64_t strips = (N + 32 * vec - 1) / (32 * vec);
+    int w = 1;
+    while (w < 8 && vec * w * 2 <= 16 && strips * w < 4096) w *= 2;
+    if (strips * w >= 2048 || vec == 1) {
+      want = {vec, w, 1};
+      break;
+    }
+  }
+  for (size_t i = 0; i < c.size(); ++i)
+    if (c[i].vec == want.vec && c[i].waves == want.waves && c[i].spw == want.spw) return (int)i;
+  return (int)c.size() - 1;
+}
+
+int default_strips(const std::vector<Cfg>& c, int64_t N) {
+  int want = 1;
+  for (int vec : {4, 2})
+    if (want == 1 && N / (32 * vec) >= 2048) want = vec;
+  for (size_t i = 0; i < c.size(); ++i)
+    if (c[i].vec == want && c[i].waves == 4) return (int)i;
+  return 0;
+}
+
+std::string key_of(const char* kind, int prec, int bf, int64_t N, int n3, int p, int vmax) {
+  return std::string(kind) + "/prec" + std::to_string(prec) + "/bf" + std::to_string(bf) + "/N" +
+         std::to_string(N) + "/n3_" + std::to_string(n3) + "/p" + std::to_string(p) + "/v" +
+         std::to_string(vmax);
+}
+
+// dynamic LDS beyond the 64 KB default, set once per kernel instance
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+size_t red_bytes(int vec, int S) { return sizeof(float) * (size_t)(S - 1) * vec * 16 * 64; }
+
+// rows of Q staged per chunk: n3 rounded up to 16, at most kKC
+int chunk_rows(int n3) { return std::min(kKC, (n3 + 15) / 16 * 16); }
+
+template <int VEC, int S, typename TIn>
+hipError_t hat_f32_go(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p, int spw,
+                      hipStream_t s) {
+  const int kcr = chunk_rows(n3);
+  const size_t lds = sizeof(float) * (size_t)kcr * 32 + red_bytes(VEC, S);
+  static hipError_t attr = allow_lds(&hat_f32_kernel<VEC, S, TIn>, 120 * 1024);
+  if (attr != hipSuccess) return attr;
+  const int64_t nstrips = (N + 32 * VEC - 1) / (32 * VEC);
+  dim3 grid((unsigned)((nstrips + spw - 1) / spw), (unsigned)((p + 31) / 32));
+  hat_f32_kernel<VEC, S, TIn><<<grid, S * 64, lds, s>>>(A, Q, Ah, N, n3, p, kcr, nstrips);
   return hipGetLastError();
 }
 
-template <int VEC>
-hipError_t unhat_f32_vec(const float* Ah, const float* Q, float* C, int64_t N, int n3, int p,
-                         hipStream_t s) {
+template <typename TIn, int NA, int NQ, int TPL, int S>
+hipError_t hat_bf16_go(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p, int spw,
+                       hipStream_t s) {
+  const int kcr = chunk_rows(n3);
+  const size_t lds = (size_t)NQ * kcr * 64 + red_bytes(TPL, S);
+  static hipError_t attr = allow_lds(&hat_bf16_kernel<TIn, NA, NQ, TPL, S>, 120 * 1024);
+  if (attr != hipSuccess) return attr;
+  const int64_t nstrips = (N + 32 * TPL - 1) / (32 * TPL);
+  dim3 grid((unsigned)((nstrips + spw - 1) / spw), (unsigned)((p + 31) / 32));
+  hat_bf16_kernel<TIn, NA, NQ, TPL, S><<<grid, S * 64, lds, s>>>(A, Q, Ah, N, n3, p, kcr, nstrips);
+  return hipGetLastError();
+}
+
+template <int VEC, int S, typename TIn>
+hipError_t proj_f32_go(const TIn* A, const float* Q, float* out, int64_t N, int n3, int p,
+                       hipStream_t s) {
+  const int ntiles = (n3 + 31) / 32;
+  const size_t lds = (size_t)(ntiles * 32 + 16) * 33 * sizeof(float) + red_bytes(VEC, S + 1);
+  static hipError_t attr = allow_lds(&proj_f32_kernel<VEC, S, TIn>, 160 * 1024);
+  if (attr != hipSuccess) return attr;
+  dim3 grid((unsigned)((N + 32 * VEC - 1) / (32 * VEC)));
+  proj_f32_kernel<VEC, S, TIn><<<grid, S * 64, lds, s>>>(A, Q, out, N, n3, p);
+  return hipGetLastError();
+}
+
+template <int VEC, int W>
+hipError_t unhat_f32_go(const float* Ah, const float* Q, float* C, int64_t N, int n3, int p,
+                        hipStream_t s) {
   const int64_t strips = (N + 32 * VEC - 1) / (32 * VEC);
-  const int64_t wgs = (strips + kWaves - 1) / kWaves;
+  const int64_t wgs = (strips + W - 1) / W;
   const int ntiles = (n3 + 31) / 32;
   // enough workgroups to fill 256 CUs several times over
   int ysplit = (int)std::min<int64_t>(ntiles, std::max<int64_t>(1, (2048 + wgs - 1) / wgs));
   const size_t lds = (size_t)((p + 1) & ~1) * 32 * sizeof(float);
   dim3 grid((unsigned)wgs, (unsigned)ysplit);
-  unhat_f32_kernel<VEC, kWaves><<<grid, kWaves * 64, lds, s>>>(Ah, Q, C, N, n3, p);
+  unhat_f32_kernel<VEC, W><<<grid, W * 64, lds, s>>>(Ah, Q, C, N, n3, p);
   return hipGetLastError();
 }
 
-template <int VEC, typename TIn>
-hipError_t proj_f32_vec(const TIn* A, const float* Q, float* out, int64_t N, int n3, int p,
+// dispatch a (vec, waves) pair onto template instances
+#define PQ_VW_DISPATCH(CFG, CALL)                                           \
+  switch ((CFG).vec * 16 + (CFG).waves) {                                   \
+    case 4 * 16 + 1: return CALL(4, 1);                                     \
+    case 4 * 16 + 2: return CALL(4, 2);                                     \
+    case 4 * 16 + 4: return CALL(4, 4);                                     \
+    case 2 * 16 + 1: return CALL(2, 1);                                     \
+    case 2 * 16 + 2: return CALL(2, 2);                                     \
+    case 2 * 16 + 4: return CALL(2, 4);                                     \
+    case 2 * 16 + 8: return CALL(2, 8);                                     \
+    case 1 * 16 + 1: return CALL(1, 1);                                     \
+    case 1 * 16 + 2: return CALL(1, 2);                                     \
+    case 1 * 16 + 4: return CALL(1, 4);                                     \
+    default: return CALL(1, 8);                                             \
+  }
+
+#define PQ_VW_DISPATCH_STRIPS(CFG, CALL)                                    \
+  switch ((CFG).vec * 16 + (CFG).waves) {                                   \
+    case 4 * 16 + 2: return CALL(4, 2);                                     \
+    case 4 * 16 + 4: return CALL(4, 4);                                     \
+    case 4 * 16 + 8: return CALL(4, 8);                                     \
+    case 2 * 16 + 2: return CALL(2, 2);                                     \
+    case 2 * 16 + 4: return CALL(2, 4);                                     \
+    case 2 * 16 + 8: return CALL(2, 8);                                     \
+    case 1 * 16 + 2: return CALL(1, 2);                                     \
+    case 1 * 16 + 4: return CALL(1, 4);                                     \
+    default: return CALL(1, 8);                                             \
+  }
+
+template <typename TIn, int NA, int NQ>
+hipError_t hat_bf16_any(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p, Cfg c,
                         hipStream_t s) {
-  const int64_t strips = (N + 32 * VEC - 1) / (32 * VEC);
-  const int ntiles = (n3 + 31) / 32;
-  const size_t lds = (size_t)(ntiles * 32 + 2) * 33 * sizeof(float);
-  dim3 grid((unsigned)((strips + kWaves - 1) / kWaves));
-  proj_f32_kernel<VEC, kWaves, TIn><<<grid, kWaves * 64, lds, s>>>(A, Q, out, N, n3, p);
-  return hipGetLastError();
+#define PQ_CALL(V, W) hat_bf16_go<TIn, NA, NQ, V, W>(A, Q, Ah, N, n3, p, c.spw, s)
+  PQ_VW_DISPATCH(c, PQ_CALL)
+#undef PQ_CALL
+}
+
+template <typename TIn>
+hipError_t hat_f32_any(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p, Cfg c,
+                       hipStream_t s) {
+#define PQ_CALL(V, W) hat_f32_go<V, W, TIn>(A, Q, Ah, N, n3, p, c.spw, s)
+  PQ_VW_DISPATCH(c, PQ_CALL)
+#undef PQ_CALL
+}
+
+template <typename TIn>
+hipError_t proj_f32_any(const TIn* A, const float* Q, float* out, int64_t N, int n3, int p, Cfg c,
+                        hipStream_t s) {
+#define PQ_CALL(V, W) proj_f32_go<V, W, TIn>(A, Q, out, N, n3, p, s)
+  PQ_VW_DISPATCH(c, PQ_CALL)
+#undef PQ_CALL
+}
+
+hipError_t unhat_f32_any(const float* Ah, const float* Q, float* C, int64_t N, int n3, int p, Cfg c,
+                         hipStream_t s) {
+#define PQ_CALL(V, W) unhat_f32_go<V, W>(Ah, Q, C, N, n3, p, s)
+  PQ_VW_DISPATCH_STRIPS(c, PQ_CALL)
+#undef PQ_CALL
 }
 
 }  // namespace
 
 hipError_t hat_f32(const void* A, bool a_bf16, const float* Q, float* Ah, int64_t N, int n3, int p,
                    Prec prec, hipStream_t s) {
-  if (prec != Prec::Default) return hipErrorNotSupported;
-  if (a_bf16) {
-    const uint16_t* a = static_cast<const uint16_t*>(A);
-    switch (std::min(pick_vec(N, {A}, 2), pick_vec(N, {Ah}, 4))) {
-      case 4: return hat_f32_vec<4>(a, Q, Ah, N, n3, p, s);
-      case 2: return hat_f32_vec<2>(a, Q, Ah, N, n3, p, s);
-      default: return hat_f32_vec<1>(a, Q, Ah, N, n3, p, s);
+  const int vmax = a_bf16 ? std::min(pick_vec(N, {A}, 2), pick_vec(N, {Ah}, 4)) : pick_vec(N, {A, Ah}, 4);
+  const std::vector<Cfg> c = cands(vmax, true);
+  const std::string key = key_of("hat", (int)prec, a_bf16, N, n3, p, vmax);
+  const uint16_t* ab = static_cast<const uint16_t*>(A);
+  const float* af = static_cast<const float*>(A);
+  return tuned_launch(key, (int)c.size(), default_splitk(c, N), s, [&](int i) -> hipError_t {
+    const Cfg g = c[i];
+    if (a_bf16) {
+      switch (prec) {
+        case Prec::Default: return hat_f32_any<uint16_t>(ab, Q, Ah, N, n3, p, g, s);
+        case Prec::BF16: return hat_bf16_any<uint16_t, 1, 1>(ab, Q, Ah, N, n3, p, g, s);
+        default: return hat_bf16_any<uint16_t, 1, 3>(ab, Q, Ah, N, n3, p, g, s);
+      }
     }
-  }
-  const float* a = static_cast<const float*>(A);
-  switch (pick_vec(N, {A, Ah}, 4)) {
-    case 4: return hat_f32_vec<4>(a, Q, Ah, N, n3, p, s);
-    case 2: return hat_f32_vec<2>(a, Q, Ah, N, n3, p, s);
-    default: return hat_f32_vec<1>(a, Q, Ah, N, n3, p, s);
-  }
+    switch (prec) {
+      case Prec::Default: return hat_f32_any<float>(af, Q, Ah, N, n3, p, g, s);
+      case Prec::BF16: return hat_bf16_any<float, 1, 1>(af, Q, Ah, N, n3, p, g, s);
+      case Prec::BF16x3: return hat_bf16_any<float, 2, 2>(af, Q, Ah, N, n3, p, g, s);
+      default: return hat_bf16_any<float, 3, 3>(af, Q, Ah, N, n3, p, g, s);
+    }
+  });
 }
 
-hipError_t unhat_f32(const float* Ah, const float* Q, float* C, int64_t N, int n3, int p,
-                     Prec prec, hipStream_t s) {
-  if (prec != Prec::Default) return hipErrorNotSupported;
-  switch (pick_vec(N, {Ah, C}, 4)) {
-    case 4: return unhat_f32_vec<4>(Ah, Q, C, N, n3, p, s);
-    case 2: return unhat_f32_vec<2>(Ah, Q, C, N, n3, p, s);
-    default: return unhat_f32_vec<1>(Ah, Q, C, N, n3, p, s);
-  }
+hipError_t unhat_f32(const float* Ah, const float* Q, float* C, int64_t N, int n3, int p, Prec prec,
+                     hipStream_t s) {
+  (void)prec;  // the return transform runs on float32 MFMA in every mode
+  const int vmax = pick_vec(N, {Ah, C}, 4);
+  const std::vector<Cfg> c = cands(vmax, false);
+  return tuned_launch(key_of("unhat", 0, 0, N, n3, p, vmax), (int)c.size(), default_strips(c, N), s,
+                      [&](int i) { return unhat_f32_any(Ah, Q, C, N, n3, p, c[i], s); });
 }
 
 bool proj_fused_ok(int n3, int p) { return p <= 32 && n3 <= 480; }
 
 hipError_t proj_fused_f32(const void* A, bool a_bf16, const float* Q, float* out, int64_t N, int n3,
                           int p, Prec prec, hipStream_t s) {
-  if (prec != Prec::Default) return hipErrorNotSupported;
-  if (a_bf16) {
-    const uint16_t* a = static_cast<const uint16_t*>(A);
-    switch (std::min(pick_vec(N, {A}, 2), pick_vec(N, {out}, 4))) {
-      case 4: return proj_f32_vec<4>(a, Q, out, N, n3, p, s);
-      case 2: return proj_f32_vec<2>(a, Q, out, N, n3, p, s);
-      default: return proj_f32_vec<1>(a, Q, out, N, n3, p, s);
-    }
-  }
-  const float* a = static_cast<const float*>(A);
-  switch (pick_vec(N, {A, out}, 4)) {
-    case 4: return proj_f32_vec<4>(a, Q, out, N, n3, p, s);
-    case 2: return proj_f32_vec<2>(a, Q, out, N, n3, p, s);
-    default: return proj_f32_vec<1>(a, Q, out, N, n3, p, s);
-  }
+  (void)prec;  // the fused projection runs on float32 MFMA in every mode
+  const int vmax = a_bf16 ? std::min(pick_vec(N, {A}, 2), pick_vec(N, {out}, 4))
+                          : pick_vec(N, {A, out}, 4);
+  std::vector<Cfg> c;
+  for (const Cfg& g : cands(vmax, true))
+    if (g.spw == 1) c.push_back(g);  // the projection stages all of Q once per strip
+  return tuned_launch(key_of("proj", 0, a_bf16, N, n3, p, vmax), (int)c.size(), default_splitk(c, N), s,
+                      [&](int i) -> hipError_t {
+                        if (a_bf16)
+                          return proj_f32_any<uint16_t>(static_cast<const uint16_t*>(A), Q, out, N,
+                                                        n3, p, c[i], s);
+                        return proj_f32_any<float>(static_cast<const float*>(A), Q, out, N, n3, p,
+                                                   c[i], s);
+                      });
 }
 
 hipError_t hat_f64(const double* A, const double* Q, double* Ah, int64_t N, int n3, int p,

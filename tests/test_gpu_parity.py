@@ -206,11 +206,14 @@ def test_tsvdq_rank_deficient(pq):
 
 
 def test_tsvdq_max_sweeps_reported(pq):
+    """max_sweeps caps each phase (float32 sweeps, then float64 polishing);
+    faces stopped by the cap are counted and their outputs still written."""
     say("tsvdq max_sweeps=1")
     A, Q = _case(9, 40, 30, 12, 3)
     r = pq.tsvdq(dev(A), devq(Q), 4, max_sweeps=1)
     info = r.info.cpu().numpy()
-    assert info[0] == 1 and info[1] == 3
+    assert info[0] == 2 and info[1] == 3 and info[2] == 6
+    assert np.all(np.isfinite(host(r.s)))
 
 
 def test_video_case_full_size(pq):
@@ -233,6 +236,70 @@ def test_hyperspectral_hat_bf16_input(pq):
     Ah = pq.hat(Ad, devq(c["Q"]))
     ref = oracle.hat(synth.logical(c["A"]), c["Q"])
     assert rel(host(Ah), ref) <= TOL32
+
+
+BF16_SHAPES = [(32, 24, 16, 4), (7, 9, 33, 5), (50, 30, 200, 20), (17, 6, 300, 37),
+               (64, 64, 256, 32)]
+
+
+@pytest.mark.parametrize("shape", BF16_SHAPES)
+def test_hat_bf16_modes_f32_input(pq, shape):
+    """bfloat16 matrix-core transform of float32 data: split x3 and x6 meet
+    the float32 tolerance; plain bfloat16 is reported (bounded loosely)."""
+    n1, n2, n3, p = shape
+    say(f"hat bf16 modes {shape}")
+    A, Q = _case(500 + n3, n1, n2, n3, p)
+    Ad, Qd = dev(A), devq(Q)
+    ref = oracle.hat(synth.logical(A), Q)
+    errs = {m: rel(host(pq.hat(Ad, Qd, prec=m)), ref) for m in ("bf16", "bf16x3", "bf16x6")}
+    say(f"  rel err {errs}")
+    assert errs["bf16x3"] <= TOL32
+    assert errs["bf16x6"] <= 1e-6
+    assert errs["bf16"] <= 1e-2
+
+
+@pytest.mark.parametrize("shape", BF16_SHAPES[:3])
+def test_hat_bf16_modes_bf16_input(pq, shape):
+    """bfloat16-stored data: with Q split three ways the products are exact in
+    float32, so split modes meet float32 accuracy."""
+    n1, n2, n3, p = shape
+    say(f"hat bf16-input modes {shape}")
+    A, Q = _case(600 + n3, n1, n2, n3, p)
+    bits = synth.bf16_bits(A)
+    vals = synth.bf16_to_f32(bits)
+    Ad = dev_bf16(bits)
+    ref = oracle.hat(synth.logical(vals), Q)
+    for m, tol in (("default", TOL32), ("bf16x3", 1e-6), ("bf16x6", 1e-6), ("bf16", 1e-2)):
+        assert rel(host(pq.hat(Ad, devq(Q), prec=m)), ref) <= tol, m
+
+
+@pytest.fixture(scope="module")
+def hyper_case():
+    c = synth.hyperspectral_case()
+    c["ref"] = oracle.tsvdq(synth.logical(c["A"]), c["Q"], c["k"])
+    return c
+
+
+@pytest.mark.parametrize("prec", ["default", "bf16x3"])
+def test_hyperspectral_tsvdq(pq, hyper_case, prec):
+    """Hyperspectral-shaped case at full size (512 x 512 x 224 bfloat16, p = 32,
+    k = 16; flat spectra at the truncation): singular values and A_k against
+    the float64 oracle, through the float32 and the split-bfloat16 transform."""
+    say(f"hyperspectral tsvdq {prec}")
+    c = hyper_case
+    Ad = dev_bf16(c["A_bits"])
+    Q, k = c["Q"], c["k"]
+    r = pq.tsvdq(Ad, devq(Q), k, prec=prec, approx=True)
+    info = r.info.cpu().numpy()
+    say(f"  jacobi info {info.tolist()}")
+    assert info[1] == 0
+    ref = c["ref"]
+    s = host(r.s)
+    for l in range(Q.shape[1]):
+        assert rel(s[:, l], ref.s[:, l]) <= TOL32, f"face {l}"
+    err = rel(host(r.Ak), ref.Ak)
+    say(f"  A_k rel err {err:.3e}")
+    assert err <= TOL32
 
 
 def test_differentiation_case(pq):
@@ -305,6 +372,32 @@ def test_check_q(pq):
     Q32 = Q.astype(np.float32)
     assert pq.check_q(devq(Q32)).item() == pytest.approx(oracle.check_q(Q32), rel=1e-9, abs=1e-15)
     assert pq.check_q(devq(Q32)).dtype == torch.float64
+
+
+def test_autotuned_launches_match(pq, tmp_path):
+    """Every candidate configuration the autotuner may pick computes the same
+    transform: results with tuning on and off agree, and the table persists."""
+    say("autotune")
+    from paper_2409_19402_amd import _lib
+    A, Q = _case(71, 45, 37, 70, 9)
+    Ad, Qd = dev(A), devq(Q)
+    ref = oracle.hat(synth.logical(A), Q)
+    pq.autotune(True)
+    try:
+        tuned = {m: host(pq.hat(Ad, Qd, prec=m)) for m in ("default", "bf16x3")}
+        P = host(pq.proj(Ad, Qd))
+    finally:
+        pq.autotune(False)
+    assert rel(tuned["default"], ref) <= TOL32
+    assert rel(tuned["bf16x3"], ref) <= TOL32
+    assert rel(P, oracle.proj(synth.logical(A), Q)) <= TOL32
+    n = _lib.load().pq_autotune_entries()
+    assert n >= 3
+    path = tmp_path / "tune.txt"
+    pq.autotune_save(path)
+    assert len(path.read_text().splitlines()) == n
+    pq.autotune_load(path)
+    assert _lib.load().pq_autotune_entries() == n
 
 
 def test_rejects_non_face_major(pq):
