@@ -238,7 +238,8 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
  * faces) are written as zero vectors.  tol is the Jacobi stopping threshold
  * on |a_i . a_j| / (|a_i| |a_j|) of the final (float64) sweeps (<= 0 selects
  * 1e-13; two singular vectors come out coupled by about tol / (2 x the
- * relative gap of their singular values)),
+ * relative gap of their singular values); for F32 and BF16 data the final
+ * sweeps work on Gram matrices of the vectors and use max(tol, 1e-10)),
  * max_sweeps caps the sweeps of each phase (<= 0: 20 for float32 data,
  * 30 for float64; at most 100).  info_dev (device int[3], may be NULL)
  * receives [0] = the largest number of sweeps any face used (both phases),

@@ -40,50 +40,7 @@ int hip_status(hipError_t e) {
     if (_rc != PQ_OK) return _rc;           \
   } while (0)
 
-// ---- per-launch timing (pq_profile_*) ------------------------------------
-// When enabled, every launch below is bracketed by two hipEvents recorded on
-// the caller's stream; the events come from a pool that grows on demand.
-struct ProfRec {
-  const char* name;
-  hipEvent_t a, b;
-};
-std::mutex g_prof_mu;
-bool g_prof_on = false;
-std::vector<ProfRec> g_prof_recs;
-std::vector<hipEvent_t> g_prof_pool;
-
-hipEvent_t prof_event() {
-  if (!g_prof_pool.empty()) {
-    hipEvent_t e = g_prof_pool.back();
-    g_prof_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-struct ProfScope {
-  const char* name;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  ProfScope(const char* n, hipStream_t st) : name(n), s(st) {
-    std::lock_guard<std::mutex> g(g_prof_mu);
-    if (!g_prof_on) return;
-    a = prof_event();
-    if (a) hipEventRecord(a, s);
-  }
-  ~ProfScope() {
-    if (!a) return;
-    std::lock_guard<std::mutex> g(g_prof_mu);
-    hipEvent_t b = prof_event();
-    if (!b) return;
-    hipEventRecord(b, s);
-    g_prof_recs.push_back({name, a, b});
-  }
-};
-
-#define PQ_PROF(name, stream) ProfScope _pq_prof_scope(name, stream)
+#define PQ_PROF(name, stream) pq::ProfScope _pq_prof_scope(name, stream)
 
 constexpr int64_t kMaxDim = (int64_t)1 << 30;
 
@@ -141,6 +98,11 @@ constexpr int kDefaultSweeps64 = 30;
 constexpr double kCoarseTol32 = 1e-5;
 constexpr int kPolishSweeps = 8;  // float64 polishing from the coarse threshold: 2-4 sweeps
 constexpr double kPolishTol = 1e-13;
+// The float64 sweeps of float32 data run on Gram matrices, whose rotation
+// angles come from G as updated within a visit: their stopping test is
+// floored here (the coupling it leaves, about tol / (2 x relative gap), is
+// still far below float32 resolution).
+constexpr double kGramTolFloor = 1e-10;
 constexpr int kMaxSweepsCap = 100;
 
 int ksplit_for(int64_t K) { return (int)std::clamp<int64_t>(K / 512, 1, 1024); }
@@ -249,59 +211,24 @@ int pq_autotune_load(const char* path) {
 }
 
 int pq_profile_enable(int on) {
-  std::lock_guard<std::mutex> g(g_prof_mu);
-  g_prof_on = on != 0;
+  pq::prof_enable(on != 0);
   return PQ_OK;
 }
 
 int pq_profile_reset(void) {
-  std::lock_guard<std::mutex> g(g_prof_mu);
-  for (ProfRec& r : g_prof_recs) {
-    g_prof_pool.push_back(r.a);
-    g_prof_pool.push_back(r.b);
-  }
-  g_prof_recs.clear();
+  pq::prof_reset();
   return PQ_OK;
 }
 
 int pq_profile_query(const char* name, double* total_ms, int* launches) {
   if (!name || !total_ms || !launches) return PQ_ERR_NULL;
-  std::lock_guard<std::mutex> g(g_prof_mu);
-  double tot = 0.0;
-  int n = 0;
-  for (const ProfRec& r : g_prof_recs) {
-    if (std::strcmp(r.name, name) != 0) continue;
-    PQ_TRY(hipEventSynchronize(r.b));
-    float ms = 0.f;
-    PQ_TRY(hipEventElapsedTime(&ms, r.a, r.b));
-    tot += ms;
-    ++n;
-  }
-  *total_ms = tot;
-  *launches = n;
+  PQ_TRY(pq::prof_query(name, total_ms, launches));
   return PQ_OK;
 }
 
 int pq_profile_names(char* buf, size_t len) {
   if (!buf || len == 0) return PQ_ERR_NULL;
-  std::lock_guard<std::mutex> g(g_prof_mu);
-  std::vector<const char*> seen;
-  for (const ProfRec& r : g_prof_recs) {
-    bool dup = false;
-    for (const char* q : seen) dup |= std::strcmp(q, r.name) == 0;
-    if (!dup) seen.push_back(r.name);
-  }
-  size_t pos = 0;
-  buf[0] = 0;
-  for (const char* q : seen) {
-    const size_t l = std::strlen(q);
-    if (pos + l + 2 > len) return PQ_ERR_ARG;
-    if (pos) buf[pos++] = ',';
-    std::memcpy(buf + pos, q, l);
-    pos += l;
-    buf[pos] = 0;
-  }
-  return PQ_OK;
+  return pq::prof_names(buf, len) ? PQ_OK : PQ_ERR_ARG;
 }
 
 int pq_check_q(const void* Q, int q_dtype, int64_t n3, int64_t p, double* out_dev, hipStream_t stream) {
@@ -607,18 +534,18 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
       PQ_PROF("jacobi_prep", stream);
       PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(Ah), W32, in1, in2, ip, stream));
     }
-    {  // float32 sweeps down to a coarse threshold
-      PQ_PROF("jacobi_sweeps", stream);
-      PQ_TRY(pq::jacobi_sweeps_f32(W32, ip, nv, L, max_sweeps, kCoarseTol32, used1, flags, stream));
-    }
+    // float32 sweeps down to a coarse threshold (each launch profiled inside)
+    PQ_TRY(pq::jacobi_sweeps_f32(W32, ip, nv, L, max_sweeps, kCoarseTol32, used1, flags, stream));
     PQ_PROF("jacobi_widen", stream);
     PQ_TRY(pq::jacobi_widen(W32, W64, N * p, stream));
   }
-  {  // float64 sweeps to tol
-    PQ_PROF("jacobi_polish", stream);
-    PQ_TRY(pq::jacobi_sweeps_f64(W64, ip, nv, L, f64 ? max_sweeps : std::min(max_sweeps, kPolishSweeps),
-                                 tol, f64 ? used1 : used2, flags, stream));
-  }
+  // float64 sweeps to tol (each launch profiled inside)
+  if (f64)
+    PQ_TRY(pq::jacobi_sweeps_f64(W64, ip, nv, L, max_sweeps, tol, used1, flags, stream));
+  else
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(W64, ip, nv, L, std::min(max_sweeps, kPolishSweeps),
+                                      std::max(tol, kGramTolFloor), used2, flags,
+                                      stream));
   {
     PQ_PROF("jacobi_finalize", stream);
     PQ_TRY(pq::jacobi_finalize_f64(W64, ip, nv, L, ik, Ft, stream));

@@ -26,6 +26,26 @@ int tune_entries();
 bool tune_save(const char* path);
 bool tune_load(const char* path);
 
+// ---- per-launch profiler (prof.cpp) ---------------------------------------
+// While enabled, a ProfScope records a hipEvent on s at construction and at
+// destruction; the pair is kept under `name` (a string literal).
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr;
+};
+void prof_enable(bool on);
+void prof_reset();
+hipError_t prof_query(const char* name, double* total_ms, int* launches);
+bool prof_names(char* buf, size_t len);
+
 // ---- mode-3 transforms (transform.hip) -----------------------------------
 // Ah (p x N) = Q^T (p x n3) * A (n3 x N); A is float32 or bfloat16 bits.
 hipError_t hat_f32(const void* A, bool a_bf16, const float* Q, float* Ah,
@@ -79,6 +99,10 @@ hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, h
 // flags: p * max_sweeps ints of scratch.
 hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol,
                              int* sweeps_used, int* flags, hipStream_t s);
+// float64 sweeps in the Gram-matrix form (the polishing sweeps of float32
+// data; falls back to the vector form when the staged vectors do not fit)
+hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
+                                  int* flags, hipStream_t s);
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol,
                              int* sweeps_used, int* flags, hipStream_t s);
 // Column norms, descending order, top k normalised vectors F (L x k x p).

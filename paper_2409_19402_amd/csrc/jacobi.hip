@@ -271,6 +271,340 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_global_kernel(T* __rest
   if (threadIdx.x == 0) sweeps_used[face] = converged ? sweep : max_sweeps + 1;
 }
 
+// ---- Gram-matrix block step ---------------------------------------------
+// One workgroup of four waves per (block pair, face).  The 2b = 32 vectors of
+// blocks I and J are staged in LDS; their Gram matrix G = X^T X is formed on
+// MFMA (v_mfma_f32_16x16x4f32 for float32 vectors, v_mfma_f64_16x16x4f64 for
+// float64; one 16x16 tile per wave, the lower off-diagonal tile mirrored from
+// the upper one).  If no pair this visit covers has |g_ac| > tol sqrt(g_aa
+// g_cc) in the freshly formed G, the visit ends there (the face's sweep flag
+// is left alone).  Otherwise the rotations are run on G alone, in float64:
+// each round takes 16 disjoint pairs, computes their angles from G's entries
+// and applies G <- J^T G J (one 2x2 block of G per pair of pairs and thread)
+// and V <- V J.  The vectors are touched once more, at the end: X <- X V on
+// the same MFMA, written back to global memory.  A rotation costs O(32) work
+// on G instead of O(L) on the vectors.
+//
+// Pairs: the first launch of a sweep runs a full round robin over the 32
+// vectors (so every pair inside a block is visited once per sweep), the
+// others the 16 x 16 pairs between their two blocks in 16 rounds.
+//
+// A face table (nullable) gives every face its own offset, vector count and
+// length; without one, face f is the f-th block of nv x L elements.
+
+struct JFace {
+  int64_t off;  // element offset of the face's first vector in W
+  int nv, L;
+};
+
+constexpr int kGB = 16;        // vectors per block
+constexpr int kG2 = 2 * kGB;   // vectors per block pair = Gram order
+constexpr int kGld = kG2 + 1;  // row stride of G and V in LDS (doubles): no bank conflicts on columns
+constexpr int kGMat = kG2 * kGld;
+// two copies of G (each round reads one and writes the other), V (updated in
+// place: every entry is read and written by one thread only), a flag word
+constexpr size_t kGramHead = sizeof(double) * 3 * kGMat + 16;
+
+__device__ __forceinline__ JFace face_of(const JFace* tab, int f, int nv, int L) {
+  if (tab) return tab[f];
+  return JFace{(int64_t)f * nv * L, nv, L};
+}
+
+// LDS row stride of the staged vectors: 16-byte reads of 16 rows hit
+// distinct banks
+template <typename T>
+__host__ __device__ __forceinline__ int gram_ldx(int L) {
+  return ((L + 15) & ~15) + (sizeof(T) == 4 ? 4 : 2);
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ size_t gram_lds_bytes(int L) {
+  return kGramHead + sizeof(T) * (size_t)kG2 * gram_ldx<T>(L);
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct GramMfma;
+// Output layout of the 16x16x4 MFMAs: lane L holds column L mod 16 of D, in
+// rows row(L / 16, j) for its four values j (float32: 4 (L / 16) + j;
+// float64: L / 16 + 4 j).
+template <> struct GramMfma<float> {
+  typedef f32x4 acc_t;
+  typedef float4 vec_t;  // 16-byte global/LDS chunk
+  static constexpr int kVec = 4;
+  static __device__ __forceinline__ int row(int kq, int j) { return 4 * kq + j; }
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ vec_t zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+};
+template <> struct GramMfma<double> {
+  typedef f64x4 acc_t;
+  typedef double2 vec_t;
+  static constexpr int kVec = 2;
+  static __device__ __forceinline__ int row(int kq, int j) { return kq + 4 * j; }
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ vec_t zero() { return make_double2(0.0, 0.0); }
+};
+
+// 1/sqrt(x) for positive normal float64 x: the hardware estimate and NS
+// Newton steps (each squares the relative error).
+template <int NS>
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
+}
+
+// Rotation (cos, sin) that zeroes gamma of the pair with squared norms alpha,
+// beta; (1, 0) when |gamma| <= tol sqrt(alpha beta).  With tau = beta - alpha
+// and d = sqrt(tau^2 + 4 gamma^2): cos(2 theta) = |tau| / d, cos^2(theta) =
+// (1 + cos 2 theta) / 2 and sin(theta) = sign(tau) gamma / (d cos theta): the
+// rotation with |theta| <= pi/4.  Computed without branches.
+template <int NS>
+__device__ __forceinline__ double2 gram_rotation(double al, double be, double ga, double tol2) {
+  const bool on = ga * ga > tol2 * al * be;
+  const double g = on ? ga : 1.0;  // keeps the arithmetic finite when off
+  const double tau = be - al;
+  const double r = rsq_nr<NS>(fma(tau, tau, 4.0 * g * g));
+  const double h = fma(0.5 * fabs(tau), r, 0.5);
+  const double y = rsq_nr<NS>(h);
+  const double cs = h * y, sn = (tau >= 0.0 ? g : -g) * r * y;
+  return on ? make_double2(cs, sn) : make_double2(1.0, 0.0);
+}
+
+__device__ __forceinline__ void gram_pair(bool full, int r, int P, int& a, int& c) {
+  if (full) {
+    circle_pair(kG2, r, P, a, c);
+  } else {
+    a = P;
+    c = kGB + ((P + r) & (kGB - 1));
+  }
+}
+
+// Workgroup -> (face, block pair): workgroups are dealt to the XCDs in turn
+// (workgroup w runs on XCD w mod 8), so face f takes the workgroups of XCD
+// f mod 8 and its vectors stay in that XCD's L2 from launch to launch.
+constexpr int kXcds = 8;
+
+__host__ __device__ __forceinline__ int gram_grid(int nfaces, int npair) {
+  return kXcds * ((nfaces + kXcds - 1) / kXcds) * npair;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, const JFace* __restrict__ faces,
+                                                          int nfaces, int npair, int nv_u, int L_u, int round,
+                                                          int sweep, int max_sweeps, double tol,
+                                                          int* __restrict__ flags) {
+  typedef GramMfma<T> M;
+  typedef typename M::vec_t vec_t;
+  constexpr int VEC = M::kVec;
+  constexpr int NS = sizeof(T) == 8 ? 2 : 1;  // Newton steps of the angle math
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Gb = reinterpret_cast<double*>(smem_raw);  // G copies at Gb, Gb + kGMat
+  double* V = Gb + 2 * kGMat;
+  int* any_rot = reinterpret_cast<int*>(V + kGMat);
+  T* X = reinterpret_cast<T*>(smem_raw + kGramHead);
+
+  const int xcd = blockIdx.x % kXcds, m = blockIdx.x / kXcds;
+  const int f = xcd + kXcds * (m / npair), pair = m % npair;
+  if (f >= nfaces) return;
+  const JFace fd = face_of(faces, f, nv_u, L_u);
+  const int nv = fd.nv, L = fd.L;
+  int nb = (nv + kGB - 1) / kGB;
+  nb += nb & 1;
+  if (round >= nb - 1 || pair >= nb / 2) return;
+  if (sweep > 0 && flags[f * max_sweeps + sweep - 1] == 0) return;
+  const int Lp = (L + 15) & ~15;
+  const int ldx = gram_ldx<T>(L);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  int I, J;
+  circle_pair(nb, round, pair, I, J);
+  T* Wf = W + fd.off;
+  auto gvec = [&](int u) { return u < kGB ? I * kGB + u : J * kGB + (u - kGB); };
+
+  // stage the 32 vectors (wave w takes vectors w, w + 4, ...), zero past nv;
+  // each lane issues the loads of its 8 vectors before their LDS stores, with
+  // clamped addresses and out-of-range values masked
+  if (L % VEC == 0 && fd.off % VEC == 0) {
+    const int nq = L / VEC;
+    for (int q0 = 0; q0 < nq; q0 += 64) {
+      const int q = q0 + lane, qc = min(q, nq - 1);
+      vec_t buf[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int g = gvec(wave + 4 * i);
+        const vec_t v = *reinterpret_cast<const vec_t*>(Wf + (int64_t)min(g, nv - 1) * L + VEC * qc);
+        buf[i] = g < nv ? v : M::zero();
+      }
+      if (q < nq) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) *reinterpret_cast<vec_t*>(X + (wave + 4 * i) * ldx + VEC * q) = buf[i];
+      }
+    }
+  } else {
+    for (int e0 = 0; e0 < L; e0 += 64) {
+      const int e = e0 + lane, ec = min(e, L - 1);
+      T buf[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int g = gvec(wave + 4 * i);
+        const T v = Wf[(int64_t)min(g, nv - 1) * L + ec];
+        buf[i] = g < nv ? v : T(0);
+      }
+      if (e < L) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) X[(wave + 4 * i) * ldx + e] = buf[i];
+      }
+    }
+  }
+  if (Lp > L) {
+    for (int e = tid; e < kG2 * 16; e += 256) {
+      const int u = e >> 4, c = L + (e & 15);
+      if (c < Lp) X[u * ldx + c] = T(0);
+    }
+  }
+  for (int e = tid; e < kG2 * kG2; e += 256) V[(e >> 5) * kGld + (e & 31)] = ((e >> 5) == (e & 31)) ? 1.0 : 0.0;
+  if (tid == 0) *any_rot = 0;
+  __syncthreads();
+
+  // G = X^T X: wave 0 tile (0,0), wave 1 tile (0,1) (and its mirror), wave 3
+  // tile (1,1).  MFMA t of a 16-element chunk takes element 4 kq + t of the
+  // chunk from the lanes of k-group kq: the chunk's 16 elements in some order,
+  // the same for both operands.
+  if (wave != 2) {
+    const int ti = wave >> 1, tj = wave & 1;
+    const T* xa = X + (16 * ti + r16) * ldx + 4 * kq;
+    const T* xb = X + (16 * tj + r16) * ldx + 4 * kq;
+    typename M::acc_t acc = {0, 0, 0, 0};
+#pragma unroll 2
+    for (int s0 = 0; s0 < Lp; s0 += 16) {
+      T a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = xa[s0 + t];
+        b[t] = xb[s0 + t];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc = M::mma(a[t], b[t], acc);
+    }
+    // lane holds G[16 ti + row(kq, j)][16 tj + r16]
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 16 * ti + M::row(kq, j), col = 16 * tj + r16;
+      if (ti != tj || row <= col) {
+        const double v = (double)acc[j];
+        Gb[row * kGld + col] = v;
+        Gb[col * kGld + row] = v;
+      }
+    }
+  }
+  __syncthreads();
+
+  // does any pair of this visit need a rotation?
+  const bool full = round == 0;
+  const double tol2 = tol * tol;
+  {
+    bool need = false;
+    if (full) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = tid + 256 * k, i = e >> 5, c = e & 31;
+        if (i < c) {
+          const double g = Gb[i * kGld + c];
+          need |= g * g > tol2 * Gb[i * kGld + i] * Gb[c * kGld + c];
+        }
+      }
+    } else {
+      const int i = tid >> 4, c = kGB + (tid & 15);
+      const double g = Gb[i * kGld + c];
+      need = g * g > tol2 * Gb[i * kGld + i] * Gb[c * kGld + c];
+    }
+    if (need) *any_rot = 1;
+    __syncthreads();
+    if (*any_rot == 0) return;  // the block pair is converged: nothing to do
+  }
+  if (tid == 0) flags[f * max_sweeps + sweep] = 1;
+
+  // Rounds on G (float64).  Each round reads the current copy of G and writes
+  // every entry of the other, so one barrier per round suffices.  Thread
+  // (P, P2) (P2 = lane mod 16) computes the rotation of pair P2, takes pair
+  // P's from lane P of its wave, writes the 2x2 block of J^T G J between the
+  // two pairs when P <= P2 (and its transpose), and rows P2 and P2 + 16 of
+  // V J in the columns of pair P.
+  const int P = tid >> 4, P2 = tid & 15;
+  const int nrounds = full ? kG2 - 1 : kGB;
+  int cur = 0;
+  for (int r = 0; r < nrounds; ++r) {
+    const double* G = Gb + cur * kGMat;
+    double* Gn = Gb + (cur ^ 1) * kGMat;
+    int a1, c1, a2, c2;
+    gram_pair(full, r, P, a1, c1);
+    gram_pair(full, r, P2, a2, c2);
+    const double m00 = G[a1 * kGld + a2], m01 = G[a1 * kGld + c2];
+    const double m10 = G[c1 * kGld + a2], m11 = G[c1 * kGld + c2];
+    const double v0a = V[P2 * kGld + a1], v0c = V[P2 * kGld + c1];
+    const double v1a = V[(P2 + 16) * kGld + a1], v1c = V[(P2 + 16) * kGld + c1];
+    const double2 q2 = gram_rotation<NS>(G[a2 * kGld + a2], G[c2 * kGld + c2], G[a2 * kGld + c2], tol2);
+    const double2 q1 = make_double2(__shfl(q2.x, P), __shfl(q2.y, P));
+    if (P <= P2) {
+      const double t00 = q2.x * m00 - q2.y * m01, t01 = q2.y * m00 + q2.x * m01;
+      const double t10 = q2.x * m10 - q2.y * m11, t11 = q2.y * m10 + q2.x * m11;
+      const double g00 = q1.x * t00 - q1.y * t10, g11 = q1.y * t01 + q1.x * t11;
+      double g01 = q1.x * t01 - q1.y * t11, g10 = q1.y * t00 + q1.x * t10;
+      if (P == P2 && q1.y != 0.0) {  // the rotation annihilates its own off-diagonal entry
+        g01 = 0.0;
+        g10 = 0.0;
+      }
+      Gn[a1 * kGld + a2] = g00;
+      Gn[a1 * kGld + c2] = g01;
+      Gn[c1 * kGld + a2] = g10;
+      Gn[c1 * kGld + c2] = g11;
+      Gn[a2 * kGld + a1] = g00;
+      Gn[c2 * kGld + a1] = g01;
+      Gn[a2 * kGld + c1] = g10;
+      Gn[c2 * kGld + c1] = g11;
+    }
+    V[P2 * kGld + a1] = q1.x * v0a - q1.y * v0c;
+    V[P2 * kGld + c1] = q1.y * v0a + q1.x * v0c;
+    V[(P2 + 16) * kGld + a1] = q1.x * v1a - q1.y * v1c;
+    V[(P2 + 16) * kGld + c1] = q1.y * v1a + q1.x * v1c;
+    cur ^= 1;
+    __syncthreads();
+  }
+
+  // X <- X V: D[c][e] = sum_a V[a][c] X[a][e]; wave w takes the 16-element
+  // column tiles te = w, w + 4, ... and both row tiles tc of each.
+  T va[2][8];
+#pragma unroll
+  for (int tc = 0; tc < 2; ++tc)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) va[tc][s] = (T)V[(4 * s + kq) * kGld + 16 * tc + r16];
+  for (int te = wave; te < (Lp >> 4); te += 4) {
+    T xb[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) xb[s] = X[(4 * s + kq) * ldx + 16 * te + r16];
+    const int e = 16 * te + r16;
+#pragma unroll
+    for (int tc = 0; tc < 2; ++tc) {
+      typename M::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) acc = M::mma(va[tc][s], xb[s], acc);
+      if (e < L) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int g = gvec(16 * tc + M::row(kq, j));
+          if (g < nv) Wf[(int64_t)g * L + e] = acc[j];
+        }
+      }
+    }
+  }
+}
+
 __global__ void zero_ints_kernel(int* __restrict__ x, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = 0;
@@ -543,6 +877,11 @@ __global__ void info_kernel(const int* __restrict__ used1, const int* __restrict
 
 constexpr size_t kLdsCap = 131072;
 
+template <typename T>
+constexpr const char* block_name() {
+  return sizeof(T) == 8 ? "jacobi_block_f64" : "jacobi_block_f32";
+}
+
 template <typename T, int R>
 hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, double tol, int* used,
                         int* flags, hipStream_t s) {
@@ -559,20 +898,84 @@ hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, doub
   }
   const dim3 block((unsigned)(64 * nw));
   if (nb == 2) {
+    ProfScope prof(block_name<T>(), s);
     jacobi_block_kernel<T, R><<<dim3(1, p), block, lds, s>>>(W, nv, L, nb, 0, 0, max_sweeps, tol, flags,
                                                               used);
     return hipGetLastError();
   }
   const int nflags = p * max_sweeps;
-  zero_ints_kernel<<<(nflags + 255) / 256, 256, 0, s>>>(flags, nflags);
+  {
+    ProfScope prof("jacobi_flags", s);
+    zero_ints_kernel<<<(nflags + 255) / 256, 256, 0, s>>>(flags, nflags);
+  }
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int round = 0; round < nb - 1; ++round) {
+      ProfScope prof(block_name<T>(), s);
       jacobi_block_kernel<T, R><<<dim3(nb / 2, p), block, lds, s>>>(W, nv, L, nb, round, sw, max_sweeps,
                                                                      tol, flags, used);
     }
   }
-  count_sweeps_kernel<<<(p + 63) / 64, 64, 0, s>>>(flags, p, max_sweeps, used);
+  {
+    ProfScope prof("jacobi_flags", s);
+    count_sweeps_kernel<<<(p + 63) / 64, 64, 0, s>>>(flags, p, max_sweeps, used);
+  }
   return hipGetLastError();
+}
+
+// Sweeps in the Gram form: max_sweeps x (nb - 1) launches; a face whose
+// sweep rotated nothing is skipped by the later launches.
+// The dynamic LDS the kernel may use: the largest of 160, 128 and 64 KiB
+// that the device accepts (set once per process).
+template <typename T>
+size_t gram_lds_cap() {
+  static size_t cap = 0;
+  if (cap == 0) {
+    for (size_t c : {(size_t)160 * 1024, (size_t)128 * 1024, (size_t)64 * 1024}) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_gram_kernel<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)c) == hipSuccess) {
+        cap = c;
+        break;
+      }
+      (void)hipGetLastError();  // clear the refused request
+    }
+  }
+  return cap;
+}
+
+template <typename T>
+bool gram_fits(int L) {
+  return gram_lds_bytes<T>(L) <= gram_lds_cap<T>();
+}
+
+template <typename T>
+hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max,
+                       int max_sweeps, double tol, int* used, int* flags, hipStream_t s) {
+  const size_t lds = gram_lds_bytes<T>(L_max);
+  const int nflags = nfaces * max_sweeps;
+  {
+    ProfScope prof("jacobi_flags", s);
+    zero_ints_kernel<<<(nflags + 255) / 256, 256, 0, s>>>(flags, nflags);
+  }
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    for (int round = 0; round < nb_max - 1; ++round) {
+      ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s);
+      jacobi_gram_kernel<T><<<(unsigned)gram_grid(nfaces, nb_max / 2), 256, lds, s>>>(
+          W, faces, nfaces, nb_max / 2, nv_u, L_u, round, sw, max_sweeps, tol, flags);
+    }
+  }
+  {
+    ProfScope prof("jacobi_flags", s);
+    count_sweeps_kernel<<<(nfaces + 63) / 64, 64, 0, s>>>(flags, nfaces, max_sweeps, used);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gram_sweeps_uniform(T* W, int p, int nv, int L, int max_sweeps, double tol, int* used, int* flags,
+                               hipStream_t s) {
+  int nb = (nv + kGB - 1) / kGB;
+  nb += nb & 1;
+  return gram_sweeps<T>(W, nullptr, p, nv, L, nb, L, max_sweeps, tol, used, flags, s);
 }
 
 // waves per workgroup (4 vectors of a block each): blocks of 16 vectors, fewer
@@ -607,6 +1010,7 @@ hipError_t sweeps(T* W, int p, int nv, int L, int max_sweeps, double tol, int* u
       default: return block_sweeps<T, 16>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
     }
   }
+  ProfScope prof(sizeof(T) == 8 ? "jacobi_global_f64" : "jacobi_global_f32", s);
   jacobi_global_kernel<T><<<p, kJacobiThreads, 0, s>>>(W, nv, L, max_sweeps, tol, used);
   return hipGetLastError();
 }
@@ -658,10 +1062,16 @@ hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, h
 }
 hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                              int* flags, hipStream_t s) {
+  if (gram_fits<float>(L)) return gram_sweeps_uniform<float>(W, p, nv, L, max_sweeps, tol, used, flags, s);
   return sweeps<float>(W, p, nv, L, max_sweeps, tol, used, flags, s);
 }
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                              int* flags, hipStream_t s) {
+  return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
+}
+hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
+                                  int* flags, hipStream_t s) {
+  if (gram_fits<double>(L)) return gram_sweeps_uniform<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
   return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
 }
 hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k, double* F, hipStream_t s) {
