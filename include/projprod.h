@@ -256,6 +256,59 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q,
              double tol, int max_sweeps, int* info_dev,
              void* ws, size_t ws_bytes, hipStream_t stream);
 
+
+/* ---- batched form: many uneven instances in one captured graph ----------- */
+/*
+ * Instance i of a batch (all float32, face-major, device pointers owned by
+ * the caller): A (n1 x n2 x n3), Q (n3 x p, row-major, orthonormal columns,
+ * p <= n3), and
+ *   - the projected product C = A *_Q B (Def. 3.1) with B (n2 x n4 x n3) and
+ *     C (n1 x n4 x n3): B and C both given, or both NULL;
+ *   - the truncated tSVDQ of A with rank k per face (Alg. 4.1 steps 2-3, the
+ *     same outputs and layout as pq_tsvdq): Uhat (n1 x k x p), s (k x p),
+ *     Vhat (n2 x k x p) all given, or all NULL; 1 <= k <= min(n1, n2) and
+ *     max(n1, n2) <= 512 (PQ_ERR_UNSUPPORTED otherwise).
+ * An instance must ask for at least one of the two.
+ */
+typedef struct {
+  int64_t n1, n2, n3, n4, p, k;
+  const void* A;
+  const void* B;
+  const void* Q;
+  void* C;
+  void* Uhat;
+  void* s;
+  void* Vhat;
+} pq_instance;
+
+typedef struct pq_batch_s* pq_batch;
+
+/* Workspace bytes for a batch of count instances (validates them). */
+int pq_batched_workspace(const pq_instance* inst, int count, size_t* bytes);
+
+/*
+ * Plans a batch: copies the face table into ws, runs every instance once on
+ * `stream` (the outputs of this run are valid; while pq_autotune_enable(1)
+ * is in force, launch shapes not yet in the autotuner's table are tuned
+ * here), then captures the same launch sequence into a hipGraph on a private
+ * stream and instantiates it.  Synchronises `stream`; allocates host memory
+ * for the handle only.  The transforms, facewise products and
+ * back-projections run per instance; the Jacobi sweeps of all tSVDQ
+ * instances run as grouped launches over every face at once.  max_sweeps
+ * (<= 0: 20) and tol (<= 0: 1e-13) as in pq_tsvdq; info_dev (device int[3],
+ * may be NULL) receives the sweep statistics over all faces, as in pq_tsvdq.
+ * Every pointer of inst[] and ws is baked into the graph: they must stay
+ * valid until pq_batched_destroy, and each run reads and writes them again.
+ */
+int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double tol, int* info_dev,
+                    void* ws, size_t ws_bytes, hipStream_t stream, pq_batch* out);
+
+/* Replays the planned batch on `stream` (one hipGraphLaunch; asynchronous). */
+int pq_batched_run(pq_batch batch, hipStream_t stream);
+
+/* Frees the graph and the handle (host call; no replay may be in flight). */
+int pq_batched_destroy(pq_batch batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,7 +45,20 @@ SIGNATURES = {
     "pq_tsvdq_workspace": (_sz, [_i64, _i64, _i64, _i64, _i64, _i32]),
     "pq_tsvdq": (_i32, [_vp, _i32, _vp, _i64, _i64, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _vp,
                         _vp, _vp, _vp, _dbl, _i32, _vp, _vp, _sz, _vp]),
+    "pq_batched_workspace": (_i32, [_vp, _i32, _vp]),
+    "pq_batched_plan": (_i32, [_vp, _i32, _i32, _dbl, _vp, _vp, _sz, _vp, _vp]),
+    "pq_batched_run": (_i32, [_vp, _vp]),
+    "pq_batched_destroy": (_i32, [_vp]),
 }
+
+
+class PQInstance(ctypes.Structure):
+    """pq_instance of include/projprod.h."""
+    _fields_ = [("n1", ctypes.c_int64), ("n2", ctypes.c_int64), ("n3", ctypes.c_int64),
+                ("n4", ctypes.c_int64), ("p", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("Q", ctypes.c_void_p),
+                ("C", ctypes.c_void_p), ("Uhat", ctypes.c_void_p), ("s", ctypes.c_void_p),
+                ("Vhat", ctypes.c_void_p)]
 
 _lib = None
 

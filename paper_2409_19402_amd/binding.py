@@ -21,6 +21,7 @@ __all__ = [
     "empty", "from_storage", "is_face_major", "autotune", "autotune_save", "autotune_load",
     "check_q", "hat", "unhat", "proj", "facewise",
     "qprod", "qprod_backward", "proj_backward", "tsvdq", "TSVDQ", "QProd", "Proj",
+    "Batch", "batched",
 ]
 
 _DT = {torch.float32: PQ_F32, torch.float64: PQ_F64, torch.bfloat16: PQ_BF16}
@@ -312,3 +313,87 @@ def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_swe
          _ptr(s), _ptr(Vh), _ptr(Uk), _ptr(Sk), _ptr(Vk), _ptr(Ak), float(tol), int(max_sweeps),
          _ptr(info), _ptr(wsb), nb, _stream(dev))
     return TSVDQ(Uh, s.t(), Vh, Uk, None if Sk is None else Sk.t(), Vk, Ak, info)
+
+
+class Batch:
+    """A planned batch of uneven instances (pq_batched_plan).
+
+    ``outputs[i]`` holds instance i's results: ``C`` (A *_Q B, when B was
+    given) and ``Uhat``, ``s`` (k, p), ``Vhat`` (when k was given).  The plan
+    already ran the batch once; ``run()`` replays the captured graph on the
+    current stream, reading the same input tensors (update them in place) and
+    writing the same output tensors.  ``info`` is the int32 device tensor of
+    sweep statistics over every face, as in tsvdq."""
+
+    def __init__(self, instances, max_sweeps=0, tol=0.0):
+        lib = _lib.load()
+        self._keep = []
+        self.outputs = []
+        arr = (_lib.PQInstance * len(instances))()
+        dev = None
+        for i, inst in enumerate(instances):
+            A, Q = inst["A"], inst["Q"]
+            _tensor(A, "A", (torch.float32,))
+            _q(Q, torch.float32)
+            dev = A.device
+            n1, n2, n3 = A.shape
+            if Q.shape[0] != n3:
+                raise ValueError("Q must have n3 rows")
+            p = Q.shape[1]
+            out = {}
+            x = arr[i]
+            x.n1, x.n2, x.n3, x.p = n1, n2, n3, p
+            x.A, x.Q = _ptr(A), _ptr(Q)
+            self._keep += [A, Q]
+            B = inst.get("B")
+            if B is not None:
+                _tensor(B, "B", (torch.float32,))
+                if B.shape[0] != n2 or B.shape[2] != n3:
+                    raise ValueError("B must be n2 x n4 x n3")
+                n4 = B.shape[1]
+                C = empty(n1, n4, n3, torch.float32, dev)
+                x.n4, x.B, x.C = n4, _ptr(B), _ptr(C)
+                out["C"] = C
+                self._keep += [B, C]
+            k = inst.get("k")
+            if k is not None:
+                Uh = empty(n1, k, p, torch.float32, dev)
+                Vh = empty(n2, k, p, torch.float32, dev)
+                s = torch.empty((p, k), dtype=torch.float32, device=dev)
+                x.k, x.Uhat, x.s, x.Vhat = k, _ptr(Uh), _ptr(s), _ptr(Vh)
+                out.update(Uhat=Uh, s=s.t(), Vhat=Vh)
+                self._keep += [Uh, Vh, s]
+            self.outputs.append(out)
+        nbytes = _lib.ctypes.c_size_t()
+        call("pq_batched_workspace", _lib.ctypes.byref(arr), len(instances), _lib.ctypes.byref(nbytes))
+        self._ws, nb = _ws(nbytes.value, dev)
+        self.info = torch.zeros(3, dtype=torch.int32, device=dev)
+        self._arr = arr
+        h = _lib.ctypes.c_void_p()
+        call("pq_batched_plan", _lib.ctypes.byref(arr), len(instances), int(max_sweeps), float(tol),
+             _ptr(self.info), _ptr(self._ws), nb, _stream(dev), _lib.ctypes.byref(h))
+        self._h = h
+        self._dev = dev
+        self.workspace_bytes = nb
+
+    def run(self):
+        call("pq_batched_run", self._h, _stream(self._dev))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self._dev)
+            _lib.load().pq_batched_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown
+            pass
+
+
+def batched(instances, max_sweeps=0, tol=0.0):
+    """Plan (and run once) a batch: ``instances`` is a list of dicts with
+    "A" (n1 x n2 x n3), "Q" (n3 x p), optionally "B" (n2 x n4 x n3) for
+    A *_Q B and "k" for the rank-k tSVDQ of A.  Returns a Batch."""
+    return Batch(instances, max_sweeps, tol)

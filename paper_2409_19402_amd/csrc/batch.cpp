@@ -1,0 +1,276 @@
+// The batched form: many independent instances of uneven sizes (A_i *_Q_i B_i
+// and the truncated tSVDQ of A_i, Def. 3.1 and Alg. 4.1) in one captured
+// graph.  The transforms, facewise products and back-projections of each
+// instance are launched per instance (each with the autotuner's choice for
+// its shape); the Jacobi sweeps, which dominate, run as grouped launches over
+// the faces of every instance at once (a device table of face offsets and
+// sizes); the per-face finishing steps run per instance again.  The plan call
+// runs the whole batch once eagerly (the outputs of that run are valid; new
+// launch shapes are tuned there while tuning is on), then captures the same
+// launch sequence on a private stream into a hipGraph; pq_batched_run replays
+// it with one hipGraphLaunch.
+#include <algorithm>
+#include <cstdint>
+#include <new>
+#include <vector>
+
+#include "../../include/projprod.h"
+#include "internal.hpp"
+
+struct pq_batch_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr int kMaxSweepsCap = 100;
+constexpr int kDefaultSweeps = 20;
+constexpr double kCoarseTol = 1e-5;
+constexpr int kPolishSweeps = 8;
+constexpr double kTolFloor = 1e-10;
+constexpr double kDefaultTol = 1e-13;
+constexpr int64_t kMaxLen = 512;  // longest Jacobi vector of a batched tSVDQ face
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? PQ_OK : PQ_ERR_HIP; }
+
+#define BQ_TRY(expr)                         \
+  do {                                       \
+    int _rc = hip_rc(expr);                  \
+    if (_rc != PQ_OK) return _rc;            \
+  } while (0)
+#define BQ_CHECK(expr)                       \
+  do {                                       \
+    int _rc = (expr);                        \
+    if (_rc != PQ_OK) return _rc;            \
+  } while (0)
+
+bool has_svd(const pq_instance& x) { return x.Uhat != nullptr; }
+
+// Workspace layout of a batch (byte offsets into the caller's workspace).
+struct Layout {
+  size_t faces = 0;            // JFace table (device)
+  size_t qws = 0, qws_bytes = 0;  // pq_qprod workspace, shared by the instances in turn
+  std::vector<size_t> ah;      // per instance: Ah (float32, n1 x n2 x p)
+  std::vector<int64_t> woff;   // per instance: element offset of its faces in W32 / W64
+  std::vector<int> face0;      // per instance: index of its first face
+  size_t w32 = 0, w64 = 0, used1 = 0, used2 = 0, flags = 0;
+  std::vector<size_t> ft, y, ys;  // per instance finishing buffers
+  size_t total = 0;
+  int nfaces = 0, nb_max = 2, L_max = 1;
+  int64_t welems = 0;
+};
+
+int validate(const pq_instance* inst, int count) {
+  if (!inst) return PQ_ERR_NULL;
+  if (count < 1) return PQ_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!x.A || !x.Q) return PQ_ERR_NULL;
+    for (int64_t d : {x.n1, x.n2, x.n3, x.p})
+      if (d < 1) return PQ_ERR_SHAPE;
+    if (x.p > x.n3) return PQ_ERR_P;
+    if (x.p > 512 || x.n1 * x.n2 >= ((int64_t)1 << 31)) return PQ_ERR_UNSUPPORTED;
+    if ((x.B == nullptr) != (x.C == nullptr)) return PQ_ERR_NULL;
+    if (x.B && x.n4 < 1) return PQ_ERR_SHAPE;
+    if (x.B && x.n1 * x.n4 >= ((int64_t)1 << 31)) return PQ_ERR_UNSUPPORTED;
+    const bool svd = has_svd(x);
+    if (svd != (x.s != nullptr) || svd != (x.Vhat != nullptr)) return PQ_ERR_NULL;
+    if (!x.B && !svd) return PQ_ERR_ARG;  // nothing to compute
+    if (svd) {
+      if (x.k < 1 || x.k > std::min(x.n1, x.n2)) return PQ_ERR_K;
+      if (std::max(x.n1, x.n2) > kMaxLen) return PQ_ERR_UNSUPPORTED;
+    }
+    for (const void* o : {(const void*)x.C, (const void*)x.Uhat, (const void*)x.s, (const void*)x.Vhat})
+      if (o && (o == x.A || o == x.B || o == x.Q)) return PQ_ERR_ALIAS;
+  }
+  return PQ_OK;
+}
+
+Layout layout(const pq_instance* inst, int count) {
+  Layout lo;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  lo.ah.resize(count);
+  lo.woff.assign(count, 0);
+  lo.face0.assign(count, 0);
+  lo.ft.assign(count, 0);
+  lo.y.assign(count, 0);
+  lo.ys.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (x.B)
+      lo.qws_bytes = std::max(lo.qws_bytes, pq_qprod_workspace(x.n1, x.n2, x.n4, x.n3, x.p, PQ_F32));
+    if (has_svd(x)) {
+      lo.face0[i] = lo.nfaces;
+      lo.woff[i] = lo.welems;
+      lo.nfaces += (int)x.p;
+      lo.welems += x.n1 * x.n2 * x.p;
+      const int nv = (int)std::min(x.n1, x.n2);
+      int nb = (nv + 15) / 16;
+      nb += nb & 1;
+      lo.nb_max = std::max(lo.nb_max, nb);
+      lo.L_max = std::max(lo.L_max, (int)std::max(x.n1, x.n2));
+    }
+  }
+  lo.faces = take(sizeof(pq::JFace) * std::max(1, lo.nfaces));
+  lo.qws = take(std::max<size_t>(lo.qws_bytes, 1));
+  for (int i = 0; i < count; ++i) lo.ah[i] = take(4 * (size_t)inst[i].n1 * inst[i].n2 * inst[i].p);
+  lo.w32 = take(4 * (size_t)std::max<int64_t>(lo.welems, 1));
+  lo.w64 = take(8 * (size_t)std::max<int64_t>(lo.welems, 1));
+  lo.used1 = take(sizeof(int) * std::max(1, lo.nfaces));
+  lo.used2 = take(sizeof(int) * std::max(1, lo.nfaces));
+  lo.flags = take(sizeof(int) * (size_t)std::max(1, lo.nfaces) * kMaxSweepsCap);
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!has_svd(x)) continue;
+    const size_t mx = std::max(x.n1, x.n2), mn = std::min(x.n1, x.n2);
+    lo.ft[i] = take(8 * mx * x.k * x.p);
+    lo.y[i] = take(8 * mn * x.k * x.p);
+    lo.ys[i] = take(4 * mn * x.k * x.p);
+  }
+  lo.total = off;
+  return lo;
+}
+
+// Enqueue every launch of the batch on s.
+int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps, double tol, int* info_dev,
+            char* ws, hipStream_t s) {
+  float* W32 = reinterpret_cast<float*>(ws + lo.w32);
+  double* W64 = reinterpret_cast<double*>(ws + lo.w64);
+  int* used1 = reinterpret_cast<int*>(ws + lo.used1);
+  int* used2 = reinterpret_cast<int*>(ws + lo.used2);
+  int* flags = reinterpret_cast<int*>(ws + lo.flags);
+  const pq::JFace* faces = reinterpret_cast<const pq::JFace*>(ws + lo.faces);
+  // transforms, facewise products and back-projections
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    void* Ah = ws + lo.ah[i];
+    if (x.B) {
+      BQ_CHECK(pq_qprod(x.A, x.B, PQ_F32, x.Q, x.C, x.n1, x.n2, x.n4, x.n3, x.p, PQ_PREC_DEFAULT, Ah, nullptr,
+                        ws + lo.qws, lo.qws_bytes, s));
+    } else {
+      BQ_CHECK(pq_hat(x.A, PQ_F32, x.Q, Ah, x.n1, x.n2, x.n3, x.p, PQ_PREC_DEFAULT, s));
+    }
+  }
+  if (lo.nfaces == 0) return PQ_OK;
+  // Jacobi vectors of every face, then the grouped sweeps
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!has_svd(x)) continue;
+    BQ_TRY(pq::jacobi_prep_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), W32 + lo.woff[i], (int)x.n1,
+                               (int)x.n2, (int)x.p, s));
+  }
+  BQ_TRY(pq::jacobi_gram_grouped_f32(W32, faces, lo.nfaces, lo.nb_max, lo.L_max, max_sweeps, kCoarseTol, used1,
+                                     flags, s));
+  BQ_TRY(pq::jacobi_widen(W32, W64, lo.welems, s));
+  const int polish = std::min(max_sweeps, kPolishSweeps);
+  BQ_TRY(pq::jacobi_gram_grouped_f64(W64, faces, lo.nfaces, lo.nb_max, lo.L_max, polish,
+                                     std::max(tol, kTolFloor), used2, flags, s));
+  // per-instance finishing: top-k vectors, the other factor, orthonormal refinement
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!has_svd(x)) continue;
+    const bool cols = x.n1 >= x.n2;
+    const int nv = (int)std::min(x.n1, x.n2), L = (int)std::max(x.n1, x.n2);
+    const int ip = (int)x.p, ik = (int)x.k;
+    double* Ft = reinterpret_cast<double*>(ws + lo.ft[i]);
+    double* Y = reinterpret_cast<double*>(ws + lo.y[i]);
+    float* Ys = reinterpret_cast<float*>(ws + lo.ys[i]);
+    float* Fo = static_cast<float*>(cols ? x.Uhat : x.Vhat);
+    float* Other = static_cast<float*>(cols ? x.Vhat : x.Uhat);
+    BQ_TRY(pq::jacobi_finalize_f64(W64 + lo.woff[i], ip, nv, L, ik, Ft, s));
+    BQ_TRY(pq::jacobi_factor_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), Ft, Y, (int)x.n1, (int)x.n2, ik,
+                                 ip, cols, s));
+    BQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, tol, static_cast<float*>(x.s), Other, Fo, Ys, s));
+  }
+  if (info_dev) BQ_TRY(pq::jacobi_info(used1, used2, lo.nfaces, max_sweeps, polish, info_dev, s));
+  return PQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pq_batched_workspace(const pq_instance* inst, int count, size_t* bytes) {
+  if (!bytes) return PQ_ERR_NULL;
+  BQ_CHECK(validate(inst, count));
+  *bytes = layout(inst, count).total;
+  return PQ_OK;
+}
+
+int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double tol, int* info_dev, void* ws,
+                    size_t ws_bytes, hipStream_t stream, pq_batch* out) {
+  if (!out || !ws) return PQ_ERR_NULL;
+  *out = nullptr;
+  BQ_CHECK(validate(inst, count));
+  if (max_sweeps <= 0) max_sweeps = kDefaultSweeps;
+  if (max_sweeps > kMaxSweepsCap) return PQ_ERR_ARG;
+  if (tol <= 0.0) tol = kDefaultTol;
+  const Layout lo = layout(inst, count);
+  if (ws_bytes < lo.total) return PQ_ERR_WORKSPACE;
+  if (lo.nfaces > 0 && lo.L_max > pq::jacobi_gram_max_len(true)) return PQ_ERR_UNSUPPORTED;
+  char* w = static_cast<char*>(ws);
+  // the face table: every face of every tSVDQ instance, in order
+  std::vector<pq::JFace> tab;
+  tab.reserve(lo.nfaces);
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!has_svd(x)) continue;
+    const int nv = (int)std::min(x.n1, x.n2), L = (int)std::max(x.n1, x.n2);
+    for (int64_t l = 0; l < x.p; ++l) tab.push_back(pq::JFace{lo.woff[i] + l * nv * L, nv, L});
+  }
+  BQ_TRY(hipStreamSynchronize(stream));
+  if (!tab.empty())
+    BQ_TRY(hipMemcpy(w + lo.faces, tab.data(), sizeof(pq::JFace) * tab.size(), hipMemcpyHostToDevice));
+  // one eager pass (valid outputs; tunes new launch shapes while tuning is on)
+  BQ_CHECK(enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, stream));
+  BQ_TRY(hipStreamSynchronize(stream));
+  // capture the same launches on a private stream
+  hipStream_t cs = nullptr;
+  BQ_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  pq_batch_s* b = new (std::nothrow) pq_batch_s;
+  if (!b) {
+    hipStreamDestroy(cs);
+    return PQ_ERR_ARG;
+  }
+  int rc = hip_rc(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  if (rc == PQ_OK) {
+    const int erc = enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, cs);
+    hipGraph_t g = nullptr;
+    const int crc = hip_rc(hipStreamEndCapture(cs, &g));
+    rc = erc != PQ_OK ? erc : crc;
+    b->graph = g;
+    if (rc == PQ_OK) rc = hip_rc(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  hipStreamDestroy(cs);
+  if (rc != PQ_OK) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return PQ_OK;
+}
+
+int pq_batched_run(pq_batch batch, hipStream_t stream) {
+  if (!batch || !batch->exec) return PQ_ERR_NULL;
+  return hip_rc(hipGraphLaunch(batch->exec, stream));
+}
+
+int pq_batched_destroy(pq_batch batch) {
+  if (!batch) return PQ_ERR_NULL;
+  if (batch->exec) hipGraphExecDestroy(batch->exec);
+  if (batch->graph) hipGraphDestroy(batch->graph);
+  delete batch;
+  return PQ_OK;
+}
+
+}  // extern "C"

@@ -292,11 +292,6 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_global_kernel(T* __rest
 // A face table (nullable) gives every face its own offset, vector count and
 // length; without one, face f is the f-th block of nv x L elements.
 
-struct JFace {
-  int64_t off;  // element offset of the face's first vector in W
-  int nv, L;
-};
-
 constexpr int kGB = 16;        // vectors per block
 constexpr int kG2 = 2 * kGB;   // vectors per block pair = Gram order
 constexpr int kGld = kG2 + 1;  // row stride of G and V in LDS (doubles): no bank conflicts on columns
@@ -1068,6 +1063,21 @@ hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, dou
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                              int* flags, hipStream_t s) {
   return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
+}
+int jacobi_gram_max_len(bool f64) {
+  const size_t cap = f64 ? gram_lds_cap<double>() : gram_lds_cap<float>();
+  const size_t per = sizeof(float) * (f64 ? 2 : 1) * kG2;
+  if (cap <= kGramHead) return 0;
+  const int ldx = (int)((cap - kGramHead) / per);
+  return ((ldx - 4) & ~15);  // largest L whose padded rows fit
+}
+hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
+                                   int max_sweeps, double tol, int* used, int* flags, hipStream_t s) {
+  return gram_sweeps<float>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, used, flags, s);
+}
+hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
+                                   int max_sweeps, double tol, int* used, int* flags, hipStream_t s) {
+  return gram_sweeps<double>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, used, flags, s);
 }
 hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                                   int* flags, hipStream_t s) {

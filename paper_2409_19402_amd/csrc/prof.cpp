@@ -1,6 +1,6 @@
 // Per-launch timing behind pq_profile_*: while enabled, every launch the
 // library makes inside a ProfScope is bracketed by two hipEvents recorded on
-// the caller's stream.  Events come from a pool that grows on demand and is
+// the caller's stream (not while that stream is being captured into a graph).  Events come from a pool that grows on demand and is
 // reused after a reset.
 #include <cstring>
 #include <mutex>
@@ -36,6 +36,8 @@ hipEvent_t take_event() {
 ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
   std::lock_guard<std::mutex> g(g_mu);
   if (!g_on) return;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;  // no events inside a captured graph
+  if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return;
   a_ = take_event();
   if (a_) hipEventRecord(a_, s_);
 }

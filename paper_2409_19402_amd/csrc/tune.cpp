@@ -4,9 +4,10 @@
 // no entry times every candidate on the caller's stream (one warm-up launch,
 // then three timed launches between hipEvents; this synchronises) and records
 // the fastest (with PQ_TUNE_TRACE set in the environment each candidate's
-// time is printed to stderr).  Otherwise the recorded choice, or the site's
-// default, is used without any synchronisation.  The table can be saved to and loaded from a
-// text file of "key choice" lines.
+// time is printed to stderr).  Otherwise, and always while the stream is
+// being captured into a graph, the recorded choice or the site's default is
+// used without any synchronisation.  The table can be saved to and loaded
+// from a text file of "key choice" lines.
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -70,6 +71,10 @@ hipError_t tuned_launch(const std::string& key, int ncand, int dflt, hipStream_t
     auto it = table().find(key);
     if (it != table().end() && it->second >= 0 && it->second < ncand) choice = it->second;
     else tune = g_on && ncand > 1;
+  }
+  if (tune) {  // timing synchronises: never while the stream is being captured into a graph
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) tune = false;
   }
   if (choice < 0 && tune) {
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -85,3 +85,41 @@ def test_workspace_queries_monotone():
     assert lib.pq_proj_workspace(100, 100, 64, 16, 0) == 0   # fused, one pass
     assert lib.pq_proj_workspace(100, 100, 64, 40, 0) > 0
     assert lib.pq_tsvdq_workspace(240, 320, 200, 20, 10, 0) > 2 * 240 * 320 * 20 * 4
+
+
+def _instances(specs):
+    arr = (_lib.PQInstance * len(specs))()
+    for i, (n1, n2, n3, n4, p, k) in enumerate(specs):
+        x = arr[i]
+        x.n1, x.n2, x.n3, x.n4, x.p, x.k = n1, n2, n3, n4, p, k
+        x.A, x.Q = 0x1000 * (i + 1), 0x100000 * (i + 1)
+        if n4:
+            x.B, x.C = 0x2000000 + i, 0x3000000 + i
+        if k:
+            x.Uhat, x.s, x.Vhat = 0x4000000 + i, 0x5000000 + i, 0x6000000 + i
+    return arr
+
+
+def test_batched_validation():
+    lib = _lib.load()
+    nb = ctypes.c_size_t()
+    good = _instances([(64, 80, 32, 70, 8, 4), (100, 50, 20, 0, 5, 2)])
+    assert lib.pq_batched_workspace(ctypes.byref(good), 2, ctypes.byref(nb)) == 0
+    assert nb.value > 0
+    one = ctypes.c_size_t()
+    assert lib.pq_batched_workspace(ctypes.byref(good), 1, ctypes.byref(one)) == 0
+    assert 0 < one.value < nb.value
+    assert lib.pq_batched_workspace(None, 2, ctypes.byref(nb)) == -1
+    assert lib.pq_batched_workspace(ctypes.byref(good), 0, ctypes.byref(nb)) == -11
+    assert lib.pq_batched_workspace(_instances([(100, 50, 20, 0, 5, 60)]), 1, ctypes.byref(nb)) == -4
+    assert lib.pq_batched_workspace(_instances([(100, 50, 20, 0, 25, 2)]), 1, ctypes.byref(nb)) == -3
+    assert lib.pq_batched_workspace(_instances([(600, 50, 20, 0, 5, 2)]), 1, ctypes.byref(nb)) == -10
+    assert lib.pq_batched_workspace(_instances([(60, 50, 20, 0, 5, 0)]), 1, ctypes.byref(nb)) == -11
+    half = _instances([(64, 80, 32, 70, 8, 4)])
+    half[0].C = None  # B without C
+    assert lib.pq_batched_workspace(ctypes.byref(half), 1, ctypes.byref(nb)) == -1
+    # planning validates before touching the device
+    h = ctypes.c_void_p()
+    assert lib.pq_batched_plan(ctypes.byref(good), 2, 0, 0.0, None, None, 0, None, ctypes.byref(h)) == -1
+    assert lib.pq_batched_run(None, None) == -1
+    assert lib.pq_batched_destroy(None) == -1
