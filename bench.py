@@ -41,6 +41,15 @@ TRAFFIC_BYTES = {}
 METRIC = "\u22c6_Q/tSVDQ GFLOP/s + % roofline, BF16-comp & batched vs FP32 at rel err\u22641e-5"
 
 
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info()
+                    if d.get("user_api") == "blas"] or [1])
+    except Exception:  # threadpoolctl missing
+        return os.cpu_count()
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -52,7 +61,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="video",
                     choices=["video", "hyper", "diff", "tiny", "copy", "hat-video", "hat-hyper",
-                             "proj-video", "qprod"])
+                             "proj-video", "qprod", "batched"])
+    ap.add_argument("--count", type=int, default=64, help="instances of the batched workload")
     ap.add_argument("--prec", default="default")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU-oracle baseline sample")
@@ -73,6 +83,20 @@ def svd_nominal_flops(n1, n2, p):
     return p * (6.0 * mx * mn * mn + 20.0 * mn ** 3)
 
 
+JACOBI_KERNELS = ("jacobi_gram_f32", "jacobi_gram_f64", "jacobi_block_f32", "jacobi_block_f64",
+                  "jacobi_global_f32", "jacobi_global_f64")
+
+
+def jacobi_models(svd_flops):
+    """Roofline models of the Jacobi sweep kernels: the nominal SVD work of a
+    step spread evenly over that step's sweep launches (float32 coarse and
+    float64 polishing sweeps), against the float64 vector peak."""
+    def share(kernels, steps):
+        n = sum(kernels.get(nm, {}).get("launches", 0) for nm in JACOBI_KERNELS)
+        return svd_flops * steps / n if n else None
+    return {nm: ("alu", share) for nm in JACOBI_KERNELS}
+
+
 def workload_tsvdq(pq, torch, A_dev, Q_dev, k, a_bytes, name, prec):
     n1, n2, n3 = A_dev.shape
     p = Q_dev.shape[1]
@@ -87,22 +111,11 @@ def workload_tsvdq(pq, torch, A_dev, Q_dev, k, a_bytes, name, prec):
              + 2.0 * N * k * p * 2                    # factor + approximation products
              + 2.0 * N * n3 * p                       # A_k back to the spatial domain
              + 2.0 * (n1 + n2 + 1) * k * n3 * p)      # spatial factors
-    svd = svd_nominal_flops(n1, n2, p)
-
-    def jacobi_share(kernels, steps):
-        # the nominal SVD work of a step, spread evenly over that step's
-        # block-kernel launches (float32 coarse and float64 polish sweeps)
-        n = sum(kernels.get(nm, {}).get("launches", 0)
-                for nm in ("jacobi_block_f32", "jacobi_block_f64", "jacobi_global_f32",
-                           "jacobi_global_f64"))
-        return svd * steps / n if n else None
-
     models = {
         "hat": ("hbm", a_bytes * N * n3 + 4.0 * N * p + 4.0 * n3 * p),
         "unhat": ("hbm", None),   # several launches of different sizes
-        "jacobi_block_f32": ("alu", jacobi_share),
-        "jacobi_block_f64": ("alu", jacobi_share),
     }
+    models.update(jacobi_models(svd_nominal_flops(n1, n2, p)))
     info = {"workload": name, "n1": n1, "n2": n2, "n3": n3, "p": p, "k": k}
     return step, flops, info, models
 
@@ -212,6 +225,44 @@ def main():
         info = {"workload": "qprod 256x128x128 * 128x256x128 fp32, p=16", "n1": n1, "m": m,
                 "n2": n2, "n3": n3, "p": p}
         dtype = "f32"
+    elif args.workload == "batched":
+        shapes = synth.batched_shapes(count=args.count)
+        insts, flops, cpu_insts = [], 0.0, []
+        for i, sh in enumerate(shapes):
+            rng = np.random.default_rng([4, i])
+            A = rng.standard_normal((sh["n3"], sh["n2"], sh["n1"]), dtype=np.float32)
+            B = rng.standard_normal((sh["n3"], sh["n4"], sh["n2"]), dtype=np.float32)
+            Qn = synth.random_orthonormal(rng, sh["n3"], sh["p"]).astype(np.float32)
+            insts.append(dict(A=up(A), B=up(B), Q=torch.from_numpy(Qn).to(dev), k=sh["k"]))
+            n1, n2, n3, n4, p, k = (sh[x] for x in ("n1", "n2", "n3", "n4", "p", "k"))
+            f = (2.0 * p * (n1 * n2 * n3 + n2 * n4 * n3 + n1 * n2 * n4 + n1 * n4 * n3)   # qprod
+                 + 2.0 * n1 * n2 * n3 * p + svd_nominal_flops(n1, n2, p))               # tSVDQ steps 2-3
+            flops += f
+            cpu_insts.append((synth.logical(A), synth.logical(B), Qn, k, f))
+        batch_box = {}
+
+        def step():
+            batch_box["b"].run()
+            return batch_box["b"]
+
+        def plan():
+            if "b" in batch_box:
+                batch_box["b"].close()
+            batch_box["b"] = pq.batched(insts)
+            return batch_box["b"]
+
+        def unbatched():
+            for x in insts:
+                pq.qprod(x["A"], x["B"], x["Q"])
+                pq.tsvdq(x["A"], x["Q"], x["k"])
+
+        models = jacobi_models(sum(svd_nominal_flops(sh["n1"], sh["n2"], sh["p"]) for sh in shapes))
+        info = {"workload": f"batched: {len(shapes)} uneven instances (qprod + rank-p/2 tSVDQ each), "
+                            "n1,n2,n4 in [64,512], n3 in [32,256], p in [4,32], fp32",
+                "instances": len(shapes),
+                "a_elements": int(sum(sh["n1"] * sh["n2"] * sh["n3"] for sh in shapes)),
+                "faces": int(sum(sh["p"] for sh in shapes))}
+        dtype = "f32"
     else:  # diff
         c = synth.differentiation_case()
         A = up(c["A"]).requires_grad_(True)
@@ -246,6 +297,9 @@ def main():
     # warm-up; the first pass also lets the library's autotuner time the
     # candidate launch configurations of every kernel shape in the step
     lib.pq_autotune_enable(1)
+    if args.workload == "batched":
+        unbatched()  # tunes the per-instance launch shapes of the plain path
+        plan()       # eager pass + graph capture
     for _ in range(max(1, args.warmup)):
         out = step()
     torch.cuda.synchronize()
@@ -265,12 +319,33 @@ def main():
     ms_per_step = total_ms / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step")
 
+    extra_batched = {}
+    if args.workload == "batched":
+        # the same work as sequential unbatched calls (the plain fp32 path)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        unbatched()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ub = ev0.elapsed_time(ev1)
+        extra_batched = {"unbatched_ms_per_step": round(ub, 4),
+                         "speedup_vs_unbatched": round(ub / ms_per_step, 3),
+                         "workspace_GB": round(out.workspace_bytes / 1e9, 3)}
+        log(f"unbatched: {ub:.3f} ms/step, batched graph {ms_per_step:.3f} ms/step")
+
     # a second pass of the same K steps with the library's per-launch
-    # profiler on (HIP events around every launch, on the launch stream)
+    # profiler on (HIP events around every launch, on the launch stream);
+    # a captured graph records no events, so the batched workload profiles
+    # the eager pass of a fresh plan instead
     lib.pq_profile_reset()
     lib.pq_profile_enable(1)
-    for _ in range(args.steps):
-        out = step()
+    if args.workload == "batched":
+        out = plan()
+        prof_steps = 1
+    else:
+        for _ in range(args.steps):
+            out = step()
+        prof_steps = args.steps
     torch.cuda.synchronize()
     lib.pq_profile_enable(0)
 
@@ -287,8 +362,8 @@ def main():
                        "avg_us": 1000.0 * t.value / max(1, n.value)}
     lib.pq_profile_reset()
     for nm, d in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"]):
-        log(f"  {nm:18s} {d['total_ms'] / args.steps * 1000:10.1f} us/step  "
-            f"{d['launches'] // max(1, args.steps)} launches/step  avg {d['avg_us']:.1f} us")
+        log(f"  {nm:18s} {d['total_ms'] / prof_steps * 1000:10.1f} us/step  "
+            f"{d['launches'] // max(1, prof_steps)} launches/step  avg {d['avg_us']:.1f} us")
 
     # dominant kernel and its roofline
     dom = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])[0] if kernels else None
@@ -296,7 +371,7 @@ def main():
     if dom is not None:
         bound, units = models.get(dom, ("hbm", None))
         if callable(units):
-            units = units(kernels, args.steps)
+            units = units(kernels, prof_steps)
         avg_s = kernels[dom]["avg_us"] * 1e-6
         if units is not None and avg_s > 0:
             if bound == "hbm":
@@ -324,14 +399,28 @@ def main():
 
     # CPU oracle baseline (float64, this host's cores), a bounded sample
     cpu = None
+    if not args.no_cpu_baseline and args.workload == "batched":
+        import oracle
+        cores = blas_threads()
+        done, t_cpu, fl = 0, 0.0, 0.0
+        t_start = time.time()
+        for (Al, Bl, Qn, k, f) in cpu_insts:
+            if time.time() - t_start > args.cpu_seconds and done > 0:
+                break
+            t1 = time.time()
+            oracle.check_q(Qn)
+            oracle.qprod(Al, Bl, Qn)
+            oracle.tsvdq(Al, Qn, k)
+            t_cpu += time.time() - t1
+            fl += f
+            done += 1
+        cpu = {"value": round(fl / t_cpu / 1e9, 4), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+               "sample": f"the first {done} of {len(cpu_insts)} instances (qprod + tSVDQ each), "
+                         f"{t_cpu:.1f}s, float64 numpy/LAPACK"}
+        log(f"cpu oracle: {cpu['value']} GFLOP/s over {done} instances on {cores} threads")
     if not args.no_cpu_baseline and cpu_case is not None:
         import oracle
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([d.get("num_threads", 1) for d in threadpool_info()
-                         if d.get("user_api") == "blas"] or [1])
-        except Exception:  # threadpoolctl missing
-            cores = os.cpu_count()
+        cores = blas_threads()
         _, Al, Qn, k = cpu_case
         oracle.check_q(Qn)
         oracle.tsvdq(Al, Qn, k)  # warm-up
@@ -362,11 +451,11 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": dict(info, prec=args.prec, **extra),
+        "config": dict(info, prec=args.prec, **extra, **extra_batched),
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    detail = {"kernels_per_step_us": {k2: v["total_ms"] / args.steps * 1000 for k2, v in kernels.items()},
+    detail = {"kernels_per_step_us": {k2: v["total_ms"] / prof_steps * 1000 for k2, v in kernels.items()},
               "kernels": kernels, "flops_per_step": flops, "line": line}
     if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
         with open(os.path.join(ROOT, "gpurun_out", f"bench_kernels_{args.workload}.json"), "w") as fh:

@@ -182,6 +182,94 @@ __global__ __launch_bounds__(S * 64) void hat_f32_kernel(const TIn* __restrict__
   }
 }
 
+// ---- float32 transform, one strip per workgroup ------------------------------
+// A workgroup of S waves owns one strip of 32*VEC tubes; its waves take the
+// pairs of frontal slices (t, t + 1) in turn, U pairs per batch.  A batch is
+// the U slices of A a lane needs (VEC tubes each) and the matching U entries
+// of Q (read through the cache: Q is a few KB).  The loads of the next batch
+// are issued before the MFMAs of the current one (two register buffers), so
+// every wave keeps a batch in flight while its MFMAs run; loads past the last
+// slice read a clamped, in-bounds address and are masked at use.  Nothing is
+// staged and nothing waits at a barrier until the S partial accumulators are
+// summed through LDS at the end.
+template <int VEC, int U, typename TIn>
+__device__ __forceinline__ void strip_load(const TIn* __restrict__ A, const float* __restrict__ Q, int64_t N,
+                                           int64_t xs, int n3, int p, int lq, int kh, int j0,
+                                           float (&b)[U][VEC], float (&a)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int tc = min(2 * (j0 + u) + kh, n3 - 1);
+    load_vec<VEC>(A + (int64_t)tc * N + xs, b[u]);
+    a[u] = Q[(int64_t)tc * p + lq];
+  }
+}
+
+template <int VEC, int U>
+__device__ __forceinline__ void strip_mma(int n3, int p, int l, bool active, int kh, int j0,
+                                          const float (&b)[U][VEC], const float (&a)[U], f32x16 (&acc)[VEC]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int t = 2 * (j0 + u) + kh;
+    const float av = (t < n3 && l < p) ? a[u] : 0.f;
+    const bool okb = active && t < n3;
+#pragma unroll
+    for (int q = 0; q < VEC; ++q)
+      acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, okb ? b[u][q] : 0.f, acc[q], 0, 0, 0);
+  }
+}
+
+// MW: minimum waves per SIMD the register allocation must allow (occupancy)
+template <int VEC, int S, int U, int MW, typename TIn>
+__global__ __launch_bounds__(S * 64, MW) void hat_strip_kernel(const TIn* __restrict__ A, const float* __restrict__ Q,
+                                                               float* __restrict__ Ah, int64_t N, int n3, int p) {
+  extern __shared__ float red[];  // (S - 1) * VEC * 16 * 64
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 31, kh = lane >> 5;
+  const int lc = blockIdx.y * 32;
+  const int64_t xl = (int64_t)blockIdx.x * (32 * VEC) + (int64_t)VEC * n;
+  const bool active = xl < N;
+  const int64_t xs = active ? xl : N - VEC;  // a valid tube for address arithmetic
+  const int l = lc + n;                      // this lane's column of Q (row of the MFMA's A operand)
+  const int lq = min(l, p - 1);
+  f32x16 acc[VEC];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[q][j] = 0.f;
+  const int npairs = (n3 + 1) >> 1;
+  constexpr int step = S * U;
+  float b0[U][VEC], a0[U], b1[U][VEC], a1[U];
+  int j0 = wave * U;
+  strip_load<VEC, U, TIn>(A, Q, N, xs, n3, p, lq, kh, j0, b0, a0);
+  // the scheduling barriers keep each batch's loads ahead of the previous
+  // batch's MFMAs (the compiler would otherwise interleave them and wait)
+  while (j0 < npairs) {
+    strip_load<VEC, U, TIn>(A, Q, N, xs, n3, p, lq, kh, j0 + step, b1, a1);
+    __builtin_amdgcn_sched_barrier(0);
+    strip_mma<VEC, U>(n3, p, l, active, kh, j0, b0, a0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    j0 += step;
+    if (j0 >= npairs) break;
+    strip_load<VEC, U, TIn>(A, Q, N, xs, n3, p, lq, kh, j0 + step, b0, a0);
+    __builtin_amdgcn_sched_barrier(0);
+    strip_mma<VEC, U>(n3, p, l, active, kh, j0, b1, a1, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    j0 += step;
+  }
+  if (reduce_waves<VEC, S>(acc, red, wave, lane) && active) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int lo = lc + 8 * (j >> 2) + 4 * kh + (j & 3);
+      if (lo < p) {
+        float v[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) v[q] = acc[q][j];
+        store_vec<VEC>(Ah + (int64_t)lo * N + xl, v);
+      }
+    }
+  }
+}
+
 template <int VEC, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void unhat_f32_kernel(const float* __restrict__ Ah,
                                                                const float* __restrict__ Q,
@@ -481,14 +569,23 @@ __global__ __launch_bounds__(S * 64) void hat_bf16_kernel(const TIn* __restrict_
           }
         }
       };
+      // loads past the last step read clamped addresses and are masked; the
+      // scheduling barriers keep each step's loads ahead of the previous
+      // step's MFMAs
       int st = wave;
-      if (st < nsteps) load_step(st, x0);
-      for (; st < nsteps; st += 2 * S) {
-        if (st + S < nsteps) load_step(st + S, x1);
+      load_step(st, x0);
+      while (st < nsteps) {
+        load_step(st + S, x1);
+        __builtin_amdgcn_sched_barrier(0);
         mfma_step(st, x0);
-        if (st + S >= nsteps) break;
-        if (st + 2 * S < nsteps) load_step(st + 2 * S, x0);
-        mfma_step(st + S, x1);
+        __builtin_amdgcn_sched_barrier(0);
+        st += S;
+        if (st >= nsteps) break;
+        load_step(st + S, x0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_step(st, x1);
+        __builtin_amdgcn_sched_barrier(0);
+        st += S;
       }
     }
     if (reduce_waves<TPL, S>(acc, red, wave, lane) && active) {
@@ -501,6 +598,106 @@ __global__ __launch_bounds__(S * 64) void hat_bf16_kernel(const TIn* __restrict_
           for (int c = 0; c < TPL; ++c) v[c] = acc[c][j];
           store_vec<TPL>(Ah + (int64_t)l * N + xl, v);
         }
+      }
+    }
+  }
+}
+
+// ---- split-bfloat16 transform, one strip per workgroup ------------------------
+// The strip design of hat_strip_kernel for the bfloat16 MFMA
+// (v_mfma_f32_32x32x16_bf16): a step is 16 frontal slices, the lanes of
+// half-wave kh holding slices 8 kh .. 8 kh + 7 of it for their TPL tubes.
+// Both operands are split into bfloat16 parts in registers as they arrive
+// (Q's 8 entries per step come through the cache), the SP::n part products
+// accumulate in float32, and the next step's loads are issued before the
+// current step's MFMAs.
+template <int TPL, typename TIn>
+__device__ __forceinline__ void bstrip_load(const TIn* __restrict__ A, const float* __restrict__ Q, int64_t N,
+                                            int64_t xs, int n3, int p, int lq, int kh, int st, float (&x)[8][TPL],
+                                            float (&qv)[8]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int tc = min(16 * st + 8 * kh + r, n3 - 1);
+    load_vec<TPL, TIn>(A + (int64_t)tc * N + xs, x[r]);
+    qv[r] = Q[(int64_t)tc * p + lq];
+  }
+}
+
+template <int TPL, int NA, int NQ>
+__device__ __forceinline__ void bstrip_mma(int n3, int p, int l, bool active, int kh, int st,
+                                           const float (&x)[8][TPL], const float (&qv)[8], f32x16 (&acc)[TPL]) {
+  using SP = Split<NA, NQ>;
+  uint32_t qw[NQ][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = 16 * st + 8 * kh + 2 * q;
+    uint32_t parts[NQ];
+    split_pack<NQ>((t < n3 && l < p) ? qv[2 * q] : 0.f, (t + 1 < n3 && l < p) ? qv[2 * q + 1] : 0.f, parts);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) qw[i][q] = parts[i];
+  }
+#pragma unroll
+  for (int c = 0; c < TPL; ++c) {
+    uint32_t bw[NA][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = 16 * st + 8 * kh + 2 * q;
+      uint32_t parts[NA];
+      split_pack<NA>((active && t < n3) ? x[2 * q][c] : 0.f, (active && t + 1 < n3) ? x[2 * q + 1][c] : 0.f, parts);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) bw[i][q] = parts[i];
+    }
+#pragma unroll
+    for (int pr = 0; pr < SP::n; ++pr) {
+      const bf16x8 aop = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(qw[SP::q[pr]]));
+      const bf16x8 bop = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(bw[SP::a[pr]]));
+      acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop, bop, acc[c], 0, 0, 0);
+    }
+  }
+}
+
+template <typename TIn, int NA, int NQ, int TPL, int S, int MW>
+__global__ __launch_bounds__(S * 64, MW) void hat_bstrip_kernel(const TIn* __restrict__ A, const float* __restrict__ Q,
+                                                                float* __restrict__ Ah, int64_t N, int n3, int p) {
+  extern __shared__ float red[];  // (S - 1) * TPL * 16 * 64
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 31, kh = lane >> 5;
+  const int lc = blockIdx.y * 32;
+  const int64_t xl = (int64_t)blockIdx.x * (32 * TPL) + (int64_t)TPL * n;
+  const bool active = xl < N;
+  const int64_t xs = active ? xl : N - TPL;  // a valid tube for address arithmetic
+  const int l = lc + n, lq = min(l, p - 1);
+  f32x16 acc[TPL];
+#pragma unroll
+  for (int c = 0; c < TPL; ++c)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[c][j] = 0.f;
+  const int nsteps = (n3 + 15) >> 4;
+  float x0[8][TPL], q0[8], x1[8][TPL], q1[8];
+  int st = wave;
+  bstrip_load<TPL, TIn>(A, Q, N, xs, n3, p, lq, kh, st, x0, q0);
+  while (st < nsteps) {
+    bstrip_load<TPL, TIn>(A, Q, N, xs, n3, p, lq, kh, st + S, x1, q1);
+    __builtin_amdgcn_sched_barrier(0);
+    bstrip_mma<TPL, NA, NQ>(n3, p, l, active, kh, st, x0, q0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    st += S;
+    if (st >= nsteps) break;
+    bstrip_load<TPL, TIn>(A, Q, N, xs, n3, p, lq, kh, st + S, x0, q0);
+    __builtin_amdgcn_sched_barrier(0);
+    bstrip_mma<TPL, NA, NQ>(n3, p, l, active, kh, st, x1, q1, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    st += S;
+  }
+  if (reduce_waves<TPL, S>(acc, red, wave, lane) && active) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int lo = lc + 8 * (j >> 2) + 4 * kh + (j & 3);
+      if (lo < p) {
+        float v[TPL];
+#pragma unroll
+        for (int c = 0; c < TPL; ++c) v[c] = acc[c][j];
+        store_vec<TPL>(Ah + (int64_t)lo * N + xl, v);
       }
     }
   }
@@ -570,6 +767,7 @@ int pick_vec(int64_t N, std::initializer_list<const void*> ptrs, int elem) {
 // `spw` strips; for the return transform each wave has its own strip.
 struct Cfg {
   int vec, waves, spw;
+  int strip = 0;  // > 0: hat_strip_kernel, `spw` slice pairs per load batch, `strip` min waves per SIMD
 };
 
 std::vector<Cfg> cands(int vmax, bool splitk) {
@@ -656,6 +854,71 @@ hipError_t hat_bf16_go(const TIn* A, const float* Q, float* Ah, int64_t N, int n
   dim3 grid((unsigned)((nstrips + spw - 1) / spw), (unsigned)((p + 31) / 32));
   hat_bf16_kernel<TIn, NA, NQ, TPL, S><<<grid, S * 64, lds, s>>>(A, Q, Ah, N, n3, p, kcr, nstrips);
   return hipGetLastError();
+}
+
+template <int VEC, int S, int U, int MW, typename TIn>
+hipError_t hat_strip_go(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p, hipStream_t s) {
+  const size_t lds = red_bytes(VEC, S);
+  dim3 grid((unsigned)((N + 32 * VEC - 1) / (32 * VEC)), (unsigned)((p + 31) / 32));
+  hat_strip_kernel<VEC, S, U, MW, TIn><<<grid, S * 64, lds, s>>>(A, Q, Ah, N, n3, p);
+  return hipGetLastError();
+}
+
+template <typename TIn>
+hipError_t hat_strip_any(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p, Cfg c,
+                         hipStream_t s) {
+#define PQ_S(V, W, U, MW)                                                                   \
+  if (c.vec == V && c.waves == W && c.spw == U && c.strip == MW)                            \
+    return hat_strip_go<V, W, U, MW, TIn>(A, Q, Ah, N, n3, p, s);
+  PQ_S(4, 1, 4, 1) PQ_S(4, 2, 4, 1) PQ_S(4, 4, 4, 1) PQ_S(4, 2, 4, 2) PQ_S(4, 4, 4, 2) PQ_S(4, 2, 2, 4)
+  PQ_S(4, 4, 2, 4) PQ_S(2, 2, 4, 1) PQ_S(2, 4, 4, 1) PQ_S(2, 2, 4, 4) PQ_S(2, 4, 4, 4) PQ_S(2, 4, 8, 2)
+  PQ_S(1, 2, 4, 1) PQ_S(1, 4, 4, 1) PQ_S(1, 4, 8, 4) PQ_S(1, 8, 8, 4)
+#undef PQ_S
+  return hipErrorInvalidValue;
+}
+
+// strip-kernel candidates (vec, waves, pairs per batch, minimum waves per
+// SIMD), widest vector first
+void strip_cands(int vmax, std::vector<Cfg>& v) {
+  static const int t[][4] = {{4, 1, 4, 1}, {4, 2, 4, 1}, {4, 4, 4, 1}, {4, 2, 4, 2}, {4, 4, 4, 2}, {4, 2, 2, 4},
+                             {4, 4, 2, 4}, {2, 2, 4, 1}, {2, 4, 4, 1}, {2, 2, 4, 4}, {2, 4, 4, 4}, {2, 4, 8, 2},
+                             {1, 2, 4, 1}, {1, 4, 4, 1}, {1, 4, 8, 4}, {1, 8, 8, 4}};
+  for (const auto& r : t)
+    if (r[0] <= vmax) {
+      Cfg c{r[0], r[1], r[2]};
+      c.strip = r[3];
+      v.push_back(c);
+    }
+}
+
+template <typename TIn, int NA, int NQ, int TPL, int S, int MW>
+hipError_t hat_bstrip_go(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p, hipStream_t s) {
+  const size_t lds = red_bytes(TPL, S);
+  dim3 grid((unsigned)((N + 32 * TPL - 1) / (32 * TPL)), (unsigned)((p + 31) / 32));
+  hat_bstrip_kernel<TIn, NA, NQ, TPL, S, MW><<<grid, S * 64, lds, s>>>(A, Q, Ah, N, n3, p);
+  return hipGetLastError();
+}
+
+template <typename TIn, int NA, int NQ>
+hipError_t hat_bstrip_any(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p, Cfg c,
+                          hipStream_t s) {
+#define PQ_B(V, W, MW)                                                                      \
+  if (c.vec == V && c.waves == W && c.strip == MW)                                          \
+    return hat_bstrip_go<TIn, NA, NQ, V, W, MW>(A, Q, Ah, N, n3, p, s);
+  PQ_B(4, 2, 2) PQ_B(4, 4, 2) PQ_B(2, 2, 4) PQ_B(2, 4, 4) PQ_B(1, 4, 4) PQ_B(1, 8, 4)
+#undef PQ_B
+  return hipErrorInvalidValue;
+}
+
+// split-bfloat16 strip candidates (tubes per lane, waves, min waves per SIMD)
+void bstrip_cands(int vmax, std::vector<Cfg>& v) {
+  static const int t[][3] = {{4, 2, 2}, {4, 4, 2}, {2, 2, 4}, {2, 4, 4}, {1, 4, 4}, {1, 8, 4}};
+  for (const auto& r : t)
+    if (r[0] <= vmax) {
+      Cfg c{r[0], r[1], 0};
+      c.strip = r[2];
+      v.push_back(c);
+    }
 }
 
 template <int VEC, int S, typename TIn>
@@ -749,12 +1012,41 @@ hipError_t unhat_f32_any(const float* Ah, const float* Q, float* C, int64_t N, i
 hipError_t hat_f32(const void* A, bool a_bf16, const float* Q, float* Ah, int64_t N, int n3, int p,
                    Prec prec, hipStream_t s) {
   const int vmax = a_bf16 ? std::min(pick_vec(N, {A}, 2), pick_vec(N, {Ah}, 4)) : pick_vec(N, {A, Ah}, 4);
-  const std::vector<Cfg> c = cands(vmax, true);
+  std::vector<Cfg> c;
+  if (prec == Prec::Default) strip_cands(vmax, c);
+  else bstrip_cands(vmax, c);
+  const int nstrip = (int)c.size();
+  for (const Cfg& g : cands(vmax, true)) c.push_back(g);
   const std::string key = key_of("hat", (int)prec, a_bf16, N, n3, p, vmax);
   const uint16_t* ab = static_cast<const uint16_t*>(A);
   const float* af = static_cast<const float*>(A);
-  return tuned_launch(key, (int)c.size(), default_splitk(c, N), s, [&](int i) -> hipError_t {
+  // untuned default: the strip kernel with two waves and four pairs per batch
+  int dflt = nstrip;
+  for (int i = 0; i < nstrip; ++i)
+    if (c[i].vec == vmax && c[i].waves == (prec == Prec::Default ? 2 : 4) &&
+        (prec != Prec::Default || c[i].spw == 4))
+      dflt = i;
+  if (dflt == nstrip) {
+    std::vector<Cfg> rest(c.begin() + nstrip, c.end());
+    dflt = nstrip + default_splitk(rest, N);
+  }
+  return tuned_launch(key, (int)c.size(), dflt, s, [&](int i) -> hipError_t {
     const Cfg g = c[i];
+    if (g.strip) {
+      if (prec == Prec::Default) {
+        if (a_bf16) return hat_strip_any<uint16_t>(ab, Q, Ah, N, n3, p, g, s);
+        return hat_strip_any<float>(af, Q, Ah, N, n3, p, g, s);
+      }
+      if (a_bf16) {
+        if (prec == Prec::BF16) return hat_bstrip_any<uint16_t, 1, 1>(ab, Q, Ah, N, n3, p, g, s);
+        return hat_bstrip_any<uint16_t, 1, 3>(ab, Q, Ah, N, n3, p, g, s);
+      }
+      switch (prec) {
+        case Prec::BF16: return hat_bstrip_any<float, 1, 1>(af, Q, Ah, N, n3, p, g, s);
+        case Prec::BF16x3: return hat_bstrip_any<float, 2, 2>(af, Q, Ah, N, n3, p, g, s);
+        default: return hat_bstrip_any<float, 3, 3>(af, Q, Ah, N, n3, p, g, s);
+      }
+    }
     if (a_bf16) {
       switch (prec) {
         case Prec::Default: return hat_f32_any<uint16_t>(ab, Q, Ah, N, n3, p, g, s);
