@@ -154,8 +154,11 @@ int pq_unhat(const void* Ahat, const void* Q, void* A, int dtype,
 /*
  * out = A x_3 Q Q^T, the orthogonal projection of every tube onto range(Q)
  * (the remark after Fig. 3.1).  A: a_dtype (F32, BF16 or F64); out float32
- * (float64 for F64).  Fused into one pass over A when p <= 32; otherwise it
- * needs pq_proj_workspace bytes of ws.
+ * (float64 for F64).  With pq_proj_workspace bytes of ws it runs the two
+ * streaming transforms (the precision mode applies to the first); with no
+ * (or too small a) workspace and p <= 32 on float32/bf16 data it runs a
+ * fused single-pass kernel (float32 MFMA, mode ignored); otherwise it
+ * returns PQ_ERR_WORKSPACE.
  */
 size_t pq_proj_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int a_dtype);
 int pq_proj(const void* A, int a_dtype, const void* Q, void* out,

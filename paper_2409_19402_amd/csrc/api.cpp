@@ -267,7 +267,7 @@ int pq_unhat(const void* Ahat, const void* Q, void* A, int dtype, int64_t n1, in
 }
 
 size_t pq_proj_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int a_dtype) {
-  if (a_dtype != PQ_F64 && pq::proj_fused_ok((int)n3, (int)p)) return 0;
+  (void)n3;
   return align_up((size_t)n1 * n2 * p * elem(a_dtype == PQ_F64 ? PQ_F64 : PQ_F32));
 }
 
@@ -280,15 +280,20 @@ int pq_proj(const void* A, int a_dtype, const void* Q, void* out, int64_t n1, in
   PQ_CHECK(check_prec(prec, a_dtype));
   PQ_CHECK(no_alias(out, {A, Q}));
   const int64_t N = n1 * n2;
-  if (a_dtype != PQ_F64 && pq::proj_fused_ok((int)n3, (int)p)) {
-    PQ_PROF("proj_fused", stream);
-    PQ_TRY(pq::proj_fused_f32(A, a_dtype == PQ_BF16, static_cast<const float*>(Q),
-                              static_cast<float*>(out), N, (int)n3, (int)p, (Prec)prec, stream));
-    return PQ_OK;
+  const size_t need = pq_proj_workspace(n1, n2, n3, p, a_dtype);
+  // with the workspace: the two streaming transforms (faster than the fused
+  // kernel on gfx950, and they honour the precision mode); without it: the
+  // fused kernel (p <= 32)
+  if (!ws || ws_bytes < need) {
+    if (a_dtype != PQ_F64 && pq::proj_fused_ok((int)n3, (int)p)) {
+      PQ_PROF("proj_fused", stream);
+      PQ_TRY(pq::proj_fused_f32(A, a_dtype == PQ_BF16, static_cast<const float*>(Q),
+                                static_cast<float*>(out), N, (int)n3, (int)p, (Prec)prec, stream));
+      return PQ_OK;
+    }
+    return PQ_ERR_WORKSPACE;
   }
   if (p > 512 && a_dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
-  const size_t need = pq_proj_workspace(n1, n2, n3, p, a_dtype);
-  if (!ws || ws_bytes < need) return PQ_ERR_WORKSPACE;
   const int dt = a_dtype == PQ_F64 ? PQ_F64 : PQ_F32;
   PQ_TRY(do_hat(A, a_dtype, Q, ws, N, (int)n3, (int)p, (Prec)prec, stream));
   PQ_TRY(do_unhat(ws, Q, out, dt, N, (int)n3, (int)p, (Prec)prec, stream));

@@ -3,11 +3,8 @@
 // the split-K reductions over the n1 n2 tubes that give dQ, the factor
 // products of the truncated SVD).
 //
-// float32: a 64x64 output tile per 256-thread workgroup, 16-deep K tiles
-// staged through LDS, one 32x32 tile per wave on v_mfma_f32_32x32x2f32.  The
-// MFMA computes the transposed tile (rows = output columns), so the 32 lanes
-// that share an accumulator register hold 32 consecutive rows of the
-// column-major output and stores coalesce.
+// float32: a 64x64 output tile per 256-thread workgroup, K tiles of 32 or 128
+// double-buffered in LDS, one 32x32 tile per wave on v_mfma_f32_32x32x2f32.
 #include <algorithm>
 
 #include "common.hpp"
@@ -16,12 +13,95 @@
 namespace pq {
 namespace {
 
-constexpr int kTM = 64, kTN = 64, kTK = 16;
+constexpr int kTM = 64, kTN = 64, kLd = 68;
 
-template <bool TA, bool TB>
+// One K-tile of KT rows: the 64 x KT block of A (as As[k][m]) or the KT x 64
+// block of B (as Bs[k][n]), KT / 4 elements per thread, fetched into
+// registers.  VEC = 4 reads float4 along the operand's contiguous dimension
+// (the host guarantees that dimension, the leading dimension, the strides and
+// the base are multiples of 4), VEC = 1 reads scalars.  Elements outside the
+// matrix or past kend are 0.  CONT_ROW: the contiguous dimension is the
+// tile's row index (m or n) rather than k.
+template <int KT>
+struct TileRegs {
+  float v[KT / 4];
+};
+
+template <int KT, int VEC, bool CONT_ROW>
+__device__ __forceinline__ void tile_fetch(const float* __restrict__ P, int64_t ld, int r0, int rmax, int k0,
+                                           int kend, TileRegs<KT>& t) {
+  const int tid = threadIdx.x;
+  if constexpr (VEC == 4) {
+#pragma unroll
+    for (int h = 0; h < KT / 16; ++h) {
+      const int idx = tid + 256 * h;
+      int r, k;
+      if (CONT_ROW) { k = idx >> 4; r = 4 * (idx & 15); } else { r = idx / (KT / 4); k = 4 * (idx % (KT / 4)); }
+      const int gr = r0 + r, gk = k0 + k;
+      const bool ok = gr < rmax && gk < kend;  // whole float4 in or out (sizes are multiples of 4)
+      const int cr = ok ? gr : 0, ck = ok ? gk : 0;
+      const float4 x = CONT_ROW ? *reinterpret_cast<const float4*>(P + cr + (int64_t)ck * ld)
+                                : *reinterpret_cast<const float4*>(P + ck + (int64_t)cr * ld);
+      t.v[4 * h + 0] = ok ? x.x : 0.f;
+      t.v[4 * h + 1] = ok ? x.y : 0.f;
+      t.v[4 * h + 2] = ok ? x.z : 0.f;
+      t.v[4 * h + 3] = ok ? x.w : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < KT / 4; ++h) {
+      const int idx = tid + 256 * h;
+      int r, k;
+      if (CONT_ROW) { k = idx >> 6; r = idx & 63; } else { r = idx / KT; k = idx % KT; }
+      const int gr = r0 + r, gk = k0 + k;
+      const bool ok = gr < rmax && gk < kend;
+      const int cr = ok ? gr : 0, ck = ok ? gk : 0;
+      const float x = CONT_ROW ? P[cr + (int64_t)ck * ld] : P[ck + (int64_t)cr * ld];
+      t.v[h] = ok ? x : 0.f;
+    }
+  }
+}
+
+template <int KT, int VEC, bool CONT_ROW>
+__device__ __forceinline__ void tile_store(const TileRegs<KT>& t, float* S) {  // S: KT x kLd
+  const int tid = threadIdx.x;
+  if constexpr (VEC == 4) {
+#pragma unroll
+    for (int h = 0; h < KT / 16; ++h) {
+      const int idx = tid + 256 * h;
+      if (CONT_ROW) {
+        const int k = idx >> 4, r = 4 * (idx & 15);
+        *reinterpret_cast<float4*>(S + k * kLd + r) =
+            make_float4(t.v[4 * h], t.v[4 * h + 1], t.v[4 * h + 2], t.v[4 * h + 3]);
+      } else {
+        const int r = idx / (KT / 4), k = 4 * (idx % (KT / 4));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S[(k + i) * kLd + r] = t.v[4 * h + i];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < KT / 4; ++h) {
+      const int idx = tid + 256 * h;
+      int r, k;
+      if (CONT_ROW) { k = idx >> 6; r = idx & 63; } else { r = idx / KT; k = idx % KT; }
+      S[k * kLd + r] = t.v[h];
+    }
+  }
+}
+
+// C tile (64 x 64) = A (64 x K) B (K x 64) over K-tiles of KT, double
+// buffered in LDS (dynamic: 4 KT kLd floats): the next tile's global loads
+// are in flight while the MFMAs of the current one run.  The MFMA computes
+// the transposed tile (rows = output columns), so the 32 lanes sharing an
+// accumulator register hold 32 consecutive rows of the column-major output
+// and stores coalesce.
+template <bool TA, bool TB, int VA, int VB, int KT>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk) {
-  __shared__ float As[kTK][kTM + 4];
-  __shared__ float Bs[kTK][kTN + 4];
+  extern __shared__ __align__(16) float gsm[];
+  // buffers: A at gsm + b * KT * kLd, B at gsm + (2 + b) * KT * kLd
+  auto As = [&](int b) { return gsm + b * KT * kLd; };
+  auto Bs = [&](int b) { return gsm + (2 + b) * KT * kLd; };
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int nl = lane & 31, kh = lane >> 5;
@@ -35,32 +115,37 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk) {
   f32x16 acc;
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-  for (int k0 = kbeg; k0 < kend; k0 += kTK) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = tid + 256 * i;
-      int m, k;
-      if (TA) { k = e & 15; m = e >> 4; } else { m = e & 63; k = e >> 6; }
-      const int gm = m0 + m, gk = k0 + k;
-      float v = 0.f;
-      if (gm < g.M && gk < kend) v = TA ? A[gk + (int64_t)gm * g.lda] : A[gm + (int64_t)gk * g.lda];
-      As[k][m] = v;
-      int n;
-      if (TB) { n = e & 63; k = e >> 6; } else { k = e & 15; n = e >> 4; }
-      const int gn = n0 + n;
-      const int gk2 = k0 + k;
-      float w = 0.f;
-      if (gn < g.N && gk2 < kend) w = TB ? B[gn + (int64_t)gk2 * g.ldb] : B[gk2 + (int64_t)gn * g.ldb];
-      Bs[k][n] = w;
+  // A(m, k) is contiguous in m unless transposed; B(k, n) is contiguous in k
+  // unless transposed
+  TileRegs<KT> ra, rb;
+  int k0 = kbeg;
+  if (k0 < kend) {
+    tile_fetch<KT, VA, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
+    tile_fetch<KT, VB, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
+    tile_store<KT, VA, !TA>(ra, As(0));
+    tile_store<KT, VB, TB>(rb, Bs(0));
+  }
+  __syncthreads();
+  int buf = 0;
+  for (; k0 < kend; k0 += KT) {
+    const bool more = k0 + KT < kend;
+    if (more) {
+      tile_fetch<KT, VA, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
+      tile_fetch<KT, VB, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
+    }
+    // the whole tile, unrolled (rows past kend were staged as zeros), so the
+    // LDS reads run ahead of the MFMAs
+    const float* as = As(buf) + kh * kLd + wm * 32 + nl;  // columns of the transposed tile: output rows
+    const float* bs = Bs(buf) + kh * kLd + wn * 32 + nl;  // rows of the transposed tile: output columns
+#pragma unroll 16
+    for (int kk = 0; kk < KT; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(bs[kk * kLd], as[kk * kLd], acc, 0, 0, 0);
+    if (more) {
+      tile_store<KT, VA, !TA>(ra, As(buf ^ 1));
+      tile_store<KT, VB, TB>(rb, Bs(buf ^ 1));
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kTK; kk += 2) {
-      const float a = Bs[kk + kh][wn * 32 + nl];  // rows of the transposed tile: output columns
-      const float b = As[kk + kh][wm * 32 + nl];  // columns of the transposed tile: output rows
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-    }
-    __syncthreads();
+    buf ^= 1;
   }
   const int gm = m0 + wm * 32 + nl;
   if (gm >= g.M) return;
@@ -110,16 +195,53 @@ int chunk_for(const Gemm& g, int align) {
 
 }  // namespace
 
+// float4 loads along an operand's contiguous dimension need that dimension,
+// its leading dimension, the batch and split strides and the base to be
+// multiples of 4 floats
+bool vec4_ok(const void* P, int64_t cont, int64_t ld, int64_t stride) {
+  return reinterpret_cast<uintptr_t>(P) % 16 == 0 && cont % 4 == 0 && ld % 4 == 0 && stride % 4 == 0;
+}
+
+template <bool TA, bool TB, int VA, int VB, int KT>
+hipError_t gemm_f32_go(const Gemm& g, int kchunk, dim3 grid, hipStream_t s) {
+  const size_t lds = sizeof(float) * 4 * KT * kLd;
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_f32_kernel<TA, TB, VA, VB, KT>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  gemm_f32_kernel<TA, TB, VA, VB, KT><<<grid, 256, lds, s>>>(g, kchunk);
+  return hipGetLastError();
+}
+
+template <bool TA, bool TB, int KT>
+hipError_t gemm_f32_launch(const Gemm& g, int kchunk, dim3 grid, hipStream_t s) {
+  // contiguous dimension: A's is M (K when transposed), B's is K (N when transposed)
+  const bool va = vec4_ok(g.A, TA ? g.K : g.M, g.lda, g.sA) && (!TA || kchunk % 4 == 0);
+  const bool vb = vec4_ok(g.B, TB ? g.N : g.K, g.ldb, g.sB) && (TB || kchunk % 4 == 0);
+  if (va && vb) return gemm_f32_go<TA, TB, 4, 4, KT>(g, kchunk, grid, s);
+  if (va) return gemm_f32_go<TA, TB, 4, 1, KT>(g, kchunk, grid, s);
+  if (vb) return gemm_f32_go<TA, TB, 1, 4, KT>(g, kchunk, grid, s);
+  return gemm_f32_go<TA, TB, 1, 1, KT>(g, kchunk, grid, s);
+}
+
 hipError_t gemm_f32(const Gemm& g, Prec prec, hipStream_t s) {
   (void)prec;
-  const int kchunk = chunk_for(g, kTK);
+  // deep K-tiles (one global round trip covers up to 128 of K) when a
+  // workgroup has that much K
+  const int kchunk = chunk_for(g, 32);
   dim3 grid((unsigned)((g.M + kTM - 1) / kTM), (unsigned)((g.N + kTN - 1) / kTN),
             (unsigned)(g.batch * std::max(1, g.ksplit)));
-  if (!g.ta && !g.tb) gemm_f32_kernel<false, false><<<grid, 256, 0, s>>>(g, kchunk);
-  else if (!g.ta && g.tb) gemm_f32_kernel<false, true><<<grid, 256, 0, s>>>(g, kchunk);
-  else if (g.ta && !g.tb) gemm_f32_kernel<true, false><<<grid, 256, 0, s>>>(g, kchunk);
-  else gemm_f32_kernel<true, true><<<grid, 256, 0, s>>>(g, kchunk);
-  return hipGetLastError();
+  const bool deep = kchunk >= 96;
+  if (!g.ta && !g.tb)
+    return deep ? gemm_f32_launch<false, false, 128>(g, kchunk, grid, s)
+                : gemm_f32_launch<false, false, 32>(g, kchunk, grid, s);
+  if (!g.ta && g.tb)
+    return deep ? gemm_f32_launch<false, true, 128>(g, kchunk, grid, s)
+                : gemm_f32_launch<false, true, 32>(g, kchunk, grid, s);
+  if (g.ta && !g.tb)
+    return deep ? gemm_f32_launch<true, false, 128>(g, kchunk, grid, s)
+                : gemm_f32_launch<true, false, 32>(g, kchunk, grid, s);
+  return deep ? gemm_f32_launch<true, true, 128>(g, kchunk, grid, s)
+              : gemm_f32_launch<true, true, 32>(g, kchunk, grid, s);
 }
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s) {

@@ -82,8 +82,9 @@ def test_workspace_queries_monotone():
     b = lib.pq_qprod_workspace(64, 24, 20, 16, 4, 0)
     assert 0 < a < b
     assert lib.pq_qprod_workspace(32, 24, 20, 16, 4, 1) > a  # float64 needs more
-    assert lib.pq_proj_workspace(100, 100, 64, 16, 0) == 0   # fused, one pass
-    assert lib.pq_proj_workspace(100, 100, 64, 40, 0) > 0
+    # the transform-domain intermediate (the fused kernel runs without it)
+    assert lib.pq_proj_workspace(100, 100, 64, 16, 0) == 100 * 100 * 16 * 4
+    assert lib.pq_proj_workspace(100, 100, 64, 40, 1) == 100 * 100 * 40 * 8
     assert lib.pq_tsvdq_workspace(240, 320, 200, 20, 10, 0) > 2 * 240 * 320 * 20 * 4
 
 

@@ -406,3 +406,25 @@ def test_rejects_non_face_major(pq):
     Q = torch.zeros((6, 2), device="cuda")
     with pytest.raises(ValueError):
         pq.hat(X, Q)
+
+
+@pytest.mark.parametrize("shape", [(50, 30, 200, 20), (7, 9, 33, 5), (64, 64, 256, 32)])
+def test_proj_fused_without_workspace(pq, shape):
+    """pq_proj with no workspace runs the fused single-pass kernel (p <= 32)."""
+    import ctypes
+    from paper_2409_19402_amd import _lib
+    n1, n2, n3, p = shape
+    say(f"proj fused {shape}")
+    A, Q = _case(300 + n3, n1, n2, n3, p)
+    Ad, Qd = dev(A), devq(Q)
+    out = pq.empty(n1, n2, n3, device=Ad.device)
+    import torch
+    s = torch.cuda.current_stream().cuda_stream
+    _lib.call("pq_proj", Ad.data_ptr(), 0, Qd.data_ptr(), out.data_ptr(), n1, n2, n3, p, 0, None, 0, s)
+    assert rel(host(out), oracle.proj(synth.logical(A), Q)) <= TOL32
+    # and it refuses p > 32 without a workspace
+    A2, Q2 = _case(301, 8, 8, 40, 33)
+    out2 = pq.empty(8, 8, 40, device=Ad.device)
+    with pytest.raises(_lib.ProjProdError):
+        _lib.call("pq_proj", dev(A2).data_ptr(), 0, devq(Q2).data_ptr(), out2.data_ptr(), 8, 8, 40, 33, 0,
+                  None, 0, s)
