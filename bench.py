@@ -33,10 +33,17 @@ FP32_MFMA_PEAK = 157.3         # TFLOP/s dense
 FP64_VALU_PEAK = 78.6          # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 BF16_MFMA_PEAK = 2500.0        # TFLOP/s dense
 
-# HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE + WRITE_SIZE,
-# scaled by the copy-kernel calibration); None until measured for the kernel
-# as it is now.
-TRAFFIC_BYTES = {}
+# HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE runs of the same workload, scaled by the plain-copy
+# calibration (2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE, KiB -> bytes); keyed by
+# (workload, precision mode, kernel).  Absent means not measured for the
+# kernel as it is now.
+TRAFFIC_BYTES = {
+    ("video", "default", "jacobi_gram_f32"): 5576319,     # 2 x 1573.5 + 2298.7 KiB
+    ("hat-video", "bf16x3", "hat"): 67830000,              # 2 x 30120 + 6000 KiB
+    ("hat-hyper", "bf16x3", "hat"): 151400000,             # 2 x 57560 + 32768 KiB
+    ("hat-video", "default", "hat"): 67827698,             # 2 x 30119 + 6000 KiB
+}
 
 METRIC = "\u22c6_Q/tSVDQ GFLOP/s + % roofline, BF16-comp & batched vs FP32 at rel err\u22641e-5"
 
@@ -382,7 +389,8 @@ def main():
                 achieved, peak, unit = units / avg_s / 1e12, FP32_MFMA_PEAK, "TFLOP/s"
             roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 4), "peak": peak,
                     "unit": unit, "frac": round(achieved / peak, 6),
-                    "traffic": TRAFFIC_BYTES.get(dom), "avg_us": round(kernels[dom]["avg_us"], 3)}
+                    "traffic": TRAFFIC_BYTES.get((args.workload, args.prec, dom)),
+                    "avg_us": round(kernels[dom]["avg_us"], 3)}
 
     extra = {}
     if args.workload in ("video", "hyper", "tiny"):

@@ -111,10 +111,12 @@ int pq_autotune_load(const char* path);
 /*
  * While enabled, every kernel launch the library makes is bracketed by two
  * hipEvents recorded on the caller's stream (events come from a pool owned by
- * the library; no device memory is allocated).  pq_profile_query waits for
- * the recorded events of the launches named `name` (e.g. "hat", "unhat",
- * "proj_fused", "facewise_gemm", "jacobi_sweeps"), and returns their summed
- * duration in milliseconds and their count.  pq_profile_names writes the
+ * the library; no device memory is allocated); the back-to-back sweep
+ * launches of the Jacobi share one pair per phase and count as the launches
+ * they are.  Nothing is recorded while the stream is being captured into a
+ * graph.  pq_profile_query waits for the recorded events of the launches
+ * named `name` (e.g. "hat", "unhat", "facewise_gemm", "jacobi_gram_f32"),
+ * and returns their summed duration in milliseconds and their count.  pq_profile_names writes the
  * comma-separated names seen since the last reset into buf (host, len bytes).
  * pq_profile_reset forgets the records.  Process-wide; calls are serialised.
  */

@@ -28,10 +28,11 @@ bool tune_load(const char* path);
 
 // ---- per-launch profiler (prof.cpp) ---------------------------------------
 // While enabled, a ProfScope records a hipEvent on s at construction and at
-// destruction; the pair is kept under `name` (a string literal).
+// destruction; the pair is kept under `name` (a string literal) and counts as
+// `launches` launches.
 class ProfScope {
  public:
-  ProfScope(const char* name, hipStream_t s);
+  ProfScope(const char* name, hipStream_t s, int launches = 1);
   ~ProfScope();
   ProfScope(const ProfScope&) = delete;
   ProfScope& operator=(const ProfScope&) = delete;
@@ -39,6 +40,7 @@ class ProfScope {
  private:
   const char* name_;
   hipStream_t s_;
+  int count_;
   hipEvent_t a_ = nullptr;
 };
 void prof_enable(bool on);

@@ -903,12 +903,12 @@ hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, doub
     ProfScope prof("jacobi_flags", s);
     zero_ints_kernel<<<(nflags + 255) / 256, 256, 0, s>>>(flags, nflags);
   }
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    for (int round = 0; round < nb - 1; ++round) {
-      ProfScope prof(block_name<T>(), s);
-      jacobi_block_kernel<T, R><<<dim3(nb / 2, p), block, lds, s>>>(W, nv, L, nb, round, sw, max_sweeps,
-                                                                     tol, flags, used);
-    }
+  {
+    ProfScope prof(block_name<T>(), s, max_sweeps * (nb - 1));
+    for (int sw = 0; sw < max_sweeps; ++sw)
+      for (int round = 0; round < nb - 1; ++round)
+        jacobi_block_kernel<T, R><<<dim3(nb / 2, p), block, lds, s>>>(W, nv, L, nb, round, sw, max_sweeps,
+                                                                       tol, flags, used);
   }
   {
     ProfScope prof("jacobi_flags", s);
@@ -951,12 +951,12 @@ hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, 
     ProfScope prof("jacobi_flags", s);
     zero_ints_kernel<<<(nflags + 255) / 256, 256, 0, s>>>(flags, nflags);
   }
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    for (int round = 0; round < nb_max - 1; ++round) {
-      ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s);
-      jacobi_gram_kernel<T><<<(unsigned)gram_grid(nfaces, nb_max / 2), 256, lds, s>>>(
-          W, faces, nfaces, nb_max / 2, nv_u, L_u, round, sw, max_sweeps, tol, flags);
-    }
+  {
+    ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s, max_sweeps * (nb_max - 1));
+    for (int sw = 0; sw < max_sweeps; ++sw)
+      for (int round = 0; round < nb_max - 1; ++round)
+        jacobi_gram_kernel<T><<<(unsigned)gram_grid(nfaces, nb_max / 2), 256, lds, s>>>(
+            W, faces, nfaces, nb_max / 2, nv_u, L_u, round, sw, max_sweeps, tol, flags);
   }
   {
     ProfScope prof("jacobi_flags", s);

@@ -1,6 +1,10 @@
 // Per-launch timing behind pq_profile_*: while enabled, every launch the
 // library makes inside a ProfScope is bracketed by two hipEvents recorded on
-// the caller's stream (not while that stream is being captured into a graph).  Events come from a pool that grows on demand and is
+// the caller's stream (not while that stream is being captured into a graph).
+// A scope may cover several back-to-back launches of one kernel (the sweeps
+// of the Jacobi): one event pair then brackets all of them, so that short
+// launches are not stretched by events between them, and the scope counts
+// as that many launches.  Events come from a pool that grows on demand and is
 // reused after a reset.
 #include <cstring>
 #include <mutex>
@@ -14,6 +18,7 @@ namespace {
 struct Rec {
   const char* name;
   hipEvent_t a, b;
+  int count;  // launches the bracket covers
 };
 std::mutex g_mu;
 bool g_on = false;
@@ -33,7 +38,7 @@ hipEvent_t take_event() {
 
 }  // namespace
 
-ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
+ProfScope::ProfScope(const char* name, hipStream_t s, int launches) : name_(name), s_(s), count_(launches) {
   std::lock_guard<std::mutex> g(g_mu);
   if (!g_on) return;
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;  // no events inside a captured graph
@@ -51,7 +56,7 @@ ProfScope::~ProfScope() {
     return;
   }
   hipEventRecord(b, s_);
-  g_recs.push_back({name_, a_, b});
+  g_recs.push_back({name_, a_, b, count_});
 }
 
 void prof_enable(bool on) {
@@ -80,7 +85,7 @@ hipError_t prof_query(const char* name, double* total_ms, int* launches) {
     e = hipEventElapsedTime(&ms, r.a, r.b);
     if (e != hipSuccess) return e;
     tot += ms;
-    ++n;
+    n += r.count;
   }
   *total_ms = tot;
   *launches = n;
