@@ -579,7 +579,7 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
     // Akh_l = Uhat_l Ys_l^T (cols) or Ys_l Vhat_l^T (rows): both Uhat S Vhat^T
     Gemm g = cols ? face_gemm(false, true, in1, in2, ik, Fo, n1, n1 * k, Ys, n2, n2 * k, Akh, n1, N, ip)
                   : face_gemm(false, true, in1, in2, ik, Ys, n1, n1 * k, Fo, n2, n2 * k, Akh, n1, N, ip);
-    PQ_TRY(do_gemm("approx_gemm", g, dt, pr, stream));
+    PQ_TRY(do_gemm("approx_gemm", g, dt, Prec::Default, stream));
     PQ_TRY(do_unhat(Akh, Q, Ak, dt, N, (int)n3, ip, pr, stream));
   }
   if (Uk) PQ_TRY(do_unhat(Uhat, Q, Uk, dt, n1 * k, (int)n3, ip, pr, stream));

@@ -5,6 +5,7 @@
 //
 // float32: a 64x64 output tile per 256-thread workgroup, K tiles of 32 or 128
 // double-buffered in LDS, one 32x32 tile per wave on v_mfma_f32_32x32x2f32.
+// The split-bfloat16 modes use the same pipeline on v_mfma_f32_32x32x16_bf16.
 #include <algorithm>
 
 #include "common.hpp"
@@ -156,6 +157,126 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk) {
   }
 }
 
+// ---- split-bfloat16 facewise GEMM --------------------------------------------
+// The same 64 x 64 tile and double-buffered K pipeline as the float32 kernel;
+// the tile is fetched as float32 and split into NP bfloat16 parts on its way
+// into LDS, stored row-major with k contiguous ([row][k], row stride KT + 8)
+// so that a lane reads the 8 consecutive k of its row as one 16-byte operand
+// of v_mfma_f32_32x32x16_bf16.  The part products of Split<NP, NP> are
+// accumulated in float32.
+constexpr int kPad16 = 8;  // bfloat16 elements of padding per LDS row
+
+template <int KT, int VEC, bool CONT_ROW, int NP>
+__device__ __forceinline__ void tile_store_split(const TileRegs<KT>& t, uint16_t* S) {
+  // S: NP parts, each 64 rows x (KT + kPad16) bfloat16
+  constexpr int ld = KT + kPad16;
+  constexpr int part = 64 * ld;
+  const int tid = threadIdx.x;
+  auto put = [&](int r, int k, float x) {
+    uint32_t w[NP];
+    split_pack<NP>(x, 0.f, w);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) S[i * part + r * ld + k] = (uint16_t)(w[i] & 0xffffu);
+  };
+  if constexpr (VEC == 4) {
+#pragma unroll
+    for (int h = 0; h < KT / 16; ++h) {
+      const int idx = tid + 256 * h;
+      if (CONT_ROW) {
+        const int k = idx >> 4, r = 4 * (idx & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) put(r + i, k, t.v[4 * h + i]);
+      } else {  // four consecutive k of one row: two packed words per part
+        const int r = idx / (KT / 4), k = 4 * (idx % (KT / 4));
+        uint32_t w0[NP], w1[NP];
+        split_pack<NP>(t.v[4 * h + 0], t.v[4 * h + 1], w0);
+        split_pack<NP>(t.v[4 * h + 2], t.v[4 * h + 3], w1);
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+          *reinterpret_cast<uint2*>(S + i * part + r * ld + k) = make_uint2(w0[i], w1[i]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < KT / 4; ++h) {
+      const int idx = tid + 256 * h;
+      int r, k;
+      if (CONT_ROW) { k = idx >> 6; r = idx & 63; } else { r = idx / KT; k = idx % KT; }
+      put(r, k, t.v[h]);
+    }
+  }
+}
+
+template <bool TA, bool TB, int VA, int VB, int KT, int NP>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(Gemm g, int kchunk) {
+  using SP = Split<NP, NP>;
+  constexpr int ld = KT + kPad16;
+  constexpr int part = 64 * ld;  // bfloat16 elements per part
+  extern __shared__ __align__(16) uint16_t hsm[];
+  // buffers: A parts at hsm + b * NP * part, B parts at hsm + (2 + b) * NP * part
+  auto Ap = [&](int b) { return hsm + b * NP * part; };
+  auto Bp = [&](int b) { return hsm + (2 + b) * NP * part; };
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int nl = lane & 31, kh = lane >> 5;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int zb = blockIdx.z % g.batch, zs = blockIdx.z / g.batch;
+  const int m0 = blockIdx.x * kTM, n0 = blockIdx.y * kTN;
+  const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
+  const float* A = static_cast<const float*>(g.A) + (int64_t)zb * g.sA;
+  const float* B = static_cast<const float*>(g.B) + (int64_t)zb * g.sB;
+  float* C = static_cast<float*>(g.C) + (int64_t)zb * g.sC + (int64_t)zs * g.sSplit;
+  f32x16 acc;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+  TileRegs<KT> ra, rb;
+  int k0 = kbeg;
+  if (k0 < kend) {
+    tile_fetch<KT, VA, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
+    tile_fetch<KT, VB, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
+    tile_store_split<KT, VA, !TA, NP>(ra, Ap(0));
+    tile_store_split<KT, VB, TB, NP>(rb, Bp(0));
+  }
+  __syncthreads();
+  int buf = 0;
+  for (; k0 < kend; k0 += KT) {
+    const bool more = k0 + KT < kend;
+    if (more) {
+      tile_fetch<KT, VA, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
+      tile_fetch<KT, VB, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
+    }
+    // rows of the transposed tile are output columns (B's n), its columns
+    // output rows (A's m)
+    const uint16_t* ap = Ap(buf) + (wm * 32 + nl) * ld + 8 * kh;
+    const uint16_t* bp = Bp(buf) + (wn * 32 + nl) * ld + 8 * kh;
+#pragma unroll
+    for (int ks = 0; ks < KT; ks += 16) {
+      bf16x8 pa[NP], pb[NP];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        pa[i] = *reinterpret_cast<const bf16x8*>(ap + i * part + ks);
+        pb[i] = *reinterpret_cast<const bf16x8*>(bp + i * part + ks);
+      }
+#pragma unroll
+      for (int pr = 0; pr < SP::n; ++pr)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pb[SP::q[pr]], pa[SP::a[pr]], acc, 0, 0, 0);
+    }
+    if (more) {
+      tile_store_split<KT, VA, !TA, NP>(ra, Ap(buf ^ 1));
+      tile_store_split<KT, VB, TB, NP>(rb, Bp(buf ^ 1));
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  const int gm = m0 + wm * 32 + nl;
+  if (gm >= g.M) return;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int gn = n0 + wn * 32 + 8 * (j >> 2) + 4 * kh + (j & 3);
+    if (gn < g.N) C[gm + (int64_t)gn * g.ldc] = acc[j];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void gemm_generic_kernel(Gemm g, int kchunk) {
   const int zb = blockIdx.z % g.batch, zs = blockIdx.z / g.batch;
@@ -223,25 +344,55 @@ hipError_t gemm_f32_launch(const Gemm& g, int kchunk, dim3 grid, hipStream_t s) 
   return gemm_f32_go<TA, TB, 1, 1, KT>(g, kchunk, grid, s);
 }
 
+template <bool TA, bool TB, int VA, int VB, int KT, int NP>
+hipError_t gemm_bf16_go(const Gemm& g, int kchunk, dim3 grid, hipStream_t s) {
+  const size_t lds = sizeof(uint16_t) * 4 * NP * 64 * (KT + kPad16);
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_bf16_kernel<TA, TB, VA, VB, KT, NP>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  gemm_bf16_kernel<TA, TB, VA, VB, KT, NP><<<grid, 256, lds, s>>>(g, kchunk);
+  return hipGetLastError();
+}
+
+template <bool TA, bool TB, int KT, int NP>
+hipError_t gemm_bf16_launch(const Gemm& g, int kchunk, dim3 grid, hipStream_t s) {
+  const bool va = vec4_ok(g.A, TA ? g.K : g.M, g.lda, g.sA) && (!TA || kchunk % 4 == 0);
+  const bool vb = vec4_ok(g.B, TB ? g.N : g.K, g.ldb, g.sB) && (TB || kchunk % 4 == 0);
+  if (va && vb) return gemm_bf16_go<TA, TB, 4, 4, KT, NP>(g, kchunk, grid, s);
+  if (va) return gemm_bf16_go<TA, TB, 4, 1, KT, NP>(g, kchunk, grid, s);
+  if (vb) return gemm_bf16_go<TA, TB, 1, 4, KT, NP>(g, kchunk, grid, s);
+  return gemm_bf16_go<TA, TB, 1, 1, KT, NP>(g, kchunk, grid, s);
+}
+
+template <bool TA, bool TB>
+hipError_t gemm_launch(const Gemm& g, Prec prec, int kchunk, dim3 grid, hipStream_t s) {
+  const bool deep = kchunk >= 96;
+  switch (prec) {
+    case Prec::BF16:
+      return deep ? gemm_bf16_launch<TA, TB, 128, 1>(g, kchunk, grid, s)
+                  : gemm_bf16_launch<TA, TB, 32, 1>(g, kchunk, grid, s);
+    case Prec::BF16x3:
+      return deep ? gemm_bf16_launch<TA, TB, 128, 2>(g, kchunk, grid, s)
+                  : gemm_bf16_launch<TA, TB, 32, 2>(g, kchunk, grid, s);
+    case Prec::BF16x6:
+      return deep ? gemm_bf16_launch<TA, TB, 64, 3>(g, kchunk, grid, s)
+                  : gemm_bf16_launch<TA, TB, 32, 3>(g, kchunk, grid, s);
+    default:
+      return deep ? gemm_f32_launch<TA, TB, 128>(g, kchunk, grid, s)
+                  : gemm_f32_launch<TA, TB, 32>(g, kchunk, grid, s);
+  }
+}
+
 hipError_t gemm_f32(const Gemm& g, Prec prec, hipStream_t s) {
-  (void)prec;
   // deep K-tiles (one global round trip covers up to 128 of K) when a
   // workgroup has that much K
   const int kchunk = chunk_for(g, 32);
   dim3 grid((unsigned)((g.M + kTM - 1) / kTM), (unsigned)((g.N + kTN - 1) / kTN),
             (unsigned)(g.batch * std::max(1, g.ksplit)));
-  const bool deep = kchunk >= 96;
-  if (!g.ta && !g.tb)
-    return deep ? gemm_f32_launch<false, false, 128>(g, kchunk, grid, s)
-                : gemm_f32_launch<false, false, 32>(g, kchunk, grid, s);
-  if (!g.ta && g.tb)
-    return deep ? gemm_f32_launch<false, true, 128>(g, kchunk, grid, s)
-                : gemm_f32_launch<false, true, 32>(g, kchunk, grid, s);
-  if (g.ta && !g.tb)
-    return deep ? gemm_f32_launch<true, false, 128>(g, kchunk, grid, s)
-                : gemm_f32_launch<true, false, 32>(g, kchunk, grid, s);
-  return deep ? gemm_f32_launch<true, true, 128>(g, kchunk, grid, s)
-              : gemm_f32_launch<true, true, 32>(g, kchunk, grid, s);
+  if (!g.ta && !g.tb) return gemm_launch<false, false>(g, prec, kchunk, grid, s);
+  if (!g.ta && g.tb) return gemm_launch<false, true>(g, prec, kchunk, grid, s);
+  if (g.ta && !g.tb) return gemm_launch<true, false>(g, prec, kchunk, grid, s);
+  return gemm_launch<true, true>(g, prec, kchunk, grid, s);
 }
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s) {

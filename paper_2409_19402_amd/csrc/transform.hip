@@ -442,35 +442,6 @@ __global__ __launch_bounds__(S * 64) void proj_f32_kernel(const TIn* __restrict_
 //   split x6: a0 q0 + a0 q1 + a1 q0 + a0 q2 + a1 q1 + a2 q0;
 //   bfloat16 input, x3 or x6: a q0 + a q1 + a q2 (exact in float32: three
 //   bfloat16 parts carry the full 24-bit significand of q).
-typedef float f32x2v __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
-  f32x2v v = {lo, hi};
-  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
-}
-__device__ __forceinline__ float bf16_lo(uint32_t d) { return __uint_as_float(d << 16); }
-__device__ __forceinline__ float bf16_hi(uint32_t d) { return __uint_as_float(d & 0xffff0000u); }
-
-template <int NA, int NQ>
-struct Split;
-// product list (a-part, q-part) per mode, smallest terms first
-template <> struct Split<1, 1> { static constexpr int n = 1; static constexpr int a[1] = {0}; static constexpr int q[1] = {0}; };
-template <> struct Split<2, 2> { static constexpr int n = 3; static constexpr int a[3] = {1, 0, 0}; static constexpr int q[3] = {0, 1, 0}; };
-template <> struct Split<3, 3> { static constexpr int n = 6; static constexpr int a[6] = {2, 1, 0, 1, 0, 0}; static constexpr int q[6] = {0, 1, 2, 0, 1, 0}; };
-template <> struct Split<1, 3> { static constexpr int n = 3; static constexpr int a[3] = {0, 0, 0}; static constexpr int q[3] = {2, 1, 0}; };
-
-// split float pairs into NP bfloat16 parts, packed: out[i] holds part i
-template <int NP>
-__device__ __forceinline__ void split_pack(float x, float y, uint32_t (&out)[NP]) {
-  out[0] = pack_bf16(x, y);
-  if constexpr (NP > 1) {
-    const float rx = x - bf16_lo(out[0]), ry = y - bf16_hi(out[0]);
-    out[1] = pack_bf16(rx, ry);
-    if constexpr (NP > 2) out[2] = pack_bf16(rx - bf16_lo(out[1]), ry - bf16_hi(out[1]));
-  }
-}
-
 template <typename TIn, int NA, int NQ, int TPL, int S>
 __global__ __launch_bounds__(S * 64) void hat_bf16_kernel(const TIn* __restrict__ A,
                                                           const float* __restrict__ Q,

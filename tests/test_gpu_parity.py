@@ -428,3 +428,44 @@ def test_proj_fused_without_workspace(pq, shape):
     with pytest.raises(_lib.ProjProdError):
         _lib.call("pq_proj", dev(A2).data_ptr(), 0, devq(Q2).data_ptr(), out2.data_ptr(), 8, 8, 40, 33, 0,
                   None, 0, s)
+
+
+FACEWISE_SHAPES = [(64, 128, 64, 4), (33, 17, 9, 3), (100, 300, 70, 2), (256, 128, 256, 4)]
+
+
+@pytest.mark.parametrize("shape", FACEWISE_SHAPES)
+def test_facewise_modes(pq, shape):
+    """Facewise product (Def. 2.3) in every precision mode: float32 and the
+    split-bfloat16 forms meet the float32 tolerance (x6 a tighter one); plain
+    bfloat16 is reported and loosely bounded."""
+    n1, m, n2, p = shape
+    rng = np.random.default_rng(900 + n1)
+    Ah = synth.gaussian(rng, n1, m, p)
+    Bh = synth.gaussian(rng, m, n2, p)
+    ref = oracle.facewise(synth.logical(Ah), synth.logical(Bh))
+    errs = {}
+    for mode in ("default", "bf16x3", "bf16x6", "bf16"):
+        errs[mode] = rel(host(pq.facewise(dev(Ah), dev(Bh), prec=mode)), ref)
+    say(f"facewise {shape}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert errs["default"] <= TOL32
+    assert errs["bf16x3"] <= TOL32
+    assert errs["bf16x6"] <= 1e-6
+    assert errs["bf16"] <= 1e-2
+
+
+@pytest.mark.parametrize("shape", [(32, 24, 20, 16, 4), (65, 31, 66, 12, 12), (128, 64, 128, 64, 16)])
+def test_qprod_modes(pq, shape):
+    """The whole product in the compensated modes (transform and facewise
+    product split, back-projection float32) against the float64 oracle."""
+    n1, m, n2, n3, p = shape
+    rng = np.random.default_rng(70 + n1)
+    A = synth.gaussian(rng, n1, m, n3)
+    B = synth.gaussian(rng, m, n2, n3)
+    Q = synth.random_orthonormal(rng, n3, p).astype(np.float32)
+    ref = oracle.qprod(synth.logical(A), synth.logical(B), Q)
+    errs = {mode: rel(host(pq.qprod(dev(A), dev(B), devq(Q), prec=mode)), ref)
+            for mode in ("bf16x3", "bf16x6", "bf16")}
+    say(f"qprod modes {shape}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert errs["bf16x3"] <= TOL32
+    assert errs["bf16x6"] <= 1e-6
+    assert errs["bf16"] <= 1e-2
