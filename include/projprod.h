@@ -42,8 +42,14 @@
  *                    is split three ways instead, which is exact in float32
  *   PQ_PREC_BF16X6   three-way split of both operands, 6 passes
  * The modes apply to the forward transform A x_3 Q^T (pq_hat and the
- * transform steps of pq_qprod and pq_tsvdq).  The return transform, the fused
- * projection and the facewise products run on float32 MFMA in every mode.
+ * transform steps of pq_qprod, pq_proj and pq_tsvdq), to the facewise product
+ * (pq_facewise and the facewise step of pq_qprod) and to the return
+ * transform (pq_unhat for p <= 32; float32 above).  Inside pq_qprod,
+ * pq_proj and pq_tsvdq the return transform of the X3 mode runs as X6: it is
+ * bound by its writes, so the extra products are free, and they keep the
+ * error of the whole chain well inside the float32 tolerance.  The fused
+ * projection, the tSVDQ's own factor products and the adjoints run on
+ * float32 MFMA in every mode.
  */
 #ifndef PROJPROD_H
 #define PROJPROD_H

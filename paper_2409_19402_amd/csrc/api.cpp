@@ -118,6 +118,13 @@ hipError_t do_hat(const void* A, int a_dtype, const void* Q, void* Ah, int64_t N
                      n3, p, prec, s);
 }
 
+// Precision of the back-projection inside a composite call: the split x3
+// mode runs it as x6.  The return transform is bound by its writes, so the
+// extra part products cost nothing, and they keep the error of the whole
+// chain (transform, facewise step, back-projection) well inside the float32
+// tolerance.
+Prec back_prec(Prec p) { return p == Prec::BF16x3 ? Prec::BF16x6 : p; }
+
 hipError_t do_unhat(const void* Ah, const void* Q, void* A, int dtype, int64_t N, int n3, int p,
                     Prec prec, hipStream_t s) {
   PQ_PROF("unhat", s);
@@ -296,7 +303,7 @@ int pq_proj(const void* A, int a_dtype, const void* Q, void* out, int64_t n1, in
   if (p > 512 && a_dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
   const int dt = a_dtype == PQ_F64 ? PQ_F64 : PQ_F32;
   PQ_TRY(do_hat(A, a_dtype, Q, ws, N, (int)n3, (int)p, (Prec)prec, stream));
-  PQ_TRY(do_unhat(ws, Q, out, dt, N, (int)n3, (int)p, (Prec)prec, stream));
+  PQ_TRY(do_unhat(ws, Q, out, dt, N, (int)n3, (int)p, back_prec((Prec)prec), stream));
   return PQ_OK;
 }
 
@@ -346,7 +353,7 @@ int pq_qprod(const void* A, const void* B, int ab_dtype, const void* Q, void* C,
   Gemm g = face_gemm(false, false, (int)n1, (int)n2, (int)m, Ah, n1, n1 * m, Bh, m, m * n2, Ch, n1,
                      n1 * n2, (int)p);
   PQ_TRY(do_gemm("facewise_gemm", g, dt, pr, stream));
-  PQ_TRY(do_unhat(Ch, Q, C, dt, n1 * n2, (int)n3, (int)p, pr, stream));
+  PQ_TRY(do_unhat(Ch, Q, C, dt, n1 * n2, (int)n3, (int)p, back_prec(pr), stream));
   return PQ_OK;
 }
 
@@ -580,11 +587,11 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
     Gemm g = cols ? face_gemm(false, true, in1, in2, ik, Fo, n1, n1 * k, Ys, n2, n2 * k, Akh, n1, N, ip)
                   : face_gemm(false, true, in1, in2, ik, Ys, n1, n1 * k, Fo, n2, n2 * k, Akh, n1, N, ip);
     PQ_TRY(do_gemm("approx_gemm", g, dt, Prec::Default, stream));
-    PQ_TRY(do_unhat(Akh, Q, Ak, dt, N, (int)n3, ip, pr, stream));
+    PQ_TRY(do_unhat(Akh, Q, Ak, dt, N, (int)n3, ip, back_prec(pr), stream));
   }
-  if (Uk) PQ_TRY(do_unhat(Uhat, Q, Uk, dt, n1 * k, (int)n3, ip, pr, stream));
-  if (Vk) PQ_TRY(do_unhat(Vhat, Q, Vk, dt, n2 * k, (int)n3, ip, pr, stream));
-  if (Sk) PQ_TRY(do_unhat(s, Q, Sk, dt, k, (int)n3, ip, pr, stream));
+  if (Uk) PQ_TRY(do_unhat(Uhat, Q, Uk, dt, n1 * k, (int)n3, ip, back_prec(pr), stream));
+  if (Vk) PQ_TRY(do_unhat(Vhat, Q, Vk, dt, n2 * k, (int)n3, ip, back_prec(pr), stream));
+  if (Sk) PQ_TRY(do_unhat(s, Q, Sk, dt, k, (int)n3, ip, back_prec(pr), stream));
   return PQ_OK;
 }
 

@@ -574,6 +574,171 @@ __global__ __launch_bounds__(S * 64) void hat_bf16_kernel(const TIn* __restrict_
   }
 }
 
+// ---- return transform, strip per wave -----------------------------------------
+// Each wave owns a strip of 32*VEC tubes and keeps Chat(:, strip) (p <= 32) in
+// registers; the workgroups along y take the 32-row tiles of the output in
+// turn.  Per tile the 32 x p block of Q is read through the cache (the next
+// tile's entries are loaded before the current tile's MFMAs), the tile is
+// formed on the MFMA and written with VEC-wide stores.  No LDS, no barrier.
+// float32: v_mfma_f32_32x32x2f32 over pairs of channels; split-bfloat16:
+// v_mfma_f32_32x32x16_bf16 over 16 channels at a time, both operands split
+// into parts (Split<NA, NQ>: Chat parts x Q parts).
+template <int VEC, int W, int MW>
+__global__ __launch_bounds__(W * 64, MW) void unhat_strip_kernel(const float* __restrict__ Ah,
+                                                                 const float* __restrict__ Q,
+                                                                 float* __restrict__ C, int64_t N, int n3, int p) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 31, kh = lane >> 5;
+  const int64_t xl = ((int64_t)blockIdx.x * W + wave) * (32 * VEC) + (int64_t)VEC * n;
+  const bool active = xl < N;
+  const int64_t xs = active ? xl : N - VEC;
+  const int ntiles = (n3 + 31) >> 5;
+  float b[16][VEC];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int l = 2 * s + kh;
+    load_vec<VEC, float>(Ah + (int64_t)min(l, p - 1) * N + xs, b[s]);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) b[s][q] = (l < p) ? b[s][q] : 0.f;
+  }
+  auto qload = [&](int tile, float (&a)[16]) {
+    const int t = min(tile * 32 + n, n3 - 1);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) a[s] = Q[(int64_t)t * p + min(2 * s + kh, p - 1)];
+  };
+  float a0[16], a1[16];
+  int tile = blockIdx.y;
+  qload(min(tile, ntiles - 1), a0);
+  while (tile < ntiles) {
+    const int nxt = tile + gridDim.y;
+    qload(min(nxt, ntiles - 1), a1);
+    __builtin_amdgcn_sched_barrier(0);
+    f32x16 acc[VEC];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[q][j] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      if (2 * s < p) {
+        const float av = (2 * s + kh < p) ? a0[s] : 0.f;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b[s][q], acc[q], 0, 0, 0);
+      }
+    }
+    if (active) {
+      const int t0 = tile * 32;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int t = t0 + 8 * (j >> 2) + 4 * kh + (j & 3);
+        if (t < n3) {
+          float v[VEC];
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) v[q] = acc[q][j];
+          store_vec<VEC>(C + (int64_t)t * N + xl, v);
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) a0[s] = a1[s];
+    tile = nxt;
+  }
+}
+
+template <int VEC, int W, int MW, int NA, int NQ>
+__global__ __launch_bounds__(W * 64, MW) void unhat_bstrip_kernel(const float* __restrict__ Ah,
+                                                                  const float* __restrict__ Q,
+                                                                  float* __restrict__ C, int64_t N, int n3, int p) {
+  using SP = Split<NA, NQ>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 31, kh = lane >> 5;
+  const int64_t xl = ((int64_t)blockIdx.x * W + wave) * (32 * VEC) + (int64_t)VEC * n;
+  const bool active = xl < N;
+  const int64_t xs = active ? xl : N - VEC;
+  const int ntiles = (n3 + 31) >> 5;
+  const int nsteps = (p + 15) >> 4;  // 16 channels per MFMA (p <= 32)
+  // Chat(16 st + 8 kh + i, strip) split into NA parts, packed by pairs of i
+  uint32_t bw[2][VEC][NA][4];
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int q2 = 0; q2 < 4; ++q2) {
+      float x0[VEC], x1[VEC];
+      const int l0 = 16 * st + 8 * kh + 2 * q2;
+      load_vec<VEC, float>(Ah + (int64_t)min(l0, p - 1) * N + xs, x0);
+      load_vec<VEC, float>(Ah + (int64_t)min(l0 + 1, p - 1) * N + xs, x1);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        uint32_t parts[NA];
+        split_pack<NA>(l0 < p ? x0[c] : 0.f, l0 + 1 < p ? x1[c] : 0.f, parts);
+#pragma unroll
+        for (int i = 0; i < NA; ++i) bw[st][c][i][q2] = parts[i];
+      }
+    }
+  auto qload = [&](int tile, float (&a)[2][8]) {
+    const int t = min(tile * 32 + n, n3 - 1);
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a[st][i] = Q[(int64_t)t * p + min(16 * st + 8 * kh + i, p - 1)];
+  };
+  float a0[2][8], a1[2][8];
+  int tile = blockIdx.y;
+  qload(min(tile, ntiles - 1), a0);
+  while (tile < ntiles) {
+    const int nxt = tile + gridDim.y;
+    qload(min(nxt, ntiles - 1), a1);
+    __builtin_amdgcn_sched_barrier(0);
+    f32x16 acc[VEC];
+#pragma unroll
+    for (int c = 0; c < VEC; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[c][j] = 0.f;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      if (st < nsteps) {
+        uint32_t qw[NQ][4];
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) {
+          const int l0 = 16 * st + 8 * kh + 2 * q2;
+          uint32_t parts[NQ];
+          split_pack<NQ>(l0 < p ? a0[st][2 * q2] : 0.f, l0 + 1 < p ? a0[st][2 * q2 + 1] : 0.f, parts);
+#pragma unroll
+          for (int i = 0; i < NQ; ++i) qw[i][q2] = parts[i];
+        }
+#pragma unroll
+        for (int c = 0; c < VEC; ++c)
+#pragma unroll
+          for (int pr = 0; pr < SP::n; ++pr) {
+            const bf16x8 aop = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(qw[SP::q[pr]]));
+            const bf16x8 bop = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(bw[st][c][SP::a[pr]]));
+            acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop, bop, acc[c], 0, 0, 0);
+          }
+      }
+    }
+    if (active) {
+      const int t0 = tile * 32;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int t = t0 + 8 * (j >> 2) + 4 * kh + (j & 3);
+        if (t < n3) {
+          float v[VEC];
+#pragma unroll
+          for (int c = 0; c < VEC; ++c) v[c] = acc[c][j];
+          store_vec<VEC>(C + (int64_t)t * N + xl, v);
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a0[st][i] = a1[st][i];
+    tile = nxt;
+  }
+}
+
 // ---- split-bfloat16 transform, one strip per workgroup ------------------------
 // The strip design of hat_strip_kernel for the bfloat16 MFMA
 // (v_mfma_f32_32x32x16_bf16): a step is 16 frontal slices, the lanes of
@@ -862,6 +1027,42 @@ void strip_cands(int vmax, std::vector<Cfg>& v) {
     }
 }
 
+template <int VEC, int W, int MW, int NA, int NQ>
+hipError_t unhat_strip_go(const float* Ah, const float* Q, float* C, int64_t N, int n3, int p, hipStream_t s) {
+  const int64_t strips = (N + 32 * VEC - 1) / (32 * VEC);
+  const int64_t wgs = (strips + W - 1) / W;
+  const int ntiles = (n3 + 31) / 32;
+  // enough workgroups to fill 256 CUs several times over
+  const int ysplit = (int)std::min<int64_t>(ntiles, std::max<int64_t>(1, (4096 + wgs - 1) / wgs));
+  dim3 grid((unsigned)wgs, (unsigned)ysplit);
+  if constexpr (NA == 0)
+    unhat_strip_kernel<VEC, W, MW><<<grid, W * 64, 0, s>>>(Ah, Q, C, N, n3, p);
+  else
+    unhat_bstrip_kernel<VEC, W, MW, NA, NQ><<<grid, W * 64, 0, s>>>(Ah, Q, C, N, n3, p);
+  return hipGetLastError();
+}
+
+// unhat strip candidates (vec, waves, min waves per SIMD); NA = 0: float32
+template <int NA, int NQ>
+hipError_t unhat_strip_any(const float* Ah, const float* Q, float* C, int64_t N, int n3, int p, Cfg c,
+                           hipStream_t s) {
+#define PQ_U(V, W, MW) \
+  if (c.vec == V && c.waves == W && c.strip == MW) return unhat_strip_go<V, W, MW, NA, NQ>(Ah, Q, C, N, n3, p, s);
+  PQ_U(4, 4, 2) PQ_U(4, 2, 2) PQ_U(2, 4, 4) PQ_U(2, 8, 4) PQ_U(1, 8, 4)
+#undef PQ_U
+  return hipErrorInvalidValue;
+}
+
+void unhat_strip_cands(int vmax, std::vector<Cfg>& v) {
+  static const int t[][3] = {{4, 4, 2}, {4, 2, 2}, {2, 4, 4}, {2, 8, 4}, {1, 8, 4}};
+  for (const auto& r : t)
+    if (r[0] <= vmax) {
+      Cfg c{r[0], r[1], 0};
+      c.strip = r[2];
+      v.push_back(c);
+    }
+}
+
 template <typename TIn, int NA, int NQ, int TPL, int S, int MW>
 hipError_t hat_bstrip_go(const TIn* A, const float* Q, float* Ah, int64_t N, int n3, int p, hipStream_t s) {
   const size_t lds = red_bytes(TPL, S);
@@ -1036,11 +1237,31 @@ hipError_t hat_f32(const void* A, bool a_bf16, const float* Q, float* Ah, int64_
 
 hipError_t unhat_f32(const float* Ah, const float* Q, float* C, int64_t N, int n3, int p, Prec prec,
                      hipStream_t s) {
-  (void)prec;  // the return transform runs on float32 MFMA in every mode
   const int vmax = pick_vec(N, {Ah, C}, 4);
-  const std::vector<Cfg> c = cands(vmax, false);
-  return tuned_launch(key_of("unhat", 0, 0, N, n3, p, vmax), (int)c.size(), default_strips(c, N), s,
-                      [&](int i) { return unhat_f32_any(Ah, Q, C, N, n3, p, c[i], s); });
+  // strip kernels (p <= 32) in the requested precision, then the older
+  // LDS-staged float32 kernels
+  std::vector<Cfg> c;
+  if (p <= 32) unhat_strip_cands(vmax, c);
+  const int nstrip = (int)c.size();
+  if (prec == Prec::Default)
+    for (const Cfg& g : cands(vmax, false)) c.push_back(g);
+  int dflt = 0;
+  if (nstrip == 0) {
+    if (prec != Prec::Default)  // p > 32: the split forms are not built for this width
+      for (const Cfg& g : cands(vmax, false)) c.push_back(g);
+    dflt = default_strips(c, N);
+  }
+  return tuned_launch(key_of("unhat", (int)prec, 0, N, n3, p, vmax), (int)c.size(), dflt, s,
+                      [&](int i) -> hipError_t {
+                        const Cfg& g = c[i];
+                        if (!g.strip) return unhat_f32_any(Ah, Q, C, N, n3, p, g, s);
+                        switch (prec) {
+                          case Prec::BF16: return unhat_strip_any<1, 1>(Ah, Q, C, N, n3, p, g, s);
+                          case Prec::BF16x3: return unhat_strip_any<2, 2>(Ah, Q, C, N, n3, p, g, s);
+                          case Prec::BF16x6: return unhat_strip_any<3, 3>(Ah, Q, C, N, n3, p, g, s);
+                          default: return unhat_strip_any<0, 0>(Ah, Q, C, N, n3, p, g, s);
+                        }
+                      });
 }
 
 bool proj_fused_ok(int n3, int p) { return p <= 32 && n3 <= 480; }

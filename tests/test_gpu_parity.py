@@ -469,3 +469,20 @@ def test_qprod_modes(pq, shape):
     assert errs["bf16x3"] <= TOL32
     assert errs["bf16x6"] <= 1e-6
     assert errs["bf16"] <= 1e-2
+
+
+@pytest.mark.parametrize("shape", [(50, 30, 200, 20), (7, 9, 33, 5), (64, 64, 256, 32), (17, 6, 300, 37)])
+def test_unhat_modes(pq, shape):
+    """Back-projection in every precision mode (p > 32 falls back to float32)."""
+    n1, n2, n3, p = shape
+    rng = np.random.default_rng(950 + n3)
+    Ah = synth.gaussian(rng, n1, n2, p)
+    Q = synth.random_orthonormal(rng, n3, p).astype(np.float32)
+    ref = oracle.unhat(synth.logical(Ah), Q)
+    errs = {mode: rel(host(pq.unhat(dev(Ah), devq(Q), prec=mode)), ref)
+            for mode in ("default", "bf16x3", "bf16x6", "bf16")}
+    say(f"unhat {shape}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert errs["default"] <= TOL32
+    assert errs["bf16x3"] <= TOL32
+    assert errs["bf16x6"] <= 1e-6
+    assert errs["bf16"] <= 1e-2
