@@ -228,6 +228,25 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
                      void* dA, void* dQ, void* ws, size_t ws_bytes,
                      hipStream_t stream);
 
+/* ---- the data-dependent transform Q = U3 (Thm. 4.3, Cor. 4.1) ------------ */
+/*
+ * Q = U3(:, 1:p), the leading p left singular vectors of the mode-3
+ * unfolding A_(3) (n3 x n1 n2): the choice of Q that Thm. 4.3 shows optimal
+ * for the projection error.  A: n1 x n2 x n3 face-major, a_dtype F32 or
+ * F64.  Computed as the top-p eigenvectors of the Gram matrix
+ * A_(3) A_(3)^T (matrix-core product split over the n1 n2 tubes, slices
+ * summed in float64) by float64 one-sided Jacobi; each column is signed so
+ * that its largest-magnitude entry (the first on ties) is positive.
+ * Outputs (float32 for F32 data, float64 for F64): Q n3 x p row-major;
+ * lambda (may be NULL) p values, the eigenvalues sigma_i(A_(3))^2 as
+ * Rayleigh quotients, descending.  info_dev (device int[3], may be NULL) as
+ * in pq_tsvdq.  Eigenvectors of (nearly) equal eigenvalues are determined
+ * only up to a rotation within their span.  Workspace: pq_u3_workspace.
+ */
+size_t pq_u3_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int a_dtype);
+int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_t p, void* Q, void* lambda,
+          int* info_dev, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- truncated tSVDQ (Alg. 4.1) ------------------------------------------ */
 /*
  * Truncated *_Q-SVD of A (n1 x n2 x n3, a_dtype F32, BF16 or F64) with rank
@@ -251,7 +270,7 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
  * 1e-13; two singular vectors come out coupled by about tol / (2 x the
  * relative gap of their singular values); for F32 and BF16 data the final
  * sweeps work on Gram matrices of the vectors and use max(tol, 1e-10)),
- * max_sweeps caps the sweeps of each phase (<= 0: 20 for float32 data,
+ * max_sweeps caps the sweeps of each phase (<= 0: 12 for float32 data,
  * 30 for float64; at most 100).  info_dev (device int[3], may be NULL)
  * receives [0] = the largest number of sweeps any face used (both phases),
  * [1] = the number of faces whose last phase hit max_sweeps before
@@ -306,7 +325,7 @@ int pq_batched_workspace(const pq_instance* inst, int count, size_t* bytes);
  * for the handle only.  The transforms, facewise products and
  * back-projections run per instance; the Jacobi sweeps of all tSVDQ
  * instances run as grouped launches over every face at once.  max_sweeps
- * (<= 0: 20) and tol (<= 0: 1e-13) as in pq_tsvdq; info_dev (device int[3],
+ * (<= 0: 12) and tol (<= 0: 1e-13) as in pq_tsvdq; info_dev (device int[3],
  * may be NULL) receives the sweep statistics over all faces, as in pq_tsvdq.
  * Every pointer of inst[] and ws is baked into the graph: they must stay
  * valid until pq_batched_destroy, and each run reads and writes them again.

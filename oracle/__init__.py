@@ -21,7 +21,7 @@ Parity status of each function is listed in ``PARITY`` below.
 
 from .core import (  # noqa: F401
     unfold3, fold3, mode3, facewise, mprod, hat, unhat, qprod, proj,
-    identity_tensor, ftranspose, check_q, fro2,
+    identity_tensor, ftranspose, check_q, fro2, u3,
 )
 from .tsvdq import (  # noqa: F401
     tsvdq, tsvdq_error_terms, relative_error, tsvdq_ii, TSVDQResult,
@@ -30,6 +30,8 @@ from .grad import qprod_backward, proj_backward  # noqa: F401
 
 # Which pin holds each oracle function (see tests/test_oracle_pins.py).
 PARITY = {
+    "u3": "pinned: Gram eigen-decomposition (independent route), orthonormality, "
+          "Cor 4.1 face norms",
     "unfold3/fold3/mode3": "pinned: Appendix A printed tubes; brute-force loops",
     "facewise": "pinned: brute-force loops",
     "mprod": "pinned: Appendix A printed a*_M b",

@@ -105,3 +105,19 @@ def check_q(Q):
     (the precondition Q in St_{n3,p} of Def. 3.1)."""
     Q = _f64(Q)
     return float(np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))))
+
+
+def u3(A, p):
+    """Q = U3(:, :p): the leading p left singular vectors of the mode-3
+    unfolding A_(3) (the data-dependent transform of Thm. 4.3 and Cor. 4.1),
+    with each column signed so that its largest-magnitude entry is positive
+    (the first such entry on ties).  Returns (Q, sigma^2) with sigma the
+    leading p singular values of A_(3)."""
+    A = _f64(A)
+    U, S, _ = np.linalg.svd(unfold3(A), full_matrices=False)
+    Q = U[:, :p].copy()
+    for j in range(p):
+        i = int(np.argmax(np.abs(Q[:, j])))
+        if Q[i, j] < 0:
+            Q[:, j] = -Q[:, j]
+    return Q, S[:p] ** 2

@@ -45,6 +45,8 @@ SIGNATURES = {
     "pq_tsvdq_workspace": (_sz, [_i64, _i64, _i64, _i64, _i64, _i32]),
     "pq_tsvdq": (_i32, [_vp, _i32, _vp, _i64, _i64, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _vp,
                         _vp, _vp, _vp, _dbl, _i32, _vp, _vp, _sz, _vp]),
+    "pq_u3_workspace": (_sz, [_i64, _i64, _i64, _i64, _i32]),
+    "pq_u3": (_i32, [_vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "pq_batched_workspace": (_i32, [_vp, _i32, _vp]),
     "pq_batched_plan": (_i32, [_vp, _i32, _i32, _dbl, _vp, _vp, _sz, _vp, _vp]),
     "pq_batched_run": (_i32, [_vp, _vp]),

@@ -21,7 +21,7 @@ __all__ = [
     "empty", "from_storage", "is_face_major", "autotune", "autotune_save", "autotune_load",
     "check_q", "hat", "unhat", "proj", "facewise",
     "qprod", "qprod_backward", "proj_backward", "tsvdq", "TSVDQ", "QProd", "Proj",
-    "Batch", "batched",
+    "Batch", "batched", "u3",
 ]
 
 _DT = {torch.float32: PQ_F32, torch.float64: PQ_F64, torch.bfloat16: PQ_BF16}
@@ -284,6 +284,24 @@ def proj(A, Q, prec="default"):
 
 
 TSVDQ = namedtuple("TSVDQ", "Uhat s Vhat Uk Sk Vk Ak info")
+
+
+def u3(A, p):
+    """Q = U3(:, :p) of A (Thm. 4.3): the leading p left singular vectors of
+    the mode-3 unfolding, as an (n3, p) tensor (float32, or float64 for
+    float64 data), with the eigenvalues sigma_i(A_(3))^2 (p,) and the Jacobi
+    info int32[3]."""
+    _tensor(A, "A", (torch.float32, torch.float64))
+    n1, n2, n3 = A.shape
+    dev = A.device
+    Q = torch.empty((n3, p), dtype=A.dtype, device=dev)
+    lam = torch.empty(p, dtype=A.dtype, device=dev)
+    info = torch.zeros(3, dtype=torch.int32, device=dev)
+    lib = _lib.load()
+    wsb, nb = _ws(lib.pq_u3_workspace(n1, n2, n3, p, _DT[A.dtype]), dev)
+    call("pq_u3", _ptr(A), _DT[A.dtype], n1, n2, n3, p, _ptr(Q), _ptr(lam), _ptr(info), _ptr(wsb), nb,
+         _stream(dev))
+    return Q, lam, info
 
 
 def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_sweeps=0):

@@ -91,7 +91,7 @@ struct Arena {
   bool fits() const { return used <= cap; }
 };
 
-constexpr int kDefaultSweeps32 = 20;  // per phase; float32 faces need 6-12 coarse sweeps
+constexpr int kDefaultSweeps32 = 12;  // per phase; float32 faces need 6-12 coarse sweeps (more go on in float64)
 constexpr int kDefaultSweeps64 = 30;
 // Jacobi thresholds on |a.c| / (|a||c|): the float32 phase stops at the coarse
 // one, the float64 phase polishes to the default final one.
@@ -473,6 +473,64 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype, int
     PQ_TRY(do_gemm("dq_gemm", dq_gemm(Gh, A, (int)p, (int)n3, N, pb + slab * ks, ks), dtype, pr, stream));
     PQ_TRY(do_sum(parts, 2 * ks, p * n3, p * n3, dQ, dtype, stream));
   }
+  return PQ_OK;
+}
+
+size_t pq_u3_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int a_dtype) {
+  const int64_t N = n1 * n2;
+  const int ks = ksplit_for(N);
+  const size_t e = elem(a_dtype == PQ_F64 ? PQ_F64 : PQ_F32);
+  return align_up(e * (size_t)ks * n3 * n3)   // split-K slices of the Gram matrix
+         + align_up(8 * (size_t)n3 * n3) * 2  // Gram matrix (float64) and the Jacobi copy
+         + align_up(sizeof(int) * 2)          // sweeps used
+         + align_up(sizeof(int) * kMaxSweepsCap)
+         + align_up(8 * (size_t)n3 * p);      // the p leading eigenvectors
+}
+
+int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_t p, void* Q, void* lambda,
+          int* info_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!A || !Q) return PQ_ERR_NULL;
+  if (a_dtype != PQ_F32 && a_dtype != PQ_F64) return PQ_ERR_DTYPE;
+  PQ_CHECK(check_dims({n1, n2, n3}));
+  PQ_CHECK(check_p(n3, p));
+  if (n3 > 4096) return PQ_ERR_UNSUPPORTED;
+  for (const void* o : {Q, lambda})
+    if (o && o == A) return PQ_ERR_ALIAS;
+  if (lambda && lambda == Q) return PQ_ERR_ALIAS;
+  if (!ws || ws_bytes < pq_u3_workspace(n1, n2, n3, p, a_dtype)) return PQ_ERR_WORKSPACE;
+  const bool f64 = a_dtype == PQ_F64;
+  const int64_t N = n1 * n2;
+  const int ks = ksplit_for(N);
+  const int in3 = (int)n3, ip = (int)p;
+  const size_t e = elem(f64 ? PQ_F64 : PQ_F32);
+  Arena ar(ws, ws_bytes);
+  void* parts = ar.take(e * (size_t)ks * n3 * n3);
+  double* G = static_cast<double*>(ar.take(8 * (size_t)n3 * n3));
+  double* W = static_cast<double*>(ar.take(8 * (size_t)n3 * n3));
+  int* used = static_cast<int*>(ar.take(sizeof(int) * 2));
+  int* flags = static_cast<int*>(ar.take(sizeof(int) * kMaxSweepsCap));
+  double* F = static_cast<double*>(ar.take(8 * (size_t)n3 * p));
+  // Gram matrix A_(3) A_(3)^T: split-K over the n1 n2 tubes, slices summed in
+  // a fixed order in float64
+  PQ_TRY(do_gemm("u3_gram", dq_gemm(A, A, in3, in3, N, parts, ks), f64 ? PQ_F64 : PQ_F32, Prec::Default, stream));
+  {
+    PQ_PROF("sum_partials", stream);
+    if (f64) PQ_TRY(pq::sum_partials_f64(static_cast<const double*>(parts), ks, n3 * n3, n3 * n3, G, stream));
+    else PQ_TRY(pq::sum_to_f64(static_cast<const float*>(parts), ks, n3 * n3, n3 * n3, G, stream));
+  }
+  // its eigenvectors: one-sided Jacobi on the symmetric positive semidefinite
+  // G (converged columns are lambda_j u_j), float64 throughout
+  PQ_TRY(hipMemcpyAsync(W, G, 8 * (size_t)n3 * n3, hipMemcpyDeviceToDevice, stream));
+  PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, kDefaultSweeps64, kPolishTol, used, flags, stream));
+  {
+    PQ_PROF("jacobi_finalize", stream);
+    PQ_TRY(pq::jacobi_finalize_f64(W, 1, in3, in3, ip, F, stream));
+  }
+  {
+    PQ_PROF("u3_finish", stream);
+    PQ_TRY(pq::u3_finish(F, G, in3, ip, Q, lambda, f64, stream));
+  }
+  if (info_dev) PQ_TRY(pq::jacobi_info(used, nullptr, 1, kDefaultSweeps64, 0, info_dev, stream));
   return PQ_OK;
 }
 

@@ -87,6 +87,14 @@ hipError_t sum_partials_f64(const double* parts, int nparts, int64_t stride,
                             int64_t count, double* out, hipStream_t s);
 
 // ---- small helpers (misc.hip) ---------------------------------------------
+// ---- Q = U3 (misc.hip) ---------------------------------------------------------
+// out = sum of nparts float32 slices (stride apart), in float64, fixed order
+hipError_t sum_to_f64(const float* parts, int nparts, int64_t stride, int64_t count, double* out, hipStream_t s);
+// Q (n3 x p row-major, float32 or float64) from the p normalised eigenvectors
+// F (vector-major, n3 each): columns signed so that the largest-magnitude
+// entry is positive; lambda[r] = f_r^T G f_r (G n3 x n3)
+hipError_t u3_finish(const double* F, const double* G, int n3, int p, void* Q, void* lambda, bool f64,
+                     hipStream_t s);
 hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, hipStream_t s);
 
 // ---- facewise one-sided Jacobi SVD (jacobi.hip) -----------------------------

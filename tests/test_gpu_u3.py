@@ -1,0 +1,70 @@
+"""The GPU construction of Q = U3 (Thm. 4.3) against the float64 oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import dev, host, rel, say
+from paper_2409_19402_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    from paper_2409_19402_amd import binding
+    return binding
+
+
+def _gapped(seed, n1, n2, n3, sig, noise, dtype):
+    """A_(3) = U diag(sig) W^T + noise: leading singular values well apart."""
+    rng = np.random.default_rng(seed)
+    r = len(sig)
+    U = synth.random_orthonormal(rng, n3, r)
+    W = synth.random_orthonormal(rng, n1 * n2, r)
+    M = (U * np.asarray(sig)) @ W.T + noise * rng.standard_normal((n3, n1 * n2))
+    return M.reshape(n3, n2, n1).astype(dtype)  # face-major storage: row t = slice t
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float32, 1e-5), (np.float64, 1e-10)])
+def test_u3_gapped(pq, dtype, tol):
+    A_st = _gapped(41, 30, 20, 40, [10, 8, 6.5, 5, 4, 3, 2.5, 2], 1e-3, dtype)
+    p = 6
+    say(f"u3 gapped {dtype.__name__}")
+    Q, lam, info = pq.u3(dev(A_st), p)
+    assert int(info[1].item()) == 0
+    Qr, lamr = oracle.u3(synth.logical(A_st), p)
+    Qg = host(Q)
+    assert np.max(np.abs(Qg - Qr)) <= tol * 10
+    assert rel(host(lam), lamr) <= tol
+    np.testing.assert_allclose(Qg.T @ Qg, np.eye(p), atol=tol * 10)
+    # Cor. 4.1: with Q = U3 the transform faces have norms sigma_i(A_(3))
+    norms2 = np.sum(oracle.hat(synth.logical(A_st), Qg) ** 2, axis=(0, 1))
+    assert rel(norms2, lamr) <= tol * 10
+
+
+def test_u3_video(pq):
+    """Video-shaped data (10 smooth components + noise): the captured energy
+    equals the optimum of Thm. 4.3; the signal eigenvectors (well separated
+    from the noise floor) match the oracle column by column."""
+    rng = np.random.default_rng(42)
+    A_st = synth.video(rng, 48, 64, 100)
+    p = 20
+    say("u3 video-shaped 48x64x100")
+    Q, lam, info = pq.u3(dev(A_st), p)
+    assert int(info[1].item()) == 0
+    Al = synth.logical(A_st)
+    Qr, lamr = oracle.u3(Al, p)
+    Qg = host(Q)
+    np.testing.assert_allclose(Qg.T @ Qg, np.eye(p), atol=1e-5)
+    captured = np.sum(oracle.hat(Al, Qg) ** 2)
+    assert abs(captured - np.sum(lamr)) <= 1e-5 * np.sum(lamr)
+    assert rel(host(lam), lamr) <= 1e-5
+    gaps = lamr[:-1] - lamr[1:]
+    strong = [j for j in range(p - 1) if gaps[j] > 1e-3 * lamr[0] and (j == 0 or gaps[j - 1] > 1e-3 * lamr[0])]
+    assert len(strong) >= 5
+    for j in strong:
+        assert np.max(np.abs(Qg[:, j] - Qr[:, j])) <= 1e-4, j

@@ -408,3 +408,22 @@ def test_synth_generators_shapes_and_structure():
     assert v.shape == (20, 32, 24) and v.dtype == np.float32
     shapes = synth.batched_shapes(count=8)
     assert all(4 <= s["p"] <= min(32, s["n3"]) for s in shapes)
+
+
+def test_u3_oracle():
+    """oracle.u3 (an SVD of the mode-3 unfolding) against the Gram
+    eigen-decomposition of the input generator, the orthonormality of Q,
+    and Cor. 4.1: the transform faces have norms sigma_i(A_(3))."""
+    rng = np.random.default_rng(31)
+    A_st = synth.gaussian(rng, 7, 6, 11, np.float64)
+    A = synth.logical(A_st)
+    p = 5
+    Q, lam = oracle.u3(A, p)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(p), atol=1e-13)
+    G = oracle.unfold3(A) @ oracle.unfold3(A).T
+    np.testing.assert_allclose(np.diag(Q.T @ G @ Q), lam, rtol=1e-12)
+    ref = synth.u3_leading(A_st, p)
+    np.testing.assert_allclose(Q, ref, atol=1e-10)
+    norms2 = np.sum(oracle.hat(A, Q) ** 2, axis=(0, 1))
+    np.testing.assert_allclose(norms2, lam, rtol=1e-12)
+    assert np.all(np.diff(lam) <= 0)
