@@ -286,6 +286,34 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q,
              double tol, int max_sweeps, int* info_dev,
              void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * *_Q-SVDII of A (Sec. 4.1, Alg. 4.2): the facewise SVD of Ahat = A x_3 Q^T
+ * as in pq_tsvdq, then one energy threshold over the singular values of all
+ * p faces together.  The r p values (r = min(n1, n2)) are put in one
+ * descending order (equal values ordered face-major: face l's value j at
+ * position j + l r of the flattened list), K is the smallest count whose
+ * squared values sum to at least gamma times the sum of all of them
+ * (0 < gamma <= 1; K = r p when rounding leaves every partial sum short),
+ * and rho_l = how many of face l's values are among the first K (the
+ * *_Q-multirank of the approximation, Def. 4.3).  Face l keeps its leading
+ * min(rho_l, kmax) singular triplets, 1 <= kmax <= r; pass kmax = r for the
+ * untruncated algorithm.  The selection runs in float64 on the GPU.
+ * Outputs (float32, or float64 for F64; same layout as pq_tsvdq with k =
+ * kmax): Uhat n1 x kmax x p, s kmax x p, Vhat n2 x kmax x p — required; the
+ * columns of face l beyond min(rho_l, kmax) are zero.  rho_dev (device
+ * int[p], may be NULL) receives rho before the kmax cap.  Ak (n1 x n2 x n3,
+ * optional) receives (Uhat tri Shat tri Vhat^T) x_3 Q, whose error obeys
+ * Thm. 4.4.  prec, tol, max_sweeps and info_dev as in pq_tsvdq.  Returns
+ * PQ_ERR_ARG for gamma outside (0, 1].  Workspace: pq_svdii_workspace bytes.
+ */
+size_t pq_svdii_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t kmax,
+                          int a_dtype);
+int pq_svdii(const void* A, int a_dtype, const void* Q,
+             int64_t n1, int64_t n2, int64_t n3, int64_t p, double gamma, int64_t kmax,
+             int prec, void* Uhat, void* s, void* Vhat, int* rho_dev, void* Ak,
+             double tol, int max_sweeps, int* info_dev,
+             void* ws, size_t ws_bytes, hipStream_t stream);
+
 
 /* ---- batched form: many uneven instances in one captured graph ----------- */
 /*

@@ -333,6 +333,38 @@ def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_swe
     return TSVDQ(Uh, s.t(), Vh, Uk, None if Sk is None else Sk.t(), Vk, Ak, info)
 
 
+SVDII = namedtuple("SVDII", "Uhat s Vhat rho Ak info")
+
+
+def svdii(A, Q, gamma, kmax=None, prec="default", approx=False, tol=0.0, max_sweeps=0):
+    """*_Q-SVDII (Alg. 4.2): per-face ranks rho from one energy threshold
+    gamma over the singular values of every face.  Returns SVDII(Uhat
+    n1 x kmax x p, s (kmax, p), Vhat n2 x kmax x p with face l's columns
+    beyond min(rho_l, kmax) zero, rho (int32 device tensor of p, before the
+    kmax cap), Ak [approx=True], info); kmax defaults to min(n1, n2)."""
+    _tensor(A, "A")
+    _q(Q, A.dtype)
+    n1, n2, n3 = A.shape
+    if Q.shape[0] != n3:
+        raise ValueError("Q must have n3 rows")
+    p = Q.shape[1]
+    k = min(n1, n2) if kmax is None else int(kmax)
+    od = _out_dtype(A.dtype)
+    dev = A.device
+    Uh = empty(n1, k, p, od, dev)
+    Vh = empty(n2, k, p, od, dev)
+    s = torch.empty((p, k), dtype=od, device=dev)
+    rho = torch.empty(p, dtype=torch.int32, device=dev)
+    Ak = empty(n1, n2, n3, od, dev) if approx else None
+    info = torch.zeros(3, dtype=torch.int32, device=dev)
+    lib = _lib.load()
+    wsb, nb = _ws(lib.pq_svdii_workspace(n1, n2, n3, p, k, _DT[A.dtype]), dev)
+    call("pq_svdii", _ptr(A), _DT[A.dtype], _ptr(Q), n1, n2, n3, p, float(gamma), k, PREC[prec],
+         _ptr(Uh), _ptr(s), _ptr(Vh), _ptr(rho), _ptr(Ak), float(tol), int(max_sweeps), _ptr(info),
+         _ptr(wsb), nb, _stream(dev))
+    return SVDII(Uh, s.t(), Vh, rho, Ak, info)
+
+
 class Batch:
     """A planned batch of uneven instances (pq_batched_plan).
 

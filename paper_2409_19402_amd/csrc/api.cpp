@@ -484,7 +484,8 @@ size_t pq_u3_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int a_dtyp
          + align_up(8 * (size_t)n3 * n3) * 2  // Gram matrix (float64) and the Jacobi copy
          + align_up(sizeof(int) * 2)          // sweeps used
          + align_up(sizeof(int) * kMaxSweepsCap)
-         + align_up(8 * (size_t)n3 * p);      // the p leading eigenvectors
+         + align_up(8 * (size_t)n3 * p)       // the p leading eigenvectors
+         + align_up(8 * (size_t)n3);          // norms of the converged columns
 }
 
 int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_t p, void* Q, void* lambda,
@@ -510,6 +511,7 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
   int* used = static_cast<int*>(ar.take(sizeof(int) * 2));
   int* flags = static_cast<int*>(ar.take(sizeof(int) * kMaxSweepsCap));
   double* F = static_cast<double*>(ar.take(8 * (size_t)n3 * p));
+  double* sig = static_cast<double*>(ar.take(8 * (size_t)n3));
   // Gram matrix A_(3) A_(3)^T: split-K over the n1 n2 tubes, slices summed in
   // a fixed order in float64
   PQ_TRY(do_gemm("u3_gram", dq_gemm(A, A, in3, in3, N, parts, ks), f64 ? PQ_F64 : PQ_F32, Prec::Default, stream));
@@ -524,7 +526,8 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
   PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, kDefaultSweeps64, kPolishTol, used, flags, stream));
   {
     PQ_PROF("jacobi_finalize", stream);
-    PQ_TRY(pq::jacobi_finalize_f64(W, 1, in3, in3, ip, F, stream));
+    PQ_TRY(pq::jacobi_norms_f64(W, 1, in3, in3, sig, nullptr, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(W, sig, 1, in3, in3, ip, nullptr, F, stream));
   }
   {
     PQ_PROF("u3_finish", stream);
@@ -544,53 +547,58 @@ size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t
          + align_up(8 * n1 * n2 * p)                      // float64 Jacobi vectors
          + align_up(sizeof(int) * p) * 2                  // sweeps per face, both phases
          + align_up(sizeof(int) * p * kMaxSweepsCap)      // per-sweep rotation flags
+         + align_up(8 * mn * p)                           // every singular value
          + align_up(8 * mx * k * p)                       // top-k Jacobi vectors
          + align_up(8 * mn * k * p)                       // other side (float64)
          + align_up(e * mn * k * p)                       // other side, ordered, unscaled
          + align_up(e * n1 * n2 * p);                     // transform-domain A_k
 }
 
-int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p,
-             int64_t k, int prec, void* Uhat, void* s, void* Vhat, void* Uk, void* Sk, void* Vk, void* Ak,
-             double tol, int max_sweeps, int* info_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (!A || !Q || !Uhat || !s || !Vhat) return PQ_ERR_NULL;
-  PQ_CHECK(check_in_dtype(a_dtype));
-  PQ_CHECK(check_dims({n1, n2, n3}));
-  PQ_CHECK(check_p(n3, p));
-  PQ_CHECK(check_area(n1, n2));
-  if (k < 1 || k > std::min(n1, n2)) return PQ_ERR_K;
-  PQ_CHECK(check_prec(prec, a_dtype));
-  const void* ins[] = {A, Q};
-  for (const void* o : {Uhat, s, Vhat, Uk, Sk, Vk, Ak})
-    for (const void* in : ins)
-      if (o && o == in) return PQ_ERR_ALIAS;
-  if (std::min(n1, n2) > 4096) return PQ_ERR_UNSUPPORTED;
-  if (p > 512 && a_dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
-  if (!ws || ws_bytes < pq_tsvdq_workspace(n1, n2, n3, p, k, a_dtype)) return PQ_ERR_WORKSPACE;
+size_t pq_svdii_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t kmax, int a_dtype) {
+  const int64_t mn = std::min(n1, n2);
+  return pq_tsvdq_workspace(n1, n2, n3, p, kmax, a_dtype)
+         + align_up(sizeof(int) * mn * p)  // global ranks
+         + align_up(8 * mn * p)            // energies in descending order
+         + align_up(sizeof(int) * p);      // multirank when the caller keeps none
+}
+
+}  // extern "C"
+
+namespace {
+
+// Steps 2-3 of Alg. 4.1 (gamma <= 0: rank k on every face) or of Alg. 4.2
+// (gamma in (0, 1]: per-face ranks rho from one energy threshold over every
+// face, each face keeping min(rho_i, k) columns, zero columns after), then
+// the approximation of Thm. 4.2 when Ak is given.  Arguments are validated
+// by the callers; the workspace is carved from ar.
+int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p,
+                 int64_t k, Prec pr, double gamma, int* rho, void* Uhat, void* s, void* Vhat, void* Ak,
+                 double tol, int max_sweeps, int* info_dev, Arena& ar, hipStream_t stream) {
   const bool f64 = a_dtype == PQ_F64;
-  if (max_sweeps <= 0) max_sweeps = f64 ? kDefaultSweeps64 : kDefaultSweeps32;
-  if (max_sweeps > kMaxSweepsCap) return PQ_ERR_ARG;
-  if (tol <= 0.0) tol = kPolishTol;
   const int dt = f64 ? PQ_F64 : PQ_F32;
   const size_t e = elem(dt);
   const int64_t N = n1 * n2;
   const int64_t mx = std::max(n1, n2), mn = std::min(n1, n2);
-  Arena ar(ws, ws_bytes);
   void* Ah = ar.take(e * N * p);
   float* W32 = f64 ? nullptr : static_cast<float*>(ar.take(4 * N * p));
   double* W64 = static_cast<double*>(ar.take(8 * N * p));
   int* used1 = static_cast<int*>(ar.take(sizeof(int) * p));
   int* used2 = static_cast<int*>(ar.take(sizeof(int) * p));
   int* flags = static_cast<int*>(ar.take(sizeof(int) * p * kMaxSweepsCap));
+  double* sig = static_cast<double*>(ar.take(8 * mn * p));
   double* Ft = static_cast<double*>(ar.take(8 * mx * k * p));
   double* Y = static_cast<double*>(ar.take(8 * mn * k * p));
   void* Ys = ar.take(e * mn * k * p);
   void* Akh = ar.take(e * N * p);
-  const Prec pr = (Prec)prec;
+  const bool select = gamma > 0.0;
+  int* rank = select ? static_cast<int*>(ar.take(sizeof(int) * mn * p)) : nullptr;
+  double* e2 = select ? static_cast<double*>(ar.take(8 * mn * p)) : nullptr;
+  int* rho_ws = select ? static_cast<int*>(ar.take(sizeof(int) * p)) : nullptr;
+  if (select && !rho) rho = rho_ws;
   const int in1 = (int)n1, in2 = (int)n2, ip = (int)p, ik = (int)k;
   // step 2: transform domain
   PQ_TRY(do_hat(A, a_dtype, Q, Ah, N, (int)n3, ip, pr, stream));
-  // step 3: facewise truncated SVD.  The Jacobi vectors are the shorter side's
+  // step 3: facewise SVD.  The Jacobi vectors are the shorter side's
   // (columns of each face when n1 >= n2, rows otherwise).
   const bool cols = n1 >= n2;
   const int nv = (int)mn, L = (int)mx;
@@ -614,11 +622,18 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
     PQ_TRY(pq::jacobi_sweeps_f64(W64, ip, nv, L, max_sweeps, tol, used1, flags, stream));
   else
     PQ_TRY(pq::jacobi_gram_sweeps_f64(W64, ip, nv, L, std::min(max_sweeps, kPolishSweeps),
-                                      std::max(tol, kGramTolFloor), used2, flags,
-                                      stream));
+                                      std::max(tol, kGramTolFloor), used2, flags, stream));
+  {
+    PQ_PROF("jacobi_norms", stream);
+    PQ_TRY(pq::jacobi_norms_f64(W64, ip, nv, L, sig, rank, stream));
+  }
+  if (select) {
+    PQ_PROF("svdii_select", stream);
+    PQ_TRY(pq::jacobi_select(sig, ip, nv, gamma, rank, e2, rho, stream));
+  }
   {
     PQ_PROF("jacobi_finalize", stream);
-    PQ_TRY(pq::jacobi_finalize_f64(W64, ip, nv, L, ik, Ft, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(W64, sig, ip, nv, L, ik, select ? rho : nullptr, Ft, stream));
   }
   {  // Y = Ah_l^T Ft_l (n2 x k) or Ah_l Ft_l (n1 x k), float64 accumulation
     PQ_PROF("factor_product", stream);
@@ -639,7 +654,7 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   if (info_dev)
     PQ_TRY(pq::jacobi_info(used1, f64 ? nullptr : used2, ip, max_sweeps,
                            f64 ? max_sweeps : std::min(max_sweeps, kPolishSweeps), info_dev, stream));
-  // step 4 and the approximation of Thm. 4.2
+  // step 4 and the approximation of Thm. 4.2 (zero columns add nothing)
   if (Ak) {
     // Akh_l = Uhat_l Ys_l^T (cols) or Ys_l Vhat_l^T (rows): both Uhat S Vhat^T
     Gemm g = cols ? face_gemm(false, true, in1, in2, ik, Fo, n1, n1 * k, Ys, n2, n2 * k, Akh, n1, N, ip)
@@ -647,10 +662,66 @@ int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
     PQ_TRY(do_gemm("approx_gemm", g, dt, Prec::Default, stream));
     PQ_TRY(do_unhat(Akh, Q, Ak, dt, N, (int)n3, ip, back_prec(pr), stream));
   }
+  return PQ_OK;
+}
+
+// argument checks shared by pq_tsvdq and pq_svdii
+int check_svd_args(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p,
+                   int64_t k, int prec, std::initializer_list<const void*> outs) {
+  PQ_CHECK(check_in_dtype(a_dtype));
+  PQ_CHECK(check_dims({n1, n2, n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_CHECK(check_area(n1, n2));
+  if (k < 1 || k > std::min(n1, n2)) return PQ_ERR_K;
+  PQ_CHECK(check_prec(prec, a_dtype));
+  for (const void* o : outs)
+    if (o && (o == A || o == Q)) return PQ_ERR_ALIAS;
+  if (std::min(n1, n2) > 4096) return PQ_ERR_UNSUPPORTED;
+  if (p > 512 && a_dtype != PQ_F64) return PQ_ERR_UNSUPPORTED;
+  return PQ_OK;
+}
+
+int sweep_defaults(int a_dtype, double& tol, int& max_sweeps) {
+  if (max_sweeps <= 0) max_sweeps = a_dtype == PQ_F64 ? kDefaultSweeps64 : kDefaultSweeps32;
+  if (max_sweeps > kMaxSweepsCap) return PQ_ERR_ARG;
+  if (tol <= 0.0) tol = kPolishTol;
+  return PQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pq_tsvdq(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p,
+             int64_t k, int prec, void* Uhat, void* s, void* Vhat, void* Uk, void* Sk, void* Vk, void* Ak,
+             double tol, int max_sweeps, int* info_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!A || !Q || !Uhat || !s || !Vhat) return PQ_ERR_NULL;
+  PQ_CHECK(check_svd_args(A, a_dtype, Q, n1, n2, n3, p, k, prec, {Uhat, s, Vhat, Uk, Sk, Vk, Ak}));
+  if (!ws || ws_bytes < pq_tsvdq_workspace(n1, n2, n3, p, k, a_dtype)) return PQ_ERR_WORKSPACE;
+  PQ_CHECK(sweep_defaults(a_dtype, tol, max_sweeps));
+  const Prec pr = (Prec)prec;
+  const int dt = a_dtype == PQ_F64 ? PQ_F64 : PQ_F32;
+  Arena ar(ws, ws_bytes);
+  PQ_CHECK(facewise_svd(A, a_dtype, Q, n1, n2, n3, p, k, pr, 0.0, nullptr, Uhat, s, Vhat, Ak, tol, max_sweeps,
+                        info_dev, ar, stream));
+  const int ip = (int)p;
   if (Uk) PQ_TRY(do_unhat(Uhat, Q, Uk, dt, n1 * k, (int)n3, ip, back_prec(pr), stream));
   if (Vk) PQ_TRY(do_unhat(Vhat, Q, Vk, dt, n2 * k, (int)n3, ip, back_prec(pr), stream));
   if (Sk) PQ_TRY(do_unhat(s, Q, Sk, dt, k, (int)n3, ip, back_prec(pr), stream));
   return PQ_OK;
+}
+
+int pq_svdii(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p,
+             double gamma, int64_t kmax, int prec, void* Uhat, void* s, void* Vhat, int* rho_dev, void* Ak,
+             double tol, int max_sweeps, int* info_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!A || !Q || !Uhat || !s || !Vhat) return PQ_ERR_NULL;
+  if (!(gamma > 0.0 && gamma <= 1.0)) return PQ_ERR_ARG;
+  PQ_CHECK(check_svd_args(A, a_dtype, Q, n1, n2, n3, p, kmax, prec, {Uhat, s, Vhat, rho_dev, Ak}));
+  if (!ws || ws_bytes < pq_svdii_workspace(n1, n2, n3, p, kmax, a_dtype)) return PQ_ERR_WORKSPACE;
+  PQ_CHECK(sweep_defaults(a_dtype, tol, max_sweeps));
+  Arena ar(ws, ws_bytes);
+  return facewise_svd(A, a_dtype, Q, n1, n2, n3, p, kmax, (Prec)prec, gamma, rho_dev, Uhat, s, Vhat, Ak, tol,
+                      max_sweeps, info_dev, ar, stream);
 }
 
 }  // extern "C"

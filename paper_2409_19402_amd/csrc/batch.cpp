@@ -57,7 +57,7 @@ struct Layout {
   std::vector<int64_t> woff;   // per instance: element offset of its faces in W32 / W64
   std::vector<int> face0;      // per instance: index of its first face
   size_t w32 = 0, w64 = 0, used1 = 0, used2 = 0, flags = 0;
-  std::vector<size_t> ft, y, ys;  // per instance finishing buffers
+  std::vector<size_t> sig, ft, y, ys;  // per instance finishing buffers
   size_t total = 0;
   int nfaces = 0, nb_max = 2, L_max = 1;
   int64_t welems = 0;
@@ -100,6 +100,7 @@ Layout layout(const pq_instance* inst, int count) {
   lo.ah.resize(count);
   lo.woff.assign(count, 0);
   lo.face0.assign(count, 0);
+  lo.sig.assign(count, 0);
   lo.ft.assign(count, 0);
   lo.y.assign(count, 0);
   lo.ys.assign(count, 0);
@@ -131,6 +132,7 @@ Layout layout(const pq_instance* inst, int count) {
     const pq_instance& x = inst[i];
     if (!has_svd(x)) continue;
     const size_t mx = std::max(x.n1, x.n2), mn = std::min(x.n1, x.n2);
+    lo.sig[i] = take(8 * mn * x.p);
     lo.ft[i] = take(8 * mx * x.k * x.p);
     lo.y[i] = take(8 * mn * x.k * x.p);
     lo.ys[i] = take(4 * mn * x.k * x.p);
@@ -185,7 +187,9 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
     float* Ys = reinterpret_cast<float*>(ws + lo.ys[i]);
     float* Fo = static_cast<float*>(cols ? x.Uhat : x.Vhat);
     float* Other = static_cast<float*>(cols ? x.Vhat : x.Uhat);
-    BQ_TRY(pq::jacobi_finalize_f64(W64 + lo.woff[i], ip, nv, L, ik, Ft, s));
+    double* sig = reinterpret_cast<double*>(ws + lo.sig[i]);
+    BQ_TRY(pq::jacobi_norms_f64(W64 + lo.woff[i], ip, nv, L, sig, nullptr, s));
+    BQ_TRY(pq::jacobi_finalize_f64(W64 + lo.woff[i], sig, ip, nv, L, ik, nullptr, Ft, s));
     BQ_TRY(pq::jacobi_factor_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), Ft, Y, (int)x.n1, (int)x.n2, ik,
                                  ip, cols, s));
     BQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, tol, static_cast<float*>(x.s), Other, Fo, Ys, s));

@@ -130,7 +130,19 @@ hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweep
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol,
                              int* sweeps_used, int* flags, hipStream_t s);
 // Column norms, descending order, top k normalised vectors F (L x k x p).
-hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k, double* F, hipStream_t s);
+// norms of all nv vectors of every face into sig (nv x p, float64); rank
+// (n = nv p ints, may be null) cleared for jacobi_select
+hipError_t jacobi_norms_f64(const double* W, int p, int nv, int L, double* sig, int* rank, hipStream_t s);
+// the top k of each face by sig, normalised into F (L x k x p); a face keeps
+// min(k, kface[f]) vectors when kface is given, zero columns after them
+hipError_t jacobi_finalize_f64(const double* W, const double* sig, int p, int nv, int L, int k, const int* kface,
+                              double* F, hipStream_t s);
+// *_Q-SVDII selection over the n = p nv values of sig (rank cleared by
+// jacobi_norms_f64): rho[f] = face f's values among the first K of the
+// descending order, K the first count whose energy reaches gamma of the
+// total; e2 is n doubles of scratch
+hipError_t jacobi_select(const double* sig, int p, int nv, double gamma, int* rank, double* e2, int* rho,
+                         hipStream_t s);
 // float64 Jacobi on the k columns of Y (m1 x k x p), each rotation applied
 // to F (m2 x k x p) too; writes s (k x p, descending), Other = Y / s, Fo = F
 // and Ys = Y, all in descending order of s, in the output type.

@@ -643,25 +643,44 @@ __global__ __launch_bounds__(256) void transpose_faces_kernel(const T* __restric
   }
 }
 
-// Norms of the converged vectors, descending order, top k normalised into F
-// (L x k x p); a zero vector stays zero.
+// Norms of the converged vectors: one wave per vector, sig[f * nv + j];
+// rank (when given) is cleared for the selection that follows.
 template <typename T>
-__global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, int nv, int L, int k,
+__global__ __launch_bounds__(256) void norms_kernel(const T* __restrict__ W, int nv, int L, double* __restrict__ sig,
+                                                    int* __restrict__ rank) {
+  const int face = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nv) return;
+  const T* v = W + ((int64_t)face * nv + j) * L;
+  double acc = 0.0;
+  for (int e = lane; e < L; e += 64) {
+    const double x = (double)v[e];
+    acc = fma(x, x, acc);
+  }
+  acc = wave_total(acc);
+  if (lane == 0) {
+    sig[(int64_t)face * nv + j] = sqrt(acc);
+    if (rank) rank[(int64_t)face * nv + j] = 0;
+  }
+}
+
+// Descending order of each face's norms (ties by index) and the leading
+// vectors normalised into F (L x k x p); a face keeps min(k, kface[f])
+// vectors when kface is given, the rest of its k columns are zero, as is a
+// zero vector.
+template <typename T>
+__global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, const double* __restrict__ sig_all,
+                                                       int nv, int L, int k, const int* __restrict__ kface,
                                                        T* __restrict__ F) {
   extern __shared__ double sig[];  // nv doubles, then k ints
   int* order = reinterpret_cast<int*>(sig + nv);
   const int face = blockIdx.x;
   const T* Wf = W + (int64_t)face * nv * L;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = wave; j < nv; j += 4) {
-    double acc = 0.0;
-    for (int e = lane; e < L; e += 64) {
-      const double x = Wf[(int64_t)j * L + e];
-      acc = fma(x, x, acc);
-    }
-    acc = wave_total(acc);
-    if (lane == 0) sig[j] = sqrt(acc);
-  }
+  const int kf = kface ? max(0, min(k, kface[face])) : k;
+  for (int j = threadIdx.x; j < nv; j += 256) sig[j] = sig_all[(int64_t)face * nv + j];
+  for (int r = threadIdx.x; r < k; r += 256) order[r] = -1;  // stays -1 only for NaN norms
   __syncthreads();
   for (int j = threadIdx.x; j < nv; j += 256) {
     const double v = sig[j];
@@ -671,11 +690,93 @@ __global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, 
   }
   __syncthreads();
   for (int r = wave; r < k; r += 4) {
+    T* dst = F + ((int64_t)face * k + r) * L;
+    if (r >= kf || order[r] < 0) {
+      for (int e = lane; e < L; e += 64) dst[e] = T(0);
+      continue;
+    }
     const int j = order[r];
     const double v = sig[j];
     const double inv = v > 0.0 ? 1.0 / v : 0.0;
-    T* dst = F + ((int64_t)face * k + r) * L;
     for (int e = lane; e < L; e += 64) dst[e] = static_cast<T>(inv * (double)Wf[(int64_t)j * L + e]);
+  }
+}
+
+// ---- global selection of *_Q-SVDII (Alg. 4.2) ------------------------------
+// rank[i] += how many of sig[c], c in this block's column range, come before
+// sig[i] in the descending order of all n values (ties by index; the values
+// are face-major, face f's at f * nv + j).  Every rank lies in [0, n - 1]
+// whatever the values are.
+__global__ __launch_bounds__(256) void rank_kernel(const double* __restrict__ sig, int n, int cols,
+                                                   int* __restrict__ rank) {
+  __shared__ double tile[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const double v = i < n ? sig[i] : 0.0;
+  const int c_begin = blockIdx.y * cols, c_end = min(n, c_begin + cols);
+  int r = 0;
+  for (int c0 = c_begin; c0 < c_end; c0 += 256) {
+    __syncthreads();
+    tile[threadIdx.x] = c0 + (int)threadIdx.x < c_end ? sig[c0 + threadIdx.x] : 0.0;
+    __syncthreads();
+    const int cn = min(256, c_end - c0);
+    for (int c = 0; c < cn; ++c) {
+      const double w = tile[c];
+      r += (w > v) || (w == v && c0 + c < i);
+    }
+  }
+  if (i < n && r) atomicAdd(&rank[i], r);
+}
+
+// One workgroup: the squared values scattered by rank into descending order
+// (e2, n doubles), their running sum, K = the first count whose running sum
+// reaches gamma times the total (n when rounding leaves it short), and
+// rho[f] = how many of face f's values are among the first K.
+constexpr int kSelThreads = 1024;
+
+__global__ __launch_bounds__(kSelThreads) void select_kernel(const double* __restrict__ sig,
+                                                             const int* __restrict__ rank, int n, int p, int nv,
+                                                             double gamma, double* __restrict__ e2,
+                                                             int* __restrict__ rho) {
+  __shared__ double part[kSelThreads];
+  __shared__ int kfirst;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += kSelThreads) {
+    const double v = sig[i];
+    e2[rank[i]] = v * v;
+  }
+  if (tid == 0) kfirst = n;
+  __syncthreads();
+  // chunk totals, an inclusive scan of them, then each chunk walked again
+  const int chunk = (n + kSelThreads - 1) / kSelThreads;
+  const int b0 = min(n, tid * chunk), b1 = min(n, b0 + chunk);
+  double s = 0.0;
+  for (int i = b0; i < b1; ++i) s += e2[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < kSelThreads; off <<= 1) {
+    const double add = tid >= off ? part[tid - off] : 0.0;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  const double target = gamma * part[kSelThreads - 1];
+  double run = tid > 0 ? part[tid - 1] : 0.0;
+  for (int i = b0; i < b1; ++i) {
+    run += e2[i];
+    if (run >= target) {
+      atomicMin(&kfirst, i + 1);
+      break;
+    }
+  }
+  __syncthreads();
+  const int K = kfirst;
+  // one wave per face
+  const int lane = tid & 63;
+  for (int f = tid >> 6; f < p; f += kSelThreads / 64) {
+    int c = 0;
+    for (int j = lane; j < nv; j += 64) c += rank[(int64_t)f * nv + j] < K;
+    c = (int)wave_total((double)c);  // exact: counts stay far below 2^53
+    if (lane == 0) rho[f] = c;
   }
 }
 
@@ -744,6 +845,7 @@ __global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __res
     acc = wave_total(acc);
     if (lane == 0) sig[j] = sqrt(acc);
   }
+  for (int r = threadIdx.x; r < k; r += 256) order[r] = -1;
   __syncthreads();
   for (int j = threadIdx.x; j < k; j += 256) {
     const double v = sig[j];
@@ -753,7 +855,8 @@ __global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __res
   }
   __syncthreads();
   for (int r = wave; r < k; r += 4) {
-    const int j = order[r];
+    // equal ranks arise only from NaN norms; such a slot reads column r
+    const int j = order[r] >= 0 && order[r] < k ? order[r] : r;
     const double v = sig[j];
     const double inv = v > 0.0 ? 1.0 / v : 0.0;
     if (lane == 0) s_out[(int64_t)face * k + r] = static_cast<TO>(v);
@@ -1021,9 +1124,10 @@ hipError_t prep(const T* Ah, T* W, int n1, int n2, int p, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t finalize(const T* W, int p, int nv, int L, int k, T* F, hipStream_t s) {
+hipError_t finalize(const T* W, const double* sig, int p, int nv, int L, int k, const int* kface, T* F,
+                    hipStream_t s) {
   const size_t lds = sizeof(double) * (size_t)nv + sizeof(int) * (size_t)k;
-  finalize_kernel<T><<<p, 256, lds, s>>>(W, nv, L, k, F);
+  finalize_kernel<T><<<p, 256, lds, s>>>(W, sig, nv, L, k, kface, F);
   return hipGetLastError();
 }
 
@@ -1084,8 +1188,24 @@ hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweep
   if (gram_fits<double>(L)) return gram_sweeps_uniform<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
   return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
 }
-hipError_t jacobi_finalize_f64(const double* W, int p, int nv, int L, int k, double* F, hipStream_t s) {
-  return finalize<double>(W, p, nv, L, k, F, s);
+hipError_t jacobi_norms_f64(const double* W, int p, int nv, int L, double* sig, int* rank, hipStream_t s) {
+  norms_kernel<double><<<dim3((unsigned)((nv + 3) / 4), (unsigned)p), 256, 0, s>>>(W, nv, L, sig, rank);
+  return hipGetLastError();
+}
+hipError_t jacobi_finalize_f64(const double* W, const double* sig, int p, int nv, int L, int k, const int* kface,
+                              double* F, hipStream_t s) {
+  return finalize<double>(W, sig, p, nv, L, k, kface, F, s);
+}
+hipError_t jacobi_select(const double* sig, int p, int nv, double gamma, int* rank, double* e2, int* rho,
+                         hipStream_t s) {
+  const int n = p * nv;
+  const int bx = (n + 255) / 256;
+  // split the comparison columns so that the grid holds about 2048 blocks
+  const int by = std::max(1, std::min(bx, (2048 + bx - 1) / bx));
+  const int cols = ((n + by - 1) / by + 255) / 256 * 256;
+  rank_kernel<<<dim3((unsigned)bx, (unsigned)((n + cols - 1) / cols)), 256, 0, s>>>(sig, n, cols, rank);
+  select_kernel<<<1, kSelThreads, 0, s>>>(sig, rank, n, p, nv, gamma, e2, rho);
+  return hipGetLastError();
 }
 hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int p, double tol,
                              float* s_out, float* Other, float* Fo, float* Ys, hipStream_t s) {
