@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="video",
                     choices=["video", "hyper", "diff", "tiny", "copy", "hat-video", "hat-hyper",
-                             "proj-video", "qprod", "batched"])
+                             "proj-video", "qprod", "batched", "svdii-video", "u3-video"])
     ap.add_argument("--count", type=int, default=64, help="instances of the batched workload")
     ap.add_argument("--prec", default="default")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -102,6 +102,19 @@ def jacobi_models(svd_flops):
         n = sum(kernels.get(nm, {}).get("launches", 0) for nm in JACOBI_KERNELS)
         return svd_flops * steps / n if n else None
     return {nm: ("alu", share) for nm in JACOBI_KERNELS}
+
+
+def oracle_mod():
+    import oracle
+    return oracle
+
+
+def tsvdq_cpu_case(Al, Qn, k):
+    def run():
+        o = oracle_mod()
+        o.check_q(Qn)
+        o.tsvdq(Al, Qn, k)
+    return run, "check_q + tsvdq with A_k, spatial factors"
 
 
 def workload_tsvdq(pq, torch, A_dev, Q_dev, k, a_bytes, name, prec):
@@ -172,7 +185,7 @@ def main():
         step, flops, info, models = workload_tsvdq(
             pq, torch, A, Q, c["k"], 4, "video-shaped tSVDQ 240x320x200 fp32, p=20, k=10", args.prec)
         dtype = "f32"
-        cpu_case = ("tsvdq", synth.logical(c["A"]), c["Q"], c["k"])
+        cpu_case = tsvdq_cpu_case(synth.logical(c["A"]), c["Q"], c["k"])
     elif args.workload == "hyper":
         c = synth.hyperspectral_case()
         A = pq.from_storage(torch.from_numpy(c["A_bits"].view(np.int16)).to(dev).view(torch.bfloat16))
@@ -181,14 +194,56 @@ def main():
             pq, torch, A, Q, c["k"], 2, "hyperspectral-shaped tSVDQ 512x512x224 bf16, p=32, k=16",
             args.prec)
         dtype = "bf16-in/f32"
-        cpu_case = ("tsvdq", synth.logical(c["A"]), c["Q"], c["k"])
+        cpu_case = tsvdq_cpu_case(synth.logical(c["A"]), c["Q"], c["k"])
     elif args.workload == "tiny":
         c = synth.tiny()
         A, Q = up(c["A"]), torch.from_numpy(c["Q"]).to(dev)
         step, flops, info, models = workload_tsvdq(
             pq, torch, A, Q, c["k"], 8, "tiny tSVDQ 32x24x16 fp64, p=4, k=5", "default")
         dtype = "f64"
-        cpu_case = ("tsvdq", synth.logical(c["A"]), c["Q"], c["k"])
+        cpu_case = tsvdq_cpu_case(synth.logical(c["A"]), c["Q"], c["k"])
+    elif args.workload == "svdii-video":
+        c = synth.video_case()
+        A, Q = up(c["A"]), torch.from_numpy(c["Q"]).to(dev)
+        n1, n2, n3 = A.shape
+        p, k = Q.shape[1], c["k"]
+        N = n1 * n2
+        kmax = min(n1, n2) // 4
+        # gamma of Thm. 4.5: the transform-domain energy the rank-k tSVDQ keeps
+        t_ = pq.tsvdq(A, Q, k)
+        gamma = float((t_.s.double() ** 2).sum() / (pq.hat(A, Q).double() ** 2).sum())
+
+        def step():
+            pq.check_q(Q)
+            return pq.svdii(A, Q, gamma, kmax=kmax, prec=args.prec, approx=True)
+        flops = (2.0 * N * n3 * p + svd_nominal_flops(n1, n2, p)
+                 + 2.0 * N * kmax * p * 2 + 2.0 * N * n3 * p)
+        models = {"hat": ("hbm", 4.0 * N * n3 + 4.0 * N * p + 4.0 * n3 * p), "unhat": ("hbm", None)}
+        models.update(jacobi_models(svd_nominal_flops(n1, n2, p)))
+        info = {"workload": f"video-shaped *_Q-SVDII 240x320x200 fp32, p=20, gamma of rank-{k} tSVDQ, "
+                            f"kmax={kmax}", "n1": n1, "n2": n2, "n3": n3, "p": p, "gamma": gamma,
+                "kmax": kmax}
+        dtype = "f32"
+        Al, Qn = synth.logical(c["A"]), c["Q"]
+        cpu_case = (lambda: (oracle_mod().check_q(Qn), oracle_mod().tsvdq_ii(Al, Qn, gamma)),
+                    "check_q + tsvdq_ii with A_k")
+    elif args.workload == "u3-video":
+        c = synth.video_case()
+        A = up(c["A"])
+        n1, n2, n3 = A.shape
+        p = 20
+        N = n1 * n2
+
+        def step():
+            return pq.u3(A, p)
+        flops = 2.0 * N * n3 * n3 + svd_nominal_flops(n3, n3, 1)
+        models = {"u3_gram": ("mfma", 2.0 * N * n3 * n3)}
+        models.update(jacobi_models(svd_nominal_flops(n3, n3, 1)))
+        info = {"workload": "Q = U3(:, 1:20) of the video-shaped 240x320x200 fp32 cube",
+                "n1": n1, "n2": n2, "n3": n3, "p": p}
+        dtype = "f32"
+        Al = synth.logical(c["A"])
+        cpu_case = (lambda: oracle_mod().u3(Al, p), "u3 (Gram eigen route of the oracle)")
     elif args.workload in ("hat-video", "hat-hyper", "proj-video"):
         if args.workload == "hat-hyper":
             c = synth.hyperspectral_case()
@@ -393,6 +448,14 @@ def main():
                     "avg_us": round(kernels[dom]["avg_us"], 3)}
 
     extra = {}
+    if args.workload == "svdii-video":
+        rho = out.rho.cpu()
+        Af = A.float()
+        re = (torch.linalg.vector_norm((Af - out.Ak).reshape(-1)) /
+              torch.linalg.vector_norm(Af.reshape(-1))).item()
+        extra = {"relative_error_A_k": re, "implicit_rank": int(rho.sum()), "rho_max": int(rho.max()),
+                 "rho_min": int(rho.min()), "tsvdq_implicit_rank": k * p}
+        log(f"RE(A_k) = {re:.6e}, rho {rho.tolist()}")
     if args.workload in ("video", "hyper", "tiny"):
         Ak = out.Ak
         Af = A.float() if A.dtype != torch.float64 else A
@@ -427,23 +490,20 @@ def main():
                          f"{t_cpu:.1f}s, float64 numpy/LAPACK"}
         log(f"cpu oracle: {cpu['value']} GFLOP/s over {done} instances on {cores} threads")
     if not args.no_cpu_baseline and cpu_case is not None:
-        import oracle
         cores = blas_threads()
-        _, Al, Qn, k = cpu_case
-        oracle.check_q(Qn)
-        oracle.tsvdq(Al, Qn, k)  # warm-up
+        run_cpu, what = cpu_case
+        run_cpu()  # warm-up
         reps, t_cpu = 0, 0.0
         t_start = time.time()
         while time.time() - t_start < args.cpu_seconds or reps == 0:
             t1 = time.time()
-            oracle.check_q(Qn)
-            oracle.tsvdq(Al, Qn, k)
+            run_cpu()
             t_cpu += time.time() - t1
             reps += 1
         cpu = {"value": round(flops * reps / t_cpu / 1e9, 4), "unit": "GFLOP/s", "cores": cores,
                "kind": "oracle",
-               "sample": f"{reps} full passes of the same workload (check_q + tsvdq with A_k, "
-                         f"spatial factors), {t_cpu:.1f}s, float64 numpy/LAPACK"}
+               "sample": f"{reps} full passes of the same workload ({what}), {t_cpu:.1f}s, "
+                         "float64 numpy/LAPACK"}
         log(f"cpu oracle: {cpu['value']} GFLOP/s over {reps} passes on {cores} threads")
 
     line = {

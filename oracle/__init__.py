@@ -26,7 +26,7 @@ from .core import (  # noqa: F401
 from .tsvdq import (  # noqa: F401
     tsvdq, tsvdq_error_terms, relative_error, tsvdq_ii, TSVDQResult,
 )
-from .grad import qprod_backward, proj_backward  # noqa: F401
+from .grad import qprod_backward, proj_backward, tsvdq_backward  # noqa: F401
 
 # Which pin holds each oracle function (see tests/test_oracle_pins.py).
 PARITY = {
@@ -44,5 +44,8 @@ PARITY = {
                 "gamma=1 reduction",
     "qprod_backward/proj_backward": "pinned: central finite differences and "
                                     "torch CPU float64 autograd",
+    "tsvdq_backward": "pinned: central finite differences of <Gbar, A_k> + <sbar, s> "
+                      "(tall, wide and square faces, k = 1 and k = min(n1, n2)) and "
+                      "torch CPU float64 autograd through torch.linalg.svd",
     "check_q": "pinned: closed form on constructed matrices",
 }

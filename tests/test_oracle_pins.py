@@ -389,6 +389,67 @@ def test_qprod_backward_torch_autograd():
     np.testing.assert_allclose(dQ, tQ.grad.numpy(), rtol=1e-11, atol=1e-11)
 
 
+def _tsvdq_loss(A, Q, k, Gbar, sbar):
+    r = oracle.tsvdq(A, Q, k)
+    return float(np.sum(Gbar * r.Ak) + np.sum(sbar * r.s))
+
+
+@pytest.mark.parametrize("n1,n2,n3,p,k", [(6, 4, 7, 3, 2), (4, 6, 7, 3, 2), (5, 5, 6, 2, 1),
+                                         (6, 4, 5, 2, 4), (3, 7, 4, 4, 3)])
+def test_tsvdq_backward_finite_differences(n1, n2, n3, p, k):
+    """The adjoint of (A, Q) -> (A_k, s) against central differences; Q is
+    perturbed as a free matrix (the forward map is defined for any Q)."""
+    rng = np.random.default_rng(100 + n1 * 10 + n2)
+    A = rng.standard_normal((n1, n2, n3))
+    Q = synth.random_orthonormal(rng, n3, p)
+    Gbar = rng.standard_normal((n1, n2, n3))
+    sbar = rng.standard_normal((k, p))
+    # the truncation must sit in a gap of every face's spectrum
+    s_all = oracle.tsvdq(A, Q, 1).s_all
+    if k < min(n1, n2):
+        assert np.min(s_all[k - 1] - s_all[k]) > 0.05
+    dA, dQ = oracle.tsvdq_backward(A, Q, k, Gbar, sbar)
+    h = 1e-5
+    for X, dX in ((A, dA), (Q, dQ)):
+        for _ in range(5):
+            D = rng.standard_normal(X.shape)
+            D /= np.linalg.norm(D)
+            if X is A:
+                fd = (_tsvdq_loss(A + h * D, Q, k, Gbar, sbar)
+                      - _tsvdq_loss(A - h * D, Q, k, Gbar, sbar)) / (2 * h)
+            else:
+                fd = (_tsvdq_loss(A, Q + h * D, k, Gbar, sbar)
+                      - _tsvdq_loss(A, Q - h * D, k, Gbar, sbar)) / (2 * h)
+            assert fd == pytest.approx(np.sum(dX * D), rel=1e-6, abs=1e-7)
+
+
+def test_tsvdq_backward_torch_autograd():
+    """The same adjoint against torch's float64 autograd through its thin SVD
+    (an independent route: torch differentiates U, S, V^T of every face)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(18)
+    n1, n2, n3, p, k = 7, 5, 9, 4, 2
+    A = rng.standard_normal((n1, n2, n3))
+    Q = synth.random_orthonormal(rng, n3, p)
+    Gbar = rng.standard_normal((n1, n2, n3))
+    sbar = rng.standard_normal((k, p))
+    tA = torch.tensor(A, requires_grad=True)
+    tQ = torch.tensor(Q, requires_grad=True)
+    Ah = torch.einsum("ijt,tl->ijl", tA, tQ)
+    loss = 0.0
+    faces = []
+    for l in range(p):
+        U, S, Vh = torch.linalg.svd(Ah[:, :, l], full_matrices=False)
+        faces.append((U[:, :k] * S[:k]) @ Vh[:k, :])
+        loss = loss + (torch.tensor(sbar[:, l]) * S[:k]).sum()
+    Ak = torch.einsum("ijl,tl->ijt", torch.stack(faces, dim=2), tQ)
+    loss = loss + (torch.tensor(Gbar) * Ak).sum()
+    loss.backward()
+    dA, dQ = oracle.tsvdq_backward(A, Q, k, Gbar, sbar)
+    np.testing.assert_allclose(dA, tA.grad.numpy(), rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(dQ, tQ.grad.numpy(), rtol=1e-9, atol=1e-9)
+
+
 def test_check_q_closed_form():
     d = 0.25
     Q = np.array([[1.0, d], [0.0, 1.0], [0.0, 0.0]])
