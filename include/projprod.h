@@ -315,6 +315,38 @@ int pq_svdii(const void* A, int a_dtype, const void* Q,
              void* ws, size_t ws_bytes, hipStream_t stream);
 
 
+/*
+ * Adjoint of the truncated tSVDQ viewed as the map (A, Q) -> (A_k, s):
+ * A_k = (Uhat tri Shat tri Vhat^T) x_3 Q the approximation of Thm. 4.2 and
+ * s (k x p) the kept transform-domain singular values of Alg. 4.1 step 3.
+ * Given Gbar = dL/dA_k (n1 x n2 x n3) and/or sbar = dL/ds (k x p, element
+ * (j, l) at j + l*k), writes dA = dL/dA (n1 x n2 x n3) and/or dQ = dL/dQ
+ * (n3 x p row-major, the Euclidean gradient of Q as a free matrix).  The
+ * paper differentiates nothing; this follows from first-order perturbation
+ * of each face's SVD: the derivative of the rank-k truncation of a face is
+ * that of its spectral projector, which couples each kept value sigma_c
+ * with each discarded one sigma_j through 1 / (sigma_c^2 - sigma_j^2), and
+ * with the null space through 1 / sigma_c^2.  It exists when every face has
+ * sigma_k > sigma_k+1; pairs with |sigma_c^2 - sigma_j^2| <= gap_tol
+ * sigma_c^2 have their coupling dropped (gap_tol <= 0 selects 1e-8) and are
+ * counted.  Losses of A_k and s are the ones whose gradient is well defined
+ * (the factors themselves are fixed only up to signs and rotations).
+ * The facewise SVD is recomputed (tol and max_sweeps as in pq_tsvdq) with
+ * every singular vector of the shorter side kept.  a_dtype F32 or F64;
+ * Gbar, sbar, dA and dQ have the output type of pq_tsvdq.  Gbar or sbar may
+ * be NULL (not both), dA or dQ may be NULL (not both).  info_dev (device
+ * int[4], may be NULL): [0..2] as in pq_tsvdq, [3] = the pairs whose
+ * coupling was dropped.  Workspace: pq_tsvdq_backward_workspace bytes.
+ */
+size_t pq_tsvdq_backward_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k,
+                                   int a_dtype);
+int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q,
+                      int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k,
+                      const void* Gbar, const void* sbar, void* dA, void* dQ,
+                      double gap_tol, double tol, int max_sweeps, int* info_dev,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+
 /* ---- batched form: many uneven instances in one captured graph ----------- */
 /*
  * Instance i of a batch (all float32, face-major, device pointers owned by

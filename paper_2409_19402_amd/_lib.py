@@ -48,6 +48,9 @@ SIGNATURES = {
     "pq_svdii_workspace": (_sz, [_i64, _i64, _i64, _i64, _i64, _i32]),
     "pq_svdii": (_i32, [_vp, _i32, _vp, _i64, _i64, _i64, _i64, _dbl, _i64, _i32, _vp, _vp, _vp, _vp,
                         _vp, _dbl, _i32, _vp, _vp, _sz, _vp]),
+    "pq_tsvdq_backward_workspace": (_sz, [_i64, _i64, _i64, _i64, _i64, _i32]),
+    "pq_tsvdq_backward": (_i32, [_vp, _i32, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _dbl,
+                                 _dbl, _i32, _vp, _vp, _sz, _vp]),
     "pq_u3_workspace": (_sz, [_i64, _i64, _i64, _i64, _i32]),
     "pq_u3": (_i32, [_vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "pq_batched_workspace": (_i32, [_vp, _i32, _vp]),

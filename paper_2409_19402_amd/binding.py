@@ -333,6 +333,64 @@ def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_swe
     return TSVDQ(Uh, s.t(), Vh, Uk, None if Sk is None else Sk.t(), Vk, Ak, info)
 
 
+def tsvdq_backward(A, Q, k, Gbar=None, sbar=None, need=(True, True), gap_tol=0.0, tol=0.0,
+                   max_sweeps=0):
+    """(dA, dQ, info) of L given Gbar = dL/dA_k (n1 x n2 x n3) and/or
+    sbar = dL/ds ((k, p), as tsvdq returns s), for the rank-k tSVDQ of A;
+    entries of `need` that are False come back as None.  info is the int32
+    device tensor [max sweeps, unconverged faces, total sweeps, dropped
+    near-degenerate pairs]."""
+    _tensor(A, "A", (torch.float32, torch.float64))
+    _q(Q, A.dtype)
+    n1, n2, n3 = A.shape
+    p = Q.shape[1]
+    dt = A.dtype
+    if Gbar is not None:
+        if tuple(Gbar.shape) != (n1, n2, n3):
+            raise ValueError("Gbar must have the shape of A")
+        Gbar = _tensor(_face_major(Gbar.to(dt)), "Gbar", (dt,))
+    if sbar is not None:
+        if tuple(sbar.shape) != (k, p):
+            raise ValueError("sbar must be (k, p)")
+        sbar = sbar.to(dt).t().contiguous()  # element (j, l) at j + l k
+    dA = empty(n1, n2, n3, dt, A.device) if need[0] else None
+    dQ = torch.empty((n3, p), dtype=dt, device=A.device) if need[1] else None
+    info = torch.zeros(4, dtype=torch.int32, device=A.device)
+    lib = _lib.load()
+    wsb, nb = _ws(lib.pq_tsvdq_backward_workspace(n1, n2, n3, p, k, _DT[dt]), A.device)
+    call("pq_tsvdq_backward", _ptr(A), _DT[dt], _ptr(Q), n1, n2, n3, p, k, _ptr(Gbar), _ptr(sbar),
+         _ptr(dA), _ptr(dQ), float(gap_tol), float(tol), int(max_sweeps), _ptr(info), _ptr(wsb), nb,
+         _stream(A.device))
+    return dA, dQ, info
+
+
+class TSVDQApprox(torch.autograd.Function):
+    """(A_k, s) of the rank-k tSVDQ (Alg. 4.1, Thm. 4.2) with the hand-written
+    adjoint for dA and dQ."""
+
+    @staticmethod
+    def forward(ctx, A, Q, k, prec="default"):
+        out = tsvdq(A, Q, k, prec=prec, approx=True)
+        ctx.save_for_backward(A, Q)
+        ctx.k = k
+        return out.Ak, out.s
+
+    @staticmethod
+    def backward(ctx, gAk, gs):
+        A, Q = ctx.saved_tensors
+        need = ctx.needs_input_grad[:2]
+        dA, dQ, _ = tsvdq_backward(A, Q, ctx.k, Gbar=gAk, sbar=gs, need=need)
+        return dA, dQ, None, None
+
+
+def tsvdq_approx(A, Q, k, prec="default"):
+    """(A_k, s) of the rank-k tSVDQ; differentiable in A and Q (float32/float64)."""
+    if torch.is_grad_enabled() and any(x.requires_grad for x in (A, Q)):
+        return TSVDQApprox.apply(A, Q, k, prec)
+    out = tsvdq(A, Q, k, prec=prec, approx=True)
+    return out.Ak, out.s
+
+
 SVDII = namedtuple("SVDII", "Uhat s Vhat rho Ak info")
 
 

@@ -104,8 +104,21 @@ constexpr double kPolishTol = 1e-13;
 // still far below float32 resolution).
 constexpr double kGramTolFloor = 1e-10;
 constexpr int kMaxSweepsCap = 100;
+// relative gap |lambda_c - lambda_j| / lambda_c at or under which the adjoint
+// of the truncation drops the coupling of a kept and a discarded pair
+constexpr double kDefaultGapTol = 1e-8;
 
 int ksplit_for(int64_t K) { return (int)std::clamp<int64_t>(K / 512, 1, 1024); }
+
+// bytes of the transform and Jacobi buffers (take_sweep_bufs takes them in
+// this order)
+size_t sweep_bytes(bool f64, int64_t N, int64_t p) {
+  return align_up(elem(f64 ? PQ_F64 : PQ_F32) * N * p)     // Ah
+         + (f64 ? 0 : align_up(4 * N * p))                 // float32 Jacobi vectors
+         + align_up(8 * N * p)                             // float64 Jacobi vectors
+         + align_up(sizeof(int) * p) * 2                   // sweeps per face, both phases
+         + align_up(sizeof(int) * p * kMaxSweepsCap);      // per-sweep rotation flags
+}
 
 // ---- dispatch by dtype -------------------------------------------------------
 hipError_t do_hat(const void* A, int a_dtype, const void* Q, void* Ah, int64_t N, int n3, int p,
@@ -527,7 +540,7 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
   {
     PQ_PROF("jacobi_finalize", stream);
     PQ_TRY(pq::jacobi_norms_f64(W, 1, in3, in3, sig, nullptr, stream));
-    PQ_TRY(pq::jacobi_finalize_f64(W, sig, 1, in3, in3, ip, nullptr, F, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(W, sig, 1, in3, in3, ip, nullptr, F, nullptr, stream));
   }
   {
     PQ_PROF("u3_finish", stream);
@@ -542,11 +555,7 @@ size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t
   const bool f64 = a_dtype == PQ_F64;
   const size_t e = elem(f64 ? PQ_F64 : PQ_F32);
   const int64_t mx = std::max(n1, n2), mn = std::min(n1, n2);
-  return align_up(e * n1 * n2 * p)                        // Ah
-         + (f64 ? 0 : align_up(4 * n1 * n2 * p))          // float32 Jacobi vectors
-         + align_up(8 * n1 * n2 * p)                      // float64 Jacobi vectors
-         + align_up(sizeof(int) * p) * 2                  // sweeps per face, both phases
-         + align_up(sizeof(int) * p * kMaxSweepsCap)      // per-sweep rotation flags
+  return sweep_bytes(f64, n1 * n2, p)
          + align_up(8 * mn * p)                           // every singular value
          + align_up(8 * mx * k * p)                       // top-k Jacobi vectors
          + align_up(8 * mn * k * p)                       // other side (float64)
@@ -566,6 +575,63 @@ size_t pq_svdii_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t
 
 namespace {
 
+// Transform and Jacobi buffers: Ah, the float32 working copy (float32 data),
+// the float64 vectors, sweep counters of both phases and rotation flags.
+struct SweepBufs {
+  void* Ah;
+  float* W32;
+  double* W64;
+  int* used1;
+  int* used2;
+  int* flags;
+};
+
+SweepBufs take_sweep_bufs(Arena& ar, bool f64, int64_t N, int64_t p) {
+  SweepBufs b;
+  b.Ah = ar.take(elem(f64 ? PQ_F64 : PQ_F32) * N * p);
+  b.W32 = f64 ? nullptr : static_cast<float*>(ar.take(4 * N * p));
+  b.W64 = static_cast<double*>(ar.take(8 * N * p));
+  b.used1 = static_cast<int*>(ar.take(sizeof(int) * p));
+  b.used2 = static_cast<int*>(ar.take(sizeof(int) * p));
+  b.flags = static_cast<int*>(ar.take(sizeof(int) * p * kMaxSweepsCap));
+  return b;
+}
+
+// Step 2 of Alg. 4.1 and the Jacobi sweeps of step 3: b.Ah = A x_3 Q^T and
+// b.W64 = the converged vectors of every face (the shorter side's: columns
+// of each face when n1 >= n2, rows otherwise); sweep statistics to info_dev.
+int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p, Prec pr,
+             double tol, int max_sweeps, const SweepBufs& b, int* info_dev, hipStream_t stream) {
+  const bool f64 = a_dtype == PQ_F64;
+  const int64_t N = n1 * n2;
+  const int in1 = (int)n1, in2 = (int)n2, ip = (int)p;
+  const int nv = (int)std::min(n1, n2), L = (int)std::max(n1, n2);
+  PQ_TRY(do_hat(A, a_dtype, Q, b.Ah, N, (int)n3, ip, pr, stream));
+  if (f64) {
+    PQ_PROF("jacobi_prep", stream);
+    PQ_TRY(pq::jacobi_prep_f64(static_cast<const double*>(b.Ah), b.W64, in1, in2, ip, stream));
+  } else {
+    {
+      PQ_PROF("jacobi_prep", stream);
+      PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(b.Ah), b.W32, in1, in2, ip, stream));
+    }
+    // float32 sweeps down to a coarse threshold (each launch profiled inside)
+    PQ_TRY(pq::jacobi_sweeps_f32(b.W32, ip, nv, L, max_sweeps, kCoarseTol32, b.used1, b.flags, stream));
+    PQ_PROF("jacobi_widen", stream);
+    PQ_TRY(pq::jacobi_widen(b.W32, b.W64, N * p, stream));
+  }
+  // float64 sweeps to tol (each launch profiled inside)
+  if (f64)
+    PQ_TRY(pq::jacobi_sweeps_f64(b.W64, ip, nv, L, max_sweeps, tol, b.used1, b.flags, stream));
+  else
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, std::min(max_sweeps, kPolishSweeps),
+                                      std::max(tol, kGramTolFloor), b.used2, b.flags, stream));
+  if (info_dev)
+    PQ_TRY(pq::jacobi_info(b.used1, f64 ? nullptr : b.used2, ip, max_sweeps,
+                           f64 ? max_sweeps : std::min(max_sweeps, kPolishSweeps), info_dev, stream));
+  return PQ_OK;
+}
+
 // Steps 2-3 of Alg. 4.1 (gamma <= 0: rank k on every face) or of Alg. 4.2
 // (gamma in (0, 1]: per-face ranks rho from one energy threshold over every
 // face, each face keeping min(rho_i, k) columns, zero columns after), then
@@ -579,12 +645,7 @@ int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t 
   const size_t e = elem(dt);
   const int64_t N = n1 * n2;
   const int64_t mx = std::max(n1, n2), mn = std::min(n1, n2);
-  void* Ah = ar.take(e * N * p);
-  float* W32 = f64 ? nullptr : static_cast<float*>(ar.take(4 * N * p));
-  double* W64 = static_cast<double*>(ar.take(8 * N * p));
-  int* used1 = static_cast<int*>(ar.take(sizeof(int) * p));
-  int* used2 = static_cast<int*>(ar.take(sizeof(int) * p));
-  int* flags = static_cast<int*>(ar.take(sizeof(int) * p * kMaxSweepsCap));
+  const SweepBufs b = take_sweep_bufs(ar, f64, N, p);
   double* sig = static_cast<double*>(ar.take(8 * mn * p));
   double* Ft = static_cast<double*>(ar.take(8 * mx * k * p));
   double* Y = static_cast<double*>(ar.take(8 * mn * k * p));
@@ -596,33 +657,13 @@ int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t 
   int* rho_ws = select ? static_cast<int*>(ar.take(sizeof(int) * p)) : nullptr;
   if (select && !rho) rho = rho_ws;
   const int in1 = (int)n1, in2 = (int)n2, ip = (int)p, ik = (int)k;
-  // step 2: transform domain
-  PQ_TRY(do_hat(A, a_dtype, Q, Ah, N, (int)n3, ip, pr, stream));
-  // step 3: facewise SVD.  The Jacobi vectors are the shorter side's
-  // (columns of each face when n1 >= n2, rows otherwise).
+  const void* Ah = b.Ah;
+  double* W64 = b.W64;
+  PQ_CHECK(converge(A, a_dtype, Q, n1, n2, n3, p, pr, tol, max_sweeps, b, info_dev, stream));
   const bool cols = n1 >= n2;
   const int nv = (int)mn, L = (int)mx;
   void* Fo = cols ? Uhat : Vhat;     // side given by the Jacobi vectors
   void* Other = cols ? Vhat : Uhat;  // side given by one more product
-  if (f64) {
-    PQ_PROF("jacobi_prep", stream);
-    PQ_TRY(pq::jacobi_prep_f64(static_cast<const double*>(Ah), W64, in1, in2, ip, stream));
-  } else {
-    {
-      PQ_PROF("jacobi_prep", stream);
-      PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(Ah), W32, in1, in2, ip, stream));
-    }
-    // float32 sweeps down to a coarse threshold (each launch profiled inside)
-    PQ_TRY(pq::jacobi_sweeps_f32(W32, ip, nv, L, max_sweeps, kCoarseTol32, used1, flags, stream));
-    PQ_PROF("jacobi_widen", stream);
-    PQ_TRY(pq::jacobi_widen(W32, W64, N * p, stream));
-  }
-  // float64 sweeps to tol (each launch profiled inside)
-  if (f64)
-    PQ_TRY(pq::jacobi_sweeps_f64(W64, ip, nv, L, max_sweeps, tol, used1, flags, stream));
-  else
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(W64, ip, nv, L, std::min(max_sweeps, kPolishSweeps),
-                                      std::max(tol, kGramTolFloor), used2, flags, stream));
   {
     PQ_PROF("jacobi_norms", stream);
     PQ_TRY(pq::jacobi_norms_f64(W64, ip, nv, L, sig, rank, stream));
@@ -633,7 +674,7 @@ int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t 
   }
   {
     PQ_PROF("jacobi_finalize", stream);
-    PQ_TRY(pq::jacobi_finalize_f64(W64, sig, ip, nv, L, ik, select ? rho : nullptr, Ft, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(W64, sig, ip, nv, L, ik, select ? rho : nullptr, Ft, nullptr, stream));
   }
   {  // Y = Ah_l^T Ft_l (n2 x k) or Ah_l Ft_l (n1 x k), float64 accumulation
     PQ_PROF("factor_product", stream);
@@ -651,9 +692,6 @@ int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t 
                                    static_cast<float*>(Other), static_cast<float*>(Fo),
                                    static_cast<float*>(Ys), stream));
   }
-  if (info_dev)
-    PQ_TRY(pq::jacobi_info(used1, f64 ? nullptr : used2, ip, max_sweeps,
-                           f64 ? max_sweeps : std::min(max_sweeps, kPolishSweeps), info_dev, stream));
   // step 4 and the approximation of Thm. 4.2 (zero columns add nothing)
   if (Ak) {
     // Akh_l = Uhat_l Ys_l^T (cols) or Ys_l Vhat_l^T (rows): both Uhat S Vhat^T
@@ -722,6 +760,144 @@ int pq_svdii(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   Arena ar(ws, ws_bytes);
   return facewise_svd(A, a_dtype, Q, n1, n2, n3, p, kmax, (Prec)prec, gamma, rho_dev, Uhat, s, Vhat, Ak, tol,
                       max_sweeps, info_dev, ar, stream);
+}
+
+size_t pq_tsvdq_backward_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t k, int a_dtype) {
+  const bool f64 = a_dtype == PQ_F64;
+  const size_t e = elem(f64 ? PQ_F64 : PQ_F32);
+  const int64_t N = n1 * n2, L = std::max(n1, n2), S = std::min(n1, n2);
+  const int ks = ksplit_for(N);
+  return sweep_bytes(f64, N, p)
+         + align_up(8 * S * p) * 2                  // norms, sorted singular values
+         + align_up(8 * L * S * p)                  // every normalised Jacobi vector (float64)
+         + (f64 ? 0 : align_up(4 * L * S * p))      // ... rounded to float32
+         + align_up(sizeof(int) * p)                // near-degenerate pairs per face
+         + align_up(e * N * p) * 3                  // Gh, the face gradient, transform-domain A_k
+         + align_up(e * S * S * p)                  // Yall
+         + align_up(e * S * k * p) * 6              // H, P1, Ba, Bb, E, Ep
+         + align_up(e * L * k * p) * 2              // Ra, UE
+         + align_up(e * L * 2 * k * p)              // [U_K X]
+         + align_up(e * S * 2 * k * p)              // [N Y]
+         + align_up(e * (size_t)ks * p * n3) * 2;   // split-K slices of the two dQ terms
+}
+
+int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p,
+                      int64_t k, const void* Gbar, const void* sbar, void* dA, void* dQ, double gap_tol, double tol,
+                      int max_sweeps, int* info_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!A || !Q) return PQ_ERR_NULL;
+  if (!Gbar && !sbar) return PQ_ERR_NULL;  // nothing to propagate
+  if (!dA && !dQ) return PQ_ERR_NULL;      // nothing asked for
+  if (a_dtype != PQ_F32 && a_dtype != PQ_F64) return PQ_ERR_DTYPE;
+  PQ_CHECK(check_svd_args(A, a_dtype, Q, n1, n2, n3, p, k, PQ_PREC_DEFAULT, {dA, dQ}));
+  for (const void* o : {dA, dQ})
+    if (o && (o == Gbar || o == sbar)) return PQ_ERR_ALIAS;
+  if (dA && dA == dQ) return PQ_ERR_ALIAS;
+  if (!ws || ws_bytes < pq_tsvdq_backward_workspace(n1, n2, n3, p, k, a_dtype)) return PQ_ERR_WORKSPACE;
+  PQ_CHECK(sweep_defaults(a_dtype, tol, max_sweeps));
+  if (gap_tol <= 0.0) gap_tol = kDefaultGapTol;
+  const bool f64 = a_dtype == PQ_F64;
+  const int dt = f64 ? PQ_F64 : PQ_F32;
+  const size_t e = elem(dt);
+  const int64_t N = n1 * n2;
+  const int L = (int)std::max(n1, n2), S = (int)std::min(n1, n2);
+  const int ip = (int)p, ik = (int)k, in3 = (int)n3;
+  const int ks = ksplit_for(N);
+  const bool cols = n1 >= n2;
+  const bool has_g = Gbar != nullptr;
+  const Prec pr = Prec::Default;
+  Arena ar(ws, ws_bytes);
+  const SweepBufs b = take_sweep_bufs(ar, f64, N, p);
+  double* sig = static_cast<double*>(ar.take(8 * (size_t)S * p));
+  double* sigs = static_cast<double*>(ar.take(8 * (size_t)S * p));
+  double* Fall = static_cast<double*>(ar.take(8 * (size_t)L * S * p));
+  float* U32 = f64 ? nullptr : static_cast<float*>(ar.take(4 * (size_t)L * S * p));
+  int* cnt = static_cast<int*>(ar.take(sizeof(int) * p));
+  void* Gh = ar.take(e * N * p);
+  void* Mbar = ar.take(e * N * p);
+  void* Akh = ar.take(e * N * p);
+  void* Yall = ar.take(e * S * S * p);
+  void* H = ar.take(e * S * k * p);
+  void* P1 = ar.take(e * S * k * p);
+  void* Ba = ar.take(e * S * k * p);
+  void* Bb = ar.take(e * S * k * p);
+  void* E = ar.take(e * S * k * p);
+  void* Ep = ar.take(e * S * k * p);
+  void* Ra = ar.take(e * L * k * p);
+  void* UE = ar.take(e * L * k * p);
+  char* LHS = static_cast<char*>(ar.take(e * L * 2 * k * p));
+  void* RHS = ar.take(e * S * 2 * k * p);
+  char* parts = static_cast<char*>(ar.take(e * (size_t)ks * p * n3 * 2));
+  const void* U = f64 ? static_cast<const void*>(Fall) : static_cast<const void*>(U32);
+  const int64_t sU = (int64_t)L * S, sY = (int64_t)S * S, sK = (int64_t)S * k, sR = (int64_t)L * k;
+  // the forward factorisation: every singular vector of the Jacobi side
+  PQ_CHECK(converge(A, a_dtype, Q, n1, n2, n3, p, pr, tol, max_sweeps, b, info_dev, stream));
+  {
+    PQ_PROF("jacobi_finalize", stream);
+    PQ_TRY(pq::jacobi_norms_f64(b.W64, ip, S, L, sig, nullptr, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(b.W64, sig, ip, S, L, S, nullptr, Fall, sigs, stream));
+    if (!f64) PQ_TRY(pq::grad_narrow(Fall, U32, (int64_t)L * S * p, stream));
+  }
+  // M_t is the face (cols) or its transpose; op(M_t^T) is the face with
+  // transpose flag `cols`, op(M_t) with `!cols`.  Yall = M_t^T U, Y = its
+  // first k columns.
+  const void* M = b.Ah;
+  PQ_TRY(do_gemm("grad_gemm", face_gemm(cols, false, S, S, L, M, n1, N, U, L, sU, Yall, S, sY, ip), dt, pr,
+                 stream));
+  if (has_g) {
+    PQ_TRY(do_hat(Gbar, dt, Q, Gh, N, in3, ip, pr, stream));
+    // H = G_t^T U_K;  Ra = G_t Y;  Ba = U^T Ra;  Bb = Yall^T H
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(cols, false, S, ik, L, Gh, n1, N, U, L, sU, H, S, sK, ip), dt, pr,
+                   stream));
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(!cols, false, L, ik, S, Gh, n1, N, Yall, S, sY, Ra, L, sR, ip), dt, pr,
+                   stream));
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(true, false, S, ik, L, U, L, sU, Ra, L, sR, Ba, S, sK, ip), dt, pr,
+                   stream));
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(true, false, S, ik, S, Yall, S, sY, H, S, sK, Bb, S, sK, ip), dt, pr,
+                   stream));
+    {
+      PQ_PROF("grad_elementwise", stream);
+      PQ_TRY(pq::grad_coef(Ba, Bb, sigs, ip, S, ik, gap_tol, E, Ep, cnt, f64, stream));
+    }
+    // X = Ra diag(1/lambda) + U E into the second half of LHS;  P1 = Yall Ep
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(false, false, L, ik, S, U, L, sU, E, S, sK, UE, L, sR, ip), dt, pr,
+                   stream));
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(false, false, S, ik, S, Yall, S, sY, Ep, S, sK, P1, S, sK, ip), dt, pr,
+                   stream));
+    pq::ProfScope prof_elementwise("grad_elementwise", stream, 3);
+    PQ_TRY(pq::grad_xcombine(Ra, UE, U, sigs, ip, L, S, ik, LHS, f64, stream));
+    PQ_TRY(pq::grad_ncombine(H, P1, Yall, sbar, sigs, ip, S, S, ik, RHS, f64, stream));
+    if (info_dev) PQ_TRY(pq::grad_count(cnt, ip, info_dev + 3, stream));
+  } else {
+    pq::ProfScope prof_elementwise("grad_elementwise", stream, 3);
+    PQ_TRY(pq::grad_xcombine(nullptr, nullptr, U, sigs, ip, L, S, ik, LHS, f64, stream));
+    PQ_TRY(pq::grad_ncombine(nullptr, nullptr, Yall, sbar, sigs, ip, S, S, ik, RHS, f64, stream));
+    if (info_dev) PQ_TRY(pq::grad_count(cnt, 0, info_dev + 3, stream));
+  }
+  // the face gradient: dM_t = [U_K X][N Y]^T, written as the face itself
+  {
+    Gemm g = cols ? face_gemm(false, true, L, S, 2 * ik, LHS, L, (int64_t)L * 2 * k, RHS, S, (int64_t)S * 2 * k,
+                              Mbar, n1, N, ip)
+                  : face_gemm(false, true, S, L, 2 * ik, RHS, S, (int64_t)S * 2 * k, LHS, L, (int64_t)L * 2 * k,
+                              Mbar, n1, N, ip);
+    PQ_TRY(do_gemm("grad_gemm", g, dt, pr, stream));
+  }
+  if (dA) PQ_TRY(do_unhat(Mbar, Q, dA, dt, N, in3, ip, pr, stream));
+  if (dQ) {
+    // dQ^T = Mbar_(3) A_(3)^T + Akh_(3) Gbar_(3)^T
+    const size_t slab = e * (size_t)p * n3;
+    PQ_TRY(do_gemm("dq_gemm", dq_gemm(Mbar, A, ip, in3, N, parts, ks), dt, pr, stream));
+    int nparts = ks;
+    if (has_g) {
+      // Akh = U_K Y^T (cols) or Y U_K^T (rows): the transform-domain A_k
+      Gemm g = cols ? face_gemm(false, true, L, S, ik, U, L, sU, Yall, S, sY, Akh, n1, N, ip)
+                    : face_gemm(false, true, S, L, ik, Yall, S, sY, U, L, sU, Akh, n1, N, ip);
+      PQ_TRY(do_gemm("approx_gemm", g, dt, pr, stream));
+      PQ_TRY(do_gemm("dq_gemm", dq_gemm(Akh, Gbar, ip, in3, N, parts + slab * ks, ks), dt, pr, stream));
+      nparts += ks;
+    }
+    PQ_TRY(do_sum(parts, nparts, p * n3, p * n3, dQ, dt, stream));
+  }
+  return PQ_OK;
 }
 
 }  // extern "C"

@@ -189,7 +189,7 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
     float* Other = static_cast<float*>(cols ? x.Vhat : x.Uhat);
     double* sig = reinterpret_cast<double*>(ws + lo.sig[i]);
     BQ_TRY(pq::jacobi_norms_f64(W64 + lo.woff[i], ip, nv, L, sig, nullptr, s));
-    BQ_TRY(pq::jacobi_finalize_f64(W64 + lo.woff[i], sig, ip, nv, L, ik, nullptr, Ft, s));
+    BQ_TRY(pq::jacobi_finalize_f64(W64 + lo.woff[i], sig, ip, nv, L, ik, nullptr, Ft, nullptr, s));
     BQ_TRY(pq::jacobi_factor_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), Ft, Y, (int)x.n1, (int)x.n2, ik,
                                  ip, cols, s));
     BQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, tol, static_cast<float*>(x.s), Other, Fo, Ys, s));

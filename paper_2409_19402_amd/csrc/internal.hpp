@@ -134,9 +134,10 @@ hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, do
 // (n = nv p ints, may be null) cleared for jacobi_select
 hipError_t jacobi_norms_f64(const double* W, int p, int nv, int L, double* sig, int* rank, hipStream_t s);
 // the top k of each face by sig, normalised into F (L x k x p); a face keeps
-// min(k, kface[f]) vectors when kface is given, zero columns after them
+// min(k, kface[f]) vectors when kface is given, zero columns after them;
+// sig_sorted (k x p, may be null) receives the matching norms (0 past them)
 hipError_t jacobi_finalize_f64(const double* W, const double* sig, int p, int nv, int L, int k, const int* kface,
-                              double* F, hipStream_t s);
+                              double* F, double* sig_sorted, hipStream_t s);
 // *_Q-SVDII selection over the n = p nv values of sig (rank cleared by
 // jacobi_norms_f64): rho[f] = face f's values among the first K of the
 // descending order, K the first count whose energy reaches gamma of the
@@ -161,6 +162,23 @@ hipError_t jacobi_factor_f64(const double* Ah, const double* F, double* Y, int n
 // info[0] = the most sweeps a face used over both phases (used2 may be
 // NULL; max1 and max2 are the phases' caps), info[1] = #faces whose last
 // phase did not converge, info[2] = the sweeps summed over the faces.
+// ---- adjoint of the truncated tSVDQ (svdgrad.hip) -------------------------
+hipError_t grad_narrow(const double* x, float* y, int64_t n, hipStream_t s);
+// E and Ep (nv x k x p) from Ba = U^T Ra, Bb = Yall^T H and the sorted
+// singular values sig (nv x p); cnt[f] = pairs of face f whose gap fell
+// under gap_tol
+hipError_t grad_coef(const void* Ba, const void* Bb, const double* sig, int p, int nv, int k, double gap_tol,
+                     void* E, void* Ep, int* cnt, bool f64, hipStream_t s);
+// LHS (L x 2k x p) = [U_K, R diag(1/lambda) + UE] (R null: zero second half)
+hipError_t grad_xcombine(const void* R, const void* UE, const void* U, const double* sig, int p, int L, int nv, int k,
+                         void* LHS, bool f64, hipStream_t s);
+// RHS (S x 2k x p) = [H + P1 + Y diag(sbar / sigma), Y] (null terms are 0;
+// Y is read from Yall, S x S per face)
+hipError_t grad_ncombine(const void* H, const void* P1, const void* Y, const void* sbar, const double* sig, int p,
+                         int S, int nv, int k, void* RHS, bool f64, hipStream_t s);
+// out[0] = sum of cnt[0..p)
+hipError_t grad_count(const int* cnt, int p, int* out, hipStream_t s);
+
 hipError_t jacobi_info(const int* used1, const int* used2, int p, int max1, int max2, int* info,
                        hipStream_t s);
 

@@ -672,7 +672,7 @@ __global__ __launch_bounds__(256) void norms_kernel(const T* __restrict__ W, int
 template <typename T>
 __global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, const double* __restrict__ sig_all,
                                                        int nv, int L, int k, const int* __restrict__ kface,
-                                                       T* __restrict__ F) {
+                                                       T* __restrict__ F, double* __restrict__ sig_sorted) {
   extern __shared__ double sig[];  // nv doubles, then k ints
   int* order = reinterpret_cast<int*>(sig + nv);
   const int face = blockIdx.x;
@@ -693,10 +693,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, 
     T* dst = F + ((int64_t)face * k + r) * L;
     if (r >= kf || order[r] < 0) {
       for (int e = lane; e < L; e += 64) dst[e] = T(0);
+      if (sig_sorted && lane == 0) sig_sorted[(int64_t)face * k + r] = 0.0;
       continue;
     }
     const int j = order[r];
     const double v = sig[j];
+    if (sig_sorted && lane == 0) sig_sorted[(int64_t)face * k + r] = v;
     const double inv = v > 0.0 ? 1.0 / v : 0.0;
     for (int e = lane; e < L; e += 64) dst[e] = static_cast<T>(inv * (double)Wf[(int64_t)j * L + e]);
   }
@@ -1125,9 +1127,9 @@ hipError_t prep(const T* Ah, T* W, int n1, int n2, int p, hipStream_t s) {
 
 template <typename T>
 hipError_t finalize(const T* W, const double* sig, int p, int nv, int L, int k, const int* kface, T* F,
-                    hipStream_t s) {
+                    double* sig_sorted, hipStream_t s) {
   const size_t lds = sizeof(double) * (size_t)nv + sizeof(int) * (size_t)k;
-  finalize_kernel<T><<<p, 256, lds, s>>>(W, sig, nv, L, k, kface, F);
+  finalize_kernel<T><<<p, 256, lds, s>>>(W, sig, nv, L, k, kface, F, sig_sorted);
   return hipGetLastError();
 }
 
@@ -1193,8 +1195,8 @@ hipError_t jacobi_norms_f64(const double* W, int p, int nv, int L, double* sig, 
   return hipGetLastError();
 }
 hipError_t jacobi_finalize_f64(const double* W, const double* sig, int p, int nv, int L, int k, const int* kface,
-                              double* F, hipStream_t s) {
-  return finalize<double>(W, sig, p, nv, L, k, kface, F, s);
+                              double* F, double* sig_sorted, hipStream_t s) {
+  return finalize<double>(W, sig, p, nv, L, k, kface, F, sig_sorted, s);
 }
 hipError_t jacobi_select(const double* sig, int p, int nv, double gamma, int* rank, double* e2, int* rho,
                          hipStream_t s) {
