@@ -15,18 +15,22 @@
 using pq::Gemm;
 using pq::Prec;
 
+namespace pq {
 namespace {
-
 thread_local int g_last_hip = 0;
+}  // namespace
+int note_hip_error(hipError_t e) {
+  g_last_hip = static_cast<int>(e);
+  return PQ_ERR_HIP;
+}
+}  // namespace pq
+
+namespace {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int hip_status(hipError_t e) {
-  if (e == hipSuccess) return PQ_OK;
-  g_last_hip = static_cast<int>(e);
-  return PQ_ERR_HIP;
-}
+int hip_status(hipError_t e) { return e == hipSuccess ? PQ_OK : pq::note_hip_error(e); }
 
 #define PQ_TRY(expr)                        \
   do {                                      \
@@ -211,7 +215,7 @@ const char* pq_status_string(int code) {
   }
 }
 
-int pq_last_hip_error(void) { return g_last_hip; }
+int pq_last_hip_error(void) { return pq::g_last_hip; }
 
 int pq_autotune_enable(int on) {
   pq::tune_enable(on != 0);
@@ -684,11 +688,11 @@ int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t 
   {
     PQ_PROF("jacobi_refine", stream);
     if (f64)
-      PQ_TRY(pq::jacobi_refine_f64(Y, Ft, nv, L, ik, ip, tol, static_cast<double*>(s),
+      PQ_TRY(pq::jacobi_refine_f64(Y, Ft, nv, L, ik, ip, select ? rho : nullptr, tol, static_cast<double*>(s),
                                    static_cast<double*>(Other), static_cast<double*>(Fo),
                                    static_cast<double*>(Ys), stream));
     else
-      PQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, tol, static_cast<float*>(s),
+      PQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, select ? rho : nullptr, tol, static_cast<float*>(s),
                                    static_cast<float*>(Other), static_cast<float*>(Fo),
                                    static_cast<float*>(Ys), stream));
   }

@@ -34,7 +34,7 @@ constexpr double kTolFloor = 1e-10;
 constexpr double kDefaultTol = 1e-13;
 constexpr int64_t kMaxLen = 512;  // longest Jacobi vector of a batched tSVDQ face
 
-int hip_rc(hipError_t e) { return e == hipSuccess ? PQ_OK : PQ_ERR_HIP; }
+int hip_rc(hipError_t e) { return e == hipSuccess ? PQ_OK : pq::note_hip_error(e); }
 
 #define BQ_TRY(expr)                         \
   do {                                       \
@@ -192,7 +192,7 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
     BQ_TRY(pq::jacobi_finalize_f64(W64 + lo.woff[i], sig, ip, nv, L, ik, nullptr, Ft, nullptr, s));
     BQ_TRY(pq::jacobi_factor_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), Ft, Y, (int)x.n1, (int)x.n2, ik,
                                  ip, cols, s));
-    BQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, tol, static_cast<float*>(x.s), Other, Fo, Ys, s));
+    BQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, nullptr, tol, static_cast<float*>(x.s), Other, Fo, Ys, s));
   }
   if (info_dev) BQ_TRY(pq::jacobi_info(used1, used2, lo.nfaces, max_sweeps, polish, info_dev, s));
   return PQ_OK;

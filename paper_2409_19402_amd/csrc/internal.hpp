@@ -147,9 +147,9 @@ hipError_t jacobi_select(const double* sig, int p, int nv, double gamma, int* ra
 // float64 Jacobi on the k columns of Y (m1 x k x p), each rotation applied
 // to F (m2 x k x p) too; writes s (k x p, descending), Other = Y / s, Fo = F
 // and Ys = Y, all in descending order of s, in the output type.
-hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int p, double tol,
+hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol,
                              float* s_out, float* Other, float* Fo, float* Ys, hipStream_t s);
-hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, double tol,
+hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol,
                              double* s_out, double* Other, double* Fo, double* Ys, hipStream_t s);
 // y[i] = x[i] for i < n (float32 -> float64)
 hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s);
@@ -178,6 +178,10 @@ hipError_t grad_ncombine(const void* H, const void* P1, const void* Y, const voi
                          int S, int nv, int k, void* RHS, bool f64, hipStream_t s);
 // out[0] = sum of cnt[0..p)
 hipError_t grad_count(const int* cnt, int p, int* out, hipStream_t s);
+
+// records e as the last failed HIP call of this thread (pq_last_hip_error)
+// and returns PQ_ERR_HIP
+int note_hip_error(hipError_t e);
 
 hipError_t jacobi_info(const int* used1, const int* used2, int p, int max1, int max2, int* info,
                        hipStream_t s);

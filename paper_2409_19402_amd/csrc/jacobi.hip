@@ -38,6 +38,8 @@
 // column norms are the singular values.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -295,6 +297,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_global_kernel(T* __rest
 constexpr int kGB = 16;        // vectors per block
 constexpr int kG2 = 2 * kGB;   // vectors per block pair = Gram order
 constexpr int kGld = kG2 + 1;  // row stride of G and V in LDS (doubles): no bank conflicts on columns
+static_assert(kGld == 33, "the round loop forms row offsets as (x << 5) + x");
 constexpr int kGMat = kG2 * kGld;
 // two copies of G (each round reads one and writes the other), V (updated in
 // place: every entry is read and written by one thread only), a flag word
@@ -371,6 +374,24 @@ __device__ __forceinline__ double2 gram_rotation(double al, double be, double ga
   return on ? make_double2(cs, sn) : make_double2(1.0, 0.0);
 }
 
+// The same rotation in float32 (the coarse sweeps of float32 data): the
+// hardware reciprocal square root without refinement, about 1e-7 relative,
+// far below the coarse stopping threshold.  A rotation that is off, or
+// whose gamma^2 underflows, is the identity.  The result is selected
+// arithmetically so that the compiler keeps the loop free of branches.
+__device__ __forceinline__ float2 gram_rotation_f32(float al, float be, float ga, float tol2) {
+  const bool on = ga * ga > tol2 * al * be;
+  const float g = on ? ga : 1.0f;
+  const float tau = be - al;
+  const float r = __builtin_amdgcn_rsqf(fmaf(tau, tau, 4.0f * g * g));
+  const float h = fmaf(0.5f * fabsf(tau), r, 0.5f);
+  const float y = __builtin_amdgcn_rsqf(h);
+  const float onf = on ? 1.0f : 0.0f;
+  const float cs = fmaf(onf, fmaf(h, y, -1.0f), 1.0f);
+  const float sn = onf * ((tau >= 0.0f ? g : -g) * r * y);
+  return make_float2(cs, sn);
+}
+
 __device__ __forceinline__ void gram_pair(bool full, int r, int P, int& a, int& c) {
   if (full) {
     circle_pair(kG2, r, P, a, c);
@@ -397,10 +418,13 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   typedef GramMfma<T> M;
   typedef typename M::vec_t vec_t;
   constexpr int VEC = M::kVec;
-  constexpr int NS = sizeof(T) == 8 ? 2 : 1;  // Newton steps of the angle math
+  constexpr bool F32 = sizeof(T) == 4;
+  // G and the angle arithmetic: float32 in the coarse sweeps of float32 data,
+  // float64 in the polishing sweeps; V is float64 in both
+  typedef typename std::conditional<F32, float, double>::type R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* Gb = reinterpret_cast<double*>(smem_raw);  // G copies at Gb, Gb + kGMat
-  double* V = Gb + 2 * kGMat;
+  R* Gb = reinterpret_cast<R*>(smem_raw);  // G copies at Gb, Gb + kGMat
+  double* V = reinterpret_cast<double*>(smem_raw) + 2 * kGMat;
   int* any_rot = reinterpret_cast<int*>(V + kGMat);
   T* X = reinterpret_cast<T*>(smem_raw + kGramHead);
 
@@ -427,18 +451,26 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   // clamped addresses and out-of-range values masked
   if (L % VEC == 0 && fd.off % VEC == 0) {
     const int nq = L / VEC;
-    for (int q0 = 0; q0 < nq; q0 += 64) {
-      const int q = q0 + lane, qc = min(q, nq - 1);
-      vec_t buf[8];
+    // two 64-chunk columns per pass: 16 loads of each lane in flight at once
+    for (int q0 = 0; q0 < nq; q0 += 128) {
+      vec_t buf[2][8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int g = gvec(wave + 4 * i);
-        const vec_t v = *reinterpret_cast<const vec_t*>(Wf + (int64_t)min(g, nv - 1) * L + VEC * qc);
-        buf[i] = g < nv ? v : M::zero();
+      for (int h = 0; h < 2; ++h) {
+        const int qc = min(q0 + 64 * h + lane, nq - 1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int g = gvec(wave + 4 * i);
+          const vec_t v = *reinterpret_cast<const vec_t*>(Wf + (int64_t)min(g, nv - 1) * L + VEC * qc);
+          buf[h][i] = g < nv ? v : M::zero();
+        }
       }
-      if (q < nq) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) *reinterpret_cast<vec_t*>(X + (wave + 4 * i) * ldx + VEC * q) = buf[i];
+      for (int h = 0; h < 2; ++h) {
+        const int q = q0 + 64 * h + lane;
+        if (q < nq) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) *reinterpret_cast<vec_t*>(X + (wave + 4 * i) * ldx + VEC * q) = buf[h][i];
+        }
       }
     }
   } else {
@@ -475,7 +507,11 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
     const int ti = wave >> 1, tj = wave & 1;
     const T* xa = X + (16 * ti + r16) * ldx + 4 * kq;
     const T* xb = X + (16 * tj + r16) * ldx + 4 * kq;
-    typename M::acc_t acc = {0, 0, 0, 0};
+    // four independent accumulation chains (one per MFMA of a chunk), summed
+    // at the end, so consecutive MFMAs do not wait on each other
+    typename M::acc_t acc4[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc4[t] = typename M::acc_t{0, 0, 0, 0};
 #pragma unroll 2
     for (int s0 = 0; s0 < Lp; s0 += 16) {
       T a[4], b[4];
@@ -485,14 +521,15 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
         b[t] = xb[s0 + t];
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc = M::mma(a[t], b[t], acc);
+      for (int t = 0; t < 4; ++t) acc4[t] = M::mma(a[t], b[t], acc4[t]);
     }
+    const typename M::acc_t acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
     // lane holds G[16 ti + row(kq, j)][16 tj + r16]
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = 16 * ti + M::row(kq, j), col = 16 * tj + r16;
       if (ti != tj || row <= col) {
-        const double v = (double)acc[j];
+        const R v = (R)acc[j];
         Gb[row * kGld + col] = v;
         Gb[col * kGld + row] = v;
       }
@@ -511,13 +548,13 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
         const int e = tid + 256 * k, i = e >> 5, c = e & 31;
         if (i < c) {
           const double g = Gb[i * kGld + c];
-          need |= g * g > tol2 * Gb[i * kGld + i] * Gb[c * kGld + c];
+          need |= g * g > tol2 * (double)Gb[i * kGld + i] * (double)Gb[c * kGld + c];
         }
       }
     } else {
       const int i = tid >> 4, c = kGB + (tid & 15);
       const double g = Gb[i * kGld + c];
-      need = g * g > tol2 * Gb[i * kGld + i] * Gb[c * kGld + c];
+      need = g * g > tol2 * (double)Gb[i * kGld + i] * (double)Gb[c * kGld + c];
     }
     if (need) *any_rot = 1;
     __syncthreads();
@@ -525,52 +562,81 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   }
   if (tid == 0) flags[f * max_sweeps + sweep] = 1;
 
-  // Rounds on G (float64).  Each round reads the current copy of G and writes
-  // every entry of the other, so one barrier per round suffices.  Thread
-  // (P, P2) (P2 = lane mod 16) computes the rotation of pair P2, takes pair
-  // P's from lane P of its wave, writes the 2x2 block of J^T G J between the
-  // two pairs when P <= P2 (and its transpose), and rows P2 and P2 + 16 of
-  // V J in the columns of pair P.
+  // Rounds on G.  Each round reads the current copy of G and writes every
+  // entry of the other, so one barrier per round suffices.  Thread (P, P2)
+  // (P2 = lane mod 16) computes the rotation of pair P2, takes pair P's from
+  // lane P of its wave, writes its own 2x2 block of J^T G J (rows of pair P,
+  // columns of pair P2: threads (P, P2) and (P2, P) write mirror blocks, equal
+  // up to rounding), and rows P2 and P2 + 16 of V J in the columns of pair P.
+  // In float32 the rotation applied to V is renormalised in float64 (first
+  // order in cos^2 + sin^2 - 1, exact to 1e-14), so V stays orthogonal to
+  // float64 precision whatever the float32 angle arithmetic does.  The work
+  // per round is a few dozen instructions per thread: at wave64 on 16-lane
+  // SIMDs every instruction costs four cycles, and the instruction count is
+  // what bounds the round.
   const int P = tid >> 4, P2 = tid & 15;
   const int nrounds = full ? kG2 - 1 : kGB;
+  const R tol2r = (R)tol2;
+  const int vr0 = P2 * kGld, vr1 = (P2 + 16) * kGld;
+  // V J of a round is applied during the next round (after the barrier that
+  // ends it, before the one that ends the next), off the angle arithmetic's
+  // path: the entries a thread updates are its own within a round, and the
+  // barriers order the updates of one entry across rounds
+  int pa = 0, pc = 0;
+  double pvc = 1.0, pvs = 0.0;
+  auto apply_v = [&]() {
+    const double v0a = V[vr0 + pa], v0c = V[vr0 + pc];
+    const double v1a = V[vr1 + pa], v1c = V[vr1 + pc];
+    V[vr0 + pa] = pvc * v0a - pvs * v0c;
+    V[vr0 + pc] = pvs * v0a + pvc * v0c;
+    V[vr1 + pa] = pvc * v1a - pvs * v1c;
+    V[vr1 + pc] = pvs * v1a + pvc * v1c;
+  };
   int cur = 0;
   for (int r = 0; r < nrounds; ++r) {
-    const double* G = Gb + cur * kGMat;
-    double* Gn = Gb + (cur ^ 1) * kGMat;
+    const R* G = Gb + cur * kGMat;
+    R* Gn = Gb + (cur ^ 1) * kGMat;
     int a1, c1, a2, c2;
     gram_pair(full, r, P, a1, c1);
     gram_pair(full, r, P2, a2, c2);
-    const double m00 = G[a1 * kGld + a2], m01 = G[a1 * kGld + c2];
-    const double m10 = G[c1 * kGld + a2], m11 = G[c1 * kGld + c2];
-    const double v0a = V[P2 * kGld + a1], v0c = V[P2 * kGld + c1];
-    const double v1a = V[(P2 + 16) * kGld + a1], v1c = V[(P2 + 16) * kGld + c1];
-    const double2 q2 = gram_rotation<NS>(G[a2 * kGld + a2], G[c2 * kGld + c2], G[a2 * kGld + c2], tol2);
-    const double2 q1 = make_double2(__shfl(q2.x, P), __shfl(q2.y, P));
-    if (P <= P2) {
-      const double t00 = q2.x * m00 - q2.y * m01, t01 = q2.y * m00 + q2.x * m01;
-      const double t10 = q2.x * m10 - q2.y * m11, t11 = q2.y * m10 + q2.x * m11;
-      const double g00 = q1.x * t00 - q1.y * t10, g11 = q1.y * t01 + q1.x * t11;
-      double g01 = q1.x * t01 - q1.y * t11, g10 = q1.y * t00 + q1.x * t10;
-      if (P == P2 && q1.y != 0.0) {  // the rotation annihilates its own off-diagonal entry
-        g01 = 0.0;
-        g10 = 0.0;
-      }
-      Gn[a1 * kGld + a2] = g00;
-      Gn[a1 * kGld + c2] = g01;
-      Gn[c1 * kGld + a2] = g10;
-      Gn[c1 * kGld + c2] = g11;
-      Gn[a2 * kGld + a1] = g00;
-      Gn[c2 * kGld + a1] = g01;
-      Gn[a2 * kGld + c1] = g10;
-      Gn[c2 * kGld + c1] = g11;
+    const int ra1 = (a1 << 5) + a1, rc1 = (c1 << 5) + c1;  // row offsets (kGld = 33)
+    const int ra2 = (a2 << 5) + a2, rc2 = (c2 << 5) + c2;
+    const R m00 = G[ra1 + a2], m01 = G[ra1 + c2];
+    const R m10 = G[rc1 + a2], m11 = G[rc1 + c2];
+    const R al2 = G[ra2 + a2], be2 = G[rc2 + c2], ga2 = G[ra2 + c2];
+    if (r > 0) apply_v();
+    R c2r, s2r;
+    if constexpr (F32) {
+      const float2 q2 = gram_rotation_f32(al2, be2, ga2, tol2r);
+      c2r = q2.x;
+      s2r = q2.y;
+    } else {
+      const double2 q2 = gram_rotation<2>(al2, be2, ga2, tol2);
+      c2r = q2.x;
+      s2r = q2.y;
     }
-    V[P2 * kGld + a1] = q1.x * v0a - q1.y * v0c;
-    V[P2 * kGld + c1] = q1.y * v0a + q1.x * v0c;
-    V[(P2 + 16) * kGld + a1] = q1.x * v1a - q1.y * v1c;
-    V[(P2 + 16) * kGld + c1] = q1.y * v1a + q1.x * v1c;
+    const R c1r = __shfl(c2r, P), s1r = __shfl(s2r, P);
+    const R t00 = c2r * m00 - s2r * m01, t01 = s2r * m00 + c2r * m01;
+    const R t10 = c2r * m10 - s2r * m11, t11 = s2r * m10 + c2r * m11;
+    const bool own = P == P2 && s1r != R(0);  // the rotation annihilates its own off-diagonal entry
+    Gn[ra1 + a2] = c1r * t00 - s1r * t10;
+    Gn[ra1 + c2] = own ? R(0) : c1r * t01 - s1r * t11;
+    Gn[rc1 + a2] = own ? R(0) : s1r * t00 + c1r * t10;
+    Gn[rc1 + c2] = s1r * t01 + c1r * t11;
+    pa = a1;
+    pc = c1;
+    pvc = c1r;
+    pvs = s1r;
+    if constexpr (F32) {
+      const double nf = fma(-0.5, fma(pvc, pvc, pvs * pvs), 1.5);
+      pvc *= nf;
+      pvs *= nf;
+    }
     cur ^= 1;
     __syncthreads();
   }
+  apply_v();
+  __syncthreads();
 
   // X <- X V: D[c][e] = sum_a V[a][c] X[a][e]; wave w takes the 16-element
   // column tiles te = w, w + 4, ... and both row tiles tc of each.
@@ -584,18 +650,21 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
 #pragma unroll
     for (int s = 0; s < 8; ++s) xb[s] = X[(4 * s + kq) * ldx + 16 * te + r16];
     const int e = 16 * te + r16;
+    // the two row tiles as interleaved, independent MFMA chains
+    typename M::acc_t acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
-    for (int tc = 0; tc < 2; ++tc) {
-      typename M::acc_t acc = {0, 0, 0, 0};
+    for (int s = 0; s < 8; ++s) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) acc = M::mma(va[tc][s], xb[s], acc);
-      if (e < L) {
+      for (int tc = 0; tc < 2; ++tc) acc[tc] = M::mma(va[tc][s], xb[s], acc[tc]);
+    }
+    if (e < L) {
+#pragma unroll
+      for (int tc = 0; tc < 2; ++tc)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int g = gvec(16 * tc + M::row(kq, j));
-          if (g < nv) Wf[(int64_t)g * L + e] = acc[j];
+          if (g < nv) Wf[(int64_t)g * L + e] = acc[tc][j];
         }
-      }
     }
   }
 }
@@ -787,7 +856,8 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const double* __res
 // the outputs (type TO): s (k), Other = Y / s, Fo = F, Ys = Y, in that order.
 template <typename T, typename TO>
 __global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __restrict__ F, int m1,
-                                                     int m2, int k, double tol, int max_sweeps,
+                                                     int m2, int k, const int* __restrict__ kface,
+                                                     double tol, int max_sweeps,
                                                      TO* __restrict__ s_out, TO* __restrict__ Other,
                                                      TO* __restrict__ Fo, TO* __restrict__ Ys) {
   extern __shared__ double sig[];  // k doubles, then k ints
@@ -797,15 +867,16 @@ __global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __res
   T* Yf = Y + (int64_t)face * m1 * k;
   T* Ff = F + (int64_t)face * m2 * k;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kp = k + (k & 1);
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+  const int kf = kface ? max(0, min(k, kface[face])) : k;  // columns past kf are zero
+  const int kp = kf + (kf & 1);
+  for (int sweep = 0; sweep < max_sweeps && kf > 1; ++sweep) {
     if (threadIdx.x == 0) any_rot = 0;
     __syncthreads();
     for (int r = 0; r < kp - 1; ++r) {
       for (int pi = wave; pi < kp / 2; pi += 4) {
         int a, c;
         circle_pair(kp, r, pi, a, c);
-        if (a >= k || c >= k) continue;
+        if (a >= kf || c >= kf) continue;
         T* ya = Yf + (int64_t)a * m1;
         T* yc = Yf + (int64_t)c * m1;
         double al = 0.0, be = 0.0, ga = 0.0;
@@ -913,44 +984,161 @@ __global__ __launch_bounds__(256) void factor_t_kernel(const TA* __restrict__ Ah
   }
 }
 
-// Y(:, c) = Ah_l F(:, c) (Ah face n1 x n2, F n2 x k, Y n1 x k) with float64
-// accumulation: one thread per row i, columns of the face read coalesced,
-// F staged in LDS 64 rows at a time and read as broadcasts.
+
+// Y (n1 x k per face) = Ah_l (n1 x n2) F_l (n2 x k) with float64
+// accumulation: a workgroup takes 64 rows and 16 columns; its four waves take
+// quarters of the j range (lane = row, coalesced loads of Ah), stage their
+// chunks of F in LDS (read back as broadcasts) and sum their partials
+// through LDS at the end.
 template <typename TA>
-__global__ __launch_bounds__(256) void factor_n_kernel(const TA* __restrict__ Ah, const double* __restrict__ F,
-                                                       double* __restrict__ Y, int n1, int n2, int k) {
-  constexpr int JC = 64;
-  __shared__ double Fs[JC][16];
-  const int face = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int c0 = blockIdx.z * 16;
-  const int kc = min(16, k - c0);
+__global__ __launch_bounds__(256) void factor_rows_kernel(const TA* __restrict__ Ah, const double* __restrict__ F,
+                                                          double* __restrict__ Y, int n1, int n2, int k) {
+  constexpr int JC = 32;
+  __shared__ double Fs[4][JC][16];
+  __shared__ double red[3][16][64];
+  const int face = blockIdx.y, c0 = blockIdx.z * 16, kc = min(16, k - c0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int jq = (n2 + 3) / 4;
+  const int jb = wave * jq, je = min(n2, jb + jq);
   const TA* a = Ah + (int64_t)face * n1 * n2;
   const double* f = F + (int64_t)face * n2 * k;
   double acc[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-  for (int j0 = 0; j0 < n2; j0 += JC) {
+  const int nchunk = (jq + JC - 1) / JC;  // the same for every wave
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int j0 = jb + ch * JC;
     __syncthreads();
-    for (int e = threadIdx.x; e < JC * 16; e += 256) {
-      const int jj = e >> 4, c = e & 15;
-      Fs[jj][c] = (j0 + jj < n2 && c < kc) ? f[(int64_t)(c0 + c) * n2 + j0 + jj] : 0.0;
+#pragma unroll
+    for (int t = 0; t < JC * 16 / 64; ++t) {
+      const int e = lane + 64 * t, jj = e >> 4, c = e & 15;
+      const int jg = j0 + jj;
+      Fs[wave][jj][c] = (jg < je && c < kc) ? f[(int64_t)(c0 + c) * n2 + jg] : 0.0;
     }
     __syncthreads();
     if (i < n1) {
-      const int jn = min(JC, n2 - j0);
+      const int jn = max(0, min(JC, je - j0));
+#pragma unroll 4
       for (int jj = 0; jj < jn; ++jj) {
         const double x = (double)a[i + (int64_t)(j0 + jj) * n1];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc[c] = fma(x, Fs[jj][c], acc[c]);
+        for (int c = 0; c < 16; ++c) acc[c] = fma(x, Fs[wave][jj][c], acc[c]);
       }
     }
   }
-  if (i >= n1) return;
-  double* y = Y + (int64_t)face * n1 * k;
+  if (wave > 0) {
 #pragma unroll
-  for (int c = 0; c < 16; ++c)
-    if (c < kc) y[(int64_t)(c0 + c) * n1 + i] = acc[c];
+    for (int c = 0; c < 16; ++c) red[wave - 1][c][lane] = acc[c];
+  }
+  __syncthreads();
+  if (wave == 0 && i < n1) {
+    double* y = Y + (int64_t)face * n1 * k;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < kc) y[(int64_t)(c0 + c) * n1 + i] = acc[c] + red[0][c][lane] + red[1][c][lane] + red[2][c][lane];
+  }
+}
+
+// The refinement of refine_kernel with the k columns of Y and F of the face
+// held in LDS and one wave per pair (16 waves): the face's k columns cost
+// 8 k (m1 + m2) bytes.  A face keeps min(k, kface[f]) columns when kface is
+// given; the rest are zero, never rotate, and sort last.
+template <typename TO>
+__global__ __launch_bounds__(1024) void refine_lds_kernel(const double* __restrict__ Yg, const double* __restrict__ Fg,
+                                                          int m1, int m2, int k, const int* __restrict__ kface,
+                                                          double tol, int max_sweeps, TO* __restrict__ s_out,
+                                                          TO* __restrict__ Other, TO* __restrict__ Fo,
+                                                          TO* __restrict__ Ys) {
+  extern __shared__ double rl_smem[];
+  double* Yf = rl_smem;               // k columns of m1
+  double* Ff = Yf + (int64_t)k * m1;  // k columns of m2
+  double* sig = Ff + (int64_t)k * m2;
+  int* order = reinterpret_cast<int*>(sig + k);
+  __shared__ int any_rot;
+  const int face = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kf = kface ? max(0, min(k, kface[face])) : k;
+  const double* yg = Yg + (int64_t)face * m1 * k;
+  const double* fg = Fg + (int64_t)face * m2 * k;
+  for (int e = tid; e < k * m1; e += 1024) Yf[e] = yg[e];
+  for (int e = tid; e < k * m2; e += 1024) Ff[e] = fg[e];
+  __syncthreads();
+  const int kp = kf + (kf & 1);
+  for (int sweep = 0; sweep < max_sweeps && kf > 1; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < kp - 1; ++r) {
+      for (int pi = wave; pi < kp / 2; pi += 16) {
+        int a, c;
+        circle_pair(kp, r, pi, a, c);
+        if (a >= kf || c >= kf) continue;
+        double* ya = Yf + (int64_t)a * m1;
+        double* yc = Yf + (int64_t)c * m1;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int e = lane; e < m1; e += 64) {
+          const double x = ya[e], y = yc[e];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+        const Rot q = rotation(wave_total(al), wave_total(be), wave_total(ga), tol);
+        if (q.on) {
+          for (int e = lane; e < m1; e += 64) {
+            const double x = ya[e], y = yc[e];
+            ya[e] = q.c * x - q.s * y;
+            yc[e] = q.s * x + q.c * y;
+          }
+          double* fa = Ff + (int64_t)a * m2;
+          double* fc = Ff + (int64_t)c * m2;
+          for (int e = lane; e < m2; e += 64) {
+            const double x = fa[e], y = fc[e];
+            fa[e] = q.c * x - q.s * y;
+            fc[e] = q.s * x + q.c * y;
+          }
+          if (lane == 0) any_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = any_rot;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int c = wave; c < k; c += 16) {
+    double acc = 0.0;
+    for (int e = lane; e < m1; e += 64) {
+      const double x = Yf[(int64_t)c * m1 + e];
+      acc = fma(x, x, acc);
+    }
+    acc = wave_total(acc);
+    if (lane == 0) sig[c] = sqrt(acc);
+  }
+  for (int r = tid; r < k; r += 1024) order[r] = -1;
+  __syncthreads();
+  for (int c = tid; c < k; c += 1024) {
+    const double v = sig[c];
+    int r = 0;
+    for (int i = 0; i < k; ++i) r += (sig[i] > v) || (sig[i] == v && i < c);
+    order[r] = c;
+  }
+  __syncthreads();
+  for (int r = wave; r < k; r += 16) {
+    // equal ranks arise only from NaN norms; such a slot reads column r
+    const int c = order[r] >= 0 && order[r] < k ? order[r] : r;
+    const double v = sig[c];
+    const double inv = v > 0.0 ? 1.0 / v : 0.0;
+    if (lane == 0) s_out[(int64_t)face * k + r] = static_cast<TO>(v);
+    TO* o = Other + ((int64_t)face * k + r) * m1;
+    TO* ys = Ys + ((int64_t)face * k + r) * m1;
+    for (int e = lane; e < m1; e += 64) {
+      const double x = Yf[(int64_t)c * m1 + e];
+      ys[e] = static_cast<TO>(x);
+      o[e] = static_cast<TO>(inv * x);
+    }
+    TO* fo = Fo + ((int64_t)face * k + r) * m2;
+    for (int e = lane; e < m2; e += 64) fo[e] = static_cast<TO>(Ff[(int64_t)c * m2 + e]);
+  }
 }
 
 __global__ void info_kernel(const int* __restrict__ used1, const int* __restrict__ used2, int p,
@@ -1134,10 +1322,23 @@ hipError_t finalize(const T* W, const double* sig, int p, int nv, int L, int k, 
 }
 
 template <typename TO>
-hipError_t refine(double* Y, double* F, int m1, int m2, int k, int p, double tol, TO* s_out, TO* Other,
-                  TO* Fo, TO* Ys, hipStream_t s) {
-  const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)k;
-  refine_kernel<double, TO><<<p, 256, lds, s>>>(Y, F, m1, m2, k, tol, 12, s_out, Other, Fo, Ys);
+hipError_t refine(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol, TO* s_out,
+                  TO* Other, TO* Fo, TO* Ys, hipStream_t s) {
+  // dynamic LDS up to 159 KiB (the kernel's static word fits in the rest)
+  constexpr size_t kLdsCap = 159 * 1024;
+  const size_t lds_lds = sizeof(double) * (size_t)k * (m1 + m2) + (sizeof(double) + sizeof(int)) * (size_t)k;
+  static const hipError_t attr = [] {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&refine_lds_kernel<TO>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsCap);
+    if (e != hipSuccess) (void)hipGetLastError();  // clear a refused request: the global form runs instead
+    return e;
+  }();
+  if (attr == hipSuccess && lds_lds <= kLdsCap) {
+    refine_lds_kernel<TO><<<p, 1024, lds_lds, s>>>(Y, F, m1, m2, k, kface, tol, 12, s_out, Other, Fo, Ys);
+  } else {
+    const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)k;
+    refine_kernel<double, TO><<<p, 256, lds, s>>>(Y, F, m1, m2, k, kface, tol, 12, s_out, Other, Fo, Ys);
+  }
   return hipGetLastError();
 }
 
@@ -1147,8 +1348,8 @@ hipError_t factor(const TA* Ah, const double* F, double* Y, int n1, int n2, int 
   if (cols) {
     factor_t_kernel<TA><<<dim3((unsigned)((n2 + 3) / 4), (unsigned)p), 256, 0, s>>>(Ah, F, Y, n1, n2, k);
   } else {
-    factor_n_kernel<TA><<<dim3((unsigned)((n1 + 255) / 256), (unsigned)p, (unsigned)((k + 15) / 16)), 256,
-                          0, s>>>(Ah, F, Y, n1, n2, k);
+    factor_rows_kernel<TA><<<dim3((unsigned)((n1 + 63) / 64), (unsigned)p, (unsigned)((k + 15) / 16)), 256, 0,
+                             s>>>(Ah, F, Y, n1, n2, k);
   }
   return hipGetLastError();
 }
@@ -1209,13 +1410,13 @@ hipError_t jacobi_select(const double* sig, int p, int nv, double gamma, int* ra
   select_kernel<<<1, kSelThreads, 0, s>>>(sig, rank, n, p, nv, gamma, e2, rho);
   return hipGetLastError();
 }
-hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int p, double tol,
+hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol,
                              float* s_out, float* Other, float* Fo, float* Ys, hipStream_t s) {
-  return refine<float>(Y, F, m1, m2, k, p, tol, s_out, Other, Fo, Ys, s);
+  return refine<float>(Y, F, m1, m2, k, p, kface, tol, s_out, Other, Fo, Ys, s);
 }
-hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, double tol,
+hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol,
                              double* s_out, double* Other, double* Fo, double* Ys, hipStream_t s) {
-  return refine<double>(Y, F, m1, m2, k, p, tol, s_out, Other, Fo, Ys, s);
+  return refine<double>(Y, F, m1, m2, k, p, kface, tol, s_out, Other, Fo, Ys, s);
 }
 hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s) {
   widen_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
