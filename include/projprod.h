@@ -42,12 +42,12 @@
  *                    is split three ways instead, which is exact in float32
  *   PQ_PREC_BF16X6   three-way split of both operands, 6 passes
  * The modes apply to the forward transform A x_3 Q^T (pq_hat and the
- * transform steps of pq_qprod, pq_proj and pq_tsvdq), to the facewise product
- * (pq_facewise and the facewise step of pq_qprod) and to the return
- * transform (pq_unhat for p <= 32; float32 above).  Inside pq_qprod,
- * pq_proj and pq_tsvdq the return transform of the X3 mode runs as X6: it is
- * bound by its writes, so the extra products are free, and they keep the
- * error of the whole chain well inside the float32 tolerance.  The fused
+ * transform steps of pq_qprod, pq_proj, pq_tsvdq and pq_svdii), to the
+ * facewise product (pq_facewise and the facewise step of pq_qprod) and to the
+ * return transform (pq_unhat for p <= 32; float32 above).  Inside pq_qprod,
+ * pq_proj, pq_tsvdq and pq_svdii the return transform of the X3 mode runs as
+ * X6: it is bound by its writes, so the extra products are free, and they
+ * keep the error of the whole chain well inside the float32 tolerance.  The fused
  * projection, the tSVDQ's own factor products and the adjoints run on
  * float32 MFMA in every mode.
  */
@@ -139,6 +139,20 @@ int pq_profile_names(char* buf, size_t len);
  */
 int pq_check_q(const void* Q, int q_dtype, int64_t n3, int64_t p,
                double* out_dev, hipStream_t stream);
+
+/*
+ * Q (n3 x p, row-major, q_dtype F32 or F64) of one of the fixed transforms
+ * that Sec. 5 compares with the data-dependent U3 (pq_u3):
+ *   PQ_Q_IDENTITY  the first p columns of I_n3;
+ *   PQ_Q_DCT       the first p rows of the orthonormal DCT-II matrix C,
+ *                  transposed: Q(t, l) = C(l, t) = w_l cos(pi (2t + 1) l /
+ *                  (2 n3)), w_0 = sqrt(1/n3), w_l = sqrt(2/n3) (the real
+ *                  stand-in for the t-product's DFT).
+ * Both have orthonormal columns.  Returns PQ_ERR_ARG for another kind.
+ */
+#define PQ_Q_IDENTITY 0
+#define PQ_Q_DCT      1
+int pq_build_q(int kind, int64_t n3, int64_t p, int q_dtype, void* Q, hipStream_t stream);
 
 /* ---- mode-3 transforms (Def. 2.2 with M = Q^T and M = Q) ----------------- */
 /*
@@ -235,8 +249,10 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
  * for the projection error.  A: n1 x n2 x n3 face-major, a_dtype F32 or
  * F64.  Computed as the top-p eigenvectors of the Gram matrix
  * A_(3) A_(3)^T (matrix-core product split over the n1 n2 tubes, slices
- * summed in float64) by float64 one-sided Jacobi; each column is signed so
- * that its largest-magnitude entry (the first on ties) is positive.
+ * summed in float64) by float64 one-sided Jacobi (F32 data: Gram-form
+ * sweeps to 1e-10, at most 16; F64 data: vector-form sweeps to 1e-13, at
+ * most 30); each column is signed so that its largest-magnitude entry (the
+ * first on ties) is positive.
  * Outputs (float32 for F32 data, float64 for F64): Q n3 x p row-major;
  * lambda (may be NULL) p values, the eigenvalues sigma_i(A_(3))^2 as
  * Rayleigh quotients, descending.  info_dev (device int[3], may be NULL) as

@@ -21,10 +21,10 @@ Parity status of each function is listed in ``PARITY`` below.
 
 from .core import (  # noqa: F401
     unfold3, fold3, mode3, facewise, mprod, hat, unhat, qprod, proj,
-    identity_tensor, ftranspose, check_q, fro2, u3,
+    identity_tensor, ftranspose, check_q, fro2, u3, identity_q, dct_q,
 )
 from .tsvdq import (  # noqa: F401
-    tsvdq, tsvdq_error_terms, relative_error, tsvdq_ii, TSVDQResult,
+    tsvdq, tsvdq_error_terms, relative_error, tsvdq_ii, TSVDQResult, hosvd,
 )
 from .grad import qprod_backward, proj_backward, tsvdq_backward  # noqa: F401
 
@@ -48,4 +48,9 @@ PARITY = {
                       "(tall, wide and square faces, k = 1 and k = min(n1, n2)) and "
                       "torch CPU float64 autograd through torch.linalg.svd",
     "check_q": "pinned: closed form on constructed matrices",
+    "identity_q/dct_q": "pinned: scipy's orthonormal DCT-II of the identity (library routine), "
+                        "the n3 = 2 Haar closed form, orthonormal columns",
+    "hosvd": "pinned: full multilinear rank reproduces A, the rank-(n1, n2, p) case equals "
+             "the projection onto U3 (Thm. 4.3), and the truncation-error bound by the "
+             "discarded mode singular values",
 }

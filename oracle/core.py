@@ -121,3 +121,20 @@ def u3(A, p):
         if Q[i, j] < 0:
             Q[:, j] = -Q[:, j]
     return Q, S[:p] ** 2
+
+
+def identity_q(n3, p):
+    """The first p columns of I_n3 (the control transform of Sec. 5)."""
+    return np.eye(n3)[:, :p]
+
+
+def dct_q(n3, p):
+    """The transposed first p rows of the orthonormal DCT-II matrix C
+    (Sec. 5.1.1): C[l, t] = w_l cos(pi (2t + 1) l / (2 n3)), w_0 = sqrt(1/n3),
+    w_l = sqrt(2/n3); Q = C[:p, :]^T, written out from that definition."""
+    C = np.zeros((n3, n3))
+    for l in range(n3):
+        w = np.sqrt(1.0 / n3) if l == 0 else np.sqrt(2.0 / n3)
+        for t in range(n3):
+            C[l, t] = w * np.cos(np.pi * (2 * t + 1) * l / (2 * n3))
+    return C[:p, :].T

@@ -120,3 +120,23 @@ def tsvdq_ii(A, Q, gamma):
         ri = int(rho[i])
         Akh[:, :, i] = (U[:, :ri] * S[:ri]) @ Vt[:ri, :]
     return rho, unhat(Akh, Q)
+
+
+def _unfold(A, mode):
+    """Mode-i unfolding: the mode-i fibres as columns (any fixed column order
+    serves, the left singular vectors do not depend on it)."""
+    return np.moveaxis(A, mode, 0).reshape(A.shape[mode], -1)
+
+
+def hosvd(A, k1, k2, k3):
+    """Truncated HOSVD of multilinear rank (k1, k2, k3) (Sec. 4.2): U_i the
+    leading left singular vectors of each unfolding, core
+    G = A x_1 U1^T x_2 U2^T x_3 U3^T, and A_k = G x_1 U1 x_2 U2 x_3 U3.
+    Used only to check Thm. 4.6 against the tSVDQ."""
+    A = _f64(A)
+    Us = []
+    for mode, k in enumerate((k1, k2, k3)):
+        U, _, _ = np.linalg.svd(_unfold(A, mode), full_matrices=False)
+        Us.append(U[:, :k])
+    G = np.einsum("ijt,ia,jb,tc->abc", A, Us[0], Us[1], Us[2])
+    return np.einsum("abc,ia,jb,tc->ijt", G, Us[0], Us[1], Us[2])

@@ -286,6 +286,19 @@ def proj(A, Q, prec="default"):
 TSVDQ = namedtuple("TSVDQ", "Uhat s Vhat Uk Sk Vk Ak info")
 
 
+Q_KINDS = {"identity": 0, "dct": 1}
+
+
+def build_q(kind, n3, p, dtype=torch.float32, device="cuda"):
+    """Q (n3, p) of a fixed transform of Sec. 5: "identity" or "dct" (the
+    first p rows of the orthonormal DCT-II matrix, transposed)."""
+    if kind not in Q_KINDS:
+        raise ValueError(f"kind must be one of {sorted(Q_KINDS)}")
+    Q = torch.empty((n3, p), dtype=dtype, device=device)
+    call("pq_build_q", Q_KINDS[kind], n3, p, _DT[dtype], _ptr(Q), _stream(Q.device))
+    return Q
+
+
 def u3(A, p):
     """Q = U3(:, :p) of A (Thm. 4.3): the leading p left singular vectors of
     the mode-3 unfolding, as an (n3, p) tensor (float32, or float64 for

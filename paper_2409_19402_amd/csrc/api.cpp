@@ -107,6 +107,9 @@ constexpr double kPolishTol = 1e-13;
 // floored here (the coupling it leaves, about tol / (2 x relative gap), is
 // still far below float32 resolution).
 constexpr double kGramTolFloor = 1e-10;
+// sweep cap of the Gram-form eigen-iteration of U3 for float32 data: the
+// float64 sweeps from scratch converge in 6-10
+constexpr int kU3GramSweeps = 16;
 constexpr int kMaxSweepsCap = 100;
 // relative gap |lambda_c - lambda_j| / lambda_c at or under which the adjoint
 // of the truncation drops the coupling of a kept and a discarded pair
@@ -262,6 +265,17 @@ int pq_check_q(const void* Q, int q_dtype, int64_t n3, int64_t p, double* out_de
   PQ_CHECK(check_p(n3, p));
   PQ_PROF("check_q", stream);
   PQ_TRY(pq::check_q_launch(Q, is_f64(q_dtype), (int)n3, (int)p, out_dev, stream));
+  return PQ_OK;
+}
+
+int pq_build_q(int kind, int64_t n3, int64_t p, int q_dtype, void* Q, hipStream_t stream) {
+  if (!Q) return PQ_ERR_NULL;
+  if (kind != PQ_Q_IDENTITY && kind != PQ_Q_DCT) return PQ_ERR_ARG;
+  PQ_CHECK(check_ar_dtype(q_dtype));
+  PQ_CHECK(check_dims({n3}));
+  PQ_CHECK(check_p(n3, p));
+  PQ_PROF("build_q", stream);
+  PQ_TRY(pq::build_q(kind, is_f64(q_dtype), (int)n3, (int)p, Q, stream));
   return PQ_OK;
 }
 
@@ -538,9 +552,16 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
     else PQ_TRY(pq::sum_to_f64(static_cast<const float*>(parts), ks, n3 * n3, n3 * n3, G, stream));
   }
   // its eigenvectors: one-sided Jacobi on the symmetric positive semidefinite
-  // G (converged columns are lambda_j u_j), float64 throughout
+  // G (converged columns are lambda_j u_j), float64 throughout.  For float32
+  // data the Gram-form sweeps serve (their 1e-10 stopping floor leaves the
+  // eigenvectors far more accurate than the data); float64 data keeps the
+  // vector form and 1e-13.
   PQ_TRY(hipMemcpyAsync(W, G, 8 * (size_t)n3 * n3, hipMemcpyDeviceToDevice, stream));
-  PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, kDefaultSweeps64, kPolishTol, used, flags, stream));
+  const int u3_sweeps = f64 ? kDefaultSweeps64 : kU3GramSweeps;
+  if (!f64)
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, u3_sweeps, kGramTolFloor, used, flags, stream));
+  else
+    PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, u3_sweeps, kPolishTol, used, flags, stream));
   {
     PQ_PROF("jacobi_finalize", stream);
     PQ_TRY(pq::jacobi_norms_f64(W, 1, in3, in3, sig, nullptr, stream));
@@ -550,7 +571,7 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
     PQ_PROF("u3_finish", stream);
     PQ_TRY(pq::u3_finish(F, G, in3, ip, Q, lambda, f64, stream));
   }
-  if (info_dev) PQ_TRY(pq::jacobi_info(used, nullptr, 1, kDefaultSweeps64, 0, info_dev, stream));
+  if (info_dev) PQ_TRY(pq::jacobi_info(used, nullptr, 1, u3_sweeps, 0, info_dev, stream));
   return PQ_OK;
 }
 

@@ -95,7 +95,10 @@ hipError_t sum_to_f64(const float* parts, int nparts, int64_t stride, int64_t co
 // entry is positive; lambda[r] = f_r^T G f_r (G n3 x n3)
 hipError_t u3_finish(const double* F, const double* G, int n3, int p, void* Q, void* lambda, bool f64,
                      hipStream_t s);
+// max |(Q^T Q - I)_ab| into out[0] (float64): two launches, the first clears out
 hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, hipStream_t s);
+// Q (n3 x p row-major) of a fixed transform: kind 0 identity, 1 DCT-II
+hipError_t build_q(int kind, bool f64, int n3, int p, void* Q, hipStream_t s);
 
 // ---- facewise one-sided Jacobi SVD (jacobi.hip) -----------------------------
 // W holds, for each of p faces, nv vectors of length L (vector j of face l at

@@ -1,33 +1,64 @@
-// The float64 Stiefel check of Q (precondition of Def. 3.1) and the last step
-// of the construction of Q = U3 (Thm. 4.3).
+// The float64 Stiefel check of Q (precondition of Def. 3.1), the fixed
+// transforms used as Q in the experiments of Sec. 5 (identity, DCT) and the
+// last step of the construction of Q = U3 (Thm. 4.3).
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace pq {
 namespace {
 
+// max over a <= b of |(Q^T Q - I)_ab| in float64: one wave per column pair
+// (lanes over t), the maximum folded into out[0] by an integer atomic on the
+// bit pattern (non-negative doubles order as their bits do); out[0] is
+// cleared by clear_q_kernel first.
 template <typename TQ>
 __global__ __launch_bounds__(256) void check_q_kernel(const TQ* __restrict__ Q, int n3, int p,
-                                                      double* __restrict__ out) {
-  __shared__ double red[256];
-  double mx = 0.0;
-  const int64_t npair = (int64_t)p * p;
-  for (int64_t e = threadIdx.x; e < npair; e += 256) {
-    const int a = (int)(e / p), b = (int)(e - (int64_t)a * p);
-    if (b < a) continue;
-    double acc = 0.0;
-    for (int t = 0; t < n3; ++t)
-      acc = fma((double)Q[(int64_t)t * p + a], (double)Q[(int64_t)t * p + b], acc);
-    if (a == b) acc -= 1.0;
-    mx = fmax(mx, fabs(acc));
+                                                      unsigned long long* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t pair = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t npair = (int64_t)p * (p + 1) / 2;
+  if (pair >= npair) return;
+  // pair -> (a, b), a <= b, row by row of the upper triangle
+  int a = 0;
+  int64_t rest = pair;
+  while (rest >= p - a) {
+    rest -= p - a;
+    ++a;
   }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
+  const int b = a + (int)rest;
+  double acc = 0.0;
+  for (int t = lane; t < n3; t += 64)
+    acc = fma((double)Q[(int64_t)t * p + a], (double)Q[(int64_t)t * p + b], acc);
+  acc = wave_total(acc);
+  if (lane == 0) {
+    const double d = fabs(a == b ? acc - 1.0 : acc);
+    atomicMax(out, (unsigned long long)__double_as_longlong(d));
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ void clear_q_kernel(unsigned long long* __restrict__ out) {
+  if (threadIdx.x == 0) out[0] = 0ull;
+}
+
+// Q (n3 x p row-major) of a fixed transform: kind 0 the first p columns of
+// the identity, kind 1 the first p rows of the orthonormal DCT-II matrix C
+// (n3 x n3), transposed: Q(t, l) = C(l, t) = w_l cos(pi (2t + 1) l / (2 n3)),
+// w_0 = sqrt(1 / n3), w_l = sqrt(2 / n3).  The cosine takes the angle as an
+// exact rational multiple of pi (the integer (2t + 1) l reduced mod 4 n3).
+template <typename TO>
+__global__ __launch_bounds__(256) void build_q_kernel(int kind, int n3, int p, TO* __restrict__ Q) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n3 * p) return;
+  const int t = (int)(e / p), l = (int)(e - (int64_t)t * p);
+  double v;
+  if (kind == 0) {
+    v = t == l ? 1.0 : 0.0;
+  } else {
+    const int64_t m = ((int64_t)(2 * t + 1) * l) % (4 * (int64_t)n3);
+    const double w = l == 0 ? sqrt(1.0 / n3) : sqrt(2.0 / n3);
+    v = w * cospi((double)m / (2.0 * n3));
+  }
+  Q[e] = static_cast<TO>(v);
 }
 
 // out[e] = sum over z of parts[z * stride + e], accumulated in float64 in a
@@ -91,8 +122,19 @@ __global__ __launch_bounds__(256) void u3_finish_kernel(const double* __restrict
 }  // namespace
 
 hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, hipStream_t s) {
-  if (f64) check_q_kernel<double><<<1, 256, 0, s>>>(static_cast<const double*>(Q), n3, p, out);
-  else check_q_kernel<float><<<1, 256, 0, s>>>(static_cast<const float*>(Q), n3, p, out);
+  unsigned long long* bits = reinterpret_cast<unsigned long long*>(out);
+  clear_q_kernel<<<1, 64, 0, s>>>(bits);
+  const int64_t npair = (int64_t)p * (p + 1) / 2;
+  const unsigned grid = (unsigned)((npair + 3) / 4);
+  if (f64) check_q_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double*>(Q), n3, p, bits);
+  else check_q_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float*>(Q), n3, p, bits);
+  return hipGetLastError();
+}
+
+hipError_t build_q(int kind, bool f64, int n3, int p, void* Q, hipStream_t s) {
+  const unsigned grid = (unsigned)(((int64_t)n3 * p + 255) / 256);
+  if (f64) build_q_kernel<double><<<grid, 256, 0, s>>>(kind, n3, p, static_cast<double*>(Q));
+  else build_q_kernel<float><<<grid, 256, 0, s>>>(kind, n3, p, static_cast<float*>(Q));
   return hipGetLastError();
 }
 

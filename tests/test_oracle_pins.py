@@ -450,6 +450,45 @@ def test_tsvdq_backward_torch_autograd():
     np.testing.assert_allclose(dQ, tQ.grad.numpy(), rtol=1e-9, atol=1e-9)
 
 
+def test_dct_q_against_scipy_and_closed_form():
+    """The DCT transform of Sec. 5.1.1 against scipy's orthonormal DCT-II
+    (a library routine applied to the identity gives C), the n3 = 2 Haar
+    matrix, and orthonormal columns."""
+    fft = pytest.importorskip("scipy.fft")
+    for n3, p in ((7, 3), (16, 16), (200, 20)):
+        C = fft.dct(np.eye(n3), type=2, norm="ortho", axis=0)
+        Q = oracle.dct_q(n3, p)
+        np.testing.assert_allclose(Q, C[:p, :].T, atol=1e-13)
+        np.testing.assert_allclose(Q.T @ Q, np.eye(p), atol=1e-12)
+    r = 1 / np.sqrt(2)
+    np.testing.assert_allclose(oracle.dct_q(2, 2), [[r, r], [r, -r]], atol=1e-15)
+    np.testing.assert_array_equal(oracle.identity_q(5, 2), np.eye(5)[:, :2])
+
+
+def test_hosvd_pins_and_thm_4_6():
+    """The truncated HOSVD: full multilinear rank reproduces A; rank
+    (n1, n2, p) is the projection onto U3(:, 1:p) (Thm. 4.3); its error obeys
+    the bound by the discarded mode singular values.  Then Thm. 4.6: with
+    Q = U3(:, 1:p) and k = min(k1, k2) the tSVDQ is no worse."""
+    rng = np.random.default_rng(21)
+    n1, n2, n3 = 9, 7, 8
+    A = rng.standard_normal((n1, n2, n3))
+    np.testing.assert_allclose(oracle.hosvd(A, n1, n2, n3), A, atol=1e-12)
+    p = 3
+    Q, _ = oracle.u3(A, p)
+    np.testing.assert_allclose(oracle.hosvd(A, n1, n2, p), oracle.proj(A, Q), atol=1e-12)
+    for k1, k2, k3 in ((3, 2, 4), (5, 5, 2), (2, 6, 6)):
+        err2 = oracle.fro2(A - oracle.hosvd(A, k1, k2, k3))
+        bound = 0.0
+        for mode, k in enumerate((k1, k2, k3)):
+            s = np.linalg.svd(np.moveaxis(A, mode, 0).reshape(A.shape[mode], -1), compute_uv=False)
+            bound += float(np.sum(s[k:] ** 2))
+        assert err2 <= bound * (1 + 1e-12)
+        Qk, _ = oracle.u3(A, k3)
+        e_t = oracle.fro2(A - oracle.tsvdq(A, Qk, min(k1, k2)).Ak)
+        assert e_t <= err2 * (1 + 1e-12)
+
+
 def test_check_q_closed_form():
     d = 0.25
     Q = np.array([[1.0, d], [0.0, 1.0], [0.0, 0.0]])
