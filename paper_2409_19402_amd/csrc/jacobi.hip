@@ -302,6 +302,9 @@ constexpr int kGMat = kG2 * kGld;
 // two copies of G (each round reads one and writes the other), V (updated in
 // place: every entry is read and written by one thread only), a flag word
 constexpr size_t kGramHead = sizeof(double) * 3 * kGMat + 16;
+// the partial Gram tiles of the four waves (float64: 4 x 3 x 4 x 64 values)
+// are staged in the G and V area before G is formed
+static_assert(sizeof(double) * 4 * 3 * 4 * 64 <= sizeof(double) * 3 * kGMat, "partial tiles exceed the G/V area");
 
 __device__ __forceinline__ JFace face_of(const JFace* tab, int f, int nv, int L) {
   if (tab) return tab[f];
@@ -495,45 +498,70 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
       if (c < Lp) X[u * ldx + c] = T(0);
     }
   }
-  for (int e = tid; e < kG2 * kG2; e += 256) V[(e >> 5) * kGld + (e & 31)] = ((e >> 5) == (e & 31)) ? 1.0 : 0.0;
-  if (tid == 0) *any_rot = 0;
   __syncthreads();
 
-  // G = X^T X: wave 0 tile (0,0), wave 1 tile (0,1) (and its mirror), wave 3
-  // tile (1,1).  MFMA t of a 16-element chunk takes element 4 kq + t of the
-  // chunk from the lanes of k-group kq: the chunk's 16 elements in some order,
-  // the same for both operands.
-  if (wave != 2) {
-    const int ti = wave >> 1, tj = wave & 1;
-    const T* xa = X + (16 * ti + r16) * ldx + 4 * kq;
-    const T* xb = X + (16 * tj + r16) * ldx + 4 * kq;
-    // four independent accumulation chains (one per MFMA of a chunk), summed
-    // at the end, so consecutive MFMAs do not wait on each other
-    typename M::acc_t acc4[4];
+  // G = X^T X.  Wave w takes the 16-element chunks w, w + 4, ... of the
+  // vectors and forms the three distinct 16 x 16 tiles (0,0), (0,1), (1,1)
+  // of its chunks' contribution: per chunk, 8 operand reads feed 12 MFMAs,
+  // and each tile has four independent accumulation chains.  MFMA t of a
+  // chunk takes element 4 kq + t of the chunk from the lanes of k-group kq:
+  // the chunk's 16 elements in some order, the same for both operands.  The
+  // four waves' partial tiles meet in LDS (the G and V area, free until
+  // here) and are summed in a fixed order.
+  {
+    typedef typename M::acc_t acc_t;
+    acc_t acc[3][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc4[t] = typename M::acc_t{0, 0, 0, 0};
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[q][t] = acc_t{0, 0, 0, 0};
+    const T* x0 = X + r16 * ldx + 4 * kq;
+    const T* x1 = X + (16 + r16) * ldx + 4 * kq;
 #pragma unroll 2
-    for (int s0 = 0; s0 < Lp; s0 += 16) {
-      T a[4], b[4];
+    for (int s0 = 16 * wave; s0 < Lp; s0 += 64) {
+      T a0[4], a1[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        a[t] = xa[s0 + t];
-        b[t] = xb[s0 + t];
+        a0[t] = x0[s0 + t];
+        a1[t] = x1[s0 + t];
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc4[t] = M::mma(a[t], b[t], acc4[t]);
+      for (int t = 0; t < 4; ++t) {
+        acc[0][t] = M::mma(a0[t], a0[t], acc[0][t]);
+        acc[1][t] = M::mma(a0[t], a1[t], acc[1][t]);
+        acc[2][t] = M::mma(a1[t], a1[t], acc[2][t]);
+      }
     }
-    const typename M::acc_t acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
-    // lane holds G[16 ti + row(kq, j)][16 tj + r16]
+    T* part = reinterpret_cast<T*>(smem_raw);  // [wave][tile][j][lane]
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = 16 * ti + M::row(kq, j), col = 16 * tj + r16;
+    for (int q = 0; q < 3; ++q) {
+      const acc_t s = (acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) part[((wave * 3 + q) * 4 + jj) * 64 + lane] = s[jj];
+    }
+    __syncthreads();
+    // thread tid sums entry (j = tid / 64, lane = tid % 64) of each tile
+    const int jj = tid >> 6;
+    R g[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const T v = ((part[((0 * 3 + q) * 4 + jj) * 64 + lane] + part[((1 * 3 + q) * 4 + jj) * 64 + lane]) +
+                   (part[((2 * 3 + q) * 4 + jj) * 64 + lane] + part[((3 * 3 + q) * 4 + jj) * 64 + lane]));
+      g[q] = (R)v;
+    }
+    __syncthreads();
+    // lane holds G[16 ti + row(kq, jj)][16 tj + r16] of tile (ti, tj)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int ti = q == 2 ? 1 : 0, tj = q == 0 ? 0 : 1;
+      const int row = 16 * ti + M::row(kq, jj), col = 16 * tj + r16;
       if (ti != tj || row <= col) {
-        const R v = (R)acc[j];
-        Gb[row * kGld + col] = v;
-        Gb[col * kGld + row] = v;
+        Gb[row * kGld + col] = g[q];
+        Gb[col * kGld + row] = g[q];
       }
     }
+    for (int e = tid; e < kG2 * kG2; e += 256) V[(e >> 5) * kGld + (e & 31)] = ((e >> 5) == (e & 31)) ? 1.0 : 0.0;
+    if (tid == 0) *any_rot = 0;
   }
   __syncthreads();
 
