@@ -39,7 +39,7 @@ BF16_MFMA_PEAK = 2500.0        # TFLOP/s dense
 # (workload, precision mode, kernel).  Absent means not measured for the
 # kernel as it is now.
 TRAFFIC_BYTES = {
-    ("video", "default", "jacobi_gram_f32"): 5576319,     # 2 x 1573.5 + 2298.7 KiB
+    ("video", "default", "jacobi_gram_f32"): 9267507,     # 2 x 2620.3 + 3809.7 KiB
     ("hat-video", "bf16x3", "hat"): 67830000,              # 2 x 30120 + 6000 KiB
     ("hat-hyper", "bf16x3", "hat"): 151400000,             # 2 x 57560 + 32768 KiB
     ("hat-video", "default", "hat"): 67827698,             # 2 x 30119 + 6000 KiB
@@ -68,7 +68,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="video",
                     choices=["video", "hyper", "diff", "tiny", "copy", "hat-video", "hat-hyper",
-                             "proj-video", "qprod", "batched", "svdii-video", "u3-video"])
+                             "proj-video", "qprod", "batched", "svdii-video", "u3-video",
+                             "tsvdq-backward-video"])
     ap.add_argument("--count", type=int, default=64, help="instances of the batched workload")
     ap.add_argument("--prec", default="default")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -102,6 +103,11 @@ def jacobi_models(svd_flops):
         n = sum(kernels.get(nm, {}).get("launches", 0) for nm in JACOBI_KERNELS)
         return svd_flops * steps / n if n else None
     return {nm: ("alu", share) for nm in JACOBI_KERNELS}
+
+
+def host_of(X):
+    """face-major device tensor -> numpy face-major storage (n3, n2, n1)"""
+    return X.permute(2, 1, 0).contiguous().cpu().numpy()
 
 
 def oracle_mod():
@@ -227,6 +233,33 @@ def main():
         Al, Qn = synth.logical(c["A"]), c["Q"]
         cpu_case = (lambda: (oracle_mod().check_q(Qn), oracle_mod().tsvdq_ii(Al, Qn, gamma)),
                     "check_q + tsvdq_ii with A_k")
+    elif args.workload == "tsvdq-backward-video":
+        c = synth.video_case()
+        A, Q = up(c["A"]), torch.from_numpy(c["Q"]).to(dev)
+        n1, n2, n3 = A.shape
+        p, k = Q.shape[1], c["k"]
+        N, L, S = n1 * n2, max(n1, n2), min(n1, n2)
+        rng = np.random.default_rng(6)
+        Gbar = up(rng.standard_normal((n3, n2, n1), dtype=np.float32))
+        sbar = torch.from_numpy(rng.standard_normal((k, p)).astype(np.float32)).to(dev)
+
+        def step():
+            return pq.tsvdq_backward(A, Q, k, Gbar=Gbar, sbar=sbar)
+        flops = (2.0 * N * n3 * p * 2                   # transforms of A and Gbar
+                 + svd_nominal_flops(n1, n2, p)         # the recomputed facewise SVD
+                 + 2.0 * L * S * S * p                  # M_t^T U
+                 + 2.0 * p * (4 * L * S * k + 2 * S * S * k)  # the k-column products
+                 + 2.0 * N * 2 * k * p                  # the face gradient
+                 + 2.0 * N * k * p                      # transform-domain A_k
+                 + 2.0 * N * n3 * p                     # dA back to the spatial domain
+                 + 2.0 * 2 * N * n3 * p)                # the two dQ products
+        models = {"hat": ("hbm", None), "unhat": ("hbm", None)}
+        models.update(jacobi_models(svd_nominal_flops(n1, n2, p)))
+        info = {"workload": "tSVDQ adjoint (dA, dQ of <Gbar, A_k> + <sbar, s>), video-shaped "
+                            "240x320x200 fp32, p=20, k=10", "n1": n1, "n2": n2, "n3": n3, "p": p, "k": k}
+        dtype = "f32"
+        Al, Qn, Gl, sb = synth.logical(c["A"]), c["Q"], synth.logical(host_of(Gbar)), sbar.cpu().numpy()
+        cpu_case = (lambda: oracle_mod().tsvdq_backward(Al, Qn, k, Gl, sb), "tsvdq_backward (float64 SVD perturbation)")
     elif args.workload == "u3-video":
         c = synth.video_case()
         A = up(c["A"])
