@@ -119,3 +119,43 @@ def test_batched_rejects_long_faces(pq):
     Q = devq(synth.random_orthonormal(rng, 8, 2).astype(np.float32))
     with pytest.raises(ProjProdError):
         pq.batched([dict(A=A, Q=Q, k=2)])
+
+
+def test_batched_full_config_sampled(pq):
+    """The full batched workload (64 uneven instances, n1, n2, n4 up to 512,
+    n3 up to 256, p up to 32, in one plan and its graph): every instance's
+    outputs are finite and sweeps converge; four sampled instances (the two
+    smallest and two others) match the float64 oracle."""
+    import torch
+    shapes = synth.batched_shapes(count=64)
+    sizes = [s["n1"] * s["n2"] * s["n3"] for s in shapes]
+    order = np.argsort(sizes)
+    sample = sorted({int(order[0]), int(order[1]), 17, 42})
+    insts, keep = [], {}
+    for i, sh in enumerate(shapes):
+        c = synth.batched_instance(4, i, sh)
+        insts.append(dict(A=dev(c["A"]), B=dev(c["B"]), Q=devq(c["Q"]), k=c["k"]))
+        if i in sample:
+            keep[i] = c
+    say(f"batched full config: 64 instances, sampled {sample}")
+    batch = pq.batched(insts)
+    batch.run()
+    torch.cuda.synchronize()
+    info = batch.info.cpu().tolist()
+    say(f"  info {info}")
+    assert info[1] == 0
+    for out in batch.outputs:
+        for t in out.values():
+            assert bool(torch.isfinite(t).all())
+    for i in sample:
+        c, out = keep[i], batch.outputs[i]
+        Al, Bl = synth.logical(c["A"]), synth.logical(c["B"])
+        e_c = rel(host(out["C"]), oracle.qprod(Al, Bl, c["Q"]))
+        ref = oracle.tsvdq(Al, c["Q"], c["k"])
+        U, s, V = host(out["Uhat"]), host(out["s"]), host(out["Vhat"])
+        e_s = rel(s, ref.s)
+        approx = np.einsum("ijl,jl,mjl->iml", U, s, V)
+        e_a = rel(approx, np.einsum("ijl,jl,mjl->iml", ref.Uhat, ref.s, ref.Vhat))
+        say(f"  instance {i} {shapes[i]}: C rel {e_c:.2e}, s rel {e_s:.2e}, approx rel {e_a:.2e}")
+        assert e_c <= TOL32 and e_s <= TOL32 and e_a <= TOL32
+    batch.close()

@@ -177,3 +177,21 @@ def test_svdii_rejects_bad_gamma(pq):
     for g in (0.0, -0.5, 1.5, float("nan")):
         with pytest.raises(ProjProdError):
             pq.svdii(dev(A), devq(Q.astype(np.float32)), g)
+
+
+def test_svdii_video_full_size(pq):
+    """The video workload at full size (240 x 320 x 200, p = 20, Q = U3),
+    gamma halfway between the cumulative energies around the rank-10 tSVDQ's
+    implicit rank."""
+    c = synth.video_case()
+    Al = synth.logical(c["A"])
+    ref = oracle.tsvdq(Al, c["Q"], 1)
+    K = 10 * c["Q"].shape[1]
+    gamma = _gamma_between(ref.s_all, K)
+    rho_ref, Ak_ref = oracle.tsvdq_ii(Al, c["Q"], gamma)
+    out = pq.svdii(dev(c["A"]), devq(c["Q"]), gamma, kmax=60, approx=True)
+    rho = out.rho.cpu().numpy()
+    say(f"svdii video full size: K={K}, rho {rho.tolist()}")
+    np.testing.assert_array_equal(rho, rho_ref)
+    assert rho_ref.max() <= 60
+    assert rel(host(out.Ak), Ak_ref) <= TOL32

@@ -149,3 +149,22 @@ def test_tsvdq_backward_rejects(pq):
         pq.tsvdq_backward(dev(A), devq(Q.astype(np.float32)), 2)  # no incoming gradient
     with pytest.raises(ProjProdError):
         pq.tsvdq_backward(dev(A), devq(Q.astype(np.float32)), 7, Gbar=dev(G))  # k > min(n1, n2)
+
+
+def test_tsvdq_backward_video_full_size(pq):
+    """The adjoint at the video workload's size (240 x 320 x 200, p = 20,
+    k = 10, Q = U3) against the float64 oracle."""
+    import torch
+    c = synth.video_case()
+    rng = np.random.default_rng(61)
+    G = synth.gaussian(rng, 240, 320, 200)
+    sbar = rng.standard_normal((10, 20)).astype(np.float32)
+    gap = _min_rel_gap(c["A"], c["Q"], 10)
+    dA, dQ, info = pq.tsvdq_backward(dev(c["A"]), devq(c["Q"]), 10, Gbar=dev(G),
+                                     sbar=torch.from_numpy(sbar).cuda())
+    inf = info.cpu().tolist()
+    assert inf[1] == 0 and inf[3] == 0, inf
+    rA, rQ = oracle.tsvdq_backward(synth.logical(c["A"]), c["Q"], 10, synth.logical(G), sbar)
+    eA, eQ = rel(host(dA), rA), rel(host(dQ), rQ)
+    say(f"tsvdq backward video full size: min rel gap {gap:.3e}, dA rel {eA:.2e}, dQ rel {eQ:.2e}")
+    assert eA <= TOL32 and eQ <= TOL32
