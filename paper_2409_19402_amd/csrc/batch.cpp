@@ -219,7 +219,6 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
   if (tol <= 0.0) tol = kDefaultTol;
   const Layout lo = layout(inst, count);
   if (ws_bytes < lo.total) return PQ_ERR_WORKSPACE;
-  if (lo.nfaces > 0 && lo.L_max > pq::jacobi_gram_max_len(true)) return PQ_ERR_UNSUPPORTED;
   char* w = static_cast<char*>(ws);
   // the face table: every face of every tSVDQ instance, in order
   std::vector<pq::JFace> tab;

@@ -115,19 +115,18 @@ hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, dou
 // Grouped Jacobi over faces of different sizes (the batched form): faces[f]
 // (device) gives face f's element offset in W, its vector count and length.
 // nb_max is the largest block count (ceil(nv / 16), rounded up to even) over
-// the faces and L_max the largest length; L_max must not exceed
-// jacobi_gram_max_len.
+// the faces and L_max the largest length (any length: vectors too long to
+// stage in LDS are read from the L2).
 struct JFace {
   int64_t off;
   int nv, L;
 };
-int jacobi_gram_max_len(bool f64);
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, int* used, int* flags, hipStream_t s);
 hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, int* used, int* flags, hipStream_t s);
 // float64 sweeps in the Gram-matrix form (the polishing sweeps of float32
-// data; falls back to the vector form when the staged vectors do not fit)
+// data)
 hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                                   int* flags, hipStream_t s);
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol,

@@ -299,12 +299,24 @@ constexpr int kG2 = 2 * kGB;   // vectors per block pair = Gram order
 constexpr int kGld = kG2 + 1;  // row stride of G and V in LDS (doubles): no bank conflicts on columns
 static_assert(kGld == 33, "the round loop forms row offsets as (x << 5) + x");
 constexpr int kGMat = kG2 * kGld;
-// two copies of G (each round reads one and writes the other), V (updated in
-// place: every entry is read and written by one thread only), a flag word
-constexpr size_t kGramHead = sizeof(double) * 3 * kGMat + 16;
-// the partial Gram tiles of the four waves (float64: 4 x 3 x 4 x 64 values)
-// are staged in the G and V area before G is formed
-static_assert(sizeof(double) * 4 * 3 * 4 * 64 <= sizeof(double) * 3 * kGMat, "partial tiles exceed the G/V area");
+// LDS head of a visit: NB copies of G in the angle type (float32 for float32
+// data; with two copies each round reads one and writes the other, with one
+// a round reads, synchronises and writes), V in float64 (updated in place:
+// every entry is read and written by one thread only) and a flag word.  The
+// four waves' partial Gram tiles (4 x 3 x 4 x 64 values of T) are staged in
+// the G and V area before G is formed.
+template <typename T, int NB>
+__host__ __device__ constexpr size_t gram_g_bytes() {
+  return ((size_t)NB * kGMat * sizeof(T) + 15) & ~(size_t)15;
+}
+template <typename T, int NB>
+__host__ __device__ constexpr size_t gram_head() {
+  return gram_g_bytes<T, NB>() + sizeof(double) * kGMat + 16;
+}
+template <typename T, int NB>
+__host__ __device__ constexpr bool gram_partials_fit() {
+  return sizeof(T) * 4 * 3 * 4 * 64 <= gram_head<T, NB>() - 16;
+}
 
 __device__ __forceinline__ JFace face_of(const JFace* tab, int f, int nv, int L) {
   if (tab) return tab[f];
@@ -318,9 +330,9 @@ __host__ __device__ __forceinline__ int gram_ldx(int L) {
   return ((L + 15) & ~15) + (sizeof(T) == 4 ? 4 : 2);
 }
 
-template <typename T>
+template <typename T, int NB, bool ST>
 __host__ __device__ __forceinline__ size_t gram_lds_bytes(int L) {
-  return kGramHead + sizeof(T) * (size_t)kG2 * gram_ldx<T>(L);
+  return gram_head<T, NB>() + (ST ? sizeof(T) * (size_t)kG2 * gram_ldx<T>(L) : 0);
 }
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -413,7 +425,7 @@ __host__ __device__ __forceinline__ int gram_grid(int nfaces, int npair) {
   return kXcds * ((nfaces + kXcds - 1) / kXcds) * npair;
 }
 
-template <typename T>
+template <typename T, int NB, bool ST>
 __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, const JFace* __restrict__ faces,
                                                           int nfaces, int npair, int nv_u, int L_u, int round,
                                                           int sweep, int max_sweeps, double tol,
@@ -425,11 +437,16 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   // G and the angle arithmetic: float32 in the coarse sweeps of float32 data,
   // float64 in the polishing sweeps; V is float64 in both
   typedef typename std::conditional<F32, float, double>::type R;
+  static_assert(NB == 1 || NB == 2, "one or two copies of G");
+  static_assert(gram_partials_fit<T, NB>(), "partial tiles exceed the G/V area");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* Gb = reinterpret_cast<R*>(smem_raw);  // G copies at Gb, Gb + kGMat
-  double* V = reinterpret_cast<double*>(smem_raw) + 2 * kGMat;
+  R* Gb = reinterpret_cast<R*>(smem_raw);  // G copies at Gb (and Gb + kGMat)
+  double* V = reinterpret_cast<double*>(smem_raw + gram_g_bytes<R, NB>());
   int* any_rot = reinterpret_cast<int*>(V + kGMat);
-  T* X = reinterpret_cast<T*>(smem_raw + kGramHead);
+  // ST: the 32 vectors are staged in LDS; otherwise the Gram step and X V
+  // read them from global memory (the L2) and the visit needs only the head,
+  // so that several visits share a CU
+  T* X = reinterpret_cast<T*>(smem_raw + gram_head<R, NB>());
 
   const int xcd = blockIdx.x % kXcds, m = blockIdx.x / kXcds;
   const int f = xcd + kXcds * (m / npair), pair = m % npair;
@@ -449,53 +466,55 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   T* Wf = W + fd.off;
   auto gvec = [&](int u) { return u < kGB ? I * kGB + u : J * kGB + (u - kGB); };
 
-  // stage the 32 vectors (wave w takes vectors w, w + 4, ...), zero past nv;
-  // each lane issues the loads of its 8 vectors before their LDS stores, with
-  // clamped addresses and out-of-range values masked
-  if (L % VEC == 0 && fd.off % VEC == 0) {
-    const int nq = L / VEC;
-    // two 64-chunk columns per pass: 16 loads of each lane in flight at once
-    for (int q0 = 0; q0 < nq; q0 += 128) {
-      vec_t buf[2][8];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int qc = min(q0 + 64 * h + lane, nq - 1);
-#pragma unroll
+  if constexpr (ST) {
+    // stage the 32 vectors (wave w takes vectors w, w + 4, ...), zero past nv;
+    // each lane issues the loads of its 8 vectors before their LDS stores, with
+    // clamped addresses and out-of-range values masked
+    if (L % VEC == 0 && fd.off % VEC == 0) {
+      const int nq = L / VEC;
+      // two 64-chunk columns per pass: 16 loads of each lane in flight at once
+      for (int q0 = 0; q0 < nq; q0 += 128) {
+        vec_t buf[2][8];
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int qc = min(q0 + 64 * h + lane, nq - 1);
+  #pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int g = gvec(wave + 4 * i);
+            const vec_t v = *reinterpret_cast<const vec_t*>(Wf + (int64_t)min(g, nv - 1) * L + VEC * qc);
+            buf[h][i] = g < nv ? v : M::zero();
+          }
+        }
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int q = q0 + 64 * h + lane;
+          if (q < nq) {
+  #pragma unroll
+            for (int i = 0; i < 8; ++i) *reinterpret_cast<vec_t*>(X + (wave + 4 * i) * ldx + VEC * q) = buf[h][i];
+          }
+        }
+      }
+    } else {
+      for (int e0 = 0; e0 < L; e0 += 64) {
+        const int e = e0 + lane, ec = min(e, L - 1);
+        T buf[8];
+  #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const int g = gvec(wave + 4 * i);
-          const vec_t v = *reinterpret_cast<const vec_t*>(Wf + (int64_t)min(g, nv - 1) * L + VEC * qc);
-          buf[h][i] = g < nv ? v : M::zero();
+          const T v = Wf[(int64_t)min(g, nv - 1) * L + ec];
+          buf[i] = g < nv ? v : T(0);
         }
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int q = q0 + 64 * h + lane;
-        if (q < nq) {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) *reinterpret_cast<vec_t*>(X + (wave + 4 * i) * ldx + VEC * q) = buf[h][i];
+        if (e < L) {
+  #pragma unroll
+          for (int i = 0; i < 8; ++i) X[(wave + 4 * i) * ldx + e] = buf[i];
         }
       }
     }
-  } else {
-    for (int e0 = 0; e0 < L; e0 += 64) {
-      const int e = e0 + lane, ec = min(e, L - 1);
-      T buf[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int g = gvec(wave + 4 * i);
-        const T v = Wf[(int64_t)min(g, nv - 1) * L + ec];
-        buf[i] = g < nv ? v : T(0);
+    if (Lp > L) {
+      for (int e = tid; e < kG2 * 16; e += 256) {
+        const int u = e >> 4, c = L + (e & 15);
+        if (c < Lp) X[u * ldx + c] = T(0);
       }
-      if (e < L) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) X[(wave + 4 * i) * ldx + e] = buf[i];
-      }
-    }
-  }
-  if (Lp > L) {
-    for (int e = tid; e < kG2 * 16; e += 256) {
-      const int u = e >> 4, c = L + (e & 15);
-      if (c < Lp) X[u * ldx + c] = T(0);
     }
   }
   __syncthreads();
@@ -515,21 +534,54 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
     for (int q = 0; q < 3; ++q)
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[q][t] = acc_t{0, 0, 0, 0};
-    const T* x0 = X + r16 * ldx + 4 * kq;
-    const T* x1 = X + (16 + r16) * ldx + 4 * kq;
-#pragma unroll 2
-    for (int s0 = 16 * wave; s0 < Lp; s0 += 64) {
-      T a0[4], a1[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        a0[t] = x0[s0 + t];
-        a1[t] = x1[s0 + t];
-      }
+    auto mma3 = [&](const T (&a0)[4], const T (&a1)[4]) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         acc[0][t] = M::mma(a0[t], a0[t], acc[0][t]);
         acc[1][t] = M::mma(a0[t], a1[t], acc[1][t]);
         acc[2][t] = M::mma(a1[t], a1[t], acc[2][t]);
+      }
+    };
+    if constexpr (ST) {
+      const T* x0 = X + r16 * ldx + 4 * kq;
+      const T* x1 = X + (16 + r16) * ldx + 4 * kq;
+#pragma unroll 2
+      for (int s0 = 16 * wave; s0 < Lp; s0 += 64) {
+        T a0[4], a1[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a0[t] = x0[s0 + t];
+          a1[t] = x1[s0 + t];
+        }
+        mma3(a0, a1);
+      }
+    } else {
+      // rows r16 of both blocks, elements 4 kq + t of each chunk, from the
+      // L2; the next chunk's loads are issued before this chunk's MFMAs
+      const int g0 = gvec(r16), g1 = gvec(16 + r16);
+      const T* w0 = Wf + (int64_t)min(g0, nv - 1) * L;
+      const T* w1 = Wf + (int64_t)min(g1, nv - 1) * L;
+      auto fetch = [&](int s0, T (&a0)[4], T (&a1)[4]) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int e = s0 + 4 * kq + t, ec = min(e, L - 1);
+          const T v0 = w0[ec], v1 = w1[ec];
+          a0[t] = (g0 < nv && e < L) ? v0 : T(0);
+          a1[t] = (g1 < nv && e < L) ? v1 : T(0);
+        }
+      };
+      T n0[4], n1[4];
+      int s0 = 16 * wave;
+      if (s0 < Lp) fetch(s0, n0, n1);
+      for (; s0 < Lp; s0 += 64) {
+        T a0[4], a1[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a0[t] = n0[t];
+          a1[t] = n1[t];
+        }
+        if (s0 + 64 < Lp) fetch(s0 + 64, n0, n1);
+        mma3(a0, a1);
       }
     }
     T* part = reinterpret_cast<T*>(smem_raw);  // [wave][tile][j][lane]
@@ -622,8 +674,8 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   };
   int cur = 0;
   for (int r = 0; r < nrounds; ++r) {
-    const R* G = Gb + cur * kGMat;
-    R* Gn = Gb + (cur ^ 1) * kGMat;
+    const R* G = Gb + (NB == 2 ? cur : 0) * kGMat;
+    R* Gn = Gb + (NB == 2 ? cur ^ 1 : 0) * kGMat;
     int a1, c1, a2, c2;
     gram_pair(full, r, P, a1, c1);
     gram_pair(full, r, P2, a2, c2);
@@ -647,10 +699,15 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
     const R t00 = c2r * m00 - s2r * m01, t01 = s2r * m00 + c2r * m01;
     const R t10 = c2r * m10 - s2r * m11, t11 = s2r * m10 + c2r * m11;
     const bool own = P == P2 && s1r != R(0);  // the rotation annihilates its own off-diagonal entry
-    Gn[ra1 + a2] = c1r * t00 - s1r * t10;
-    Gn[ra1 + c2] = own ? R(0) : c1r * t01 - s1r * t11;
-    Gn[rc1 + a2] = own ? R(0) : s1r * t00 + c1r * t10;
-    Gn[rc1 + c2] = s1r * t01 + c1r * t11;
+    const R g00 = c1r * t00 - s1r * t10;
+    const R g01 = own ? R(0) : c1r * t01 - s1r * t11;
+    const R g10 = own ? R(0) : s1r * t00 + c1r * t10;
+    const R g11 = s1r * t01 + c1r * t11;
+    if constexpr (NB == 1) __syncthreads();  // every read of the round before any write
+    Gn[ra1 + a2] = g00;
+    Gn[ra1 + c2] = g01;
+    Gn[rc1 + a2] = g10;
+    Gn[rc1 + c2] = g11;
     pa = a1;
     pc = c1;
     pvc = c1r;
@@ -673,10 +730,32 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   for (int tc = 0; tc < 2; ++tc)
 #pragma unroll
     for (int s = 0; s < 8; ++s) va[tc][s] = (T)V[(4 * s + kq) * kGld + 16 * tc + r16];
+  // (without staging: tile te's 8 rows per lane come from the L2, the next
+  // tile's issued before this tile's MFMAs; the tiles of one launch are
+  // disjoint column ranges, read before they are written)
+  T nb8[8];
+  auto fetch_tile = [&](int te, T (&xb)[8]) {
+    const int e = 16 * te + r16, ec = min(e, L - 1);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int g = gvec(4 * s + kq);
+      const T v = Wf[(int64_t)min(g, nv - 1) * L + ec];
+      xb[s] = (g < nv && e < L) ? v : T(0);
+    }
+  };
+  if constexpr (!ST) {
+    if (wave < (Lp >> 4)) fetch_tile(wave, nb8);
+  }
   for (int te = wave; te < (Lp >> 4); te += 4) {
     T xb[8];
+    if constexpr (ST) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) xb[s] = X[(4 * s + kq) * ldx + 16 * te + r16];
+      for (int s = 0; s < 8; ++s) xb[s] = X[(4 * s + kq) * ldx + 16 * te + r16];
+    } else {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) xb[s] = nb8[s];
+      if (te + 4 < (Lp >> 4)) fetch_tile(te + 4, nb8);
+    }
     const int e = 16 * te + r16;
     // the two row tiles as interleaved, independent MFMA chains
     typename M::acc_t acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
@@ -1241,13 +1320,13 @@ hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, doub
 // Sweeps in the Gram form: max_sweeps x (nb - 1) launches; a face whose
 // sweep rotated nothing is skipped by the later launches.
 // The dynamic LDS the kernel may use: the largest of 160, 128 and 64 KiB
-// that the device accepts (set once per process).
-template <typename T>
+// that the device accepts (set once per process and instantiation).
+template <typename T, int NB, bool ST>
 size_t gram_lds_cap() {
   static size_t cap = 0;
   if (cap == 0) {
     for (size_t c : {(size_t)160 * 1024, (size_t)128 * 1024, (size_t)64 * 1024}) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_gram_kernel<T>),
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_gram_kernel<T, NB, ST>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)c) == hipSuccess) {
         cap = c;
         break;
@@ -1258,26 +1337,71 @@ size_t gram_lds_cap() {
   return cap;
 }
 
+// Visit forms: the 32 vectors staged in LDS with two copies of G, staged
+// with one copy of G (float32 only: one more barrier per round, half the
+// head), or not staged (the Gram step and X V read the L2; only the head in
+// LDS).  A launch with at most one visit per CU stages its vectors; with more
+// visits than CUs, float32 takes the form that lets two visits share a CU
+// (staged, with one copy of G where two do not fit in half a CU's LDS).
+// float64 vectors of 512 elements fill a CU's LDS when staged; unstaged they
+// let two visits share a CU but wait on the L2, which measured 8% slower at
+// two visits per CU (512-vector faces, 512 visits per launch) and 10% faster
+// with more than four per CU (the batched form): float64 stays staged unless
+// a launch has more than four visits per CU.  Vectors too long to stage at
+// all are never staged.
+enum class GramForm { Staged2, Staged1, Stream };
+constexpr size_t kHalfCuLds = 80 * 1024;
+
 template <typename T>
-bool gram_fits(int L) {
-  return gram_lds_bytes<T>(L) <= gram_lds_cap<T>();
+GramForm gram_form(int L, int grid) {
+  const size_t two = gram_lds_bytes<T, 2, true>(L);
+  const bool many = grid > 256;
+  const bool fits2 = two <= gram_lds_cap<T, 2, true>();
+  if constexpr (sizeof(T) == 4) {
+    const size_t one = gram_lds_bytes<T, 1, true>(L);
+    const bool fits1 = one <= gram_lds_cap<T, 1, true>();
+    if (fits2 && (!many || two <= kHalfCuLds)) return GramForm::Staged2;
+    if (fits1 && (one <= kHalfCuLds || !fits2)) return GramForm::Staged1;
+    if (fits2 && !many) return GramForm::Staged2;
+    return GramForm::Stream;
+  } else {
+    if (fits2 && (grid <= 4 * 256 || two <= kHalfCuLds)) return GramForm::Staged2;
+    return GramForm::Stream;
+  }
+}
+
+template <typename T, int NB, bool ST>
+void gram_launch_all(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max, int max_sweeps,
+                     double tol, int* flags, hipStream_t s) {
+  const size_t lds = gram_lds_bytes<T, NB, ST>(L_max);
+  (void)gram_lds_cap<T, NB, ST>();  // sets the kernel's LDS limit once
+  for (int sw = 0; sw < max_sweeps; ++sw)
+    for (int round = 0; round < nb_max - 1; ++round)
+      jacobi_gram_kernel<T, NB, ST><<<(unsigned)gram_grid(nfaces, nb_max / 2), 256, lds, s>>>(
+          W, faces, nfaces, nb_max / 2, nv_u, L_u, round, sw, max_sweeps, tol, flags);
 }
 
 template <typename T>
 hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max,
                        int max_sweeps, double tol, int* used, int* flags, hipStream_t s) {
-  const size_t lds = gram_lds_bytes<T>(L_max);
   const int nflags = nfaces * max_sweeps;
   {
     ProfScope prof("jacobi_flags", s);
     zero_ints_kernel<<<(nflags + 255) / 256, 256, 0, s>>>(flags, nflags);
   }
+  const GramForm form = gram_form<T>(L_max, gram_grid(nfaces, nb_max / 2));
   {
     ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s, max_sweeps * (nb_max - 1));
-    for (int sw = 0; sw < max_sweeps; ++sw)
-      for (int round = 0; round < nb_max - 1; ++round)
-        jacobi_gram_kernel<T><<<(unsigned)gram_grid(nfaces, nb_max / 2), 256, lds, s>>>(
-            W, faces, nfaces, nb_max / 2, nv_u, L_u, round, sw, max_sweeps, tol, flags);
+    if (form == GramForm::Stream) {
+      gram_launch_all<T, 2, false>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+    } else if constexpr (sizeof(T) == 4) {
+      if (form == GramForm::Staged1)
+        gram_launch_all<T, 1, true>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+      else
+        gram_launch_all<T, 2, true>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+    } else {
+      gram_launch_all<T, 2, true>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+    }
   }
   {
     ProfScope prof("jacobi_flags", s);
@@ -1392,19 +1516,11 @@ hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, h
 }
 hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                              int* flags, hipStream_t s) {
-  if (gram_fits<float>(L)) return gram_sweeps_uniform<float>(W, p, nv, L, max_sweeps, tol, used, flags, s);
-  return sweeps<float>(W, p, nv, L, max_sweeps, tol, used, flags, s);
+  return gram_sweeps_uniform<float>(W, p, nv, L, max_sweeps, tol, used, flags, s);
 }
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                              int* flags, hipStream_t s) {
   return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
-}
-int jacobi_gram_max_len(bool f64) {
-  const size_t cap = f64 ? gram_lds_cap<double>() : gram_lds_cap<float>();
-  const size_t per = sizeof(float) * (f64 ? 2 : 1) * kG2;
-  if (cap <= kGramHead) return 0;
-  const int ldx = (int)((cap - kGramHead) / per);
-  return ((ldx - 4) & ~15);  // largest L whose padded rows fit
 }
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, int* used, int* flags, hipStream_t s) {
@@ -1416,8 +1532,7 @@ hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, in
 }
 hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                                   int* flags, hipStream_t s) {
-  if (gram_fits<double>(L)) return gram_sweeps_uniform<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
-  return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
+  return gram_sweeps_uniform<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
 }
 hipError_t jacobi_norms_f64(const double* W, int p, int nv, int L, double* sig, int* rank, hipStream_t s) {
   norms_kernel<double><<<dim3((unsigned)((nv + 3) / 4), (unsigned)p), 256, 0, s>>>(W, nv, L, sig, rank);
