@@ -269,9 +269,10 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
  * k per face, 1 <= k <= min(n1, n2).
  *   step 2: Ahat = A x_3 Q^T;
  *   step 3: every face Ahat_l ~ Uhat_l diag(s_l) Vhat_l^T, the exact rank-k
- *           truncation (one-sided Jacobi with float64 rotation angles: for
- *           float32 data, float32 sweeps to a coarse threshold and then
- *           float64 polishing sweeps);
+ *           truncation (one-sided Jacobi: for float32 data, float32 sweeps
+ *           to a coarse threshold and then float64 polishing sweeps on Gram
+ *           matrices; for float64 data, float64 sweeps on Gram matrices to
+ *           1e-10 and then float64 sweeps on the vectors themselves to tol);
  *   step 4 (optional outputs): Uk = Uhat x_3 Q, the diagonal tubes of
  *           S_k = Shat x_3 Q, Vk = Vhat x_3 Q, and the approximation
  *           A_k = (Uhat tri Shat tri Vhat^T) x_3 Q of Thm. 4.2.
@@ -287,7 +288,8 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
  * relative gap of their singular values); for F32 and BF16 data the final
  * sweeps work on Gram matrices of the vectors and use max(tol, 1e-10)),
  * max_sweeps caps the sweeps of each phase (<= 0: 12 for float32 data,
- * 30 for float64; at most 100).  info_dev (device int[3], may be NULL)
+ * 30 for float64, whose Gram phase takes at most 16 and whose vector phase
+ * at most 8; at most 100).  info_dev (device int[3], may be NULL)
  * receives [0] = the largest number of sweeps any face used (both phases),
  * [1] = the number of faces whose last phase hit max_sweeps before
  * converging (their outputs are still written) and [2] = the sweeps summed
@@ -347,9 +349,14 @@ int pq_svdii(const void* A, int a_dtype, const void* Q,
  * sigma_c^2 have their coupling dropped (gap_tol <= 0 selects 1e-8) and are
  * counted.  Losses of A_k and s are the ones whose gradient is well defined
  * (the factors themselves are fixed only up to signs and rotations).
- * The facewise SVD is recomputed (tol and max_sweeps as in pq_tsvdq) with
- * every singular vector of the shorter side kept.  a_dtype F32 or F64;
- * Gbar, sbar, dA and dQ have the output type of pq_tsvdq.  Gbar or sbar may
+ * The facewise SVD is recomputed with every singular vector of the shorter
+ * side kept.  The coefficients divide by the spectral gaps, so float32
+ * arithmetic anywhere on the path (the transforms included) would leave
+ * errors of about 1e-7 / (relative gap); float32 data are therefore widened
+ * and the whole computation runs in float64 (tol and max_sweeps as for
+ * float64 data in pq_tsvdq), the gradients rounded to float32 at the end.
+ * a_dtype F32 or F64; Gbar, sbar, dA and dQ have the output type of
+ * pq_tsvdq.  Gbar or sbar may
  * be NULL (not both), dA or dQ may be NULL (not both).  info_dev (device
  * int[4], may be NULL): [0..2] as in pq_tsvdq, [3] = the pairs whose
  * coupling was dropped.  Workspace: pq_tsvdq_backward_workspace bytes.

@@ -110,6 +110,8 @@ constexpr double kGramTolFloor = 1e-10;
 // sweep cap of the Gram-form eigen-iteration of U3 for float32 data: the
 // float64 sweeps from scratch converge in 6-10
 constexpr int kU3GramSweeps = 16;
+// sweep cap of the Gram-form phase of float64 data (from scratch: 6-12)
+constexpr int kGramSweeps64 = 16;
 constexpr int kMaxSweepsCap = 100;
 // relative gap |lambda_c - lambda_j| / lambda_c at or under which the adjoint
 // of the truncation drops the coupling of a kept and a discarded pair
@@ -646,14 +648,20 @@ int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
     PQ_TRY(pq::jacobi_widen(b.W32, b.W64, N * p, stream));
   }
   // float64 sweeps to tol (each launch profiled inside)
-  if (f64)
-    PQ_TRY(pq::jacobi_sweeps_f64(b.W64, ip, nv, L, max_sweeps, tol, b.used1, b.flags, stream));
-  else
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, std::min(max_sweeps, kPolishSweeps),
-                                      std::max(tol, kGramTolFloor), b.used2, b.flags, stream));
-  if (info_dev)
-    PQ_TRY(pq::jacobi_info(b.used1, f64 ? nullptr : b.used2, ip, max_sweeps,
-                           f64 ? max_sweeps : std::min(max_sweeps, kPolishSweeps), info_dev, stream));
+  // float64 data: Gram-form sweeps to max(tol, 1e-10), then vector-form
+  // sweeps (dot products from the vectors themselves) to tol; float32 data:
+  // Gram-form float64 sweeps to max(tol, 1e-10)
+  const int max1 = f64 ? std::min(max_sweeps, kGramSweeps64) : max_sweeps;
+  const int max2 = std::min(max_sweeps, kPolishSweeps);
+  if (f64) {
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max1, std::max(tol, kGramTolFloor), b.used1, b.flags,
+                                      stream));
+    PQ_TRY(pq::jacobi_sweeps_f64(b.W64, ip, nv, L, max2, tol, b.used2, b.flags, stream));
+  } else {
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max2, std::max(tol, kGramTolFloor), b.used2, b.flags,
+                                      stream));
+  }
+  if (info_dev) PQ_TRY(pq::jacobi_info(b.used1, b.used2, ip, max1, max2, info_dev, stream));
   return PQ_OK;
 }
 
@@ -792,17 +800,19 @@ size_t pq_tsvdq_backward_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p
   const size_t e = elem(f64 ? PQ_F64 : PQ_F32);
   const int64_t N = n1 * n2, L = std::max(n1, n2), S = std::min(n1, n2);
   const int ks = ksplit_for(N);
-  return sweep_bytes(f64, N, p)
+  return (f64 ? 0 : align_up(8 * N * n3) * 2 + align_up(8 * n3 * p) + align_up(8 * k * p))  // widened inputs
+         + sweep_bytes(true, N, p)                  // transform and Jacobi buffers (float64)
          + align_up(8 * S * p) * 2                  // norms, sorted singular values
-         + align_up(8 * L * S * p)                  // every normalised Jacobi vector (float64)
-         + (f64 ? 0 : align_up(4 * L * S * p))      // ... rounded to float32
+         + align_up(8 * L * S * p)                  // every normalised Jacobi vector
          + align_up(sizeof(int) * p)                // near-degenerate pairs per face
-         + align_up(e * N * p) * 3                  // Gh, the face gradient, transform-domain A_k
-         + align_up(e * S * S * p)                  // Yall
-         + align_up(e * S * k * p) * 6              // H, P1, Ba, Bb, E, Ep
-         + align_up(e * L * k * p) * 2              // Ra, UE
-         + align_up(e * L * 2 * k * p)              // [U_K X]
-         + align_up(e * S * 2 * k * p)              // [N Y]
+         + align_up(8 * N * p)                      // Gh
+         + align_up(8 * N * p) * 2                  // the face gradient and transform-domain A_k
+         + (f64 ? 0 : align_up(4 * N * p) * 2)      // ... rounded to float32
+         + align_up(8 * S * S * p)                  // Yall
+         + align_up(8 * S * k * p) * 6              // H, P1, Ba, Bb, E, Ep
+         + align_up(8 * L * k * p) * 2              // Ra, UE
+         + align_up(8 * L * 2 * k * p)              // [U_K X]
+         + align_up(8 * S * 2 * k * p)              // [N Y]
          + align_up(e * (size_t)ks * p * n3) * 2;   // split-K slices of the two dQ terms
 }
 
@@ -818,7 +828,7 @@ int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q, int64_t n1, int
     if (o && (o == Gbar || o == sbar)) return PQ_ERR_ALIAS;
   if (dA && dA == dQ) return PQ_ERR_ALIAS;
   if (!ws || ws_bytes < pq_tsvdq_backward_workspace(n1, n2, n3, p, k, a_dtype)) return PQ_ERR_WORKSPACE;
-  PQ_CHECK(sweep_defaults(a_dtype, tol, max_sweeps));
+  PQ_CHECK(sweep_defaults(PQ_F64, tol, max_sweeps));
   if (gap_tol <= 0.0) gap_tol = kDefaultGapTol;
   const bool f64 = a_dtype == PQ_F64;
   const int dt = f64 ? PQ_F64 : PQ_F32;
@@ -831,71 +841,96 @@ int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q, int64_t n1, int
   const bool has_g = Gbar != nullptr;
   const Prec pr = Prec::Default;
   Arena ar(ws, ws_bytes);
-  const SweepBufs b = take_sweep_bufs(ar, f64, N, p);
+  // The adjoint's coefficients divide by the gaps of the face spectra, so
+  // float32 arithmetic anywhere from the data to the face gradient (the
+  // transforms included) would leave errors of about 1e-7 / (relative gap).
+  // float32 data are exact in float64: they are widened, and everything up
+  // to the face gradient runs in float64; the two transforms back (dA, dQ),
+  // where no gap enters any more, run in the data's type.
+  const double* A64 = static_cast<const double*>(A);
+  const double* Q64 = static_cast<const double*>(Q);
+  const double* G64 = static_cast<const double*>(Gbar);
+  const double* s64 = static_cast<const double*>(sbar);
+  if (!f64) {
+    double* a64 = static_cast<double*>(ar.take(8 * N * n3));
+    double* g64 = static_cast<double*>(ar.take(8 * N * n3));
+    double* q64 = static_cast<double*>(ar.take(8 * n3 * p));
+    double* sb64 = static_cast<double*>(ar.take(8 * k * p));
+    PQ_PROF("grad_elementwise", stream);
+    PQ_TRY(pq::jacobi_widen(static_cast<const float*>(A), a64, N * n3, stream));
+    PQ_TRY(pq::jacobi_widen(static_cast<const float*>(Q), q64, n3 * p, stream));
+    if (has_g) PQ_TRY(pq::jacobi_widen(static_cast<const float*>(Gbar), g64, N * n3, stream));
+    if (sbar) PQ_TRY(pq::jacobi_widen(static_cast<const float*>(sbar), sb64, k * p, stream));
+    A64 = a64;
+    Q64 = q64;
+    G64 = has_g ? g64 : nullptr;
+    s64 = sbar ? sb64 : nullptr;
+  }
+  const SweepBufs b = take_sweep_bufs(ar, true, N, p);
   double* sig = static_cast<double*>(ar.take(8 * (size_t)S * p));
   double* sigs = static_cast<double*>(ar.take(8 * (size_t)S * p));
-  double* Fall = static_cast<double*>(ar.take(8 * (size_t)L * S * p));
-  float* U32 = f64 ? nullptr : static_cast<float*>(ar.take(4 * (size_t)L * S * p));
+  double* U = static_cast<double*>(ar.take(8 * (size_t)L * S * p));
   int* cnt = static_cast<int*>(ar.take(sizeof(int) * p));
-  void* Gh = ar.take(e * N * p);
-  void* Mbar = ar.take(e * N * p);
-  void* Akh = ar.take(e * N * p);
-  void* Yall = ar.take(e * S * S * p);
-  void* H = ar.take(e * S * k * p);
-  void* P1 = ar.take(e * S * k * p);
-  void* Ba = ar.take(e * S * k * p);
-  void* Bb = ar.take(e * S * k * p);
-  void* E = ar.take(e * S * k * p);
-  void* Ep = ar.take(e * S * k * p);
-  void* Ra = ar.take(e * L * k * p);
-  void* UE = ar.take(e * L * k * p);
-  char* LHS = static_cast<char*>(ar.take(e * L * 2 * k * p));
-  void* RHS = ar.take(e * S * 2 * k * p);
+  double* Gh = static_cast<double*>(ar.take(8 * N * p));
+  double* Mbar = static_cast<double*>(ar.take(8 * N * p));
+  double* Akh = static_cast<double*>(ar.take(8 * N * p));
+  float* Mbar32 = f64 ? nullptr : static_cast<float*>(ar.take(4 * N * p));
+  float* Akh32 = f64 ? nullptr : static_cast<float*>(ar.take(4 * N * p));
+  double* Yall = static_cast<double*>(ar.take(8 * (size_t)S * S * p));
+  double* H = static_cast<double*>(ar.take(8 * (size_t)S * k * p));
+  double* P1 = static_cast<double*>(ar.take(8 * (size_t)S * k * p));
+  double* Ba = static_cast<double*>(ar.take(8 * (size_t)S * k * p));
+  double* Bb = static_cast<double*>(ar.take(8 * (size_t)S * k * p));
+  double* E = static_cast<double*>(ar.take(8 * (size_t)S * k * p));
+  double* Ep = static_cast<double*>(ar.take(8 * (size_t)S * k * p));
+  double* Ra = static_cast<double*>(ar.take(8 * (size_t)L * k * p));
+  double* UE = static_cast<double*>(ar.take(8 * (size_t)L * k * p));
+  double* LHS = static_cast<double*>(ar.take(8 * (size_t)L * 2 * k * p));
+  double* RHS = static_cast<double*>(ar.take(8 * (size_t)S * 2 * k * p));
   char* parts = static_cast<char*>(ar.take(e * (size_t)ks * p * n3 * 2));
-  const void* U = f64 ? static_cast<const void*>(Fall) : static_cast<const void*>(U32);
   const int64_t sU = (int64_t)L * S, sY = (int64_t)S * S, sK = (int64_t)S * k, sR = (int64_t)L * k;
-  // the forward factorisation: every singular vector of the Jacobi side
-  PQ_CHECK(converge(A, a_dtype, Q, n1, n2, n3, p, pr, tol, max_sweeps, b, info_dev, stream));
+  // the forward factorisation in float64: every singular vector of the
+  // Jacobi side
+  PQ_CHECK(converge(A64, PQ_F64, Q64, n1, n2, n3, p, pr, tol, max_sweeps, b, info_dev, stream));
   {
     PQ_PROF("jacobi_finalize", stream);
     PQ_TRY(pq::jacobi_norms_f64(b.W64, ip, S, L, sig, nullptr, stream));
-    PQ_TRY(pq::jacobi_finalize_f64(b.W64, sig, ip, S, L, S, nullptr, Fall, sigs, stream));
-    if (!f64) PQ_TRY(pq::grad_narrow(Fall, U32, (int64_t)L * S * p, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(b.W64, sig, ip, S, L, S, nullptr, U, sigs, stream));
   }
+  const double* M = static_cast<const double*>(b.Ah);
   // M_t is the face (cols) or its transpose; op(M_t^T) is the face with
   // transpose flag `cols`, op(M_t) with `!cols`.  Yall = M_t^T U, Y = its
   // first k columns.
-  const void* M = b.Ah;
-  PQ_TRY(do_gemm("grad_gemm", face_gemm(cols, false, S, S, L, M, n1, N, U, L, sU, Yall, S, sY, ip), dt, pr,
+  PQ_TRY(do_gemm("grad_gemm", face_gemm(cols, false, S, S, L, M, n1, N, U, L, sU, Yall, S, sY, ip), PQ_F64, pr,
                  stream));
   if (has_g) {
-    PQ_TRY(do_hat(Gbar, dt, Q, Gh, N, in3, ip, pr, stream));
+    PQ_TRY(do_hat(G64, PQ_F64, Q64, Gh, N, in3, ip, pr, stream));
     // H = G_t^T U_K;  Ra = G_t Y;  Ba = U^T Ra;  Bb = Yall^T H
-    PQ_TRY(do_gemm("grad_gemm", face_gemm(cols, false, S, ik, L, Gh, n1, N, U, L, sU, H, S, sK, ip), dt, pr,
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(cols, false, S, ik, L, Gh, n1, N, U, L, sU, H, S, sK, ip), PQ_F64, pr,
                    stream));
-    PQ_TRY(do_gemm("grad_gemm", face_gemm(!cols, false, L, ik, S, Gh, n1, N, Yall, S, sY, Ra, L, sR, ip), dt, pr,
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(!cols, false, L, ik, S, Gh, n1, N, Yall, S, sY, Ra, L, sR, ip), PQ_F64,
+                   pr, stream));
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(true, false, S, ik, L, U, L, sU, Ra, L, sR, Ba, S, sK, ip), PQ_F64, pr,
                    stream));
-    PQ_TRY(do_gemm("grad_gemm", face_gemm(true, false, S, ik, L, U, L, sU, Ra, L, sR, Ba, S, sK, ip), dt, pr,
-                   stream));
-    PQ_TRY(do_gemm("grad_gemm", face_gemm(true, false, S, ik, S, Yall, S, sY, H, S, sK, Bb, S, sK, ip), dt, pr,
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(true, false, S, ik, S, Yall, S, sY, H, S, sK, Bb, S, sK, ip), PQ_F64, pr,
                    stream));
     {
       PQ_PROF("grad_elementwise", stream);
-      PQ_TRY(pq::grad_coef(Ba, Bb, sigs, ip, S, ik, gap_tol, E, Ep, cnt, f64, stream));
+      PQ_TRY(pq::grad_coef(Ba, Bb, sigs, ip, S, ik, gap_tol, E, Ep, cnt, true, stream));
     }
     // X = Ra diag(1/lambda) + U E into the second half of LHS;  P1 = Yall Ep
-    PQ_TRY(do_gemm("grad_gemm", face_gemm(false, false, L, ik, S, U, L, sU, E, S, sK, UE, L, sR, ip), dt, pr,
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(false, false, L, ik, S, U, L, sU, E, S, sK, UE, L, sR, ip), PQ_F64, pr,
                    stream));
-    PQ_TRY(do_gemm("grad_gemm", face_gemm(false, false, S, ik, S, Yall, S, sY, Ep, S, sK, P1, S, sK, ip), dt, pr,
-                   stream));
+    PQ_TRY(do_gemm("grad_gemm", face_gemm(false, false, S, ik, S, Yall, S, sY, Ep, S, sK, P1, S, sK, ip), PQ_F64,
+                   pr, stream));
     pq::ProfScope prof_elementwise("grad_elementwise", stream, 3);
-    PQ_TRY(pq::grad_xcombine(Ra, UE, U, sigs, ip, L, S, ik, LHS, f64, stream));
-    PQ_TRY(pq::grad_ncombine(H, P1, Yall, sbar, sigs, ip, S, S, ik, RHS, f64, stream));
+    PQ_TRY(pq::grad_xcombine(Ra, UE, U, sigs, ip, L, S, ik, LHS, true, stream));
+    PQ_TRY(pq::grad_ncombine(H, P1, Yall, s64, sigs, ip, S, S, ik, RHS, true, false, stream));
     if (info_dev) PQ_TRY(pq::grad_count(cnt, ip, info_dev + 3, stream));
   } else {
     pq::ProfScope prof_elementwise("grad_elementwise", stream, 3);
-    PQ_TRY(pq::grad_xcombine(nullptr, nullptr, U, sigs, ip, L, S, ik, LHS, f64, stream));
-    PQ_TRY(pq::grad_ncombine(nullptr, nullptr, Yall, sbar, sigs, ip, S, S, ik, RHS, f64, stream));
+    PQ_TRY(pq::grad_xcombine(nullptr, nullptr, U, sigs, ip, L, S, ik, LHS, true, stream));
+    PQ_TRY(pq::grad_ncombine(nullptr, nullptr, Yall, s64, sigs, ip, S, S, ik, RHS, true, false, stream));
     if (info_dev) PQ_TRY(pq::grad_count(cnt, 0, info_dev + 3, stream));
   }
   // the face gradient: dM_t = [U_K X][N Y]^T, written as the face itself
@@ -904,20 +939,33 @@ int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q, int64_t n1, int
                               Mbar, n1, N, ip)
                   : face_gemm(false, true, S, L, 2 * ik, RHS, S, (int64_t)S * 2 * k, LHS, L, (int64_t)L * 2 * k,
                               Mbar, n1, N, ip);
-    PQ_TRY(do_gemm("grad_gemm", g, dt, pr, stream));
+    PQ_TRY(do_gemm("grad_gemm", g, PQ_F64, pr, stream));
   }
-  if (dA) PQ_TRY(do_unhat(Mbar, Q, dA, dt, N, in3, ip, pr, stream));
+  // the transforms back run in the data's type, on its own A, Q and Gbar
+  const void* Mb = Mbar;
+  if (!f64) {
+    PQ_PROF("grad_elementwise", stream);
+    PQ_TRY(pq::grad_narrow(Mbar, Mbar32, N * p, stream));
+    Mb = Mbar32;
+  }
+  if (dA) PQ_TRY(do_unhat(Mb, Q, dA, dt, N, in3, ip, pr, stream));
   if (dQ) {
     // dQ^T = Mbar_(3) A_(3)^T + Akh_(3) Gbar_(3)^T
     const size_t slab = e * (size_t)p * n3;
-    PQ_TRY(do_gemm("dq_gemm", dq_gemm(Mbar, A, ip, in3, N, parts, ks), dt, pr, stream));
+    PQ_TRY(do_gemm("dq_gemm", dq_gemm(Mb, A, ip, in3, N, parts, ks), dt, pr, stream));
     int nparts = ks;
     if (has_g) {
       // Akh = U_K Y^T (cols) or Y U_K^T (rows): the transform-domain A_k
       Gemm g = cols ? face_gemm(false, true, L, S, ik, U, L, sU, Yall, S, sY, Akh, n1, N, ip)
                     : face_gemm(false, true, S, L, ik, Yall, S, sY, U, L, sU, Akh, n1, N, ip);
-      PQ_TRY(do_gemm("approx_gemm", g, dt, pr, stream));
-      PQ_TRY(do_gemm("dq_gemm", dq_gemm(Akh, Gbar, ip, in3, N, parts + slab * ks, ks), dt, pr, stream));
+      PQ_TRY(do_gemm("approx_gemm", g, PQ_F64, pr, stream));
+      const void* Ak = Akh;
+      if (!f64) {
+        PQ_PROF("grad_elementwise", stream);
+        PQ_TRY(pq::grad_narrow(Akh, Akh32, N * p, stream));
+        Ak = Akh32;
+      }
+      PQ_TRY(do_gemm("dq_gemm", dq_gemm(Ak, Gbar, ip, in3, N, parts + slab * ks, ks), dt, pr, stream));
       nparts += ks;
     }
     PQ_TRY(do_sum(parts, nparts, p * n3, p * n3, dQ, dt, stream));

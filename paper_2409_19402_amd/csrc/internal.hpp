@@ -177,7 +177,7 @@ hipError_t grad_xcombine(const void* R, const void* UE, const void* U, const dou
 // RHS (S x 2k x p) = [H + P1 + Y diag(sbar / sigma), Y] (null terms are 0;
 // Y is read from Yall, S x S per face)
 hipError_t grad_ncombine(const void* H, const void* P1, const void* Y, const void* sbar, const double* sig, int p,
-                         int S, int nv, int k, void* RHS, bool f64, hipStream_t s);
+                         int S, int nv, int k, void* RHS, bool f64, bool sbar_f32, hipStream_t s);
 // out[0] = sum of cnt[0..p)
 hipError_t grad_count(const int* cnt, int p, int* out, hipStream_t s);
 

@@ -425,19 +425,28 @@ __host__ __device__ __forceinline__ int gram_grid(int nfaces, int npair) {
   return kXcds * ((nfaces + kXcds - 1) / kXcds) * npair;
 }
 
-template <typename T, int NB, bool ST>
-__global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, const JFace* __restrict__ faces,
-                                                          int nfaces, int npair, int nv_u, int L_u, int round,
-                                                          int sweep, int max_sweeps, double tol,
-                                                          int* __restrict__ flags) {
+// Adjacent-lane swap (lanes 2i <-> 2i + 1) on the VALU.
+__device__ __forceinline__ float swap_pair(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double swap_pair(double v) { return dpp_f64<0xB1>(v); }
+
+template <typename T, int NB, bool ST, int NW>
+__global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W, const JFace* __restrict__ faces,
+                                                              int nfaces, int npair, int nv_u, int L_u, int round,
+                                                              int sweep, int max_sweeps, double tol,
+                                                              int* __restrict__ flags) {
   typedef GramMfma<T> M;
   typedef typename M::vec_t vec_t;
   constexpr int VEC = M::kVec;
   constexpr bool F32 = sizeof(T) == 4;
+  constexpr int NT = 64 * NW;    // threads of a visit
+  constexpr int VPW = kG2 / NW;  // staged vectors per wave
   // G and the angle arithmetic: float32 in the coarse sweeps of float32 data,
   // float64 in the polishing sweeps; V is float64 in both
   typedef typename std::conditional<F32, float, double>::type R;
   static_assert(NB == 1 || NB == 2, "one or two copies of G");
+  static_assert(NW == 4 || NW == 8, "four or eight waves per visit");
   static_assert(gram_partials_fit<T, NB>(), "partial tiles exceed the G/V area");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* Gb = reinterpret_cast<R*>(smem_raw);  // G copies at Gb (and Gb + kGMat)
@@ -467,51 +476,51 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   auto gvec = [&](int u) { return u < kGB ? I * kGB + u : J * kGB + (u - kGB); };
 
   if constexpr (ST) {
-    // stage the 32 vectors (wave w takes vectors w, w + 4, ...), zero past nv;
-    // each lane issues the loads of its 8 vectors before their LDS stores, with
-    // clamped addresses and out-of-range values masked
+    // stage the 32 vectors (wave w takes vectors w, w + NW, ...), zero past
+    // nv; each lane issues the loads of its vectors before their LDS stores,
+    // with clamped addresses and out-of-range values masked
     if (L % VEC == 0 && fd.off % VEC == 0) {
       const int nq = L / VEC;
-      // two 64-chunk columns per pass: 16 loads of each lane in flight at once
+      // two 64-chunk columns per pass: all loads of a lane in flight at once
       for (int q0 = 0; q0 < nq; q0 += 128) {
-        vec_t buf[2][8];
-  #pragma unroll
+        vec_t buf[2][VPW];
+#pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int qc = min(q0 + 64 * h + lane, nq - 1);
-  #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int g = gvec(wave + 4 * i);
+#pragma unroll
+          for (int i = 0; i < VPW; ++i) {
+            const int g = gvec(wave + NW * i);
             const vec_t v = *reinterpret_cast<const vec_t*>(Wf + (int64_t)min(g, nv - 1) * L + VEC * qc);
             buf[h][i] = g < nv ? v : M::zero();
           }
         }
-  #pragma unroll
+#pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int q = q0 + 64 * h + lane;
           if (q < nq) {
-  #pragma unroll
-            for (int i = 0; i < 8; ++i) *reinterpret_cast<vec_t*>(X + (wave + 4 * i) * ldx + VEC * q) = buf[h][i];
+#pragma unroll
+            for (int i = 0; i < VPW; ++i) *reinterpret_cast<vec_t*>(X + (wave + NW * i) * ldx + VEC * q) = buf[h][i];
           }
         }
       }
     } else {
       for (int e0 = 0; e0 < L; e0 += 64) {
         const int e = e0 + lane, ec = min(e, L - 1);
-        T buf[8];
-  #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int g = gvec(wave + 4 * i);
+        T buf[VPW];
+#pragma unroll
+        for (int i = 0; i < VPW; ++i) {
+          const int g = gvec(wave + NW * i);
           const T v = Wf[(int64_t)min(g, nv - 1) * L + ec];
           buf[i] = g < nv ? v : T(0);
         }
         if (e < L) {
-  #pragma unroll
-          for (int i = 0; i < 8; ++i) X[(wave + 4 * i) * ldx + e] = buf[i];
+#pragma unroll
+          for (int i = 0; i < VPW; ++i) X[(wave + NW * i) * ldx + e] = buf[i];
         }
       }
     }
     if (Lp > L) {
-      for (int e = tid; e < kG2 * 16; e += 256) {
+      for (int e = tid; e < kG2 * 16; e += NT) {
         const int u = e >> 4, c = L + (e & 15);
         if (c < Lp) X[u * ldx + c] = T(0);
       }
@@ -519,14 +528,15 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   }
   __syncthreads();
 
-  // G = X^T X.  Wave w takes the 16-element chunks w, w + 4, ... of the
+  // G = X^T X.  Wave w takes the 16-element chunks w, w + NW, ... of the
   // vectors and forms the three distinct 16 x 16 tiles (0,0), (0,1), (1,1)
   // of its chunks' contribution: per chunk, 8 operand reads feed 12 MFMAs,
   // and each tile has four independent accumulation chains.  MFMA t of a
   // chunk takes element 4 kq + t of the chunk from the lanes of k-group kq:
   // the chunk's 16 elements in some order, the same for both operands.  The
-  // four waves' partial tiles meet in LDS (the G and V area, free until
-  // here) and are summed in a fixed order.
+  // waves' partial tiles meet in LDS (the G and V area, free until here;
+  // with eight waves, waves 4-7 first fold theirs into waves 0-3) and are
+  // summed in a fixed order.
   {
     typedef typename M::acc_t acc_t;
     acc_t acc[3][4];
@@ -546,7 +556,7 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
       const T* x0 = X + r16 * ldx + 4 * kq;
       const T* x1 = X + (16 + r16) * ldx + 4 * kq;
 #pragma unroll 2
-      for (int s0 = 16 * wave; s0 < Lp; s0 += 64) {
+      for (int s0 = 16 * wave; s0 < Lp; s0 += 16 * NW) {
         T a0[4], a1[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -573,46 +583,72 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
       T n0[4], n1[4];
       int s0 = 16 * wave;
       if (s0 < Lp) fetch(s0, n0, n1);
-      for (; s0 < Lp; s0 += 64) {
+      for (; s0 < Lp; s0 += 16 * NW) {
         T a0[4], a1[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           a0[t] = n0[t];
           a1[t] = n1[t];
         }
-        if (s0 + 64 < Lp) fetch(s0 + 64, n0, n1);
+        if (s0 + 16 * NW < Lp) fetch(s0 + 16 * NW, n0, n1);
         mma3(a0, a1);
       }
     }
-    T* part = reinterpret_cast<T*>(smem_raw);  // [wave][tile][j][lane]
+    T* part = reinterpret_cast<T*>(smem_raw);  // [wave][tile][j][lane], waves 0-3
+    acc_t sum[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const acc_t s = (acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]);
+    for (int q = 0; q < 3; ++q) sum[q] = (acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]);
+    if constexpr (NW == 8) {
+      if (wave >= 4) {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) part[((wave * 3 + q) * 4 + jj) * 64 + lane] = s[jj];
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) part[(((wave - 4) * 3 + q) * 4 + jj) * 64 + lane] = sum[q][jj];
+      }
+      __syncthreads();
+      if (wave < 4) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) sum[q][jj] += part[((wave * 3 + q) * 4 + jj) * 64 + lane];
+      }
+      __syncthreads();
+    }
+    if (wave < 4) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) part[((wave * 3 + q) * 4 + jj) * 64 + lane] = sum[q][jj];
     }
     __syncthreads();
-    // thread tid sums entry (j = tid / 64, lane = tid % 64) of each tile
-    const int jj = tid >> 6;
-    R g[3];
+    // the 768 entries (tile q, value jj, lane ln) summed over the four waves
+    constexpr int kPer = (3 * 256 + NT - 1) / NT;
+    R gsum[kPer];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const T v = ((part[((0 * 3 + q) * 4 + jj) * 64 + lane] + part[((1 * 3 + q) * 4 + jj) * 64 + lane]) +
-                   (part[((2 * 3 + q) * 4 + jj) * 64 + lane] + part[((3 * 3 + q) * 4 + jj) * 64 + lane]));
-      g[q] = (R)v;
-    }
-    __syncthreads();
-    // lane holds G[16 ti + row(kq, jj)][16 tj + r16] of tile (ti, tj)
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int ti = q == 2 ? 1 : 0, tj = q == 0 ? 0 : 1;
-      const int row = 16 * ti + M::row(kq, jj), col = 16 * tj + r16;
-      if (ti != tj || row <= col) {
-        Gb[row * kGld + col] = g[q];
-        Gb[col * kGld + row] = g[q];
+    for (int i = 0; i < kPer; ++i) {
+      const int e = tid + NT * i;
+      if (e < 3 * 256) {
+        const int q = e >> 8, jj = (e >> 6) & 3, ln = e & 63;
+        gsum[i] = (R)((part[((0 * 3 + q) * 4 + jj) * 64 + ln] + part[((1 * 3 + q) * 4 + jj) * 64 + ln]) +
+                      (part[((2 * 3 + q) * 4 + jj) * 64 + ln] + part[((3 * 3 + q) * 4 + jj) * 64 + ln]));
       }
     }
-    for (int e = tid; e < kG2 * kG2; e += 256) V[(e >> 5) * kGld + (e & 31)] = ((e >> 5) == (e & 31)) ? 1.0 : 0.0;
+    __syncthreads();
+    // lane ln of value jj holds G[16 ti + row(ln / 16, jj)][16 tj + ln mod 16]
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = tid + NT * i;
+      if (e < 3 * 256) {
+        const int q = e >> 8, jj = (e >> 6) & 3, ln = e & 63;
+        const int ti = q == 2 ? 1 : 0, tj = q == 0 ? 0 : 1;
+        const int row = 16 * ti + M::row(ln >> 4, jj), col = 16 * tj + (ln & 15);
+        if (ti != tj || row <= col) {
+          Gb[row * kGld + col] = gsum[i];
+          Gb[col * kGld + row] = gsum[i];
+        }
+      }
+    }
+    for (int e = tid; e < kG2 * kG2; e += NT) V[(e >> 5) * kGld + (e & 31)] = ((e >> 5) == (e & 31)) ? 1.0 : 0.0;
     if (tid == 0) *any_rot = 0;
   }
   __syncthreads();
@@ -623,15 +659,14 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   {
     bool need = false;
     if (full) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = tid + 256 * k, i = e >> 5, c = e & 31;
+      for (int e = tid; e < kG2 * kG2; e += NT) {
+        const int i = e >> 5, c = e & 31;
         if (i < c) {
           const double g = Gb[i * kGld + c];
           need |= g * g > tol2 * (double)Gb[i * kGld + i] * (double)Gb[c * kGld + c];
         }
       }
-    } else {
+    } else if (tid < kGB * kGB) {
       const int i = tid >> 4, c = kGB + (tid & 15);
       const double g = Gb[i * kGld + c];
       need = g * g > tol2 * (double)Gb[i * kGld + i] * (double)Gb[c * kGld + c];
@@ -642,89 +677,156 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   }
   if (tid == 0) flags[f * max_sweeps + sweep] = 1;
 
-  // Rounds on G.  Each round reads the current copy of G and writes every
-  // entry of the other, so one barrier per round suffices.  Thread (P, P2)
-  // (P2 = lane mod 16) computes the rotation of pair P2, takes pair P's from
-  // lane P of its wave, writes its own 2x2 block of J^T G J (rows of pair P,
-  // columns of pair P2: threads (P, P2) and (P2, P) write mirror blocks, equal
-  // up to rounding), and rows P2 and P2 + 16 of V J in the columns of pair P.
-  // In float32 the rotation applied to V is renormalised in float64 (first
-  // order in cos^2 + sin^2 - 1, exact to 1e-14), so V stays orthogonal to
-  // float64 precision whatever the float32 angle arithmetic does.  The work
-  // per round is a few dozen instructions per thread: at wave64 on 16-lane
-  // SIMDs every instruction costs four cycles, and the instruction count is
-  // what bounds the round.
-  const int P = tid >> 4, P2 = tid & 15;
-  const int nrounds = full ? kG2 - 1 : kGB;
-  const R tol2r = (R)tol2;
-  const int vr0 = P2 * kGld, vr1 = (P2 + 16) * kGld;
-  // V J of a round is applied during the next round (after the barrier that
-  // ends it, before the one that ends the next), off the angle arithmetic's
-  // path: the entries a thread updates are its own within a round, and the
-  // barriers order the updates of one entry across rounds
-  int pa = 0, pc = 0;
-  double pvc = 1.0, pvs = 0.0;
-  auto apply_v = [&]() {
-    const double v0a = V[vr0 + pa], v0c = V[vr0 + pc];
-    const double v1a = V[vr1 + pa], v1c = V[vr1 + pc];
-    V[vr0 + pa] = pvc * v0a - pvs * v0c;
-    V[vr0 + pc] = pvs * v0a + pvc * v0c;
-    V[vr1 + pa] = pvc * v1a - pvs * v1c;
-    V[vr1 + pc] = pvs * v1a + pvc * v1c;
-  };
-  int cur = 0;
-  for (int r = 0; r < nrounds; ++r) {
-    const R* G = Gb + (NB == 2 ? cur : 0) * kGMat;
-    R* Gn = Gb + (NB == 2 ? cur ^ 1 : 0) * kGMat;
-    int a1, c1, a2, c2;
-    gram_pair(full, r, P, a1, c1);
-    gram_pair(full, r, P2, a2, c2);
-    const int ra1 = (a1 << 5) + a1, rc1 = (c1 << 5) + c1;  // row offsets (kGld = 33)
-    const int ra2 = (a2 << 5) + a2, rc2 = (c2 << 5) + c2;
-    const R m00 = G[ra1 + a2], m01 = G[ra1 + c2];
-    const R m10 = G[rc1 + a2], m11 = G[rc1 + c2];
-    const R al2 = G[ra2 + a2], be2 = G[rc2 + c2], ga2 = G[ra2 + c2];
-    if (r > 0) apply_v();
-    R c2r, s2r;
-    if constexpr (F32) {
-      const float2 q2 = gram_rotation_f32(al2, be2, ga2, tol2r);
-      c2r = q2.x;
-      s2r = q2.y;
-    } else {
-      const double2 q2 = gram_rotation<2>(al2, be2, ga2, tol2);
-      c2r = q2.x;
-      s2r = q2.y;
+  if constexpr (NW == 4) {
+    // Rounds on G.  Each round reads the current copy of G and writes every
+    // entry of the other, so one barrier per round suffices.  Thread (P, P2)
+    // (P2 = lane mod 16) computes the rotation of pair P2, takes pair P's from
+    // lane P of its wave, writes its own 2x2 block of J^T G J (rows of pair P,
+    // columns of pair P2: threads (P, P2) and (P2, P) write mirror blocks, equal
+    // up to rounding), and rows P2 and P2 + 16 of V J in the columns of pair P.
+    // In float32 the rotation applied to V is renormalised in float64 (first
+    // order in cos^2 + sin^2 - 1, exact to 1e-14), so V stays orthogonal to
+    // float64 precision whatever the float32 angle arithmetic does.  The work
+    // per round is a few dozen instructions per thread: at wave64 on 16-lane
+    // SIMDs every instruction costs four cycles, and the instruction count is
+    // what bounds the round.
+    const int P = tid >> 4, P2 = tid & 15;
+    const int nrounds = full ? kG2 - 1 : kGB;
+    const R tol2r = (R)tol2;
+    const int vr0 = P2 * kGld, vr1 = (P2 + 16) * kGld;
+    // V J of a round is applied during the next round (after the barrier that
+    // ends it, before the one that ends the next), off the angle arithmetic's
+    // path: the entries a thread updates are its own within a round, and the
+    // barriers order the updates of one entry across rounds
+    int pa = 0, pc = 0;
+    double pvc = 1.0, pvs = 0.0;
+    auto apply_v = [&]() {
+      const double v0a = V[vr0 + pa], v0c = V[vr0 + pc];
+      const double v1a = V[vr1 + pa], v1c = V[vr1 + pc];
+      V[vr0 + pa] = pvc * v0a - pvs * v0c;
+      V[vr0 + pc] = pvs * v0a + pvc * v0c;
+      V[vr1 + pa] = pvc * v1a - pvs * v1c;
+      V[vr1 + pc] = pvs * v1a + pvc * v1c;
+    };
+    int cur = 0;
+    for (int r = 0; r < nrounds; ++r) {
+      const R* G = Gb + (NB == 2 ? cur : 0) * kGMat;
+      R* Gn = Gb + (NB == 2 ? cur ^ 1 : 0) * kGMat;
+      int a1, c1, a2, c2;
+      gram_pair(full, r, P, a1, c1);
+      gram_pair(full, r, P2, a2, c2);
+      const int ra1 = (a1 << 5) + a1, rc1 = (c1 << 5) + c1;  // row offsets (kGld = 33)
+      const int ra2 = (a2 << 5) + a2, rc2 = (c2 << 5) + c2;
+      const R m00 = G[ra1 + a2], m01 = G[ra1 + c2];
+      const R m10 = G[rc1 + a2], m11 = G[rc1 + c2];
+      const R al2 = G[ra2 + a2], be2 = G[rc2 + c2], ga2 = G[ra2 + c2];
+      if (r > 0) apply_v();
+      R c2r, s2r;
+      if constexpr (F32) {
+        const float2 q2 = gram_rotation_f32(al2, be2, ga2, tol2r);
+        c2r = q2.x;
+        s2r = q2.y;
+      } else {
+        const double2 q2 = gram_rotation<2>(al2, be2, ga2, tol2);
+        c2r = q2.x;
+        s2r = q2.y;
+      }
+      const R c1r = __shfl(c2r, P), s1r = __shfl(s2r, P);
+      const R t00 = c2r * m00 - s2r * m01, t01 = s2r * m00 + c2r * m01;
+      const R t10 = c2r * m10 - s2r * m11, t11 = s2r * m10 + c2r * m11;
+      const bool own = P == P2 && s1r != R(0);  // the rotation annihilates its own off-diagonal entry
+      const R g00 = c1r * t00 - s1r * t10;
+      const R g01 = own ? R(0) : c1r * t01 - s1r * t11;
+      const R g10 = own ? R(0) : s1r * t00 + c1r * t10;
+      const R g11 = s1r * t01 + c1r * t11;
+      if constexpr (NB == 1) __syncthreads();  // every read of the round before any write
+      Gn[ra1 + a2] = g00;
+      Gn[ra1 + c2] = g01;
+      Gn[rc1 + a2] = g10;
+      Gn[rc1 + c2] = g11;
+      pa = a1;
+      pc = c1;
+      pvc = c1r;
+      pvs = s1r;
+      if constexpr (F32) {
+        const double nf = fma(-0.5, fma(pvc, pvc, pvs * pvs), 1.5);
+        pvc *= nf;
+        pvs *= nf;
+      }
+      cur ^= 1;
+      __syncthreads();
     }
-    const R c1r = __shfl(c2r, P), s1r = __shfl(s2r, P);
-    const R t00 = c2r * m00 - s2r * m01, t01 = s2r * m00 + c2r * m01;
-    const R t10 = c2r * m10 - s2r * m11, t11 = s2r * m10 + c2r * m11;
-    const bool own = P == P2 && s1r != R(0);  // the rotation annihilates its own off-diagonal entry
-    const R g00 = c1r * t00 - s1r * t10;
-    const R g01 = own ? R(0) : c1r * t01 - s1r * t11;
-    const R g10 = own ? R(0) : s1r * t00 + c1r * t10;
-    const R g11 = s1r * t01 + c1r * t11;
-    if constexpr (NB == 1) __syncthreads();  // every read of the round before any write
-    Gn[ra1 + a2] = g00;
-    Gn[ra1 + c2] = g01;
-    Gn[rc1 + a2] = g10;
-    Gn[rc1 + c2] = g11;
-    pa = a1;
-    pc = c1;
-    pvc = c1r;
-    pvs = s1r;
-    if constexpr (F32) {
-      const double nf = fma(-0.5, fma(pvc, pvc, pvs * pvs), 1.5);
-      pvc *= nf;
-      pvs *= nf;
+    apply_v();
+    __syncthreads();
+
+  } else {
+    // Eight waves: threads 2b and 2b + 1 share the 2x2 block b = (P, P2)
+    // of the four-wave form, one row of it each (h = 0: row of a1, h = 1:
+    // row of c1), and swap the row products J_P2 they need by DPP; each
+    // updates one of the block's two V rows (P2 + 16 h).
+    const int blk = tid >> 1, h = tid & 1;
+    const int P = blk >> 4, P2 = blk & 15;
+    const int srcl = (2 * 17 * P) & 63;  // a lane of this wave that holds block (P, P)
+    const int nrounds = full ? kG2 - 1 : kGB;
+    const R tol2r = (R)tol2;
+    const int vr = (P2 + 16 * h) * kGld;
+    int pa = 0, pc = 0;
+    double pvc = 1.0, pvs = 0.0;
+    auto apply_v = [&]() {
+      const double va_ = V[vr + pa], vc_ = V[vr + pc];
+      V[vr + pa] = pvc * va_ - pvs * vc_;
+      V[vr + pc] = pvs * va_ + pvc * vc_;
+    };
+    int cur = 0;
+    for (int r = 0; r < nrounds; ++r) {
+      const R* G = Gb + (NB == 2 ? cur : 0) * kGMat;
+      R* Gn = Gb + (NB == 2 ? cur ^ 1 : 0) * kGMat;
+      int a1, c1, a2, c2;
+      gram_pair(full, r, P, a1, c1);
+      gram_pair(full, r, P2, a2, c2);
+      const int rx = h ? (c1 << 5) + c1 : (a1 << 5) + a1;  // this thread's row of the block
+      const int ra2 = (a2 << 5) + a2, rc2 = (c2 << 5) + c2;
+      const R mx0 = G[rx + a2], mx1 = G[rx + c2];
+      const R al2 = G[ra2 + a2], be2 = G[rc2 + c2], ga2 = G[ra2 + c2];
+      if (r > 0) apply_v();
+      R c2r, s2r;
+      if constexpr (F32) {
+        const float2 q2 = gram_rotation_f32(al2, be2, ga2, tol2r);
+        c2r = q2.x;
+        s2r = q2.y;
+      } else {
+        const double2 q2 = gram_rotation<2>(al2, be2, ga2, tol2);
+        c2r = q2.x;
+        s2r = q2.y;
+      }
+      const R c1r = __shfl(c2r, srcl), s1r = __shfl(s2r, srcl);
+      const R tx0 = c2r * mx0 - s2r * mx1, tx1 = s2r * mx0 + c2r * mx1;  // this row times J_P2
+      const R ty0 = swap_pair(tx0), ty1 = swap_pair(tx1);                 // the other row's
+      const R sg = h ? s1r : -s1r;
+      const bool own = P == P2 && s1r != R(0);  // the rotation annihilates its own off-diagonal entry
+      const R gA = (own && h) ? R(0) : c1r * tx0 + sg * ty0;
+      const R gB = (own && !h) ? R(0) : c1r * tx1 + sg * ty1;
+      if constexpr (NB == 1) __syncthreads();  // every read of the round before any write
+      Gn[rx + a2] = gA;
+      Gn[rx + c2] = gB;
+      pa = a1;
+      pc = c1;
+      pvc = c1r;
+      pvs = s1r;
+      if constexpr (F32) {
+        const double nf = fma(-0.5, fma(pvc, pvc, pvs * pvs), 1.5);
+        pvc *= nf;
+        pvs *= nf;
+      }
+      cur ^= 1;
+      __syncthreads();
     }
-    cur ^= 1;
+    apply_v();
     __syncthreads();
   }
-  apply_v();
-  __syncthreads();
 
   // X <- X V: D[c][e] = sum_a V[a][c] X[a][e]; wave w takes the 16-element
-  // column tiles te = w, w + 4, ... and both row tiles tc of each.
+  // column tiles te = w, w + NW, ... and both row tiles tc of each.
   T va[2][8];
 #pragma unroll
   for (int tc = 0; tc < 2; ++tc)
@@ -746,7 +848,7 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
   if constexpr (!ST) {
     if (wave < (Lp >> 4)) fetch_tile(wave, nb8);
   }
-  for (int te = wave; te < (Lp >> 4); te += 4) {
+  for (int te = wave; te < (Lp >> 4); te += NW) {
     T xb[8];
     if constexpr (ST) {
 #pragma unroll
@@ -754,7 +856,7 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(T* __restrict__ W, con
     } else {
 #pragma unroll
       for (int s = 0; s < 8; ++s) xb[s] = nb8[s];
-      if (te + 4 < (Lp >> 4)) fetch_tile(te + 4, nb8);
+      if (te + NW < (Lp >> 4)) fetch_tile(te + NW, nb8);
     }
     const int e = 16 * te + r16;
     // the two row tiles as interleaved, independent MFMA chains
@@ -1321,12 +1423,12 @@ hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, doub
 // sweep rotated nothing is skipped by the later launches.
 // The dynamic LDS the kernel may use: the largest of 160, 128 and 64 KiB
 // that the device accepts (set once per process and instantiation).
-template <typename T, int NB, bool ST>
+template <typename T, int NB, bool ST, int NW = 4>
 size_t gram_lds_cap() {
   static size_t cap = 0;
   if (cap == 0) {
     for (size_t c : {(size_t)160 * 1024, (size_t)128 * 1024, (size_t)64 * 1024}) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_gram_kernel<T, NB, ST>),
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_gram_kernel<T, NB, ST, NW>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)c) == hipSuccess) {
         cap = c;
         break;
@@ -1370,14 +1472,14 @@ GramForm gram_form(int L, int grid) {
   }
 }
 
-template <typename T, int NB, bool ST>
+template <typename T, int NB, bool ST, int NW>
 void gram_launch_all(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max, int max_sweeps,
                      double tol, int* flags, hipStream_t s) {
   const size_t lds = gram_lds_bytes<T, NB, ST>(L_max);
-  (void)gram_lds_cap<T, NB, ST>();  // sets the kernel's LDS limit once
+  (void)gram_lds_cap<T, NB, ST, NW>();  // sets the kernel's LDS limit once
   for (int sw = 0; sw < max_sweeps; ++sw)
     for (int round = 0; round < nb_max - 1; ++round)
-      jacobi_gram_kernel<T, NB, ST><<<(unsigned)gram_grid(nfaces, nb_max / 2), 256, lds, s>>>(
+      jacobi_gram_kernel<T, NB, ST, NW><<<(unsigned)gram_grid(nfaces, nb_max / 2), 64 * NW, lds, s>>>(
           W, faces, nfaces, nb_max / 2, nv_u, L_u, round, sw, max_sweeps, tol, flags);
 }
 
@@ -1392,15 +1494,22 @@ hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, 
   const GramForm form = gram_form<T>(L_max, gram_grid(nfaces, nb_max / 2));
   {
     ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s, max_sweeps * (nb_max - 1));
+    // a launch with at most one visit per CU gives each visit eight waves
+    const bool wide = gram_grid(nfaces, nb_max / 2) <= 256;
     if (form == GramForm::Stream) {
-      gram_launch_all<T, 2, false>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+      gram_launch_all<T, 2, false, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
     } else if constexpr (sizeof(T) == 4) {
       if (form == GramForm::Staged1)
-        gram_launch_all<T, 1, true>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+        gram_launch_all<T, 1, true, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+      else if (wide)
+        gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
       else
-        gram_launch_all<T, 2, true>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+        gram_launch_all<T, 2, true, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
     } else {
-      gram_launch_all<T, 2, true>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+      if (wide)
+        gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+      else
+        gram_launch_all<T, 2, true, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
     }
   }
   {

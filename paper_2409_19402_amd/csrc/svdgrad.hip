@@ -100,9 +100,9 @@ __global__ __launch_bounds__(256) void xcombine_kernel(const T* __restrict__ R, 
 
 // RHS (S x 2k per face) = [H + P1 + Y diag(sbar / sigma), Y]; null terms are
 // 0; Y is the first k columns of Yall (S x S per face)
-template <typename T>
+template <typename T, typename TS>
 __global__ __launch_bounds__(256) void ncombine_kernel(const T* __restrict__ H, const T* __restrict__ P1,
-                                                       const T* __restrict__ Y, const T* __restrict__ sbar,
+                                                       const T* __restrict__ Y, const TS* __restrict__ sbar,
                                                        const double* __restrict__ sig, int S, int nv, int k,
                                                        int64_t total, T* __restrict__ RHS) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -171,14 +171,18 @@ hipError_t grad_xcombine(const void* R, const void* UE, const void* U, const dou
 }
 
 hipError_t grad_ncombine(const void* H, const void* P1, const void* Y, const void* sbar, const double* sig, int p,
-                         int S, int nv, int k, void* RHS, bool f64, hipStream_t s) {
+                         int S, int nv, int k, void* RHS, bool f64, bool sbar_f32, hipStream_t s) {
   const int64_t total = (int64_t)p * S * 2 * k;
-  if (f64)
-    ncombine_kernel<double><<<blocks(total), 256, 0, s>>>(
+  if (f64 && sbar_f32)
+    ncombine_kernel<double, float><<<blocks(total), 256, 0, s>>>(
+        static_cast<const double*>(H), static_cast<const double*>(P1), static_cast<const double*>(Y),
+        static_cast<const float*>(sbar), sig, S, nv, k, total, static_cast<double*>(RHS));
+  else if (f64)
+    ncombine_kernel<double, double><<<blocks(total), 256, 0, s>>>(
         static_cast<const double*>(H), static_cast<const double*>(P1), static_cast<const double*>(Y),
         static_cast<const double*>(sbar), sig, S, nv, k, total, static_cast<double*>(RHS));
   else
-    ncombine_kernel<float><<<blocks(total), 256, 0, s>>>(
+    ncombine_kernel<float, float><<<blocks(total), 256, 0, s>>>(
         static_cast<const float*>(H), static_cast<const float*>(P1), static_cast<const float*>(Y),
         static_cast<const float*>(sbar), sig, S, nv, k, total, static_cast<float*>(RHS));
   return hipGetLastError();
