@@ -287,7 +287,7 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
  * 1e-13; two singular vectors come out coupled by about tol / (2 x the
  * relative gap of their singular values); for F32 and BF16 data the final
  * sweeps work on Gram matrices of the vectors and use max(tol, 1e-10)),
- * max_sweeps caps the sweeps of each phase (<= 0: 12 for float32 data,
+ * max_sweeps caps the sweeps of each phase (<= 0: 10 for float32 data,
  * 30 for float64, whose Gram phase takes at most 16 and whose vector phase
  * at most 8; at most 100).  info_dev (device int[3], may be NULL)
  * receives [0] = the largest number of sweeps any face used (both phases),
@@ -408,7 +408,7 @@ int pq_batched_workspace(const pq_instance* inst, int count, size_t* bytes);
  * for the handle only.  The transforms, facewise products and
  * back-projections run per instance; the Jacobi sweeps of all tSVDQ
  * instances run as grouped launches over every face at once.  max_sweeps
- * (<= 0: 12) and tol (<= 0: 1e-13) as in pq_tsvdq; info_dev (device int[3],
+ * (<= 0: 10) and tol (<= 0: 1e-13) as in pq_tsvdq; info_dev (device int[3],
  * may be NULL) receives the sweep statistics over all faces, as in pq_tsvdq.
  * Every pointer of inst[] and ws is baked into the graph: they must stay
  * valid until pq_batched_destroy, and each run reads and writes them again.

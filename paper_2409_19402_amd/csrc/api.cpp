@@ -95,7 +95,7 @@ struct Arena {
   bool fits() const { return used <= cap; }
 };
 
-constexpr int kDefaultSweeps32 = 12;  // per phase; float32 faces need 6-12 coarse sweeps (more go on in float64)
+constexpr int kDefaultSweeps32 = 10;  // per phase; float32 faces need 6-11 coarse sweeps to 1e-5 (the float64 phase continues from where they stop)
 constexpr int kDefaultSweeps64 = 30;
 // Jacobi thresholds on |a.c| / (|a||c|): the float32 phase stops at the coarse
 // one, the float64 phase polishes to the default final one.

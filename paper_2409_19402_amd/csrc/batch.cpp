@@ -27,7 +27,7 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kMaxSweepsCap = 100;
-constexpr int kDefaultSweeps = 12;
+constexpr int kDefaultSweeps = 10;
 constexpr double kCoarseTol = 1e-5;
 constexpr int kPolishSweeps = 8;
 constexpr double kTolFloor = 1e-10;
