@@ -1494,22 +1494,16 @@ hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, 
   const GramForm form = gram_form<T>(L_max, gram_grid(nfaces, nb_max / 2));
   {
     ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s, max_sweeps * (nb_max - 1));
-    // a launch with at most one visit per CU gives each visit eight waves
-    const bool wide = gram_grid(nfaces, nb_max / 2) <= 256;
+    // staged visits get eight waves (two per SIMD hide each other's latency)
     if (form == GramForm::Stream) {
       gram_launch_all<T, 2, false, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
     } else if constexpr (sizeof(T) == 4) {
       if (form == GramForm::Staged1)
-        gram_launch_all<T, 1, true, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
-      else if (wide)
-        gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+        gram_launch_all<T, 1, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
       else
-        gram_launch_all<T, 2, true, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+        gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
     } else {
-      if (wide)
-        gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
-      else
-        gram_launch_all<T, 2, true, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+      gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
     }
   }
   {
