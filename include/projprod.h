@@ -288,8 +288,8 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
  * relative gap of their singular values); for F32 and BF16 data the final
  * sweeps work on Gram matrices of the vectors and use max(tol, 1e-10)),
  * max_sweeps caps the sweeps of each phase (<= 0: 10 for float32 data,
- * 30 for float64, whose Gram phase takes at most 16 and whose vector phase
- * at most 8; at most 100).  info_dev (device int[3], may be NULL)
+ * whose float64 phase takes at most 6; 30 for float64 data, whose Gram
+ * phase takes at most 16 and whose vector phase at most 6; at most 100).  info_dev (device int[3], may be NULL)
  * receives [0] = the largest number of sweeps any face used (both phases),
  * [1] = the number of faces whose last phase hit max_sweeps before
  * converging (their outputs are still written) and [2] = the sweeps summed

@@ -100,7 +100,7 @@ constexpr int kDefaultSweeps64 = 30;
 // Jacobi thresholds on |a.c| / (|a||c|): the float32 phase stops at the coarse
 // one, the float64 phase polishes to the default final one.
 constexpr double kCoarseTol32 = 1e-5;
-constexpr int kPolishSweeps = 8;  // float64 polishing from the coarse threshold: 2-4 sweeps
+constexpr int kPolishSweeps = 6;  // float64 phase from the coarse threshold: 2-4 sweeps (the last one rotates nothing)
 constexpr double kPolishTol = 1e-13;
 // The float64 sweeps of float32 data run on Gram matrices, whose rotation
 // angles come from G as updated within a visit: their stopping test is

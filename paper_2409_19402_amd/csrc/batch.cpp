@@ -29,7 +29,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kMaxSweepsCap = 100;
 constexpr int kDefaultSweeps = 10;
 constexpr double kCoarseTol = 1e-5;
-constexpr int kPolishSweeps = 8;
+constexpr int kPolishSweeps = 6;
 constexpr double kTolFloor = 1e-10;
 constexpr double kDefaultTol = 1e-13;
 constexpr int64_t kMaxLen = 512;  // longest Jacobi vector of a batched tSVDQ face
