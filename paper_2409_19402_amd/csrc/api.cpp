@@ -117,7 +117,12 @@ constexpr int kMaxSweepsCap = 100;
 // of the truncation drops the coupling of a kept and a discarded pair
 constexpr double kDefaultGapTol = 1e-8;
 
-int ksplit_for(int64_t K) { return (int)std::clamp<int64_t>(K / 512, 1, 1024); }
+// split-K slices of a reduction over K: 512 of K per slice, 256 when the
+// product has at most 32 rows (the dQ products, M = p, on the narrow GEMM
+// tile: twice the workgroups for the same partial-sum traffic per row)
+int ksplit_for(int64_t K, int64_t M = 64) {
+  return (int)std::clamp<int64_t>(K / (M <= 32 ? 256 : 512), 1, 1024);
+}
 
 // bytes of the transform and Jacobi buffers (take_sweep_bufs takes them in
 // this order)
@@ -395,7 +400,7 @@ size_t pq_qprod_backward_workspace(int64_t n1, int64_t m, int64_t n2, int64_t n3
   size_t bytes = align_up(e * n1 * m * p) + align_up(e * m * n2 * p)   // Ah, Bh
                  + align_up(e * n1 * n2 * p) + align_up(e * n1 * n2 * p)  // Ch, dCh
                  + align_up(e * n1 * m * p) + align_up(e * m * n2 * p);   // dAh, dBh
-  const int parts = ksplit_for(n1 * n2) + ksplit_for(n1 * m) + ksplit_for(m * n2);
+  const int parts = ksplit_for(n1 * n2, p) + ksplit_for(n1 * m, p) + ksplit_for(m * n2, p);
   bytes += align_up(e * (size_t)parts * p * n3);
   return bytes;
 }
@@ -426,7 +431,7 @@ int pq_qprod_backward(const void* G, const void* A, const void* B, const void* Q
   void* dCh = ar.take(e * n1 * n2 * p);
   void* dAh = ar.take(e * n1 * m * p);
   void* dBh = ar.take(e * m * n2 * p);
-  const int ks1 = ksplit_for(n1 * n2), ks2 = ksplit_for(n1 * m), ks3 = ksplit_for(m * n2);
+  const int ks1 = ksplit_for(n1 * n2, p), ks2 = ksplit_for(n1 * m, p), ks3 = ksplit_for(m * n2, p);
   void* parts = ar.take(e * (size_t)(ks1 + ks2 + ks3) * p * n3);
   const Prec pr = Prec::Default;
   const void* Ah = Ahat;
@@ -471,7 +476,7 @@ int pq_qprod_backward(const void* G, const void* A, const void* B, const void* Q
 
 size_t pq_proj_backward_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int dtype) {
   const size_t e = elem(dtype);
-  const int ks = ksplit_for(n1 * n2);
+  const int ks = ksplit_for(n1 * n2, p);
   return align_up(e * n1 * n2 * p) * 2 + align_up(e * (size_t)2 * ks * p * n3);
 }
 
@@ -492,7 +497,7 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype, int
   Arena ar(ws, ws_bytes);
   void* Ah = ar.take(e * N * p);
   void* Gh = ar.take(e * N * p);
-  const int ks = ksplit_for(N);
+  const int ks = ksplit_for(N, p);
   void* parts = ar.take(e * (size_t)2 * ks * p * n3);
   const Prec pr = Prec::Default;
   PQ_TRY(do_hat(G, dtype, Q, Gh, N, (int)n3, (int)p, pr, stream));
@@ -563,7 +568,7 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
   if (!f64)
     PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, u3_sweeps, kGramTolFloor, used, flags, stream));
   else
-    PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, u3_sweeps, kPolishTol, used, flags, stream));
+    PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, u3_sweeps, kPolishTol, used, flags, nullptr, 0, stream));
   {
     PQ_PROF("jacobi_finalize", stream);
     PQ_TRY(pq::jacobi_norms_f64(W, 1, in3, in3, sig, nullptr, stream));
@@ -627,13 +632,22 @@ SweepBufs take_sweep_bufs(Arena& ar, bool f64, int64_t N, int64_t p) {
 // Step 2 of Alg. 4.1 and the Jacobi sweeps of step 3: b.Ah = A x_3 Q^T and
 // b.W64 = the converged vectors of every face (the shorter side's: columns
 // of each face when n1 >= n2, rows otherwise); sweep statistics to info_dev.
+// wide: float32 data (a_dtype PQ_F32) factorised in float64 as if widened
+// (Q is then float64, and so is the transform)
 int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p, Prec pr,
-             double tol, int max_sweeps, const SweepBufs& b, int* info_dev, hipStream_t stream) {
-  const bool f64 = a_dtype == PQ_F64;
+             double tol, int max_sweeps, const SweepBufs& b, int* info_dev, hipStream_t stream,
+             bool wide = false) {
+  const bool f64 = a_dtype == PQ_F64 || wide;
   const int64_t N = n1 * n2;
   const int in1 = (int)n1, in2 = (int)n2, ip = (int)p;
   const int nv = (int)std::min(n1, n2), L = (int)std::max(n1, n2);
-  PQ_TRY(do_hat(A, a_dtype, Q, b.Ah, N, (int)n3, ip, pr, stream));
+  if (wide) {
+    PQ_PROF("hat", stream);
+    PQ_TRY(pq::hat_f64_wide(static_cast<const float*>(A), static_cast<const double*>(Q),
+                            static_cast<double*>(b.Ah), N, (int)n3, ip, stream));
+  } else {
+    PQ_TRY(do_hat(A, a_dtype, Q, b.Ah, N, (int)n3, ip, pr, stream));
+  }
   if (f64) {
     PQ_PROF("jacobi_prep", stream);
     PQ_TRY(pq::jacobi_prep_f64(static_cast<const double*>(b.Ah), b.W64, in1, in2, ip, stream));
@@ -648,15 +662,16 @@ int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
     PQ_TRY(pq::jacobi_widen(b.W32, b.W64, N * p, stream));
   }
   // float64 sweeps to tol (each launch profiled inside)
-  // float64 data: Gram-form sweeps to max(tol, 1e-10), then vector-form
-  // sweeps (dot products from the vectors themselves) to tol; float32 data:
+  // float64 data: Gram-form sweeps to tol (the stopping test is evaluated on
+  // G freshly formed from the vectors, as accurate as their dot products),
+  // then vector-form sweeps (rotation angles from the vectors themselves) to
+  // tol for the faces the Gram form left unconverged; float32 data:
   // Gram-form float64 sweeps to max(tol, 1e-10)
   const int max1 = f64 ? std::min(max_sweeps, kGramSweeps64) : max_sweeps;
   const int max2 = std::min(max_sweeps, kPolishSweeps);
   if (f64) {
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max1, std::max(tol, kGramTolFloor), b.used1, b.flags,
-                                      stream));
-    PQ_TRY(pq::jacobi_sweeps_f64(b.W64, ip, nv, L, max2, tol, b.used2, b.flags, stream));
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max1, tol, b.used1, b.flags, stream));
+    PQ_TRY(pq::jacobi_sweeps_f64(b.W64, ip, nv, L, max2, tol, b.used2, b.flags, b.used1, max1, stream));
   } else {
     PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max2, std::max(tol, kGramTolFloor), b.used2, b.flags,
                                       stream));
@@ -799,8 +814,8 @@ size_t pq_tsvdq_backward_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p
   const bool f64 = a_dtype == PQ_F64;
   const size_t e = elem(f64 ? PQ_F64 : PQ_F32);
   const int64_t N = n1 * n2, L = std::max(n1, n2), S = std::min(n1, n2);
-  const int ks = ksplit_for(N);
-  return (f64 ? 0 : align_up(8 * N * n3) * 2 + align_up(8 * n3 * p) + align_up(8 * k * p))  // widened inputs
+  const int ks = ksplit_for(N, p);
+  return (f64 ? 0 : align_up(8 * n3 * p) + align_up(8 * k * p))  // widened Q and sbar
          + sweep_bytes(true, N, p)                  // transform and Jacobi buffers (float64)
          + align_up(8 * S * p) * 2                  // norms, sorted singular values
          + align_up(8 * L * S * p)                  // every normalised Jacobi vector
@@ -836,7 +851,7 @@ int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q, int64_t n1, int
   const int64_t N = n1 * n2;
   const int L = (int)std::max(n1, n2), S = (int)std::min(n1, n2);
   const int ip = (int)p, ik = (int)k, in3 = (int)n3;
-  const int ks = ksplit_for(N);
+  const int ks = ksplit_for(N, p);
   const bool cols = n1 >= n2;
   const bool has_g = Gbar != nullptr;
   const Prec pr = Prec::Default;
@@ -844,26 +859,19 @@ int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q, int64_t n1, int
   // The adjoint's coefficients divide by the gaps of the face spectra, so
   // float32 arithmetic anywhere from the data to the face gradient (the
   // transforms included) would leave errors of about 1e-7 / (relative gap).
-  // float32 data are exact in float64: they are widened, and everything up
-  // to the face gradient runs in float64; the two transforms back (dA, dQ),
-  // where no gap enters any more, run in the data's type.
-  const double* A64 = static_cast<const double*>(A);
+  // float32 data are exact in float64: they are widened (A and Gbar inside
+  // the float64 transform, Q and sbar here), and everything up to the face
+  // gradient runs in float64; the two transforms back (dA, dQ), where no gap
+  // enters any more, run in the data's type.
   const double* Q64 = static_cast<const double*>(Q);
-  const double* G64 = static_cast<const double*>(Gbar);
   const double* s64 = static_cast<const double*>(sbar);
   if (!f64) {
-    double* a64 = static_cast<double*>(ar.take(8 * N * n3));
-    double* g64 = static_cast<double*>(ar.take(8 * N * n3));
     double* q64 = static_cast<double*>(ar.take(8 * n3 * p));
     double* sb64 = static_cast<double*>(ar.take(8 * k * p));
     PQ_PROF("grad_elementwise", stream);
-    PQ_TRY(pq::jacobi_widen(static_cast<const float*>(A), a64, N * n3, stream));
     PQ_TRY(pq::jacobi_widen(static_cast<const float*>(Q), q64, n3 * p, stream));
-    if (has_g) PQ_TRY(pq::jacobi_widen(static_cast<const float*>(Gbar), g64, N * n3, stream));
     if (sbar) PQ_TRY(pq::jacobi_widen(static_cast<const float*>(sbar), sb64, k * p, stream));
-    A64 = a64;
     Q64 = q64;
-    G64 = has_g ? g64 : nullptr;
     s64 = sbar ? sb64 : nullptr;
   }
   const SweepBufs b = take_sweep_bufs(ar, true, N, p);
@@ -891,7 +899,7 @@ int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q, int64_t n1, int
   const int64_t sU = (int64_t)L * S, sY = (int64_t)S * S, sK = (int64_t)S * k, sR = (int64_t)L * k;
   // the forward factorisation in float64: every singular vector of the
   // Jacobi side
-  PQ_CHECK(converge(A64, PQ_F64, Q64, n1, n2, n3, p, pr, tol, max_sweeps, b, info_dev, stream));
+  PQ_CHECK(converge(A, dt, Q64, n1, n2, n3, p, pr, tol, max_sweeps, b, info_dev, stream, !f64));
   {
     PQ_PROF("jacobi_finalize", stream);
     PQ_TRY(pq::jacobi_norms_f64(b.W64, ip, S, L, sig, nullptr, stream));
@@ -904,7 +912,12 @@ int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q, int64_t n1, int
   PQ_TRY(do_gemm("grad_gemm", face_gemm(cols, false, S, S, L, M, n1, N, U, L, sU, Yall, S, sY, ip), PQ_F64, pr,
                  stream));
   if (has_g) {
-    PQ_TRY(do_hat(G64, PQ_F64, Q64, Gh, N, in3, ip, pr, stream));
+    if (f64) {
+      PQ_TRY(do_hat(Gbar, PQ_F64, Q64, Gh, N, in3, ip, pr, stream));
+    } else {
+      PQ_PROF("hat", stream);
+      PQ_TRY(pq::hat_f64_wide(static_cast<const float*>(Gbar), Q64, Gh, N, in3, ip, stream));
+    }
     // H = G_t^T U_K;  Ra = G_t Y;  Ba = U^T Ra;  Bb = Yall^T H
     PQ_TRY(do_gemm("grad_gemm", face_gemm(cols, false, S, ik, L, Gh, n1, N, U, L, sU, H, S, sK, ip), PQ_F64, pr,
                    stream));

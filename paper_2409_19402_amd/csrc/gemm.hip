@@ -6,6 +6,7 @@
 // float32: a 64x64 output tile per 256-thread workgroup, K tiles of 32 or 128
 // double-buffered in LDS, one 32x32 tile per wave on v_mfma_f32_32x32x2f32.
 // The split-bfloat16 modes use the same pipeline on v_mfma_f32_32x32x16_bf16.
+// float64: 64x64 or 64x16 output tiles on v_mfma_f64_16x16x4f64.
 #include <algorithm>
 
 #include "common.hpp"
@@ -14,30 +15,40 @@
 namespace pq {
 namespace {
 
-constexpr int kTM = 64, kTN = 64, kLd = 68;
+// Output tiles: 64 x 64, or 32 x 128 when the output has at most 32 rows
+// (the dQ products, M = p), both four 32 x 32 wave tiles.
+//
+// LDS floats of one staged K-tile of R rows: k-major ([k][row], row stride
+// R + 4) for an operand that is contiguous along its row index, row-major
+// ([row][k], row stride KT + 4) for one that is contiguous along k, so that
+// both the float4 stores and the MFMA operand reads avoid bank conflicts.
+template <int R, int KT>
+__host__ __device__ constexpr int tile_floats() {
+  return KT * (R + 4) > R * (KT + 4) ? KT * (R + 4) : R * (KT + 4);
+}
 
-// One K-tile of KT rows: the 64 x KT block of A (as As[k][m]) or the KT x 64
-// block of B (as Bs[k][n]), KT / 4 elements per thread, fetched into
-// registers.  VEC = 4 reads float4 along the operand's contiguous dimension
-// (the host guarantees that dimension, the leading dimension, the strides and
-// the base are multiples of 4), VEC = 1 reads scalars.  Elements outside the
-// matrix or past kend are 0.  CONT_ROW: the contiguous dimension is the
-// tile's row index (m or n) rather than k.
-template <int KT>
+// One K-tile of KT rows: the R x KT block of A or the KT x R block of B,
+// R KT / 256 elements per thread, fetched into registers.  VEC = 4 reads
+// float4 along the operand's contiguous dimension (the host guarantees that
+// dimension, the leading dimension, the strides and the base are multiples
+// of 4), VEC = 1 reads scalars.  Elements outside the matrix or past kend
+// are 0.  CONT_ROW: the contiguous dimension is the tile's row index (m or
+// n) rather than k.
+template <int R, int KT>
 struct TileRegs {
-  float v[KT / 4];
+  float v[R * KT / 256];
 };
 
-template <int KT, int VEC, bool CONT_ROW>
+template <int R, int KT, int VEC, bool CONT_ROW>
 __device__ __forceinline__ void tile_fetch(const float* __restrict__ P, int64_t ld, int r0, int rmax, int k0,
-                                           int kend, TileRegs<KT>& t) {
+                                           int kend, TileRegs<R, KT>& t) {
   const int tid = threadIdx.x;
   if constexpr (VEC == 4) {
 #pragma unroll
-    for (int h = 0; h < KT / 16; ++h) {
+    for (int h = 0; h < R * KT / 1024; ++h) {
       const int idx = tid + 256 * h;
       int r, k;
-      if (CONT_ROW) { k = idx >> 4; r = 4 * (idx & 15); } else { r = idx / (KT / 4); k = 4 * (idx % (KT / 4)); }
+      if (CONT_ROW) { k = idx / (R / 4); r = 4 * (idx % (R / 4)); } else { r = idx / (KT / 4); k = 4 * (idx % (KT / 4)); }
       const int gr = r0 + r, gk = k0 + k;
       const bool ok = gr < rmax && gk < kend;  // whole float4 in or out (sizes are multiples of 4)
       const int cr = ok ? gr : 0, ck = ok ? gk : 0;
@@ -50,10 +61,10 @@ __device__ __forceinline__ void tile_fetch(const float* __restrict__ P, int64_t 
     }
   } else {
 #pragma unroll
-    for (int h = 0; h < KT / 4; ++h) {
+    for (int h = 0; h < R * KT / 256; ++h) {
       const int idx = tid + 256 * h;
       int r, k;
-      if (CONT_ROW) { k = idx >> 6; r = idx & 63; } else { r = idx / KT; k = idx % KT; }
+      if (CONT_ROW) { k = idx / R; r = idx % R; } else { r = idx / KT; k = idx % KT; }
       const int gr = r0 + r, gk = k0 + k;
       const bool ok = gr < rmax && gk < kend;
       const int cr = ok ? gr : 0, ck = ok ? gk : 0;
@@ -63,52 +74,60 @@ __device__ __forceinline__ void tile_fetch(const float* __restrict__ P, int64_t 
   }
 }
 
-template <int KT, int VEC, bool CONT_ROW>
-__device__ __forceinline__ void tile_store(const TileRegs<KT>& t, float* S) {  // S: KT x kLd
+// S: the tile in the layout tile_floats describes (CONT_ROW: [k][row])
+template <int R, int KT, int VEC, bool CONT_ROW>
+__device__ __forceinline__ void tile_store(const TileRegs<R, KT>& t, float* S) {
+  constexpr int ldr = R + 4, ldk = KT + 4;
   const int tid = threadIdx.x;
   if constexpr (VEC == 4) {
 #pragma unroll
-    for (int h = 0; h < KT / 16; ++h) {
+    for (int h = 0; h < R * KT / 1024; ++h) {
       const int idx = tid + 256 * h;
+      const float4 x = make_float4(t.v[4 * h], t.v[4 * h + 1], t.v[4 * h + 2], t.v[4 * h + 3]);
       if (CONT_ROW) {
-        const int k = idx >> 4, r = 4 * (idx & 15);
-        *reinterpret_cast<float4*>(S + k * kLd + r) =
-            make_float4(t.v[4 * h], t.v[4 * h + 1], t.v[4 * h + 2], t.v[4 * h + 3]);
+        *reinterpret_cast<float4*>(S + (idx / (R / 4)) * ldr + 4 * (idx % (R / 4))) = x;
       } else {
-        const int r = idx / (KT / 4), k = 4 * (idx % (KT / 4));
-#pragma unroll
-        for (int i = 0; i < 4; ++i) S[(k + i) * kLd + r] = t.v[4 * h + i];
+        *reinterpret_cast<float4*>(S + (idx / (KT / 4)) * ldk + 4 * (idx % (KT / 4))) = x;
       }
     }
   } else {
 #pragma unroll
-    for (int h = 0; h < KT / 4; ++h) {
+    for (int h = 0; h < R * KT / 256; ++h) {
       const int idx = tid + 256 * h;
-      int r, k;
-      if (CONT_ROW) { k = idx >> 6; r = idx & 63; } else { r = idx / KT; k = idx % KT; }
-      S[k * kLd + r] = t.v[h];
+      if (CONT_ROW) {
+        S[(idx / R) * ldr + idx % R] = t.v[h];
+      } else {
+        S[(idx / KT) * ldk + idx % KT] = t.v[h];
+      }
     }
   }
 }
 
-// C tile (64 x 64) = A (64 x K) B (K x 64) over K-tiles of KT, double
-// buffered in LDS (dynamic: 4 KT kLd floats): the next tile's global loads
-// are in flight while the MFMAs of the current one run.  The MFMA computes
-// the transposed tile (rows = output columns), so the 32 lanes sharing an
-// accumulator register hold 32 consecutive rows of the column-major output
-// and stores coalesce.
-template <bool TA, bool TB, int VA, int VB, int KT>
+// C tile (TM x TN) = A (TM x K) B (K x TN) over K-tiles of KT, double
+// buffered in LDS (dynamic: 2 (tile_floats<TM, KT>() + tile_floats<TN, KT>())
+// floats): the next tile's global loads are in flight while the MFMAs of the
+// current one run.  The MFMA computes the transposed tile (rows = output
+// columns), so the 32 lanes sharing an accumulator register hold 32
+// consecutive rows of the column-major output and stores coalesce.  MFMA
+// step j of a K-tile takes k = j in lanes 0-31 and k = KT/2 + j in lanes
+// 32-63, so that a lane's k are consecutive and a row-major operand is read
+// four steps at a time.
+template <bool TA, bool TB, int VA, int VB, int KT, int TM>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk) {
+  constexpr int TN = 4096 / TM;
+  constexpr int WM = TM / 32;  // wave grid WM x (4 / WM)
   extern __shared__ __align__(16) float gsm[];
-  // buffers: A at gsm + b * KT * kLd, B at gsm + (2 + b) * KT * kLd
-  auto As = [&](int b) { return gsm + b * KT * kLd; };
-  auto Bs = [&](int b) { return gsm + (2 + b) * KT * kLd; };
+  constexpr int FA = tile_floats<TM, KT>(), FB = tile_floats<TN, KT>();
+  constexpr int H = KT / 2, ldk = KT + 4;
+  // buffers: A at gsm + b FA, B at gsm + 2 FA + b FB
+  auto As = [&](int b) { return gsm + b * FA; };
+  auto Bs = [&](int b) { return gsm + 2 * FA + b * FB; };
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int nl = lane & 31, kh = lane >> 5;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WM, wn = wave / WM;
   const int zb = blockIdx.z % g.batch, zs = blockIdx.z / g.batch;
-  const int m0 = blockIdx.x * kTM, n0 = blockIdx.y * kTN;
+  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
   const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
   const float* A = static_cast<const float*>(g.A) + (int64_t)zb * g.sA;
   const float* B = static_cast<const float*>(g.B) + (int64_t)zb * g.sB;
@@ -118,32 +137,51 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk) {
   for (int j = 0; j < 16; ++j) acc[j] = 0.f;
   // A(m, k) is contiguous in m unless transposed; B(k, n) is contiguous in k
   // unless transposed
-  TileRegs<KT> ra, rb;
+  TileRegs<TM, KT> ra;
+  TileRegs<TN, KT> rb;
   int k0 = kbeg;
   if (k0 < kend) {
-    tile_fetch<KT, VA, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
-    tile_fetch<KT, VB, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
-    tile_store<KT, VA, !TA>(ra, As(0));
-    tile_store<KT, VB, TB>(rb, Bs(0));
+    tile_fetch<TM, KT, VA, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
+    tile_fetch<TN, KT, VB, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
+    tile_store<TM, KT, VA, !TA>(ra, As(0));
+    tile_store<TN, KT, VB, TB>(rb, Bs(0));
   }
   __syncthreads();
   int buf = 0;
   for (; k0 < kend; k0 += KT) {
     const bool more = k0 + KT < kend;
     if (more) {
-      tile_fetch<KT, VA, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
-      tile_fetch<KT, VB, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
+      tile_fetch<TM, KT, VA, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
+      tile_fetch<TN, KT, VB, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
     }
     // the whole tile, unrolled (rows past kend were staged as zeros), so the
-    // LDS reads run ahead of the MFMAs
-    const float* as = As(buf) + kh * kLd + wm * 32 + nl;  // columns of the transposed tile: output rows
-    const float* bs = Bs(buf) + kh * kLd + wn * 32 + nl;  // rows of the transposed tile: output columns
-#pragma unroll 16
-    for (int kk = 0; kk < KT; kk += 2)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(bs[kk * kLd], as[kk * kLd], acc, 0, 0, 0);
+    // LDS reads run ahead of the MFMAs; A's rows are the output rows (the
+    // columns of the transposed tile), B's the output columns
+    const float* as = !TA ? As(buf) + kh * H * (TM + 4) + wm * 32 + nl : As(buf) + (wm * 32 + nl) * ldk + kh * H;
+    const float* bs = TB ? Bs(buf) + kh * H * (TN + 4) + wn * 32 + nl : Bs(buf) + (wn * 32 + nl) * ldk + kh * H;
+#pragma unroll
+    for (int q = 0; q < H; q += 4) {
+      float a[4], b[4];
+      if constexpr (!TA) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = as[(q + i) * (TM + 4)];
+      } else {
+        const float4 v = *reinterpret_cast<const float4*>(as + q);
+        a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+      }
+      if constexpr (TB) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[i] = bs[(q + i) * (TN + 4)];
+      } else {
+        const float4 v = *reinterpret_cast<const float4*>(bs + q);
+        b[0] = v.x; b[1] = v.y; b[2] = v.z; b[3] = v.w;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b[i], a[i], acc, 0, 0, 0);
+    }
     if (more) {
-      tile_store<KT, VA, !TA>(ra, As(buf ^ 1));
-      tile_store<KT, VB, TB>(rb, Bs(buf ^ 1));
+      tile_store<TM, KT, VA, !TA>(ra, As(buf ^ 1));
+      tile_store<TN, KT, VB, TB>(rb, Bs(buf ^ 1));
     }
     __syncthreads();
     buf ^= 1;
@@ -167,7 +205,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk) {
 constexpr int kPad16 = 8;  // bfloat16 elements of padding per LDS row
 
 template <int KT, int VEC, bool CONT_ROW, int NP>
-__device__ __forceinline__ void tile_store_split(const TileRegs<KT>& t, uint16_t* S) {
+__device__ __forceinline__ void tile_store_split(const TileRegs<64, KT>& t, uint16_t* S) {
   // S: NP parts, each 64 rows x (KT + kPad16) bfloat16
   constexpr int ld = KT + kPad16;
   constexpr int part = 64 * ld;
@@ -221,7 +259,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Gemm g, int kchunk) {
   const int nl = lane & 31, kh = lane >> 5;
   const int wm = wave & 1, wn = wave >> 1;
   const int zb = blockIdx.z % g.batch, zs = blockIdx.z / g.batch;
-  const int m0 = blockIdx.x * kTM, n0 = blockIdx.y * kTN;
+  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
   const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
   const float* A = static_cast<const float*>(g.A) + (int64_t)zb * g.sA;
   const float* B = static_cast<const float*>(g.B) + (int64_t)zb * g.sB;
@@ -229,11 +267,11 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Gemm g, int kchunk) {
   f32x16 acc;
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-  TileRegs<KT> ra, rb;
+  TileRegs<64, KT> ra, rb;
   int k0 = kbeg;
   if (k0 < kend) {
-    tile_fetch<KT, VA, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
-    tile_fetch<KT, VB, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
+    tile_fetch<64, KT, VA, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
+    tile_fetch<64, KT, VB, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
     tile_store_split<KT, VA, !TA, NP>(ra, Ap(0));
     tile_store_split<KT, VB, TB, NP>(rb, Bp(0));
   }
@@ -242,8 +280,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Gemm g, int kchunk) {
   for (; k0 < kend; k0 += KT) {
     const bool more = k0 + KT < kend;
     if (more) {
-      tile_fetch<KT, VA, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
-      tile_fetch<KT, VB, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
+      tile_fetch<64, KT, VA, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
+      tile_fetch<64, KT, VB, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
     }
     // rows of the transposed tile are output columns (B's n), its columns
     // output rows (A's m)
@@ -277,34 +315,156 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Gemm g, int kchunk) {
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void gemm_generic_kernel(Gemm g, int kchunk) {
-  const int zb = blockIdx.z % g.batch, zs = blockIdx.z / g.batch;
-  const int m = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int n = blockIdx.y * 16 + (threadIdx.x >> 4);
-  if (m >= g.M || n >= g.N) return;
-  const T* A = static_cast<const T*>(g.A) + (int64_t)zb * g.sA;
-  const T* B = static_cast<const T*>(g.B) + (int64_t)zb * g.sB;
-  T* C = static_cast<T*>(g.C) + (int64_t)zb * g.sC + (int64_t)zs * g.sSplit;
-  const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
-  T acc = T(0);
-  for (int k = kbeg; k < kend; ++k) {
-    const T a = g.ta ? A[k + (int64_t)m * g.lda] : A[m + (int64_t)k * g.lda];
-    const T b = g.tb ? B[n + (int64_t)k * g.ldb] : B[k + (int64_t)n * g.ldb];
-    acc = fma(a, b, acc);
+// ---- float64 GEMM -------------------------------------------------------------
+// A 64 x TN output tile (TN = 64, or 16 for outputs of at most 16 columns) per
+// 256-thread workgroup on v_mfma_f64_16x16x4f64, K-tiles of 16 double
+// buffered in LDS.  Both operands are staged k-major ([k][row], row stride
+// R + 1 doubles: the odd stride keeps the transposing stores of a
+// k-contiguous operand and the MFMA reads free of bank conflicts).  The MFMA
+// takes B's columns as its first operand, so lane l holds output rows
+// m = 16 i + l mod 16 and stores coalesce along the column-major output.
+constexpr int kKT64 = 16;
+
+template <int R>
+struct Tile64 {
+  double v[R * kKT64 / 256];
+};
+
+// elements (r, k) of an R x 16 operand tile, zero outside the matrix or past
+// kend; CONT_ROW: the operand is contiguous along r
+template <int R, bool CONT_ROW>
+__device__ __forceinline__ void tile64_fetch(const double* __restrict__ P, int64_t ld, int r0, int rmax, int k0,
+                                             int kend, Tile64<R>& t) {
+#pragma unroll
+  for (int h = 0; h < R * kKT64 / 256; ++h) {
+    const int idx = threadIdx.x + 256 * h;
+    const int r = CONT_ROW ? idx % R : idx / kKT64, k = CONT_ROW ? idx / R : idx % kKT64;
+    const int gr = r0 + r, gk = k0 + k;
+    const bool ok = gr < rmax && gk < kend;
+    const int cr = ok ? gr : 0, ck = ok ? gk : 0;
+    const double x = CONT_ROW ? P[cr + (int64_t)ck * ld] : P[ck + (int64_t)cr * ld];
+    t.v[h] = ok ? x : 0.0;
   }
-  C[m + (int64_t)n * g.ldc] = acc;
 }
 
+template <int R, bool CONT_ROW>
+__device__ __forceinline__ void tile64_store(const Tile64<R>& t, double* S) {
+#pragma unroll
+  for (int h = 0; h < R * kKT64 / 256; ++h) {
+    const int idx = threadIdx.x + 256 * h;
+    const int r = CONT_ROW ? idx % R : idx / kKT64, k = CONT_ROW ? idx / R : idx % kKT64;
+    S[k * (R + 1) + r] = t.v[h];
+  }
+}
+
+template <bool TA, bool TB, int TN>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g, int kchunk) {
+  constexpr int TM = 64, KT = kKT64;
+  constexpr int WN = TN >= 32 ? 2 : 1, WM = 4 / WN;  // wave grid
+  constexpr int SM = TM / 16 / WM, SN = TN / 16 / WN;  // 16 x 16 blocks per wave
+  static_assert(SM >= 1 && SN >= 1, "tile shape");
+  __shared__ double As[2][KT * (TM + 1)];
+  __shared__ double Bs[2][KT * (TN + 1)];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int wm = wave % WM, wn = wave / WM;
+  const int zb = blockIdx.z % g.batch, zs = blockIdx.z / g.batch;
+  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+  const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
+  const double* A = static_cast<const double*>(g.A) + (int64_t)zb * g.sA;
+  const double* B = static_cast<const double*>(g.B) + (int64_t)zb * g.sB;
+  double* C = static_cast<double*>(g.C) + (int64_t)zb * g.sC + (int64_t)zs * g.sSplit;
+  f64x4 acc[SM][SN];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // A(m, k) is contiguous in m unless transposed; B(k, n) is contiguous in k
+  // unless transposed
+  Tile64<TM> ra;
+  Tile64<TN> rb;
+  int k0 = kbeg;
+  if (k0 < kend) {
+    tile64_fetch<TM, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
+    tile64_fetch<TN, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
+    tile64_store<TM, !TA>(ra, As[0]);
+    tile64_store<TN, TB>(rb, Bs[0]);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (; k0 < kend; k0 += KT) {
+    const bool more = k0 + KT < kend;
+    if (more) {
+      tile64_fetch<TM, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
+      tile64_fetch<TN, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < KT; s4 += 4) {
+      double a[SM], b[SN];
+#pragma unroll
+      for (int i = 0; i < SM; ++i) a[i] = As[buf][(s4 + kq) * (TM + 1) + (wm * SM + i) * 16 + l16];
+#pragma unroll
+      for (int j = 0; j < SN; ++j) b[j] = Bs[buf][(s4 + kq) * (TN + 1) + (wn * SN + j) * 16 + l16];
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      tile64_store<TM, !TA>(ra, As[buf ^ 1]);
+      tile64_store<TN, TB>(rb, Bs[buf ^ 1]);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  // lane l, value v of block (i, j): row m = 16 (wm SM + i) + l mod 16,
+  // column n = 16 (wn SN + j) + l / 16 + 4 v
+#pragma unroll
+  for (int i = 0; i < SM; ++i) {
+    const int gm = m0 + (wm * SM + i) * 16 + l16;
+    if (gm >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < SN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gn = n0 + (wn * SN + j) * 16 + kq + 4 * v;
+        if (gn < g.N) C[gm + (int64_t)gn * g.ldc] = acc[i][j][v];
+      }
+  }
+}
+
+// out[e] = sum over z of parts[z * stride + e]; 64 consecutive outputs per
+// workgroup of 16 waves.  Wave w sums the slices z = w (mod 16) of its lane's
+// output in four independent chains (z = w + 16 c (mod 64), c = 0..3), and
+// the 16 wave sums are added in wave order: a fixed order for every call.
+constexpr int kSumWaves = 16;
+
 template <typename T>
-__global__ __launch_bounds__(256) void sum_partials_kernel(const T* __restrict__ parts, int nparts,
-                                                           int64_t stride, int64_t count,
-                                                           T* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= count) return;
-  T acc = T(0);
-  for (int z = 0; z < nparts; ++z) acc += parts[(int64_t)z * stride + e];
-  out[e] = acc;
+__global__ __launch_bounds__(64 * kSumWaves) void sum_partials_kernel(const T* __restrict__ parts, int nparts,
+                                                                      int64_t stride, int64_t count,
+                                                                      T* __restrict__ out) {
+  __shared__ T red[kSumWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  if (e < count) {
+    int z = w;
+    for (; z + 3 * kSumWaves < nparts; z += 4 * kSumWaves) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] += parts[(int64_t)(z + c * kSumWaves) * stride + e];
+    }
+    // at most three slices remain (z + 48 >= nparts)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (z + c * kSumWaves < nparts) acc[c] += parts[(int64_t)(z + c * kSumWaves) * stride + e];
+  }
+  red[w][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (w == 0 && e < count) {
+    T t = red[0][lane];
+    for (int i = 1; i < kSumWaves; ++i) t += red[i][lane];
+    out[e] = t;
+  }
 }
 
 int chunk_for(const Gemm& g, int align) {
@@ -323,63 +483,68 @@ bool vec4_ok(const void* P, int64_t cont, int64_t ld, int64_t stride) {
   return reinterpret_cast<uintptr_t>(P) % 16 == 0 && cont % 4 == 0 && ld % 4 == 0 && stride % 4 == 0;
 }
 
-template <bool TA, bool TB, int VA, int VB, int KT>
-hipError_t gemm_f32_go(const Gemm& g, int kchunk, dim3 grid, hipStream_t s) {
-  const size_t lds = sizeof(float) * 4 * KT * kLd;
-  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_f32_kernel<TA, TB, VA, VB, KT>),
+template <bool TA, bool TB, int VA, int VB, int KT, int TM>
+hipError_t gemm_f32_go(const Gemm& g, int kchunk, hipStream_t s) {
+  constexpr int TN = 4096 / TM;
+  const size_t lds = sizeof(float) * 2 * (tile_floats<TM, KT>() + tile_floats<TN, KT>());
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_f32_kernel<TA, TB, VA, VB, KT, TM>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
-  gemm_f32_kernel<TA, TB, VA, VB, KT><<<grid, 256, lds, s>>>(g, kchunk);
+  const dim3 grid((unsigned)((g.M + TM - 1) / TM), (unsigned)((g.N + TN - 1) / TN),
+                  (unsigned)(g.batch * std::max(1, g.ksplit)));
+  gemm_f32_kernel<TA, TB, VA, VB, KT, TM><<<grid, 256, lds, s>>>(g, kchunk);
   return hipGetLastError();
 }
 
-template <bool TA, bool TB, int KT>
-hipError_t gemm_f32_launch(const Gemm& g, int kchunk, dim3 grid, hipStream_t s) {
+template <bool TA, bool TB, int KT, int TM>
+hipError_t gemm_f32_launch(const Gemm& g, int kchunk, hipStream_t s) {
   // contiguous dimension: A's is M (K when transposed), B's is K (N when transposed)
   const bool va = vec4_ok(g.A, TA ? g.K : g.M, g.lda, g.sA) && (!TA || kchunk % 4 == 0);
   const bool vb = vec4_ok(g.B, TB ? g.N : g.K, g.ldb, g.sB) && (TB || kchunk % 4 == 0);
-  if (va && vb) return gemm_f32_go<TA, TB, 4, 4, KT>(g, kchunk, grid, s);
-  if (va) return gemm_f32_go<TA, TB, 4, 1, KT>(g, kchunk, grid, s);
-  if (vb) return gemm_f32_go<TA, TB, 1, 4, KT>(g, kchunk, grid, s);
-  return gemm_f32_go<TA, TB, 1, 1, KT>(g, kchunk, grid, s);
+  if (va && vb) return gemm_f32_go<TA, TB, 4, 4, KT, TM>(g, kchunk, s);
+  if (va) return gemm_f32_go<TA, TB, 4, 1, KT, TM>(g, kchunk, s);
+  if (vb) return gemm_f32_go<TA, TB, 1, 4, KT, TM>(g, kchunk, s);
+  return gemm_f32_go<TA, TB, 1, 1, KT, TM>(g, kchunk, s);
 }
 
 template <bool TA, bool TB, int VA, int VB, int KT, int NP>
-hipError_t gemm_bf16_go(const Gemm& g, int kchunk, dim3 grid, hipStream_t s) {
+hipError_t gemm_bf16_go(const Gemm& g, int kchunk, hipStream_t s) {
   const size_t lds = sizeof(uint16_t) * 4 * NP * 64 * (KT + kPad16);
   static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_bf16_kernel<TA, TB, VA, VB, KT, NP>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
+  const dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64),
+                  (unsigned)(g.batch * std::max(1, g.ksplit)));
   gemm_bf16_kernel<TA, TB, VA, VB, KT, NP><<<grid, 256, lds, s>>>(g, kchunk);
   return hipGetLastError();
 }
 
 template <bool TA, bool TB, int KT, int NP>
-hipError_t gemm_bf16_launch(const Gemm& g, int kchunk, dim3 grid, hipStream_t s) {
+hipError_t gemm_bf16_launch(const Gemm& g, int kchunk, hipStream_t s) {
   const bool va = vec4_ok(g.A, TA ? g.K : g.M, g.lda, g.sA) && (!TA || kchunk % 4 == 0);
   const bool vb = vec4_ok(g.B, TB ? g.N : g.K, g.ldb, g.sB) && (TB || kchunk % 4 == 0);
-  if (va && vb) return gemm_bf16_go<TA, TB, 4, 4, KT, NP>(g, kchunk, grid, s);
-  if (va) return gemm_bf16_go<TA, TB, 4, 1, KT, NP>(g, kchunk, grid, s);
-  if (vb) return gemm_bf16_go<TA, TB, 1, 4, KT, NP>(g, kchunk, grid, s);
-  return gemm_bf16_go<TA, TB, 1, 1, KT, NP>(g, kchunk, grid, s);
+  if (va && vb) return gemm_bf16_go<TA, TB, 4, 4, KT, NP>(g, kchunk, s);
+  if (va) return gemm_bf16_go<TA, TB, 4, 1, KT, NP>(g, kchunk, s);
+  if (vb) return gemm_bf16_go<TA, TB, 1, 4, KT, NP>(g, kchunk, s);
+  return gemm_bf16_go<TA, TB, 1, 1, KT, NP>(g, kchunk, s);
 }
 
 template <bool TA, bool TB>
-hipError_t gemm_launch(const Gemm& g, Prec prec, int kchunk, dim3 grid, hipStream_t s) {
+hipError_t gemm_launch(const Gemm& g, Prec prec, int kchunk, hipStream_t s) {
   const bool deep = kchunk >= 96;
   switch (prec) {
     case Prec::BF16:
-      return deep ? gemm_bf16_launch<TA, TB, 128, 1>(g, kchunk, grid, s)
-                  : gemm_bf16_launch<TA, TB, 32, 1>(g, kchunk, grid, s);
+      return deep ? gemm_bf16_launch<TA, TB, 128, 1>(g, kchunk, s) : gemm_bf16_launch<TA, TB, 32, 1>(g, kchunk, s);
     case Prec::BF16x3:
-      return deep ? gemm_bf16_launch<TA, TB, 128, 2>(g, kchunk, grid, s)
-                  : gemm_bf16_launch<TA, TB, 32, 2>(g, kchunk, grid, s);
+      return deep ? gemm_bf16_launch<TA, TB, 128, 2>(g, kchunk, s) : gemm_bf16_launch<TA, TB, 32, 2>(g, kchunk, s);
     case Prec::BF16x6:
-      return deep ? gemm_bf16_launch<TA, TB, 64, 3>(g, kchunk, grid, s)
-                  : gemm_bf16_launch<TA, TB, 32, 3>(g, kchunk, grid, s);
+      return deep ? gemm_bf16_launch<TA, TB, 64, 3>(g, kchunk, s) : gemm_bf16_launch<TA, TB, 32, 3>(g, kchunk, s);
     default:
-      return deep ? gemm_f32_launch<TA, TB, 128>(g, kchunk, grid, s)
-                  : gemm_f32_launch<TA, TB, 32>(g, kchunk, grid, s);
+      // outputs of at most 32 rows and more than 64 columns (the dQ
+      // products) take the 32 x 128 tile, whose deep K-tile is 64 (LDS)
+      if (g.M <= 32 && g.N > 64)
+        return deep ? gemm_f32_launch<TA, TB, 64, 32>(g, kchunk, s) : gemm_f32_launch<TA, TB, 32, 32>(g, kchunk, s);
+      return deep ? gemm_f32_launch<TA, TB, 128, 64>(g, kchunk, s) : gemm_f32_launch<TA, TB, 32, 64>(g, kchunk, s);
   }
 }
 
@@ -387,32 +552,42 @@ hipError_t gemm_f32(const Gemm& g, Prec prec, hipStream_t s) {
   // deep K-tiles (one global round trip covers up to 128 of K) when a
   // workgroup has that much K
   const int kchunk = chunk_for(g, 32);
-  dim3 grid((unsigned)((g.M + kTM - 1) / kTM), (unsigned)((g.N + kTN - 1) / kTN),
-            (unsigned)(g.batch * std::max(1, g.ksplit)));
-  if (!g.ta && !g.tb) return gemm_launch<false, false>(g, prec, kchunk, grid, s);
-  if (!g.ta && g.tb) return gemm_launch<false, true>(g, prec, kchunk, grid, s);
-  if (g.ta && !g.tb) return gemm_launch<true, false>(g, prec, kchunk, grid, s);
-  return gemm_launch<true, true>(g, prec, kchunk, grid, s);
+  if (!g.ta && !g.tb) return gemm_launch<false, false>(g, prec, kchunk, s);
+  if (!g.ta && g.tb) return gemm_launch<false, true>(g, prec, kchunk, s);
+  if (g.ta && !g.tb) return gemm_launch<true, false>(g, prec, kchunk, s);
+  return gemm_launch<true, true>(g, prec, kchunk, s);
+}
+
+template <bool TA, bool TB>
+hipError_t gemm_f64_go(const Gemm& g, int kchunk, hipStream_t s) {
+  const unsigned gz = (unsigned)(g.batch * std::max(1, g.ksplit));
+  if (g.N <= 16) {
+    gemm_f64_kernel<TA, TB, 16><<<dim3((unsigned)((g.M + 63) / 64), 1, gz), 256, 0, s>>>(g, kchunk);
+  } else {
+    gemm_f64_kernel<TA, TB, 64><<<dim3((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64), gz), 256, 0, s>>>(
+        g, kchunk);
+  }
+  return hipGetLastError();
 }
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
-  const int kchunk = chunk_for(g, 1);
-  dim3 grid((unsigned)((g.M + 15) / 16), (unsigned)((g.N + 15) / 16),
-            (unsigned)(g.batch * std::max(1, g.ksplit)));
-  gemm_generic_kernel<double><<<grid, 256, 0, s>>>(g, kchunk);
-  return hipGetLastError();
+  const int kchunk = chunk_for(g, kKT64);
+  if (!g.ta && !g.tb) return gemm_f64_go<false, false>(g, kchunk, s);
+  if (!g.ta && g.tb) return gemm_f64_go<false, true>(g, kchunk, s);
+  if (g.ta && !g.tb) return gemm_f64_go<true, false>(g, kchunk, s);
+  return gemm_f64_go<true, true>(g, kchunk, s);
 }
 
 hipError_t sum_partials_f32(const float* parts, int nparts, int64_t stride, int64_t count,
                             float* out, hipStream_t s) {
-  sum_partials_kernel<float><<<(unsigned)((count + 255) / 256), 256, 0, s>>>(parts, nparts, stride,
+  sum_partials_kernel<float><<<(unsigned)((count + 63) / 64), 64 * kSumWaves, 0, s>>>(parts, nparts, stride,
                                                                            count, out);
   return hipGetLastError();
 }
 
 hipError_t sum_partials_f64(const double* parts, int nparts, int64_t stride, int64_t count,
                             double* out, hipStream_t s) {
-  sum_partials_kernel<double><<<(unsigned)((count + 255) / 256), 256, 0, s>>>(parts, nparts, stride,
+  sum_partials_kernel<double><<<(unsigned)((count + 63) / 64), 64 * kSumWaves, 0, s>>>(parts, nparts, stride,
                                                                             count, out);
   return hipGetLastError();
 }

@@ -54,6 +54,8 @@ hipError_t hat_f32(const void* A, bool a_bf16, const float* Q, float* Ah,
                    int64_t N, int n3, int p, Prec prec, hipStream_t s);
 hipError_t hat_f64(const double* A, const double* Q, double* Ah,
                    int64_t N, int n3, int p, hipStream_t s);
+// the float64 transform of float32 data (each element widened exactly)
+hipError_t hat_f64_wide(const float* A, const double* Q, double* Ah, int64_t N, int n3, int p, hipStream_t s);
 // A (n3 x N) = Q (n3 x p) * Ah (p x N)
 hipError_t unhat_f32(const float* Ah, const float* Q, float* A,
                      int64_t N, int n3, int p, Prec prec, hipStream_t s);
@@ -129,8 +131,10 @@ hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, in
 // data)
 hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                                   int* flags, hipStream_t s);
+// prior (may be null): a face with prior[f] <= prior_max converged in an
+// earlier phase and is left alone (sweeps_used[f] = 0)
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol,
-                             int* sweeps_used, int* flags, hipStream_t s);
+                             int* sweeps_used, int* flags, const int* prior, int prior_max, hipStream_t s);
 // Column norms, descending order, top k normalised vectors F (L x k x p).
 // norms of all nv vectors of every face into sig (nv x p, float64); rank
 // (n = nv p ints, may be null) cleared for jacobi_select

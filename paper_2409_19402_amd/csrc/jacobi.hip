@@ -145,7 +145,8 @@ template <typename T, int R>
 __global__ __launch_bounds__(256) void jacobi_block_kernel(T* __restrict__ W, int nv, int L, int nb,
                                                             int round, int sweep, int max_sweeps,
                                                             double tol, int* __restrict__ flags,
-                                                            int* __restrict__ sweeps_used) {
+                                                            int* __restrict__ sweeps_used,
+                                                            const int* __restrict__ prior, int prior_max) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* V = reinterpret_cast<T*>(smem_raw);
   __shared__ int any_rot;
@@ -155,6 +156,10 @@ __global__ __launch_bounds__(256) void jacobi_block_kernel(T* __restrict__ W, in
   const int nvl = 2 * b;
   const int face = blockIdx.y;
   const bool whole = nb == 2;
+  if (prior && prior[face] <= prior_max) {  // converged in an earlier phase: no sweep
+    if (whole && threadIdx.x == 0) sweeps_used[face] = 0;
+    return;
+  }
   if (!whole && sweep > 0 && flags[face * max_sweeps + sweep - 1] == 0) return;
   int I, J;
   circle_pair(nb, round, blockIdx.x, I, J);
@@ -224,10 +229,16 @@ __global__ __launch_bounds__(256) void jacobi_block_kernel(T* __restrict__ W, in
 template <typename T>
 __global__ __launch_bounds__(kJacobiThreads) void jacobi_global_kernel(T* __restrict__ W, int nv, int L,
                                                                        int max_sweeps, double tol,
-                                                                       int* __restrict__ sweeps_used) {
+                                                                       int* __restrict__ sweeps_used,
+                                                                       const int* __restrict__ prior,
+                                                                       int prior_max) {
   constexpr int NW = kJacobiThreads / 64;
   __shared__ int any_rot;
   const int face = blockIdx.x;
+  if (prior && prior[face] <= prior_max) {  // converged in an earlier phase: no sweep
+    if (threadIdx.x == 0) sweeps_used[face] = 0;
+    return;
+  }
   T* Wf = W + (int64_t)face * nv * L;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nvp = nv + (nv & 1);
@@ -334,8 +345,6 @@ template <typename T, int NB, bool ST>
 __host__ __device__ __forceinline__ size_t gram_lds_bytes(int L) {
   return gram_head<T, NB>() + (ST ? sizeof(T) * (size_t)kG2 * gram_ldx<T>(L) : 0);
 }
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct GramMfma;
 // Output layout of the 16x16x4 MFMAs: lane L holds column L mod 16 of D, in
@@ -886,9 +895,14 @@ __global__ void zero_ints_kernel(int* __restrict__ x, int n) {
 // sweeps_used[l] from the per-sweep rotation flags: the first sweep without a
 // rotation ends the iteration (it is counted); none means not converged.
 __global__ void count_sweeps_kernel(const int* __restrict__ flags, int p, int max_sweeps,
-                                    int* __restrict__ sweeps_used) {
+                                    int* __restrict__ sweeps_used, const int* __restrict__ prior = nullptr,
+                                    int prior_max = 0) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= p) return;
+  if (prior && prior[l] <= prior_max) {  // skipped: converged in an earlier phase
+    sweeps_used[l] = 0;
+    return;
+  }
   int u = max_sweeps + 1;
   for (int s = 0; s < max_sweeps; ++s) {
     if (flags[l * max_sweeps + s] == 0) {
@@ -946,35 +960,38 @@ __global__ __launch_bounds__(256) void norms_kernel(const T* __restrict__ W, int
 // Descending order of each face's norms (ties by index) and the leading
 // vectors normalised into F (L x k x p); a face keeps min(k, kface[f])
 // vectors when kface is given, the rest of its k columns are zero, as is a
-// zero vector.
+// zero vector.  Workgroup (f, c) writes the columns [16 c, 16 c + 16) of
+// face f (each workgroup ranks the face's norms itself).
+constexpr int kFinCols = 16;
+
 template <typename T>
 __global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, const double* __restrict__ sig_all,
                                                        int nv, int L, int k, const int* __restrict__ kface,
                                                        T* __restrict__ F, double* __restrict__ sig_sorted) {
-  extern __shared__ double sig[];  // nv doubles, then k ints
-  int* order = reinterpret_cast<int*>(sig + nv);
-  const int face = blockIdx.x;
+  extern __shared__ double sig[];  // nv doubles
+  __shared__ int order[kFinCols];
+  const int face = blockIdx.x, r0 = blockIdx.y * kFinCols;
   const T* Wf = W + (int64_t)face * nv * L;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kf = kface ? max(0, min(k, kface[face])) : k;
   for (int j = threadIdx.x; j < nv; j += 256) sig[j] = sig_all[(int64_t)face * nv + j];
-  for (int r = threadIdx.x; r < k; r += 256) order[r] = -1;  // stays -1 only for NaN norms
+  if (threadIdx.x < kFinCols) order[threadIdx.x] = -1;  // stays -1 only for NaN norms
   __syncthreads();
   for (int j = threadIdx.x; j < nv; j += 256) {
     const double v = sig[j];
     int r = 0;
     for (int i = 0; i < nv; ++i) r += (sig[i] > v) || (sig[i] == v && i < j);
-    if (r < k) order[r] = j;
+    if (r >= r0 && r < min(k, r0 + kFinCols)) order[r - r0] = j;
   }
   __syncthreads();
-  for (int r = wave; r < k; r += 4) {
+  for (int r = r0 + wave; r < min(k, r0 + kFinCols); r += 4) {
     T* dst = F + ((int64_t)face * k + r) * L;
-    if (r >= kf || order[r] < 0) {
+    const int j = order[r - r0];
+    if (r >= kf || j < 0) {
       for (int e = lane; e < L; e += 64) dst[e] = T(0);
       if (sig_sorted && lane == 0) sig_sorted[(int64_t)face * k + r] = 0.0;
       continue;
     }
-    const int j = order[r];
     const double v = sig[j];
     if (sig_sorted && lane == 0) sig_sorted[(int64_t)face * k + r] = v;
     const double inv = v > 0.0 ? 1.0 / v : 0.0;
@@ -1381,7 +1398,7 @@ constexpr const char* block_name() {
 
 template <typename T, int R>
 hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, double tol, int* used,
-                        int* flags, hipStream_t s) {
+                        int* flags, const int* prior, int prior_max, hipStream_t s) {
   const int b = nw * kPairsPerWave;
   int nb = (nv + b - 1) / b;
   nb += nb & 1;
@@ -1397,7 +1414,7 @@ hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, doub
   if (nb == 2) {
     ProfScope prof(block_name<T>(), s);
     jacobi_block_kernel<T, R><<<dim3(1, p), block, lds, s>>>(W, nv, L, nb, 0, 0, max_sweeps, tol, flags,
-                                                              used);
+                                                              used, prior, prior_max);
     return hipGetLastError();
   }
   const int nflags = p * max_sweeps;
@@ -1410,11 +1427,11 @@ hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, doub
     for (int sw = 0; sw < max_sweeps; ++sw)
       for (int round = 0; round < nb - 1; ++round)
         jacobi_block_kernel<T, R><<<dim3(nb / 2, p), block, lds, s>>>(W, nv, L, nb, round, sw, max_sweeps,
-                                                                       tol, flags, used);
+                                                                       tol, flags, used, prior, prior_max);
   }
   {
     ProfScope prof("jacobi_flags", s);
-    count_sweeps_kernel<<<(p + 63) / 64, 64, 0, s>>>(flags, p, max_sweeps, used);
+    count_sweeps_kernel<<<(p + 63) / 64, 64, 0, s>>>(flags, p, max_sweeps, used, prior, prior_max);
   }
   return hipGetLastError();
 }
@@ -1533,7 +1550,7 @@ int pick_waves(int nv, int Lp) {
 
 template <typename T>
 hipError_t sweeps(T* W, int p, int nv, int L, int max_sweeps, double tol, int* used, int* flags,
-                  hipStream_t s) {
+                  const int* prior, int prior_max, hipStream_t s) {
   const int R = (L + 63) / 64;
   int Rk = 0;
   for (int c : {1, 2, 3, 4, 5, 6, 8, 10, 12, 16})
@@ -1541,20 +1558,20 @@ hipError_t sweeps(T* W, int p, int nv, int L, int max_sweeps, double tol, int* u
   if (Rk > 0 && sizeof(T) * (size_t)2 * kPairsPerWave * 64 * Rk <= kLdsCap) {
     const int nw = pick_waves<T>(nv, 64 * Rk);
     switch (Rk) {
-      case 1: return block_sweeps<T, 1>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
-      case 2: return block_sweeps<T, 2>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
-      case 3: return block_sweeps<T, 3>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
-      case 4: return block_sweeps<T, 4>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
-      case 5: return block_sweeps<T, 5>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
-      case 6: return block_sweeps<T, 6>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
-      case 8: return block_sweeps<T, 8>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
-      case 10: return block_sweeps<T, 10>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
-      case 12: return block_sweeps<T, 12>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
-      default: return block_sweeps<T, 16>(W, p, nv, L, nw, max_sweeps, tol, used, flags, s);
+      case 1: return block_sweeps<T, 1>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
+      case 2: return block_sweeps<T, 2>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
+      case 3: return block_sweeps<T, 3>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
+      case 4: return block_sweeps<T, 4>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
+      case 5: return block_sweeps<T, 5>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
+      case 6: return block_sweeps<T, 6>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
+      case 8: return block_sweeps<T, 8>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
+      case 10: return block_sweeps<T, 10>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
+      case 12: return block_sweeps<T, 12>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
+      default: return block_sweeps<T, 16>(W, p, nv, L, nw, max_sweeps, tol, used, flags, prior, prior_max, s);
     }
   }
   ProfScope prof(sizeof(T) == 8 ? "jacobi_global_f64" : "jacobi_global_f32", s);
-  jacobi_global_kernel<T><<<p, kJacobiThreads, 0, s>>>(W, nv, L, max_sweeps, tol, used);
+  jacobi_global_kernel<T><<<p, kJacobiThreads, 0, s>>>(W, nv, L, max_sweeps, tol, used, prior, prior_max);
   return hipGetLastError();
 }
 
@@ -1571,8 +1588,9 @@ hipError_t prep(const T* Ah, T* W, int n1, int n2, int p, hipStream_t s) {
 template <typename T>
 hipError_t finalize(const T* W, const double* sig, int p, int nv, int L, int k, const int* kface, T* F,
                     double* sig_sorted, hipStream_t s) {
-  const size_t lds = sizeof(double) * (size_t)nv + sizeof(int) * (size_t)k;
-  finalize_kernel<T><<<p, 256, lds, s>>>(W, sig, nv, L, k, kface, F, sig_sorted);
+  const size_t lds = sizeof(double) * (size_t)nv;
+  finalize_kernel<T><<<dim3((unsigned)p, (unsigned)((k + kFinCols - 1) / kFinCols)), 256, lds, s>>>(
+      W, sig, nv, L, k, kface, F, sig_sorted);
   return hipGetLastError();
 }
 
@@ -1622,8 +1640,8 @@ hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, dou
   return gram_sweeps_uniform<float>(W, p, nv, L, max_sweeps, tol, used, flags, s);
 }
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
-                             int* flags, hipStream_t s) {
-  return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
+                             int* flags, const int* prior, int prior_max, hipStream_t s) {
+  return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, prior, prior_max, s);
 }
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, int* used, int* flags, hipStream_t s) {

@@ -840,35 +840,53 @@ __global__ __launch_bounds__(S * 64, MW) void hat_bstrip_kernel(const TIn* __res
 }
 
 // ---- float64 (plain VALU; the float64 path serves small problems) --------
-template <typename T>
-__global__ __launch_bounds__(256) void hat_generic_kernel(const T* __restrict__ A,
-                                                          const T* __restrict__ Q,
-                                                          T* __restrict__ Ah, int64_t N, int n3,
-                                                          int p) {
-  __shared__ T Qs[64][32];
-  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int lc = blockIdx.y * 32;
-  T acc[32];
+// float64 forward transform Ah (p x N) = Q^T A for float32 A (widened on
+// load, exactly) or float64 A: 64 tubes per workgroup of four waves and PC
+// columns of Q per grid row.  Q is staged in LDS 64 rows at a time (zero past
+// n3 and p; every lane of a wave reads the same entry, a broadcast); wave w
+// accumulates the rows t = w (mod 4) of its lane's tube, and the four
+// partial sums are added in wave order through LDS.
+constexpr int kHat64Rows = 64;
+
+template <typename TA, int PC>
+__global__ __launch_bounds__(256) void hat64_kernel(const TA* __restrict__ A, const double* __restrict__ Q,
+                                                    double* __restrict__ Ah, int64_t N, int n3, int p) {
+  __shared__ __align__(16) double Qs[kHat64Rows][PC];
+  __shared__ double part[3][PC][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t x = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t xc = x < N ? x : N - 1;
+  const int lc = blockIdx.y * PC;
+  double acc[PC];
 #pragma unroll
-  for (int c = 0; c < 32; ++c) acc[c] = T(0);
-  for (int kc = 0; kc < n3; kc += 64) {
-    const int rows = min(64, n3 - kc);
+  for (int c = 0; c < PC; ++c) acc[c] = 0.0;
+  for (int kc = 0; kc < n3; kc += kHat64Rows) {
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-      const int r = e >> 5, c = e & 31;
-      Qs[r][c] = (r < rows && lc + c < p) ? Q[(int64_t)(kc + r) * p + lc + c] : T(0);
+    for (int e = threadIdx.x; e < kHat64Rows * PC; e += 256) {
+      const int r = e / PC, c = e % PC;
+      Qs[r][c] = (kc + r < n3 && lc + c < p) ? Q[(int64_t)(kc + r) * p + lc + c] : 0.0;
     }
     __syncthreads();
-    if (x < N) {
-      for (int r = 0; r < rows; ++r) {
-        const T a = A[(int64_t)(kc + r) * N + x];
+    const int rows = min(kHat64Rows, n3 - kc);
+#pragma unroll 2
+    for (int r = w; r < rows; r += 4) {
+      const double a = (double)A[(int64_t)(kc + r) * N + xc];
 #pragma unroll
-        for (int c = 0; c < 32; ++c) acc[c] = fma(Qs[r][c], a, acc[c]);
-      }
+      for (int c = 0; c < PC; ++c) acc[c] = fma(Qs[r][c], a, acc[c]);
     }
   }
-  if (x >= N) return;
-  for (int c = 0; c < 32 && lc + c < p; ++c) Ah[(int64_t)(lc + c) * N + x] = acc[c];
+  if (w > 0) {
+#pragma unroll
+    for (int c = 0; c < PC; ++c) part[w - 1][c][lane] = acc[c];
+  }
+  __syncthreads();
+  if (w == 0 && x < N) {
+#pragma unroll
+    for (int c = 0; c < PC; ++c)
+      if (lc + c < p)
+        Ah[(int64_t)(lc + c) * N + x] = ((acc[c] + part[0][c][lane]) + part[1][c][lane]) + part[2][c][lane];
+  }
 }
 
 template <typename T>
@@ -1284,11 +1302,28 @@ hipError_t proj_fused_f32(const void* A, bool a_bf16, const float* Q, float* out
                       });
 }
 
+template <typename TA>
+hipError_t hat64_launch(const TA* A, const double* Q, double* Ah, int64_t N, int n3, int p, hipStream_t s) {
+  const unsigned gx = (unsigned)((N + 63) / 64);
+  if (p <= 8) {
+    hat64_kernel<TA, 8><<<dim3(gx, 1), 256, 0, s>>>(A, Q, Ah, N, n3, p);
+  } else if (p <= 16) {
+    hat64_kernel<TA, 16><<<dim3(gx, 1), 256, 0, s>>>(A, Q, Ah, N, n3, p);
+  } else if (p <= 24) {
+    hat64_kernel<TA, 24><<<dim3(gx, 1), 256, 0, s>>>(A, Q, Ah, N, n3, p);
+  } else {
+    hat64_kernel<TA, 32><<<dim3(gx, (unsigned)((p + 31) / 32)), 256, 0, s>>>(A, Q, Ah, N, n3, p);
+  }
+  return hipGetLastError();
+}
+
 hipError_t hat_f64(const double* A, const double* Q, double* Ah, int64_t N, int n3, int p,
                    hipStream_t s) {
-  dim3 grid((unsigned)((N + 255) / 256), (unsigned)((p + 31) / 32));
-  hat_generic_kernel<double><<<grid, 256, 0, s>>>(A, Q, Ah, N, n3, p);
-  return hipGetLastError();
+  return hat64_launch(A, Q, Ah, N, n3, p, s);
+}
+
+hipError_t hat_f64_wide(const float* A, const double* Q, double* Ah, int64_t N, int n3, int p, hipStream_t s) {
+  return hat64_launch(A, Q, Ah, N, n3, p, s);
 }
 
 hipError_t unhat_f64(const double* Ah, const double* Q, double* C, int64_t N, int n3, int p,

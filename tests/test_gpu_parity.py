@@ -107,6 +107,22 @@ def test_proj_idempotent(pq):
     assert rel(host(P2), host(P1)) <= TOL32
 
 
+@pytest.mark.parametrize("shape", [(33, 21, 70, 50, 40), (9, 40, 17, 300, 8), (64, 16, 80, 24, 24)])
+def test_transforms_and_qprod_f64(pq, shape):
+    """float64 transforms (p up to 40: several column groups per grid row)
+    and the float64 facewise product on MFMA tiles of both widths."""
+    n1, m, n2, n3, p = shape
+    say(f"f64 transforms and qprod {shape}")
+    rng = np.random.default_rng(13 + n1)
+    A = synth.gaussian(rng, n1, m, n3, np.float64)
+    B = synth.gaussian(rng, m, n2, n3, np.float64)
+    Q = synth.random_orthonormal(rng, n3, p)
+    Al, Bl = synth.logical(A), synth.logical(B)
+    assert rel(host(pq.hat(dev(A), devq(Q))), oracle.hat(Al, Q)) <= TOL64
+    C = pq.qprod(dev(A), dev(B), devq(Q))
+    assert rel(host(C), oracle.qprod(Al, Bl, Q)) <= TOL64
+
+
 def test_f64_tiny_case(pq):
     """Tiny plain-method case in float64: qprod and tSVDQ (k=5)."""
     say("tiny f64")
@@ -330,6 +346,27 @@ def test_differentiation_case(pq):
     r2 = pq.qprod_backward(G, Ad.detach(), Bd.detach(), Qd.detach())
     for x, y in zip(r1, r2):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("shape", [(20, 70, 130, 90, 24), (7, 33, 97, 130, 5), (32, 128, 256, 200, 32)])
+def test_qprod_backward_narrow_outputs(pq, shape):
+    """Products whose outputs have at most 32 rows and more than 64 columns
+    (the facewise product and dA-hat of thin faces, the dQ products), on
+    aligned and unaligned sizes, forward and backward."""
+    n1, m, n2, n3, p = shape
+    say(f"qprod backward narrow {shape}")
+    rng = np.random.default_rng(91 + n1)
+    A = synth.gaussian(rng, n1, m, n3)
+    B = synth.gaussian(rng, m, n2, n3)
+    G = synth.gaussian(rng, n1, n2, n3)
+    Q = synth.random_orthonormal(rng, n3, p).astype(np.float32)
+    Al, Bl, Gl = synth.logical(A), synth.logical(B), synth.logical(G)
+    C = pq.qprod(dev(A), dev(B), devq(Q))
+    assert rel(host(C), oracle.qprod(Al, Bl, Q)) <= TOL32
+    dA, dB, dQ = pq.qprod_backward(dev(G), dev(A), dev(B), devq(Q))
+    ref = oracle.qprod_backward(Gl, Al, Bl, Q)
+    for got, want in zip((dA, dB, dQ), ref):
+        assert rel(host(got), want) <= 1e-4
 
 
 def test_proj_backward(pq):
