@@ -105,6 +105,33 @@ def jacobi_models(svd_flops):
     return {nm: ("alu", share) for nm in JACOBI_KERNELS}
 
 
+def per_launch(name, bytes_per_step):
+    """units per launch of a kernel whose launches in a step differ in size:
+    the step's algorithmic total over its launches"""
+    def units(kernels, steps):
+        n = kernels.get(name, {}).get("launches", 0) / max(1, steps)
+        return bytes_per_step / n if n else None
+    return units
+
+
+def qprod_models(n1, m, n2, n3, p, backward):
+    """HBM models of the transforms and dQ products of one qprod step (float32):
+    every tensor a launch reads or writes, once."""
+    hat = 4.0 * (n1 * m + m * n2) * (n3 + p) + 8.0 * n3 * p            # A and B to the transform domain
+    unhat = 4.0 * n1 * n2 * (p + n3) + 4.0 * n3 * p                    # C back
+    models = {"facewise_gemm": ("mfma", 2.0 * n1 * m * n2 * p)}
+    if backward:
+        # the backward transforms A and B again (their transforms are not
+        # kept), and G
+        hat = 2.0 * hat + 4.0 * n1 * n2 * (n3 + p) + 4.0 * n3 * p
+        unhat += 4.0 * (n1 * m + m * n2) * (p + n3) + 8.0 * n3 * p      # dA, dB back
+        dq = 4.0 * (p + n3) * (n1 * n2 + n1 * m + m * n2)               # the three dQ products' operands
+        models["dq_gemm"] = ("hbm", per_launch("dq_gemm", dq))
+    models["hat"] = ("hbm", per_launch("hat", hat))
+    models["unhat"] = ("hbm", per_launch("unhat", unhat))
+    return models
+
+
 def host_of(X):
     """face-major device tensor -> numpy face-major storage (n3, n2, n1)"""
     return X.permute(2, 1, 0).contiguous().cpu().numpy()
@@ -315,8 +342,7 @@ def main():
         def step():
             return pq.qprod(A, B, Q, prec=args.prec)
         flops = 2.0 * p * (n1 * m * n3 + m * n2 * n3 + n1 * m * n2 + n1 * n2 * n3)
-        models = {"hat": ("hbm", None), "facewise_gemm": ("mfma", 2.0 * n1 * m * n2 * p),
-                  "unhat": ("hbm", 4.0 * n1 * n2 * p + 4.0 * n1 * n2 * n3 + 4.0 * n3 * p)}
+        models = qprod_models(n1, m, n2, n3, p, backward=False)
         info = {"workload": "qprod 256x128x128 * 128x256x128 fp32, p=16", "n1": n1, "m": m,
                 "n2": n2, "n3": n3, "p": p}
         dtype = "f32"
@@ -381,8 +407,7 @@ def main():
               + 2.0 * n3 * p * (n1 * n2 + n1 * m + m * n2) + 2.0 * p * (n1 * m * n3 + m * n2 * n3)
               + 2.0 * p * n1 * m * n2)
         flops = fw + bw
-        models = {"hat": ("hbm", None), "facewise_gemm": ("mfma", 2.0 * n1 * m * n2 * p),
-                  "dq_gemm": ("hbm", None)}
+        models = qprod_models(n1, m, n2, n3, p, backward=True)
         info = {"workload": "qprod forward+backward 256x128x128 * 128x256x128 fp32, p=16",
                 "n1": n1, "m": m, "n2": n2, "n3": n3, "p": p}
         dtype = "f32"

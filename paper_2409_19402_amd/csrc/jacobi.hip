@@ -1243,15 +1243,16 @@ __global__ __launch_bounds__(256) void factor_rows_kernel(const TA* __restrict__
       Fs[wave][jj][c] = (jg < je && c < kc) ? f[(int64_t)(c0 + c) * n2 + jg] : 0.0;
     }
     __syncthreads();
-    if (i < n1) {
-      const int jn = max(0, min(JC, je - j0));
-#pragma unroll 4
-      for (int jj = 0; jj < jn; ++jj) {
-        const double x = (double)a[i + (int64_t)(j0 + jj) * n1];
+    // the chunk's 32 loads of this row issued together (clamped addresses;
+    // rows of F past je are zero in LDS, so the clamped values add nothing)
+    const int ic = min(i, n1 - 1);
+    double xs[JC];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc[c] = fma(x, Fs[wave][jj][c], acc[c]);
-      }
-    }
+    for (int jj = 0; jj < JC; ++jj) xs[jj] = (double)a[ic + (int64_t)min(j0 + jj, n2 - 1) * n1];
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj)
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc[c] = fma(xs[jj], Fs[wave][jj][c], acc[c]);
   }
   if (wave > 0) {
 #pragma unroll
