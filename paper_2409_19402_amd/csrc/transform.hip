@@ -889,17 +889,42 @@ __global__ __launch_bounds__(256) void hat64_kernel(const TA* __restrict__ A, co
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void unhat_generic_kernel(const T* __restrict__ Ah,
-                                                            const T* __restrict__ Q,
-                                                            T* __restrict__ C, int64_t N, int n3,
-                                                            int p) {
+// float64 return transform C (n3 x N) = Q Ah: one tube per thread and TR
+// slices per grid row, the TR x 64 block of Q for the current 64 columns
+// staged in LDS (every lane reads the same entry, a broadcast); each thread
+// reads its tube's p transform-domain values once per grid row and keeps
+// the TR outputs in registers.
+constexpr int kUnhat64Rows = 32;
+
+__global__ __launch_bounds__(256) void unhat64_kernel(const double* __restrict__ Ah, const double* __restrict__ Q,
+                                                      double* __restrict__ C, int64_t N, int n3, int p) {
+  constexpr int TR = kUnhat64Rows;
+  __shared__ double Qs[64][TR];  // Qs[i][j] = Q[t0 + j][l0 + i]
   const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int t = blockIdx.y;
-  if (x >= N || t >= n3) return;
-  T acc = T(0);
-  for (int l = 0; l < p; ++l) acc = fma(Q[(int64_t)t * p + l], Ah[(int64_t)l * N + x], acc);
-  C[(int64_t)t * N + x] = acc;
+  const int64_t xc = x < N ? x : N - 1;
+  const int t0 = blockIdx.y * TR;
+  double acc[TR];
+#pragma unroll
+  for (int j = 0; j < TR; ++j) acc[j] = 0.0;
+  for (int l0 = 0; l0 < p; l0 += 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * TR; e += 256) {
+      const int i = e / TR, j = e % TR;
+      Qs[i][j] = (l0 + i < p && t0 + j < n3) ? Q[(int64_t)(t0 + j) * p + l0 + i] : 0.0;
+    }
+    __syncthreads();
+    const int ln = min(64, p - l0);
+#pragma unroll 2
+    for (int i = 0; i < ln; ++i) {
+      const double a = Ah[(int64_t)(l0 + i) * N + xc];
+#pragma unroll
+      for (int j = 0; j < TR; ++j) acc[j] = fma(Qs[i][j], a, acc[j]);
+    }
+  }
+  if (x >= N) return;
+#pragma unroll
+  for (int j = 0; j < TR; ++j)
+    if (t0 + j < n3) C[(int64_t)(t0 + j) * N + x] = acc[j];
 }
 
 // Widest vector that divides N and the alignment of every base pointer.
@@ -1328,8 +1353,8 @@ hipError_t hat_f64_wide(const float* A, const double* Q, double* Ah, int64_t N, 
 
 hipError_t unhat_f64(const double* Ah, const double* Q, double* C, int64_t N, int n3, int p,
                      hipStream_t s) {
-  dim3 grid((unsigned)((N + 255) / 256), (unsigned)n3);
-  unhat_generic_kernel<double><<<grid, 256, 0, s>>>(Ah, Q, C, N, n3, p);
+  const dim3 grid((unsigned)((N + 255) / 256), (unsigned)((n3 + kUnhat64Rows - 1) / kUnhat64Rows));
+  unhat64_kernel<<<grid, 256, 0, s>>>(Ah, Q, C, N, n3, p);
   return hipGetLastError();
 }
 
