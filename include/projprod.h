@@ -154,6 +154,27 @@ int pq_check_q(const void* Q, int q_dtype, int64_t n3, int64_t p,
 #define PQ_Q_DCT      1
 int pq_build_q(int kind, int64_t n3, int64_t p, int q_dtype, void* Q, hipStream_t stream);
 
+/*
+ * Re-orthonormalisation of Q (the optional repair of the St_{n3,p}
+ * precondition of Def. 3.1): Qout = Q R^{-1} by CholeskyQR2 in float64 --
+ * twice G = W^T W, G = R^T R (upper Cholesky factor, positive diagonal),
+ * W <- W R^{-1}, starting from W = Q -- so that Qout has orthonormal columns
+ * spanning those of Q (for float32 Q to float32 rounding of the float64
+ * result).  For full-rank Q this is the Q factor of the thin QR
+ * decomposition whose R has a positive diagonal.
+ * Q, Qout: n3 x p row-major, q_dtype F32 or F64; Qout may be Q itself.
+ * 1 <= p <= min(n3, 128), else PQ_ERR_P / PQ_ERR_UNSUPPORTED.
+ * info_dev: one int32 in device memory; 0, or c + 1 when column c (0-based)
+ * is numerically dependent on the earlier ones (its pivot is not above
+ * 64 eps times its squared norm, in either pass); Qout is then left
+ * unwritten.  Accurate for condition numbers of Q up to about 1e7 (the
+ * first pass squares it).  Workspace: pq_orthonormalize_q_workspace bytes
+ * (n3 p doubles).  One workgroup: an intake step, not a hot loop.
+ */
+size_t pq_orthonormalize_q_workspace(int64_t n3, int64_t p);
+int pq_orthonormalize_q(const void* Q, int q_dtype, int64_t n3, int64_t p, void* Qout, int* info_dev,
+                        void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- mode-3 transforms (Def. 2.2 with M = Q^T and M = Q) ----------------- */
 /*
  * Ahat = A x_3 Q^T (the "hat" transform after Def. 3.1; Alg. 4.1 step 2).

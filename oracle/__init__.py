@@ -21,7 +21,7 @@ Parity status of each function is listed in ``PARITY`` below.
 
 from .core import (  # noqa: F401
     unfold3, fold3, mode3, facewise, mprod, hat, unhat, qprod, proj,
-    identity_tensor, ftranspose, check_q, fro2, u3, identity_q, dct_q,
+    identity_tensor, ftranspose, check_q, fro2, u3, identity_q, dct_q, orthonormalize_q,
 )
 from .tsvdq import (  # noqa: F401
     tsvdq, tsvdq_error_terms, relative_error, tsvdq_ii, TSVDQResult, hosvd,
@@ -48,6 +48,9 @@ PARITY = {
                       "(tall, wide and square faces, k = 1 and k = min(n1, n2)) and "
                       "torch CPU float64 autograd through torch.linalg.svd",
     "check_q": "pinned: closed form on constructed matrices",
+    "orthonormalize_q": "pinned: numpy's Householder thin QR (library routine, sign-fixed to a "
+                        "positive diagonal R), orthonormal input returned unchanged, dependent "
+                        "column reported",
     "identity_q/dct_q": "pinned: scipy's orthonormal DCT-II of the identity (library routine), "
                         "the n3 = 2 Haar closed form, orthonormal columns",
     "hosvd": "pinned: full multilinear rank reproduces A, the rank-(n1, n2, p) case equals "

@@ -107,6 +107,34 @@ def check_q(Q):
     return float(np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))))
 
 
+def orthonormalize_q(Q):
+    """Q with its columns re-orthonormalised, as a repair of the precondition
+    Q in St_{n3,p} of Def. 3.1 (the paper itself assumes that precondition
+    and gives no repair): CholeskyQR2, i.e. twice W <- W R^{-1} with R the
+    upper Cholesky factor (positive diagonal) of W^T W, starting from W = Q.
+    Returns (W, 0), or (None, c + 1) when the pivot of column c is not above
+    64 eps times that column's squared norm in either pass."""
+    W = _f64(Q).copy()
+    eps = np.finfo(np.float64).eps
+    for _ in range(2):
+        G = W.T @ W
+        p = G.shape[0]
+        R = np.zeros_like(G)
+        for c in range(p):
+            d = G[c, c] - R[:c, c] @ R[:c, c]
+            if not d > 64.0 * eps * G[c, c]:
+                return None, c + 1
+            R[c, c] = np.sqrt(d)
+            for b in range(c + 1, p):
+                R[c, b] = (G[c, b] - R[:c, c] @ R[:c, b]) / R[c, c]
+        # rows of W solve x R = w: W R^{-1} column by column
+        X = np.empty_like(W)
+        for c in range(p):
+            X[:, c] = (W[:, c] - X[:, :c] @ R[:c, c]) / R[c, c]
+        W = X
+    return W, 0
+
+
 def u3(A, p):
     """Q = U3(:, :p): the leading p left singular vectors of the mode-3
     unfolding A_(3) (the data-dependent transform of Thm. 4.3 and Cor. 4.1),

@@ -19,7 +19,7 @@ from ._lib import PQ_F32, PQ_F64, PQ_BF16, PREC, call
 
 __all__ = [
     "empty", "from_storage", "is_face_major", "autotune", "autotune_save", "autotune_load",
-    "check_q", "hat", "unhat", "proj", "facewise",
+    "check_q", "orthonormalize_q", "hat", "unhat", "proj", "facewise",
     "qprod", "qprod_backward", "proj_backward", "tsvdq", "TSVDQ", "QProd", "Proj",
     "Batch", "batched", "u3",
 ]
@@ -115,6 +115,28 @@ def check_q(Q):
     out = torch.empty((), dtype=torch.float64, device=Q.device)
     call("pq_check_q", _ptr(Q), _DT[Q.dtype], Q.shape[0], Q.shape[1], _ptr(out), _stream(Q.device))
     return out
+
+
+def orthonormalize_q(Q, out=None):
+    """(Qout, info): Q re-orthonormalised by CholeskyQR2 in float64 (the Q
+    factor of the thin QR with positive diagonal R; float32 Q gives float32
+    Qout), and an int32 device tensor info[0] = 0, or c + 1 for a column c
+    numerically dependent on the earlier ones (Qout is then not written).
+    `out` (optional, may be Q itself) receives the result."""
+    if Q.dtype not in (torch.float32, torch.float64):
+        raise TypeError("Q must be float32 or float64")
+    Q = _q(Q, Q.dtype)
+    n3, p = Q.shape
+    if out is None:
+        out = torch.empty_like(Q)
+    elif out.dtype != Q.dtype or tuple(out.shape) != (n3, p) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor of Q's shape and dtype")
+    info = torch.zeros(1, dtype=torch.int32, device=Q.device)
+    lib = _lib.load()
+    wsb, nb = _ws(lib.pq_orthonormalize_q_workspace(n3, p), Q.device)
+    call("pq_orthonormalize_q", _ptr(Q), _DT[Q.dtype], n3, p, _ptr(out), _ptr(info), _ptr(wsb), nb,
+         _stream(Q.device))
+    return out, info
 
 
 def hat(A, Q, prec="default"):

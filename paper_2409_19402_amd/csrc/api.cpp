@@ -113,6 +113,8 @@ constexpr int kU3GramSweeps = 16;
 // sweep cap of the Gram-form phase of float64 data (from scratch: 6-12)
 constexpr int kGramSweeps64 = 16;
 constexpr int kMaxSweepsCap = 100;
+// widest Q that pq_orthonormalize_q takes (its Cholesky factor lives in LDS)
+constexpr int64_t kOrthoMaxP = 128;
 // relative gap |lambda_c - lambda_j| / lambda_c at or under which the adjoint
 // of the truncation drops the coupling of a kept and a discarded pair
 constexpr double kDefaultGapTol = 1e-8;
@@ -283,6 +285,21 @@ int pq_build_q(int kind, int64_t n3, int64_t p, int q_dtype, void* Q, hipStream_
   PQ_CHECK(check_p(n3, p));
   PQ_PROF("build_q", stream);
   PQ_TRY(pq::build_q(kind, is_f64(q_dtype), (int)n3, (int)p, Q, stream));
+  return PQ_OK;
+}
+
+size_t pq_orthonormalize_q_workspace(int64_t n3, int64_t p) { return align_up(8 * (size_t)n3 * p); }
+
+int pq_orthonormalize_q(const void* Q, int q_dtype, int64_t n3, int64_t p, void* Qout, int* info_dev, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  if (!Q || !Qout || !info_dev) return PQ_ERR_NULL;
+  PQ_CHECK(check_ar_dtype(q_dtype));
+  PQ_CHECK(check_dims({n3}));
+  PQ_CHECK(check_p(n3, p));
+  if (p > kOrthoMaxP) return PQ_ERR_UNSUPPORTED;
+  if (!ws || ws_bytes < pq_orthonormalize_q_workspace(n3, p)) return PQ_ERR_WORKSPACE;
+  PQ_PROF("orthonormalize_q", stream);
+  PQ_TRY(pq::cholqr2(Q, is_f64(q_dtype), (int)n3, (int)p, static_cast<double*>(ws), Qout, info_dev, stream));
   return PQ_OK;
 }
 

@@ -99,6 +99,10 @@ hipError_t u3_finish(const double* F, const double* G, int n3, int p, void* Q, v
                      hipStream_t s);
 // max |(Q^T Q - I)_ab| into out[0] (float64): two launches, the first clears out
 hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, hipStream_t s);
+// Qout = Q R^{-1} by CholeskyQR2 in float64 (one workgroup; p <= 128; W:
+// n3 p doubles of scratch); info[0] = 0, or c + 1 for a column c that is
+// numerically dependent on the earlier ones (Qout then unwritten)
+hipError_t cholqr2(const void* Q, bool f64, int n3, int p, double* W, void* Qout, int* info, hipStream_t s);
 // Q (n3 x p row-major) of a fixed transform: kind 0 identity, 1 DCT-II
 hipError_t build_q(int kind, bool f64, int n3, int p, void* Q, hipStream_t s);
 

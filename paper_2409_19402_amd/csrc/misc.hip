@@ -40,6 +40,77 @@ __global__ void clear_q_kernel(unsigned long long* __restrict__ out) {
   if (threadIdx.x == 0) out[0] = 0ull;
 }
 
+// CholeskyQR2 of Q (n3 x p row-major) in float64, one workgroup: W = Q
+// (widened), then twice G = W^T W, G = R^T R (Cholesky, R upper triangular
+// with a positive diagonal, in LDS), W <- W R^{-1}; Qout = W in Q's type.
+// info[0] = 0, or c + 1 when the pivot of column c in either pass is not
+// above 64 eps times that column's squared norm (Q numerically rank
+// deficient): the kernel then stops and leaves Qout unwritten.  Q is read in
+// full before Qout is written, so the two may be the same array.
+constexpr int kQrThreads = 1024;
+
+template <typename TQ>
+__global__ __launch_bounds__(kQrThreads) void cholqr2_kernel(const TQ* __restrict__ Q, int n3, int p,
+                                                           double* __restrict__ W, TQ* __restrict__ Qout,
+                                                           int* __restrict__ info) {
+  extern __shared__ double R[];  // p x p, row a at R + a p; then the p squared column norms
+  double* gd = R + (size_t)p * p;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int64_t n = (int64_t)n3 * p;
+  for (int64_t e = tid; e < n; e += kQrThreads) W[e] = (double)Q[e];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    // G = W^T W, upper triangle
+    for (int e = tid; e < p * p; e += kQrThreads) {
+      const int a = e / p, b = e - a * p;
+      if (a <= b) {
+        double g = 0.0;
+        for (int t = 0; t < n3; ++t) g = fma(W[(int64_t)t * p + a], W[(int64_t)t * p + b], g);
+        R[e] = g;
+        if (a == b) gd[a] = g;
+      }
+    }
+    __syncthreads();
+    // upper Cholesky G = R^T R, right-looking, column by column
+    for (int c = 0; c < p; ++c) {
+      if (tid == 0) {
+        // the column's squared norm less its projection on the earlier columns
+        const double d = R[c * p + c];
+        if (!(d > 64.0 * 2.220446049250313e-16 * gd[c])) bad = c + 1;
+        else R[c * p + c] = sqrt(d);
+      }
+      __syncthreads();
+      if (bad) break;
+      const double rcc = R[c * p + c];
+      for (int b = c + 1 + tid; b < p; b += kQrThreads) R[c * p + b] /= rcc;
+      __syncthreads();
+      // trailing update G[a][b] -= R[c][a] R[c][b] for c < a <= b
+      const int m = p - c - 1;
+      for (int e = tid; e < m * m; e += kQrThreads) {
+        const int a = c + 1 + e / m, b = c + 1 + e % m;
+        if (a <= b) R[a * p + b] -= R[c * p + a] * R[c * p + b];
+      }
+      __syncthreads();
+    }
+    if (bad) break;
+    // W <- W R^{-1}: row t solves x R = w by forward substitution
+    for (int t = tid; t < n3; t += kQrThreads) {
+      double* w = W + (int64_t)t * p;
+      for (int c = 0; c < p; ++c) {
+        double x = w[c];
+        for (int k = 0; k < c; ++k) x = fma(-w[k], R[k * p + c], x);
+        w[c] = x / R[c * p + c];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) info[0] = bad;
+  if (bad) return;
+  for (int64_t e = tid; e < n; e += kQrThreads) Qout[e] = static_cast<TQ>(W[e]);
+}
+
 // Q (n3 x p row-major) of a fixed transform: kind 0 the first p columns of
 // the identity, kind 1 the first p rows of the orthonormal DCT-II matrix C
 // (n3 x n3), transposed: Q(t, l) = C(l, t) = w_l cos(pi (2t + 1) l / (2 n3)),
@@ -128,6 +199,23 @@ hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, h
   const unsigned grid = (unsigned)((npair + 3) / 4);
   if (f64) check_q_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double*>(Q), n3, p, bits);
   else check_q_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float*>(Q), n3, p, bits);
+  return hipGetLastError();
+}
+
+hipError_t cholqr2(const void* Q, bool f64, int n3, int p, double* W, void* Qout, int* info, hipStream_t s) {
+  const size_t lds = sizeof(double) * ((size_t)p * p + p);
+  const void* fn = f64 ? reinterpret_cast<const void*>(&cholqr2_kernel<double>)
+                       : reinterpret_cast<const void*>(&cholqr2_kernel<float>);
+  if (lds > 48 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (f64)
+    cholqr2_kernel<double><<<1, kQrThreads, lds, s>>>(static_cast<const double*>(Q), n3, p, W,
+                                                      static_cast<double*>(Qout), info);
+  else
+    cholqr2_kernel<float><<<1, kQrThreads, lds, s>>>(static_cast<const float*>(Q), n3, p, W,
+                                                     static_cast<float*>(Qout), info);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 """The transforms Q of Sec. 5 built on the GPU (identity, DCT; U3 has its own
 tests) against the float64 oracle, the Stiefel check on many column pairs,
-and Thms. 4.3 and 4.6 on the GPU's own results."""
+the CholeskyQR2 re-orthonormalisation of Q, and Thms. 4.3 and 4.6 on the
+GPU's own results."""
 
 import numpy as np
 import pytest
@@ -79,3 +80,39 @@ def test_thm_4_3_and_4_6_on_gpu_results(pq):
         e_h = oracle.fro2(Al - oracle.hosvd(Al, k1, k2, p))
         say(f"Thm 4.6 k1={k1} k2={k2}: tSVDQ {e_t:.6e} <= HOSVD {e_h:.6e}")
         assert e_t <= e_h * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("n3,p", [(16, 4), (200, 20), (257, 33), (130, 128), (5, 1), (64, 64)])
+def test_orthonormalize_q(pq, n3, p):
+    """Q pushed off the Stiefel manifold, re-orthonormalised on the GPU,
+    against the oracle on the values the GPU sees (float32 input widened)."""
+    import torch
+    say(f"orthonormalize_q n3={n3} p={p}")
+    rng = np.random.default_rng(70 + p)
+    Qp = synth.random_orthonormal(rng, n3, p) + 1e-3 * rng.standard_normal((n3, p))
+    for dt, tol, otol in ((np.float64, 1e-13, 1e-14), (np.float32, 1.5e-7, 2e-6)):
+        Qin = devq(Qp.astype(dt))
+        out, info = pq.orthonormalize_q(Qin)
+        assert int(info.item()) == 0
+        ref, rinfo = oracle.orthonormalize_q(host(Qin))
+        assert rinfo == 0
+        assert np.max(np.abs(host(out) - ref)) <= tol
+        assert pq.check_q(out).item() <= otol
+        # in place
+        pq.orthonormalize_q(Qin, out=Qin)
+        assert torch.equal(Qin, out)
+
+
+def test_orthonormalize_q_dependent_column_and_rejects(pq):
+    import torch
+    from paper_2409_19402_amd._lib import ProjProdError
+    rng = np.random.default_rng(71)
+    Q = synth.random_orthonormal(rng, 30, 5)
+    Q[:, 3] = Q[:, 0] + 0.5 * Q[:, 1]
+    Qd = devq(Q)
+    sentinel = torch.full_like(Qd, 7.0)
+    _, info = pq.orthonormalize_q(Qd, out=sentinel)
+    assert int(info.item()) == 4
+    assert bool((sentinel == 7.0).all())  # left unwritten
+    with pytest.raises(ProjProdError):
+        pq.orthonormalize_q(devq(synth.random_orthonormal(rng, 300, 129)))  # p > 128

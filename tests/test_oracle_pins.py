@@ -527,3 +527,38 @@ def test_u3_oracle():
     norms2 = np.sum(oracle.hat(A, Q) ** 2, axis=(0, 1))
     np.testing.assert_allclose(norms2, lam, rtol=1e-12)
     assert np.all(np.diff(lam) <= 0)
+
+
+def test_orthonormalize_q_against_householder_qr():
+    """CholeskyQR2 against numpy's Householder thin QR (a library routine),
+    signs fixed so that R has a positive diagonal: the unique thin QR of a
+    full-rank matrix; also an input with condition number about 1e4."""
+    rng = np.random.default_rng(17)
+    for n3, p, scale in ((16, 4, 1e-3), (200, 20, 1e-3), (9, 9, 1e-2), (50, 1, 0.5), (120, 30, 0.0)):
+        Q0 = synth.random_orthonormal(rng, n3, p)
+        Qp = Q0 + scale * rng.standard_normal((n3, p))
+        W, info = oracle.orthonormalize_q(Qp)
+        assert info == 0
+        Qh, Rh = np.linalg.qr(Qp)
+        Qh = Qh * np.sign(np.diag(Rh))
+        np.testing.assert_allclose(W, Qh, rtol=0, atol=1e-13)
+        assert oracle.check_q(W) < 1e-14
+    # graded columns: condition number about 1e4
+    Q0 = synth.random_orthonormal(rng, 80, 12)
+    Qg = (Q0 + 1e-2 * rng.standard_normal((80, 12))) * np.logspace(0, -4, 12)
+    W, info = oracle.orthonormalize_q(Qg)
+    Qh, Rh = np.linalg.qr(Qg)
+    assert info == 0
+    np.testing.assert_allclose(W, Qh * np.sign(np.diag(Rh)), rtol=0, atol=1e-9)
+    assert oracle.check_q(W) < 1e-14
+
+
+def test_orthonormalize_q_fixed_point_and_dependent_column():
+    rng = np.random.default_rng(18)
+    Q0 = synth.random_orthonormal(rng, 40, 6)
+    W, info = oracle.orthonormalize_q(Q0)
+    assert info == 0 and np.max(np.abs(W - Q0)) < 1e-14
+    Qd = Q0.copy()
+    Qd[:, 3] = Qd[:, 0] - 2.0 * Qd[:, 2]
+    W, info = oracle.orthonormalize_q(Qd)
+    assert W is None and info == 4
