@@ -175,6 +175,25 @@ size_t pq_orthonormalize_q_workspace(int64_t n3, int64_t p);
 int pq_orthonormalize_q(const void* Q, int q_dtype, int64_t n3, int64_t p, void* Qout, int* info_dev,
                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- layouts ---------------------------------------------------------------- */
+/*
+ * Every tensor argument of this library is in the paper's order (Def. 2.1):
+ * element (i, j, t) of an n1 x n2 x n3 tensor at i + n1 (j + n2 t), each
+ * frontal slice a contiguous column-major matrix (PQ_LAYOUT_FACE_MAJOR).
+ * Data held in numpy / torch C order of an (n1, n2, n3) array, element at
+ * t + n3 (j + n2 i) (PQ_LAYOUT_TUBE_MAJOR), is converted with pq_relayout.
+ *
+ * dst = src in the other layout: src_layout names src's (the one given or
+ * PQ_ERR_ARG), dst gets the other.  dtype F32, F64 or BF16 (bits copied
+ * unchanged); dst must not overlap src (PQ_ERR_ALIAS).  A transpose of
+ * each (i, t) plane through LDS: one read and one write of the tensor.
+ * Workspace: none.  PQ_ERR_UNSUPPORTED when ceil(n1 / 32) > 65535.
+ */
+#define PQ_LAYOUT_FACE_MAJOR 0
+#define PQ_LAYOUT_TUBE_MAJOR 1
+int pq_relayout(const void* src, int src_layout, void* dst, int dtype, int64_t n1, int64_t n2, int64_t n3,
+                hipStream_t stream);
+
 /* ---- mode-3 transforms (Def. 2.2 with M = Q^T and M = Q) ----------------- */
 /*
  * Ahat = A x_3 Q^T (the "hat" transform after Def. 3.1; Alg. 4.1 step 2).

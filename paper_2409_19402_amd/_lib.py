@@ -46,6 +46,7 @@ SIGNATURES = {
     "pq_tsvdq": (_i32, [_vp, _i32, _vp, _i64, _i64, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _vp,
                         _vp, _vp, _vp, _dbl, _i32, _vp, _vp, _sz, _vp]),
     "pq_build_q": (_i32, [_i32, _i64, _i64, _i32, _vp, _vp]),
+    "pq_relayout": (_i32, [_vp, _i32, _vp, _i32, _i64, _i64, _i64, _vp]),
     "pq_orthonormalize_q_workspace": (_sz, [_i64, _i64]),
     "pq_orthonormalize_q": (_i32, [_vp, _i32, _i64, _i64, _vp, _vp, _vp, _sz, _vp]),
     "pq_svdii_workspace": (_sz, [_i64, _i64, _i64, _i64, _i64, _i32]),

@@ -18,7 +18,8 @@ from . import _lib
 from ._lib import PQ_F32, PQ_F64, PQ_BF16, PREC, call
 
 __all__ = [
-    "empty", "from_storage", "is_face_major", "autotune", "autotune_save", "autotune_load",
+    "empty", "from_storage", "is_face_major", "to_face_major", "to_tube_major",
+    "autotune", "autotune_save", "autotune_load",
     "check_q", "orthonormalize_q", "hat", "unhat", "proj", "facewise",
     "qprod", "qprod_backward", "proj_backward", "tsvdq", "TSVDQ", "QProd", "Proj",
     "Batch", "batched", "u3",
@@ -218,9 +219,40 @@ def _qprod_fwd(A, B, Q, prec, save=False):
     return C, Ah, Bh
 
 
+PQ_LAYOUT_FACE_MAJOR, PQ_LAYOUT_TUBE_MAJOR = 0, 1
+
+
+def to_face_major(X):
+    """A face-major copy of X (n1, n2, n3): a contiguous (C-order, tube-major)
+    tensor is converted by the library's relayout kernel."""
+    if not isinstance(X, torch.Tensor) or X.device.type != "cuda" or X.dtype not in _DT:
+        raise TypeError("X must be a float32, float64 or bfloat16 torch tensor on a ROCm device")
+    if X.dim() != 3 or not X.is_contiguous():
+        raise ValueError("to_face_major expects a contiguous (n1, n2, n3) tensor")
+    n1, n2, n3 = X.shape
+    out = empty(n1, n2, n3, X.dtype, X.device)
+    call("pq_relayout", _ptr(X), PQ_LAYOUT_TUBE_MAJOR, _ptr(out), _DT[X.dtype], n1, n2, n3, _stream(X.device))
+    return out
+
+
+def to_tube_major(X):
+    """A contiguous (C-order) copy of the face-major tensor X (n1, n2, n3)."""
+    _tensor(X, "X")
+    if not is_face_major(X):
+        raise ValueError("to_tube_major expects a face-major tensor")
+    n1, n2, n3 = X.shape
+    out = torch.empty((n1, n2, n3), dtype=X.dtype, device=X.device)
+    call("pq_relayout", _ptr(X), PQ_LAYOUT_FACE_MAJOR, _ptr(out), _DT[X.dtype], n1, n2, n3, _stream(X.device))
+    return out
+
+
 def _face_major(G):
-    # the adjoint kernels read face-major storage; autograd may hand over any layout
-    return G if is_face_major(G) else G.permute(2, 1, 0).contiguous().permute(2, 1, 0)
+    # the adjoint kernels read face-major storage; autograd may hand over any
+    # layout: C order goes through the relayout kernel, any other strides are
+    # first made contiguous
+    if is_face_major(G):
+        return G
+    return to_face_major(G if G.is_contiguous() else G.contiguous())
 
 
 def qprod_backward(G, A, B, Q, Ahat=None, Bhat=None, need=(True, True, True)):

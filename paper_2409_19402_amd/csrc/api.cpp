@@ -288,6 +288,21 @@ int pq_build_q(int kind, int64_t n3, int64_t p, int q_dtype, void* Q, hipStream_
   return PQ_OK;
 }
 
+int pq_relayout(const void* src, int src_layout, void* dst, int dtype, int64_t n1, int64_t n2, int64_t n3,
+                hipStream_t stream) {
+  if (!src || !dst) return PQ_ERR_NULL;
+  if (src_layout != PQ_LAYOUT_FACE_MAJOR && src_layout != PQ_LAYOUT_TUBE_MAJOR) return PQ_ERR_ARG;
+  PQ_CHECK(check_in_dtype(dtype));
+  PQ_CHECK(check_dims({n1, n2, n3}));
+  PQ_CHECK(no_alias(dst, {src}));
+  // grid: (ceil(n3 / 32) n2, ceil(n1 / 32)); the second dimension is limited to 65535
+  if ((n1 + 31) / 32 > 65535 || (n3 + 31) / 32 * n2 > INT32_MAX) return PQ_ERR_UNSUPPORTED;
+  const int bytes = dtype == PQ_F64 ? 8 : dtype == PQ_BF16 ? 2 : 4;
+  PQ_PROF("relayout", stream);
+  PQ_TRY(pq::relayout(src, dst, bytes, src_layout == PQ_LAYOUT_TUBE_MAJOR, (int)n1, (int)n2, (int)n3, stream));
+  return PQ_OK;
+}
+
 size_t pq_orthonormalize_q_workspace(int64_t n3, int64_t p) { return align_up(8 * (size_t)n3 * p); }
 
 int pq_orthonormalize_q(const void* Q, int q_dtype, int64_t n3, int64_t p, void* Qout, int* info_dev, void* ws,

@@ -99,6 +99,10 @@ hipError_t u3_finish(const double* F, const double* G, int n3, int p, void* Q, v
                      hipStream_t s);
 // max |(Q^T Q - I)_ab| into out[0] (float64): two launches, the first clears out
 hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, hipStream_t s);
+// dst = src in the other layout: tube-major (t + n3 (j + n2 i)) to face-major
+// (i + n1 (j + n2 t)) when to_face, the reverse otherwise; elements of
+// elem_bytes (2, 4 or 8) bytes; (ceil(n3 / 32) n2, ceil(n1 / 32)) workgroups
+hipError_t relayout(const void* src, void* dst, int elem_bytes, bool to_face, int n1, int n2, int n3, hipStream_t s);
 // Qout = Q R^{-1} by CholeskyQR2 in float64 (one workgroup; p <= 128; W:
 // n3 p doubles of scratch); info[0] = 0, or c + 1 for a column c that is
 // numerically dependent on the earlier ones (Qout then unwritten)

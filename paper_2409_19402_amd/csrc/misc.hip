@@ -40,6 +40,42 @@ __global__ void clear_q_kernel(unsigned long long* __restrict__ out) {
   if (threadIdx.x == 0) out[0] = 0ull;
 }
 
+// Layout conversion between the paper's face-major order (element (i, j, t)
+// at i + n1 (j + n2 t)) and tube-major order (t + n3 (j + n2 i): numpy's
+// C order of an n1 x n2 x n3 array).  For each j it is a transpose of the
+// (i, t) plane: 32 x 32 tiles through LDS, loads and stores both coalesced
+// (lanes along the contiguous index of each side).  E is the element's bit
+// pattern (2, 4 or 8 bytes).
+template <typename E, bool TO_FACE>
+__global__ __launch_bounds__(256) void relayout_kernel(const E* __restrict__ src, E* __restrict__ dst, int n1,
+                                                       int n2, int n3, int tiles_t) {
+  __shared__ E tile[32][33];
+  const int j = blockIdx.x / tiles_t, t0 = (blockIdx.x % tiles_t) * 32, i0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int64_t face = (int64_t)n1 * n2;
+  // tile[r][c] holds element (i0 + r, t0 + c) when converting to face-major,
+  // element (i0 + c, t0 + r) otherwise; either way the stores read tile[tx][r]
+  for (int r = ty; r < 32; r += 8) {
+    if (TO_FACE) {
+      const int i = i0 + r, t = t0 + tx;
+      if (i < n1 && t < n3) tile[r][tx] = src[t + (int64_t)n3 * (j + (int64_t)n2 * i)];
+    } else {
+      const int i = i0 + tx, t = t0 + r;
+      if (i < n1 && t < n3) tile[r][tx] = src[i + (int64_t)n1 * j + face * t];
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    if (TO_FACE) {
+      const int i = i0 + tx, t = t0 + r;
+      if (i < n1 && t < n3) dst[i + (int64_t)n1 * j + face * t] = tile[tx][r];
+    } else {
+      const int i = i0 + r, t = t0 + tx;
+      if (i < n1 && t < n3) dst[t + (int64_t)n3 * (j + (int64_t)n2 * i)] = tile[tx][r];
+    }
+  }
+}
+
 // CholeskyQR2 of Q (n3 x p row-major) in float64, one workgroup: W = Q
 // (widened), then twice G = W^T W, G = R^T R (Cholesky, R upper triangular
 // with a positive diagonal, in LDS), W <- W R^{-1}; Qout = W in Q's type.
@@ -200,6 +236,27 @@ hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, h
   if (f64) check_q_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double*>(Q), n3, p, bits);
   else check_q_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float*>(Q), n3, p, bits);
   return hipGetLastError();
+}
+
+template <typename E>
+hipError_t relayout_go(const void* src, void* dst, bool to_face, int n1, int n2, int n3, hipStream_t s) {
+  const int tiles_t = (n3 + 31) / 32;
+  const dim3 grid((unsigned)((int64_t)tiles_t * n2), (unsigned)((n1 + 31) / 32));
+  if (to_face)
+    relayout_kernel<E, true><<<grid, 256, 0, s>>>(static_cast<const E*>(src), static_cast<E*>(dst), n1, n2, n3,
+                                                 tiles_t);
+  else
+    relayout_kernel<E, false><<<grid, 256, 0, s>>>(static_cast<const E*>(src), static_cast<E*>(dst), n1, n2, n3,
+                                                  tiles_t);
+  return hipGetLastError();
+}
+
+hipError_t relayout(const void* src, void* dst, int elem_bytes, bool to_face, int n1, int n2, int n3, hipStream_t s) {
+  switch (elem_bytes) {
+    case 2: return relayout_go<uint16_t>(src, dst, to_face, n1, n2, n3, s);
+    case 4: return relayout_go<uint32_t>(src, dst, to_face, n1, n2, n3, s);
+    default: return relayout_go<uint64_t>(src, dst, to_face, n1, n2, n3, s);
+  }
 }
 
 hipError_t cholqr2(const void* Q, bool f64, int n3, int p, double* W, void* Qout, int* info, hipStream_t s) {

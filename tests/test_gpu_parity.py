@@ -369,6 +369,23 @@ def test_qprod_backward_narrow_outputs(pq, shape):
         assert rel(host(got), want) <= 1e-4
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (33, 17, 65), (64, 32, 128), (5, 300, 7)])
+def test_relayout(pq, shape):
+    """numpy C order (tube-major) <-> the paper's face-major order, every
+    dtype, bit-exact both ways; a C-order gradient goes through it."""
+    import torch
+    say(f"relayout {shape}")
+    rng = np.random.default_rng(sum(shape))
+    X = torch.from_numpy(rng.standard_normal(shape)).cuda()
+    for dt in (torch.float32, torch.float64, torch.bfloat16):
+        Xd = X.to(dt).contiguous()
+        F = pq.to_face_major(Xd)
+        assert pq.is_face_major(F) and torch.equal(F, Xd)
+        T = pq.to_tube_major(F)
+        assert T.is_contiguous() and torch.equal(T, Xd)
+        assert torch.equal(pq._face_major(Xd), Xd)
+
+
 def test_proj_backward(pq):
     say("proj backward")
     A, Q = _case(44, 30, 20, 48, 6)
