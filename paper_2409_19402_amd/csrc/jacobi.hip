@@ -1080,8 +1080,12 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const double* __res
 // Jacobi on the k columns of Y (m1 x k, face-major) with every rotation also
 // applied to the k columns of F (m2 x k); then norms, descending order and
 // the outputs (type TO): s (k), Other = Y / s, Fo = F, Ys = Y, in that order.
+// The columns stay in global memory (the form for k columns that do not fit
+// in LDS); 16 waves per face, one pair per wave at a time.
+constexpr int kRefineWaves = 16;
+
 template <typename T, typename TO>
-__global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __restrict__ F, int m1,
+__global__ __launch_bounds__(64 * kRefineWaves) void refine_kernel(T* __restrict__ Y, T* __restrict__ F, int m1,
                                                      int m2, int k, const int* __restrict__ kface,
                                                      double tol, int max_sweeps,
                                                      TO* __restrict__ s_out, TO* __restrict__ Other,
@@ -1099,7 +1103,7 @@ __global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __res
     if (threadIdx.x == 0) any_rot = 0;
     __syncthreads();
     for (int r = 0; r < kp - 1; ++r) {
-      for (int pi = wave; pi < kp / 2; pi += 4) {
+      for (int pi = wave; pi < kp / 2; pi += kRefineWaves) {
         int a, c;
         circle_pair(kp, r, pi, a, c);
         if (a >= kf || c >= kf) continue;
@@ -1135,7 +1139,7 @@ __global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __res
     __syncthreads();
     if (!any) break;
   }
-  for (int j = wave; j < k; j += 4) {
+  for (int j = wave; j < k; j += kRefineWaves) {
     double acc = 0.0;
     for (int e = lane; e < m1; e += 64) {
       const double x = Yf[(int64_t)j * m1 + e];
@@ -1144,16 +1148,16 @@ __global__ __launch_bounds__(256) void refine_kernel(T* __restrict__ Y, T* __res
     acc = wave_total(acc);
     if (lane == 0) sig[j] = sqrt(acc);
   }
-  for (int r = threadIdx.x; r < k; r += 256) order[r] = -1;
+  for (int r = threadIdx.x; r < k; r += 64 * kRefineWaves) order[r] = -1;
   __syncthreads();
-  for (int j = threadIdx.x; j < k; j += 256) {
+  for (int j = threadIdx.x; j < k; j += 64 * kRefineWaves) {
     const double v = sig[j];
     int r = 0;
     for (int i = 0; i < k; ++i) r += (sig[i] > v) || (sig[i] == v && i < j);
     order[r] = j;
   }
   __syncthreads();
-  for (int r = wave; r < k; r += 4) {
+  for (int r = wave; r < k; r += kRefineWaves) {
     // equal ranks arise only from NaN norms; such a slot reads column r
     const int j = order[r] >= 0 && order[r] < k ? order[r] : r;
     const double v = sig[j];
@@ -1611,7 +1615,8 @@ hipError_t refine(double* Y, double* F, int m1, int m2, int k, int p, const int*
     refine_lds_kernel<TO><<<p, 1024, lds_lds, s>>>(Y, F, m1, m2, k, kface, tol, 12, s_out, Other, Fo, Ys);
   } else {
     const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)k;
-    refine_kernel<double, TO><<<p, 256, lds, s>>>(Y, F, m1, m2, k, kface, tol, 12, s_out, Other, Fo, Ys);
+    refine_kernel<double, TO><<<p, 64 * kRefineWaves, lds, s>>>(Y, F, m1, m2, k, kface, tol, 12, s_out, Other, Fo,
+                                                               Ys);
   }
   return hipGetLastError();
 }
