@@ -308,7 +308,6 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_global_kernel(T* __rest
 constexpr int kGB = 16;        // vectors per block
 constexpr int kG2 = 2 * kGB;   // vectors per block pair = Gram order
 constexpr int kGld = kG2 + 1;  // row stride of G and V in LDS (doubles): no bank conflicts on columns
-static_assert(kGld == 33, "the round loop forms row offsets as (x << 5) + x");
 constexpr int kGMat = kG2 * kGld;
 // LDS head of a visit: NB copies of G in the angle type (float32 for float32
 // data; with two copies each round reads one and writes the other, with one
@@ -724,8 +723,9 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
       int a1, c1, a2, c2;
       gram_pair(full, r, P, a1, c1);
       gram_pair(full, r, P2, a2, c2);
-      const int ra1 = (a1 << 5) + a1, rc1 = (c1 << 5) + c1;  // row offsets (kGld = 33)
-      const int ra2 = (a2 << 5) + a2, rc2 = (c2 << 5) + c2;
+      // row offsets on the full-rate 24-bit multiplier
+      const int ra1 = __mul24(a1, kGld), rc1 = __mul24(c1, kGld);
+      const int ra2 = __mul24(a2, kGld), rc2 = __mul24(c2, kGld);
       const R m00 = G[ra1 + a2], m01 = G[ra1 + c2];
       const R m10 = G[rc1 + a2], m11 = G[rc1 + c2];
       const R al2 = G[ra2 + a2], be2 = G[rc2 + c2], ga2 = G[ra2 + c2];
@@ -776,7 +776,6 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
     const int blk = tid >> 1, h = tid & 1;
     const int P = blk >> 4, P2 = blk & 15;
     const int srcl = (2 * 17 * P) & 63;  // a lane of this wave that holds block (P, P)
-    const int nrounds = full ? kG2 - 1 : kGB;
     const R tol2r = (R)tol2;
     const int vr = (P2 + 16 * h) * kGld;
     int pa = 0, pc = 0;
@@ -787,14 +786,19 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
       V[vr + pc] = pvs * va_ + pvc * vc_;
     };
     int cur = 0;
-    for (int r = 0; r < nrounds; ++r) {
+    // one round; FULL: the first launch of a sweep (the round robin over all
+    // 32 vectors).  The float32 rounds run in two loops with FULL constant
+    // (straight-line code, measured faster); the float64 rounds in one loop
+    // (measured faster there)
+    auto do_round = [&](int r, bool FULL) {
       const R* G = Gb + (NB == 2 ? cur : 0) * kGMat;
       R* Gn = Gb + (NB == 2 ? cur ^ 1 : 0) * kGMat;
       int a1, c1, a2, c2;
-      gram_pair(full, r, P, a1, c1);
-      gram_pair(full, r, P2, a2, c2);
-      const int rx = h ? (c1 << 5) + c1 : (a1 << 5) + a1;  // this thread's row of the block
-      const int ra2 = (a2 << 5) + a2, rc2 = (c2 << 5) + c2;
+      gram_pair(FULL, r, P, a1, c1);
+      gram_pair(FULL, r, P2, a2, c2);
+      // row offsets on the full-rate 24-bit multiplier
+      const int rx = __mul24(h ? c1 : a1, kGld);  // this thread's row of the block
+      const int ra2 = __mul24(a2, kGld), rc2 = __mul24(c2, kGld);
       const R mx0 = G[rx + a2], mx1 = G[rx + c2];
       const R al2 = G[ra2 + a2], be2 = G[rc2 + c2], ga2 = G[ra2 + c2];
       if (r > 0) apply_v();
@@ -829,6 +833,16 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
       }
       cur ^= 1;
       __syncthreads();
+    };
+    if constexpr (F32) {
+      if (full) {
+        for (int r = 0; r < kG2 - 1; ++r) do_round(r, true);
+      } else {
+        for (int r = 0; r < kGB; ++r) do_round(r, false);
+      }
+    } else {
+      const int nrounds = full ? kG2 - 1 : kGB;
+      for (int r = 0; r < nrounds; ++r) do_round(r, full);
     }
     apply_v();
     __syncthreads();
