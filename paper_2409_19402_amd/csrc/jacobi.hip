@@ -397,6 +397,22 @@ __device__ __forceinline__ double2 gram_rotation(double al, double be, double ga
   return on ? make_double2(cs, sn) : make_double2(1.0, 0.0);
 }
 
+// The rotation of rotation() (same test, same annihilating angle up to the
+// choice at beta = alpha) through gram_rotation: reciprocal square roots
+// refined by two Newton steps instead of a chain of float64 square roots and
+// divisions, for the latency-bound refinement rounds.
+__device__ __forceinline__ Rot rotation_rsq(double al, double be, double ga, double tol) {
+  Rot q{1.0, 0.0, false};
+  const double tol2 = tol * tol;
+  if (ga != 0.0 && ga * ga > tol2 * al * be) {
+    const double2 cs = gram_rotation<2>(al, be, ga, tol2);
+    q.c = cs.x;
+    q.s = cs.y;
+    q.on = true;
+  }
+  return q;
+}
+
 // The same rotation in float32 (the coarse sweeps of float32 data): the
 // hardware reciprocal square root without refinement, about 1e-7 relative,
 // far below the coarse stopping threshold.  A rotation that is off, or
@@ -1130,7 +1146,7 @@ __global__ __launch_bounds__(64 * kRefineWaves) void refine_kernel(T* __restrict
           be = fma(y, y, be);
           ga = fma(x, y, ga);
         }
-        const Rot q = rotation(wave_total(al), wave_total(be), wave_total(ga), tol);
+        const Rot q = rotation_rsq(wave_total(al), wave_total(be), wave_total(ga), tol);
         if (q.on) {
           for (int e = lane; e < m1; e += 64) {
             const double x = ya[e], y = yc[e];
@@ -1321,14 +1337,16 @@ __global__ __launch_bounds__(1024) void refine_lds_kernel(const double* __restri
         double* ya = Yf + (int64_t)a * m1;
         double* yc = Yf + (int64_t)c * m1;
         double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll 4
         for (int e = lane; e < m1; e += 64) {
           const double x = ya[e], y = yc[e];
           al = fma(x, x, al);
           be = fma(y, y, be);
           ga = fma(x, y, ga);
         }
-        const Rot q = rotation(wave_total(al), wave_total(be), wave_total(ga), tol);
+        const Rot q = rotation_rsq(wave_total(al), wave_total(be), wave_total(ga), tol);
         if (q.on) {
+#pragma unroll 4
           for (int e = lane; e < m1; e += 64) {
             const double x = ya[e], y = yc[e];
             ya[e] = q.c * x - q.s * y;
@@ -1336,6 +1354,7 @@ __global__ __launch_bounds__(1024) void refine_lds_kernel(const double* __restri
           }
           double* fa = Ff + (int64_t)a * m2;
           double* fc = Ff + (int64_t)c * m2;
+#pragma unroll 4
           for (int e = lane; e < m2; e += 64) {
             const double x = fa[e], y = fc[e];
             fa[e] = q.c * x - q.s * y;
