@@ -426,18 +426,24 @@ def main():
     lib.pq_autotune_enable(0)
     log(f"warmup done ({lib.pq_autotune_entries()} tuned launch shapes)")
 
-    # the timed region: K steps between two events on the launch stream
+    # the timed region: K steps between two events on the launch stream, with
+    # an event after each step for the spread of single-step times
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     ev0.record(stream)
-    for _ in range(args.steps):
+    for i in range(args.steps):
         out = step()
+        marks[i].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
     ms_per_step = total_ms / args.steps
-    log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step")
+    singles = [ev0.elapsed_time(marks[0])] + [marks[i - 1].elapsed_time(marks[i]) for i in range(1, args.steps)]
+    q10, q50, q90 = (float(np.percentile(singles, q)) for q in (10, 50, 90))
+    log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step (single steps p10 {q10:.4f}, median {q50:.4f}, "
+        f"p90 {q90:.4f} ms)")
 
     extra_batched = {}
     if args.workload == "batched":
@@ -572,6 +578,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step_quantiles": {"p10": round(q10, 5), "p50": round(q50, 5), "p90": round(q90, 5)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
