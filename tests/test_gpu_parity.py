@@ -203,6 +203,22 @@ def test_tsvdq_f64_blocked(pq):
     assert r.info.cpu().numpy()[1] == 0
 
 
+def test_tsvdq_nonfinite_input_returns(pq):
+    """A NaN in the data reaches every face through the transform; the call
+    still returns (every sweep loop is bounded and a NaN never requests a
+    rotation), with the sweep counts inside their caps and NaN values out."""
+    import torch
+    say("tsvdq with a NaN")
+    A, Q = _case(12, 40, 30, 16, 4)
+    A = A.copy()
+    A[3, 5, 7] = np.nan  # storage (n3, n2, n1)
+    r = pq.tsvdq(dev(A), devq(Q), 3, approx=True)
+    torch.cuda.synchronize()
+    info = r.info.cpu().numpy()
+    assert 0 <= info[0] <= 16 and 0 <= info[1] <= 4
+    assert not np.all(np.isfinite(host(r.s)))
+
+
 def test_tsvdq_rank_deficient(pq):
     """Example 4.1 with the Haar column: the transform face is rank one, so the
     second singular vector of each side must come back as zeros, and the error
