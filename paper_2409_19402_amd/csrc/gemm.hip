@@ -437,31 +437,32 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g, int kchunk) {
 // workgroup of 16 waves.  Wave w sums the slices z = w (mod 16) of its lane's
 // output in four independent chains (z = w + 16 c (mod 64), c = 0..3), and
 // the 16 wave sums are added in wave order: a fixed order for every call.
+// Sums run in TO (float64 for float32 slices summed into float64).
 constexpr int kSumWaves = 16;
 
-template <typename T>
-__global__ __launch_bounds__(64 * kSumWaves) void sum_partials_kernel(const T* __restrict__ parts, int nparts,
+template <typename TI, typename TO>
+__global__ __launch_bounds__(64 * kSumWaves) void sum_partials_kernel(const TI* __restrict__ parts, int nparts,
                                                                       int64_t stride, int64_t count,
-                                                                      T* __restrict__ out) {
-  __shared__ T red[kSumWaves][64];
+                                                                      TO* __restrict__ out) {
+  __shared__ TO red[kSumWaves][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-  T acc[4] = {T(0), T(0), T(0), T(0)};
+  TO acc[4] = {TO(0), TO(0), TO(0), TO(0)};
   if (e < count) {
     int z = w;
     for (; z + 3 * kSumWaves < nparts; z += 4 * kSumWaves) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] += parts[(int64_t)(z + c * kSumWaves) * stride + e];
+      for (int c = 0; c < 4; ++c) acc[c] += (TO)parts[(int64_t)(z + c * kSumWaves) * stride + e];
     }
     // at most three slices remain (z + 48 >= nparts)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      if (z + c * kSumWaves < nparts) acc[c] += parts[(int64_t)(z + c * kSumWaves) * stride + e];
+      if (z + c * kSumWaves < nparts) acc[c] += (TO)parts[(int64_t)(z + c * kSumWaves) * stride + e];
   }
   red[w][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
   if (w == 0 && e < count) {
-    T t = red[0][lane];
+    TO t = red[0][lane];
     for (int i = 1; i < kSumWaves; ++i) t += red[i][lane];
     out[e] = t;
   }
@@ -580,15 +581,21 @@ hipError_t gemm_f64(const Gemm& g, hipStream_t s) {
 
 hipError_t sum_partials_f32(const float* parts, int nparts, int64_t stride, int64_t count,
                             float* out, hipStream_t s) {
-  sum_partials_kernel<float><<<(unsigned)((count + 63) / 64), 64 * kSumWaves, 0, s>>>(parts, nparts, stride,
-                                                                           count, out);
+  sum_partials_kernel<float, float><<<(unsigned)((count + 63) / 64), 64 * kSumWaves, 0, s>>>(parts, nparts, stride,
+                                                                                            count, out);
   return hipGetLastError();
 }
 
 hipError_t sum_partials_f64(const double* parts, int nparts, int64_t stride, int64_t count,
                             double* out, hipStream_t s) {
-  sum_partials_kernel<double><<<(unsigned)((count + 63) / 64), 64 * kSumWaves, 0, s>>>(parts, nparts, stride,
-                                                                            count, out);
+  sum_partials_kernel<double, double><<<(unsigned)((count + 63) / 64), 64 * kSumWaves, 0, s>>>(parts, nparts, stride,
+                                                                                              count, out);
+  return hipGetLastError();
+}
+
+hipError_t sum_to_f64(const float* parts, int nparts, int64_t stride, int64_t count, double* out, hipStream_t s) {
+  sum_partials_kernel<float, double><<<(unsigned)((count + 63) / 64), 64 * kSumWaves, 0, s>>>(parts, nparts, stride,
+                                                                                             count, out);
   return hipGetLastError();
 }
 

@@ -82,16 +82,15 @@ struct Gemm {
 };
 hipError_t gemm_f32(const Gemm& g, Prec prec, hipStream_t s);
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
-// out[e] = sum_{z < nparts} parts[z * stride + e] for e < count, fixed order.
+// out[e] = sum_{z < nparts} parts[z * stride + e] for e < count, fixed order
 hipError_t sum_partials_f32(const float* parts, int nparts, int64_t stride,
                             int64_t count, float* out, hipStream_t s);
 hipError_t sum_partials_f64(const double* parts, int nparts, int64_t stride,
                             int64_t count, double* out, hipStream_t s);
-
-// ---- small helpers (misc.hip) ---------------------------------------------
-// ---- Q = U3 (misc.hip) ---------------------------------------------------------
-// out = sum of nparts float32 slices (stride apart), in float64, fixed order
+// the same for float32 slices, summed in float64
 hipError_t sum_to_f64(const float* parts, int nparts, int64_t stride, int64_t count, double* out, hipStream_t s);
+
+// ---- Q = U3 (misc.hip) ---------------------------------------------------------
 // Q (n3 x p row-major, float32 or float64) from the p normalised eigenvectors
 // F (vector-major, n3 each): columns signed so that the largest-magnitude
 // entry is positive; lambda[r] = f_r^T G f_r (G n3 x n3)

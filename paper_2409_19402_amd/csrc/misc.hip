@@ -168,17 +168,6 @@ __global__ __launch_bounds__(256) void build_q_kernel(int kind, int n3, int p, T
   Q[e] = static_cast<TO>(v);
 }
 
-// out[e] = sum over z of parts[z * stride + e], accumulated in float64 in a
-// fixed order (the split-K slices of a float32 product)
-__global__ __launch_bounds__(256) void sum_to_f64_kernel(const float* __restrict__ parts, int nparts,
-                                                         int64_t stride, int64_t count, double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= count) return;
-  double acc = 0.0;
-  for (int z = 0; z < nparts; ++z) acc += (double)parts[(int64_t)z * stride + e];
-  out[e] = acc;
-}
-
 // Column r of Q from the r-th normalised eigenvector f = F[r * n3 .. +n3):
 // signed so that its largest-magnitude entry (the first on ties) is positive,
 // written row-major (Q[t * p + r]); lambda[r] = f^T G f (Rayleigh quotient,
@@ -280,11 +269,6 @@ hipError_t build_q(int kind, bool f64, int n3, int p, void* Q, hipStream_t s) {
   const unsigned grid = (unsigned)(((int64_t)n3 * p + 255) / 256);
   if (f64) build_q_kernel<double><<<grid, 256, 0, s>>>(kind, n3, p, static_cast<double*>(Q));
   else build_q_kernel<float><<<grid, 256, 0, s>>>(kind, n3, p, static_cast<float*>(Q));
-  return hipGetLastError();
-}
-
-hipError_t sum_to_f64(const float* parts, int nparts, int64_t stride, int64_t count, double* out, hipStream_t s) {
-  sum_to_f64_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(parts, nparts, stride, count, out);
   return hipGetLastError();
 }
 
