@@ -289,10 +289,11 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
  * for the projection error.  A: n1 x n2 x n3 face-major, a_dtype F32 or
  * F64.  Computed as the top-p eigenvectors of the Gram matrix
  * A_(3) A_(3)^T (matrix-core product split over the n1 n2 tubes, slices
- * summed in float64) by float64 one-sided Jacobi (F32 data: Gram-form
- * sweeps to 1e-10, at most 16; F64 data: vector-form sweeps to 1e-13, at
- * most 30); each column is signed so that its largest-magnitude entry (the
- * first on ties) is positive.
+ * summed in float64) by one-sided Jacobi (F32 data: float32 Gram-form
+ * sweeps to 1e-5, at most 10, on the Gram matrix rounded to float32, then
+ * float64 Gram-form sweeps to 1e-10, at most 6; F64 data: float64
+ * vector-form sweeps to 1e-13, at most 30); each column is signed so that
+ * its largest-magnitude entry (the first on ties) is positive.
  * Outputs (float32 for F32 data, float64 for F64): Q n3 x p row-major;
  * lambda (may be NULL) p values, the eigenvalues sigma_i(A_(3))^2 as
  * Rayleigh quotients, descending.  info_dev (device int[3], may be NULL) as

@@ -107,9 +107,6 @@ constexpr double kPolishTol = 1e-13;
 // floored here (the coupling it leaves, about tol / (2 x relative gap), is
 // still far below float32 resolution).
 constexpr double kGramTolFloor = 1e-10;
-// sweep cap of the Gram-form eigen-iteration of U3 for float32 data: the
-// float64 sweeps from scratch converge in 6-10
-constexpr int kU3GramSweeps = 16;
 // sweep cap of the Gram-form phase of float64 data (from scratch: 6-12)
 constexpr int kGramSweeps64 = 16;
 constexpr int kMaxSweepsCap = 100;
@@ -591,16 +588,24 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
     else PQ_TRY(pq::sum_to_f64(static_cast<const float*>(parts), ks, n3 * n3, n3 * n3, G, stream));
   }
   // its eigenvectors: one-sided Jacobi on the symmetric positive semidefinite
-  // G (converged columns are lambda_j u_j), float64 throughout.  For float32
-  // data the Gram-form sweeps serve (their 1e-10 stopping floor leaves the
-  // eigenvectors far more accurate than the data); float64 data keeps the
-  // vector form and 1e-13.
-  PQ_TRY(hipMemcpyAsync(W, G, 8 * (size_t)n3 * n3, hipMemcpyDeviceToDevice, stream));
-  const int u3_sweeps = f64 ? kDefaultSweeps64 : kU3GramSweeps;
-  if (!f64)
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, u3_sweeps, kGramTolFloor, used, flags, stream));
-  else
-    PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, u3_sweeps, kPolishTol, used, flags, nullptr, 0, stream));
+  // G (converged columns are lambda_j u_j).  float32 data: the sweep phases
+  // of the float32 tSVDQ, float32 sweeps to the coarse threshold on G rounded
+  // to float32 (no coarser than the float32 products that formed it), then
+  // float64 Gram-form sweeps to 1e-10; float64 data: float64 vector-form
+  // sweeps to 1e-13.
+  if (!f64) {
+    float* W32 = static_cast<float*>(parts);  // the slices are summed: their space is free
+    PQ_TRY(pq::grad_narrow(G, W32, n3 * n3, stream));
+    PQ_TRY(pq::jacobi_sweeps_f32(W32, 1, in3, in3, kDefaultSweeps32, kCoarseTol32, used, flags, stream));
+    {
+      PQ_PROF("jacobi_widen", stream);
+      PQ_TRY(pq::jacobi_widen(W32, W, n3 * n3, stream));
+    }
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kPolishSweeps, kGramTolFloor, used + 1, flags, stream));
+  } else {
+    PQ_TRY(hipMemcpyAsync(W, G, 8 * (size_t)n3 * n3, hipMemcpyDeviceToDevice, stream));
+    PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, kDefaultSweeps64, kPolishTol, used, flags, nullptr, 0, stream));
+  }
   {
     PQ_PROF("jacobi_finalize", stream);
     PQ_TRY(pq::jacobi_norms_f64(W, 1, in3, in3, sig, nullptr, stream));
@@ -610,7 +615,10 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
     PQ_PROF("u3_finish", stream);
     PQ_TRY(pq::u3_finish(F, G, in3, ip, Q, lambda, f64, stream));
   }
-  if (info_dev) PQ_TRY(pq::jacobi_info(used, nullptr, 1, u3_sweeps, 0, info_dev, stream));
+  if (info_dev) {
+    if (f64) PQ_TRY(pq::jacobi_info(used, nullptr, 1, kDefaultSweeps64, 0, info_dev, stream));
+    else PQ_TRY(pq::jacobi_info(used, used + 1, 1, kDefaultSweeps32, kPolishSweeps, info_dev, stream));
+  }
   return PQ_OK;
 }
 
