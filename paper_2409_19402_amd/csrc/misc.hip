@@ -175,19 +175,34 @@ __global__ __launch_bounds__(256) void build_q_kernel(int kind, int n3, int p, T
 template <typename TO>
 __global__ __launch_bounds__(256) void u3_finish_kernel(const double* __restrict__ F, const double* __restrict__ G,
                                                         int n3, int p, TO* __restrict__ Q, TO* __restrict__ lambda) {
+  extern __shared__ double fs[];  // the eigenvector (n3 doubles)
   __shared__ double rv[256];
   __shared__ int ri[256];
   const int r = blockIdx.x;
   const double* f = F + (int64_t)r * n3;
+  for (int i = threadIdx.x; i < n3; i += 256) fs[i] = f[i];
+  __syncthreads();
   double best = -1.0;
   int bi = 0;
   double quad = 0.0;
   for (int i = threadIdx.x; i < n3; i += 256) {
-    const double a = fabs(f[i]);
+    const double a = fabs(fs[i]);
     if (a > best) { best = a; bi = i; }
-    double gi = 0.0;  // (G f)_i
-    for (int j = 0; j < n3; ++j) gi = fma(G[i + (int64_t)j * n3], f[j], gi);
-    quad = fma(f[i], gi, quad);
+    // (G f)_i: eight chains over j (mod 8), eight loads of column i in
+    // flight, summed in a fixed order
+    const double* gc = G + i;
+    double c8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int j = 0;
+    for (; j + 7 < n3; j += 8) {
+      double g[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) g[c] = gc[(int64_t)(j + c) * n3];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) c8[c] = fma(g[c], fs[j + c], c8[c]);
+    }
+    for (int c = 0; j < n3; ++j, ++c) c8[c] = fma(gc[(int64_t)j * n3], fs[j], c8[c]);
+    const double gi = ((c8[0] + c8[1]) + (c8[2] + c8[3])) + ((c8[4] + c8[5]) + (c8[6] + c8[7]));
+    quad = fma(fs[i], gi, quad);
   }
   rv[threadIdx.x] = best;
   ri[threadIdx.x] = bi;
@@ -203,7 +218,7 @@ __global__ __launch_bounds__(256) void u3_finish_kernel(const double* __restrict
     }
     __syncthreads();
   }
-  const double sgn = f[ri[0]] < 0.0 ? -1.0 : 1.0;
+  const double sgn = fs[ri[0]] < 0.0 ? -1.0 : 1.0;
   __syncthreads();
   rv[threadIdx.x] = quad;
   __syncthreads();
@@ -211,7 +226,7 @@ __global__ __launch_bounds__(256) void u3_finish_kernel(const double* __restrict
     if ((int)threadIdx.x < w) rv[threadIdx.x] += rv[threadIdx.x + w];
     __syncthreads();
   }
-  for (int t = threadIdx.x; t < n3; t += 256) Q[(int64_t)t * p + r] = static_cast<TO>(sgn * f[t]);
+  for (int t = threadIdx.x; t < n3; t += 256) Q[(int64_t)t * p + r] = static_cast<TO>(sgn * fs[t]);
   if (threadIdx.x == 0 && lambda) lambda[r] = static_cast<TO>(rv[0]);
 }
 
@@ -274,10 +289,11 @@ hipError_t build_q(int kind, bool f64, int n3, int p, void* Q, hipStream_t s) {
 
 hipError_t u3_finish(const double* F, const double* G, int n3, int p, void* Q, void* lambda, bool f64,
                      hipStream_t s) {
+  const size_t lds = 8 * (size_t)n3;  // n3 <= 4096: at most 32 KB
   if (f64)
-    u3_finish_kernel<double><<<p, 256, 0, s>>>(F, G, n3, p, static_cast<double*>(Q), static_cast<double*>(lambda));
+    u3_finish_kernel<double><<<p, 256, lds, s>>>(F, G, n3, p, static_cast<double*>(Q), static_cast<double*>(lambda));
   else
-    u3_finish_kernel<float><<<p, 256, 0, s>>>(F, G, n3, p, static_cast<float*>(Q), static_cast<float*>(lambda));
+    u3_finish_kernel<float><<<p, 256, lds, s>>>(F, G, n3, p, static_cast<float*>(Q), static_cast<float*>(lambda));
   return hipGetLastError();
 }
 
