@@ -85,3 +85,26 @@ def test_u3_video_full_size(pq):
     e_ref = oracle.fro2(Al - oracle.proj(Al, Qr))
     say(f"  projection error {e_gpu:.8e} vs oracle {e_ref:.8e}")
     assert abs(e_gpu - e_ref) <= 1e-5 * e_ref
+
+
+@pytest.mark.parametrize("dtype,n1,n2,n3", [(np.float32, 3, 2, 1), (np.float64, 3, 2, 1),
+                                            (np.float32, 4, 5, 3), (np.float64, 4, 5, 3),
+                                            (np.float32, 9, 7, 33), (np.float64, 9, 7, 33),
+                                            (np.float64, 24, 16, 256)])
+def test_u3_every_column(pq, dtype, n1, n2, n3):
+    """p = n3 (every eigenvector) at degenerate and ragged n3: one vector of
+    length one, fewer vectors than a block, a block pair plus a tail, and the
+    full 16-block width.  The spectrum is spread evenly so that each
+    eigenvector is determined; columns, signs and eigenvalues match the
+    oracle."""
+    sig = np.linspace(10.0, 1.0, n3) if n3 > 1 else [3.0]
+    A_st = _gapped(500 + n3, n1, n2, n3, sig, 0.0, dtype)
+    say(f"u3 every column {dtype.__name__} {n1}x{n2}x{n3}")
+    Q, lam, info = pq.u3(dev(A_st), n3)
+    assert int(info[1].item()) == 0
+    Qr, lamr = oracle.u3(synth.logical(A_st), n3)
+    Qg = host(Q)
+    tol = 1e-4 if dtype == np.float32 else 1e-9
+    assert np.max(np.abs(Qg - Qr)) <= tol, np.max(np.abs(Qg - Qr))
+    assert rel(host(lam), lamr) <= tol / 10
+    np.testing.assert_allclose(Qg.T @ Qg, np.eye(n3), atol=tol)
