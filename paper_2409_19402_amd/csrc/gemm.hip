@@ -112,8 +112,24 @@ __device__ __forceinline__ void tile_store(const TileRegs<R, KT>& t, float* S) {
 // step j of a K-tile takes k = j in lanes 0-31 and k = KT/2 + j in lanes
 // 32-63, so that a lane's k are consecutive and a row-major operand is read
 // four steps at a time.
+// Workgroups are dealt to the 8 XCDs round robin by their linear index, and
+// each XCD has its own L2.  With grouped set the grid is one-dimensional and
+// every tile of one slab z (a batch entry and K-slice, whose operand rows
+// the tiles share) runs on the XCD z mod 8, so that the slab is fetched into
+// one L2 instead of all eight.
+constexpr int kXcds = 8;
+struct TileIdx {
+  int x, y, z;
+};
+__device__ __forceinline__ TileIdx tile_idx(bool grouped, int mt, int nt) {
+  if (!grouped) return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
+  const int b = blockIdx.x, m = b / kXcds, per = mt * nt;
+  const int t = m % per;
+  return {t % mt, t / mt, b % kXcds + kXcds * (m / per)};
+}
+
 template <bool TA, bool TB, int VA, int VB, int KT, int TM>
-__global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk) {
+__global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk, bool grouped) {
   constexpr int TN = 4096 / TM;
   constexpr int WM = TM / 32;  // wave grid WM x (4 / WM)
   extern __shared__ __align__(16) float gsm[];
@@ -126,8 +142,10 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk) {
   const int lane = tid & 63, wave = tid >> 6;
   const int nl = lane & 31, kh = lane >> 5;
   const int wm = wave % WM, wn = wave / WM;
-  const int zb = blockIdx.z % g.batch, zs = blockIdx.z / g.batch;
-  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+  const TileIdx ti = tile_idx(grouped, (g.M + TM - 1) / TM, (g.N + TN - 1) / TN);
+  if (ti.z >= g.batch * max(1, g.ksplit)) return;  // the grouped grid's last slots
+  const int zb = ti.z % g.batch, zs = ti.z / g.batch;
+  const int m0 = ti.x * TM, n0 = ti.y * TN;
   const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
   const float* A = static_cast<const float*>(g.A) + (int64_t)zb * g.sA;
   const float* B = static_cast<const float*>(g.B) + (int64_t)zb * g.sB;
@@ -491,9 +509,13 @@ hipError_t gemm_f32_go(const Gemm& g, int kchunk, hipStream_t s) {
   static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_f32_kernel<TA, TB, VA, VB, KT, TM>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
-  const dim3 grid((unsigned)((g.M + TM - 1) / TM), (unsigned)((g.N + TN - 1) / TN),
-                  (unsigned)(g.batch * std::max(1, g.ksplit)));
-  gemm_f32_kernel<TA, TB, VA, VB, KT, TM><<<grid, 256, lds, s>>>(g, kchunk);
+  const unsigned mt = (unsigned)((g.M + TM - 1) / TM), nt = (unsigned)((g.N + TN - 1) / TN);
+  const unsigned nz = (unsigned)(g.batch * std::max(1, g.ksplit));
+  // grouped when the slabs fill the XCDs evenly (a multiple of 8, or enough
+  // that the last partial round costs little)
+  const bool grouped = nz % kXcds == 0 || nz >= 8 * kXcds;
+  const dim3 grid = grouped ? dim3(kXcds * mt * nt * ((nz + kXcds - 1) / kXcds)) : dim3(mt, nt, nz);
+  gemm_f32_kernel<TA, TB, VA, VB, KT, TM><<<grid, 256, lds, s>>>(g, kchunk, grouped);
   return hipGetLastError();
 }
 
