@@ -118,6 +118,7 @@ __device__ __forceinline__ void tile_store(const TileRegs<R, KT>& t, float* S) {
 // the tiles share) runs on the XCD z mod 8, so that the slab is fetched into
 // one L2 instead of all eight.
 constexpr int kXcds = 8;
+constexpr int kCUs = 256;
 struct TileIdx {
   int x, y, z;
 };
@@ -562,12 +563,19 @@ hipError_t gemm_launch(const Gemm& g, Prec prec, int kchunk, hipStream_t s) {
       return deep ? gemm_bf16_launch<TA, TB, 128, 2>(g, kchunk, s) : gemm_bf16_launch<TA, TB, 32, 2>(g, kchunk, s);
     case Prec::BF16x6:
       return deep ? gemm_bf16_launch<TA, TB, 64, 3>(g, kchunk, s) : gemm_bf16_launch<TA, TB, 32, 3>(g, kchunk, s);
-    default:
+    default: {
       // outputs of at most 32 rows and more than 64 columns (the dQ
       // products) take the 32 x 128 tile, whose deep K-tile is 64 (LDS)
-      if (g.M <= 32 && g.N > 64)
-        return deep ? gemm_f32_launch<TA, TB, 64, 32>(g, kchunk, s) : gemm_f32_launch<TA, TB, 32, 32>(g, kchunk, s);
-      return deep ? gemm_f32_launch<TA, TB, 128, 64>(g, kchunk, s) : gemm_f32_launch<TA, TB, 32, 64>(g, kchunk, s);
+      const bool narrow = g.M <= 32 && g.N > 64;
+      const int tm = narrow ? 32 : 64, tn = 4096 / tm;
+      const int64_t wgs = (int64_t)((g.M + tm - 1) / tm) * ((g.N + tn - 1) / tn) * g.batch * std::max(1, g.ksplit);
+      // a deep K-tile's LDS leaves one workgroup per CU: a split-K grid with
+      // more workgroups than CUs takes the shallow one (several per CU)
+      const bool d = deep && (g.ksplit <= 1 || wgs <= kCUs);
+      if (narrow)
+        return d ? gemm_f32_launch<TA, TB, 64, 32>(g, kchunk, s) : gemm_f32_launch<TA, TB, 32, 32>(g, kchunk, s);
+      return d ? gemm_f32_launch<TA, TB, 128, 64>(g, kchunk, s) : gemm_f32_launch<TA, TB, 32, 64>(g, kchunk, s);
+    }
   }
 }
 
