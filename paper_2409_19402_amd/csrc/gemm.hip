@@ -103,15 +103,6 @@ __device__ __forceinline__ void tile_store(const TileRegs<R, KT>& t, float* S) {
   }
 }
 
-// C tile (TM x TN) = A (TM x K) B (K x TN) over K-tiles of KT, double
-// buffered in LDS (dynamic: 2 (tile_floats<TM, KT>() + tile_floats<TN, KT>())
-// floats): the next tile's global loads are in flight while the MFMAs of the
-// current one run.  The MFMA computes the transposed tile (rows = output
-// columns), so the 32 lanes sharing an accumulator register hold 32
-// consecutive rows of the column-major output and stores coalesce.  MFMA
-// step j of a K-tile takes k = j in lanes 0-31 and k = KT/2 + j in lanes
-// 32-63, so that a lane's k are consecutive and a row-major operand is read
-// four steps at a time.
 // Workgroups are dealt to the 8 XCDs round robin by their linear index, and
 // each XCD has its own L2.  With grouped set the grid is one-dimensional and
 // every tile of one slab z (a batch entry and K-slice, whose operand rows
@@ -129,6 +120,15 @@ __device__ __forceinline__ TileIdx tile_idx(bool grouped, int mt, int nt) {
   return {t % mt, t / mt, b % kXcds + kXcds * (m / per)};
 }
 
+// C tile (TM x TN) = A (TM x K) B (K x TN) over K-tiles of KT, double
+// buffered in LDS (dynamic: 2 (tile_floats<TM, KT>() + tile_floats<TN, KT>())
+// floats): the next tile's global loads are in flight while the MFMAs of the
+// current one run.  The MFMA computes the transposed tile (rows = output
+// columns), so the 32 lanes sharing an accumulator register hold 32
+// consecutive rows of the column-major output and stores coalesce.  MFMA
+// step j of a K-tile takes k = j in lanes 0-31 and k = KT/2 + j in lanes
+// 32-63, so that a lane's k are consecutive and a row-major operand is read
+// four steps at a time.
 template <bool TA, bool TB, int VA, int VB, int KT, int TM>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(Gemm g, int kchunk, bool grouped) {
   constexpr int TN = 4096 / TM;
