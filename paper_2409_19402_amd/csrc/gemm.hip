@@ -513,7 +513,7 @@ hipError_t gemm_f32_go(const Gemm& g, int kchunk, hipStream_t s) {
   const unsigned mt = (unsigned)((g.M + TM - 1) / TM), nt = (unsigned)((g.N + TN - 1) / TN);
   const unsigned nz = (unsigned)(g.batch * std::max(1, g.ksplit));
   // grouped when the slabs fill the XCDs evenly (a multiple of 8, or enough
-  // that the last partial round costs little)
+  // that the last, partial pass over the XCDs costs little)
   const bool grouped = nz % kXcds == 0 || nz >= 8 * kXcds;
   const dim3 grid = grouped ? dim3(kXcds * mt * nt * ((nz + kXcds - 1) / kXcds)) : dim3(mt, nt, nz);
   gemm_f32_kernel<TA, TB, VA, VB, KT, TM><<<grid, 256, lds, s>>>(g, kchunk, grouped);
