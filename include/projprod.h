@@ -292,8 +292,10 @@ int pq_proj_backward(const void* G, const void* A, const void* Q, int dtype,
  * summed in float64) by one-sided Jacobi (F32 data: float32 Gram-form
  * sweeps to 1e-5, at most 10, on the Gram matrix rounded to float32, then
  * float64 Gram-form sweeps to 1e-10, at most 6; F64 data: float64
- * vector-form sweeps to 1e-13, at most 30); each column is signed so that
- * its largest-magnitude entry (the first on ties) is positive.
+ * Gram-form sweeps to 1e-13, at most 16, then float64 vector-form sweeps
+ * to 1e-13, at most 6, only if the Gram form stopped short); each column is
+ * signed so that its largest-magnitude entry (the first on ties) is
+ * positive.
  * Outputs (float32 for F32 data, float64 for F64): Q n3 x p row-major;
  * lambda (may be NULL) p values, the eigenvalues sigma_i(A_(3))^2 as
  * Rayleigh quotients, descending.  info_dev (device int[3], may be NULL) as

@@ -591,8 +591,9 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
   // G (converged columns are lambda_j u_j).  float32 data: the sweep phases
   // of the float32 tSVDQ, float32 sweeps to the coarse threshold on G rounded
   // to float32 (no coarser than the float32 products that formed it), then
-  // float64 Gram-form sweeps to 1e-10; float64 data: float64 vector-form
-  // sweeps to 1e-13.
+  // float64 Gram-form sweeps to 1e-10; float64 data: the phases of the
+  // float64 tSVDQ, float64 Gram-form sweeps to 1e-13, then vector-form sweeps
+  // (angles from the vectors themselves) only if the Gram form stopped short.
   if (!f64) {
     float* W32 = static_cast<float*>(parts);  // the slices are summed: their space is free
     PQ_TRY(pq::grad_narrow(G, W32, n3 * n3, stream));
@@ -604,7 +605,9 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
     PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kPolishSweeps, kGramTolFloor, used + 1, flags, stream));
   } else {
     PQ_TRY(hipMemcpyAsync(W, G, 8 * (size_t)n3 * n3, hipMemcpyDeviceToDevice, stream));
-    PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, kDefaultSweeps64, kPolishTol, used, flags, nullptr, 0, stream));
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kGramSweeps64, kPolishTol, used, flags, stream));
+    PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, kPolishSweeps, kPolishTol, used + 1, flags, used, kGramSweeps64,
+                                 stream));
   }
   {
     PQ_PROF("jacobi_finalize", stream);
@@ -616,7 +619,7 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
     PQ_TRY(pq::u3_finish(F, G, in3, ip, Q, lambda, f64, stream));
   }
   if (info_dev) {
-    if (f64) PQ_TRY(pq::jacobi_info(used, nullptr, 1, kDefaultSweeps64, 0, info_dev, stream));
+    if (f64) PQ_TRY(pq::jacobi_info(used, used + 1, 1, kGramSweeps64, kPolishSweeps, info_dev, stream));
     else PQ_TRY(pq::jacobi_info(used, used + 1, 1, kDefaultSweeps32, kPolishSweeps, info_dev, stream));
   }
   return PQ_OK;
