@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_MFMA_PEAK = 157.3         # TFLOP/s dense
 FP64_VALU_PEAK = 78.6          # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 BF16_MFMA_PEAK = 2500.0        # TFLOP/s dense
+FP64_MFMA_PEAK = 78.6          # TFLOP/s dense
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE
 # and WRITE_SIZE runs of the same workload, scaled by the plain-copy
@@ -69,7 +70,7 @@ def parse():
     ap.add_argument("--workload", default="video",
                     choices=["video", "hyper", "diff", "tiny", "copy", "hat-video", "hat-hyper",
                              "proj-video", "qprod", "batched", "svdii-video", "u3-video",
-                             "tsvdq-backward-video"])
+                             "u3-video-f64", "tsvdq-backward-video"])
     ap.add_argument("--count", type=int, default=64, help="instances of the batched workload")
     ap.add_argument("--prec", default="default")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -293,9 +294,11 @@ def main():
         dtype = "f32"
         Al, Qn, Gl, sb = synth.logical(c["A"]), c["Q"], synth.logical(host_of(Gbar)), sbar.cpu().numpy()
         cpu_case = (lambda: oracle_mod().tsvdq_backward(Al, Qn, k, Gl, sb), "tsvdq_backward (float64 SVD perturbation)")
-    elif args.workload == "u3-video":
+    elif args.workload in ("u3-video", "u3-video-f64"):
         c = synth.video_case()
-        A = up(c["A"])
+        f64 = args.workload == "u3-video-f64"
+        A_st = c["A"].astype(np.float64) if f64 else c["A"]
+        A = up(A_st)
         n1, n2, n3 = A.shape
         p = 20
         N = n1 * n2
@@ -303,12 +306,13 @@ def main():
         def step():
             return pq.u3(A, p)
         flops = 2.0 * N * n3 * n3 + svd_nominal_flops(n3, n3, 1)
-        models = {"u3_gram": ("mfma", 2.0 * N * n3 * n3)}
+        models = {"u3_gram": ("mfma64" if f64 else "mfma", 2.0 * N * n3 * n3)}
         models.update(jacobi_models(svd_nominal_flops(n3, n3, 1)))
-        info = {"workload": "Q = U3(:, 1:20) of the video-shaped 240x320x200 fp32 cube",
+        info = {"workload": "Q = U3(:, 1:20) of the video-shaped 240x320x200 "
+                            + ("cube in float64" if f64 else "fp32 cube"),
                 "n1": n1, "n2": n2, "n3": n3, "p": p}
-        dtype = "f32"
-        Al = synth.logical(c["A"])
+        dtype = "f64" if f64 else "f32"
+        Al = synth.logical(A_st)
         cpu_case = (lambda: oracle_mod().u3(Al, p), "u3 (Gram eigen route of the oracle)")
     elif args.workload in ("hat-video", "hat-hyper", "proj-video"):
         if args.workload == "hat-hyper":
@@ -510,9 +514,12 @@ def main():
                 achieved, peak, unit = units / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
             elif bound == "alu":
                 achieved, peak, unit = units / avg_s / 1e12, FP64_VALU_PEAK, "TFLOP/s"
+            elif bound == "mfma64":
+                achieved, peak, unit = units / avg_s / 1e12, FP64_MFMA_PEAK, "TFLOP/s"
             else:
                 achieved, peak, unit = units / avg_s / 1e12, FP32_MFMA_PEAK, "TFLOP/s"
-            roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 4), "peak": peak,
+            roof = {"kernel": dom, "bound": "mfma" if bound == "mfma64" else bound,
+                    "achieved": round(achieved, 4), "peak": peak,
                     "unit": unit, "frac": round(achieved / peak, 6),
                     "traffic": TRAFFIC_BYTES.get((args.workload, args.prec, dom)),
                     "avg_us": round(kernels[dom]["avg_us"], 3)}
