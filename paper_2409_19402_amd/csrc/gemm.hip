@@ -377,7 +377,7 @@ __device__ __forceinline__ void tile64_store(const Tile64<R>& t, double* S) {
 }
 
 template <bool TA, bool TB, int TN>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g, int kchunk) {
+__global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g, int kchunk, bool grouped) {
   constexpr int TM = 64, KT = kKT64;
   constexpr int WN = TN >= 32 ? 2 : 1, WM = 4 / WN;  // wave grid
   constexpr int SM = TM / 16 / WM, SN = TN / 16 / WN;  // 16 x 16 blocks per wave
@@ -387,8 +387,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(Gemm g, int kchunk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   const int wm = wave % WM, wn = wave / WM;
-  const int zb = blockIdx.z % g.batch, zs = blockIdx.z / g.batch;
-  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+  const TileIdx ti = tile_idx(grouped, (g.M + TM - 1) / TM, (g.N + TN - 1) / TN);
+  if (ti.z >= g.batch * max(1, g.ksplit)) return;  // the grouped grid's last slots
+  const int zb = ti.z % g.batch, zs = ti.z / g.batch;
+  const int m0 = ti.x * TM, n0 = ti.y * TN;
   const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
   const double* A = static_cast<const double*>(g.A) + (int64_t)zb * g.sA;
   const double* B = static_cast<const double*>(g.B) + (int64_t)zb * g.sB;
@@ -592,11 +594,14 @@ hipError_t gemm_f32(const Gemm& g, Prec prec, hipStream_t s) {
 template <bool TA, bool TB>
 hipError_t gemm_f64_go(const Gemm& g, int kchunk, hipStream_t s) {
   const unsigned gz = (unsigned)(g.batch * std::max(1, g.ksplit));
+  const unsigned mt = (unsigned)((g.M + 63) / 64), nt = g.N <= 16 ? 1u : (unsigned)((g.N + 63) / 64);
+  // grouped by slab on the XCDs under the same condition as the float32 kernel
+  const bool grouped = gz % kXcds == 0 || gz >= 8 * kXcds;
+  const dim3 grid = grouped ? dim3(kXcds * mt * nt * ((gz + kXcds - 1) / kXcds)) : dim3(mt, nt, gz);
   if (g.N <= 16) {
-    gemm_f64_kernel<TA, TB, 16><<<dim3((unsigned)((g.M + 63) / 64), 1, gz), 256, 0, s>>>(g, kchunk);
+    gemm_f64_kernel<TA, TB, 16><<<grid, 256, 0, s>>>(g, kchunk, grouped);
   } else {
-    gemm_f64_kernel<TA, TB, 64><<<dim3((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64), gz), 256, 0, s>>>(
-        g, kchunk);
+    gemm_f64_kernel<TA, TB, 64><<<grid, 256, 0, s>>>(g, kchunk, grouped);
   }
   return hipGetLastError();
 }
