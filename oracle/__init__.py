@@ -41,8 +41,12 @@ PARITY = {
     "tsvdq": "pinned: Example 4.1 printed errors, Thm 4.2 identity, Cor 4.1, "
              "Eckart-Young optimality, full-rank reduction to proj",
     "tsvdq_ii": "pinned: Thm 4.5 (SVDII error <= tSVDQ error at equal storage), "
-                "gamma=1 reduction",
-    "qprod_backward/proj_backward": "pinned: central finite differences and "
+                "gamma=1 reduction, the exact K and multirank of diagonal faces with gamma "
+                "strictly between consecutive energy fractions (ties ordered face-major)",
+    "relative_error": "pinned: Example 4.1 (RE = sqrt(3)/2 and sqrt(2)/2 from the printed squared "
+                      "errors and the printed entries) and closed forms",
+    "qprod_backward/proj_backward": "pinned: central finite differences (tiny tensors, and "
+                                    "qprod_backward at the full differentiation size) and "
                                     "torch CPU float64 autograd",
     "tsvdq_backward": "pinned: central finite differences of <Gbar, A_k> + <sbar, s> "
                       "(tall, wide and square faces, k = 1 and k = min(n1, n2)) and "

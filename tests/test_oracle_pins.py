@@ -562,3 +562,138 @@ def test_orthonormalize_q_fixed_point_and_dependent_column():
     Qd[:, 3] = Qd[:, 0] - 2.0 * Qd[:, 2]
     W, info = oracle.orthonormalize_q(Qd)
     assert W is None and info == 4
+
+
+# ---------------------------------------------------------------------------
+# RE (Sec. 5.1.2) and the threshold rule of Alg. 4.2
+# ---------------------------------------------------------------------------
+
+def test_relative_error_example_4_1_and_closed_forms():
+    """RE = ||A - Atilde||_F / ||A||_F (Sec. 5.1.2).  Example 4.1 prints the
+    squared errors 3 (Q = e1) and 2 (the Haar column); ||A||_F^2 is the sum of
+    squares of the printed entries, 4, so RE is sqrt(3)/2 and sqrt(2)/2.  A
+    dropped square root (3/4, 1/2) or a missing normalisation (sqrt 3, sqrt 2)
+    fails; so does a swapped argument order on the closed forms below."""
+    A, g = example41_tensor()
+    norm2 = 0.0
+    for key in ("face1_row0", "face1_row1", "face2_row0", "face2_row1"):
+        for v in g[key]:
+            norm2 += v * v
+    assert norm2 == 4.0
+    k = int(g["k"][0])
+    for qkey, ekey, scale in (("Q_u3", "err2_u3", 1.0),
+                              ("Q_haar_scaled_by_sqrt2", "err2_haar", 1 / math.sqrt(2))):
+        Q = scale * np.array(g[qkey]).reshape(2, 1)
+        res = oracle.tsvdq(A, Q, k)
+        want = math.sqrt(g[ekey][0] / norm2)
+        assert oracle.relative_error(A, res.Ak) == pytest.approx(want, abs=1e-14)
+    assert math.sqrt(3) / 2 == pytest.approx(math.sqrt(3.0 / 4.0))
+    # closed forms: Atilde = c A has RE |1 - c|; Atilde = 0 has RE 1; RE is
+    # measured relative to the first argument
+    rng = np.random.default_rng(30)
+    X = rng.standard_normal((3, 4, 5))
+    for c in (0.0, 0.25, 0.5, 2.0, -1.0):
+        assert oracle.relative_error(X, c * X) == pytest.approx(abs(1.0 - c), rel=1e-14, abs=1e-15)
+    assert oracle.relative_error(2.0 * X, X) == pytest.approx(0.5, rel=1e-14)
+
+
+# the global descending order of the SVDII example below, with the owner face
+# of each value: equal values (the two 3s) ordered face-major (reading of the
+# tie in Alg. 4.2's permutation)
+_SVDII_FACES = [[5.0, 3.0, 1.0, 0.5], [4.0, 2.0, 0.75, 0.125], [6.0, 3.0, 0.875, 0.25]]
+_SVDII_ORDER = [(6.0, 2), (5.0, 0), (4.0, 1), (3.0, 0), (3.0, 2), (2.0, 1), (1.0, 0), (0.875, 2),
+                (0.75, 1), (0.5, 0), (0.25, 2), (0.125, 1)]
+
+
+def _svdii_diagonal_case():
+    """Q = I with p = n3 = 3, so the transform-domain faces are A's own faces;
+    each is diagonal, so LAPACK returns its singular values exactly."""
+    A = np.zeros((4, 4, 3))
+    for l, vals in enumerate(_SVDII_FACES):
+        A[:, :, l] = np.diag(vals)
+    return A, np.eye(3)
+
+
+@pytest.mark.parametrize("K", list(range(1, 13)))
+def test_tsvdq_ii_threshold_rule(K):
+    """Alg. 4.2 keeps the first K values of the global descending order, K the
+    first count whose energy fraction reaches gamma.  With gamma strictly
+    between the fractions of K - 1 and K values, K is fixed exactly: a K one
+    too large or one too small changes rho.sum().  The multirank rho and the
+    approximation (each diagonal face keeps its rho_i largest entries) are
+    checked entry by entry; K = 4 splits the tie of the two 3s, which the
+    face-major order gives to face 0."""
+    A, Q = _svdii_diagonal_case()
+    e = [0.0]
+    for v, _ in _SVDII_ORDER:
+        e.append(e[-1] + v * v)
+    total = e[-1]
+    gamma = 0.5 * (e[K - 1] + e[K]) / total
+    rho, Ak = oracle.tsvdq_ii(A, Q, gamma)
+    want = [0, 0, 0]
+    for _, face in _SVDII_ORDER[:K]:
+        want[face] += 1
+    assert int(rho.sum()) == K
+    assert rho.tolist() == want
+    ref = np.zeros_like(A)
+    for l, vals in enumerate(_SVDII_FACES):
+        keep = sorted(vals, reverse=True)[:want[l]]
+        ref[:, :, l] = np.diag([v if v in keep else 0.0 for v in vals])
+    np.testing.assert_allclose(Ak, ref, atol=1e-14)
+
+
+def test_tsvdq_ii_threshold_extremes():
+    """gamma = 1 keeps every value (K = r p); a gamma below the first value's
+    fraction keeps only the largest value (K = 1)."""
+    A, Q = _svdii_diagonal_case()
+    rho, Ak = oracle.tsvdq_ii(A, Q, 1.0)
+    assert rho.tolist() == [4, 4, 4]
+    np.testing.assert_allclose(Ak, A, atol=1e-14)
+    rho, _ = oracle.tsvdq_ii(A, Q, 1e-6)
+    assert rho.tolist() == [0, 0, 1]
+
+
+# ---------------------------------------------------------------------------
+# Gradients at the differentiation workload's full size
+# ---------------------------------------------------------------------------
+
+def test_qprod_backward_finite_differences_full_size():
+    """The adjoint of L = ||A *_Q B - T||_F^2 at A 256x128x128, B 128x256x128,
+    Q 128x16 (the differentiation workload) against central differences with
+    h = 1e-3 in float64: 8 random unit directions per argument and 16 random
+    single entries.  L is quadratic in A alone and in B alone, so their
+    differences carry rounding only: |dL| is about 2e-16 log2(N) L over
+    N = 8.4e6 summed squares, which after the division by 2h bounds the error
+    by 2e-9 ||dX||_F.  L has degree 6 in Q: the O(h^2) term leaves a relative
+    error of a few 1e-6, held to 1e-5."""
+    c = synth.differentiation_case()
+    A, B, T = (synth.logical(c[x]).astype(np.float64) for x in "ABT")
+    Q = c["Q"].astype(np.float64)
+    G = 2 * (oracle.qprod(A, B, Q) - T)
+    dA, dB, dQ = oracle.qprod_backward(G, A, B, Q)
+    h = 1e-3
+    rng = np.random.default_rng(31)
+
+    def fd(X, D):
+        args_p = [X + h * D if Y is X else Y for Y in (A, B, Q)]
+        args_m = [X - h * D if Y is X else Y for Y in (A, B, Q)]
+        return (_loss(*args_p, T) - _loss(*args_m, T)) / (2 * h)
+
+    def check(X, dX, D, an):
+        err = abs(fd(X, D) - an)
+        if X is Q:
+            assert err <= 1e-5 * abs(an) + 2e-9 * np.linalg.norm(dX)
+        else:
+            assert err <= 2e-9 * np.linalg.norm(dX)
+
+    for X, dX in ((A, dA), (B, dB), (Q, dQ)):
+        for _ in range(8):
+            D = rng.standard_normal(X.shape)
+            D /= np.linalg.norm(D)
+            check(X, dX, D, float(np.sum(dX * D)))
+    for j in range(16):
+        X, dX = ((A, dA), (B, dB), (Q, dQ))[j % 3]
+        idx = tuple(int(rng.integers(0, s)) for s in X.shape)
+        E = np.zeros_like(X)
+        E[idx] = 1.0
+        check(X, dX, E, float(dX[idx]))
