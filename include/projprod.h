@@ -141,6 +141,20 @@ int pq_check_q(const void* Q, int q_dtype, int64_t n3, int64_t p,
                double* out_dev, hipStream_t stream);
 
 /*
+ * The same precondition as a device-side status flag.  The products and the
+ * tSVDQ do not check Q themselves (a check costs a launch and Q is usually
+ * reused across many calls); a caller that wants the check in front of them
+ * without a host round trip -- inside a captured graph, or in a loop that
+ * polls the flag later -- enqueues this call first on the same stream.
+ * Writes the distance max_ij |(Q^T Q - I_p)_ij| to dist_dev (one double, as
+ * pq_check_q) and to flag_dev (one int32) 1 when that distance exceeds tol or
+ * is not a number, 0 otherwise.  tol >= 0, else PQ_ERR_ARG (NaN included).
+ * q_dtype PQ_F32 or PQ_F64.  Workspace: none.
+ */
+int pq_check_q_flag(const void* Q, int q_dtype, int64_t n3, int64_t p, double tol,
+                    double* dist_dev, int* flag_dev, hipStream_t stream);
+
+/*
  * Q (n3 x p, row-major, q_dtype F32 or F64) of one of the fixed transforms
  * that Sec. 5 compares with the data-dependent U3 (pq_u3):
  *   PQ_Q_IDENTITY  the first p columns of I_n3;

@@ -28,6 +28,7 @@ SIGNATURES = {
                                 ctypes.POINTER(ctypes.c_int)]),
     "pq_profile_names": (_i32, [ctypes.c_char_p, _sz]),
     "pq_check_q": (_i32, [_vp, _i32, _i64, _i64, _vp, _vp]),
+    "pq_check_q_flag": (_i32, [_vp, _i32, _i64, _i64, _dbl, _vp, _vp, _vp]),
     "pq_hat": (_i32, [_vp, _i32, _vp, _vp, _i64, _i64, _i64, _i64, _i32, _vp]),
     "pq_unhat": (_i32, [_vp, _vp, _vp, _i32, _i64, _i64, _i64, _i64, _i32, _vp]),
     "pq_proj_workspace": (_sz, [_i64, _i64, _i64, _i64, _i32]),

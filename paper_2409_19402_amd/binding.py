@@ -20,7 +20,7 @@ from ._lib import PQ_F32, PQ_F64, PQ_BF16, PREC, call
 __all__ = [
     "empty", "from_storage", "is_face_major", "to_face_major", "to_tube_major",
     "autotune", "autotune_save", "autotune_load",
-    "check_q", "orthonormalize_q", "hat", "unhat", "proj", "facewise",
+    "check_q", "check_q_flag", "orthonormalize_q", "hat", "unhat", "proj", "facewise",
     "qprod", "qprod_backward", "proj_backward", "tsvdq", "TSVDQ", "QProd", "Proj",
     "Batch", "batched", "u3",
 ]
@@ -118,6 +118,21 @@ def check_q(Q):
     return out
 
 
+def check_q_flag(Q, tol):
+    """(dist, flag): the float64 distance max |Q^T Q - I| as a 0-d device
+    tensor and an int32 device flag, 1 when the distance exceeds tol or is not
+    a number (the Def. 3.1 precondition checked on the device, without a host
+    round trip)."""
+    if Q.dtype not in (torch.float32, torch.float64):
+        raise TypeError("Q must be float32 or float64")
+    Q = _q(Q, Q.dtype)
+    dist = torch.empty((), dtype=torch.float64, device=Q.device)
+    flag = torch.empty((), dtype=torch.int32, device=Q.device)
+    call("pq_check_q_flag", _ptr(Q), _DT[Q.dtype], Q.shape[0], Q.shape[1], float(tol), _ptr(dist),
+         _ptr(flag), _stream(Q.device))
+    return dist, flag
+
+
 def orthonormalize_q(Q, out=None):
     """(Qout, info): Q re-orthonormalised by CholeskyQR2 in float64 (the Q
     factor of the thin QR with positive diagonal R; float32 Q gives float32
@@ -132,7 +147,7 @@ def orthonormalize_q(Q, out=None):
         out = torch.empty_like(Q)
     elif out.dtype != Q.dtype or tuple(out.shape) != (n3, p) or not out.is_contiguous():
         raise ValueError("out must be a contiguous tensor of Q's shape and dtype")
-    info = torch.zeros(1, dtype=torch.int32, device=Q.device)
+    info = torch.empty(1, dtype=torch.int32, device=Q.device)
     lib = _lib.load()
     wsb, nb = _ws(lib.pq_orthonormalize_q_workspace(n3, p), Q.device)
     call("pq_orthonormalize_q", _ptr(Q), _DT[Q.dtype], n3, p, _ptr(out), _ptr(info), _ptr(wsb), nb,
@@ -353,17 +368,27 @@ def build_q(kind, n3, p, dtype=torch.float32, device="cuda"):
     return Q
 
 
-def u3(A, p):
+def _info(info, n, dev):
+    """The caller's int32 info tensor of n entries (every entry is written by
+    the library), or a new uninitialised one."""
+    if info is None:
+        return torch.empty(n, dtype=torch.int32, device=dev)
+    if info.dtype != torch.int32 or info.numel() != n or not info.is_contiguous() or info.device != dev:
+        raise ValueError(f"info must be a contiguous int32 tensor of {n} entries on the data's device")
+    return info
+
+
+def u3(A, p, info=None):
     """Q = U3(:, :p) of A (Thm. 4.3): the leading p left singular vectors of
     the mode-3 unfolding, as an (n3, p) tensor (float32, or float64 for
     float64 data), with the eigenvalues sigma_i(A_(3))^2 (p,) and the Jacobi
-    info int32[3]."""
+    info int32[3] (`info`, when given, receives it)."""
     _tensor(A, "A", (torch.float32, torch.float64))
     n1, n2, n3 = A.shape
     dev = A.device
     Q = torch.empty((n3, p), dtype=A.dtype, device=dev)
     lam = torch.empty(p, dtype=A.dtype, device=dev)
-    info = torch.zeros(3, dtype=torch.int32, device=dev)
+    info = _info(info, 3, dev)
     lib = _lib.load()
     wsb, nb = _ws(lib.pq_u3_workspace(n1, n2, n3, p, _DT[A.dtype]), dev)
     call("pq_u3", _ptr(A), _DT[A.dtype], n1, n2, n3, p, _ptr(Q), _ptr(lam), _ptr(info), _ptr(wsb), nb,
@@ -371,11 +396,11 @@ def u3(A, p):
     return Q, lam, info
 
 
-def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_sweeps=0):
+def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_sweeps=0, info=None):
     """Truncated *_Q-SVD (Alg. 4.1).  Returns TSVDQ(Uhat n1 x k x p,
     s (k, p), Vhat n2 x k x p, Uk, Sk (k, n3), Vk [spatial=True], Ak
     [approx=True], info = int32 device tensor [max sweeps, unconverged faces,
-    total sweeps])."""
+    total sweeps] (`info`, when given, receives it))."""
     _tensor(A, "A")
     _q(Q, A.dtype)
     n1, n2, n3 = A.shape
@@ -391,7 +416,7 @@ def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_swe
     Vk = empty(n2, k, n3, od, dev) if spatial else None
     Sk = torch.empty((n3, k), dtype=od, device=dev) if spatial else None
     Ak = empty(n1, n2, n3, od, dev) if approx else None
-    info = torch.zeros(3, dtype=torch.int32, device=dev)
+    info = _info(info, 3, dev)
     lib = _lib.load()
     wsb, nb = _ws(lib.pq_tsvdq_workspace(n1, n2, n3, p, k, _DT[A.dtype]), dev)
     call("pq_tsvdq", _ptr(A), _DT[A.dtype], _ptr(Q), n1, n2, n3, p, k, PREC[prec], _ptr(Uh),
@@ -401,12 +426,12 @@ def tsvdq(A, Q, k, prec="default", spatial=False, approx=False, tol=0.0, max_swe
 
 
 def tsvdq_backward(A, Q, k, Gbar=None, sbar=None, need=(True, True), gap_tol=0.0, tol=0.0,
-                   max_sweeps=0):
+                   max_sweeps=0, info=None):
     """(dA, dQ, info) of L given Gbar = dL/dA_k (n1 x n2 x n3) and/or
     sbar = dL/ds ((k, p), as tsvdq returns s), for the rank-k tSVDQ of A;
     entries of `need` that are False come back as None.  info is the int32
     device tensor [max sweeps, unconverged faces, total sweeps, dropped
-    near-degenerate pairs]."""
+    near-degenerate pairs] (`info`, when given, receives it)."""
     _tensor(A, "A", (torch.float32, torch.float64))
     _q(Q, A.dtype)
     n1, n2, n3 = A.shape
@@ -422,7 +447,7 @@ def tsvdq_backward(A, Q, k, Gbar=None, sbar=None, need=(True, True), gap_tol=0.0
         sbar = sbar.to(dt).t().contiguous()  # element (j, l) at j + l k
     dA = empty(n1, n2, n3, dt, A.device) if need[0] else None
     dQ = torch.empty((n3, p), dtype=dt, device=A.device) if need[1] else None
-    info = torch.zeros(4, dtype=torch.int32, device=A.device)
+    info = _info(info, 4, A.device)
     lib = _lib.load()
     wsb, nb = _ws(lib.pq_tsvdq_backward_workspace(n1, n2, n3, p, k, _DT[dt]), A.device)
     call("pq_tsvdq_backward", _ptr(A), _DT[dt], _ptr(Q), n1, n2, n3, p, k, _ptr(Gbar), _ptr(sbar),
@@ -461,7 +486,7 @@ def tsvdq_approx(A, Q, k, prec="default"):
 SVDII = namedtuple("SVDII", "Uhat s Vhat rho Ak info")
 
 
-def svdii(A, Q, gamma, kmax=None, prec="default", approx=False, tol=0.0, max_sweeps=0):
+def svdii(A, Q, gamma, kmax=None, prec="default", approx=False, tol=0.0, max_sweeps=0, info=None):
     """*_Q-SVDII (Alg. 4.2): per-face ranks rho from one energy threshold
     gamma over the singular values of every face.  Returns SVDII(Uhat
     n1 x kmax x p, s (kmax, p), Vhat n2 x kmax x p with face l's columns
@@ -481,7 +506,7 @@ def svdii(A, Q, gamma, kmax=None, prec="default", approx=False, tol=0.0, max_swe
     s = torch.empty((p, k), dtype=od, device=dev)
     rho = torch.empty(p, dtype=torch.int32, device=dev)
     Ak = empty(n1, n2, n3, od, dev) if approx else None
-    info = torch.zeros(3, dtype=torch.int32, device=dev)
+    info = _info(info, 3, dev)
     lib = _lib.load()
     wsb, nb = _ws(lib.pq_svdii_workspace(n1, n2, n3, p, k, _DT[A.dtype]), dev)
     call("pq_svdii", _ptr(A), _DT[A.dtype], _ptr(Q), n1, n2, n3, p, float(gamma), k, PREC[prec],
@@ -542,7 +567,7 @@ class Batch:
         nbytes = _lib.ctypes.c_size_t()
         call("pq_batched_workspace", _lib.ctypes.byref(arr), len(instances), _lib.ctypes.byref(nbytes))
         self._ws, nb = _ws(nbytes.value, dev)
-        self.info = torch.zeros(3, dtype=torch.int32, device=dev)
+        self.info = torch.empty(3, dtype=torch.int32, device=dev)
         self._arr = arr
         h = _lib.ctypes.c_void_p()
         call("pq_batched_plan", _lib.ctypes.byref(arr), len(instances), int(max_sweeps), float(tol),

@@ -274,6 +274,19 @@ int pq_check_q(const void* Q, int q_dtype, int64_t n3, int64_t p, double* out_de
   return PQ_OK;
 }
 
+int pq_check_q_flag(const void* Q, int q_dtype, int64_t n3, int64_t p, double tol, double* dist_dev, int* flag_dev,
+                    hipStream_t stream) {
+  if (!Q || !dist_dev || !flag_dev) return PQ_ERR_NULL;
+  PQ_CHECK(check_ar_dtype(q_dtype));
+  PQ_CHECK(check_dims({n3}));
+  PQ_CHECK(check_p(n3, p));
+  if (!(tol >= 0.0)) return PQ_ERR_ARG;
+  PQ_PROF("check_q", stream);
+  PQ_TRY(pq::check_q_launch(Q, is_f64(q_dtype), (int)n3, (int)p, dist_dev, stream));
+  PQ_TRY(pq::check_q_flag(dist_dev, tol, flag_dev, stream));
+  return PQ_OK;
+}
+
 int pq_build_q(int kind, int64_t n3, int64_t p, int q_dtype, void* Q, hipStream_t stream) {
   if (!Q) return PQ_ERR_NULL;
   if (kind != PQ_Q_IDENTITY && kind != PQ_Q_DCT) return PQ_ERR_ARG;
@@ -561,6 +574,7 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
   if (a_dtype != PQ_F32 && a_dtype != PQ_F64) return PQ_ERR_DTYPE;
   PQ_CHECK(check_dims({n1, n2, n3}));
   PQ_CHECK(check_p(n3, p));
+  PQ_CHECK(check_area(n1, n2));  // the Gram product's depth is n1 n2
   if (n3 > 4096) return PQ_ERR_UNSUPPORTED;
   for (const void* o : {Q, lambda})
     if (o && o == A) return PQ_ERR_ALIAS;

@@ -98,6 +98,7 @@ hipError_t u3_finish(const double* F, const double* G, int n3, int p, void* Q, v
                      hipStream_t s);
 // max |(Q^T Q - I)_ab| into out[0] (float64): two launches, the first clears out
 hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, hipStream_t s);
+hipError_t check_q_flag(const double* dist, double tol, int* flag, hipStream_t s);
 // dst = src in the other layout: tube-major (t + n3 (j + n2 i)) to face-major
 // (i + n1 (j + n2 t)) when to_face, the reverse otherwise; elements of
 // elem_bytes (2, 4 or 8) bytes; (ceil(n3 / 32) n2, ceil(n1 / 32)) workgroups

@@ -40,6 +40,12 @@ __global__ void clear_q_kernel(unsigned long long* __restrict__ out) {
   if (threadIdx.x == 0) out[0] = 0ull;
 }
 
+// flag[0] = 1 when the distance dist[0] exceeds tol or is not a number
+// (a NaN's bit pattern wins the integer maximum above), else 0
+__global__ void q_flag_kernel(const double* __restrict__ dist, double tol, int* __restrict__ flag) {
+  if (threadIdx.x == 0) flag[0] = (dist[0] <= tol) ? 0 : 1;
+}
+
 // Layout conversion between the paper's face-major order (element (i, j, t)
 // at i + n1 (j + n2 t)) and tube-major order (t + n3 (j + n2 i): numpy's
 // C order of an n1 x n2 x n3 array).  For each j it is a transpose of the
@@ -239,6 +245,11 @@ hipError_t check_q_launch(const void* Q, bool f64, int n3, int p, double* out, h
   const unsigned grid = (unsigned)((npair + 3) / 4);
   if (f64) check_q_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double*>(Q), n3, p, bits);
   else check_q_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float*>(Q), n3, p, bits);
+  return hipGetLastError();
+}
+
+hipError_t check_q_flag(const double* dist, double tol, int* flag, hipStream_t s) {
+  q_flag_kernel<<<1, 64, 0, s>>>(dist, tol, flag);
   return hipGetLastError();
 }
 

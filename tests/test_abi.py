@@ -124,3 +124,18 @@ def test_batched_validation():
     assert lib.pq_batched_plan(ctypes.byref(good), 2, 0, 0.0, None, None, 0, None, ctypes.byref(h)) == -1
     assert lib.pq_batched_run(None, None) == -1
     assert lib.pq_batched_destroy(None) == -1
+
+
+def test_check_q_flag_and_u3_validation():
+    F2 = ctypes.c_void_p(0x2000)
+    F3 = ctypes.c_void_p(0x3000)
+    assert rc("pq_check_q_flag", None, 0, 8, 2, 1e-6, F2, F3, None) == -1
+    assert rc("pq_check_q_flag", FAKE, 0, 8, 2, 1e-6, None, F3, None) == -1
+    assert rc("pq_check_q_flag", FAKE, 2, 8, 2, 1e-6, F2, F3, None) == -5
+    assert rc("pq_check_q_flag", FAKE, 0, 8, 9, 1e-6, F2, F3, None) == -3
+    assert rc("pq_check_q_flag", FAKE, 0, 8, 2, -1.0, F2, F3, None) == -11
+    assert rc("pq_check_q_flag", FAKE, 0, 8, 2, float("nan"), F2, F3, None) == -11
+    # the U3 Gram product runs over n1 n2 tubes with a 32-bit depth: an area
+    # of 2^31 or more is refused before anything else is looked at
+    assert rc("pq_u3", FAKE, 0, 65536, 32768, 8, 4, F2, None, None, None, 0, None) == -10
+    assert rc("pq_u3", FAKE, 0, 65536, 32767, 8, 4, F2, None, None, None, 0, None) == -8

@@ -56,6 +56,58 @@ def test_check_q_many_pairs(pq):
     assert pq.check_q(devq(Qp)).item() == pytest.approx(oracle.check_q(Qp), rel=1e-12)
 
 
+def test_check_q_flag(pq):
+    """The device-side flag of the Def. 3.1 precondition: 0 for orthonormal Q
+    (float32 and float64), 1 once one entry is perturbed beyond the tolerance
+    and for a NaN entry; the distance matches the oracle's."""
+    import torch
+    rng = np.random.default_rng(9)
+    Q = synth.random_orthonormal(rng, 300, 64)
+    for dt, tol in ((torch.float32, 1e-6), (torch.float64, 1e-13)):
+        Qd = devq(Q.astype(np.float32 if dt == torch.float32 else np.float64))
+        dist, flag = pq.check_q_flag(Qd, tol)
+        assert flag.item() == 0
+        assert dist.item() == pytest.approx(pq.check_q(Qd).item(), abs=0)
+    Qp = Q.copy()
+    Qp[17, 40] += 1e-3
+    dist, flag = pq.check_q_flag(devq(Qp), 1e-5)
+    assert flag.item() == 1
+    assert dist.item() == pytest.approx(oracle.check_q(Qp), rel=1e-12)
+    _, flag = pq.check_q_flag(devq(Qp), 1.0)  # within a loose tolerance
+    assert flag.item() == 0
+    Qn = Q.copy()
+    Qn[3, 5] = np.nan
+    dist, flag = pq.check_q_flag(devq(Qn), 1.0)
+    assert flag.item() == 1 and np.isnan(dist.item())
+
+
+def test_info_entries_all_written(pq):
+    """The info arrays come back from torch.empty: the library writes every
+    entry of them (checked here on arrays filled with a sentinel first)."""
+    import torch
+    c = synth.tiny()
+    A = dev(c["A"].astype(np.float32))
+    Q = devq(c["Q"].astype(np.float32))
+    k = c["k"]
+    sentinel = -12345
+    for n, call in ((3, lambda i: pq.tsvdq(A, Q, k, info=i)),
+                    (3, lambda i: pq.svdii(A, Q, 0.9, info=i)),
+                    (3, lambda i: pq.u3(A, 4, info=i)),
+                    (4, lambda i: pq.tsvdq_backward(A, Q, k, sbar=torch.ones(k, Q.shape[1], device="cuda"),
+                                                    info=i))):
+        info = torch.full((n,), sentinel, dtype=torch.int32, device="cuda")
+        call(info)
+        got = info.cpu().tolist()
+        assert all(v >= 0 for v in got), got
+    info = torch.full((1,), sentinel, dtype=torch.int32, device="cuda")
+    qs = torch.empty_like(Q)
+    import paper_2409_19402_amd._lib as L
+    ws = torch.empty(L.load().pq_orthonormalize_q_workspace(*Q.shape), dtype=torch.uint8, device="cuda")
+    L.call("pq_orthonormalize_q", Q.data_ptr(), 0, Q.shape[0], Q.shape[1], qs.data_ptr(), info.data_ptr(),
+           ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+    assert info.item() == 0
+
+
 def test_thm_4_3_and_4_6_on_gpu_results(pq):
     """Video-shaped data: the projection error with Q = U3 (GPU) is no larger
     than with the DCT or the identity (Thm. 4.3), and the GPU tSVDQ with
