@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the projected-product hot path on one MI355X.
 
-Default workload: the video-shaped truncated tSVDQ, A 240 x 320 x 200 float32
-(a sum of 10 separable blob x drifting-cosine components plus noise),
-Q = U3(:, :20), rank k = 10 per face.  One step is the whole path on that
-input: the float64 Stiefel check of Q, the transform A x_3 Q^T, the facewise
-one-sided-Jacobi SVD truncated to rank 10, the factor products, and the
-return to the spatial domain of the factors and of the approximation A_k.
+Default workload: the batched form, 64 independent instances of uneven sizes
+(n1, n2, n4 uniform in [64, 512], n3 in [32, 256], p in [4, 32], float32
+N(0,1) data, a random orthonormal Q each, k = p/2).  One step is one replay
+of the captured graph that computes, for every instance, C = A *_Q B
+(Def. 3.1) and the rank-k truncated tSVDQ of A (Alg. 4.1 steps 2-3).  The
+same line carries what the metric compares the batched and the compensated
+forms with: the same 64 instances as sequential unbatched float32 calls, the
+hyperspectral-shaped tSVDQ (512 x 512 x 224 bfloat16, p = 32, k = 16) in the
+float32 and split-bfloat16 (x3) transforms, the differentiation-shaped
+product in float32, bf16x3 and plain bf16, and the relative errors of every
+timed result against the float64 oracle (plain bf16's as reported numbers).
 
 Prints ONE JSON line (metric, value in GFLOP/s of the nominal flop count,
 roofline of the dominant kernel measured with HIP events on the launch stream,
 and the float64 CPU oracle timed on this host as a baseline).  Per-kernel
-details go to stderr and to gpurun_out/bench_kernels.json when that folder
-exists.
+details go to stderr, and as JSON to the file named by --details.
 
-    python bench.py [--steps K] [--warmup W] [--workload video|hyper|diff|tiny]
+    python bench.py [--steps K] [--warmup W] [--workload batched|video|hyper|...]
 """
 
 import argparse
@@ -30,7 +34,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_MFMA_PEAK = 157.3         # TFLOP/s dense
-FP64_VALU_PEAK = 78.6          # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 BF16_MFMA_PEAK = 2500.0        # TFLOP/s dense
 FP64_MFMA_PEAK = 78.6          # TFLOP/s dense
 
@@ -65,9 +68,9 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="video",
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batched",
                     choices=["video", "hyper", "diff", "tiny", "copy", "hat-video", "hat-hyper",
                              "proj-video", "qprod", "batched", "svdii-video", "u3-video",
                              "u3-video-f64", "tsvdq-backward-video"])
@@ -76,13 +79,17 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--details", default=None, help="file for the per-kernel details (JSON)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="batched workload: skip the float32/compensated comparisons and oracle errors")
     return ap.parse_args()
 
 
 # ---------------------------------------------------------------------------
 # workloads: each returns (step_fn, flops_per_step, info dict, kernel models)
 # kernel model: name -> (bound, units_per_launch_fn) giving algorithmic
-# bytes ("hbm") or flops ("alu"/"mfma") per launch
+# bytes ("hbm") or flops ("mfma": float32 matrix cores, "mfma64": float64)
+# per launch
 # ---------------------------------------------------------------------------
 
 def svd_nominal_flops(n1, n2, p):
@@ -99,11 +106,14 @@ JACOBI_KERNELS = ("jacobi_gram_f32", "jacobi_gram_f64", "jacobi_block_f32", "jac
 def jacobi_models(svd_flops):
     """Roofline models of the Jacobi sweep kernels: the nominal SVD work of a
     step spread evenly over that step's sweep launches (float32 coarse and
-    float64 polishing sweeps), against the float64 vector peak."""
+    float64 polishing sweeps), so each phase carries the share of its own
+    launches; each kernel's rate is its share per launch over its own average
+    launch time, against the matrix-core peak of its own type (the Gram
+    products and X <- XV run on float32 or float64 MFMA)."""
     def share(kernels, steps):
         n = sum(kernels.get(nm, {}).get("launches", 0) for nm in JACOBI_KERNELS)
         return svd_flops * steps / n if n else None
-    return {nm: ("alu", share) for nm in JACOBI_KERNELS}
+    return {nm: ("mfma64" if nm.endswith("f64") else "mfma", share) for nm in JACOBI_KERNELS}
 
 
 def per_launch(name, bytes_per_step):
@@ -174,11 +184,178 @@ def workload_tsvdq(pq, torch, A_dev, Q_dev, k, a_bytes, name, prec):
     return step, flops, info, models
 
 
+def host_info():
+    """CPU model and BLAS build of this host, for the baseline's record."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        for d in threadpool_info():
+            if d.get("user_api") == "blas":
+                blas = f"{d.get('internal_api')} {d.get('version')} ({d.get('threading_layer', '')})"
+                break
+    except Exception:  # threadpoolctl missing
+        pass
+    return {"cpu_model": model, "blas": blas, "numpy": np.__version__, "nproc": os.cpu_count()}
+
+
+def cpu_baseline(cpu_case, flops, seconds):
+    """The float64 oracle timed on this host: a bounded sample of the same
+    workload with every BLAS thread, then with one thread (half the budget
+    each).  cpu_case is (run, description) for a callable that runs one full
+    pass, or ("per-instance", factory, description) for one whose calls each
+    time one instance and return (seconds, flops)."""
+    from threadpoolctl import threadpool_limits
+
+    def sample(budget):
+        if cpu_case[0] == "per-instance":
+            run = cpu_case[1]()
+            t_cpu, fl, n = 0.0, 0.0, 0
+            t_start = time.time()
+            while time.time() - t_start < budget or n == 0:
+                dt, f = run()
+                t_cpu += dt
+                fl += f
+                n += 1
+            return fl / t_cpu / 1e9, f"the first {n} instances (qprod + tSVDQ each), {t_cpu:.1f}s"
+        run = cpu_case[0]
+        run()  # warm-up
+        reps, t_cpu = 0, 0.0
+        t_start = time.time()
+        while time.time() - t_start < budget or reps == 0:
+            t1 = time.time()
+            run()
+            t_cpu += time.time() - t1
+            reps += 1
+        return flops * reps / t_cpu / 1e9, f"{reps} full passes of the same workload, {t_cpu:.1f}s"
+
+    what = cpu_case[-1]
+    cores = blas_threads()
+    v_all, s_all = sample(0.5 * seconds)
+    with threadpool_limits(limits=1, user_api="blas"):
+        v_one, s_one = sample(0.5 * seconds)
+    cpu = {"value": round(v_all, 4), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"{s_all} ({what}), float64 numpy/LAPACK on {cores} threads",
+           "one_core": {"value": round(v_one, 4), "cores": 1, "sample": s_one}}
+    cpu.update(host_info())
+    log(f"cpu oracle: {cpu['value']} GFLOP/s on {cores} threads, {v_one:.4f} on one "
+        f"({cpu['cpu_model']}, {cpu['blas']})")
+    return cpu
+
+
+def timed(torch, stream, fn, steps, warmup, lib):
+    """ms per call of fn over `steps` calls after `warmup` calls (the
+    autotuner on during the warm-up), between two events on the stream."""
+    lib.pq_autotune_enable(1)
+    for _ in range(max(1, warmup)):
+        out = fn()
+    torch.cuda.synchronize()
+    lib.pq_autotune_enable(0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        out = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, out
+
+
+def rel_err(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def compare_forms(pq, torch, dev, up, args, insts, batch, shapes):
+    """What the metric compares: the batched form against the plain float32
+    path (sequential unbatched calls on the same instances), and the
+    compensated split-bfloat16 forms against float32, each with its relative
+    Frobenius error against the float64 oracle; plain bfloat16's error is
+    reported as a number."""
+    from paper_2409_19402_amd import _lib, synth
+    import oracle
+    lib = _lib.load()
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+
+    # the batched results against the oracle on four instances: the two
+    # smallest and the two largest by element count
+    sizes = [sh["n1"] * sh["n2"] * sh["n3"] for sh in shapes]
+    order = [int(i) for i in np.argsort(sizes)]
+    sample = order[:2] + order[-2:]
+    e_c, e_s, e_a = 0.0, 0.0, 0.0
+    for i in sample:
+        sh, o = shapes[i], batch.outputs[i]
+        c = synth.batched_instance(4, i, sh)
+        Al, Bl = synth.logical(c["A"]), synth.logical(c["B"])
+        ref = oracle.tsvdq(Al, c["Q"], sh["k"])
+        U, s_, V = (o[x].double().cpu().numpy() for x in ("Uhat", "s", "Vhat"))
+        e_c = max(e_c, rel_err(o["C"].double().cpu().numpy(), oracle.qprod(Al, Bl, c["Q"])))
+        e_s = max(e_s, rel_err(s_, ref.s))
+        e_a = max(e_a, rel_err(np.einsum("ijl,jl,mjl->iml", U, s_, V),
+                               np.einsum("ijl,jl,mjl->iml", ref.Uhat, ref.s, ref.Vhat)))
+    out["batched_rel_err_vs_oracle"] = {"instances": sample, "C": e_c, "s": e_s, "facewise_A_k": e_a}
+    log(f"batched vs oracle on instances {sample}: C {e_c:.2e}, s {e_s:.2e}, facewise A_k {e_a:.2e}")
+
+    # the hyperspectral-shaped tSVDQ: float32 transform vs split-bfloat16 x3
+    # (and plain bfloat16, reported), whole step as the hyper workload times it
+    c = synth.hyperspectral_case()
+    A = pq.from_storage(torch.from_numpy(c["A_bits"].view(np.int16)).to(dev).view(torch.bfloat16))
+    Q = torch.from_numpy(c["Q"]).to(dev)
+    k = c["k"]
+    ref = oracle.tsvdq(synth.logical(c["A"]), c["Q"], k)
+    hyper = {}
+    for prec in ("default", "bf16x3", "bf16"):
+        ms, r = timed(torch, stream, lambda: (pq.check_q(Q), pq.tsvdq(A, Q, k, prec=prec, spatial=True,
+                                                                        approx=True))[1],
+                      5, 2, lib)
+        err = rel_err(r.Ak.double().cpu().numpy(), ref.Ak)
+        s_err = rel_err(r.s.double().cpu().numpy(), ref.s)
+        name = "fp32" if prec == "default" else prec
+        hyper[name] = {"ms_per_step": round(ms, 4), "rel_err_A_k": err, "rel_err_s": s_err}
+        log(f"hyperspectral tSVDQ {name}: {ms:.3f} ms/step, A_k rel err {err:.2e}, s rel err {s_err:.2e}")
+    ref_h = oracle.hat(synth.logical(c["A"]), c["Q"])
+    for prec in ("default", "bf16x3", "bf16"):
+        ms, Ah = timed(torch, stream, lambda: pq.hat(A, Q, prec=prec), 20, 3, lib)
+        name = "fp32" if prec == "default" else prec
+        hyper[name]["hat_us"] = round(1000 * ms, 2)
+        hyper[name]["hat_rel_err"] = rel_err(Ah.double().cpu().numpy(), ref_h)
+    hyper["bf16x3_speedup_vs_fp32"] = round(hyper["fp32"]["ms_per_step"] / hyper["bf16x3"]["ms_per_step"], 4)
+    out["hyperspectral_tsvdq"] = hyper
+    del A, c, ref, ref_h
+
+    # the differentiation-shaped product A *_Q B (256x128x128 * 128x256x128,
+    # p = 16) in the three precisions
+    c = synth.differentiation_case()
+    Ad, Bd = up(c["A"]), up(c["B"])
+    Qd = torch.from_numpy(c["Q"]).to(dev)
+    ref = oracle.qprod(synth.logical(c["A"]), synth.logical(c["B"]), c["Q"])
+    qp = {}
+    for prec in ("default", "bf16x3", "bf16"):
+        ms, C = timed(torch, stream, lambda: pq.qprod(Ad, Bd, Qd, prec=prec), 50, 3, lib)
+        name = "fp32" if prec == "default" else prec
+        qp[name] = {"us_per_call": round(1000 * ms, 2), "rel_err": rel_err(C.double().cpu().numpy(), ref)}
+        log(f"qprod {name}: {1000 * ms:.1f} us, rel err {qp[name]['rel_err']:.2e}")
+    out["qprod_256x128x128"] = qp
+    out["plain_bf16_rel_err"] = {"hyperspectral_hat": hyper["bf16"]["hat_rel_err"],
+                                 "hyperspectral_A_k": hyper["bf16"]["rel_err_A_k"],
+                                 "qprod_256x128x128": qp["bf16"]["rel_err"]}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(every GPU box here has one GPU)", file=sys.stderr)
+              "(the multi-GPU path, sharding over faces or rows, is not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2409_19402_amd import binding as pq
@@ -360,16 +537,13 @@ def main():
         shapes = synth.batched_shapes(count=args.count)
         insts, flops, cpu_insts = [], 0.0, []
         for i, sh in enumerate(shapes):
-            rng = np.random.default_rng([4, i])
-            A = rng.standard_normal((sh["n3"], sh["n2"], sh["n1"]), dtype=np.float32)
-            B = rng.standard_normal((sh["n3"], sh["n4"], sh["n2"]), dtype=np.float32)
-            Qn = synth.random_orthonormal(rng, sh["n3"], sh["p"]).astype(np.float32)
-            insts.append(dict(A=up(A), B=up(B), Q=torch.from_numpy(Qn).to(dev), k=sh["k"]))
+            c = synth.batched_instance(4, i, sh)
+            insts.append(dict(A=up(c["A"]), B=up(c["B"]), Q=torch.from_numpy(c["Q"]).to(dev), k=sh["k"]))
             n1, n2, n3, n4, p, k = (sh[x] for x in ("n1", "n2", "n3", "n4", "p", "k"))
             f = (2.0 * p * (n1 * n2 * n3 + n2 * n4 * n3 + n1 * n2 * n4 + n1 * n4 * n3)   # qprod
                  + 2.0 * n1 * n2 * n3 * p + svd_nominal_flops(n1, n2, p))               # tSVDQ steps 2-3
             flops += f
-            cpu_insts.append((synth.logical(A), synth.logical(B), Qn, k, f))
+            cpu_insts.append((i, sh, f))
         batch_box = {}
 
         def step():
@@ -394,6 +568,24 @@ def main():
                 "a_elements": int(sum(sh["n1"] * sh["n2"] * sh["n3"] for sh in shapes)),
                 "faces": int(sum(sh["p"] for sh in shapes))}
         dtype = "f32"
+
+        def cpu_batched():
+            import oracle
+            state = {"i": 0}
+
+            def run():
+                # one instance per call, in order: check_q + qprod + tSVDQ
+                j, sh, f = cpu_insts[state["i"] % len(cpu_insts)]
+                state["i"] += 1
+                c = synth.batched_instance(4, j, sh)
+                Al, Bl = synth.logical(c["A"]), synth.logical(c["B"])
+                t1 = time.time()
+                oracle.check_q(c["Q"])
+                oracle.qprod(Al, Bl, c["Q"])
+                oracle.tsvdq(Al, c["Q"], sh["k"])
+                return time.time() - t1, f
+            return run
+        cpu_case = ("per-instance", cpu_batched, "check_q + qprod + tSVDQ of the batch's instances in order")
     else:  # diff
         c = synth.differentiation_case()
         A = up(c["A"]).requires_grad_(True)
@@ -457,15 +649,17 @@ def main():
 
     extra_batched = {}
     if args.workload == "batched":
-        # the same work as sequential unbatched calls (the plain fp32 path)
+        # the same work as sequential unbatched calls (the plain fp32 path),
+        # three passes after the warm-up's tuned one
         torch.cuda.synchronize()
         ev0.record(stream)
-        unbatched()
+        for _ in range(3):
+            unbatched()
         ev1.record(stream)
         torch.cuda.synchronize()
-        ub = ev0.elapsed_time(ev1)
-        extra_batched = {"unbatched_ms_per_step": round(ub, 4),
-                         "speedup_vs_unbatched": round(ub / ms_per_step, 3),
+        ub = ev0.elapsed_time(ev1) / 3
+        extra_batched = {"fp32_unbatched_ms_per_step": round(ub, 4),
+                         "batched_speedup_vs_fp32_unbatched": round(ub / ms_per_step, 3),
                          "workspace_GB": round(out.workspace_bytes / 1e9, 3)}
         log(f"unbatched: {ub:.3f} ms/step, batched graph {ms_per_step:.3f} ms/step")
 
@@ -512,8 +706,6 @@ def main():
         if units is not None and avg_s > 0:
             if bound == "hbm":
                 achieved, peak, unit = units / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
-            elif bound == "alu":
-                achieved, peak, unit = units / avg_s / 1e12, FP64_VALU_PEAK, "TFLOP/s"
             elif bound == "mfma64":
                 achieved, peak, unit = units / avg_s / 1e12, FP64_MFMA_PEAK, "TFLOP/s"
             else:
@@ -552,41 +744,11 @@ def main():
 
     # CPU oracle baseline (float64, this host's cores), a bounded sample
     cpu = None
-    if not args.no_cpu_baseline and args.workload == "batched":
-        import oracle
-        cores = blas_threads()
-        done, t_cpu, fl = 0, 0.0, 0.0
-        t_start = time.time()
-        for (Al, Bl, Qn, k, f) in cpu_insts:
-            if time.time() - t_start > args.cpu_seconds and done > 0:
-                break
-            t1 = time.time()
-            oracle.check_q(Qn)
-            oracle.qprod(Al, Bl, Qn)
-            oracle.tsvdq(Al, Qn, k)
-            t_cpu += time.time() - t1
-            fl += f
-            done += 1
-        cpu = {"value": round(fl / t_cpu / 1e9, 4), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-               "sample": f"the first {done} of {len(cpu_insts)} instances (qprod + tSVDQ each), "
-                         f"{t_cpu:.1f}s, float64 numpy/LAPACK"}
-        log(f"cpu oracle: {cpu['value']} GFLOP/s over {done} instances on {cores} threads")
     if not args.no_cpu_baseline and cpu_case is not None:
-        cores = blas_threads()
-        run_cpu, what = cpu_case
-        run_cpu()  # warm-up
-        reps, t_cpu = 0, 0.0
-        t_start = time.time()
-        while time.time() - t_start < args.cpu_seconds or reps == 0:
-            t1 = time.time()
-            run_cpu()
-            t_cpu += time.time() - t1
-            reps += 1
-        cpu = {"value": round(flops * reps / t_cpu / 1e9, 4), "unit": "GFLOP/s", "cores": cores,
-               "kind": "oracle",
-               "sample": f"{reps} full passes of the same workload ({what}), {t_cpu:.1f}s, "
-                         "float64 numpy/LAPACK"}
-        log(f"cpu oracle: {cpu['value']} GFLOP/s over {reps} passes on {cores} threads")
+        cpu = cpu_baseline(cpu_case, flops, args.cpu_seconds)
+
+    if args.workload == "batched" and not args.no_compare:
+        extra_batched.update(compare_forms(pq, torch, dev, up, args, insts, out, shapes))
 
     line = {
         "metric": METRIC,
@@ -608,8 +770,8 @@ def main():
     }
     detail = {"kernels_per_step_us": {k2: v["total_ms"] / prof_steps * 1000 for k2, v in kernels.items()},
               "kernels": kernels, "flops_per_step": flops, "line": line}
-    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
-        with open(os.path.join(ROOT, "gpurun_out", f"bench_kernels_{args.workload}.json"), "w") as fh:
+    if args.details:
+        with open(args.details, "w") as fh:
             json.dump(detail, fh, indent=1)
     print(json.dumps(line), flush=True)
 

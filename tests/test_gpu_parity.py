@@ -10,13 +10,15 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import dev, dev_bf16, devq, host, rel, say
+from helpers import dev, dev_bf16, devq, host, rel, relmax, say
 from paper_2409_19402_amd import synth
 
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
 TOL64 = 1e-12
+# element-wise companion of the float32 norms: max |x - ref| over max |ref|
+TOLMAX = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -54,11 +56,14 @@ def test_transforms_f32(pq, shape):
     Ad, Qd = dev(A), devq(Q)
     Al = synth.logical(A)
     Ah = pq.hat(Ad, Qd)
-    assert rel(host(Ah), oracle.hat(Al, Q)) <= TOL32
+    ref = oracle.hat(Al, Q)
+    assert rel(host(Ah), ref) <= TOL32 and relmax(host(Ah), ref) <= TOLMAX
     back = pq.unhat(Ah, Qd)
-    assert rel(host(back), oracle.unhat(host(Ah), Q)) <= TOL32
+    ref = oracle.unhat(host(Ah), Q)
+    assert rel(host(back), ref) <= TOL32 and relmax(host(back), ref) <= TOLMAX
     P = pq.proj(Ad, Qd)
-    assert rel(host(P), oracle.proj(Al, Q)) <= TOL32
+    ref = oracle.proj(Al, Q)
+    assert rel(host(P), ref) <= TOL32 and relmax(host(P), ref) <= TOLMAX
 
 
 @pytest.mark.parametrize("shape", [(32, 24, 20, 16, 4), (33, 17, 9, 40, 7), (5, 70, 3, 64, 33),
@@ -160,6 +165,7 @@ def _check_tsvdq(pq, A_st, Q, k, tol_s=TOL32, tol_a=TOL32, a_dev=None):
     for l in range(p):
         assert rel(s[:, l], ref.s[:, l]) <= tol_s, f"face {l}"
     assert rel(host(r.Ak), ref.Ak) <= tol_a
+    assert relmax(host(r.Ak), ref.Ak) <= 10 * tol_a
     Uh, Vh = host(r.Uhat), host(r.Vhat)
     Ah = oracle.hat(Al, Q)
     for l in range(p):
@@ -268,6 +274,7 @@ def test_hyperspectral_hat_bf16_input(pq):
     Ah = pq.hat(Ad, devq(c["Q"]))
     ref = oracle.hat(synth.logical(c["A"]), c["Q"])
     assert rel(host(Ah), ref) <= TOL32
+    assert relmax(host(Ah), ref) <= TOLMAX
 
 
 BF16_SHAPES = [(32, 24, 16, 4), (7, 9, 33, 5), (50, 30, 200, 20), (17, 6, 300, 37),
@@ -330,8 +337,10 @@ def test_hyperspectral_tsvdq(pq, hyper_case, prec):
     for l in range(Q.shape[1]):
         assert rel(s[:, l], ref.s[:, l]) <= TOL32, f"face {l}"
     err = rel(host(r.Ak), ref.Ak)
-    say(f"  A_k rel err {err:.3e}")
+    errmax = relmax(host(r.Ak), ref.Ak)
+    say(f"  A_k rel err {err:.3e}, element-wise {errmax:.3e}")
     assert err <= TOL32
+    assert errmax <= TOLMAX
 
 
 def test_differentiation_case(pq):
@@ -351,10 +360,11 @@ def test_differentiation_case(pq):
     Al, Bl, Tl = synth.logical(A), synth.logical(B), synth.logical(T)
     Cref = oracle.qprod(Al, Bl, Q)
     assert rel(host(C), Cref) <= TOL32
+    assert relmax(host(C), Cref) <= TOLMAX
     dA, dB, dQ = oracle.qprod_backward(2 * (Cref - Tl), Al, Bl, Q)
-    assert rel(host(Ad.grad), dA) <= 1e-4
-    assert rel(host(Bd.grad), dB) <= 1e-4
-    assert rel(host(Qd.grad), dQ) <= 1e-4
+    for got, want in ((Ad.grad, dA), (Bd.grad, dB), (Qd.grad, dQ)):
+        assert rel(host(got), want) <= 1e-4
+        assert relmax(host(got), want) <= 1e-3
     # fixed-order split-K reduction: bit-identical on repetition
     G = pq.from_storage(torch.from_numpy(np.ascontiguousarray(
         synth.storage(2 * (host(C) - Tl)).astype(np.float32))).cuda())
