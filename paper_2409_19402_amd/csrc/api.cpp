@@ -626,7 +626,7 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
   {
     PQ_PROF("jacobi_finalize", stream);
     PQ_TRY(pq::jacobi_norms_f64(W, 1, in3, in3, sig, nullptr, stream));
-    PQ_TRY(pq::jacobi_finalize_f64(W, sig, 1, in3, in3, ip, nullptr, F, nullptr, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(W, sig, 1, in3, in3, ip, nullptr, 0, F, nullptr, stream));
   }
   {
     PQ_PROF("u3_finish", stream);
@@ -644,10 +644,11 @@ size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t
   const bool f64 = a_dtype == PQ_F64;
   const size_t e = elem(f64 ? PQ_F64 : PQ_F32);
   const int64_t mx = std::max(n1, n2), mn = std::min(n1, n2);
+  const int64_t kr = pq::ritz_cols(k, mn);
   return sweep_bytes(f64, n1 * n2, p)
          + align_up(8 * mn * p)                           // every singular value
-         + align_up(8 * mx * k * p)                       // top-k Jacobi vectors
-         + align_up(8 * mn * k * p)                       // other side (float64)
+         + align_up(8 * mx * kr * p)                      // top-kr Jacobi vectors
+         + align_up(8 * mn * kr * p)                      // other side (float64)
          + align_up(e * mn * k * p)                       // other side, ordered, unscaled
          + align_up(e * n1 * n2 * p);                     // transform-domain A_k
 }
@@ -751,9 +752,10 @@ int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t 
   const int64_t N = n1 * n2;
   const int64_t mx = std::max(n1, n2), mn = std::min(n1, n2);
   const SweepBufs b = take_sweep_bufs(ar, f64, N, p);
+  const int kr = pq::ritz_cols(k, mn);  // columns of the Rayleigh-Ritz step
   double* sig = static_cast<double*>(ar.take(8 * mn * p));
-  double* Ft = static_cast<double*>(ar.take(8 * mx * k * p));
-  double* Y = static_cast<double*>(ar.take(8 * mn * k * p));
+  double* Ft = static_cast<double*>(ar.take(8 * mx * kr * p));
+  double* Y = static_cast<double*>(ar.take(8 * mn * kr * p));
   void* Ys = ar.take(e * mn * k * p);
   void* Akh = ar.take(e * N * p);
   const bool select = gamma > 0.0;
@@ -779,22 +781,23 @@ int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t 
   }
   {
     PQ_PROF("jacobi_finalize", stream);
-    PQ_TRY(pq::jacobi_finalize_f64(W64, sig, ip, nv, L, ik, select ? rho : nullptr, Ft, nullptr, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(W64, sig, ip, nv, L, kr, select ? rho : nullptr, pq::kRitzExtra, Ft, nullptr,
+                                   stream));
   }
-  {  // Y = Ah_l^T Ft_l (n2 x k) or Ah_l Ft_l (n1 x k), float64 accumulation
+  {  // Y = Ah_l^T Ft_l (n2 x kr) or Ah_l Ft_l (n1 x kr), float64 accumulation
     PQ_PROF("factor_product", stream);
-    if (f64) PQ_TRY(pq::jacobi_factor_f64(static_cast<const double*>(Ah), Ft, Y, in1, in2, ik, ip, cols, stream));
-    else PQ_TRY(pq::jacobi_factor_f32(static_cast<const float*>(Ah), Ft, Y, in1, in2, ik, ip, cols, stream));
+    if (f64) PQ_TRY(pq::jacobi_factor_f64(static_cast<const double*>(Ah), Ft, Y, in1, in2, kr, ip, cols, stream));
+    else PQ_TRY(pq::jacobi_factor_f32(static_cast<const float*>(Ah), Ft, Y, in1, in2, kr, ip, cols, stream));
   }
-  {
+  {  // Rayleigh-Ritz on the kr columns, the leading k kept
     PQ_PROF("jacobi_refine", stream);
     if (f64)
-      PQ_TRY(pq::jacobi_refine_f64(Y, Ft, nv, L, ik, ip, select ? rho : nullptr, tol, static_cast<double*>(s),
-                                   static_cast<double*>(Other), static_cast<double*>(Fo),
+      PQ_TRY(pq::jacobi_refine_f64(Y, Ft, nv, L, kr, ik, ip, select ? rho : nullptr, pq::kRitzExtra, tol,
+                                   static_cast<double*>(s), static_cast<double*>(Other), static_cast<double*>(Fo),
                                    static_cast<double*>(Ys), stream));
     else
-      PQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, select ? rho : nullptr, tol, static_cast<float*>(s),
-                                   static_cast<float*>(Other), static_cast<float*>(Fo),
+      PQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, kr, ik, ip, select ? rho : nullptr, pq::kRitzExtra, tol,
+                                   static_cast<float*>(s), static_cast<float*>(Other), static_cast<float*>(Fo),
                                    static_cast<float*>(Ys), stream));
   }
   // step 4 and the approximation of Thm. 4.2 (zero columns add nothing)
@@ -960,7 +963,7 @@ int pq_tsvdq_backward(const void* A, int a_dtype, const void* Q, int64_t n1, int
   {
     PQ_PROF("jacobi_finalize", stream);
     PQ_TRY(pq::jacobi_norms_f64(b.W64, ip, S, L, sig, nullptr, stream));
-    PQ_TRY(pq::jacobi_finalize_f64(b.W64, sig, ip, S, L, S, nullptr, U, sigs, stream));
+    PQ_TRY(pq::jacobi_finalize_f64(b.W64, sig, ip, S, L, S, nullptr, 0, U, sigs, stream));
   }
   const double* M = static_cast<const double*>(b.Ah);
   // M_t is the face (cols) or its transpose; op(M_t^T) is the face with

@@ -132,9 +132,10 @@ Layout layout(const pq_instance* inst, int count) {
     const pq_instance& x = inst[i];
     if (!has_svd(x)) continue;
     const size_t mx = std::max(x.n1, x.n2), mn = std::min(x.n1, x.n2);
+    const size_t kr = (size_t)pq::ritz_cols(x.k, (int64_t)mn);
     lo.sig[i] = take(8 * mn * x.p);
-    lo.ft[i] = take(8 * mx * x.k * x.p);
-    lo.y[i] = take(8 * mn * x.k * x.p);
+    lo.ft[i] = take(8 * mx * kr * x.p);
+    lo.y[i] = take(8 * mn * kr * x.p);
     lo.ys[i] = take(4 * mn * x.k * x.p);
   }
   lo.total = off;
@@ -181,7 +182,7 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
     if (!has_svd(x)) continue;
     const bool cols = x.n1 >= x.n2;
     const int nv = (int)std::min(x.n1, x.n2), L = (int)std::max(x.n1, x.n2);
-    const int ip = (int)x.p, ik = (int)x.k;
+    const int ip = (int)x.p, ik = (int)x.k, kr = pq::ritz_cols(x.k, nv);
     double* Ft = reinterpret_cast<double*>(ws + lo.ft[i]);
     double* Y = reinterpret_cast<double*>(ws + lo.y[i]);
     float* Ys = reinterpret_cast<float*>(ws + lo.ys[i]);
@@ -189,10 +190,11 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
     float* Other = static_cast<float*>(cols ? x.Vhat : x.Uhat);
     double* sig = reinterpret_cast<double*>(ws + lo.sig[i]);
     BQ_TRY(pq::jacobi_norms_f64(W64 + lo.woff[i], ip, nv, L, sig, nullptr, s));
-    BQ_TRY(pq::jacobi_finalize_f64(W64 + lo.woff[i], sig, ip, nv, L, ik, nullptr, Ft, nullptr, s));
-    BQ_TRY(pq::jacobi_factor_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), Ft, Y, (int)x.n1, (int)x.n2, ik,
+    BQ_TRY(pq::jacobi_finalize_f64(W64 + lo.woff[i], sig, ip, nv, L, kr, nullptr, 0, Ft, nullptr, s));
+    BQ_TRY(pq::jacobi_factor_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), Ft, Y, (int)x.n1, (int)x.n2, kr,
                                  ip, cols, s));
-    BQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, ik, ip, nullptr, tol, static_cast<float*>(x.s), Other, Fo, Ys, s));
+    BQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, kr, ik, ip, nullptr, 0, tol, static_cast<float*>(x.s), Other, Fo, Ys,
+                                 s));
   }
   if (info_dev) BQ_TRY(pq::jacobi_info(used1, used2, lo.nfaces, max_sweeps, polish, info_dev, s));
   return PQ_OK;

@@ -148,23 +148,38 @@ hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, do
 // (n = nv p ints, may be null) cleared for jacobi_select
 hipError_t jacobi_norms_f64(const double* W, int p, int nv, int L, double* sig, int* rank, hipStream_t s);
 // the top k of each face by sig, normalised into F (L x k x p); a face keeps
-// min(k, kface[f]) vectors when kface is given, zero columns after them;
-// sig_sorted (k x p, may be null) receives the matching norms (0 past them)
+// min(k, kface[f] + extra) vectors when kface is given, zero columns after
+// them; sig_sorted (k x p, may be null) receives the matching norms (0 past
+// them)
 hipError_t jacobi_finalize_f64(const double* W, const double* sig, int p, int nv, int L, int k, const int* kface,
-                              double* F, double* sig_sorted, hipStream_t s);
+                              int extra, double* F, double* sig_sorted, hipStream_t s);
 // *_Q-SVDII selection over the n = p nv values of sig (rank cleared by
 // jacobi_norms_f64): rho[f] = face f's values among the first K of the
 // descending order, K the first count whose energy reaches gamma of the
 // total; e2 is n doubles of scratch
 hipError_t jacobi_select(const double* sig, int p, int nv, double gamma, int* rank, double* e2, int* rho,
                          hipStream_t s);
-// float64 Jacobi on the k columns of Y (m1 x k x p), each rotation applied
-// to F (m2 x k x p) too; writes s (k x p, descending), Other = Y / s, Fo = F
-// and Ys = Y, all in descending order of s, in the output type.
-hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol,
-                             float* s_out, float* Other, float* Fo, float* Ys, hipStream_t s);
-hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol,
-                             double* s_out, double* Other, double* Fo, double* Ys, hipStream_t s);
+// The Rayleigh-Ritz step of the truncation: float64 Jacobi on the k columns
+// of Y (m1 x k x p), each rotation applied to F (m2 x k x p) too; writes the
+// leading kout <= k of the results: s (kout x p, descending), Other = Y / s,
+// Fo = F and Ys = Y, in descending order of s, in the output type.  With
+// kface given a face works on min(k, kface[f] + extra) columns and keeps
+// min(kout, kface[f]), zero columns after them.
+hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int kout, int p, const int* kface,
+                             int extra, double tol, float* s_out, float* Other, float* Fo, float* Ys,
+                             hipStream_t s);
+hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int kout, int p, const int* kface,
+                             int extra, double tol, double* s_out, double* Other, double* Fo, double* Ys,
+                             hipStream_t s);
+// Columns of the Rayleigh-Ritz step for a rank-k truncation of faces with nv
+// singular values: k plus kRitzExtra more, at most nv.  The leading k of the
+// Ritz values and vectors on the span of the top k + kRitzExtra Jacobi vectors
+// (with the transform-domain face itself in the products) are first-order
+// sensitive to the Jacobi's own rounding only through the gap between the
+// k-th and the (k + kRitzExtra + 1)-th singular value, instead of the gap
+// between the k-th and the (k + 1)-th.
+constexpr int kRitzExtra = 8;
+inline int ritz_cols(int64_t k, int64_t nv) { return (int)(k + kRitzExtra < nv ? k + kRitzExtra : nv); }
 // y[i] = x[i] for i < n (float32 -> float64)
 hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s);
 // Y = Ah_l^T F_l (cols: Y n2 x k, F n1 x k) or Ah_l F_l (rows: Y n1 x k,

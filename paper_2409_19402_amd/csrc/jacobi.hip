@@ -988,22 +988,23 @@ __global__ __launch_bounds__(256) void norms_kernel(const T* __restrict__ W, int
 }
 
 // Descending order of each face's norms (ties by index) and the leading
-// vectors normalised into F (L x k x p); a face keeps min(k, kface[f])
-// vectors when kface is given, the rest of its k columns are zero, as is a
-// zero vector.  Workgroup (f, c) writes the columns [16 c, 16 c + 16) of
+// vectors normalised into F (L x k x p); a face keeps min(k, kface[f] +
+// extra) vectors when kface is given, the rest of its k columns are zero, as
+// is a zero vector.  Workgroup (f, c) writes the columns [16 c, 16 c + 16) of
 // face f (each workgroup ranks the face's norms itself).
 constexpr int kFinCols = 16;
 
 template <typename T>
 __global__ __launch_bounds__(256) void finalize_kernel(const T* __restrict__ W, const double* __restrict__ sig_all,
                                                        int nv, int L, int k, const int* __restrict__ kface,
-                                                       T* __restrict__ F, double* __restrict__ sig_sorted) {
+                                                       int extra, T* __restrict__ F,
+                                                       double* __restrict__ sig_sorted) {
   extern __shared__ double sig[];  // nv doubles
   __shared__ int order[kFinCols];
   const int face = blockIdx.x, r0 = blockIdx.y * kFinCols;
   const T* Wf = W + (int64_t)face * nv * L;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kf = kface ? max(0, min(k, kface[face])) : k;
+  const int kf = kface ? max(0, min(k, kface[face] + extra)) : k;
   for (int j = threadIdx.x; j < nv; j += 256) sig[j] = sig_all[(int64_t)face * nv + j];
   if (threadIdx.x < kFinCols) order[threadIdx.x] = -1;  // stays -1 only for NaN norms
   __syncthreads();
@@ -1107,17 +1108,21 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const double* __res
   }
 }
 
-// Jacobi on the k columns of Y (m1 x k, face-major) with every rotation also
-// applied to the k columns of F (m2 x k); then norms, descending order and
-// the outputs (type TO): s (k), Other = Y / s, Fo = F, Ys = Y, in that order.
-// The columns stay in global memory (the form for k columns that do not fit
-// in LDS); 16 waves per face, one pair per wave at a time.
+// Rayleigh-Ritz step of the truncation: Jacobi on the k columns of Y (m1 x
+// k, face-major) with every rotation also applied to the k columns of F (m2
+// x k); then norms, descending order and the leading kout of the results
+// (type TO): s (kout), Other = Y / s, Fo = F, Ys = Y, in that order, each
+// face's outputs kout apart.  With kface given a face works on min(k,
+// kface[f] + extra) columns (the rest are zero) and keeps min(kout,
+// kface[f]); its other output columns are zero.  The columns stay in global
+// memory (the form for k columns that do not fit in LDS); 16 waves per face,
+// one pair per wave at a time.
 constexpr int kRefineWaves = 16;
 
 template <typename T, typename TO>
 __global__ __launch_bounds__(64 * kRefineWaves) void refine_kernel(T* __restrict__ Y, T* __restrict__ F, int m1,
-                                                     int m2, int k, const int* __restrict__ kface,
-                                                     double tol, int max_sweeps,
+                                                     int m2, int k, int kout, const int* __restrict__ kface,
+                                                     int extra, double tol, int max_sweeps,
                                                      TO* __restrict__ s_out, TO* __restrict__ Other,
                                                      TO* __restrict__ Fo, TO* __restrict__ Ys) {
   extern __shared__ double sig[];  // k doubles, then k ints
@@ -1127,7 +1132,8 @@ __global__ __launch_bounds__(64 * kRefineWaves) void refine_kernel(T* __restrict
   T* Yf = Y + (int64_t)face * m1 * k;
   T* Ff = F + (int64_t)face * m2 * k;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kf = kface ? max(0, min(k, kface[face])) : k;  // columns past kf are zero
+  const int kf = kface ? max(0, min(k, kface[face] + extra)) : k;  // columns past kf are zero
+  const int ko = kface ? max(0, min(kout, kface[face])) : kout;     // kept columns
   const int kp = kf + (kf & 1);
   for (int sweep = 0; sweep < max_sweeps && kf > 1; ++sweep) {
     if (threadIdx.x == 0) any_rot = 0;
@@ -1187,23 +1193,24 @@ __global__ __launch_bounds__(64 * kRefineWaves) void refine_kernel(T* __restrict
     order[r] = j;
   }
   __syncthreads();
-  for (int r = wave; r < k; r += kRefineWaves) {
+  for (int r = wave; r < kout; r += kRefineWaves) {
     // equal ranks arise only from NaN norms; such a slot reads column r
     const int j = order[r] >= 0 && order[r] < k ? order[r] : r;
-    const double v = sig[j];
+    const bool keep = r < ko;
+    const double v = keep ? sig[j] : 0.0;
     const double inv = v > 0.0 ? 1.0 / v : 0.0;
-    if (lane == 0) s_out[(int64_t)face * k + r] = static_cast<TO>(v);
+    if (lane == 0) s_out[(int64_t)face * kout + r] = static_cast<TO>(v);
     const T* yj = Yf + (int64_t)j * m1;
-    TO* o = Other + ((int64_t)face * k + r) * m1;
-    TO* ys = Ys + ((int64_t)face * k + r) * m1;
+    TO* o = Other + ((int64_t)face * kout + r) * m1;
+    TO* ys = Ys + ((int64_t)face * kout + r) * m1;
     for (int e = lane; e < m1; e += 64) {
-      const double x = (double)yj[e];
+      const double x = keep ? (double)yj[e] : 0.0;
       ys[e] = static_cast<TO>(x);
       o[e] = static_cast<TO>(inv * x);
     }
     const T* fj = Ff + (int64_t)j * m2;
-    TO* fo = Fo + ((int64_t)face * k + r) * m2;
-    for (int e = lane; e < m2; e += 64) fo[e] = static_cast<TO>(fj[e]);
+    TO* fo = Fo + ((int64_t)face * kout + r) * m2;
+    for (int e = lane; e < m2; e += 64) fo[e] = static_cast<TO>(keep ? (double)fj[e] : 0.0);
   }
 }
 
@@ -1303,12 +1310,14 @@ __global__ __launch_bounds__(256) void factor_rows_kernel(const TA* __restrict__
 
 // The refinement of refine_kernel with the k columns of Y and F of the face
 // held in LDS and one wave per pair (16 waves): the face's k columns cost
-// 8 k (m1 + m2) bytes.  A face keeps min(k, kface[f]) columns when kface is
-// given; the rest are zero, never rotate, and sort last.
+// 8 k (m1 + m2) bytes.  A face works on min(k, kface[f] + extra) columns
+// when kface is given (the rest are zero, never rotate, and sort last) and
+// keeps min(kout, kface[f]) of them.
 template <typename TO>
 __global__ __launch_bounds__(1024) void refine_lds_kernel(const double* __restrict__ Yg, const double* __restrict__ Fg,
-                                                          int m1, int m2, int k, const int* __restrict__ kface,
-                                                          double tol, int max_sweeps, TO* __restrict__ s_out,
+                                                          int m1, int m2, int k, int kout,
+                                                          const int* __restrict__ kface, int extra, double tol,
+                                                          int max_sweeps, TO* __restrict__ s_out,
                                                           TO* __restrict__ Other, TO* __restrict__ Fo,
                                                           TO* __restrict__ Ys) {
   extern __shared__ double rl_smem[];
@@ -1319,7 +1328,8 @@ __global__ __launch_bounds__(1024) void refine_lds_kernel(const double* __restri
   __shared__ int any_rot;
   const int face = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int kf = kface ? max(0, min(k, kface[face])) : k;
+  const int kf = kface ? max(0, min(k, kface[face] + extra)) : k;
+  const int ko = kface ? max(0, min(kout, kface[face])) : kout;
   const double* yg = Yg + (int64_t)face * m1 * k;
   const double* fg = Fg + (int64_t)face * m2 * k;
   for (int e = tid; e < k * m1; e += 1024) Yf[e] = yg[e];
@@ -1387,21 +1397,22 @@ __global__ __launch_bounds__(1024) void refine_lds_kernel(const double* __restri
     order[r] = c;
   }
   __syncthreads();
-  for (int r = wave; r < k; r += 16) {
+  for (int r = wave; r < kout; r += 16) {
     // equal ranks arise only from NaN norms; such a slot reads column r
     const int c = order[r] >= 0 && order[r] < k ? order[r] : r;
-    const double v = sig[c];
+    const bool keep = r < ko;
+    const double v = keep ? sig[c] : 0.0;
     const double inv = v > 0.0 ? 1.0 / v : 0.0;
-    if (lane == 0) s_out[(int64_t)face * k + r] = static_cast<TO>(v);
-    TO* o = Other + ((int64_t)face * k + r) * m1;
-    TO* ys = Ys + ((int64_t)face * k + r) * m1;
+    if (lane == 0) s_out[(int64_t)face * kout + r] = static_cast<TO>(v);
+    TO* o = Other + ((int64_t)face * kout + r) * m1;
+    TO* ys = Ys + ((int64_t)face * kout + r) * m1;
     for (int e = lane; e < m1; e += 64) {
-      const double x = Yf[(int64_t)c * m1 + e];
+      const double x = keep ? Yf[(int64_t)c * m1 + e] : 0.0;
       ys[e] = static_cast<TO>(x);
       o[e] = static_cast<TO>(inv * x);
     }
-    TO* fo = Fo + ((int64_t)face * k + r) * m2;
-    for (int e = lane; e < m2; e += 64) fo[e] = static_cast<TO>(Ff[(int64_t)c * m2 + e]);
+    TO* fo = Fo + ((int64_t)face * kout + r) * m2;
+    for (int e = lane; e < m2; e += 64) fo[e] = static_cast<TO>(keep ? Ff[(int64_t)c * m2 + e] : 0.0);
   }
 }
 
@@ -1624,17 +1635,17 @@ hipError_t prep(const T* Ah, T* W, int n1, int n2, int p, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t finalize(const T* W, const double* sig, int p, int nv, int L, int k, const int* kface, T* F,
+hipError_t finalize(const T* W, const double* sig, int p, int nv, int L, int k, const int* kface, int extra, T* F,
                     double* sig_sorted, hipStream_t s) {
   const size_t lds = sizeof(double) * (size_t)nv;
   finalize_kernel<T><<<dim3((unsigned)p, (unsigned)((k + kFinCols - 1) / kFinCols)), 256, lds, s>>>(
-      W, sig, nv, L, k, kface, F, sig_sorted);
+      W, sig, nv, L, k, kface, extra, F, sig_sorted);
   return hipGetLastError();
 }
 
 template <typename TO>
-hipError_t refine(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol, TO* s_out,
-                  TO* Other, TO* Fo, TO* Ys, hipStream_t s) {
+hipError_t refine(double* Y, double* F, int m1, int m2, int k, int kout, int p, const int* kface, int extra,
+                  double tol, TO* s_out, TO* Other, TO* Fo, TO* Ys, hipStream_t s) {
   // dynamic LDS up to 159 KiB (the kernel's static word fits in the rest)
   constexpr size_t kLdsCap = 159 * 1024;
   const size_t lds_lds = sizeof(double) * (size_t)k * (m1 + m2) + (sizeof(double) + sizeof(int)) * (size_t)k;
@@ -1645,11 +1656,12 @@ hipError_t refine(double* Y, double* F, int m1, int m2, int k, int p, const int*
     return e;
   }();
   if (attr == hipSuccess && lds_lds <= kLdsCap) {
-    refine_lds_kernel<TO><<<p, 1024, lds_lds, s>>>(Y, F, m1, m2, k, kface, tol, 12, s_out, Other, Fo, Ys);
+    refine_lds_kernel<TO><<<p, 1024, lds_lds, s>>>(Y, F, m1, m2, k, kout, kface, extra, tol, 12, s_out, Other, Fo,
+                                                   Ys);
   } else {
     const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)k;
-    refine_kernel<double, TO><<<p, 64 * kRefineWaves, lds, s>>>(Y, F, m1, m2, k, kface, tol, 12, s_out, Other, Fo,
-                                                               Ys);
+    refine_kernel<double, TO><<<p, 64 * kRefineWaves, lds, s>>>(Y, F, m1, m2, k, kout, kface, extra, tol, 12,
+                                                               s_out, Other, Fo, Ys);
   }
   return hipGetLastError();
 }
@@ -1699,8 +1711,8 @@ hipError_t jacobi_norms_f64(const double* W, int p, int nv, int L, double* sig, 
   return hipGetLastError();
 }
 hipError_t jacobi_finalize_f64(const double* W, const double* sig, int p, int nv, int L, int k, const int* kface,
-                              double* F, double* sig_sorted, hipStream_t s) {
-  return finalize<double>(W, sig, p, nv, L, k, kface, F, sig_sorted, s);
+                              int extra, double* F, double* sig_sorted, hipStream_t s) {
+  return finalize<double>(W, sig, p, nv, L, k, kface, extra, F, sig_sorted, s);
 }
 hipError_t jacobi_select(const double* sig, int p, int nv, double gamma, int* rank, double* e2, int* rho,
                          hipStream_t s) {
@@ -1713,13 +1725,15 @@ hipError_t jacobi_select(const double* sig, int p, int nv, double gamma, int* ra
   select_kernel<<<1, kSelThreads, 0, s>>>(sig, rank, n, p, nv, gamma, e2, rho);
   return hipGetLastError();
 }
-hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol,
-                             float* s_out, float* Other, float* Fo, float* Ys, hipStream_t s) {
-  return refine<float>(Y, F, m1, m2, k, p, kface, tol, s_out, Other, Fo, Ys, s);
+hipError_t jacobi_refine_f32(double* Y, double* F, int m1, int m2, int k, int kout, int p, const int* kface,
+                             int extra, double tol, float* s_out, float* Other, float* Fo, float* Ys,
+                             hipStream_t s) {
+  return refine<float>(Y, F, m1, m2, k, kout, p, kface, extra, tol, s_out, Other, Fo, Ys, s);
 }
-hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int p, const int* kface, double tol,
-                             double* s_out, double* Other, double* Fo, double* Ys, hipStream_t s) {
-  return refine<double>(Y, F, m1, m2, k, p, kface, tol, s_out, Other, Fo, Ys, s);
+hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int kout, int p, const int* kface,
+                             int extra, double tol, double* s_out, double* Other, double* Fo, double* Ys,
+                             hipStream_t s) {
+  return refine<double>(Y, F, m1, m2, k, kout, p, kface, extra, tol, s_out, Other, Fo, Ys, s);
 }
 hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s) {
   widen_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
