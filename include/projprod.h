@@ -267,6 +267,27 @@ int pq_qprod(const void* A, const void* B, int ab_dtype, const void* Q, void* C,
              void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * pq_qprod for callers that cannot allocate device memory (code being
+ * captured into a graph, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results as pq_qprod, with the
+ * workspace taken from a fixed array inside the library instead of a ws
+ * argument.  The array holds PQ_QPROD_NOALLOC_MAX_BYTES (64 MiB) on every
+ * GPU the call runs on, from the first call on that GPU until the process
+ * ends; sizes whose workspace (pq_qprod_workspace) exceeds it return
+ * PQ_ERR_UNSUPPORTED before anything is enqueued.  The first call on a device
+ * looks up the array's address with that device current (the stream must
+ * belong to the current device).  Nothing in the array needs to start at
+ * zero: each call writes every byte it reads.  Every call on one GPU shares
+ * that GPU's array, so calls that may overlap in time on one GPU (different
+ * streams, or threads without ordering) race and must be serialised by the
+ * caller.  Allocates nothing; never synchronises.
+ */
+#define PQ_QPROD_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int pq_qprod_noalloc(const void* A, const void* B, int ab_dtype, const void* Q, void* C,
+                     int64_t n1, int64_t m, int64_t n2, int64_t n3, int64_t p, int prec,
+                     void* Ahat_out, void* Bhat_out, hipStream_t stream);
+
+/*
  * Adjoint of pq_qprod (chain rule through Def. 3.1).  G = dL/dC is
  * n1 x n2 x n3.  With dCh = G x_3 Q^T:
  *   dAh_l = dCh_l Bh_l^T,  dBh_l = Ah_l^T dCh_l,  dA = dAh x_3 Q,

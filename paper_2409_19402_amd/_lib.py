@@ -37,6 +37,8 @@ SIGNATURES = {
     "pq_qprod_workspace": (_sz, [_i64, _i64, _i64, _i64, _i64, _i32]),
     "pq_qprod": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _i32, _vp, _vp,
                         _vp, _sz, _vp]),
+    "pq_qprod_noalloc": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _i32, _vp, _vp,
+                                _vp]),
     "pq_qprod_backward_workspace": (_sz, [_i64, _i64, _i64, _i64, _i64, _i32]),
     "pq_qprod_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _i64, _i64,
                                  _i64, _vp, _vp, _vp, _vp, _sz, _vp]),

@@ -234,6 +234,26 @@ def _qprod_fwd(A, B, Q, prec, save=False):
     return C, Ah, Bh
 
 
+def qprod_noalloc(A, B, Q, prec="default"):
+    """A *_Q B through pq_qprod_noalloc: the library's fixed scratch array
+    instead of a workspace (forward only; the output C is still allocated
+    here, as the caller's)."""
+    _tensor(A, "A")
+    _tensor(B, "B", (A.dtype,))
+    _q(Q, A.dtype)
+    n1, m, n3 = A.shape
+    if B.shape[0] != m or B.shape[2] != n3:
+        raise ValueError("qprod: A is n1 x m x n3 and B must be m x n2 x n3")
+    n2 = B.shape[1]
+    if Q.shape[0] != n3:
+        raise ValueError("Q must have n3 rows")
+    p = Q.shape[1]
+    C = empty(n1, n2, n3, _out_dtype(A.dtype), A.device)
+    call("pq_qprod_noalloc", _ptr(A), _ptr(B), _DT[A.dtype], _ptr(Q), _ptr(C), n1, m, n2, n3, p,
+         PREC[prec], None, None, _stream(A.device))
+    return C
+
+
 PQ_LAYOUT_FACE_MAJOR, PQ_LAYOUT_TUBE_MAJOR = 0, 1
 
 

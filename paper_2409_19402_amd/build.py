@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libprojprod.so")
 
-SOURCES = ["transform.hip", "gemm.hip", "jacobi.hip", "misc.hip", "svdgrad.hip", "tune.cpp", "prof.cpp", "api.cpp", "batch.cpp"]
+SOURCES = ["transform.hip", "gemm.hip", "jacobi.hip", "misc.hip", "svdgrad.hip", "noalloc.hip", "tune.cpp", "prof.cpp", "api.cpp", "batch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -139,3 +139,17 @@ def test_check_q_flag_and_u3_validation():
     # of 2^31 or more is refused before anything else is looked at
     assert rc("pq_u3", FAKE, 0, 65536, 32768, 8, 4, F2, None, None, None, 0, None) == -10
     assert rc("pq_u3", FAKE, 0, 65536, 32767, 8, 4, F2, None, None, None, 0, None) == -8
+
+
+def test_qprod_noalloc_validation():
+    F = [ctypes.c_void_p(0x1000 * (i + 1)) for i in range(4)]
+    # a workspace beyond the library's fixed array is refused on the host
+    assert rc("pq_qprod_noalloc", F[0], F[1], 0, F[2], F[3], 2048, 2048, 2048, 64, 32, 0, None, None,
+              None) == -10
+    # sizes large enough to overflow a byte count are refused too
+    assert rc("pq_qprod_noalloc", F[0], F[1], 0, F[2], F[3], 1 << 40, 1 << 40, 8, 8, 2, 0, None, None,
+              None) == -10
+    assert rc("pq_qprod_noalloc", None, F[1], 0, F[2], F[3], 8, 8, 8, 8, 2, 0, None, None, None) == -1
+    assert rc("pq_qprod_noalloc", F[0], F[1], 0, F[2], F[3], 8, 8, 8, 8, 9, 0, None, None, None) == -3
+    assert rc("pq_qprod_noalloc", F[0], F[1], 5, F[2], F[3], 8, 8, 8, 8, 2, 0, None, None, None) == -5
+    assert rc("pq_qprod_noalloc", F[0], F[1], 0, F[2], F[3], 0, 8, 8, 8, 2, 0, None, None, None) == -2
