@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--workload", default="batched",
                     choices=["video", "hyper", "diff", "tiny", "copy", "hat-video", "hat-hyper",
                              "proj-video", "qprod", "batched", "svdii-video", "u3-video",
-                             "u3-video-f64", "tsvdq-backward-video"])
+                             "u3-video-f64", "tsvdq-backward-video", "facewise"])
     ap.add_argument("--count", type=int, default=64, help="instances of the batched workload")
     ap.add_argument("--prec", default="default")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -533,6 +533,25 @@ def main():
         info = {"workload": "qprod 256x128x128 * 128x256x128 fp32, p=16", "n1": n1, "m": m,
                 "n2": n2, "n3": n3, "p": p}
         dtype = "f32"
+    elif args.workload == "facewise":
+        # the facewise product (Def. 2.3) alone on the largest faces of the
+        # batched workload: 32 faces of 512 x 512 times 512 x 512
+        n1 = m = n2 = 512
+        p = 32
+        rng = np.random.default_rng(8)
+        Ah, Bh = up(synth.gaussian(rng, n1, m, p)), up(synth.gaussian(rng, m, n2, p))
+
+        def step():
+            return pq.facewise(Ah, Bh, prec=args.prec)
+        flops = 2.0 * n1 * m * n2 * p
+        passes = {"default": 0, "fp32": 0, "bf16": 1, "bf16x3": 3, "bf16x6": 6}[args.prec]
+        # float32 MFMA: the algorithmic flops against the float32 peak; the
+        # split-bfloat16 modes: the bfloat16 products they execute (passes x
+        # the algorithmic flops) against the bfloat16 peak
+        models = {"facewise_gemm": ("mfma", flops) if passes == 0 else ("mfma_bf16", passes * flops)}
+        info = {"workload": f"facewise product, {p} faces of {n1}x{m} times {m}x{n2}, fp32 data",
+                "n1": n1, "m": m, "n2": n2, "p": p}
+        dtype = "f32" if passes == 0 else "bf16"
     elif args.workload == "batched":
         shapes = synth.batched_shapes(count=args.count)
         insts, flops, cpu_insts = [], 0.0, []
@@ -708,9 +727,11 @@ def main():
                 achieved, peak, unit = units / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
             elif bound == "mfma64":
                 achieved, peak, unit = units / avg_s / 1e12, FP64_MFMA_PEAK, "TFLOP/s"
+            elif bound == "mfma_bf16":
+                achieved, peak, unit = units / avg_s / 1e12, BF16_MFMA_PEAK, "TFLOP/s"
             else:
                 achieved, peak, unit = units / avg_s / 1e12, FP32_MFMA_PEAK, "TFLOP/s"
-            roof = {"kernel": dom, "bound": "mfma" if bound == "mfma64" else bound,
+            roof = {"kernel": dom, "bound": "mfma" if bound in ("mfma64", "mfma_bf16") else bound,
                     "achieved": round(achieved, 4), "peak": peak,
                     "unit": unit, "frac": round(achieved / peak, 6),
                     "traffic": TRAFFIC_BYTES.get((args.workload, args.prec, dom)),

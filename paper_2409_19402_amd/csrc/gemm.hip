@@ -8,6 +8,7 @@
 // The split-bfloat16 modes use the same pipeline on v_mfma_f32_32x32x16_bf16.
 // float64: 64x64 or 64x16 output tiles on v_mfma_f64_16x16x4f64.
 #include <algorithm>
+#include <cstdio>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -489,6 +490,313 @@ __global__ __launch_bounds__(64 * kSumWaves) void sum_partials_kernel(const TI* 
   }
 }
 
+// ---- 128 x 128 output tiles ---------------------------------------------------
+// For products big enough to be bound by the matrix cores (the facewise
+// products of Def. 2.3 on faces of a few hundred rows and columns).  Four
+// waves per workgroup, wave w owning the 64 x 64 quadrant (w mod 2, w / 2) as
+// 2 x 2 blocks of 32 x 32: per MFMA step a lane reads one value of each of
+// its two A blocks and two B blocks and feeds four independent accumulation
+// chains, so that every LDS read serves two MFMAs and the matrix core never
+// waits on one chain.  K-tiles of KT are double buffered in LDS (the next
+// tile's global loads in flight during the current tile's MFMAs) in the same
+// layouts as the 64 x 64 kernels (tile_floats); step j of a K-tile takes k =
+// j in lanes 0-31 and k = KT/2 + j in lanes 32-63.
+constexpr int kBig = 128;
+
+// The MFMA operands of one 32-row block of a staged K-tile (rows rb .. rb +
+// 31 of the tile; lane rl = lane mod 32 takes row rb + rl, lane half h the k
+// half): v[j] = element (rb + rl, h KT/2 + j).
+template <int R, int KT, bool CONT_ROW>
+__device__ __forceinline__ void block_operands(const float* S, int rb, int rl, int h, float (&v)[KT / 2]) {
+  constexpr int H = KT / 2;
+  if constexpr (CONT_ROW) {  // [k][row], row stride R + 4
+#pragma unroll
+    for (int j = 0; j < H; ++j) v[j] = S[(h * H + j) * (R + 4) + rb + rl];
+  } else {                   // [row][k], row stride KT + 4: four k per 16-byte read
+#pragma unroll
+    for (int j = 0; j < H; j += 4) {
+      const float4 x = *reinterpret_cast<const float4*>(S + (rb + rl) * (KT + 4) + h * H + j);
+      v[j] = x.x; v[j + 1] = x.y; v[j + 2] = x.z; v[j + 3] = x.w;
+    }
+  }
+}
+
+template <bool TA, bool TB, int VA, int VB, int KT>
+__global__ __launch_bounds__(256, 2) void gemm_f32_big_kernel(Gemm g, int kchunk, bool grouped) {
+  constexpr int H = KT / 2;
+  constexpr int FA = tile_floats<kBig, KT>(), FB = FA;
+  extern __shared__ __align__(16) float bsm[];
+  auto As = [&](int b) { return bsm + b * FA; };
+  auto Bs = [&](int b) { return bsm + 2 * FA + b * FB; };
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rl = lane & 31, h = lane >> 5;
+  const int wm = wave & 1, wn = wave >> 1;
+  const TileIdx ti = tile_idx(grouped, (g.M + kBig - 1) / kBig, (g.N + kBig - 1) / kBig);
+  if (ti.z >= g.batch * max(1, g.ksplit)) return;  // the grouped grid's last slots
+  const int zb = ti.z % g.batch, zs = ti.z / g.batch;
+  const int m0 = ti.x * kBig, n0 = ti.y * kBig;
+  const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
+  const float* A = static_cast<const float*>(g.A) + (int64_t)zb * g.sA;
+  const float* B = static_cast<const float*>(g.B) + (int64_t)zb * g.sB;
+  float* C = static_cast<float*>(g.C) + (int64_t)zb * g.sC + (int64_t)zs * g.sSplit;
+  f32x16 acc[2][2];  // [B block][A block]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  TileRegs<kBig, KT> ra, rb;
+  int k0 = kbeg;
+  if (k0 < kend) {
+    tile_fetch<kBig, KT, VA, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
+    tile_fetch<kBig, KT, VB, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
+    tile_store<kBig, KT, VA, !TA>(ra, As(0));
+    tile_store<kBig, KT, VB, TB>(rb, Bs(0));
+  }
+  __syncthreads();
+  int buf = 0;
+  for (; k0 < kend; k0 += KT) {
+    const bool more = k0 + KT < kend;
+    if (more) {
+      tile_fetch<kBig, KT, VA, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
+      tile_fetch<kBig, KT, VB, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
+    }
+    float a[2][H], b[2][H];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      block_operands<kBig, KT, !TA>(As(buf), wm * 64 + 32 * i, rl, h, a[i]);
+      block_operands<kBig, KT, TB>(Bs(buf), wn * 64 + 32 * i, rl, h, b[i]);
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm)
+          acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x2f32(b[bn][j], a[bm][j], acc[bn][bm], 0, 0, 0);
+    if (more) {
+      tile_store<kBig, KT, VA, !TA>(ra, As(buf ^ 1));
+      tile_store<kBig, KT, VB, TB>(rb, Bs(buf ^ 1));
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  // lane (rl, h), value e of block (bn, bm): row m = m0 + 64 wm + 32 bm + rl,
+  // column n = n0 + 64 wn + 32 bn + 8 (e / 4) + 4 h + e mod 4
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm) {
+    const int gm = m0 + wm * 64 + 32 * bm + rl;
+    if (gm >= g.M) continue;
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int gn = n0 + wn * 64 + 32 * bn + 8 * (e >> 2) + 4 * h + (e & 3);
+        if (gn < g.N) C[gm + (int64_t)gn * g.ldc] = acc[bn][bm][e];
+      }
+  }
+}
+
+// The split-bfloat16 form of the 128 x 128 kernel: the tiles are fetched as
+// float32 and split into NP bfloat16 parts on their way into LDS ([row][k],
+// row stride KT + 8 bfloat16, k contiguous), and a lane reads the 8
+// consecutive k of its row as one 16-byte operand of
+// v_mfma_f32_32x32x16_bf16 (k = 8 h + i of each 16-wide step).  The part
+// products of Split<NP, NP> are accumulated in float32, smallest first.
+template <int R, int KT, int VEC, bool CONT_ROW, int NP>
+__device__ __forceinline__ void tile_store_split_r(const TileRegs<R, KT>& t, uint16_t* S) {
+  constexpr int ld = KT + kPad16;
+  constexpr int part = R * ld;
+  const int tid = threadIdx.x;
+  auto put = [&](int r, int k, float x) {
+    uint32_t w[NP];
+    split_pack<NP>(x, 0.f, w);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) S[i * part + r * ld + k] = (uint16_t)(w[i] & 0xffffu);
+  };
+  if constexpr (VEC == 4) {
+#pragma unroll
+    for (int hh = 0; hh < R * KT / 1024; ++hh) {
+      const int idx = tid + 256 * hh;
+      if (CONT_ROW) {  // four consecutive rows of one k
+        const int k = idx / (R / 4), r = 4 * (idx % (R / 4));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) put(r + i, k, t.v[4 * hh + i]);
+      } else {         // four consecutive k of one row: two packed words per part
+        const int r = idx / (KT / 4), k = 4 * (idx % (KT / 4));
+        uint32_t w0[NP], w1[NP];
+        split_pack<NP>(t.v[4 * hh + 0], t.v[4 * hh + 1], w0);
+        split_pack<NP>(t.v[4 * hh + 2], t.v[4 * hh + 3], w1);
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+          *reinterpret_cast<uint2*>(S + i * part + r * ld + k) = make_uint2(w0[i], w1[i]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int hh = 0; hh < R * KT / 256; ++hh) {
+      const int idx = tid + 256 * hh;
+      int r, k;
+      if (CONT_ROW) { k = idx / R; r = idx % R; } else { r = idx / KT; k = idx % KT; }
+      put(r, k, t.v[hh]);
+    }
+  }
+}
+
+// An operand contiguous along its rows (VEC = 4, CONT_ROW) is fetched for
+// the split kernel as 4 x 4 blocks instead: thread t takes rows 4 (t mod
+// (R / 4)) .. + 3 at the four consecutive k = 4 (t / (R / 4)) .. + 3 of a
+// 16-k slab (R = 128: 32 row quads x 8 k quads = 256 threads per 32 k), so
+// that after the split the four k of each row leave as one packed 8-byte LDS
+// store per part.  The float4 loads of a wave still cover 512 contiguous
+// bytes of one k.
+template <int R, int KT>
+__device__ __forceinline__ void tile_fetch_quads(const float* __restrict__ P, int64_t ld, int r0, int rmax, int k0,
+                                                 int kend, TileRegs<R, KT>& t) {
+  constexpr int RQ = R / 4, KQ = 256 / RQ;  // row quads, k quads per pass
+  static_assert(RQ * KQ == 256 && KT % (4 * KQ) == 0, "quad tiling");
+  const int rq = threadIdx.x % RQ, kq = threadIdx.x / RQ;
+#pragma unroll
+  for (int pass = 0; pass < KT / (4 * KQ); ++pass) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gr = r0 + 4 * rq, gk = k0 + 4 * (kq + KQ * pass) + j;
+      const bool ok = gr < rmax && gk < kend;
+      const float4 x = *reinterpret_cast<const float4*>(P + (ok ? gr : 0) + (int64_t)(ok ? gk : 0) * ld);
+      float* v = t.v + 16 * pass + 4 * j;
+      v[0] = ok ? x.x : 0.f;
+      v[1] = ok ? x.y : 0.f;
+      v[2] = ok ? x.z : 0.f;
+      v[3] = ok ? x.w : 0.f;
+    }
+  }
+}
+
+// t.v[16 pass + 4 j + i] = element (row 4 rq + i, k = 4 (kq + KQ pass) + j)
+template <int R, int KT, int NP>
+__device__ __forceinline__ void tile_store_split_quads(const TileRegs<R, KT>& t, uint16_t* S) {
+  constexpr int RQ = R / 4, KQ = 256 / RQ;
+  constexpr int ld = KT + kPad16;
+  constexpr int part = R * ld;
+  const int rq = threadIdx.x % RQ, kq = threadIdx.x / RQ;
+#pragma unroll
+  for (int pass = 0; pass < KT / (4 * KQ); ++pass) {
+    const float* v = t.v + 16 * pass;
+    const int k = 4 * (kq + KQ * pass);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint32_t w0[NP], w1[NP];
+      split_pack<NP>(v[i], v[4 + i], w0);
+      split_pack<NP>(v[8 + i], v[12 + i], w1);
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        *reinterpret_cast<uint2*>(S + q * part + (4 * rq + i) * ld + k) = make_uint2(w0[q], w1[q]);
+    }
+  }
+}
+
+// operand fetch and split store of the split kernel: 4 x 4 blocks for an
+// operand contiguous along its rows with 16-byte loads (when the K-tile
+// holds whole passes of them), the 64 x 64 kernel's mapping otherwise
+template <int R, int KT>
+__host__ __device__ constexpr bool quads_fit() {
+  return KT % (4 * (256 / (R / 4))) == 0;
+}
+template <int R, int KT, int VEC, bool CONT_ROW>
+__device__ __forceinline__ void split_fetch(const float* __restrict__ P, int64_t ld, int r0, int rmax, int k0,
+                                            int kend, TileRegs<R, KT>& t) {
+  if constexpr (VEC == 4 && CONT_ROW && quads_fit<R, KT>()) tile_fetch_quads<R, KT>(P, ld, r0, rmax, k0, kend, t);
+  else tile_fetch<R, KT, VEC, CONT_ROW>(P, ld, r0, rmax, k0, kend, t);
+}
+template <int R, int KT, int VEC, bool CONT_ROW, int NP>
+__device__ __forceinline__ void split_store(const TileRegs<R, KT>& t, uint16_t* S) {
+  if constexpr (VEC == 4 && CONT_ROW && quads_fit<R, KT>()) tile_store_split_quads<R, KT, NP>(t, S);
+  else tile_store_split_r<R, KT, VEC, CONT_ROW, NP>(t, S);
+}
+
+template <bool TA, bool TB, int VA, int VB, int KT, int NP>
+__global__ __launch_bounds__(256, 2) void gemm_bf16_big_kernel(Gemm g, int kchunk, bool grouped) {
+  using SP = Split<NP, NP>;
+  constexpr int ld = KT + kPad16;
+  constexpr int part = kBig * ld;  // bfloat16 elements per part
+  extern __shared__ __align__(16) uint16_t hbsm[];
+  auto Ap = [&](int b) { return hbsm + b * NP * part; };
+  auto Bp = [&](int b) { return hbsm + (2 + b) * NP * part; };
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rl = lane & 31, h = lane >> 5;
+  const int wm = wave & 1, wn = wave >> 1;
+  const TileIdx ti = tile_idx(grouped, (g.M + kBig - 1) / kBig, (g.N + kBig - 1) / kBig);
+  if (ti.z >= g.batch * max(1, g.ksplit)) return;
+  const int zb = ti.z % g.batch, zs = ti.z / g.batch;
+  const int m0 = ti.x * kBig, n0 = ti.y * kBig;
+  const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
+  const float* A = static_cast<const float*>(g.A) + (int64_t)zb * g.sA;
+  const float* B = static_cast<const float*>(g.B) + (int64_t)zb * g.sB;
+  float* C = static_cast<float*>(g.C) + (int64_t)zb * g.sC + (int64_t)zs * g.sSplit;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  TileRegs<kBig, KT> ra, rb;
+  int k0 = kbeg;
+  if (k0 < kend) {
+    split_fetch<kBig, KT, VA, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
+    split_fetch<kBig, KT, VB, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
+    split_store<kBig, KT, VA, !TA, NP>(ra, Ap(0));
+    split_store<kBig, KT, VB, TB, NP>(rb, Bp(0));
+  }
+  __syncthreads();
+  int buf = 0;
+  for (; k0 < kend; k0 += KT) {
+    const bool more = k0 + KT < kend;
+    if (more) {
+      split_fetch<kBig, KT, VA, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
+      split_fetch<kBig, KT, VB, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
+    }
+#pragma unroll
+    for (int ks = 0; ks < KT; ks += 16) {
+      bf16x8 pa[2][NP], pb[2][NP];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          pa[i][q] = *reinterpret_cast<const bf16x8*>(Ap(buf) + q * part + (wm * 64 + 32 * i + rl) * ld + ks + 8 * h);
+          pb[i][q] = *reinterpret_cast<const bf16x8*>(Bp(buf) + q * part + (wn * 64 + 32 * i + rl) * ld + ks + 8 * h);
+        }
+#pragma unroll
+      for (int pr = 0; pr < SP::n; ++pr)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+          for (int bm = 0; bm < 2; ++bm)
+            acc[bn][bm] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pb[bn][SP::q[pr]], pa[bm][SP::a[pr]], acc[bn][bm],
+                                                                  0, 0, 0);
+    }
+    if (more) {
+      split_store<kBig, KT, VA, !TA, NP>(ra, Ap(buf ^ 1));
+      split_store<kBig, KT, VB, TB, NP>(rb, Bp(buf ^ 1));
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm) {
+    const int gm = m0 + wm * 64 + 32 * bm + rl;
+    if (gm >= g.M) continue;
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int gn = n0 + wn * 64 + 32 * bn + 8 * (e >> 2) + 4 * h + (e & 3);
+        if (gn < g.N) C[gm + (int64_t)gn * g.ldc] = acc[bn][bm][e];
+      }
+  }
+}
+
 int chunk_for(const Gemm& g, int align) {
   const int ks = std::max(1, g.ksplit);
   int c = (g.K + ks - 1) / ks;
@@ -555,8 +863,92 @@ hipError_t gemm_bf16_launch(const Gemm& g, int kchunk, hipStream_t s) {
   return gemm_bf16_go<TA, TB, 1, 1, KT, NP>(g, kchunk, s);
 }
 
+// grid of the 128 x 128 kernels: grouped by slab on the XCDs under the same
+// condition as the 64 x 64 float32 kernel
+inline dim3 big_grid(const Gemm& g, bool& grouped) {
+  const unsigned mt = (unsigned)((g.M + kBig - 1) / kBig), nt = (unsigned)((g.N + kBig - 1) / kBig);
+  const unsigned nz = (unsigned)(g.batch * std::max(1, g.ksplit));
+  grouped = nz % kXcds == 0 || nz >= 8 * kXcds;
+  return grouped ? dim3(kXcds * mt * nt * ((nz + kXcds - 1) / kXcds)) : dim3(mt, nt, nz);
+}
+
+template <bool TA, bool TB, int VA, int VB, int KT>
+hipError_t gemm_f32_big_go(const Gemm& g, int kchunk, hipStream_t s) {
+  const size_t lds = sizeof(float) * 4 * tile_floats<kBig, KT>();
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_f32_big_kernel<TA, TB, VA, VB, KT>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  bool grouped = false;
+  const dim3 grid = big_grid(g, grouped);
+  gemm_f32_big_kernel<TA, TB, VA, VB, KT><<<grid, 256, lds, s>>>(g, kchunk, grouped);
+  return hipGetLastError();
+}
+
+template <bool TA, bool TB, int VA, int VB, int KT, int NP>
+hipError_t gemm_bf16_big_go(const Gemm& g, int kchunk, hipStream_t s) {
+  const size_t lds = sizeof(uint16_t) * 4 * NP * kBig * (KT + kPad16);
+  static hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&gemm_bf16_big_kernel<TA, TB, VA, VB, KT, NP>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  bool grouped = false;
+  const dim3 grid = big_grid(g, grouped);
+  gemm_bf16_big_kernel<TA, TB, VA, VB, KT, NP><<<grid, 256, lds, s>>>(g, kchunk, grouped);
+  return hipGetLastError();
+}
+
+// NP = 0: float32 MFMA; otherwise NP bfloat16 parts
+template <bool TA, bool TB, int KT, int NP>
+hipError_t gemm_big_launch(const Gemm& g, int kchunk, hipStream_t s) {
+  const bool va = vec4_ok(g.A, TA ? g.K : g.M, g.lda, g.sA) && (!TA || kchunk % 4 == 0);
+  const bool vb = vec4_ok(g.B, TB ? g.N : g.K, g.ldb, g.sB) && (TB || kchunk % 4 == 0);
+  if constexpr (NP == 0) {
+    if (va && vb) return gemm_f32_big_go<TA, TB, 4, 4, KT>(g, kchunk, s);
+    if (va) return gemm_f32_big_go<TA, TB, 4, 1, KT>(g, kchunk, s);
+    if (vb) return gemm_f32_big_go<TA, TB, 1, 4, KT>(g, kchunk, s);
+    return gemm_f32_big_go<TA, TB, 1, 1, KT>(g, kchunk, s);
+  } else {
+    if (va && vb) return gemm_bf16_big_go<TA, TB, 4, 4, KT, NP>(g, kchunk, s);
+    if (va) return gemm_bf16_big_go<TA, TB, 4, 1, KT, NP>(g, kchunk, s);
+    if (vb) return gemm_bf16_big_go<TA, TB, 1, 4, KT, NP>(g, kchunk, s);
+    return gemm_bf16_big_go<TA, TB, 1, 1, KT, NP>(g, kchunk, s);
+  }
+}
+
+// The 128 x 128 kernels take products without a K split whose output holds
+// at least one whole 128 x 128 tile
+inline bool big_tiles(const Gemm& g) { return g.ksplit <= 1 && g.M >= kBig && g.N >= kBig; }
+
+template <bool TA, bool TB>
+hipError_t gemm_small_launch(const Gemm& g, Prec prec, int kchunk, hipStream_t s);
+
 template <bool TA, bool TB>
 hipError_t gemm_launch(const Gemm& g, Prec prec, int kchunk, hipStream_t s) {
+  if (big_tiles(g)) {
+    // autotuned: 128 x 128 tiles with K-tiles of 32 (the default) or 16
+    // (less LDS, more workgroups per CU), or the 64 x 64 kernel
+    char key[160];
+    std::snprintf(key, sizeof key, "gemm:%d:%d%d:%dx%dx%dx%d", (int)prec, (int)TA, (int)TB, g.M, g.N, g.K, g.batch);
+    return tuned_launch(key, 3, 0, s, [&](int c) -> hipError_t {
+      if (c == 2) return gemm_small_launch<TA, TB>(g, prec, kchunk, s);
+      switch (prec) {
+        case Prec::BF16:
+          return c ? gemm_big_launch<TA, TB, 16, 1>(g, kchunk, s) : gemm_big_launch<TA, TB, 32, 1>(g, kchunk, s);
+        case Prec::BF16x3:
+          return c ? gemm_big_launch<TA, TB, 16, 2>(g, kchunk, s) : gemm_big_launch<TA, TB, 32, 2>(g, kchunk, s);
+        case Prec::BF16x6:
+          return c ? gemm_big_launch<TA, TB, 16, 3>(g, kchunk, s) : gemm_big_launch<TA, TB, 32, 3>(g, kchunk, s);
+        default:
+          return c ? gemm_big_launch<TA, TB, 16, 0>(g, kchunk, s) : gemm_big_launch<TA, TB, 32, 0>(g, kchunk, s);
+      }
+    });
+  }
+  return gemm_small_launch<TA, TB>(g, prec, kchunk, s);
+}
+
+// the 64 x 64 (or 32 x 128) kernels
+template <bool TA, bool TB>
+hipError_t gemm_small_launch(const Gemm& g, Prec prec, int kchunk, hipStream_t s) {
   const bool deep = kchunk >= 96;
   switch (prec) {
     case Prec::BF16:
