@@ -611,15 +611,16 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
   if (!f64) {
     float* W32 = static_cast<float*>(parts);  // the slices are summed: their space is free
     PQ_TRY(pq::grad_narrow(G, W32, n3 * n3, stream));
-    PQ_TRY(pq::jacobi_sweeps_f32(W32, 1, in3, in3, kDefaultSweeps32, kCoarseTol32, used, flags, stream));
+    PQ_TRY(pq::jacobi_sweeps_f32(W32, 1, in3, in3, kDefaultSweeps32, kCoarseTol32, false, used, flags, stream));
     {
       PQ_PROF("jacobi_widen", stream);
       PQ_TRY(pq::jacobi_widen(W32, W, n3 * n3, stream));
     }
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kPolishSweeps, kGramTolFloor, used + 1, flags, stream));
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kPolishSweeps, kGramTolFloor, false, 0, used + 1, flags,
+                                      stream));
   } else {
     PQ_TRY(hipMemcpyAsync(W, G, 8 * (size_t)n3 * n3, hipMemcpyDeviceToDevice, stream));
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kGramSweeps64, kPolishTol, used, flags, stream));
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kGramSweeps64, kPolishTol, false, 0, used, flags, stream));
     PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, kPolishSweeps, kPolishTol, used + 1, flags, used, kGramSweeps64,
                                  stream));
   }
@@ -647,6 +648,7 @@ size_t pq_tsvdq_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int64_t
   const int64_t kr = pq::ritz_cols(k, mn);
   return sweep_bytes(f64, n1 * n2, p)
          + align_up(8 * mn * p)                           // every singular value
+         + align_up(sizeof(int) * mn * p)                 // top-block positions
          + align_up(8 * mx * kr * p)                      // top-kr Jacobi vectors
          + align_up(8 * mn * kr * p)                      // other side (float64)
          + align_up(e * mn * k * p)                       // other side, ordered, unscaled
@@ -694,7 +696,7 @@ SweepBufs take_sweep_bufs(Arena& ar, bool f64, int64_t N, int64_t p) {
 // (Q is then float64, and so is the transform)
 int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, int64_t n3, int64_t p, Prec pr,
              double tol, int max_sweeps, const SweepBufs& b, int* info_dev, hipStream_t stream,
-             bool wide = false) {
+             bool wide = false, int ntop = 0, double* top_nrm = nullptr, int* top_pos = nullptr) {
   const bool f64 = a_dtype == PQ_F64 || wide;
   const int64_t N = n1 * n2;
   const int in1 = (int)n1, in2 = (int)n2, ip = (int)p;
@@ -715,9 +717,11 @@ int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
       PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(b.Ah), b.W32, in1, in2, ip, stream));
     }
     // float32 sweeps down to a coarse threshold (each launch profiled inside)
-    PQ_TRY(pq::jacobi_sweeps_f32(b.W32, ip, nv, L, max_sweeps, kCoarseTol32, b.used1, b.flags, stream));
+    PQ_TRY(pq::jacobi_sweeps_f32(b.W32, ip, nv, L, max_sweeps, kCoarseTol32, true, b.used1, b.flags, stream));
     PQ_PROF("jacobi_widen", stream);
-    PQ_TRY(pq::jacobi_widen(b.W32, b.W64, N * p, stream));
+    if (ntop > 0)
+      PQ_TRY(pq::jacobi_widen_top(b.W32, b.W64, nullptr, ip, nv, L, nv, 16 * ntop, top_nrm, top_pos, stream));
+    else PQ_TRY(pq::jacobi_widen(b.W32, b.W64, N * p, stream));
   }
   // float64 sweeps to tol (each launch profiled inside)
   // float64 data: Gram-form sweeps to tol (the stopping test is evaluated on
@@ -728,11 +732,11 @@ int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   const int max1 = f64 ? std::min(max_sweeps, kGramSweeps64) : max_sweeps;
   const int max2 = std::min(max_sweeps, kPolishSweeps);
   if (f64) {
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max1, tol, b.used1, b.flags, stream));
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max1, tol, false, 0, b.used1, b.flags, stream));
     PQ_TRY(pq::jacobi_sweeps_f64(b.W64, ip, nv, L, max2, tol, b.used2, b.flags, b.used1, max1, stream));
   } else {
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max2, std::max(tol, kGramTolFloor), b.used2, b.flags,
-                                      stream));
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max2, std::max(tol, kGramTolFloor), true, ntop, b.used2,
+                                      b.flags, stream));
   }
   if (info_dev) PQ_TRY(pq::jacobi_info(b.used1, b.used2, ip, max1, max2, info_dev, stream));
   return PQ_OK;
@@ -754,6 +758,7 @@ int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t 
   const SweepBufs b = take_sweep_bufs(ar, f64, N, p);
   const int kr = pq::ritz_cols(k, mn);  // columns of the Rayleigh-Ritz step
   double* sig = static_cast<double*>(ar.take(8 * mn * p));
+  int* tpos = static_cast<int*>(ar.take(sizeof(int) * mn * p));
   double* Ft = static_cast<double*>(ar.take(8 * mx * kr * p));
   double* Y = static_cast<double*>(ar.take(8 * mn * kr * p));
   void* Ys = ar.take(e * mn * k * p);
@@ -766,7 +771,12 @@ int facewise_svd(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t 
   const int in1 = (int)n1, in2 = (int)n2, ip = (int)p, ik = (int)k;
   const void* Ah = b.Ah;
   double* W64 = b.W64;
-  PQ_CHECK(converge(A, a_dtype, Q, n1, n2, n3, p, pr, tol, max_sweeps, b, info_dev, stream));
+  // float32 data of a plain truncation: the float64 polish only separates
+  // the leading blocks, which hold the Ritz step's kr columns; the SVDII
+  // selection ranks every singular value and keeps every pair
+  const int ntop = select ? 0 : pq::top_blocks(kr);
+  PQ_CHECK(converge(A, a_dtype, Q, n1, n2, n3, p, pr, tol, max_sweeps, b, info_dev, stream, false, ntop, sig,
+                    tpos));
   const bool cols = n1 >= n2;
   const int nv = (int)mn, L = (int)mx;
   void* Fo = cols ? Uhat : Vhat;     // side given by the Jacobi vectors

@@ -60,6 +60,9 @@ struct Layout {
   std::vector<size_t> sig, ft, y, ys;  // per instance finishing buffers
   size_t total = 0;
   int nfaces = 0, nb_max = 2, L_max = 1;
+  int nv_max = 1;
+  size_t tnrm = 0, tpos = 0;  // top-block norms and positions, nfaces x nv_max
+  int ntop = 2;  // leading blocks of the top-block polish (0: every pair)
   int64_t welems = 0;
 };
 
@@ -118,6 +121,10 @@ Layout layout(const pq_instance* inst, int count) {
       nb += nb & 1;
       lo.nb_max = std::max(lo.nb_max, nb);
       lo.L_max = std::max(lo.L_max, (int)std::max(x.n1, x.n2));
+      lo.nv_max = std::max(lo.nv_max, nv);
+      // enough leading blocks for every instance's Ritz columns
+      const int tb = pq::top_blocks(pq::ritz_cols(x.k, nv));
+      lo.ntop = (tb == 0 || lo.ntop == 0) ? 0 : std::max(lo.ntop, tb);
     }
   }
   lo.faces = take(sizeof(pq::JFace) * std::max(1, lo.nfaces));
@@ -128,6 +135,8 @@ Layout layout(const pq_instance* inst, int count) {
   lo.used1 = take(sizeof(int) * std::max(1, lo.nfaces));
   lo.used2 = take(sizeof(int) * std::max(1, lo.nfaces));
   lo.flags = take(sizeof(int) * (size_t)std::max(1, lo.nfaces) * kMaxSweepsCap);
+  lo.tnrm = take(sizeof(double) * (size_t)std::max(1, lo.nfaces) * lo.nv_max);
+  lo.tpos = take(sizeof(int) * (size_t)std::max(1, lo.nfaces) * lo.nv_max);
   for (int i = 0; i < count; ++i) {
     const pq_instance& x = inst[i];
     if (!has_svd(x)) continue;
@@ -170,12 +179,16 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
     BQ_TRY(pq::jacobi_prep_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), W32 + lo.woff[i], (int)x.n1,
                                (int)x.n2, (int)x.p, s));
   }
-  BQ_TRY(pq::jacobi_gram_grouped_f32(W32, faces, lo.nfaces, lo.nb_max, lo.L_max, max_sweeps, kCoarseTol, used1,
+  BQ_TRY(pq::jacobi_gram_grouped_f32(W32, faces, lo.nfaces, lo.nb_max, lo.L_max, max_sweeps, kCoarseTol, true, used1,
                                      flags, s));
-  BQ_TRY(pq::jacobi_widen(W32, W64, lo.welems, s));
+  if (lo.ntop > 0)
+    BQ_TRY(pq::jacobi_widen_top(W32, W64, faces, lo.nfaces, 0, 0, lo.nv_max, 16 * lo.ntop,
+                                reinterpret_cast<double*>(ws + lo.tnrm), reinterpret_cast<int*>(ws + lo.tpos), s));
+  else
+    BQ_TRY(pq::jacobi_widen(W32, W64, lo.welems, s));
   const int polish = std::min(max_sweeps, kPolishSweeps);
-  BQ_TRY(pq::jacobi_gram_grouped_f64(W64, faces, lo.nfaces, lo.nb_max, lo.L_max, polish,
-                                     std::max(tol, kTolFloor), used2, flags, s));
+  BQ_TRY(pq::jacobi_gram_grouped_f64(W64, faces, lo.nfaces, lo.nb_max, lo.L_max, polish, std::max(tol, kTolFloor),
+                                     true, lo.ntop, used2, flags, s));
   // per-instance finishing: top-k vectors, the other factor, orthonormal refinement
   for (int i = 0; i < count; ++i) {
     const pq_instance& x = inst[i];

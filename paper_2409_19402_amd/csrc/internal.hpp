@@ -119,8 +119,11 @@ hipError_t jacobi_prep_f32(const float* Ah, float* W, int n1, int n2, int p, hip
 hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, hipStream_t s);
 // Orthogonalises the nv vectors of every face; sweeps_used[l] gets the sweep
 // count of face l, or max_sweeps + 1 when it stopped without converging.
-// flags: p * max_sweeps ints of scratch.
-hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol,
+// flags: p * max_sweeps ints of scratch.  A face stops after a sweep that
+// rotated nothing or, with predict set, after a sweep whose largest cosine c
+// had c^2 <= tol (near convergence a sweep squares c, so the sweep itself
+// brought the face to about tol).
+hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, bool predict,
                              int* sweeps_used, int* flags, hipStream_t s);
 // Grouped Jacobi over faces of different sizes (the batched form): faces[f]
 // (device) gives face f's element offset in W, its vector count and length.
@@ -132,13 +135,16 @@ struct JFace {
   int nv, L;
 };
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, int* used, int* flags, hipStream_t s);
+                                   int max_sweeps, double tol, bool predict, int* used, int* flags, hipStream_t s);
+// ntop (1 or 2; 0 = every pair): the top-block schedule, which visits only
+// the pairs with a vector in the first ntop 16-vector blocks of a face
 hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, int* used, int* flags, hipStream_t s);
+                                   int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags,
+                                   hipStream_t s);
 // float64 sweeps in the Gram-matrix form (the polishing sweeps of float32
-// data)
-hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
-                                  int* flags, hipStream_t s);
+// data); ntop as above
+hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, bool predict,
+                                  int ntop, int* used, int* flags, hipStream_t s);
 // prior (may be null): a face with prior[f] <= prior_max converged in an
 // earlier phase and is left alone (sweeps_used[f] = 0)
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol,
@@ -182,6 +188,16 @@ constexpr int kRitzExtra = 8;
 inline int ritz_cols(int64_t k, int64_t nv) { return (int)(k + kRitzExtra < nv ? k + kRitzExtra : nv); }
 // y[i] = x[i] for i < n (float32 -> float64)
 hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s);
+// the same per face (faces: the table of the grouped form, or null for p =
+// nfaces faces of nv_u x L_u), the ntop16 vectors of largest norm moved to
+// the front in descending order (the leading blocks of the top-block
+// schedule), the others after them in their own order; nrm (doubles) and
+// pos (ints): nfaces x nv_max of scratch each; nv_max <= 4096
+hipError_t jacobi_widen_top(const float* W32, double* W64, const JFace* faces, int nfaces, int nv_u, int L_u,
+                            int nv_max, int ntop16, double* nrm, int* pos, hipStream_t s);
+// leading 16-vector blocks of the top-block polish for a Ritz step on kr
+// columns: 1 or 2, or 0 (the full schedule) when kr needs more
+inline int top_blocks(int kr) { return kr <= 16 ? 1 : kr <= 32 ? 2 : 0; }
 // Y = Ah_l^T F_l (cols: Y n2 x k, F n1 x k) or Ah_l F_l (rows: Y n1 x k,
 // F n2 x k) per face, float64 accumulation and result
 hipError_t jacobi_factor_f32(const float* Ah, const double* F, double* Y, int n1, int n2, int k, int p,

@@ -8,7 +8,9 @@
 // rotation that zeroes gamma, and applies it.  Converged vectors are mutually
 // orthogonal; their norms are the singular values and, normalised, they are
 // the singular vectors of their side.  A face has converged after a sweep in
-// which no pair had |gamma| > tol sqrt(alpha beta).
+// which no pair had |gamma| > tol sqrt(alpha beta), or (the sweeps of
+// float32 data) after a sweep whose largest |gamma| / sqrt(alpha beta) was
+// at most sqrt(tol), which by quadratic convergence leaves it near tol.
 //
 // Schedule (block form): the nv vectors are cut into nb blocks of b vectors
 // (nb even; vectors past nv are zero and never rotate; b = 4 per wave, one
@@ -455,11 +457,46 @@ __device__ __forceinline__ float swap_pair(float v) {
 }
 __device__ __forceinline__ double swap_pair(double v) { return dpp_f64<0xB1>(v); }
 
+// Top-block schedule of a sweep (ntop = 1 or 2 leading blocks, on a face of
+// nb >= 2 ntop + 2 blocks; other faces keep the full schedule): only the
+// pairs with at least one vector in the leading blocks are visited.  Round r
+// < nb - ntop pairs leading block t = pair with trailing block ntop + (r + t)
+// mod (nb - ntop), so that the visits of a round touch distinct blocks; with
+// two leading blocks one more round visits (0, 1).  The first visit of each
+// leading block in a sweep (round 0) and the (0, 1) visit run the full round
+// robin over their 32 vectors, which covers the pairs inside the blocks.
+// Launches per sweep: nb - ntop (+ 1 for two leading blocks), ntop visits
+// each.  Used for the float64 polishing of float32 data once the leading
+// blocks hold the vectors of largest norm: the Ritz step that follows needs
+// only those to be orthogonal to all others.
+__host__ __device__ __forceinline__ bool top_schedule(int ntop, int nb) {
+  return (ntop == 1 || ntop == 2) && nb >= 2 * ntop + 2;
+}
+__host__ __device__ __forceinline__ int top_rounds(int ntop, int nb) { return nb - ntop + (ntop > 1 ? 1 : 0); }
+
+// visit `pair` of round `round`: blocks (I, J) and whether it runs the full
+// round robin; false when the slot is idle
+__device__ __forceinline__ bool top_pair(int ntop, int nb, int round, int pair, int& I, int& J, bool& full) {
+  const int nbot = nb - ntop;
+  if (pair >= ntop || round >= top_rounds(ntop, nb)) return false;
+  if (round < nbot) {
+    I = pair;
+    J = ntop + (round + pair) % nbot;
+    full = round == 0;
+    return true;
+  }
+  if (pair > 0) return false;
+  I = 0;
+  J = 1;
+  full = true;
+  return true;
+}
+
 template <typename T, int NB, bool ST, int NW>
 __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W, const JFace* __restrict__ faces,
                                                               int nfaces, int npair, int nv_u, int L_u, int round,
-                                                              int sweep, int max_sweeps, double tol,
-                                                              int* __restrict__ flags) {
+                                                              int sweep, int max_sweeps, double tol, float skip2,
+                                                              int ntop, int* __restrict__ flags) {
   typedef GramMfma<T> M;
   typedef typename M::vec_t vec_t;
   constexpr int VEC = M::kVec;
@@ -488,14 +525,19 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
   const int nv = fd.nv, L = fd.L;
   int nb = (nv + kGB - 1) / kGB;
   nb += nb & 1;
-  if (round >= nb - 1 || pair >= nb / 2) return;
-  if (sweep > 0 && flags[f * max_sweeps + sweep - 1] == 0) return;
+  int I, J;
+  bool full = round == 0;
+  if (top_schedule(ntop, nb)) {
+    if (!top_pair(ntop, nb, round, pair, I, J, full)) return;
+  } else {
+    if (round >= nb - 1 || pair >= nb / 2) return;
+    circle_pair(nb, round, pair, I, J);
+  }
+  if (sweep > 0 && __int_as_float(flags[f * max_sweeps + sweep - 1]) <= skip2) return;
   const int Lp = (L + 15) & ~15;
   const int ldx = gram_ldx<T>(L);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  int I, J;
-  circle_pair(nb, round, pair, I, J);
   T* Wf = W + fd.off;
   auto gvec = [&](int u) { return u < kGB ? I * kGB + u : J * kGB + (u - kGB); };
 
@@ -677,29 +719,36 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
   }
   __syncthreads();
 
-  // does any pair of this visit need a rotation?
-  const bool full = round == 0;
+  // does any pair of this visit need a rotation?  The largest squared
+  // cosine g^2 / (g_aa g_cc) of the pairs this visit covers (0 for zero or
+  // non-finite columns) is taken as float bits, whose integer order is the
+  // order of non-negative floats, and the visits of a sweep leave the face's
+  // largest in its flag word
   const double tol2 = tol * tol;
   {
-    bool need = false;
+    float mx = 0.f;
+    auto cos2 = [&](int i, int c) {
+      const double g = Gb[i * kGld + c];
+      // the hardware reciprocal (about 1e-15 relative): the value only meets thresholds
+      const double r = g * g * __builtin_amdgcn_rcp((double)Gb[i * kGld + i] * (double)Gb[c * kGld + c]);
+      return r > 0.0 ? (float)r : 0.f;  // NaN (0 / 0 included) never asks for a rotation
+    };
     if (full) {
       for (int e = tid; e < kG2 * kG2; e += NT) {
         const int i = e >> 5, c = e & 31;
-        if (i < c) {
-          const double g = Gb[i * kGld + c];
-          need |= g * g > tol2 * (double)Gb[i * kGld + i] * (double)Gb[c * kGld + c];
-        }
+        if (i < c) mx = fmaxf(mx, cos2(i, c));
       }
     } else if (tid < kGB * kGB) {
-      const int i = tid >> 4, c = kGB + (tid & 15);
-      const double g = Gb[i * kGld + c];
-      need = g * g > tol2 * (double)Gb[i * kGld + i] * (double)Gb[c * kGld + c];
+      mx = cos2(tid >> 4, kGB + (tid & 15));
     }
-    if (need) *any_rot = 1;
+    // one LDS atomic per wave
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0 && mx > (float)tol2) atomicMax(any_rot, __float_as_int(mx));
     __syncthreads();
     if (*any_rot == 0) return;  // the block pair is converged: nothing to do
   }
-  if (tid == 0) flags[f * max_sweeps + sweep] = 1;
+  if (tid == 0) atomicMax(&flags[f * max_sweeps + sweep], *any_rot);
 
   if constexpr (NW == 4) {
     // Rounds on G.  Each round reads the current copy of G and writes every
@@ -924,7 +973,7 @@ __global__ void zero_ints_kernel(int* __restrict__ x, int n) {
 
 // sweeps_used[l] from the per-sweep rotation flags: the first sweep without a
 // rotation ends the iteration (it is counted); none means not converged.
-__global__ void count_sweeps_kernel(const int* __restrict__ flags, int p, int max_sweeps,
+__global__ void count_sweeps_kernel(const int* __restrict__ flags, int p, int max_sweeps, float skip2,
                                     int* __restrict__ sweeps_used, const int* __restrict__ prior = nullptr,
                                     int prior_max = 0) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -935,7 +984,7 @@ __global__ void count_sweeps_kernel(const int* __restrict__ flags, int p, int ma
   }
   int u = max_sweeps + 1;
   for (int s = 0; s < max_sweeps; ++s) {
-    if (flags[l * max_sweeps + s] == 0) {
+    if (__int_as_float(flags[l * max_sweeps + s]) <= skip2) {
       u = s + 1;
       break;
     }
@@ -1214,6 +1263,67 @@ __global__ __launch_bounds__(64 * kRefineWaves) void refine_kernel(T* __restrict
   }
 }
 
+// The float32 -> float64 copy of the Jacobi vectors for the top-block
+// polishing sweeps, in three launches: the squared norm of every vector
+// (one wave per vector), the target position of every vector (one workgroup
+// per face: the ntop16 of largest norm, ties by index and a NaN norm counting
+// as the smallest, go to the front in descending order of norm, the others
+// follow in their own order), and the permuted copy (one wave per vector).
+// Per-face arrays (norms, positions) are ld entries apart.
+__global__ __launch_bounds__(256) void top_norms_kernel(const float* __restrict__ W32, const JFace* __restrict__ faces,
+                                                        int nv_u, int L_u, int ld, double* __restrict__ nrm) {
+  const JFace fd = face_of(faces, blockIdx.y, nv_u, L_u);
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= fd.nv) return;
+  const float* v = W32 + fd.off + (int64_t)j * fd.L;
+  double acc = 0.0;
+  for (int e = lane; e < fd.L; e += 64) {
+    const double x = (double)v[e];
+    acc = fma(x, x, acc);
+  }
+  acc = wave_total(acc);
+  if (lane == 0) nrm[(int64_t)blockIdx.y * ld + j] = acc == acc ? acc : -1.0;
+}
+
+__global__ __launch_bounds__(256) void top_perm_kernel(const double* __restrict__ nrm_g, const JFace* __restrict__ faces,
+                                                       int nv_u, int L_u, int ld, int ntop16, int* __restrict__ pos_g) {
+  extern __shared__ double tp_smem[];  // nv norms, then nv ranks
+  const int nv = face_of(faces, blockIdx.x, nv_u, L_u).nv;
+  double* nrm = tp_smem;
+  int* rank = reinterpret_cast<int*>(tp_smem + nv);
+  for (int j = threadIdx.x; j < nv; j += 256) nrm[j] = nrm_g[(int64_t)blockIdx.x * ld + j];
+  __syncthreads();
+  for (int j = threadIdx.x; j < nv; j += 256) {
+    const double v = nrm[j];
+    int r = 0;
+    for (int i = 0; i < nv; ++i) r += (nrm[i] > v) || (nrm[i] == v && i < j);
+    rank[j] = r;
+  }
+  __syncthreads();
+  const int nt = min(ntop16, nv);
+  for (int j = threadIdx.x; j < nv; j += 256) {
+    int to = rank[j];
+    if (to >= nt) {  // after the leading nt, in index order
+      int c = 0;
+      for (int i = 0; i < j; ++i) c += rank[i] >= nt;
+      to = nt + c;
+    }
+    pos_g[(int64_t)blockIdx.x * ld + j] = to;
+  }
+}
+
+__global__ __launch_bounds__(256) void top_copy_kernel(const float* __restrict__ W32, double* __restrict__ W64,
+                                                       const JFace* __restrict__ faces, int nv_u, int L_u, int ld,
+                                                       const int* __restrict__ pos_g) {
+  const JFace fd = face_of(faces, blockIdx.y, nv_u, L_u);
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= fd.nv) return;
+  const int to = pos_g[(int64_t)blockIdx.y * ld + j];
+  const float* src = W32 + fd.off + (int64_t)j * fd.L;
+  double* dst = W64 + fd.off + (int64_t)to * fd.L;
+  for (int e = lane; e < fd.L; e += 64) dst[e] = (double)src[e];
+}
+
 // float32 -> float64 copy of the Jacobi vectors (the float64 polishing sweeps)
 __global__ __launch_bounds__(256) void widen_kernel(const float* __restrict__ x, double* __restrict__ y,
                                                     int64_t n) {
@@ -1313,17 +1423,19 @@ __global__ __launch_bounds__(256) void factor_rows_kernel(const TA* __restrict__
 // 8 k (m1 + m2) bytes.  A face works on min(k, kface[f] + extra) columns
 // when kface is given (the rest are zero, never rotate, and sort last) and
 // keeps min(kout, kface[f]) of them.
-template <typename TO>
-__global__ __launch_bounds__(1024) void refine_lds_kernel(const double* __restrict__ Yg, const double* __restrict__ Fg,
+// FG: only Y is held in LDS and F is rotated in place in global memory (the
+// L2), for faces whose k columns of both do not fit.
+template <typename TO, bool FG>
+__global__ __launch_bounds__(1024) void refine_lds_kernel(const double* __restrict__ Yg, double* __restrict__ Fg,
                                                           int m1, int m2, int k, int kout,
                                                           const int* __restrict__ kface, int extra, double tol,
                                                           int max_sweeps, TO* __restrict__ s_out,
                                                           TO* __restrict__ Other, TO* __restrict__ Fo,
                                                           TO* __restrict__ Ys) {
   extern __shared__ double rl_smem[];
-  double* Yf = rl_smem;               // k columns of m1
-  double* Ff = Yf + (int64_t)k * m1;  // k columns of m2
-  double* sig = Ff + (int64_t)k * m2;
+  double* Yf = rl_smem;  // k columns of m1
+  double* Ff = FG ? Fg + (int64_t)blockIdx.x * m2 * k : Yf + (int64_t)k * m1;  // k columns of m2
+  double* sig = FG ? Yf + (int64_t)k * m1 : Ff + (int64_t)k * m2;
   int* order = reinterpret_cast<int*>(sig + k);
   __shared__ int any_rot;
   const int face = blockIdx.x;
@@ -1333,7 +1445,9 @@ __global__ __launch_bounds__(1024) void refine_lds_kernel(const double* __restri
   const double* yg = Yg + (int64_t)face * m1 * k;
   const double* fg = Fg + (int64_t)face * m2 * k;
   for (int e = tid; e < k * m1; e += 1024) Yf[e] = yg[e];
-  for (int e = tid; e < k * m2; e += 1024) Ff[e] = fg[e];
+  if constexpr (!FG) {
+    for (int e = tid; e < k * m2; e += 1024) Ff[e] = fg[e];
+  }
   __syncthreads();
   const int kp = kf + (kf & 1);
   for (int sweep = 0; sweep < max_sweeps && kf > 1; ++sweep) {
@@ -1480,7 +1594,7 @@ hipError_t block_sweeps(T* W, int p, int nv, int L, int nw, int max_sweeps, doub
   }
   {
     ProfScope prof("jacobi_flags", s);
-    count_sweeps_kernel<<<(p + 63) / 64, 64, 0, s>>>(flags, p, max_sweeps, used, prior, prior_max);
+    count_sweeps_kernel<<<(p + 63) / 64, 64, 0, s>>>(flags, p, max_sweeps, 0.f, used, prior, prior_max);
   }
   return hipGetLastError();
 }
@@ -1538,53 +1652,88 @@ GramForm gram_form(int L, int grid) {
   }
 }
 
+// launches of one sweep and visit slots per face: the full schedule of the
+// largest face, or the top-block schedule (whose smaller faces, on the full
+// schedule, fit in as many slots and rounds: nb <= 2 ntop blocks take at most
+// ntop slots and 2 ntop - 1 <= top_rounds rounds)
+inline void sweep_shape(int ntop, int nb_max, int& rounds, int& slots) {
+  if (top_schedule(ntop, nb_max)) {
+    rounds = top_rounds(ntop, nb_max);
+    slots = ntop;
+  } else {
+    rounds = nb_max - 1;
+    slots = nb_max / 2;
+  }
+}
+
 template <typename T, int NB, bool ST, int NW>
 void gram_launch_all(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max, int max_sweeps,
-                     double tol, int* flags, hipStream_t s) {
+                     double tol, float skip2, int ntop, int* flags, hipStream_t s) {
   const size_t lds = gram_lds_bytes<T, NB, ST>(L_max);
   (void)gram_lds_cap<T, NB, ST, NW>();  // sets the kernel's LDS limit once
+  int rounds, slots;
+  sweep_shape(ntop, nb_max, rounds, slots);
+  if (!top_schedule(ntop, nb_max)) ntop = 0;
   for (int sw = 0; sw < max_sweeps; ++sw)
-    for (int round = 0; round < nb_max - 1; ++round)
-      jacobi_gram_kernel<T, NB, ST, NW><<<(unsigned)gram_grid(nfaces, nb_max / 2), 64 * NW, lds, s>>>(
-          W, faces, nfaces, nb_max / 2, nv_u, L_u, round, sw, max_sweeps, tol, flags);
+    for (int round = 0; round < rounds; ++round)
+      jacobi_gram_kernel<T, NB, ST, NW><<<(unsigned)gram_grid(nfaces, slots), 64 * NW, lds, s>>>(
+          W, faces, nfaces, slots, nv_u, L_u, round, sw, max_sweeps, tol, skip2, ntop, flags);
 }
+
+// Stopping rule of the Gram-form sweeps.  A face stops after a sweep in
+// which no pair needed a rotation (largest squared cosine <= tol^2 on its
+// flag word).  With predict set it also stops after a sweep whose largest
+// cosine c before rotation had c^2 <= tol: near convergence a cyclic Jacobi
+// sweep squares the largest cosine (the quadratic convergence of the cyclic
+// method), so that sweep itself left the face at about tol, and the sweep
+// that would only confirm it is not run.  The float32 data's phases predict
+// (their result is settled by the float64 Ritz step on the transform-domain
+// face); float64 data and the U3 eigenvectors confirm.
+inline float sweep_skip2(double tol, bool predict) { return (float)(predict ? std::max(tol * tol, tol) : tol * tol); }
 
 template <typename T>
 hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max,
-                       int max_sweeps, double tol, int* used, int* flags, hipStream_t s) {
+                       int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags, hipStream_t s) {
   const int nflags = nfaces * max_sweeps;
   {
     ProfScope prof("jacobi_flags", s);
     zero_ints_kernel<<<(nflags + 255) / 256, 256, 0, s>>>(flags, nflags);
   }
-  const GramForm form = gram_form<T>(L_max, gram_grid(nfaces, nb_max / 2));
+  int rounds, slots;
+  sweep_shape(ntop, nb_max, rounds, slots);
+  const GramForm form = gram_form<T>(L_max, gram_grid(nfaces, slots));
+  const float skip2 = sweep_skip2(tol, predict);
   {
-    ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s, max_sweeps * (nb_max - 1));
+    ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s, max_sweeps * rounds);
     // staged visits get eight waves (two per SIMD hide each other's latency)
     if (form == GramForm::Stream) {
-      gram_launch_all<T, 2, false, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+      gram_launch_all<T, 2, false, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop,
+                                       flags, s);
     } else if constexpr (sizeof(T) == 4) {
       if (form == GramForm::Staged1)
-        gram_launch_all<T, 1, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+        gram_launch_all<T, 1, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop,
+                                       flags, s);
       else
-        gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+        gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop,
+                                       flags, s);
     } else {
-      gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, flags, s);
+      gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop, flags,
+                                     s);
     }
   }
   {
     ProfScope prof("jacobi_flags", s);
-    count_sweeps_kernel<<<(nfaces + 63) / 64, 64, 0, s>>>(flags, nfaces, max_sweeps, used);
+    count_sweeps_kernel<<<(nfaces + 63) / 64, 64, 0, s>>>(flags, nfaces, max_sweeps, skip2, used);
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t gram_sweeps_uniform(T* W, int p, int nv, int L, int max_sweeps, double tol, int* used, int* flags,
-                               hipStream_t s) {
+hipError_t gram_sweeps_uniform(T* W, int p, int nv, int L, int max_sweeps, double tol, bool predict, int ntop,
+                               int* used, int* flags, hipStream_t s) {
   int nb = (nv + kGB - 1) / kGB;
   nb += nb & 1;
-  return gram_sweeps<T>(W, nullptr, p, nv, L, nb, L, max_sweeps, tol, used, flags, s);
+  return gram_sweeps<T>(W, nullptr, p, nv, L, nb, L, max_sweeps, tol, predict, ntop, used, flags, s);
 }
 
 // waves per workgroup (4 vectors of a block each): blocks of 16 vectors, fewer
@@ -1648,16 +1797,24 @@ hipError_t refine(double* Y, double* F, int m1, int m2, int k, int kout, int p, 
                   double tol, TO* s_out, TO* Other, TO* Fo, TO* Ys, hipStream_t s) {
   // dynamic LDS up to 159 KiB (the kernel's static word fits in the rest)
   constexpr size_t kLdsCap = 159 * 1024;
-  const size_t lds_lds = sizeof(double) * (size_t)k * (m1 + m2) + (sizeof(double) + sizeof(int)) * (size_t)k;
+  const size_t tail = (sizeof(double) + sizeof(int)) * (size_t)k;
+  const size_t lds_both = sizeof(double) * (size_t)k * (m1 + m2) + tail;
+  const size_t lds_y = sizeof(double) * (size_t)k * m1 + tail;
   static const hipError_t attr = [] {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&refine_lds_kernel<TO>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsCap);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&refine_lds_kernel<TO, false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsCap);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&refine_lds_kernel<TO, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsCap);
     if (e != hipSuccess) (void)hipGetLastError();  // clear a refused request: the global form runs instead
     return e;
   }();
-  if (attr == hipSuccess && lds_lds <= kLdsCap) {
-    refine_lds_kernel<TO><<<p, 1024, lds_lds, s>>>(Y, F, m1, m2, k, kout, kface, extra, tol, 12, s_out, Other, Fo,
-                                                   Ys);
+  if (attr == hipSuccess && lds_both <= kLdsCap) {
+    refine_lds_kernel<TO, false><<<p, 1024, lds_both, s>>>(Y, F, m1, m2, k, kout, kface, extra, tol, 12, s_out, Other,
+                                                          Fo, Ys);
+  } else if (attr == hipSuccess && lds_y <= kLdsCap) {
+    refine_lds_kernel<TO, true><<<p, 1024, lds_y, s>>>(Y, F, m1, m2, k, kout, kface, extra, tol, 12, s_out, Other,
+                                                         Fo, Ys);
   } else {
     const size_t lds = (sizeof(double) + sizeof(int)) * (size_t)k;
     refine_kernel<double, TO><<<p, 64 * kRefineWaves, lds, s>>>(Y, F, m1, m2, k, kout, kface, extra, tol, 12,
@@ -1686,25 +1843,27 @@ hipError_t jacobi_prep_f32(const float* Ah, float* W, int n1, int n2, int p, hip
 hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, hipStream_t s) {
   return prep<double>(Ah, W, n1, n2, p, s);
 }
-hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
+hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, bool predict, int* used,
                              int* flags, hipStream_t s) {
-  return gram_sweeps_uniform<float>(W, p, nv, L, max_sweeps, tol, used, flags, s);
+  return gram_sweeps_uniform<float>(W, p, nv, L, max_sweeps, tol, predict, 0, used, flags, s);
 }
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                              int* flags, const int* prior, int prior_max, hipStream_t s) {
   return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, prior, prior_max, s);
 }
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, int* used, int* flags, hipStream_t s) {
-  return gram_sweeps<float>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, used, flags, s);
+                                   int max_sweeps, double tol, bool predict, int* used, int* flags, hipStream_t s) {
+  return gram_sweeps<float>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, predict, 0, used, flags, s);
 }
 hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, int* used, int* flags, hipStream_t s) {
-  return gram_sweeps<double>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, used, flags, s);
+                                   int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags,
+                                   hipStream_t s) {
+  return gram_sweeps<double>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, predict, ntop, used, flags,
+                             s);
 }
-hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
-                                  int* flags, hipStream_t s) {
-  return gram_sweeps_uniform<double>(W, p, nv, L, max_sweeps, tol, used, flags, s);
+hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, bool predict,
+                                  int ntop, int* used, int* flags, hipStream_t s) {
+  return gram_sweeps_uniform<double>(W, p, nv, L, max_sweeps, tol, predict, ntop, used, flags, s);
 }
 hipError_t jacobi_norms_f64(const double* W, int p, int nv, int L, double* sig, int* rank, hipStream_t s) {
   norms_kernel<double><<<dim3((unsigned)((nv + 3) / 4), (unsigned)p), 256, 0, s>>>(W, nv, L, sig, rank);
@@ -1734,6 +1893,15 @@ hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int ko
                              int extra, double tol, double* s_out, double* Other, double* Fo, double* Ys,
                              hipStream_t s) {
   return refine<double>(Y, F, m1, m2, k, kout, p, kface, extra, tol, s_out, Other, Fo, Ys, s);
+}
+hipError_t jacobi_widen_top(const float* W32, double* W64, const JFace* faces, int nfaces, int nv_u, int L_u,
+                            int nv_max, int ntop16, double* nrm, int* pos, hipStream_t s) {
+  const dim3 grid((unsigned)((nv_max + 3) / 4), (unsigned)nfaces);
+  top_norms_kernel<<<grid, 256, 0, s>>>(W32, faces, nv_u, L_u, nv_max, nrm);
+  top_perm_kernel<<<(unsigned)nfaces, 256, (sizeof(double) + sizeof(int)) * (size_t)nv_max, s>>>(
+      nrm, faces, nv_u, L_u, nv_max, ntop16, pos);
+  top_copy_kernel<<<grid, 256, 0, s>>>(W32, W64, faces, nv_u, L_u, nv_max, pos);
+  return hipGetLastError();
 }
 hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s) {
   widen_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
