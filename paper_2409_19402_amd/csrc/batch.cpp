@@ -52,8 +52,10 @@ bool has_svd(const pq_instance& x) { return x.Uhat != nullptr; }
 // Workspace layout of a batch (byte offsets into the caller's workspace).
 struct Layout {
   size_t faces = 0;            // JFace table (device)
-  size_t qws = 0, qws_bytes = 0;  // pq_qprod workspace, shared by the instances in turn
   std::vector<size_t> ah;      // per instance: Ah (float32, n1 x n2 x p)
+  std::vector<size_t> bh, ch;  // per product instance: Bh (n2 x n4 x p), Ch (n1 x n4 x p)
+  size_t gdesc = 0, gtile = 0;  // grouped facewise GEMM: product and tile tables
+  int nprod = 0, ntiles = 0;
   std::vector<int64_t> woff;   // per instance: element offset of its faces in W32 / W64
   std::vector<int> face0;      // per instance: index of its first face
   size_t w32 = 0, w64 = 0, used1 = 0, used2 = 0, flags = 0;
@@ -62,6 +64,8 @@ struct Layout {
   int nfaces = 0, nb_max = 2, L_max = 1;
   int nv_max = 1;
   size_t tnrm = 0, tpos = 0;  // top-block norms and positions, nfaces x nv_max
+  size_t fin = 0;             // finishing table (FinFace per face)
+  pq::FinMax fmax;
   int ntop = 2;  // leading blocks of the top-block polish (0: every pair)
   int64_t welems = 0;
 };
@@ -110,7 +114,10 @@ Layout layout(const pq_instance* inst, int count) {
   for (int i = 0; i < count; ++i) {
     const pq_instance& x = inst[i];
     if (x.B)
-      lo.qws_bytes = std::max(lo.qws_bytes, pq_qprod_workspace(x.n1, x.n2, x.n4, x.n3, x.p, PQ_F32));
+    {
+      ++lo.nprod;
+      lo.ntiles += (int)(((x.n1 + 127) / 128) * ((x.n4 + 127) / 128) * x.p);
+    }
     if (has_svd(x)) {
       lo.face0[i] = lo.nfaces;
       lo.woff[i] = lo.welems;
@@ -122,14 +129,28 @@ Layout layout(const pq_instance* inst, int count) {
       lo.nb_max = std::max(lo.nb_max, nb);
       lo.L_max = std::max(lo.L_max, (int)std::max(x.n1, x.n2));
       lo.nv_max = std::max(lo.nv_max, nv);
+      lo.fmax.n1 = std::max(lo.fmax.n1, (int)x.n1);
+      lo.fmax.n2 = std::max(lo.fmax.n2, (int)x.n2);
+      lo.fmax.nv = std::max(lo.fmax.nv, nv);
+      lo.fmax.nvL = std::max(lo.fmax.nvL, (int)(x.n1 + x.n2));
+      lo.fmax.kr = std::max(lo.fmax.kr, pq::ritz_cols(x.k, nv));
       // enough leading blocks for every instance's Ritz columns
       const int tb = pq::top_blocks(pq::ritz_cols(x.k, nv));
       lo.ntop = (tb == 0 || lo.ntop == 0) ? 0 : std::max(lo.ntop, tb);
     }
   }
   lo.faces = take(sizeof(pq::JFace) * std::max(1, lo.nfaces));
-  lo.qws = take(std::max<size_t>(lo.qws_bytes, 1));
   for (int i = 0; i < count; ++i) lo.ah[i] = take(4 * (size_t)inst[i].n1 * inst[i].n2 * inst[i].p);
+  lo.bh.assign(count, 0);
+  lo.ch.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!x.B) continue;
+    lo.bh[i] = take(4 * (size_t)x.n2 * x.n4 * x.p);
+    lo.ch[i] = take(4 * (size_t)x.n1 * x.n4 * x.p);
+  }
+  lo.gdesc = take(sizeof(pq::GemmDesc) * (size_t)std::max(1, lo.nprod));
+  lo.gtile = take(sizeof(pq::GemmTile) * (size_t)std::max(1, lo.ntiles));
   lo.w32 = take(4 * (size_t)std::max<int64_t>(lo.welems, 1));
   lo.w64 = take(8 * (size_t)std::max<int64_t>(lo.welems, 1));
   lo.used1 = take(sizeof(int) * std::max(1, lo.nfaces));
@@ -137,6 +158,7 @@ Layout layout(const pq_instance* inst, int count) {
   lo.flags = take(sizeof(int) * (size_t)std::max(1, lo.nfaces) * kMaxSweepsCap);
   lo.tnrm = take(sizeof(double) * (size_t)std::max(1, lo.nfaces) * lo.nv_max);
   lo.tpos = take(sizeof(int) * (size_t)std::max(1, lo.nfaces) * lo.nv_max);
+  lo.fin = take(sizeof(pq::FinFace) * (size_t)std::max(1, lo.nfaces));
   for (int i = 0; i < count; ++i) {
     const pq_instance& x = inst[i];
     if (!has_svd(x)) continue;
@@ -160,16 +182,21 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
   int* used2 = reinterpret_cast<int*>(ws + lo.used2);
   int* flags = reinterpret_cast<int*>(ws + lo.flags);
   const pq::JFace* faces = reinterpret_cast<const pq::JFace*>(ws + lo.faces);
-  // transforms, facewise products and back-projections
+  // transforms of every instance, the facewise products of all of them in
+  // one launch, the back-projections
   for (int i = 0; i < count; ++i) {
     const pq_instance& x = inst[i];
-    void* Ah = ws + lo.ah[i];
-    if (x.B) {
-      BQ_CHECK(pq_qprod(x.A, x.B, PQ_F32, x.Q, x.C, x.n1, x.n2, x.n4, x.n3, x.p, PQ_PREC_DEFAULT, Ah, nullptr,
-                        ws + lo.qws, lo.qws_bytes, s));
-    } else {
-      BQ_CHECK(pq_hat(x.A, PQ_F32, x.Q, Ah, x.n1, x.n2, x.n3, x.p, PQ_PREC_DEFAULT, s));
-    }
+    BQ_CHECK(pq_hat(x.A, PQ_F32, x.Q, ws + lo.ah[i], x.n1, x.n2, x.n3, x.p, PQ_PREC_DEFAULT, s));
+    if (x.B) BQ_CHECK(pq_hat(x.B, PQ_F32, x.Q, ws + lo.bh[i], x.n2, x.n4, x.n3, x.p, PQ_PREC_DEFAULT, s));
+  }
+  if (lo.ntiles > 0) {
+    pq::ProfScope prof("facewise_gemm", s);
+    BQ_TRY(pq::gemm_f32_grouped(reinterpret_cast<const pq::GemmDesc*>(ws + lo.gdesc),
+                                reinterpret_cast<const pq::GemmTile*>(ws + lo.gtile), lo.ntiles, s));
+  }
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (x.B) BQ_CHECK(pq_unhat(ws + lo.ch[i], x.Q, x.C, PQ_F32, x.n1, x.n4, x.n3, x.p, PQ_PREC_DEFAULT, s));
   }
   if (lo.nfaces == 0) return PQ_OK;
   // Jacobi vectors of every face, then the grouped sweeps
@@ -189,26 +216,9 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
   const int polish = std::min(max_sweeps, kPolishSweeps);
   BQ_TRY(pq::jacobi_gram_grouped_f64(W64, faces, lo.nfaces, lo.nb_max, lo.L_max, polish, std::max(tol, kTolFloor),
                                      true, lo.ntop, used2, flags, s));
-  // per-instance finishing: top-k vectors, the other factor, orthonormal refinement
-  for (int i = 0; i < count; ++i) {
-    const pq_instance& x = inst[i];
-    if (!has_svd(x)) continue;
-    const bool cols = x.n1 >= x.n2;
-    const int nv = (int)std::min(x.n1, x.n2), L = (int)std::max(x.n1, x.n2);
-    const int ip = (int)x.p, ik = (int)x.k, kr = pq::ritz_cols(x.k, nv);
-    double* Ft = reinterpret_cast<double*>(ws + lo.ft[i]);
-    double* Y = reinterpret_cast<double*>(ws + lo.y[i]);
-    float* Ys = reinterpret_cast<float*>(ws + lo.ys[i]);
-    float* Fo = static_cast<float*>(cols ? x.Uhat : x.Vhat);
-    float* Other = static_cast<float*>(cols ? x.Vhat : x.Uhat);
-    double* sig = reinterpret_cast<double*>(ws + lo.sig[i]);
-    BQ_TRY(pq::jacobi_norms_f64(W64 + lo.woff[i], ip, nv, L, sig, nullptr, s));
-    BQ_TRY(pq::jacobi_finalize_f64(W64 + lo.woff[i], sig, ip, nv, L, kr, nullptr, 0, Ft, nullptr, s));
-    BQ_TRY(pq::jacobi_factor_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), Ft, Y, (int)x.n1, (int)x.n2, kr,
-                                 ip, cols, s));
-    BQ_TRY(pq::jacobi_refine_f32(Y, Ft, nv, L, kr, ik, ip, nullptr, 0, tol, static_cast<float*>(x.s), Other, Fo, Ys,
-                                 s));
-  }
+  // finishing of every face at once: the top kr vectors, the other factor
+  // and the Ritz step (one launch each over the face table)
+  BQ_TRY(pq::jacobi_finish_grouped(reinterpret_cast<const pq::FinFace*>(ws + lo.fin), lo.nfaces, lo.fmax, tol, s));
   if (info_dev) BQ_TRY(pq::jacobi_info(used1, used2, lo.nfaces, max_sweeps, polish, info_dev, s));
   return PQ_OK;
 }
@@ -244,9 +254,75 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
     const int nv = (int)std::min(x.n1, x.n2), L = (int)std::max(x.n1, x.n2);
     for (int64_t l = 0; l < x.p; ++l) tab.push_back(pq::JFace{lo.woff[i] + l * nv * L, nv, L});
   }
+  // the finishing table: every face's operands and outputs
+  std::vector<pq::FinFace> fin;
+  fin.reserve(lo.nfaces);
+  double* W64 = reinterpret_cast<double*>(w + lo.w64);
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!has_svd(x)) continue;
+    const bool cols = x.n1 >= x.n2;
+    const int64_t nv = std::min(x.n1, x.n2), L = std::max(x.n1, x.n2);
+    const int64_t kr = pq::ritz_cols(x.k, nv);
+    float* Fo = static_cast<float*>(cols ? x.Uhat : x.Vhat);
+    float* Other = static_cast<float*>(cols ? x.Vhat : x.Uhat);
+    for (int64_t l = 0; l < x.p; ++l) {
+      pq::FinFace f;
+      f.w = W64 + lo.woff[i] + l * nv * L;
+      f.ah = reinterpret_cast<const float*>(w + lo.ah[i]) + l * x.n1 * x.n2;
+      f.sig = reinterpret_cast<double*>(w + lo.sig[i]) + l * nv;
+      f.ft = reinterpret_cast<double*>(w + lo.ft[i]) + l * L * kr;
+      f.y = reinterpret_cast<double*>(w + lo.y[i]) + l * nv * kr;
+      f.s = static_cast<float*>(x.s) + l * x.k;
+      f.other = Other + l * nv * x.k;
+      f.fo = Fo + l * L * x.k;
+      f.ys = reinterpret_cast<float*>(w + lo.ys[i]) + l * nv * x.k;
+      f.n1 = (int)x.n1;
+      f.n2 = (int)x.n2;
+      f.kr = (int)kr;
+      f.kout = (int)x.k;
+      fin.push_back(f);
+    }
+  }
+  // the facewise products: one descriptor per product instance, one entry
+  // per 128 x 128 output tile, deepest products first (the longest tiles
+  // start first)
+  std::vector<pq::GemmDesc> descs;
+  std::vector<pq::GemmTile> tiles;
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!x.B) continue;
+    pq::GemmDesc d;
+    d.A = reinterpret_cast<const float*>(w + lo.ah[i]);
+    d.B = reinterpret_cast<const float*>(w + lo.bh[i]);
+    d.C = reinterpret_cast<float*>(w + lo.ch[i]);
+    d.M = (int)x.n1;
+    d.N = (int)x.n4;
+    d.K = (int)x.n2;
+    d.lda = x.n1;
+    d.sA = x.n1 * x.n2;
+    d.ldb = x.n2;
+    d.sB = x.n2 * x.n4;
+    d.ldc = x.n1;
+    d.sC = x.n1 * x.n4;
+    d.vec4 = pq::gemm_vec4_ok(d) ? 1 : 0;
+    const int id = (int)descs.size();
+    descs.push_back(d);
+    for (int z = 0; z < (int)x.p; ++z)
+      for (int ty = 0; ty < (d.N + 127) / 128; ++ty)
+        for (int tx = 0; tx < (d.M + 127) / 128; ++tx) tiles.push_back(pq::GemmTile{id, tx, ty, z});
+  }
+  std::stable_sort(tiles.begin(), tiles.end(),
+                   [&](const pq::GemmTile& a, const pq::GemmTile& b) { return descs[a.desc].K > descs[b.desc].K; });
   BQ_TRY(hipStreamSynchronize(stream));
   if (!tab.empty())
     BQ_TRY(hipMemcpy(w + lo.faces, tab.data(), sizeof(pq::JFace) * tab.size(), hipMemcpyHostToDevice));
+  if (!descs.empty())
+    BQ_TRY(hipMemcpy(w + lo.gdesc, descs.data(), sizeof(pq::GemmDesc) * descs.size(), hipMemcpyHostToDevice));
+  if (!tiles.empty())
+    BQ_TRY(hipMemcpy(w + lo.gtile, tiles.data(), sizeof(pq::GemmTile) * tiles.size(), hipMemcpyHostToDevice));
+  if (!fin.empty())
+    BQ_TRY(hipMemcpy(w + lo.fin, fin.data(), sizeof(pq::FinFace) * fin.size(), hipMemcpyHostToDevice));
   // one eager pass (valid outputs; tunes new launch shapes while tuning is on)
   BQ_CHECK(enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, stream));
   BQ_TRY(hipStreamSynchronize(stream));

@@ -521,24 +521,20 @@ __device__ __forceinline__ void block_operands(const float* S, int rb, int rl, i
   }
 }
 
+// One 128 x 128 output tile: C(m0.., n0..) = A(m0.., kbeg:kend) B(kbeg:kend,
+// n0..), A, B, C already offset to the batch entry.  bsm: the dynamic LDS
+// (4 tile_floats<128, KT>() floats).
 template <bool TA, bool TB, int VA, int VB, int KT>
-__global__ __launch_bounds__(256, 2) void gemm_f32_big_kernel(Gemm g, int kchunk, bool grouped) {
+__device__ __forceinline__ void big_tile_f32(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+                                             int64_t ldb, float* __restrict__ C, int64_t ldc, int M, int N, int m0,
+                                             int n0, int kbeg, int kend, float* bsm) {
   constexpr int H = KT / 2;
   constexpr int FA = tile_floats<kBig, KT>(), FB = FA;
-  extern __shared__ __align__(16) float bsm[];
   auto As = [&](int b) { return bsm + b * FA; };
   auto Bs = [&](int b) { return bsm + 2 * FA + b * FB; };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rl = lane & 31, h = lane >> 5;
   const int wm = wave & 1, wn = wave >> 1;
-  const TileIdx ti = tile_idx(grouped, (g.M + kBig - 1) / kBig, (g.N + kBig - 1) / kBig);
-  if (ti.z >= g.batch * max(1, g.ksplit)) return;  // the grouped grid's last slots
-  const int zb = ti.z % g.batch, zs = ti.z / g.batch;
-  const int m0 = ti.x * kBig, n0 = ti.y * kBig;
-  const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
-  const float* A = static_cast<const float*>(g.A) + (int64_t)zb * g.sA;
-  const float* B = static_cast<const float*>(g.B) + (int64_t)zb * g.sB;
-  float* C = static_cast<float*>(g.C) + (int64_t)zb * g.sC + (int64_t)zs * g.sSplit;
   f32x16 acc[2][2];  // [B block][A block]
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -549,8 +545,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_big_kernel(Gemm g, int kchunk
   TileRegs<kBig, KT> ra, rb;
   int k0 = kbeg;
   if (k0 < kend) {
-    tile_fetch<kBig, KT, VA, !TA>(A, g.lda, m0, g.M, k0, kend, ra);
-    tile_fetch<kBig, KT, VB, TB>(B, g.ldb, n0, g.N, k0, kend, rb);
+    tile_fetch<kBig, KT, VA, !TA>(A, lda, m0, M, k0, kend, ra);
+    tile_fetch<kBig, KT, VB, TB>(B, ldb, n0, N, k0, kend, rb);
     tile_store<kBig, KT, VA, !TA>(ra, As(0));
     tile_store<kBig, KT, VB, TB>(rb, Bs(0));
   }
@@ -559,8 +555,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_big_kernel(Gemm g, int kchunk
   for (; k0 < kend; k0 += KT) {
     const bool more = k0 + KT < kend;
     if (more) {
-      tile_fetch<kBig, KT, VA, !TA>(A, g.lda, m0, g.M, k0 + KT, kend, ra);
-      tile_fetch<kBig, KT, VB, TB>(B, g.ldb, n0, g.N, k0 + KT, kend, rb);
+      tile_fetch<kBig, KT, VA, !TA>(A, lda, m0, M, k0 + KT, kend, ra);
+      tile_fetch<kBig, KT, VB, TB>(B, ldb, n0, N, k0 + KT, kend, rb);
     }
     float a[2][H], b[2][H];
 #pragma unroll
@@ -587,15 +583,49 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_big_kernel(Gemm g, int kchunk
 #pragma unroll
   for (int bm = 0; bm < 2; ++bm) {
     const int gm = m0 + wm * 64 + 32 * bm + rl;
-    if (gm >= g.M) continue;
+    if (gm >= M) continue;
 #pragma unroll
     for (int bn = 0; bn < 2; ++bn)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int gn = n0 + wn * 64 + 32 * bn + 8 * (e >> 2) + 4 * h + (e & 3);
-        if (gn < g.N) C[gm + (int64_t)gn * g.ldc] = acc[bn][bm][e];
+        if (gn < N) C[gm + (int64_t)gn * ldc] = acc[bn][bm][e];
       }
   }
+}
+
+template <bool TA, bool TB, int VA, int VB, int KT>
+__global__ __launch_bounds__(256, 2) void gemm_f32_big_kernel(Gemm g, int kchunk, bool grouped) {
+  extern __shared__ __align__(16) float bsm[];
+  const TileIdx ti = tile_idx(grouped, (g.M + kBig - 1) / kBig, (g.N + kBig - 1) / kBig);
+  if (ti.z >= g.batch * max(1, g.ksplit)) return;  // the grouped grid's last slots
+  const int zb = ti.z % g.batch, zs = ti.z / g.batch;
+  const int kbeg = zs * kchunk, kend = min(g.K, kbeg + kchunk);
+  big_tile_f32<TA, TB, VA, VB, KT>(static_cast<const float*>(g.A) + (int64_t)zb * g.sA, g.lda,
+                                   static_cast<const float*>(g.B) + (int64_t)zb * g.sB, g.ldb,
+                                   static_cast<float*>(g.C) + (int64_t)zb * g.sC + (int64_t)zs * g.sSplit, g.ldc, g.M,
+                                   g.N, ti.x * kBig, ti.y * kBig, kbeg, kend, bsm);
+}
+
+// Many independent facewise products (of different shapes) in one launch:
+// workgroup w computes tile tiles[w] (a 128 x 128 output tile of one face of
+// one product, the tiles ordered by the host, deepest K first).  Products
+// whose operands allow 16-byte loads take them, the others scalar loads.
+template <int KT>
+__global__ __launch_bounds__(256, 2) void gemm_f32_grouped_kernel(const GemmDesc* __restrict__ descs,
+                                                                 const GemmTile* __restrict__ tiles) {
+  extern __shared__ __align__(16) float bsm[];
+  const GemmTile t = tiles[blockIdx.x];
+  const GemmDesc d = descs[t.desc];
+  const float* A = d.A + (int64_t)t.z * d.sA;
+  const float* B = d.B + (int64_t)t.z * d.sB;
+  float* C = d.C + (int64_t)t.z * d.sC;
+  if (d.vec4)
+    big_tile_f32<false, false, 4, 4, KT>(A, d.lda, B, d.ldb, C, d.ldc, d.M, d.N, t.tx * kBig, t.ty * kBig, 0, d.K,
+                                         bsm);
+  else
+    big_tile_f32<false, false, 1, 1, KT>(A, d.lda, B, d.ldb, C, d.ldc, d.M, d.N, t.tx * kBig, t.ty * kBig, 0, d.K,
+                                         bsm);
 }
 
 // The split-bfloat16 form of the 128 x 128 kernel: the tiles are fetched as
@@ -996,6 +1026,21 @@ hipError_t gemm_f64_go(const Gemm& g, int kchunk, hipStream_t s) {
     gemm_f64_kernel<TA, TB, 64><<<grid, 256, 0, s>>>(g, kchunk, grouped);
   }
   return hipGetLastError();
+}
+
+hipError_t gemm_f32_grouped(const GemmDesc* descs, const GemmTile* tiles, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  constexpr int KT = 32;
+  const size_t lds = sizeof(float) * 4 * tile_floats<kBig, KT>();
+  static hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_f32_grouped_kernel<KT>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  gemm_f32_grouped_kernel<KT><<<(unsigned)ntiles, 256, lds, s>>>(descs, tiles);
+  return hipGetLastError();
+}
+
+bool gemm_vec4_ok(const GemmDesc& d) {
+  return vec4_ok(d.A, d.M, d.lda, d.sA) && vec4_ok(d.B, d.K, d.ldb, d.sB);
 }
 
 hipError_t gemm_f64(const Gemm& g, hipStream_t s) {

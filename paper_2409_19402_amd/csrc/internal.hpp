@@ -81,6 +81,23 @@ struct Gemm {
   int ksplit; int64_t sSplit;
 };
 hipError_t gemm_f32(const Gemm& g, Prec prec, hipStream_t s);
+// Many float32 products C_z = A_z B_z (no transposes, column-major) of
+// different shapes in one launch: descs (device) one per product, tiles
+// (device) one per 128 x 128 output tile {product, tile row, tile column,
+// batch entry}, in the order the host wants them started.
+struct GemmDesc {
+  const float* A;
+  const float* B;
+  float* C;
+  int M, N, K;
+  int64_t lda, sA, ldb, sB, ldc, sC;
+  int vec4;  // operands allow 16-byte loads (gemm_vec4_ok)
+};
+struct GemmTile {
+  int desc, tx, ty, z;
+};
+bool gemm_vec4_ok(const GemmDesc& d);
+hipError_t gemm_f32_grouped(const GemmDesc* descs, const GemmTile* tiles, int ntiles, hipStream_t s);
 hipError_t gemm_f64(const Gemm& g, hipStream_t s);
 // out[e] = sum_{z < nparts} parts[z * stride + e] for e < count, fixed order
 hipError_t sum_partials_f32(const float* parts, int nparts, int64_t stride,
@@ -186,6 +203,27 @@ hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int ko
 // between the k-th and the (k + 1)-th.
 constexpr int kRitzExtra = 8;
 inline int ritz_cols(int64_t k, int64_t nv) { return (int)(k + kRitzExtra < nv ? k + kRitzExtra : nv); }
+// The finishing steps of the truncation (norms, the top kr normalised vectors
+// F, Y = Ah^T F or Ah F, the Ritz step keeping kout) for many faces of
+// different shapes, one launch each: every face described by a FinFace in a
+// device table.
+struct FinFace {
+  const double* w;  // Jacobi vectors: nv x L, vector-major (nv = min(n1, n2), L = max)
+  const float* ah;  // the transform-domain face: n1 x n2, column-major
+  double* sig;      // nv norms (scratch)
+  double* ft;       // kr columns of L (scratch)
+  double* y;        // kr columns of nv (scratch)
+  float* s;         // kout singular values
+  float* other;     // kout columns of nv: Y / s (the side of Y)
+  float* fo;        // kout columns of L: F (the side of the Jacobi vectors)
+  float* ys;        // kout columns of nv: Y (scratch for A_k)
+  int n1, n2, kr, kout;
+};
+// maxima over the table's faces: n1, n2, nv = min(n1, n2), nvL = n1 + n2, kr
+struct FinMax {
+  int n1 = 1, n2 = 1, nv = 1, nvL = 2, kr = 1;
+};
+hipError_t jacobi_finish_grouped(const FinFace* tab, int nfaces, const FinMax& m, double tol, hipStream_t s);
 // y[i] = x[i] for i < n (float32 -> float64)
 hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s);
 // the same per face (faces: the table of the grouped form, or null for p =
