@@ -1,14 +1,17 @@
 // The batched form: many independent instances of uneven sizes (A_i *_Q_i B_i
 // and the truncated tSVDQ of A_i, Def. 3.1 and Alg. 4.1) in one captured
-// graph.  The transforms, facewise products and back-projections of each
-// instance are launched per instance (each with the autotuner's choice for
-// its shape); the Jacobi sweeps, which dominate, run as grouped launches over
-// the faces of every instance at once (a device table of face offsets and
-// sizes); the per-face finishing steps run per instance again.  The plan call
-// runs the whole batch once eagerly (the outputs of that run are valid; new
-// launch shapes are tuned there while tuning is on), then captures the same
-// launch sequence on a private stream into a hipGraph; pq_batched_run replays
-// it with one hipGraphLaunch.
+// graph.  The transforms and back-projections of each instance are launched
+// per instance (each with the autotuner's choice for its shape); the
+// facewise products of all instances run as one grouped GEMM launch over a
+// table of 128 x 128 output tiles; the Jacobi sweeps, which dominate, run as
+// grouped launches over the faces of every instance at once (a device table
+// of face offsets and sizes, and per-round lists of the block-pair visits
+// that exist, so that a launch has no workgroup for a face without a visit
+// in that round); the finishing steps run as grouped launches over a table
+// of every face's operands.  The plan call runs the whole batch once eagerly
+// (the outputs of that run are valid; new launch shapes are tuned there
+// while tuning is on), then captures the same launch sequence on a private
+// stream into a hipGraph; pq_batched_run replays it with one hipGraphLaunch.
 #include <algorithm>
 #include <cstdint>
 #include <new>
@@ -68,6 +71,12 @@ struct Layout {
   pq::FinMax fmax;
   int ntop = 2;  // leading blocks of the top-block polish (0: every pair)
   int64_t welems = 0;
+  std::vector<pq::JFace> tab;  // host copy of the face table
+  // per-round visit lists of the float32 sweeps (every pair) and of the
+  // float64 polish (top-block schedule), host copies and device offsets
+  std::vector<int> v32, off32, v64, off64;
+  size_t dv32 = 0, dv64 = 0;
+  bool listed = false;
 };
 
 int validate(const pq_instance* inst, int count) {
@@ -140,6 +149,19 @@ Layout layout(const pq_instance* inst, int count) {
     }
   }
   lo.faces = take(sizeof(pq::JFace) * std::max(1, lo.nfaces));
+  // the face table: every face of every tSVDQ instance, in order, and the
+  // sweeps' visit lists over it
+  lo.tab.reserve(lo.nfaces);
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!has_svd(x)) continue;
+    const int nv = (int)std::min(x.n1, x.n2), L = (int)std::max(x.n1, x.n2);
+    for (int64_t l = 0; l < x.p; ++l) lo.tab.push_back(pq::JFace{lo.woff[i] + l * nv * L, nv, L});
+  }
+  lo.listed = pq::jacobi_visit_list(lo.tab.data(), lo.nfaces, 0, lo.v32, lo.off32) &&
+              pq::jacobi_visit_list(lo.tab.data(), lo.nfaces, lo.ntop, lo.v64, lo.off64);
+  lo.dv32 = take(sizeof(int) * std::max<size_t>(1, lo.v32.size()));
+  lo.dv64 = take(sizeof(int) * std::max<size_t>(1, lo.v64.size()));
   for (int i = 0; i < count; ++i) lo.ah[i] = take(4 * (size_t)inst[i].n1 * inst[i].n2 * inst[i].p);
   lo.bh.assign(count, 0);
   lo.ch.assign(count, 0);
@@ -206,8 +228,10 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
     BQ_TRY(pq::jacobi_prep_f32(reinterpret_cast<const float*>(ws + lo.ah[i]), W32 + lo.woff[i], (int)x.n1,
                                (int)x.n2, (int)x.p, s));
   }
+  const pq::VisitList vl32{reinterpret_cast<const int*>(ws + lo.dv32), lo.off32.data()};
+  const pq::VisitList vl64{reinterpret_cast<const int*>(ws + lo.dv64), lo.off64.data()};
   BQ_TRY(pq::jacobi_gram_grouped_f32(W32, faces, lo.nfaces, lo.nb_max, lo.L_max, max_sweeps, kCoarseTol, true, used1,
-                                     flags, s));
+                                     flags, lo.listed ? &vl32 : nullptr, s));
   if (lo.ntop > 0)
     BQ_TRY(pq::jacobi_widen_top(W32, W64, faces, lo.nfaces, 0, 0, lo.nv_max, 16 * lo.ntop,
                                 reinterpret_cast<double*>(ws + lo.tnrm), reinterpret_cast<int*>(ws + lo.tpos), s));
@@ -215,7 +239,7 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
     BQ_TRY(pq::jacobi_widen(W32, W64, lo.welems, s));
   const int polish = std::min(max_sweeps, kPolishSweeps);
   BQ_TRY(pq::jacobi_gram_grouped_f64(W64, faces, lo.nfaces, lo.nb_max, lo.L_max, polish, std::max(tol, kTolFloor),
-                                     true, lo.ntop, used2, flags, s));
+                                     true, lo.ntop, used2, flags, lo.listed ? &vl64 : nullptr, s));
   // finishing of every face at once: the top kr vectors, the other factor
   // and the Ritz step (one launch each over the face table)
   BQ_TRY(pq::jacobi_finish_grouped(reinterpret_cast<const pq::FinFace*>(ws + lo.fin), lo.nfaces, lo.fmax, tol, s));
@@ -245,15 +269,6 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
   const Layout lo = layout(inst, count);
   if (ws_bytes < lo.total) return PQ_ERR_WORKSPACE;
   char* w = static_cast<char*>(ws);
-  // the face table: every face of every tSVDQ instance, in order
-  std::vector<pq::JFace> tab;
-  tab.reserve(lo.nfaces);
-  for (int i = 0; i < count; ++i) {
-    const pq_instance& x = inst[i];
-    if (!has_svd(x)) continue;
-    const int nv = (int)std::min(x.n1, x.n2), L = (int)std::max(x.n1, x.n2);
-    for (int64_t l = 0; l < x.p; ++l) tab.push_back(pq::JFace{lo.woff[i] + l * nv * L, nv, L});
-  }
   // the finishing table: every face's operands and outputs
   std::vector<pq::FinFace> fin;
   fin.reserve(lo.nfaces);
@@ -315,8 +330,12 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
   std::stable_sort(tiles.begin(), tiles.end(),
                    [&](const pq::GemmTile& a, const pq::GemmTile& b) { return descs[a.desc].K > descs[b.desc].K; });
   BQ_TRY(hipStreamSynchronize(stream));
-  if (!tab.empty())
-    BQ_TRY(hipMemcpy(w + lo.faces, tab.data(), sizeof(pq::JFace) * tab.size(), hipMemcpyHostToDevice));
+  if (!lo.tab.empty())
+    BQ_TRY(hipMemcpy(w + lo.faces, lo.tab.data(), sizeof(pq::JFace) * lo.tab.size(), hipMemcpyHostToDevice));
+  if (lo.listed && !lo.v32.empty())
+    BQ_TRY(hipMemcpy(w + lo.dv32, lo.v32.data(), sizeof(int) * lo.v32.size(), hipMemcpyHostToDevice));
+  if (lo.listed && !lo.v64.empty())
+    BQ_TRY(hipMemcpy(w + lo.dv64, lo.v64.data(), sizeof(int) * lo.v64.size(), hipMemcpyHostToDevice));
   if (!descs.empty())
     BQ_TRY(hipMemcpy(w + lo.gdesc, descs.data(), sizeof(pq::GemmDesc) * descs.size(), hipMemcpyHostToDevice));
   if (!tiles.empty())

@@ -9,6 +9,7 @@
 
 #include <functional>
 #include <string>
+#include <vector>
 
 namespace pq {
 
@@ -151,13 +152,30 @@ struct JFace {
   int64_t off;
   int nv, L;
 };
+// Visits of a grouped sweep listed per round, so that a launch has one
+// workgroup per visit that exists (faces of fewer blocks have fewer rounds
+// and pairs): entry (f << kVisitShift) | slot names face f of the table and
+// its visit slot; round r's entries are dev[off[r] .. off[r + 1]) (off on
+// the host, one more value than rounds).  Built by jacobi_visit_list with the
+// same ntop as the launches that use it.
+constexpr int kVisitShift = 6;
+struct VisitList {
+  const int* dev = nullptr;
+  const int* off = nullptr;
+};
+// the visit list of the grouped sweeps over faces (host copy of the face
+// table); false when the table is too large to list
+bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int>& entries, std::vector<int>& off);
+// vl: the sweep's visit list (nullptr: every face at the largest face's
+// rounds and slots, idle workgroups exiting at once)
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, bool predict, int* used, int* flags, hipStream_t s);
+                                   int max_sweeps, double tol, bool predict, int* used, int* flags,
+                                   const VisitList* vl, hipStream_t s);
 // ntop (1 or 2; 0 = every pair): the top-block schedule, which visits only
 // the pairs with a vector in the first ntop 16-vector blocks of a face
 hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags,
-                                   hipStream_t s);
+                                   const VisitList* vl, hipStream_t s);
 // float64 sweeps in the Gram-matrix form (the polishing sweeps of float32
 // data); ntop as above
 hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, bool predict,

@@ -39,6 +39,7 @@
 // both factors orthonormal to working precision without changing Y F^T; its
 // column norms are the singular values.
 #include <algorithm>
+#include <climits>
 
 #include <type_traits>
 
@@ -476,7 +477,8 @@ __host__ __device__ __forceinline__ int top_rounds(int ntop, int nb) { return nb
 
 // visit `pair` of round `round`: blocks (I, J) and whether it runs the full
 // round robin; false when the slot is idle
-__device__ __forceinline__ bool top_pair(int ntop, int nb, int round, int pair, int& I, int& J, bool& full) {
+__host__ __device__ __forceinline__ bool top_pair(int ntop, int nb, int round, int pair, int& I, int& J,
+                                                    bool& full) {
   const int nbot = nb - ntop;
   if (pair >= ntop || round >= top_rounds(ntop, nb)) return false;
   if (round < nbot) {
@@ -496,7 +498,8 @@ template <typename T, int NB, bool ST, int NW>
 __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W, const JFace* __restrict__ faces,
                                                               int nfaces, int npair, int nv_u, int L_u, int round,
                                                               int sweep, int max_sweeps, double tol, float skip2,
-                                                              int ntop, int* __restrict__ flags) {
+                                                              int ntop, int* __restrict__ flags,
+                                                              const int* __restrict__ visits) {
   typedef GramMfma<T> M;
   typedef typename M::vec_t vec_t;
   constexpr int VEC = M::kVec;
@@ -518,9 +521,19 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
   // so that several visits share a CU
   T* X = reinterpret_cast<T*>(smem_raw + gram_head<R, NB>());
 
-  const int xcd = blockIdx.x % kXcds, m = blockIdx.x / kXcds;
-  const int f = xcd + kXcds * (m / npair), pair = m % npair;
-  if (f >= nfaces) return;
+  int f, pair;
+  if (visits) {
+    // listed visit: face index and slot
+    const int v = visits[blockIdx.x];
+    if (v < 0) return;
+    f = v >> kVisitShift;
+    pair = v & ((1 << kVisitShift) - 1);
+  } else {
+    const int xcd = blockIdx.x % kXcds, m = blockIdx.x / kXcds;
+    f = xcd + kXcds * (m / npair);
+    pair = m % npair;
+    if (f >= nfaces) return;
+  }
   const JFace fd = face_of(faces, f, nv_u, L_u);
   const int nv = fd.nv, L = fd.L;
   int nb = (nv + kGB - 1) / kGB;
@@ -1756,16 +1769,34 @@ inline void sweep_shape(int ntop, int nb_max, int& rounds, int& slots) {
 
 template <typename T, int NB, bool ST, int NW>
 void gram_launch_all(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max, int max_sweeps,
-                     double tol, float skip2, int ntop, int* flags, hipStream_t s) {
+                     double tol, float skip2, int ntop, int* flags, const VisitList* vl, hipStream_t s) {
   const size_t lds = gram_lds_bytes<T, NB, ST>(L_max);
   (void)gram_lds_cap<T, NB, ST, NW>();  // sets the kernel's LDS limit once
   int rounds, slots;
   sweep_shape(ntop, nb_max, rounds, slots);
   if (!top_schedule(ntop, nb_max)) ntop = 0;
   for (int sw = 0; sw < max_sweeps; ++sw)
-    for (int round = 0; round < rounds; ++round)
-      jacobi_gram_kernel<T, NB, ST, NW><<<(unsigned)gram_grid(nfaces, slots), 64 * NW, lds, s>>>(
-          W, faces, nfaces, slots, nv_u, L_u, round, sw, max_sweeps, tol, skip2, ntop, flags);
+    for (int round = 0; round < rounds; ++round) {
+      unsigned grid = (unsigned)gram_grid(nfaces, slots);
+      const int* visits = nullptr;
+      if (vl) {
+        grid = (unsigned)(vl->off[round + 1] - vl->off[round]);
+        visits = vl->dev + vl->off[round];
+        if (grid == 0) continue;
+      }
+      jacobi_gram_kernel<T, NB, ST, NW><<<grid, 64 * NW, lds, s>>>(W, faces, nfaces, slots, nv_u, L_u, round, sw,
+                                                                   max_sweeps, tol, skip2, ntop, flags, visits);
+    }
+}
+
+// launches of a sweep
+int sweep_launches(int ntop, int nb_max, const VisitList* vl) {
+  int rounds, slots;
+  sweep_shape(ntop, nb_max, rounds, slots);
+  if (!vl) return rounds;
+  int n = 0;
+  for (int r = 0; r < rounds; ++r) n += vl->off[r + 1] > vl->off[r];
+  return n;
 }
 
 // Stopping rule of the Gram-form sweeps.  A face stops after a sweep in
@@ -1781,7 +1812,8 @@ inline float sweep_skip2(double tol, bool predict) { return (float)(predict ? st
 
 template <typename T>
 hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max,
-                       int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags, hipStream_t s) {
+                       int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags, hipStream_t s,
+                       const VisitList* vl = nullptr) {
   const int nflags = nfaces * max_sweeps;
   {
     ProfScope prof("jacobi_flags", s);
@@ -1798,21 +1830,22 @@ hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, 
                             : gram_form<T>(L_max, gram_grid(nfaces, slots));
   const float skip2 = sweep_skip2(tol, predict);
   {
-    ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s, max_sweeps * rounds);
+    ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s,
+                   max_sweeps * sweep_launches(ntop, nb_max, vl));
     // staged visits get eight waves (two per SIMD hide each other's latency)
     if (form == GramForm::Stream) {
       gram_launch_all<T, 2, false, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop,
-                                       flags, s);
+                                       flags, vl, s);
     } else if constexpr (sizeof(T) == 4) {
       if (form == GramForm::Staged1)
         gram_launch_all<T, 1, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop,
-                                       flags, s);
+                                       flags, vl, s);
       else
         gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop,
-                                       flags, s);
+                                       flags, vl, s);
     } else {
       gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop, flags,
-                                     s);
+                                     vl, s);
     }
   }
   {
@@ -1946,14 +1979,52 @@ hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, do
   return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, prior, prior_max, s);
 }
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, bool predict, int* used, int* flags, hipStream_t s) {
-  return gram_sweeps<float>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, predict, 0, used, flags, s);
+                                   int max_sweeps, double tol, bool predict, int* used, int* flags,
+                                   const VisitList* vl, hipStream_t s) {
+  return gram_sweeps<float>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, predict, 0, used, flags, s, vl);
 }
 hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags,
-                                   hipStream_t s) {
+                                   const VisitList* vl, hipStream_t s) {
   return gram_sweeps<double>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, predict, ntop, used, flags,
-                             s);
+                             s, vl);
+}
+bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int>& entries, std::vector<int>& off) {
+  entries.clear();
+  off.assign(1, 0);
+  if (nfaces < 0 || nfaces > (INT_MAX >> kVisitShift)) return false;
+  auto blocks = [](int nv) {
+    const int nb = (nv + kGB - 1) / kGB;
+    return nb + (nb & 1);
+  };
+  int nb_max = 2;
+  for (int f = 0; f < nfaces; ++f) nb_max = std::max(nb_max, blocks(faces[f].nv));
+  int rounds, slots;
+  sweep_shape(ntop, nb_max, rounds, slots);
+  if (!top_schedule(ntop, nb_max)) ntop = 0;
+  if (slots > (1 << kVisitShift)) return false;
+  // longest vectors first within a round
+  std::vector<int> order((size_t)nfaces);
+  for (int f = 0; f < nfaces; ++f) order[(size_t)f] = f;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return faces[a].L > faces[b].L; });
+  for (int r = 0; r < rounds; ++r) {
+    for (const int f : order) {
+      const int nb = blocks(faces[f].nv);
+      for (int pair = 0; pair < slots; ++pair) {
+        bool valid;
+        if (top_schedule(ntop, nb)) {
+          int I, J;
+          bool full;
+          valid = top_pair(ntop, nb, r, pair, I, J, full);
+        } else {
+          valid = r < nb - 1 && pair < nb / 2;
+        }
+        if (valid) entries.push_back((f << kVisitShift) | pair);
+      }
+    }
+    off.push_back((int)entries.size());
+  }
+  return true;
 }
 hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, bool predict,
                                   int ntop, int* used, int* flags, hipStream_t s) {
