@@ -322,9 +322,12 @@ template <typename T, int NB>
 __host__ __device__ constexpr size_t gram_g_bytes() {
   return ((size_t)NB * kGMat * sizeof(T) + 15) & ~(size_t)15;
 }
+// (after the flag word: the rotations of the last two rounds, 2 x 16 pairs
+// of (c, s) in the angle type)
+constexpr size_t kRotBytes = 2 * 16 * 2 * sizeof(double);
 template <typename T, int NB>
 __host__ __device__ constexpr size_t gram_head() {
-  return gram_g_bytes<T, NB>() + sizeof(double) * kGMat + 16;
+  return gram_g_bytes<T, NB>() + sizeof(double) * kGMat + 16 + kRotBytes;
 }
 template <typename T, int NB>
 __host__ __device__ constexpr bool gram_partials_fit() {
@@ -492,6 +495,76 @@ __host__ __device__ __forceinline__ bool top_pair(int ntop, int nb, int round, i
   J = 1;
   full = true;
   return true;
+}
+
+// Rounds of the eight-wave visit with fixed addresses.  The 32 vectors of a
+// visit sit in slots 0..31 (block I in 0..15, block J in 16..31).  A round
+// rotates 16 fixed pairs of slots; afterwards every element moves to slot
+// sigma(slot), so that the same slot pairs hold new pairs of vectors in the
+// next round.  Intra rounds (the first 15 of a full visit) pair slots q and
+// 15 - q of each block, and sigma keeps slot 0 of a block and cycles its
+// slots 1..15 (the circle method on 16 vectors, in both blocks at once):
+// every pair inside a block once in 15 rounds.  Cross rounds pair slot i
+// with slot 16 + i, and sigma moves the J slots down by one: every (I, J)
+// pair once in 16 rounds.  Each phase returns every element to its own slot.
+// G is held as one 2 x 2 block ("quad") per pair of slot pairs (k, k2): the
+// entries (u_k, u_k2), (u_k, w_k2), (w_k, u_k2), (w_k, w_k2) of pair k's
+// slots u_k, w_k and pair k2's, so that a thread updates its quad from the
+// quad itself and the rotations of k and k2, and writes each entry to the
+// quad and position that hold it in the next round: addresses fixed for the
+// whole phase.
+struct GSlot {
+  int pair, side;  // slot pair holding the slot, and which of its two slots
+};
+__device__ __forceinline__ GSlot gslot(bool intra, int s) {
+  const int b = s >> 4, q = s & 15;
+  if (intra) return q < 8 ? GSlot{8 * b + q, 0} : GSlot{8 * b + 15 - q, 1};
+  return GSlot{q, b};
+}
+__device__ __forceinline__ int gslot_of(bool intra, int k, int side) {
+  if (intra) return 16 * (k >> 3) + (side ? 15 - (k & 7) : (k & 7));
+  return k + 16 * side;
+}
+__device__ __forceinline__ int gsigma(bool intra, int s) {
+  const int q = s & 15;
+  if (intra) return (s & 16) | (q == 0 ? 0 : q == 15 ? 1 : q + 1);
+  return s < 16 ? s : 16 + ((q - 1) & 15);
+}
+// element index of entry (slot a, slot b) in the quad array
+__device__ __forceinline__ int gquad_index(bool intra, int a, int b) {
+  const GSlot x = gslot(intra, a), y = gslot(intra, b);
+  return 4 * (16 * x.pair + y.pair) + 2 * x.side + y.side;
+}
+// vector (0..31) in slot u_k (side 0) or w_k (side 1) of pair k at round r
+// of a phase
+__device__ __forceinline__ int gslot_vector(bool intra, int k, int side, int r) {
+  if (intra) {
+    const int q = side ? 15 - (k & 7) : (k & 7);
+    int v = q;
+    if (q > 0) {
+      v = q - 1 - r + 15;  // 1 + ((q - 1 - r) mod 15), r < 15
+      if (v >= 15) v -= 15;
+      ++v;
+    }
+    return 16 * (k >> 3) + v;
+  }
+  return side ? 16 + ((k + r) & 15) : k;
+}
+template <typename R>
+__device__ __forceinline__ void load_quad(const R* p, R (&q)[4]) {
+  if constexpr (sizeof(R) == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    q[0] = v.x;
+    q[1] = v.y;
+    q[2] = v.z;
+    q[3] = v.w;
+  } else {
+    const double2 a = *reinterpret_cast<const double2*>(p), b = *reinterpret_cast<const double2*>(p + 2);
+    q[0] = a.x;
+    q[1] = a.y;
+    q[2] = b.x;
+    q[3] = b.y;
+  }
 }
 
 template <typename T, int NB, bool ST, int NW>
@@ -722,8 +795,14 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
         const int ti = q == 2 ? 1 : 0, tj = q == 0 ? 0 : 1;
         const int row = 16 * ti + M::row(ln >> 4, jj), col = 16 * tj + (ln & 15);
         if (ti != tj || row <= col) {
-          Gb[row * kGld + col] = gsum[i];
-          Gb[col * kGld + row] = gsum[i];
+          if constexpr (NW == 8) {
+            // the quads of the first round's slot pairs
+            Gb[gquad_index(full, row, col)] = gsum[i];
+            Gb[gquad_index(full, col, row)] = gsum[i];
+          } else {
+            Gb[row * kGld + col] = gsum[i];
+            Gb[col * kGld + row] = gsum[i];
+          }
         }
       }
     }
@@ -740,10 +819,16 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
   const double tol2 = tol * tol;
   {
     float mx = 0.f;
+    auto gat = [&](int a, int b) -> R {
+      if constexpr (NW == 8)
+        return Gb[gquad_index(full, a, b)];
+      else
+        return Gb[a * kGld + b];
+    };
     auto cos2 = [&](int i, int c) {
-      const double g = Gb[i * kGld + c];
+      const double g = gat(i, c);
       // the hardware reciprocal (about 1e-15 relative): the value only meets thresholds
-      const double r = g * g * __builtin_amdgcn_rcp((double)Gb[i * kGld + i] * (double)Gb[c * kGld + c]);
+      const double r = g * g * __builtin_amdgcn_rcp((double)gat(i, i) * (double)gat(c, c));
       return r > 0.0 ? (float)r : 0.f;  // NaN (0 / 0 included) never asks for a rotation
     };
     if (full) {
@@ -847,82 +932,105 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
     __syncthreads();
 
   } else {
-    // Eight waves: threads 2b and 2b + 1 share the 2x2 block b = (P, P2)
-    // of the four-wave form, one row of it each (h = 0: row of a1, h = 1:
-    // row of c1), and swap the row products J_P2 they need by DPP; each
-    // updates one of the block's two V rows (P2 + 16 h).
-    const int blk = tid >> 1, h = tid & 1;
-    const int P = blk >> 4, P2 = blk & 15;
-    const int srcl = (2 * 17 * P) & 63;  // a lane of this wave that holds block (P, P)
+    // Eight waves: waves 0-3 update G, one quad per thread (thread (k, k2),
+    // k = tid / 16, k2 = tid mod 16), with the fixed-address rounds described
+    // above; waves 4-7 update V, two rows of one slot pair's two columns per
+    // thread, applying each round's rotations during the next round (V keeps
+    // the vectors' own numbering: a thread maps its pair's slots to vectors).
+    // A G thread computes pair k2's rotation from quad (k2, k2) and takes
+    // pair k's from the lane that holds quad (k, k).  Per round and thread:
+    // two quad reads, the angle, sixteen multiply-adds and four writes.
     const R tol2r = (R)tol2;
-    const int vr = (P2 + 16 * h) * kGld;
-    int pa = 0, pc = 0;
-    double pvc = 1.0, pvs = 0.0;
-    auto apply_v = [&]() {
-      const double va_ = V[vr + pa], vc_ = V[vr + pc];
-      V[vr + pa] = pvc * va_ - pvs * vc_;
-      V[vr + pc] = pvs * va_ + pvc * vc_;
-    };
-    int cur = 0;
-    // one round; FULL: the first launch of a sweep (the round robin over all
-    // 32 vectors).  The float32 rounds run in two loops with FULL constant
-    // (straight-line code, measured faster); the float64 rounds in one loop
-    // (measured faster there)
-    auto do_round = [&](int r, bool FULL) {
-      const R* G = Gb + (NB == 2 ? cur : 0) * kGMat;
-      R* Gn = Gb + (NB == 2 ? cur ^ 1 : 0) * kGMat;
-      int a1, c1, a2, c2;
-      gram_pair(FULL, r, P, a1, c1);
-      gram_pair(FULL, r, P2, a2, c2);
-      // row offsets on the full-rate 24-bit multiplier
-      const int rx = __mul24(h ? c1 : a1, kGld);  // this thread's row of the block
-      const int ra2 = __mul24(a2, kGld), rc2 = __mul24(c2, kGld);
-      const R mx0 = G[rx + a2], mx1 = G[rx + c2];
-      const R al2 = G[ra2 + a2], be2 = G[rc2 + c2], ga2 = G[ra2 + c2];
-      if (r > 0) apply_v();
-      R c2r, s2r;
+    const bool gw = tid < 256;
+    const int k = (tid >> 4) & 15, k2 = tid & 15;
+    const int srcl = (17 * k) & 63;  // lane of this wave with quad (k, k)
+    R* rot = reinterpret_cast<R*>(reinterpret_cast<unsigned char*>(any_rot) + 16);
+    // where this thread's four entries go: after an intra round, after the
+    // last intra round (into the cross rounds' quads), after a cross round
+    int tgI[4], tgT[4], tgC[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int aI = gsigma(true, gslot_of(true, k, e >> 1)), bI = gsigma(true, gslot_of(true, k2, e & 1));
+      tgI[e] = gquad_index(true, aI, bI);
+      tgT[e] = gquad_index(false, aI, bI);
+      const int aC = gsigma(false, gslot_of(false, k, e >> 1)), bC = gsigma(false, gslot_of(false, k2, e & 1));
+      tgC[e] = gquad_index(false, aC, bC);
+    }
+    const int own4 = 4 * (16 * k + k2), diag4 = 4 * 17 * k2;
+    const int vt = tid - 256, vrow = (vt >> 4) * kGld, vp = vt & 15;
+    auto apply_v = [&](bool intra, int r, int buf) {
+      double c = (double)rot[buf * 32 + 2 * vp], sn = (double)rot[buf * 32 + 2 * vp + 1];
       if constexpr (F32) {
-        const float2 q2 = gram_rotation_f32(al2, be2, ga2, tol2r);
-        c2r = q2.x;
-        s2r = q2.y;
-      } else {
-        const double2 q2 = gram_rotation<2>(al2, be2, ga2, tol2);
-        c2r = q2.x;
-        s2r = q2.y;
+        // float32 angles renormalised in float64 (first order in
+        // c^2 + s^2 - 1, exact to 1e-14): V stays orthogonal to float64
+        // precision whatever the float32 arithmetic does
+        const double nf = fma(-0.5, fma(c, c, sn * sn), 1.5);
+        c *= nf;
+        sn *= nf;
       }
-      const R c1r = __shfl(c2r, srcl), s1r = __shfl(s2r, srcl);
-      const R tx0 = c2r * mx0 - s2r * mx1, tx1 = s2r * mx0 + c2r * mx1;  // this row times J_P2
-      const R ty0 = swap_pair(tx0), ty1 = swap_pair(tx1);                 // the other row's
-      const R sg = h ? s1r : -s1r;
-      const bool own = P == P2 && s1r != R(0);  // the rotation annihilates its own off-diagonal entry
-      const R gA = (own && h) ? R(0) : c1r * tx0 + sg * ty0;
-      const R gB = (own && !h) ? R(0) : c1r * tx1 + sg * ty1;
+      const int ca = gslot_vector(intra, vp, 0, r), cw = gslot_vector(intra, vp, 1, r);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int o = vrow + 16 * kGld * h;
+        const double va_ = V[o + ca], vw_ = V[o + cw];
+        V[o + ca] = c * va_ - sn * vw_;
+        V[o + cw] = sn * va_ + c * vw_;
+      }
+    };
+    int cur = 0, rr = 0;
+    // one round with write targets tg; the V waves apply round rr - 1 (of
+    // phase pv_intra, round pv_r within it; pv_r < 0: none)
+    auto do_round = [&](const int (&tg)[4], bool pv_intra, int pv_r) {
+      const R* G = Gb + (NB == 2 ? cur : 0) * 1024;
+      R* Gn = Gb + (NB == 2 ? cur ^ 1 : 0) * 1024;
+      R g[4], c2r = R(1), s2r = R(0);
+      if (gw) {
+        R m[4], d[4];
+        load_quad(G + own4, m);
+        load_quad(G + diag4, d);
+        if constexpr (F32) {
+          const float2 q2 = gram_rotation_f32(d[0], d[3], d[1], tol2r);
+          c2r = q2.x;
+          s2r = q2.y;
+        } else {
+          const double2 q2 = gram_rotation<2>(d[0], d[3], d[1], tol2);
+          c2r = q2.x;
+          s2r = q2.y;
+        }
+        const R c1r = __shfl(c2r, srcl), s1r = __shfl(s2r, srcl);
+        const R t00 = c2r * m[0] - s2r * m[1], t01 = s2r * m[0] + c2r * m[1];
+        const R t10 = c2r * m[2] - s2r * m[3], t11 = s2r * m[2] + c2r * m[3];
+        const bool own = k == k2 && s1r != R(0);  // the rotation annihilates its own off-diagonal entries
+        g[0] = c1r * t00 - s1r * t10;
+        g[1] = own ? R(0) : c1r * t01 - s1r * t11;
+        g[2] = own ? R(0) : s1r * t00 + c1r * t10;
+        g[3] = s1r * t01 + c1r * t11;
+      } else if (pv_r >= 0) {
+        apply_v(pv_intra, pv_r, (rr - 1) & 1);
+      }
       if constexpr (NB == 1) __syncthreads();  // every read of the round before any write
-      Gn[rx + a2] = gA;
-      Gn[rx + c2] = gB;
-      pa = a1;
-      pc = c1;
-      pvc = c1r;
-      pvs = s1r;
-      if constexpr (F32) {
-        const double nf = fma(-0.5, fma(pvc, pvc, pvs * pvs), 1.5);
-        pvc *= nf;
-        pvs *= nf;
+      if (gw) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Gn[tg[e]] = g[e];
+        if (tid < 16) {
+          rot[(rr & 1) * 32 + 2 * k2] = c2r;
+          rot[(rr & 1) * 32 + 2 * k2 + 1] = s2r;
+        }
       }
       cur ^= 1;
+      ++rr;
       __syncthreads();
     };
-    if constexpr (F32) {
-      if (full) {
-        for (int r = 0; r < kG2 - 1; ++r) do_round(r, true);
-      } else {
-        for (int r = 0; r < kGB; ++r) do_round(r, false);
-      }
+    if (full) {
+      do_round(tgI, true, -1);
+      for (int r = 1; r < kGB - 2; ++r) do_round(tgI, true, r - 1);
+      do_round(tgT, true, kGB - 3);
+      do_round(tgC, true, kGB - 2);
     } else {
-      const int nrounds = full ? kG2 - 1 : kGB;
-      for (int r = 0; r < nrounds; ++r) do_round(r, full);
+      do_round(tgC, false, -1);
     }
-    apply_v();
+    for (int r = 1; r < kGB; ++r) do_round(tgC, false, r - 1);
+    if (!gw) apply_v(false, kGB - 1, (rr - 1) & 1);
     __syncthreads();
   }
 
