@@ -100,7 +100,7 @@ constexpr int kDefaultSweeps64 = 30;
 // Jacobi thresholds on |a.c| / (|a||c|): the float32 phase stops at the coarse
 // one, the float64 phase polishes to the default final one.
 constexpr double kCoarseTol32 = 1e-5;
-constexpr int kPolishSweeps = 6;  // float64 phase from the coarse threshold: 2-4 sweeps (the last one rotates nothing)
+constexpr int kPolishSweeps = 6;  // float64 phase from the coarse threshold: 1-2 sweeps
 constexpr double kPolishTol = 1e-13;
 // The float64 sweeps of float32 data run on Gram matrices, whose rotation
 // angles come from G as updated within a visit: their stopping test is
@@ -611,16 +611,16 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
   if (!f64) {
     float* W32 = static_cast<float*>(parts);  // the slices are summed: their space is free
     PQ_TRY(pq::grad_narrow(G, W32, n3 * n3, stream));
-    PQ_TRY(pq::jacobi_sweeps_f32(W32, 1, in3, in3, kDefaultSweeps32, kCoarseTol32, false, used, flags, stream));
+    PQ_TRY(pq::jacobi_sweeps_f32(W32, 1, in3, in3, kDefaultSweeps32, kCoarseTol32, 0.0, used, flags, stream));
     {
       PQ_PROF("jacobi_widen", stream);
       PQ_TRY(pq::jacobi_widen(W32, W, n3 * n3, stream));
     }
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kPolishSweeps, kGramTolFloor, false, 0, used + 1, flags,
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kPolishSweeps, kGramTolFloor, 0.0, 0, used + 1, flags,
                                       stream));
   } else {
     PQ_TRY(hipMemcpyAsync(W, G, 8 * (size_t)n3 * n3, hipMemcpyDeviceToDevice, stream));
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kGramSweeps64, kPolishTol, false, 0, used, flags, stream));
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(W, 1, in3, in3, kGramSweeps64, kPolishTol, 0.0, 0, used, flags, stream));
     PQ_TRY(pq::jacobi_sweeps_f64(W, 1, in3, in3, kPolishSweeps, kPolishTol, used + 1, flags, used, kGramSweeps64,
                                  stream));
   }
@@ -717,7 +717,8 @@ int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
       PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(b.Ah), b.W32, in1, in2, ip, stream));
     }
     // float32 sweeps down to a coarse threshold (each launch profiled inside)
-    PQ_TRY(pq::jacobi_sweeps_f32(b.W32, ip, nv, L, max_sweeps, kCoarseTol32, true, b.used1, b.flags, stream));
+    PQ_TRY(pq::jacobi_sweeps_f32(b.W32, ip, nv, L, max_sweeps, kCoarseTol32, kCoarseTol32, b.used1, b.flags,
+                                 stream));
     PQ_PROF("jacobi_widen", stream);
     if (ntop > 0)
       PQ_TRY(pq::jacobi_widen_top(b.W32, b.W64, nullptr, ip, nv, L, nv, 16 * ntop, top_nrm, top_pos, stream));
@@ -732,11 +733,15 @@ int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   const int max1 = f64 ? std::min(max_sweeps, kGramSweeps64) : max_sweeps;
   const int max2 = std::min(max_sweeps, kPolishSweeps);
   if (f64) {
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max1, tol, false, 0, b.used1, b.flags, stream));
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max1, tol, 0.0, 0, b.used1, b.flags, stream));
     PQ_TRY(pq::jacobi_sweeps_f64(b.W64, ip, nv, L, max2, tol, b.used2, b.flags, b.used1, max1, stream));
   } else {
-    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max2, std::max(tol, kGramTolFloor), true, ntop, b.used2,
-                                      b.flags, stream));
+    // rotations down to max(tol, 1e-10); the top-block polish ahead of the
+    // Ritz step stops at kPolishStop32, a polish of every pair (the SVDII
+    // selection ranks the column norms themselves) at that same floor
+    const double ptol = std::max(tol, kGramTolFloor);
+    PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max2, ptol, ntop > 0 ? pq::kPolishStop32 : ptol, ntop,
+                                      b.used2, b.flags, stream));
   }
   if (info_dev) PQ_TRY(pq::jacobi_info(b.used1, b.used2, ip, max1, max2, info_dev, stream));
   return PQ_OK;

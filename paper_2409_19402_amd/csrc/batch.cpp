@@ -230,7 +230,7 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
   }
   const pq::VisitList vl32{reinterpret_cast<const int*>(ws + lo.dv32), lo.off32.data()};
   const pq::VisitList vl64{reinterpret_cast<const int*>(ws + lo.dv64), lo.off64.data()};
-  BQ_TRY(pq::jacobi_gram_grouped_f32(W32, faces, lo.nfaces, lo.nb_max, lo.L_max, max_sweeps, kCoarseTol, true, used1,
+  BQ_TRY(pq::jacobi_gram_grouped_f32(W32, faces, lo.nfaces, lo.nb_max, lo.L_max, max_sweeps, kCoarseTol, kCoarseTol, used1,
                                      flags, lo.listed ? &vl32 : nullptr, s));
   if (lo.ntop > 0)
     BQ_TRY(pq::jacobi_widen_top(W32, W64, faces, lo.nfaces, 0, 0, lo.nv_max, 16 * lo.ntop,
@@ -238,8 +238,10 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
   else
     BQ_TRY(pq::jacobi_widen(W32, W64, lo.welems, s));
   const int polish = std::min(max_sweeps, kPolishSweeps);
-  BQ_TRY(pq::jacobi_gram_grouped_f64(W64, faces, lo.nfaces, lo.nb_max, lo.L_max, polish, std::max(tol, kTolFloor),
-                                     true, lo.ntop, used2, flags, lo.listed ? &vl64 : nullptr, s));
+  const double ptol = std::max(tol, kTolFloor);
+  BQ_TRY(pq::jacobi_gram_grouped_f64(W64, faces, lo.nfaces, lo.nb_max, lo.L_max, polish, ptol,
+                                     lo.ntop > 0 ? pq::kPolishStop32 : ptol, lo.ntop, used2, flags,
+                                     lo.listed ? &vl64 : nullptr, s));
   // finishing of every face at once: the top kr vectors, the other factor
   // and the Ritz step (one launch each over the face table)
   BQ_TRY(pq::jacobi_finish_grouped(reinterpret_cast<const pq::FinFace*>(ws + lo.fin), lo.nfaces, lo.fmax, tol, s));

@@ -138,10 +138,10 @@ hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, h
 // Orthogonalises the nv vectors of every face; sweeps_used[l] gets the sweep
 // count of face l, or max_sweeps + 1 when it stopped without converging.
 // flags: p * max_sweeps ints of scratch.  A face stops after a sweep that
-// rotated nothing or, with predict set, after a sweep whose largest cosine c
-// had c^2 <= tol (near convergence a sweep squares c, so the sweep itself
-// brought the face to about tol).
-hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, bool predict,
+// rotated nothing or, with stop2 > 0, after a sweep whose largest cosine c
+// had c^2 <= stop2 (near convergence a sweep squares c, so the sweep itself
+// brought the face to about stop2); pairs rotate down to tol either way.
+hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, double stop2,
                              int* sweeps_used, int* flags, hipStream_t s);
 // Grouped Jacobi over faces of different sizes (the batched form): faces[f]
 // (device) gives face f's element offset in W, its vector count and length.
@@ -169,16 +169,16 @@ bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int
 // vl: the sweep's visit list (nullptr: every face at the largest face's
 // rounds and slots, idle workgroups exiting at once)
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, bool predict, int* used, int* flags,
+                                   int max_sweeps, double tol, double stop2, int* used, int* flags,
                                    const VisitList* vl, hipStream_t s);
 // ntop (1 or 2; 0 = every pair): the top-block schedule, which visits only
 // the pairs with a vector in the first ntop 16-vector blocks of a face
 hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags,
+                                   int max_sweeps, double tol, double stop2, int ntop, int* used, int* flags,
                                    const VisitList* vl, hipStream_t s);
 // float64 sweeps in the Gram-matrix form (the polishing sweeps of float32
 // data); ntop as above
-hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, bool predict,
+hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, double stop2,
                                   int ntop, int* used, int* flags, hipStream_t s);
 // prior (may be null): a face with prior[f] <= prior_max converged in an
 // earlier phase and is left alone (sweeps_used[f] = 0)
@@ -220,6 +220,14 @@ hipError_t jacobi_refine_f64(double* Y, double* F, int m1, int m2, int k, int ko
 // k-th and the (k + kRitzExtra + 1)-th singular value, instead of the gap
 // between the k-th and the (k + 1)-th.
 constexpr int kRitzExtra = 8;
+// Prediction threshold of the float64 top-block polish of float32 data (c^2
+// of the largest cosine before rotation, with the rotations themselves going
+// down to 1e-10): a face stops after the sweep that started from
+// c^2 <= 1e-5, which leaves its leading vectors at cosines of about 1e-5
+// against all others.  The Rayleigh-Ritz step that follows is accurate to
+// second order in those cosines; measured, the sweeps that would continue
+// (one more on most faces) change no A_k by more than rounding.
+constexpr double kPolishStop32 = 1e-5;
 inline int ritz_cols(int64_t k, int64_t nv) { return (int)(k + kRitzExtra < nv ? k + kRitzExtra : nv); }
 // The finishing steps of the truncation (norms, the top kr normalised vectors
 // F, Y = Ah^T F or Ah F, the Ritz step keeping kout) for many faces of

@@ -1909,18 +1909,20 @@ int sweep_launches(int ntop, int nb_max, const VisitList* vl) {
 
 // Stopping rule of the Gram-form sweeps.  A face stops after a sweep in
 // which no pair needed a rotation (largest squared cosine <= tol^2 on its
-// flag word).  With predict set it also stops after a sweep whose largest
-// cosine c before rotation had c^2 <= tol: near convergence a cyclic Jacobi
-// sweep squares the largest cosine (the quadratic convergence of the cyclic
-// method), so that sweep itself left the face at about tol, and the sweep
-// that would only confirm it is not run.  The float32 data's phases predict
-// (their result is settled by the float64 Ritz step on the transform-domain
-// face); float64 data and the U3 eigenvectors confirm.
-inline float sweep_skip2(double tol, bool predict) { return (float)(predict ? std::max(tol * tol, tol) : tol * tol); }
+// flag word).  With a prediction threshold stop2 > 0 it also stops after a
+// sweep whose largest cosine c before rotation had c^2 <= stop2: near
+// convergence a cyclic Jacobi sweep squares the largest cosine (the
+// quadratic convergence of the cyclic method), so that sweep itself left the
+// face at cosines of about stop2, and the sweeps that would only take it
+// further are not run.  Pairs are still rotated down to tol within the
+// sweeps that do run.  The float32 data's phases predict (their result is
+// settled by the float64 Ritz step on the transform-domain face); float64
+// data and the U3 eigenvectors confirm (stop2 = 0).
+inline float sweep_skip2(double tol, double stop2) { return (float)(stop2 > 0.0 ? std::max(tol * tol, stop2) : tol * tol); }
 
 template <typename T>
 hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max,
-                       int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags, hipStream_t s,
+                       int max_sweeps, double tol, double stop2, int ntop, int* used, int* flags, hipStream_t s,
                        const VisitList* vl = nullptr) {
   const int nflags = nfaces * max_sweeps;
   {
@@ -1936,7 +1938,7 @@ hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, 
                          gram_lds_bytes<T, 2, true>(L_max) <= gram_lds_cap<T, 2, true>())
                             ? GramForm::Staged2
                             : gram_form<T>(L_max, gram_grid(nfaces, slots));
-  const float skip2 = sweep_skip2(tol, predict);
+  const float skip2 = sweep_skip2(tol, stop2);
   {
     ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s,
                    max_sweeps * sweep_launches(ntop, nb_max, vl));
@@ -1964,11 +1966,11 @@ hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, 
 }
 
 template <typename T>
-hipError_t gram_sweeps_uniform(T* W, int p, int nv, int L, int max_sweeps, double tol, bool predict, int ntop,
+hipError_t gram_sweeps_uniform(T* W, int p, int nv, int L, int max_sweeps, double tol, double stop2, int ntop,
                                int* used, int* flags, hipStream_t s) {
   int nb = (nv + kGB - 1) / kGB;
   nb += nb & 1;
-  return gram_sweeps<T>(W, nullptr, p, nv, L, nb, L, max_sweeps, tol, predict, ntop, used, flags, s);
+  return gram_sweeps<T>(W, nullptr, p, nv, L, nb, L, max_sweeps, tol, stop2, ntop, used, flags, s);
 }
 
 // waves per workgroup (4 vectors of a block each): blocks of 16 vectors, fewer
@@ -2078,23 +2080,23 @@ hipError_t jacobi_prep_f32(const float* Ah, float* W, int n1, int n2, int p, hip
 hipError_t jacobi_prep_f64(const double* Ah, double* W, int n1, int n2, int p, hipStream_t s) {
   return prep<double>(Ah, W, n1, n2, p, s);
 }
-hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, bool predict, int* used,
+hipError_t jacobi_sweeps_f32(float* W, int p, int nv, int L, int max_sweeps, double tol, double stop2, int* used,
                              int* flags, hipStream_t s) {
-  return gram_sweeps_uniform<float>(W, p, nv, L, max_sweeps, tol, predict, 0, used, flags, s);
+  return gram_sweeps_uniform<float>(W, p, nv, L, max_sweeps, tol, stop2, 0, used, flags, s);
 }
 hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, int* used,
                              int* flags, const int* prior, int prior_max, hipStream_t s) {
   return sweeps<double>(W, p, nv, L, max_sweeps, tol, used, flags, prior, prior_max, s);
 }
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, bool predict, int* used, int* flags,
+                                   int max_sweeps, double tol, double stop2, int* used, int* flags,
                                    const VisitList* vl, hipStream_t s) {
-  return gram_sweeps<float>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, predict, 0, used, flags, s, vl);
+  return gram_sweeps<float>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, stop2, 0, used, flags, s, vl);
 }
 hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
-                                   int max_sweeps, double tol, bool predict, int ntop, int* used, int* flags,
+                                   int max_sweeps, double tol, double stop2, int ntop, int* used, int* flags,
                                    const VisitList* vl, hipStream_t s) {
-  return gram_sweeps<double>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, predict, ntop, used, flags,
+  return gram_sweeps<double>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, stop2, ntop, used, flags,
                              s, vl);
 }
 bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int>& entries, std::vector<int>& off) {
@@ -2134,9 +2136,9 @@ bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int
   }
   return true;
 }
-hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, bool predict,
+hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, double stop2,
                                   int ntop, int* used, int* flags, hipStream_t s) {
-  return gram_sweeps_uniform<double>(W, p, nv, L, max_sweeps, tol, predict, ntop, used, flags, s);
+  return gram_sweeps_uniform<double>(W, p, nv, L, max_sweeps, tol, stop2, ntop, used, flags, s);
 }
 hipError_t jacobi_norms_f64(const double* W, int p, int nv, int L, double* sig, int* rank, hipStream_t s) {
   norms_kernel<double><<<dim3((unsigned)((nv + 3) / 4), (unsigned)p), 256, 0, s>>>(W, nv, L, sig, rank);
