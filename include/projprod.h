@@ -364,7 +364,10 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
  * on |a_i . a_j| / (|a_i| |a_j|) of the final (float64) sweeps (<= 0 selects
  * 1e-13; two singular vectors come out coupled by about tol / (2 x the
  * relative gap of their singular values); for F32 and BF16 data the final
- * sweeps work on Gram matrices of the vectors and use max(tol, 1e-10)),
+ * sweeps work on Gram matrices of the vectors, rotate down to
+ * max(tol, 1e-10) and, ahead of the Rayleigh-Ritz step on the leading
+ * k + 8 vectors, stop once a sweep started from squared cosines of at most
+ * 1e-5, which it squares),
  * max_sweeps caps the sweeps of each phase (<= 0: 10 for float32 data,
  * whose float64 phase takes at most 6; 30 for float64 data, whose Gram
  * phase takes at most 16 and whose vector phase at most 6; at most 100).  info_dev (device int[3], may be NULL)
@@ -483,9 +486,10 @@ int pq_batched_workspace(const pq_instance* inst, int count, size_t* bytes);
  * is in force, launch shapes not yet in the autotuner's table are tuned
  * here), then captures the same launch sequence into a hipGraph on a private
  * stream and instantiates it.  Synchronises `stream`; allocates host memory
- * for the handle only.  The transforms, facewise products and
- * back-projections run per instance; the Jacobi sweeps of all tSVDQ
- * instances run as grouped launches over every face at once.  max_sweeps
+ * for the handle only.  The transforms and back-projections run per
+ * instance; the facewise products of all instances run as one grouped
+ * launch, and the Jacobi sweeps and finishing steps of all tSVDQ instances
+ * as grouped launches over every face at once.  max_sweeps
  * (<= 0: 10) and tol (<= 0: 1e-13) as in pq_tsvdq; info_dev (device int[3],
  * may be NULL) receives the sweep statistics over all faces, as in pq_tsvdq.
  * Every pointer of inst[] and ws is baked into the graph: they must stay
