@@ -717,8 +717,8 @@ int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
       PQ_TRY(pq::jacobi_prep_f32(static_cast<const float*>(b.Ah), b.W32, in1, in2, ip, stream));
     }
     // float32 sweeps down to a coarse threshold (each launch profiled inside)
-    PQ_TRY(pq::jacobi_sweeps_f32(b.W32, ip, nv, L, max_sweeps, kCoarseTol32, kCoarseTol32, b.used1, b.flags,
-                                 stream));
+    PQ_TRY(pq::jacobi_sweeps_f32(b.W32, ip, nv, L, max_sweeps, kCoarseTol32,
+                                 ntop > 0 ? pq::kCoarseStop32 : kCoarseTol32, b.used1, b.flags, stream));
     PQ_PROF("jacobi_widen", stream);
     if (ntop > 0)
       PQ_TRY(pq::jacobi_widen_top(b.W32, b.W64, nullptr, ip, nv, L, nv, 16 * ntop, top_nrm, top_pos, stream));

@@ -230,7 +230,8 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
   }
   const pq::VisitList vl32{reinterpret_cast<const int*>(ws + lo.dv32), lo.off32.data()};
   const pq::VisitList vl64{reinterpret_cast<const int*>(ws + lo.dv64), lo.off64.data()};
-  BQ_TRY(pq::jacobi_gram_grouped_f32(W32, faces, lo.nfaces, lo.nb_max, lo.L_max, max_sweeps, kCoarseTol, kCoarseTol, used1,
+  BQ_TRY(pq::jacobi_gram_grouped_f32(W32, faces, lo.nfaces, lo.nb_max, lo.L_max, max_sweeps, kCoarseTol,
+                                     lo.ntop > 0 ? pq::kCoarseStop32 : kCoarseTol, used1,
                                      flags, lo.listed ? &vl32 : nullptr, s));
   if (lo.ntop > 0)
     BQ_TRY(pq::jacobi_widen_top(W32, W64, faces, lo.nfaces, 0, 0, lo.nv_max, 16 * lo.ntop,

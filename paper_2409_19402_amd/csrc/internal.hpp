@@ -228,6 +228,13 @@ constexpr int kRitzExtra = 8;
 // second order in those cosines; measured, the sweeps that would continue
 // (one more on most faces) change no A_k by more than rounding.
 constexpr double kPolishStop32 = 1e-5;
+// Prediction threshold of the float32 sweeps ahead of that polish (their
+// rotations still go down to 1e-5): the leading vectors by norm must hold
+// the Ritz step's columns when the polish takes over.  Measured on the
+// batched test instances: 1e-4 and 3e-4 change no result; 1e-3 moved one
+// instance whose Ritz columns (15) nearly fill its single leading block by
+// 2.5e-5, so the threshold keeps a factor of ten from there.
+constexpr double kCoarseStop32 = 1e-4;
 inline int ritz_cols(int64_t k, int64_t nv) { return (int)(k + kRitzExtra < nv ? k + kRitzExtra : nv); }
 // The finishing steps of the truncation (norms, the top kr normalised vectors
 // F, Y = Ah^T F or Ah F, the Ritz step keeping kout) for many faces of
