@@ -486,10 +486,11 @@ int pq_batched_workspace(const pq_instance* inst, int count, size_t* bytes);
  * is in force, launch shapes not yet in the autotuner's table are tuned
  * here), then captures the same launch sequence into a hipGraph on a private
  * stream and instantiates it.  Synchronises `stream`; allocates host memory
- * for the handle only.  The transforms and back-projections run per
- * instance; the facewise products of all instances run as one grouped
- * launch, and the Jacobi sweeps and finishing steps of all tSVDQ instances
- * as grouped launches over every face at once.  max_sweeps
+ * for the handle only.  The transforms, the facewise products and the
+ * back-projections of all instances run as grouped launches (one per
+ * vector width for the transforms; back-projections of more than 32 faces
+ * per instance), and the Jacobi sweeps and finishing steps of all tSVDQ
+ * instances as grouped launches over every face at once.  max_sweeps
  * (<= 0: 10) and tol (<= 0: 1e-13) as in pq_tsvdq; info_dev (device int[3],
  * may be NULL) receives the sweep statistics over all faces, as in pq_tsvdq.
  * Every pointer of inst[] and ws is baked into the graph: they must stay

@@ -1,7 +1,7 @@
 // The batched form: many independent instances of uneven sizes (A_i *_Q_i B_i
 // and the truncated tSVDQ of A_i, Def. 3.1 and Alg. 4.1) in one captured
-// graph.  The transforms and back-projections of each instance are launched
-// per instance (each with the autotuner's choice for its shape); the
+// graph.  The transforms and back-projections of all instances run as
+// grouped launches over tables of strips (one per vector width); the
 // facewise products of all instances run as one grouped GEMM launch over a
 // table of 128 x 128 output tiles; the Jacobi sweeps, which dominate, run as
 // grouped launches over the faces of every instance at once (a device table
@@ -59,6 +59,11 @@ struct Layout {
   std::vector<size_t> bh, ch;  // per product instance: Bh (n2 x n4 x p), Ch (n1 x n4 x p)
   size_t gdesc = 0, gtile = 0;  // grouped facewise GEMM: product and tile tables
   int nprod = 0, ntiles = 0;
+  // grouped transforms: descriptors (forward ones first), forward and return
+  // tile tables (sized for one tube per lane, the most tiles)
+  size_t xdesc = 0, htile = 0, utile = 0;
+  int nxdesc = 0;
+  int64_t hmax = 0, umax = 0;
   std::vector<int64_t> woff;   // per instance: element offset of its faces in W32 / W64
   std::vector<int> face0;      // per instance: index of its first face
   size_t w32 = 0, w64 = 0, used1 = 0, used2 = 0, flags = 0;
@@ -171,6 +176,23 @@ Layout layout(const pq_instance* inst, int count) {
     lo.bh[i] = take(4 * (size_t)x.n2 * x.n4 * x.p);
     lo.ch[i] = take(4 * (size_t)x.n1 * x.n4 * x.p);
   }
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    const int chunks = (int)((x.p + 31) / 32);
+    lo.hmax += (x.n1 * x.n2 + 31) / 32 * chunks;
+    ++lo.nxdesc;
+    if (x.B) {
+      lo.hmax += (x.n2 * x.n4 + 31) / 32 * chunks;
+      ++lo.nxdesc;
+      if (x.p <= 32) {
+        lo.umax += ((x.n1 * x.n4 + 31) / 32 + 3) / 4;
+        ++lo.nxdesc;
+      }
+    }
+  }
+  lo.xdesc = take(sizeof(pq::XformDesc) * (size_t)lo.nxdesc);
+  lo.htile = take(sizeof(pq::XformTile) * (size_t)std::max<int64_t>(1, lo.hmax));
+  lo.utile = take(sizeof(pq::XformTile) * (size_t)std::max<int64_t>(1, lo.umax));
   lo.gdesc = take(sizeof(pq::GemmDesc) * (size_t)std::max(1, lo.nprod));
   lo.gtile = take(sizeof(pq::GemmTile) * (size_t)std::max(1, lo.ntiles));
   lo.w32 = take(4 * (size_t)std::max<int64_t>(lo.welems, 1));
@@ -196,29 +218,46 @@ Layout layout(const pq_instance* inst, int count) {
 }
 
 // Enqueue every launch of the batch on s.
+// host side of the grouped transforms: tiles of the forward and return
+// transforms by vector width (index 0: two tubes per lane, 1: one)
+struct XformPlan {
+  int nh[3] = {0, 0, 0}, nu[3] = {0, 0, 0};  // by tubes per lane: 4, 2, 1
+};
+
 int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps, double tol, int* info_dev,
-            char* ws, hipStream_t s) {
+            char* ws, const XformPlan& xp, hipStream_t s) {
   float* W32 = reinterpret_cast<float*>(ws + lo.w32);
   double* W64 = reinterpret_cast<double*>(ws + lo.w64);
   int* used1 = reinterpret_cast<int*>(ws + lo.used1);
   int* used2 = reinterpret_cast<int*>(ws + lo.used2);
   int* flags = reinterpret_cast<int*>(ws + lo.flags);
   const pq::JFace* faces = reinterpret_cast<const pq::JFace*>(ws + lo.faces);
-  // transforms of every instance, the facewise products of all of them in
-  // one launch, the back-projections
-  for (int i = 0; i < count; ++i) {
-    const pq_instance& x = inst[i];
-    BQ_CHECK(pq_hat(x.A, PQ_F32, x.Q, ws + lo.ah[i], x.n1, x.n2, x.n3, x.p, PQ_PREC_DEFAULT, s));
-    if (x.B) BQ_CHECK(pq_hat(x.B, PQ_F32, x.Q, ws + lo.bh[i], x.n2, x.n4, x.n3, x.p, PQ_PREC_DEFAULT, s));
+  // the transforms of every instance, the facewise products and the
+  // back-projections, one launch each (per vector width)
+  const pq::XformDesc* xd = reinterpret_cast<const pq::XformDesc*>(ws + lo.xdesc);
+  const pq::XformTile* ht = reinterpret_cast<const pq::XformTile*>(ws + lo.htile);
+  const pq::XformTile* ut = reinterpret_cast<const pq::XformTile*>(ws + lo.utile);
+  {
+    pq::ProfScope prof("hat", s, (xp.nh[0] > 0) + (xp.nh[1] > 0) + (xp.nh[2] > 0));
+    BQ_TRY(pq::hat_grouped(xd, ht, xp.nh[0], 4, s));
+    BQ_TRY(pq::hat_grouped(xd, ht + xp.nh[0], xp.nh[1], 2, s));
+    BQ_TRY(pq::hat_grouped(xd, ht + xp.nh[0] + xp.nh[1], xp.nh[2], 1, s));
   }
   if (lo.ntiles > 0) {
     pq::ProfScope prof("facewise_gemm", s);
     BQ_TRY(pq::gemm_f32_grouped(reinterpret_cast<const pq::GemmDesc*>(ws + lo.gdesc),
                                 reinterpret_cast<const pq::GemmTile*>(ws + lo.gtile), lo.ntiles, s));
   }
-  for (int i = 0; i < count; ++i) {
+  {
+    pq::ProfScope prof("unhat", s, (xp.nu[0] > 0) + (xp.nu[1] > 0) + (xp.nu[2] > 0));
+    BQ_TRY(pq::unhat_grouped(xd, ut, xp.nu[0], 4, s));
+    BQ_TRY(pq::unhat_grouped(xd, ut + xp.nu[0], xp.nu[1], 2, s));
+    BQ_TRY(pq::unhat_grouped(xd, ut + xp.nu[0] + xp.nu[1], xp.nu[2], 1, s));
+  }
+  for (int i = 0; i < count; ++i) {  // products of more than 32 faces
     const pq_instance& x = inst[i];
-    if (x.B) BQ_CHECK(pq_unhat(ws + lo.ch[i], x.Q, x.C, PQ_F32, x.n1, x.n4, x.n3, x.p, PQ_PREC_DEFAULT, s));
+    if (x.B && x.p > 32)
+      BQ_CHECK(pq_unhat(ws + lo.ch[i], x.Q, x.C, PQ_F32, x.n1, x.n4, x.n3, x.p, PQ_PREC_DEFAULT, s));
   }
   if (lo.nfaces == 0) return PQ_OK;
   // Jacobi vectors of every face, then the grouped sweeps
@@ -332,6 +371,46 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
   }
   std::stable_sort(tiles.begin(), tiles.end(),
                    [&](const pq::GemmTile& a, const pq::GemmTile& b) { return descs[a.desc].K > descs[b.desc].K; });
+  // the transforms: forward ones of every A and B, return ones of every C;
+  // tiles grouped by vector width, longest tubes (most slices) first
+  std::vector<pq::XformDesc> xds;
+  std::vector<pq::XformTile> hts[3], uts[3];
+  auto add_hat = [&](const void* in, void* out, int64_t N, const pq_instance& x) {
+    const pq::XformDesc d{static_cast<const float*>(in), static_cast<const float*>(x.Q), static_cast<float*>(out), N,
+                          (int)x.n3, (int)x.p};
+    const int hv = pq::xform_group_vec(d);
+    pq::hat_group_tiles(d, (int)xds.size(), hts[hv == 4 ? 0 : hv == 2 ? 1 : 2]);
+    xds.push_back(d);
+  };
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    add_hat(x.A, w + lo.ah[i], x.n1 * x.n2, x);
+    if (x.B) add_hat(x.B, w + lo.bh[i], x.n2 * x.n4, x);
+  }
+  for (int i = 0; i < count; ++i) {
+    const pq_instance& x = inst[i];
+    if (!x.B || x.p > 32) continue;
+    const pq::XformDesc d{reinterpret_cast<const float*>(w + lo.ch[i]), static_cast<const float*>(x.Q),
+                          static_cast<float*>(x.C), x.n1 * x.n4, (int)x.n3, (int)x.p};
+    const int uv = pq::unhat_group_vec(d);
+    pq::unhat_group_tiles(d, (int)xds.size(), uts[uv == 4 ? 0 : uv == 2 ? 1 : 2]);
+    xds.push_back(d);
+  }
+  XformPlan xp;
+  std::vector<pq::XformTile> htab, utab;
+  auto by_n3 = [&](const pq::XformTile& a, const pq::XformTile& b) { return xds[a.desc].n3 > xds[b.desc].n3; };
+  for (int v = 0; v < 3; ++v) {
+    std::stable_sort(hts[v].begin(), hts[v].end(), by_n3);
+    xp.nh[v] = (int)hts[v].size();
+    htab.insert(htab.end(), hts[v].begin(), hts[v].end());
+  }
+  for (int v = 0; v < 3; ++v) {
+    std::stable_sort(uts[v].begin(), uts[v].end(), by_n3);
+    xp.nu[v] = (int)uts[v].size();
+    utab.insert(utab.end(), uts[v].begin(), uts[v].end());
+  }
+  if ((int64_t)htab.size() > lo.hmax || (int64_t)utab.size() > lo.umax || (int)xds.size() > lo.nxdesc)
+    return PQ_ERR_ARG;  // cannot happen: the layout counts the most tiles
   BQ_TRY(hipStreamSynchronize(stream));
   if (!lo.tab.empty())
     BQ_TRY(hipMemcpy(w + lo.faces, lo.tab.data(), sizeof(pq::JFace) * lo.tab.size(), hipMemcpyHostToDevice));
@@ -345,8 +424,14 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
     BQ_TRY(hipMemcpy(w + lo.gtile, tiles.data(), sizeof(pq::GemmTile) * tiles.size(), hipMemcpyHostToDevice));
   if (!fin.empty())
     BQ_TRY(hipMemcpy(w + lo.fin, fin.data(), sizeof(pq::FinFace) * fin.size(), hipMemcpyHostToDevice));
+  if (!xds.empty())
+    BQ_TRY(hipMemcpy(w + lo.xdesc, xds.data(), sizeof(pq::XformDesc) * xds.size(), hipMemcpyHostToDevice));
+  if (!htab.empty())
+    BQ_TRY(hipMemcpy(w + lo.htile, htab.data(), sizeof(pq::XformTile) * htab.size(), hipMemcpyHostToDevice));
+  if (!utab.empty())
+    BQ_TRY(hipMemcpy(w + lo.utile, utab.data(), sizeof(pq::XformTile) * utab.size(), hipMemcpyHostToDevice));
   // one eager pass (valid outputs; tunes new launch shapes while tuning is on)
-  BQ_CHECK(enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, stream));
+  BQ_CHECK(enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, xp, stream));
   BQ_TRY(hipStreamSynchronize(stream));
   // capture the same launches on a private stream
   hipStream_t cs = nullptr;
@@ -358,7 +443,7 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
   }
   int rc = hip_rc(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   if (rc == PQ_OK) {
-    const int erc = enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, cs);
+    const int erc = enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, xp, cs);
     hipGraph_t g = nullptr;
     const int crc = hip_rc(hipStreamEndCapture(cs, &g));
     rc = erc != PQ_OK ? erc : crc;

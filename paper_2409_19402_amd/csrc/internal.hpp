@@ -152,6 +152,33 @@ struct JFace {
   int64_t off;
   int nv, L;
 };
+// Many float32 mode-3 transforms in one launch each (the batched form): a
+// descriptor per tensor (in: A for the forward transform, Chat for the
+// return one; Q; out; N = n1 n2 tubes; n3; p) and one entry per workgroup
+// (x: strip of 32 vec tubes for the forward transform, group of four such
+// strips for the return one; y: 32-row chunk of p for the forward
+// transform; 0 for the return one, whose workgroups write every output
+// tile of their strips).  The return transform
+// keeps a strip's p <= 32 rows in registers: larger p is not grouped.
+struct XformDesc {
+  const float* in;
+  const float* Q;
+  float* out;
+  int64_t N;
+  int n3, p;
+};
+struct XformTile {
+  int64_t x;
+  int desc, y;
+};
+// tubes per lane for a tensor: 4, 2 or 1, the widest accesses (16, 8 or 4
+// bytes) that N and both pointers allow (the tiles of one launch share it)
+int xform_group_vec(const XformDesc& d);
+int unhat_group_vec(const XformDesc& d);
+void hat_group_tiles(const XformDesc& d, int desc, std::vector<XformTile>& tiles);
+void unhat_group_tiles(const XformDesc& d, int desc, std::vector<XformTile>& tiles);
+hipError_t hat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, hipStream_t s);
+hipError_t unhat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, hipStream_t s);
 // Visits of a grouped sweep listed per round, so that a launch has one
 // workgroup per visit that exists (faces of fewer blocks have fewer rounds
 // and pairs): entry (f << kVisitShift) | slot names face f of the table and

@@ -218,15 +218,15 @@ __device__ __forceinline__ void strip_mma(int n3, int p, int l, bool active, int
   }
 }
 
-// MW: minimum waves per SIMD the register allocation must allow (occupancy)
-template <int VEC, int S, int U, int MW, typename TIn>
-__global__ __launch_bounds__(S * 64, MW) void hat_strip_kernel(const TIn* __restrict__ A, const float* __restrict__ Q,
-                                                               float* __restrict__ Ah, int64_t N, int n3, int p) {
-  extern __shared__ float red[];  // (S - 1) * VEC * 16 * 64
+// One workgroup's strip `strip` of tubes and 32-row chunk `lc` of the
+// transform (red: (S - 1) * VEC * 16 * 64 floats of LDS)
+template <int VEC, int S, int U, typename TIn>
+__device__ __forceinline__ void hat_strip_body(const TIn* __restrict__ A, const float* __restrict__ Q,
+                                               float* __restrict__ Ah, int64_t N, int n3, int p, int64_t strip,
+                                               int lc, float* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 31, kh = lane >> 5;
-  const int lc = blockIdx.y * 32;
-  const int64_t xl = (int64_t)blockIdx.x * (32 * VEC) + (int64_t)VEC * n;
+  const int64_t xl = strip * (32 * VEC) + (int64_t)VEC * n;
   const bool active = xl < N;
   const int64_t xs = active ? xl : N - VEC;  // a valid tube for address arithmetic
   const int l = lc + n;                      // this lane's column of Q (row of the MFMA's A operand)
@@ -268,6 +268,25 @@ __global__ __launch_bounds__(S * 64, MW) void hat_strip_kernel(const TIn* __rest
       }
     }
   }
+}
+
+// MW: minimum waves per SIMD the register allocation must allow (occupancy)
+template <int VEC, int S, int U, int MW, typename TIn>
+__global__ __launch_bounds__(S * 64, MW) void hat_strip_kernel(const TIn* __restrict__ A, const float* __restrict__ Q,
+                                                               float* __restrict__ Ah, int64_t N, int n3, int p) {
+  extern __shared__ float red[];  // (S - 1) * VEC * 16 * 64
+  hat_strip_body<VEC, S, U, TIn>(A, Q, Ah, N, n3, p, blockIdx.x, blockIdx.y * 32, red);
+}
+
+// Many forward transforms of float32 tensors in one launch (the batched
+// form): workgroup w takes tile tiles[w] (descriptor, strip, 32-row chunk).
+template <int VEC, int S, int U, int MW>
+__global__ __launch_bounds__(S * 64, MW) void hat_grouped_kernel(const XformDesc* __restrict__ descs,
+                                                                 const XformTile* __restrict__ tiles) {
+  extern __shared__ float red[];
+  const XformTile t = tiles[blockIdx.x];
+  const XformDesc d = descs[t.desc];
+  hat_strip_body<VEC, S, U, float>(d.in, d.Q, d.out, d.N, d.n3, d.p, t.x, 32 * t.y, red);
 }
 
 template <int VEC, int WAVES>
@@ -583,13 +602,14 @@ __global__ __launch_bounds__(S * 64) void hat_bf16_kernel(const TIn* __restrict_
 // float32: v_mfma_f32_32x32x2f32 over pairs of channels; split-bfloat16:
 // v_mfma_f32_32x32x16_bf16 over 16 channels at a time, both operands split
 // into parts (Split<NA, NQ>: Chat parts x Q parts).
-template <int VEC, int W, int MW>
-__global__ __launch_bounds__(W * 64, MW) void unhat_strip_kernel(const float* __restrict__ Ah,
-                                                                 const float* __restrict__ Q,
-                                                                 float* __restrict__ C, int64_t N, int n3, int p) {
+// (workgroup bx of the strips; output tiles y0, y0 + ystep, ...)
+template <int VEC, int W>
+__device__ __forceinline__ void unhat_strip_body(const float* __restrict__ Ah, const float* __restrict__ Q,
+                                                 float* __restrict__ C, int64_t N, int n3, int p, int64_t bx,
+                                                 int y0, int ystep) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 31, kh = lane >> 5;
-  const int64_t xl = ((int64_t)blockIdx.x * W + wave) * (32 * VEC) + (int64_t)VEC * n;
+  const int64_t xl = (bx * W + wave) * (32 * VEC) + (int64_t)VEC * n;
   const bool active = xl < N;
   const int64_t xs = active ? xl : N - VEC;
   const int ntiles = (n3 + 31) >> 5;
@@ -607,10 +627,10 @@ __global__ __launch_bounds__(W * 64, MW) void unhat_strip_kernel(const float* __
     for (int s = 0; s < 16; ++s) a[s] = Q[(int64_t)t * p + min(2 * s + kh, p - 1)];
   };
   float a0[16], a1[16];
-  int tile = blockIdx.y;
+  int tile = y0;
   qload(min(tile, ntiles - 1), a0);
   while (tile < ntiles) {
-    const int nxt = tile + gridDim.y;
+    const int nxt = tile + ystep;
     qload(min(nxt, ntiles - 1), a1);
     __builtin_amdgcn_sched_barrier(0);
     f32x16 acc[VEC];
@@ -645,6 +665,24 @@ __global__ __launch_bounds__(W * 64, MW) void unhat_strip_kernel(const float* __
     tile = nxt;
   }
 }
+
+template <int VEC, int W, int MW>
+__global__ __launch_bounds__(W * 64, MW) void unhat_strip_kernel(const float* __restrict__ Ah,
+                                                                 const float* __restrict__ Q,
+                                                                 float* __restrict__ C, int64_t N, int n3, int p) {
+  unhat_strip_body<VEC, W>(Ah, Q, C, N, n3, p, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
+// Many return transforms in one launch (the batched form): workgroup w takes
+// tile tiles[w] (descriptor, workgroup of strips, every output tile).
+template <int VEC, int W, int MW>
+__global__ __launch_bounds__(W * 64, MW) void unhat_grouped_kernel(const XformDesc* __restrict__ descs,
+                                                                   const XformTile* __restrict__ tiles) {
+  const XformTile t = tiles[blockIdx.x];
+  const XformDesc d = descs[t.desc];
+  unhat_strip_body<VEC, W>(d.in, d.Q, d.out, d.N, d.n3, d.p, t.x, t.y, 1);
+}
+
 
 template <int VEC, int W, int MW, int NA, int NQ>
 __global__ __launch_bounds__(W * 64, MW) void unhat_bstrip_kernel(const float* __restrict__ Ah,
@@ -1223,6 +1261,47 @@ hipError_t unhat_f32_any(const float* Ah, const float* Q, float* C, int64_t N, i
 }
 
 }  // namespace
+
+int xform_group_vec(const XformDesc& d) { return pick_vec(d.N, {d.in, d.out}, 4); }
+int unhat_group_vec(const XformDesc& d) { return pick_vec(d.N, {d.in, d.out}, 4); }
+
+void hat_group_tiles(const XformDesc& d, int desc, std::vector<XformTile>& tiles) {
+  const int vec = xform_group_vec(d);
+  const int64_t strips = (d.N + 32 * vec - 1) / (32 * vec);
+  for (int y = 0; y < (d.p + 31) / 32; ++y)
+    for (int64_t x = 0; x < strips; ++x) tiles.push_back(XformTile{x, desc, y});
+}
+
+void unhat_group_tiles(const XformDesc& d, int desc, std::vector<XformTile>& tiles) {
+  const int vec = unhat_group_vec(d);
+  const int64_t strips = (d.N + 32 * vec - 1) / (32 * vec);
+  for (int64_t x = 0; x < (strips + 3) / 4; ++x) tiles.push_back(XformTile{x, desc, 0});
+}
+
+// the strip kernels' shapes that the autotuner picks most often for single
+// transforms: four waves splitting the slices of a strip four pairs per
+// batch (forward), four waves with a strip each (return)
+hipError_t hat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (vec == 4)
+    hat_grouped_kernel<4, 4, 2, 4><<<(unsigned)ntiles, 256, red_bytes(4, 4), s>>>(d, t);
+  else if (vec == 2)
+    hat_grouped_kernel<2, 4, 4, 4><<<(unsigned)ntiles, 256, red_bytes(2, 4), s>>>(d, t);
+  else
+    hat_grouped_kernel<1, 4, 4, 4><<<(unsigned)ntiles, 256, red_bytes(1, 4), s>>>(d, t);
+  return hipGetLastError();
+}
+
+hipError_t unhat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (vec == 4)
+    unhat_grouped_kernel<4, 4, 2><<<(unsigned)ntiles, 256, 0, s>>>(d, t);
+  else if (vec == 2)
+    unhat_grouped_kernel<2, 4, 4><<<(unsigned)ntiles, 256, 0, s>>>(d, t);
+  else
+    unhat_grouped_kernel<1, 4, 4><<<(unsigned)ntiles, 256, 0, s>>>(d, t);
+  return hipGetLastError();
+}
 
 hipError_t hat_f32(const void* A, bool a_bf16, const float* Q, float* Ah, int64_t N, int n3, int p,
                    Prec prec, hipStream_t s) {
