@@ -369,9 +369,10 @@ int pq_u3(const void* A, int a_dtype, int64_t n1, int64_t n2, int64_t n3, int64_
  * k + 8 vectors, stop once a sweep started from squared cosines of at most
  * 1e-5, which it squares),
  * max_sweeps caps the sweeps of each phase (<= 0: 10 for float32 data,
- * whose float64 phase takes at most 6; 30 for float64 data, whose Gram
- * phase takes at most 16 and whose vector phase at most 6; at most 100).  info_dev (device int[3], may be NULL)
- * receives [0] = the largest number of sweeps any face used (both phases),
+ * whose float64 phase takes at most 4 ahead of the Rayleigh-Ritz step; 30
+ * for float64 data, whose Gram phase takes at most 16 and whose vector
+ * phase at most 6; at most 100).  info_dev (device int[3], may be NULL)
+ * receives [0] = the largest number of sweeps any face used (all phases),
  * [1] = the number of faces whose last phase hit max_sweeps before
  * converging (their outputs are still written) and [2] = the sweeps summed
  * over the faces.  Workspace: pq_tsvdq_workspace bytes.

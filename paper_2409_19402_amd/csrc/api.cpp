@@ -100,7 +100,10 @@ constexpr int kDefaultSweeps64 = 30;
 // Jacobi thresholds on |a.c| / (|a||c|): the float32 phase stops at the coarse
 // one, the float64 phase polishes to the default final one.
 constexpr double kCoarseTol32 = 1e-5;
-constexpr int kPolishSweeps = 6;  // float64 phase from the coarse threshold: 1-2 sweeps
+constexpr int kPolishSweeps = 6;  // float64 phase from the coarse threshold
+// the top-block polish ahead of the Ritz step of a plain truncation (1-2
+// sweeps from the float32 stop, the rest margin)
+constexpr int kTopPolishSweeps = 4;
 constexpr double kPolishTol = 1e-13;
 // The float64 sweeps of float32 data run on Gram matrices, whose rotation
 // angles come from G as updated within a visit: their stopping test is
@@ -731,7 +734,7 @@ int converge(const void* A, int a_dtype, const void* Q, int64_t n1, int64_t n2, 
   // tol for the faces the Gram form left unconverged; float32 data:
   // Gram-form float64 sweeps to max(tol, 1e-10)
   const int max1 = f64 ? std::min(max_sweeps, kGramSweeps64) : max_sweeps;
-  const int max2 = std::min(max_sweeps, kPolishSweeps);
+  const int max2 = std::min(max_sweeps, (!f64 && ntop > 0) ? kTopPolishSweeps : kPolishSweeps);
   if (f64) {
     PQ_TRY(pq::jacobi_gram_sweeps_f64(b.W64, ip, nv, L, max1, tol, 0.0, 0, b.used1, b.flags, stream));
     PQ_TRY(pq::jacobi_sweeps_f64(b.W64, ip, nv, L, max2, tol, b.used2, b.flags, b.used1, max1, stream));

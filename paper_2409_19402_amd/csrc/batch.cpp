@@ -33,6 +33,7 @@ constexpr int kMaxSweepsCap = 100;
 constexpr int kDefaultSweeps = 10;
 constexpr double kCoarseTol = 1e-5;
 constexpr int kPolishSweeps = 6;
+constexpr int kTopPolishSweeps = 4;  // the top-block polish: 1-2 sweeps from the float32 stop
 constexpr double kTolFloor = 1e-10;
 constexpr double kDefaultTol = 1e-13;
 constexpr int64_t kMaxLen = 512;  // longest Jacobi vector of a batched tSVDQ face
@@ -277,7 +278,7 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
                                 reinterpret_cast<double*>(ws + lo.tnrm), reinterpret_cast<int*>(ws + lo.tpos), s));
   else
     BQ_TRY(pq::jacobi_widen(W32, W64, lo.welems, s));
-  const int polish = std::min(max_sweeps, kPolishSweeps);
+  const int polish = std::min(max_sweeps, lo.ntop > 0 ? kTopPolishSweeps : kPolishSweeps);
   const double ptol = std::max(tol, kTolFloor);
   BQ_TRY(pq::jacobi_gram_grouped_f64(W64, faces, lo.nfaces, lo.nb_max, lo.L_max, polish, ptol,
                                      lo.ntop > 0 ? pq::kPolishStop32 : ptol, lo.ntop, used2, flags,
