@@ -148,10 +148,10 @@ hipError_t do_hat(const void* A, int a_dtype, const void* Q, void* Ah, int64_t N
 }
 
 // Precision of the back-projection inside a composite call: the split x3
-// mode runs it as x6.  The return transform is bound by its writes, so the
-// extra part products cost nothing, and they keep the error of the whole
-// chain (transform, facewise step, back-projection) well inside the float32
-// tolerance.
+// mode runs it as x6, which keeps the error of the whole chain (transform,
+// facewise step, back-projection) well inside the float32 tolerance.  The
+// return transform is bound by its float32 writes: in the split modes the
+// autotuner also times its float32 kernels and keeps the faster.
 Prec back_prec(Prec p) { return p == Prec::BF16x3 ? Prec::BF16x6 : p; }
 
 hipError_t do_unhat(const void* Ah, const void* Q, void* A, int dtype, int64_t N, int n3, int p,

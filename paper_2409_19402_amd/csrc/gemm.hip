@@ -956,12 +956,18 @@ template <bool TA, bool TB>
 hipError_t gemm_launch(const Gemm& g, Prec prec, int kchunk, hipStream_t s) {
   if (big_tiles(g)) {
     // autotuned: 128 x 128 tiles with K-tiles of 32 (the default) or 16
-    // (less LDS, more workgroups per CU), or the 64 x 64 kernel
+    // (less LDS, more workgroups per CU), or the 64 x 64 kernel; the
+    // compensated modes also time the same three in float32, which are at
+    // least as accurate (and faster where few tiles leave the product bound
+    // by latency rather than by matrix-core rate)
     char key[160];
     std::snprintf(key, sizeof key, "gemm:%d:%d%d:%dx%dx%dx%d", (int)prec, (int)TA, (int)TB, g.M, g.N, g.K, g.batch);
-    return tuned_launch(key, 3, 0, s, [&](int c) -> hipError_t {
-      if (c == 2) return gemm_small_launch<TA, TB>(g, prec, kchunk, s);
-      switch (prec) {
+    const bool comp = prec == Prec::BF16x3 || prec == Prec::BF16x6;
+    return tuned_launch(key, comp ? 6 : 3, 0, s, [&](int c) -> hipError_t {
+      const Prec pc = c >= 3 ? Prec::Default : prec;
+      c %= 3;
+      if (c == 2) return gemm_small_launch<TA, TB>(g, pc, kchunk, s);
+      switch (pc) {
         case Prec::BF16:
           return c ? gemm_big_launch<TA, TB, 16, 1>(g, kchunk, s) : gemm_big_launch<TA, TB, 32, 1>(g, kchunk, s);
         case Prec::BF16x3:

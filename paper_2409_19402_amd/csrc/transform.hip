@@ -985,6 +985,7 @@ int pick_vec(int64_t N, std::initializer_list<const void*> ptrs, int elem) {
 struct Cfg {
   int vec, waves, spw;
   int strip = 0;  // > 0: hat_strip_kernel, `spw` slice pairs per load batch, `strip` min waves per SIMD
+  bool f32 = false;  // a split-bfloat16 mode's candidate that runs the float32 kernel
 };
 
 std::vector<Cfg> cands(int vmax, bool splitk) {
@@ -1365,18 +1366,26 @@ hipError_t unhat_f32(const float* Ah, const float* Q, float* C, int64_t N, int n
   std::vector<Cfg> c;
   if (p <= 32) unhat_strip_cands(vmax, c);
   const int nstrip = (int)c.size();
-  if (prec == Prec::Default)
+  // the compensated modes also time the float32 kernels (strip and
+  // LDS-staged): the return transform is bound by its float32 writes, and
+  // float32 products are at least as accurate as the split ones
+  const bool comp = prec == Prec::BF16x3 || prec == Prec::BF16x6;
+  if (comp)
+    for (int i = 0; i < nstrip; ++i) {
+      Cfg g = c[(size_t)i];
+      g.f32 = true;
+      c.push_back(g);
+    }
+  // (p > 32: the split forms are not built for this width)
+  if (prec == Prec::Default || comp || nstrip == 0)
     for (const Cfg& g : cands(vmax, false)) c.push_back(g);
   int dflt = 0;
-  if (nstrip == 0) {
-    if (prec != Prec::Default)  // p > 32: the split forms are not built for this width
-      for (const Cfg& g : cands(vmax, false)) c.push_back(g);
-    dflt = default_strips(c, N);
-  }
+  if (nstrip == 0) dflt = default_strips(c, N);
   return tuned_launch(key_of("unhat", (int)prec, 0, N, n3, p, vmax), (int)c.size(), dflt, s,
                       [&](int i) -> hipError_t {
                         const Cfg& g = c[i];
                         if (!g.strip) return unhat_f32_any(Ah, Q, C, N, n3, p, g, s);
+                        if (g.f32) return unhat_strip_any<0, 0>(Ah, Q, C, N, n3, p, g, s);
                         switch (prec) {
                           case Prec::BF16: return unhat_strip_any<1, 1>(Ah, Q, C, N, n3, p, g, s);
                           case Prec::BF16x3: return unhat_strip_any<2, 2>(Ah, Q, C, N, n3, p, g, s);
