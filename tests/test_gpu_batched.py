@@ -18,7 +18,9 @@ TOLMAX = 1e-4
 
 # (n1, n2, n3, n4 or None, p, k or None): tall and wide faces, faces of
 # fewer than 16 and more than 32 vectors, p = n3, product-only and
-# tSVDQ-only instances
+# tSVDQ-only instances, odd tube counts (one tube per lane in the grouped
+# transforms), a product of more than 32 faces (its back-projection is not
+# grouped)
 SHAPES = [
     (40, 24, 16, 20, 4, 3),
     (150, 70, 33, 45, 9, 4),
@@ -26,6 +28,7 @@ SHAPES = [
     (64, 64, 48, 64, 16, 8),
     (33, 130, 24, 17, 7, None),
     (200, 10, 12, 30, 5, 10),
+    (37, 21, 40, 29, 36, None),
 ]
 
 
