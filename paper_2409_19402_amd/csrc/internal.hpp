@@ -294,8 +294,12 @@ hipError_t jacobi_widen(const float* x, double* y, int64_t n, hipStream_t s);
 hipError_t jacobi_widen_top(const float* W32, double* W64, const JFace* faces, int nfaces, int nv_u, int L_u,
                             int nv_max, int ntop16, double* nrm, int* pos, hipStream_t s);
 // leading 16-vector blocks of the top-block polish for a Ritz step on kr
-// columns: 1 or 2, or 0 (the full schedule) when kr needs more
-inline int top_blocks(int kr) { return kr <= 16 ? 1 : kr <= 32 ? 2 : 0; }
+// columns: 1 or 2, or 0 (the full schedule) when kr needs more.  The
+// polish makes the leading vectors orthogonal to the others; it does not
+// move a leading singular direction that the float32 sweeps left among the
+// trailing vectors into the leading blocks, so the blocks hold kr + 8
+// vectors: the kr of largest norm and a margin against that.
+inline int top_blocks(int kr) { return kr + 8 <= 16 ? 1 : kr + 8 <= 32 ? 2 : 0; }
 // Y = Ah_l^T F_l (cols: Y n2 x k, F n1 x k) or Ah_l F_l (rows: Y n1 x k,
 // F n2 x k) per face, float64 accumulation and result
 hipError_t jacobi_factor_f32(const float* Ah, const double* F, double* Y, int n1, int n2, int k, int p,
