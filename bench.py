@@ -646,6 +646,18 @@ def main():
     torch.cuda.synchronize()
     lib.pq_autotune_enable(0)
     log(f"warmup done ({lib.pq_autotune_entries()} tuned launch shapes)")
+    # cycles of torch's bounded spin kernel per millisecond on this device
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    torch.cuda._sleep(2_000_000)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    spin_cycles_per_ms = 2_000_000 / max(1e-3, e0.elapsed_time(e1))
+    # the host time to enqueue one step (tuned, nothing to wait for)
+    t_host = time.perf_counter()
+    out = step()
+    t_host = time.perf_counter() - t_host
+    torch.cuda.synchronize()
 
     # the timed region: K steps between two events on the launch stream, with
     # an event after each step for the spread of single-step times
@@ -692,6 +704,14 @@ def main():
         out = plan()
         prof_steps = 1
     else:
+        # A step whose kernels finish before the host has enqueued the next
+        # launch leaves the GPU idle between a launch's start event and the
+        # kernel itself, and the event pair would time the host.  A bounded
+        # spin kernel queued first holds the stream for longer than the host
+        # needs to enqueue the K steps, so every event pair brackets its
+        # kernel alone (the timed region above keeps the host in the loop).
+        spin_ms = min(200.0, 4.0 * args.steps * t_host * 1e3 + 2.0)
+        torch.cuda._sleep(int(spin_ms * spin_cycles_per_ms))
         for _ in range(args.steps):
             out = step()
         prof_steps = args.steps
@@ -780,6 +800,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 5),
         "ms_per_step_quantiles": {"p10": round(q10, 5), "p50": round(q50, 5), "p90": round(q90, 5)},
+        "host_enqueue_ms_per_step": round(t_host * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
