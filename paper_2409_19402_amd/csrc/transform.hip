@@ -1130,13 +1130,13 @@ hipError_t unhat_strip_any(const float* Ah, const float* Q, float* C, int64_t N,
                            hipStream_t s) {
 #define PQ_U(V, W, MW) \
   if (c.vec == V && c.waves == W && c.strip == MW) return unhat_strip_go<V, W, MW, NA, NQ>(Ah, Q, C, N, n3, p, s);
-  PQ_U(4, 4, 2) PQ_U(4, 2, 2) PQ_U(2, 4, 4) PQ_U(2, 8, 4) PQ_U(1, 8, 4)
+  PQ_U(4, 4, 2) PQ_U(4, 2, 2) PQ_U(2, 4, 4) PQ_U(2, 8, 4) PQ_U(2, 4, 2) PQ_U(2, 8, 2) PQ_U(1, 8, 4)
 #undef PQ_U
   return hipErrorInvalidValue;
 }
 
 void unhat_strip_cands(int vmax, std::vector<Cfg>& v) {
-  static const int t[][3] = {{4, 4, 2}, {4, 2, 2}, {2, 4, 4}, {2, 8, 4}, {1, 8, 4}};
+  static const int t[][3] = {{4, 4, 2}, {4, 2, 2}, {2, 4, 4}, {2, 8, 4}, {2, 4, 2}, {2, 8, 2}, {1, 8, 4}};
   for (const auto& r : t)
     if (r[0] <= vmax) {
       Cfg c{r[0], r[1], 0};
@@ -1279,9 +1279,8 @@ void unhat_group_tiles(const XformDesc& d, int desc, std::vector<XformTile>& til
   for (int64_t x = 0; x < (strips + 3) / 4; ++x) tiles.push_back(XformTile{x, desc, 0});
 }
 
-// the strip kernels' shapes that the autotuner picks most often for single
-// transforms: four waves splitting the slices of a strip four pairs per
-// batch (forward), four waves with a strip each (return)
+// the forward strip kernel's shapes that the autotuner picks most often for
+// single transforms: four waves splitting the slices of a strip
 hipError_t hat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (vec == 4)
@@ -1293,15 +1292,27 @@ hipError_t hat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int v
   return hipGetLastError();
 }
 
+// The return transform's two shapes per vector width, chosen by the
+// autotuner per group (key: width and tile count): four waves with a strip
+// each, at two or four waves per SIMD (the two-tube form needs more than 128
+// registers with its Q entries double-buffered, and spills at four).
 hipError_t unhat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (vec == 4)
-    unhat_grouped_kernel<4, 4, 2><<<(unsigned)ntiles, 256, 0, s>>>(d, t);
-  else if (vec == 2)
-    unhat_grouped_kernel<2, 4, 4><<<(unsigned)ntiles, 256, 0, s>>>(d, t);
-  else
-    unhat_grouped_kernel<1, 4, 4><<<(unsigned)ntiles, 256, 0, s>>>(d, t);
-  return hipGetLastError();
+  const std::string key = "unhatg/" + std::to_string(vec) + "/" + std::to_string(ntiles);
+  return tuned_launch(key, 2, 0, s, [&](int c) -> hipError_t {
+    const unsigned g = (unsigned)ntiles;
+    if (vec == 4) {
+      if (c == 0) unhat_grouped_kernel<4, 4, 2><<<g, 256, 0, s>>>(d, t);
+      else unhat_grouped_kernel<4, 4, 1><<<g, 256, 0, s>>>(d, t);
+    } else if (vec == 2) {
+      if (c == 0) unhat_grouped_kernel<2, 4, 2><<<g, 256, 0, s>>>(d, t);
+      else unhat_grouped_kernel<2, 4, 4><<<g, 256, 0, s>>>(d, t);
+    } else {
+      if (c == 0) unhat_grouped_kernel<1, 4, 4><<<g, 256, 0, s>>>(d, t);
+      else unhat_grouped_kernel<1, 4, 2><<<g, 256, 0, s>>>(d, t);
+    }
+    return hipGetLastError();
+  });
 }
 
 hipError_t hat_f32(const void* A, bool a_bf16, const float* Q, float* Ah, int64_t N, int n3, int p,
