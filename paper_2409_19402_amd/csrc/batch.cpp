@@ -223,6 +223,7 @@ Layout layout(const pq_instance* inst, int count) {
 // transforms by vector width (index 0: two tubes per lane, 1: one)
 struct XformPlan {
   int nh[3] = {0, 0, 0}, nu[3] = {0, 0, 0};  // by tubes per lane: 4, 2, 1
+  size_t uq[3] = {0, 0, 0};                  // largest Q of each return group, staged in LDS (bytes)
 };
 
 int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps, double tol, int* info_dev,
@@ -251,9 +252,9 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
   }
   {
     pq::ProfScope prof("unhat", s, (xp.nu[0] > 0) + (xp.nu[1] > 0) + (xp.nu[2] > 0));
-    BQ_TRY(pq::unhat_grouped(xd, ut, xp.nu[0], 4, s));
-    BQ_TRY(pq::unhat_grouped(xd, ut + xp.nu[0], xp.nu[1], 2, s));
-    BQ_TRY(pq::unhat_grouped(xd, ut + xp.nu[0] + xp.nu[1], xp.nu[2], 1, s));
+    BQ_TRY(pq::unhat_grouped(xd, ut, xp.nu[0], 4, xp.uq[0], s));
+    BQ_TRY(pq::unhat_grouped(xd, ut + xp.nu[0], xp.nu[1], 2, xp.uq[1], s));
+    BQ_TRY(pq::unhat_grouped(xd, ut + xp.nu[0] + xp.nu[1], xp.nu[2], 1, xp.uq[2], s));
   }
   for (int i = 0; i < count; ++i) {  // products of more than 32 faces
     const pq_instance& x = inst[i];
@@ -376,6 +377,7 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
   // tiles grouped by vector width, longest tubes (most slices) first
   std::vector<pq::XformDesc> xds;
   std::vector<pq::XformTile> hts[3], uts[3];
+  size_t uq[3] = {0, 0, 0};
   auto add_hat = [&](const void* in, void* out, int64_t N, const pq_instance& x) {
     const pq::XformDesc d{static_cast<const float*>(in), static_cast<const float*>(x.Q), static_cast<float*>(out), N,
                           (int)x.n3, (int)x.p};
@@ -394,10 +396,13 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
     const pq::XformDesc d{reinterpret_cast<const float*>(w + lo.ch[i]), static_cast<const float*>(x.Q),
                           static_cast<float*>(x.C), x.n1 * x.n4, (int)x.n3, (int)x.p};
     const int uv = pq::unhat_group_vec(d);
-    pq::unhat_group_tiles(d, (int)xds.size(), uts[uv == 4 ? 0 : uv == 2 ? 1 : 2]);
+    const int gi = uv == 4 ? 0 : uv == 2 ? 1 : 2;
+    pq::unhat_group_tiles(d, (int)xds.size(), uts[gi]);
+    uq[gi] = std::max(uq[gi], pq::unhat_group_q_bytes(d));
     xds.push_back(d);
   }
   XformPlan xp;
+  for (int v = 0; v < 3; ++v) xp.uq[v] = uq[v];
   std::vector<pq::XformTile> htab, utab;
   auto by_n3 = [&](const pq::XformTile& a, const pq::XformTile& b) { return xds[a.desc].n3 > xds[b.desc].n3; };
   for (int v = 0; v < 3; ++v) {

@@ -178,7 +178,10 @@ int unhat_group_vec(const XformDesc& d);
 void hat_group_tiles(const XformDesc& d, int desc, std::vector<XformTile>& tiles);
 void unhat_group_tiles(const XformDesc& d, int desc, std::vector<XformTile>& tiles);
 hipError_t hat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, hipStream_t s);
-hipError_t unhat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, hipStream_t s);
+hipError_t unhat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, size_t q_bytes,
+                         hipStream_t s);
+// LDS bytes of a return transform's Q staged in LDS
+size_t unhat_group_q_bytes(const XformDesc& d);
 // Visits of a grouped sweep listed per round, so that a launch has one
 // workgroup per visit that exists (faces of fewer blocks have fewer rounds
 // and pairs): entry (f << kVisitShift) | slot names face f of the table and

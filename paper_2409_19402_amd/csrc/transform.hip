@@ -603,10 +603,27 @@ __global__ __launch_bounds__(S * 64) void hat_bf16_kernel(const TIn* __restrict_
 // v_mfma_f32_32x32x16_bf16 over 16 channels at a time, both operands split
 // into parts (Split<NA, NQ>: Chat parts x Q parts).
 // (workgroup bx of the strips; output tiles y0, y0 + ystep, ...)
-template <int VEC, int W>
+// QL: the workgroup's copy of Q in LDS (row stride p | 1, so that the 32
+// rows a half-wave reads fall in distinct banks).  Reading Q from memory
+// inside the loop makes each tile wait for the previous tile's stores: the
+// memory counter orders loads and stores together, and with stores under a
+// branch the compiler's wait for the Q loads has to cover them all.  From
+// LDS, the stores of one tile drain while the next tile's MFMAs run.
+__host__ __device__ __forceinline__ int q_lds_stride(int p) { return p | 1; }
+
+template <bool QL>
+__device__ __forceinline__ void stage_q(const float* __restrict__ Q, int n3, int p, float* qs) {
+  if constexpr (QL) {
+    const int ps = q_lds_stride(p);
+    for (int e = threadIdx.x; e < n3 * p; e += blockDim.x) qs[(e / p) * ps + e % p] = Q[e];
+    __syncthreads();
+  }
+}
+
+template <int VEC, int W, bool QL>
 __device__ __forceinline__ void unhat_strip_body(const float* __restrict__ Ah, const float* __restrict__ Q,
                                                  float* __restrict__ C, int64_t N, int n3, int p, int64_t bx,
-                                                 int y0, int ystep) {
+                                                 int y0, int ystep, const float* qs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 31, kh = lane >> 5;
   const int64_t xl = (bx * W + wave) * (32 * VEC) + (int64_t)VEC * n;
@@ -623,8 +640,14 @@ __device__ __forceinline__ void unhat_strip_body(const float* __restrict__ Ah, c
   }
   auto qload = [&](int tile, float (&a)[16]) {
     const int t = min(tile * 32 + n, n3 - 1);
+    if constexpr (QL) {
+      const int ps = q_lds_stride(p);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) a[s] = Q[(int64_t)t * p + min(2 * s + kh, p - 1)];
+      for (int s = 0; s < 16; ++s) a[s] = qs[t * ps + min(2 * s + kh, p - 1)];
+    } else {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) a[s] = Q[(int64_t)t * p + min(2 * s + kh, p - 1)];
+    }
   };
   float a0[16], a1[16];
   int tile = y0;
@@ -666,21 +689,25 @@ __device__ __forceinline__ void unhat_strip_body(const float* __restrict__ Ah, c
   }
 }
 
-template <int VEC, int W, int MW>
+template <int VEC, int W, int MW, bool QL>
 __global__ __launch_bounds__(W * 64, MW) void unhat_strip_kernel(const float* __restrict__ Ah,
                                                                  const float* __restrict__ Q,
                                                                  float* __restrict__ C, int64_t N, int n3, int p) {
-  unhat_strip_body<VEC, W>(Ah, Q, C, N, n3, p, blockIdx.x, blockIdx.y, gridDim.y);
+  extern __shared__ float qs[];  // QL: n3 rows of q_lds_stride(p)
+  stage_q<QL>(Q, n3, p, qs);
+  unhat_strip_body<VEC, W, QL>(Ah, Q, C, N, n3, p, blockIdx.x, blockIdx.y, gridDim.y, qs);
 }
 
 // Many return transforms in one launch (the batched form): workgroup w takes
 // tile tiles[w] (descriptor, workgroup of strips, every output tile).
-template <int VEC, int W, int MW>
+template <int VEC, int W, int MW, bool QL>
 __global__ __launch_bounds__(W * 64, MW) void unhat_grouped_kernel(const XformDesc* __restrict__ descs,
                                                                    const XformTile* __restrict__ tiles) {
+  extern __shared__ float qs[];
   const XformTile t = tiles[blockIdx.x];
   const XformDesc d = descs[t.desc];
-  unhat_strip_body<VEC, W>(d.in, d.Q, d.out, d.N, d.n3, d.p, t.x, t.y, 1);
+  stage_q<QL>(d.Q, d.n3, d.p, qs);
+  unhat_strip_body<VEC, W, QL>(d.in, d.Q, d.out, d.N, d.n3, d.p, t.x, t.y, 1, qs);
 }
 
 
@@ -986,6 +1013,7 @@ struct Cfg {
   int vec, waves, spw;
   int strip = 0;  // > 0: hat_strip_kernel, `spw` slice pairs per load batch, `strip` min waves per SIMD
   bool f32 = false;  // a split-bfloat16 mode's candidate that runs the float32 kernel
+  bool qlds = false;  // float32 return strip with Q staged in LDS
 };
 
 std::vector<Cfg> cands(int vmax, bool splitk) {
@@ -1109,7 +1137,7 @@ void strip_cands(int vmax, std::vector<Cfg>& v) {
     }
 }
 
-template <int VEC, int W, int MW, int NA, int NQ>
+template <int VEC, int W, int MW, int NA, int NQ, bool QL = false>
 hipError_t unhat_strip_go(const float* Ah, const float* Q, float* C, int64_t N, int n3, int p, hipStream_t s) {
   const int64_t strips = (N + 32 * VEC - 1) / (32 * VEC);
   const int64_t wgs = (strips + W - 1) / W;
@@ -1118,7 +1146,8 @@ hipError_t unhat_strip_go(const float* Ah, const float* Q, float* C, int64_t N, 
   const int ysplit = (int)std::min<int64_t>(ntiles, std::max<int64_t>(1, (4096 + wgs - 1) / wgs));
   dim3 grid((unsigned)wgs, (unsigned)ysplit);
   if constexpr (NA == 0)
-    unhat_strip_kernel<VEC, W, MW><<<grid, W * 64, 0, s>>>(Ah, Q, C, N, n3, p);
+    unhat_strip_kernel<VEC, W, MW, QL>
+        <<<grid, W * 64, QL ? sizeof(float) * (size_t)n3 * q_lds_stride(p) : 0, s>>>(Ah, Q, C, N, n3, p);
   else
     unhat_bstrip_kernel<VEC, W, MW, NA, NQ><<<grid, W * 64, 0, s>>>(Ah, Q, C, N, n3, p);
   return hipGetLastError();
@@ -1130,6 +1159,15 @@ hipError_t unhat_strip_any(const float* Ah, const float* Q, float* C, int64_t N,
                            hipStream_t s) {
 #define PQ_U(V, W, MW) \
   if (c.vec == V && c.waves == W && c.strip == MW) return unhat_strip_go<V, W, MW, NA, NQ>(Ah, Q, C, N, n3, p, s);
+  if constexpr (NA == 0) {
+    if (c.qlds) {
+#define PQ_UL(V, W, MW) \
+  if (c.vec == V && c.waves == W && c.strip == MW) return unhat_strip_go<V, W, MW, 0, 0, true>(Ah, Q, C, N, n3, p, s);
+      PQ_UL(4, 4, 2) PQ_UL(4, 2, 2) PQ_UL(2, 4, 2) PQ_UL(2, 4, 4) PQ_UL(1, 8, 4)
+#undef PQ_UL
+      return hipErrorInvalidValue;
+    }
+  }
   PQ_U(4, 4, 2) PQ_U(4, 2, 2) PQ_U(2, 4, 4) PQ_U(2, 8, 4) PQ_U(2, 4, 2) PQ_U(2, 8, 2) PQ_U(1, 8, 4)
 #undef PQ_U
   return hipErrorInvalidValue;
@@ -1141,6 +1179,21 @@ void unhat_strip_cands(int vmax, std::vector<Cfg>& v) {
     if (r[0] <= vmax) {
       Cfg c{r[0], r[1], 0};
       c.strip = r[2];
+      v.push_back(c);
+    }
+}
+
+// the float32 strip shapes with Q staged in LDS, when Q fits
+constexpr size_t kQLdsMax = 64 * 1024;
+void unhat_strip_ql_cands(int vmax, int n3, int p, std::vector<Cfg>& v) {
+  if (sizeof(float) * (size_t)n3 * q_lds_stride(p) > kQLdsMax) return;
+  static const int t[][3] = {{4, 4, 2}, {4, 2, 2}, {2, 4, 2}, {2, 4, 4}, {1, 8, 4}};
+  for (const auto& r : t)
+    if (r[0] <= vmax) {
+      Cfg c{r[0], r[1], 0};
+      c.strip = r[2];
+      c.qlds = true;
+      c.f32 = true;
       v.push_back(c);
     }
 }
@@ -1292,28 +1345,41 @@ hipError_t hat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int v
   return hipGetLastError();
 }
 
-// The return transform's two shapes per vector width, chosen by the
-// autotuner per group (key: width and tile count): four waves with a strip
-// each, at two or four waves per SIMD (the two-tube form needs more than 128
-// registers with its Q entries double-buffered, and spills at four).
-hipError_t unhat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, hipStream_t s) {
+// The return transform's shapes per vector width, chosen by the autotuner
+// per group (key: width and tile count): four waves with a strip each, at
+// two or four waves per SIMD (the two-tube form needs more than 128
+// registers with its Q entries double-buffered, and spills at four), with
+// Q staged in LDS when the group's largest Q fits (q_bytes: its n3 rows of
+// q_lds_stride(p) floats; 0: read from memory).
+hipError_t unhat_grouped(const XformDesc* d, const XformTile* t, int ntiles, int vec, size_t q_bytes,
+                         hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  const std::string key = "unhatg/" + std::to_string(vec) + "/" + std::to_string(ntiles);
-  return tuned_launch(key, 2, 0, s, [&](int c) -> hipError_t {
+  const bool ql = q_bytes > 0 && q_bytes <= kQLdsMax;
+  const std::string key = "unhatg/" + std::to_string(vec) + "/" + std::to_string(ntiles) + (ql ? "/q" : "");
+  return tuned_launch(key, ql ? 4 : 2, ql ? 2 : 0, s, [&](int c) -> hipError_t {
     const unsigned g = (unsigned)ntiles;
+    const size_t lds = c >= 2 ? q_bytes : 0;
     if (vec == 4) {
-      if (c == 0) unhat_grouped_kernel<4, 4, 2><<<g, 256, 0, s>>>(d, t);
-      else unhat_grouped_kernel<4, 4, 1><<<g, 256, 0, s>>>(d, t);
+      if (c == 0) unhat_grouped_kernel<4, 4, 2, false><<<g, 256, 0, s>>>(d, t);
+      else if (c == 1) unhat_grouped_kernel<4, 4, 1, false><<<g, 256, 0, s>>>(d, t);
+      else if (c == 2) unhat_grouped_kernel<4, 4, 2, true><<<g, 256, lds, s>>>(d, t);
+      else unhat_grouped_kernel<4, 4, 1, true><<<g, 256, lds, s>>>(d, t);
     } else if (vec == 2) {
-      if (c == 0) unhat_grouped_kernel<2, 4, 2><<<g, 256, 0, s>>>(d, t);
-      else unhat_grouped_kernel<2, 4, 4><<<g, 256, 0, s>>>(d, t);
+      if (c == 0) unhat_grouped_kernel<2, 4, 2, false><<<g, 256, 0, s>>>(d, t);
+      else if (c == 1) unhat_grouped_kernel<2, 4, 4, false><<<g, 256, 0, s>>>(d, t);
+      else if (c == 2) unhat_grouped_kernel<2, 4, 2, true><<<g, 256, lds, s>>>(d, t);
+      else unhat_grouped_kernel<2, 4, 4, true><<<g, 256, lds, s>>>(d, t);
     } else {
-      if (c == 0) unhat_grouped_kernel<1, 4, 4><<<g, 256, 0, s>>>(d, t);
-      else unhat_grouped_kernel<1, 4, 2><<<g, 256, 0, s>>>(d, t);
+      if (c == 0) unhat_grouped_kernel<1, 4, 4, false><<<g, 256, 0, s>>>(d, t);
+      else if (c == 1) unhat_grouped_kernel<1, 4, 2, false><<<g, 256, 0, s>>>(d, t);
+      else if (c == 2) unhat_grouped_kernel<1, 4, 4, true><<<g, 256, lds, s>>>(d, t);
+      else unhat_grouped_kernel<1, 4, 2, true><<<g, 256, lds, s>>>(d, t);
     }
     return hipGetLastError();
   });
 }
+
+size_t unhat_group_q_bytes(const XformDesc& d) { return sizeof(float) * (size_t)d.n3 * q_lds_stride(d.p); }
 
 hipError_t hat_f32(const void* A, bool a_bf16, const float* Q, float* Ah, int64_t N, int n3, int p,
                    Prec prec, hipStream_t s) {
@@ -1377,6 +1443,11 @@ hipError_t unhat_f32(const float* Ah, const float* Q, float* C, int64_t N, int n
   std::vector<Cfg> c;
   if (p <= 32) unhat_strip_cands(vmax, c);
   const int nstrip = (int)c.size();
+  // the float32 strip shapes with Q in LDS (also timed by the compensated
+  // modes, like the float32 strips below)
+  std::vector<Cfg> ql;
+  if (p <= 32 && (prec == Prec::Default || prec == Prec::BF16x3 || prec == Prec::BF16x6))
+    unhat_strip_ql_cands(vmax, n3, p, ql);
   // the compensated modes also time the float32 kernels (strip and
   // LDS-staged): the return transform is bound by its float32 writes, and
   // float32 products are at least as accurate as the split ones
@@ -1387,6 +1458,7 @@ hipError_t unhat_f32(const float* Ah, const float* Q, float* C, int64_t N, int n
       g.f32 = true;
       c.push_back(g);
     }
+  for (const Cfg& g : ql) c.push_back(g);
   // (p > 32: the split forms are not built for this width)
   if (prec == Prec::Default || comp || nstrip == 0)
     for (const Cfg& g : cands(vmax, false)) c.push_back(g);
