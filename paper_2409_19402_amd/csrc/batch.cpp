@@ -82,6 +82,11 @@ struct Layout {
   // float64 polish (top-block schedule), host copies and device offsets
   std::vector<int> v32, off32, v64, off64;
   size_t dv32 = 0, dv64 = 0;
+  // the float32 lists of the parts of the faces (faces dealt in turn in
+  // order of vector length) for the sweeps on several streams
+  std::vector<int> v32p[pq::kSweepParts], off32p[pq::kSweepParts];
+  std::vector<int> v64p[pq::kSweepParts], off64p[pq::kSweepParts];
+  size_t dv32p[pq::kSweepParts] = {}, dv64p[pq::kSweepParts] = {};
   bool listed = false;
 };
 
@@ -164,10 +169,25 @@ Layout layout(const pq_instance* inst, int count) {
     const int nv = (int)std::min(x.n1, x.n2), L = (int)std::max(x.n1, x.n2);
     for (int64_t l = 0; l < x.p; ++l) lo.tab.push_back(pq::JFace{lo.woff[i] + l * nv * L, nv, L});
   }
+  std::vector<char> pick[pq::kSweepParts];
+  {
+    std::vector<int> order((size_t)lo.nfaces);
+    for (int f = 0; f < lo.nfaces; ++f) order[(size_t)f] = f;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lo.tab[a].L > lo.tab[b].L; });
+    for (int k = 0; k < pq::kSweepParts; ++k) pick[k].assign((size_t)lo.nfaces, 0);
+    for (size_t r = 0; r < order.size(); ++r) pick[r % pq::kSweepParts][(size_t)order[r]] = 1;
+  }
   lo.listed = pq::jacobi_visit_list(lo.tab.data(), lo.nfaces, 0, lo.v32, lo.off32) &&
               pq::jacobi_visit_list(lo.tab.data(), lo.nfaces, lo.ntop, lo.v64, lo.off64);
+  for (int k = 0; k < pq::kSweepParts && lo.listed; ++k)
+    lo.listed = pq::jacobi_visit_list(lo.tab.data(), lo.nfaces, 0, lo.v32p[k], lo.off32p[k], &pick[k]) &&
+                pq::jacobi_visit_list(lo.tab.data(), lo.nfaces, lo.ntop, lo.v64p[k], lo.off64p[k], &pick[k]);
   lo.dv32 = take(sizeof(int) * std::max<size_t>(1, lo.v32.size()));
   lo.dv64 = take(sizeof(int) * std::max<size_t>(1, lo.v64.size()));
+  for (int k = 0; k < pq::kSweepParts; ++k) {
+    lo.dv32p[k] = take(sizeof(int) * std::max<size_t>(1, lo.v32p[k].size()));
+    lo.dv64p[k] = take(sizeof(int) * std::max<size_t>(1, lo.v64p[k].size()));
+  }
   for (int i = 0; i < count; ++i) lo.ah[i] = take(4 * (size_t)inst[i].n1 * inst[i].n2 * inst[i].p);
   lo.bh.assign(count, 0);
   lo.ch.assign(count, 0);
@@ -227,7 +247,7 @@ struct XformPlan {
 };
 
 int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps, double tol, int* info_dev,
-            char* ws, const XformPlan& xp, hipStream_t s) {
+            char* ws, const XformPlan& xp, hipStream_t s, const pq::SweepPair* pair) {
   float* W32 = reinterpret_cast<float*>(ws + lo.w32);
   double* W64 = reinterpret_cast<double*>(ws + lo.w64);
   int* used1 = reinterpret_cast<int*>(ws + lo.used1);
@@ -271,9 +291,20 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
   }
   const pq::VisitList vl32{reinterpret_cast<const int*>(ws + lo.dv32), lo.off32.data()};
   const pq::VisitList vl64{reinterpret_cast<const int*>(ws + lo.dv64), lo.off64.data()};
+  pq::VisitList vl32p[pq::kSweepParts], vl64p[pq::kSweepParts];
+  pq::SweepPair sp, sp64;
+  if (pair && lo.listed) {
+    sp = sp64 = *pair;
+    for (int k = 0; k < pq::kSweepParts; ++k) {
+      vl32p[k] = pq::VisitList{reinterpret_cast<const int*>(ws + lo.dv32p[k]), lo.off32p[k].data()};
+      vl64p[k] = pq::VisitList{reinterpret_cast<const int*>(ws + lo.dv64p[k]), lo.off64p[k].data()};
+      sp.vl[k] = &vl32p[k];
+      sp64.vl[k] = &vl64p[k];
+    }
+  }
   BQ_TRY(pq::jacobi_gram_grouped_f32(W32, faces, lo.nfaces, lo.nb_max, lo.L_max, max_sweeps, kCoarseTol,
                                      lo.ntop > 0 ? pq::kCoarseStop32 : kCoarseTol, used1,
-                                     flags, lo.listed ? &vl32 : nullptr, s));
+                                     flags, lo.listed ? &vl32 : nullptr, s, pair && lo.listed ? &sp : nullptr));
   if (lo.ntop > 0)
     BQ_TRY(pq::jacobi_widen_top(W32, W64, faces, lo.nfaces, 0, 0, lo.nv_max, 16 * lo.ntop,
                                 reinterpret_cast<double*>(ws + lo.tnrm), reinterpret_cast<int*>(ws + lo.tpos), s));
@@ -283,7 +314,7 @@ int enqueue(const Layout& lo, const pq_instance* inst, int count, int max_sweeps
   const double ptol = std::max(tol, kTolFloor);
   BQ_TRY(pq::jacobi_gram_grouped_f64(W64, faces, lo.nfaces, lo.nb_max, lo.L_max, polish, ptol,
                                      lo.ntop > 0 ? pq::kPolishStop32 : ptol, lo.ntop, used2, flags,
-                                     lo.listed ? &vl64 : nullptr, s));
+                                     lo.listed ? &vl64 : nullptr, s, pair && lo.listed ? &sp64 : nullptr));
   // finishing of every face at once: the top kr vectors, the other factor
   // and the Ritz step (one launch each over the face table)
   BQ_TRY(pq::jacobi_finish_grouped(reinterpret_cast<const pq::FinFace*>(ws + lo.fin), lo.nfaces, lo.fmax, tol, s));
@@ -424,6 +455,12 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
     BQ_TRY(hipMemcpy(w + lo.dv32, lo.v32.data(), sizeof(int) * lo.v32.size(), hipMemcpyHostToDevice));
   if (lo.listed && !lo.v64.empty())
     BQ_TRY(hipMemcpy(w + lo.dv64, lo.v64.data(), sizeof(int) * lo.v64.size(), hipMemcpyHostToDevice));
+  for (int k = 0; k < pq::kSweepParts; ++k) {
+    if (lo.listed && !lo.v32p[k].empty())
+      BQ_TRY(hipMemcpy(w + lo.dv32p[k], lo.v32p[k].data(), sizeof(int) * lo.v32p[k].size(), hipMemcpyHostToDevice));
+    if (lo.listed && !lo.v64p[k].empty())
+      BQ_TRY(hipMemcpy(w + lo.dv64p[k], lo.v64p[k].data(), sizeof(int) * lo.v64p[k].size(), hipMemcpyHostToDevice));
+  }
   if (!descs.empty())
     BQ_TRY(hipMemcpy(w + lo.gdesc, descs.data(), sizeof(pq::GemmDesc) * descs.size(), hipMemcpyHostToDevice));
   if (!tiles.empty())
@@ -436,20 +473,47 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
     BQ_TRY(hipMemcpy(w + lo.htile, htab.data(), sizeof(pq::XformTile) * htab.size(), hipMemcpyHostToDevice));
   if (!utab.empty())
     BQ_TRY(hipMemcpy(w + lo.utile, utab.data(), sizeof(pq::XformTile) * utab.size(), hipMemcpyHostToDevice));
+  // the second stream and the fork/join events of the float32 sweeps (the
+  // captured graph keeps only the dependencies they express)
+  pq::SweepPair pair;
+  auto release_pair = [&]() {
+    if (pair.fork) hipEventDestroy(pair.fork);
+    for (int k = 0; k + 1 < pq::kSweepParts; ++k) {
+      if (pair.join[k]) hipEventDestroy(pair.join[k]);
+      if (pair.s2[k]) hipStreamDestroy(pair.s2[k]);
+    }
+  };
+  hipError_t pe = hipEventCreateWithFlags(&pair.fork, hipEventDisableTiming);
+  for (int k = 0; k + 1 < pq::kSweepParts && pe == hipSuccess; ++k) {
+    pe = hipStreamCreateWithFlags(&pair.s2[k], hipStreamNonBlocking);
+    if (pe == hipSuccess) pe = hipEventCreateWithFlags(&pair.join[k], hipEventDisableTiming);
+  }
+  if (pe != hipSuccess) {
+    release_pair();
+    return hip_rc(pe);
+  }
   // one eager pass (valid outputs; tunes new launch shapes while tuning is on)
-  BQ_CHECK(enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, xp, stream));
-  BQ_TRY(hipStreamSynchronize(stream));
+  int erc0 = enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, xp, stream, &pair);
+  if (erc0 == PQ_OK) erc0 = hip_rc(hipStreamSynchronize(stream));
+  if (erc0 != PQ_OK) {
+    release_pair();
+    return erc0;
+  }
   // capture the same launches on a private stream
   hipStream_t cs = nullptr;
-  BQ_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  if ((pe = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
+    release_pair();
+    return hip_rc(pe);
+  }
   pq_batch_s* b = new (std::nothrow) pq_batch_s;
   if (!b) {
     hipStreamDestroy(cs);
+    release_pair();
     return PQ_ERR_ARG;
   }
   int rc = hip_rc(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   if (rc == PQ_OK) {
-    const int erc = enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, xp, cs);
+    const int erc = enqueue(lo, inst, count, max_sweeps, tol, info_dev, w, xp, cs, &pair);
     hipGraph_t g = nullptr;
     const int crc = hip_rc(hipStreamEndCapture(cs, &g));
     rc = erc != PQ_OK ? erc : crc;
@@ -457,6 +521,7 @@ int pq_batched_plan(const pq_instance* inst, int count, int max_sweeps, double t
     if (rc == PQ_OK) rc = hip_rc(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   }
   hipStreamDestroy(cs);
+  release_pair();
   if (rc != PQ_OK) {
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);

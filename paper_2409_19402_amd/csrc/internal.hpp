@@ -195,17 +195,30 @@ struct VisitList {
 };
 // the visit list of the grouped sweeps over faces (host copy of the face
 // table); false when the table is too large to list
-bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int>& entries, std::vector<int>& off);
+bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int>& entries, std::vector<int>& off,
+                       const std::vector<char>* pick = nullptr);
 // vl: the sweep's visit list (nullptr: every face at the largest face's
 // rounds and slots, idle workgroups exiting at once)
+// A second stream for the grouped sweeps: the faces split in two
+// halves with visit lists of their own (vla, vlb), the first half's rounds
+// on the caller's stream and the second's on s2, between a fork and a join
+// event, so that one half's memory phases (staging, write-back) overlap the
+// other's rotation rounds.  Used when a launch would hold two or more
+// visits per CU; otherwise the sweeps run the full list on one stream.
+constexpr int kSweepParts = 2;  // three or four parts measured no faster
+struct SweepPair {
+  hipStream_t s2[kSweepParts - 1] = {};
+  hipEvent_t fork = nullptr, join[kSweepParts - 1] = {};
+  const VisitList* vl[kSweepParts] = {};
+};
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, double stop2, int* used, int* flags,
-                                   const VisitList* vl, hipStream_t s);
+                                   const VisitList* vl, hipStream_t s, const SweepPair* sp = nullptr);
 // ntop (1 or 2; 0 = every pair): the top-block schedule, which visits only
 // the pairs with a vector in the first ntop 16-vector blocks of a face
 hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, double stop2, int ntop, int* used, int* flags,
-                                   const VisitList* vl, hipStream_t s);
+                                   const VisitList* vl, hipStream_t s, const SweepPair* sp = nullptr);
 // float64 sweeps in the Gram-matrix form (the polishing sweeps of float32
 // data); ntop as above
 hipError_t jacobi_gram_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, double tol, double stop2,

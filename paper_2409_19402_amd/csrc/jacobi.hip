@@ -1841,6 +1841,7 @@ size_t gram_lds_cap() {
 // a launch has more than four visits per CU.  Vectors too long to stage at
 // all are never staged.
 enum class GramForm { Staged2, Staged1, Stream };
+constexpr int kSplitVisitsPerCu = 256;  // CUs of the device
 constexpr size_t kHalfCuLds = 80 * 1024;
 
 template <typename T>
@@ -1923,7 +1924,7 @@ inline float sweep_skip2(double tol, double stop2) { return (float)(stop2 > 0.0 
 template <typename T>
 hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max,
                        int max_sweeps, double tol, double stop2, int ntop, int* used, int* flags, hipStream_t s,
-                       const VisitList* vl = nullptr) {
+                       const VisitList* vl = nullptr, const SweepPair* sp = nullptr) {
   const int nflags = nfaces * max_sweeps;
   {
     ProfScope prof("jacobi_flags", s);
@@ -1939,23 +1940,60 @@ hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, 
                             ? GramForm::Staged2
                             : gram_form<T>(L_max, gram_grid(nfaces, slots));
   const float skip2 = sweep_skip2(tol, stop2);
-  {
-    ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s,
-                   max_sweeps * sweep_launches(ntop, nb_max, vl));
-    // staged visits get eight waves (two per SIMD hide each other's latency)
+  // The faces in two parts on two streams (sp) when a launch would hold two
+  // or more visits per CU: the visits of one launch start together and move
+  // through the same phases at once, so that the memory system idles during
+  // the rotation rounds and is flooded by the write-backs; two independent
+  // chains of launches fall out of step and overlap the two.  Measured: the
+  // batched workload's float32 sweeps 62.7 -> 58.0 ms, the hyperspectral
+  // faces (512 visits per launch, split by face halves) 7.59 -> 6.85 ms; a
+  // launch with fewer visits than CUs only gains dispatch cost (video 1.89
+  // -> 2.10 ms), hence the threshold.
+  bool split = sp != nullptr;
+  int split_visits = 0;
+  for (int k = 0; split && k < kSweepParts; ++k) {
+    split = sp->vl[k] != nullptr && (k == 0 || sp->s2[k - 1] != nullptr);
+    if (split) split_visits += sp->vl[k]->off[1] - sp->vl[k]->off[0];
+  }
+  split = split && split_visits >= 2 * kSplitVisitsPerCu;
+  // every launch of the sweeps over visit list l on stream st, in the form
+  // chosen (staged visits get eight waves: two per SIMD hide each other's
+  // latency)
+  auto launch = [&](const VisitList* l, hipStream_t st) {
     if (form == GramForm::Stream) {
       gram_launch_all<T, 2, false, 4>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop,
-                                       flags, vl, s);
+                                       flags, l, st);
     } else if constexpr (sizeof(T) == 4) {
       if (form == GramForm::Staged1)
         gram_launch_all<T, 1, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop,
-                                       flags, vl, s);
+                                       flags, l, st);
       else
         gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop,
-                                       flags, vl, s);
+                                       flags, l, st);
     } else {
       gram_launch_all<T, 2, true, 8>(W, faces, nfaces, nv_u, L_u, nb_max, L_max, max_sweeps, tol, skip2, ntop, flags,
-                                     vl, s);
+                                     l, st);
+    }
+  };
+  {
+    int nl = 0;
+    if (split)
+      for (int k = 0; k < kSweepParts; ++k) nl += sweep_launches(ntop, nb_max, sp->vl[k]);
+    else
+      nl = sweep_launches(ntop, nb_max, vl);
+    ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s, max_sweeps * nl);
+    if (split) {
+      hipError_t e = hipEventRecord(sp->fork, s);
+      for (int k = 1; k < kSweepParts && e == hipSuccess; ++k) e = hipStreamWaitEvent(sp->s2[k - 1], sp->fork, 0);
+      if (e != hipSuccess) return e;
+      for (int k = 0; k < kSweepParts; ++k) launch(sp->vl[k], k == 0 ? s : sp->s2[k - 1]);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      for (int k = 1; k < kSweepParts; ++k) {
+        if ((e = hipEventRecord(sp->join[k - 1], sp->s2[k - 1])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, sp->join[k - 1], 0)) != hipSuccess) return e;
+      }
+    } else {
+      launch(vl, s);
     }
   }
   {
@@ -2090,16 +2128,18 @@ hipError_t jacobi_sweeps_f64(double* W, int p, int nv, int L, int max_sweeps, do
 }
 hipError_t jacobi_gram_grouped_f32(float* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, double stop2, int* used, int* flags,
-                                   const VisitList* vl, hipStream_t s) {
-  return gram_sweeps<float>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, stop2, 0, used, flags, s, vl);
+                                   const VisitList* vl, hipStream_t s, const SweepPair* sp) {
+  return gram_sweeps<float>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, stop2, 0, used, flags, s, vl,
+                            sp);
 }
 hipError_t jacobi_gram_grouped_f64(double* W, const JFace* faces, int nfaces, int nb_max, int L_max,
                                    int max_sweeps, double tol, double stop2, int ntop, int* used, int* flags,
-                                   const VisitList* vl, hipStream_t s) {
+                                   const VisitList* vl, hipStream_t s, const SweepPair* sp) {
   return gram_sweeps<double>(W, faces, nfaces, 0, 0, nb_max, L_max, max_sweeps, tol, stop2, ntop, used, flags,
-                             s, vl);
+                             s, vl, sp);
 }
-bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int>& entries, std::vector<int>& off) {
+bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int>& entries, std::vector<int>& off,
+                       const std::vector<char>* pick) {
   entries.clear();
   off.assign(1, 0);
   if (nfaces < 0 || nfaces > (INT_MAX >> kVisitShift)) return false;
@@ -2119,6 +2159,7 @@ bool jacobi_visit_list(const JFace* faces, int nfaces, int ntop, std::vector<int
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return faces[a].L > faces[b].L; });
   for (int r = 0; r < rounds; ++r) {
     for (const int f : order) {
+      if (pick && !(*pick)[(size_t)f]) continue;
       const int nb = blocks(faces[f].nv);
       for (int pair = 0; pair < slots; ++pair) {
         bool valid;
