@@ -44,6 +44,15 @@ class ProfScope {
   int count_;
   hipEvent_t a_ = nullptr;
 };
+// While a ProfMute lives, the ProfScopes of its host thread record nothing
+// (launches that an enclosing scope on another stream already brackets).
+class ProfMute {
+ public:
+  ProfMute();
+  ~ProfMute();
+  ProfMute(const ProfMute&) = delete;
+  ProfMute& operator=(const ProfMute&) = delete;
+};
 void prof_enable(bool on);
 void prof_reset();
 hipError_t prof_query(const char* name, double* total_ms, int* launches);

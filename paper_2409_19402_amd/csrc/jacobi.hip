@@ -1924,7 +1924,7 @@ inline float sweep_skip2(double tol, double stop2) { return (float)(stop2 > 0.0 
 template <typename T>
 hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, int nb_max, int L_max,
                        int max_sweeps, double tol, double stop2, int ntop, int* used, int* flags, hipStream_t s,
-                       const VisitList* vl = nullptr, const SweepPair* sp = nullptr) {
+                       const VisitList* vl = nullptr, const SweepPair* sp = nullptr, int form_grid = 0) {
   const int nflags = nfaces * max_sweeps;
   {
     ProfScope prof("jacobi_flags", s);
@@ -1938,7 +1938,7 @@ hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, 
   const GramForm form = (sizeof(T) == 8 && top_schedule(ntop, nb_max) &&
                          gram_lds_bytes<T, 2, true>(L_max) <= gram_lds_cap<T, 2, true>())
                             ? GramForm::Staged2
-                            : gram_form<T>(L_max, gram_grid(nfaces, slots));
+                            : gram_form<T>(L_max, form_grid > 0 ? form_grid : gram_grid(nfaces, slots));
   const float skip2 = sweep_skip2(tol, stop2);
   // The faces in two parts on two streams (sp) when a launch would hold two
   // or more visits per CU: the visits of one launch start together and move
@@ -2003,12 +2003,70 @@ hipError_t gram_sweeps(T* W, const JFace* faces, int nfaces, int nv_u, int L_u, 
   return hipGetLastError();
 }
 
+// The second stream of a single call's split sweeps: one per device and host
+// thread, created on first use outside graph capture and kept for the
+// thread's life (null where it cannot be had: the sweeps then run on one
+// stream).
+struct DevicePair {
+  hipStream_t s2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  bool tried = false;
+};
+constexpr int kMaxDevices = 64;
+const DevicePair* device_pair(hipStream_t s) {
+  thread_local DevicePair pairs[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  DevicePair& d = pairs[dev];
+  if (d.s2) return &d;
+  if (d.tried) return nullptr;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return nullptr;
+  d.tried = true;
+  hipError_t e = hipStreamCreateWithFlags(&d.s2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&d.join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (d.fork) hipEventDestroy(d.fork);
+    if (d.join) hipEventDestroy(d.join);
+    if (d.s2) hipStreamDestroy(d.s2);
+    d = DevicePair{};
+    d.tried = true;
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return &d;
+}
+
+// p faces of nv vectors of length L.  Where a launch would hold two or more
+// visits per CU, the two halves of the face range run on two streams (the
+// reason is given at gram_sweeps), under one profiler bracket on s.
 template <typename T>
 hipError_t gram_sweeps_uniform(T* W, int p, int nv, int L, int max_sweeps, double tol, double stop2, int ntop,
                                int* used, int* flags, hipStream_t s) {
   int nb = (nv + kGB - 1) / kGB;
   nb += nb & 1;
-  return gram_sweeps<T>(W, nullptr, p, nv, L, nb, L, max_sweeps, tol, stop2, ntop, used, flags, s);
+  int rounds, slots;
+  sweep_shape(ntop, nb, rounds, slots);
+  const DevicePair* dp = nullptr;
+  if (p >= 2 && gram_grid(p, slots) >= 2 * kSplitVisitsPerCu) dp = device_pair(s);
+  if (!dp) return gram_sweeps<T>(W, nullptr, p, nv, L, nb, L, max_sweeps, tol, stop2, ntop, used, flags, s);
+  const int h = p / 2;
+  ProfScope prof(sizeof(T) == 8 ? "jacobi_gram_f64" : "jacobi_gram_f32", s, 2 * max_sweeps * rounds);
+  ProfMute mute;
+  hipError_t e = hipEventRecord(dp->fork, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(dp->s2, dp->fork, 0);
+  // the visit form of the whole set's launches (two halves share the CUs)
+  const int grid = gram_grid(p, slots);
+  if (e == hipSuccess)
+    e = gram_sweeps<T>(W, nullptr, h, nv, L, nb, L, max_sweeps, tol, stop2, ntop, used, flags, s, nullptr, nullptr,
+                       grid);
+  if (e == hipSuccess)
+    e = gram_sweeps<T>(W + (size_t)h * nv * L, nullptr, p - h, nv, L, nb, L, max_sweeps, tol, stop2, ntop, used + h,
+                       flags + (size_t)h * max_sweeps, dp->s2, nullptr, nullptr, grid);
+  if (e == hipSuccess) e = hipEventRecord(dp->join, dp->s2);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, dp->join, 0);
+  return e;
 }
 
 // waves per workgroup (4 vectors of a block each): blocks of 16 vectors, fewer

@@ -38,7 +38,13 @@ hipEvent_t take_event() {
 
 }  // namespace
 
+thread_local int t_mute = 0;
+
+ProfMute::ProfMute() { ++t_mute; }
+ProfMute::~ProfMute() { --t_mute; }
+
 ProfScope::ProfScope(const char* name, hipStream_t s, int launches) : name_(name), s_(s), count_(launches) {
+  if (t_mute > 0) return;
   std::lock_guard<std::mutex> g(g_mu);
   if (!g_on) return;
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;  // no events inside a captured graph
