@@ -243,6 +243,44 @@ def test_tsvdq_rank_deficient(pq):
     assert r.Ak.dtype == torch.float64
 
 
+def test_tsvdq_split_sweeps_and_graph_replay(pq):
+    """32 faces of 512 x 512 hold two visits per CU in a sweep launch, so the
+    float32 sweeps run the two halves of the face range on two streams: the
+    result against the oracle, and a captured graph of the same call (the
+    fork and join captured as graph dependencies) replayed three times with
+    eager work between replays, each replay equal to the eager call."""
+    import torch
+    say("tsvdq split sweeps 512x512x32, p=32, and a captured graph")
+    A, Q = _case(41, 512, 512, 32, 32)
+    Ad, Qd = dev(A), devq(Q)
+    k = 4
+    r0 = pq.tsvdq(Ad, Qd, k, approx=True)
+    torch.cuda.synchronize()
+    assert r0.info.cpu().numpy()[1] == 0
+    ref = oracle.tsvdq(synth.logical(A), Q, k)
+    assert rel(host(r0.s), ref.s) <= TOL32
+    assert rel(host(r0.Ak), ref.Ak) <= TOL32
+    s0, ak0 = r0.s.clone(), r0.Ak.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pq.tsvdq(Ad, Qd, k, approx=True)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r1 = pq.tsvdq(Ad, Qd, k, approx=True)
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device=Ad.device).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say(f"  replay {rep}: max |s - s_eager| = {(r1.s - s0).abs().max().item():.3e}")
+        assert torch.equal(r1.s, s0), f"replay {rep}: s differs"
+        assert torch.equal(r1.Ak, ak0), f"replay {rep}: A_k differs"
+        del junk
+
+
 def test_tsvdq_max_sweeps_reported(pq):
     """max_sweeps caps each phase (float32 sweeps, then float64 polishing);
     faces stopped by the cap are counted and their outputs still written."""
