@@ -17,7 +17,13 @@
  *
  * Every pointer argument is a DEVICE pointer owned by the caller, except where
  * a comment says "host".  Entry points never allocate and never synchronise;
- * all work is enqueued on `stream` in order.  Inputs are read only; outputs
+ * all work is enqueued on `stream` in order.  (Where a Jacobi sweep launch
+ * would hold two or more visits per CU -- tSVDQ, SVDII and their adjoint on
+ * many large faces -- the sweeps fork from `stream` onto a second stream of
+ * the library's, one per device and host thread created on first use
+ * outside graph capture, and join back into `stream` before the call's next
+ * step: ordering with respect to `stream` is unchanged, and under graph
+ * capture the fork and join become graph dependencies.)  Inputs are read only; outputs
  * must not overlap inputs (PQ_ERR_ALIAS is returned for exact pointer
  * equality; partial overlap is the caller's responsibility).  Scratch memory
  * is passed in `ws` (device, 256-byte aligned) of `ws_bytes` bytes; the
@@ -487,7 +493,9 @@ int pq_batched_workspace(const pq_instance* inst, int count, size_t* bytes);
  * is in force, launch shapes not yet in the autotuner's table are tuned
  * here), then captures the same launch sequence into a hipGraph on a private
  * stream and instantiates it.  Synchronises `stream`; allocates host memory
- * for the handle only.  The transforms, the facewise products and the
+ * for the handle only.  The faces' Jacobi sweeps run in two parts on two
+ * streams (a stream and events created and destroyed by this call; the
+ * graph keeps the two parts as parallel branches).  The transforms, the facewise products and the
  * back-projections of all instances run as grouped launches (one per
  * vector width for the transforms; back-projections of more than 32 faces
  * per instance), and the Jacobi sweeps and finishing steps of all tSVDQ
