@@ -959,6 +959,16 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
     const int own4 = 4 * (16 * k + k2), diag4 = 4 * 17 * k2;
     const int vt = tid - 256, vrow = (vt >> 4) * kGld, vp = vt & 15;
     auto apply_v = [&](bool intra, int r, int buf) {
+      // the four V entries and the rotation are read together (one LDS
+      // round trip, not one per dependent group), then updated
+      const int ca = gslot_vector(intra, vp, 0, r), cw = gslot_vector(intra, vp, 1, r);
+      double va[2], vw[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int o = vrow + 16 * kGld * h;
+        va[h] = V[o + ca];
+        vw[h] = V[o + cw];
+      }
       double c = (double)rot[buf * 32 + 2 * vp], sn = (double)rot[buf * 32 + 2 * vp + 1];
       if constexpr (F32) {
         // float32 angles renormalised in float64 (first order in
@@ -968,13 +978,11 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
         c *= nf;
         sn *= nf;
       }
-      const int ca = gslot_vector(intra, vp, 0, r), cw = gslot_vector(intra, vp, 1, r);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int o = vrow + 16 * kGld * h;
-        const double va_ = V[o + ca], vw_ = V[o + cw];
-        V[o + ca] = c * va_ - sn * vw_;
-        V[o + cw] = sn * va_ + c * vw_;
+        V[o + ca] = c * va[h] - sn * vw[h];
+        V[o + cw] = sn * va[h] + c * vw[h];
       }
     };
     int cur = 0, rr = 0;
