@@ -567,6 +567,23 @@ __device__ __forceinline__ void load_quad(const R* p, R (&q)[4]) {
   }
 }
 
+// Largest of the 64 lanes' non-negative values on the VALU (DPP, the
+// pattern of wave_total; lanes a step leaves out read 0, neutral here),
+// returned wave-uniform.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ float wave_max_nonneg(float v) {
+  v = fmaxf(v, dpp_f32<0xB1>(v));
+  v = fmaxf(v, dpp_f32<0x4E>(v));
+  v = fmaxf(v, dpp_f32<0x141>(v));
+  v = fmaxf(v, dpp_f32<0x140>(v));
+  v = fmaxf(v, dpp_f32<0x142, 0xA>(v));
+  v = fmaxf(v, dpp_f32<0x143, 0xC>(v));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 template <typename T, int NB, bool ST, int NW>
 __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W, const JFace* __restrict__ faces,
                                                               int nfaces, int npair, int nv_u, int L_u, int round,
@@ -840,8 +857,7 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
       mx = cos2(tid >> 4, kGB + (tid & 15));
     }
     // one LDS atomic per wave
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    mx = wave_max_nonneg(mx);
     if (lane == 0 && mx > (float)tol2) atomicMax(any_rot, __float_as_int(mx));
     __syncthreads();
     if (*any_rot == 0) return;  // the block pair is converged: nothing to do
