@@ -775,13 +775,14 @@ __global__ __launch_bounds__(64 * NW) void jacobi_gram_kernel(T* __restrict__ W,
           for (int jj = 0; jj < 4; ++jj) part[(((wave - 4) * 3 + q) * 4 + jj) * 64 + lane] = sum[q][jj];
       }
       __syncthreads();
+      // (each of waves 0-3 then reads and rewrites only its own region:
+      // no barrier between the read and the write below)
       if (wave < 4) {
 #pragma unroll
         for (int q = 0; q < 3; ++q)
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) sum[q][jj] += part[((wave * 3 + q) * 4 + jj) * 64 + lane];
       }
-      __syncthreads();
     }
     if (wave < 4) {
 #pragma unroll
