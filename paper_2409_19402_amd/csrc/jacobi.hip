@@ -1764,11 +1764,18 @@ __global__ __launch_bounds__(1024) void fin_refine_kernel(const FinFace* __restr
                          rl_smem_g, any_rot);
 }
 
-__global__ void info_kernel(const int* __restrict__ used1, const int* __restrict__ used2, int p,
-                            int max1, int max2, int* __restrict__ info) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// one workgroup of kInfoThreads: each thread takes every kInfoThreads-th
+// face, then the three integers are combined through LDS (order-free:
+// maximum and sums of integers)
+constexpr int kInfoThreads = 256;
+__global__ __launch_bounds__(kInfoThreads) void info_kernel(const int* __restrict__ used1,
+                                                            const int* __restrict__ used2, int p, int max1,
+                                                            int max2, int* __restrict__ info) {
+  __shared__ int acc[3];
+  if (threadIdx.x == 0) acc[0] = acc[1] = acc[2] = 0;
+  __syncthreads();
   int mx = 0, bad = 0, total = 0;
-  for (int l = 0; l < p; ++l) {
+  for (int l = threadIdx.x; l < p; l += kInfoThreads) {
     const int u1 = used1[l];
     int n = min(u1, max1);
     bool conv = u1 <= max1;
@@ -1781,9 +1788,15 @@ __global__ void info_kernel(const int* __restrict__ used1, const int* __restrict
     mx = max(mx, n);
     total += n;
   }
-  info[0] = mx;
-  info[1] = bad;
-  info[2] = total;
+  atomicMax(&acc[0], mx);
+  atomicAdd(&acc[1], bad);
+  atomicAdd(&acc[2], total);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    info[0] = acc[0];
+    info[1] = acc[1];
+    info[2] = acc[2];
+  }
 }
 
 constexpr size_t kLdsCap = 131072;
@@ -2349,7 +2362,7 @@ hipError_t jacobi_factor_f64(const double* Ah, const double* F, double* Y, int n
 }
 hipError_t jacobi_info(const int* used1, const int* used2, int p, int max1, int max2, int* info,
                        hipStream_t s) {
-  info_kernel<<<1, 64, 0, s>>>(used1, used2, p, max1, max2, info);
+  info_kernel<<<1, kInfoThreads, 0, s>>>(used1, used2, p, max1, max2, info);
   return hipGetLastError();
 }
 
